@@ -1,0 +1,277 @@
+"""Oracle: geometric p-multigrid V-cycle and outer iterations (test infrastructure only).
+
+Sec. 6 of the paper:
+* grid hierarchy by reducing the polynomial order with the mesh kept (Sec. 6.1).  Eq. gridcoars
+  as printed, P_{n-1} = ceil((P_n + 1)/2), stalls at 2 and never reaches the P = 1 coarsest
+  grid the section names; it is read as P_{n-1} = ceil(P_n / 2) (8 -> 4 -> 2 -> 1);
+* prolongation from interpolation, I_{Pp} = Phi^p V^{-1}, applied per element and per
+  direction (tensor product), and restriction R = P^T (Sec. 6.2);
+* a fixed number of smoothing steps on every level before and after the coarse correction
+  (Sec. 6.3, V-cycle of Sec. 6); the smoothers here are damped Jacobi and Chebyshev
+  acceleration of Jacobi (polynomials in D^{-1} A), with the paper's additive Schwarz smoother
+  kept in ``asm_element_solve``;
+* the coarsest (P = 1) problem solved exactly (sparse direct);
+* coarse operators re-discretised with the same formula at the coarse order;
+* outer iterations: preconditioned defect correction x += B(b - A x) (Sec. 6.4) and flexible
+  conjugate gradients (one-term Polak-Ribiere beta) with B as preconditioner.
+
+Chebyshev smoothing follows the classical three-term recurrence on the interval
+[lo, hi] = [a, b] lambda_hat of D^{-1} A (Saad, "Iterative Methods for Sparse Linear Systems",
+Alg. 12.1):  theta = (b+a)/2, delta = (b-a)/2, sigma1 = theta/delta, rho_0 = 1/sigma1,
+d_0 = D^{-1} r_0 / theta; then rho_j = 1/(2 sigma1 - rho_{j-1}),
+d_j = rho_j rho_{j-1} d_{j-1} + (2 rho_j / delta) D^{-1} r_j, and x_{j+1} = x_j + d_j.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from . import gll
+from .assemble import assemble_operator
+from .mesh import Mesh2D, Mesh3D
+
+
+def coarsen_orders(P):
+    """P, ceil(P/2), ..., 1."""
+    out = [int(P)]
+    while out[-1] > 1:
+        out.append((out[-1] + 1) // 2)
+    return out
+
+
+def prolongation_1d(Ne, Pc, Pf):
+    """Global 1D interpolation matrix from order Pc to order Pf on Ne elements.
+
+    Row of fine node exPf + i, column of coarse node exPc + k holds I_{Pc->Pf}[i, k]; a node
+    shared by two elements takes the row of the element on its left (both agree: the
+    coarse Lagrange basis is continuous).
+    """
+    J = gll.transfer_matrix(Pc, Pf)
+    nf, nc = Ne * Pf + 1, Ne * Pc + 1
+    M = np.zeros((nf, nc))
+    for ex in range(Ne - 1, -1, -1):
+        M[ex * Pf: ex * Pf + Pf + 1, ex * Pc: ex * Pc + Pc + 1] = J
+    return sp.csr_matrix(M)
+
+
+class Level:
+    def __init__(self, mesh):
+        self.mesh = mesh
+        self.A = assemble_operator(mesh, dirichlet=True)
+        self.diag = self.A.diagonal().copy()
+        self.dinv = 1.0 / self.diag
+        self.dn = mesh.dirichlet_nodes()
+        self.N = mesh.N
+        self.lam = None          # largest eigenvalue estimate of D^{-1} A
+        self.lu = None
+
+
+class Hierarchy:
+    """Levels 0 (finest) .. L-1 (P = 1), prolongations P_l : level l+1 -> level l."""
+
+    def __init__(self, mesh_args, orders, smoother="chebyshev", nu_pre=2, nu_post=2,
+                 cheb_degree=3, jacobi_omega=2.0 / 3.0, cheb_lo=0.1, cheb_hi=1.1):
+        self.dim = mesh_args["dim"]
+        self.orders = list(orders)
+        if self.orders[-1] != 1:
+            raise ValueError("coarsest order must be 1")
+        self.levels = []
+        Pf = self.orders[0]
+        for p in self.orders:
+            if self.dim == 2:
+                m = Mesh2D(mesh_args["Nx"], mesh_args["Nz"], p, mesh_args["Lx"],
+                           mesh_args["h"], mesh_args["eta"], P_fine=Pf)
+            else:
+                m = Mesh3D(mesh_args["Nx"], mesh_args["Ny"], mesh_args["Nz"], p,
+                           mesh_args["Lx"], mesh_args["Ly"], mesh_args["h"], mesh_args["eta"],
+                           P_fine=Pf)
+            self.levels.append(Level(m))
+        self.P = []
+        for l in range(len(self.orders) - 1):
+            pf, pc = self.orders[l], self.orders[l + 1]
+            Px = prolongation_1d(mesh_args["Nx"], pc, pf)
+            Pz = prolongation_1d(mesh_args["Nz"], pc, pf)
+            if self.dim == 2:
+                Pm = sp.kron(Px, Pz)
+            else:
+                Py = prolongation_1d(mesh_args["Ny"], pc, pf)
+                Pm = sp.kron(sp.kron(Px, Py), Pz)
+            self.P.append(Pm.tocsr())
+        last = self.levels[-1]
+        last.lu = spla.splu(sp.csc_matrix(last.A))
+        self.smoother = smoother
+        self.nu_pre, self.nu_post = nu_pre, nu_post
+        self.cheb_degree = cheb_degree
+        self.omega = jacobi_omega
+        self.cheb_lo, self.cheb_hi = cheb_lo, cheb_hi
+
+    # ---- smoothing -------------------------------------------------------------------
+    def set_lambda(self, l, lam):
+        self.levels[l].lam = float(lam)
+
+    def jacobi(self, l, b, x, sweeps):
+        L = self.levels[l]
+        for _ in range(sweeps):
+            x = x + self.omega * L.dinv * (b - L.A @ x)
+        return x
+
+    def chebyshev(self, l, b, x, degree):
+        L = self.levels[l]
+        a_ = self.cheb_lo * L.lam
+        b_ = self.cheb_hi * L.lam
+        theta = 0.5 * (b_ + a_)
+        delta = 0.5 * (b_ - a_)
+        sigma1 = theta / delta
+        rho = 1.0 / sigma1
+        r = b - L.A @ x
+        d = L.dinv * r / theta
+        x = x + d
+        for _ in range(1, degree):
+            rho_new = 1.0 / (2.0 * sigma1 - rho)
+            r = b - L.A @ x
+            d = rho_new * rho * d + (2.0 * rho_new / delta) * (L.dinv * r)
+            rho = rho_new
+            x = x + d
+        return x
+
+    def smooth(self, l, b, x, pre):
+        if self.smoother == "jacobi":
+            return self.jacobi(l, b, x, self.nu_pre if pre else self.nu_post)
+        return self.chebyshev(l, b, x, self.cheb_degree)
+
+    # ---- V-cycle -----------------------------------------------------------------------
+    def restrict(self, l, r_fine):
+        rc = self.P[l].T @ r_fine
+        rc[self.levels[l + 1].dn] = 0.0
+        return rc
+
+    def prolong(self, l, e_coarse):
+        return self.P[l] @ e_coarse
+
+    def coarse_solve(self, b):
+        return self.levels[-1].lu.solve(b)
+
+    def vcycle(self, b, l=0, hook=None):
+        """z = B b with zero initial guess.  ``hook(l, b, x)`` may add a stage after
+        pre-smoothing on level l and return the new x (used for the learned stage)."""
+        if l == len(self.levels) - 1:
+            return self.coarse_solve(b)
+        L = self.levels[l]
+        x = self.smooth(l, b, np.zeros_like(b), pre=True)
+        if hook is not None:
+            x = hook(l, b, x)
+        r = b - L.A @ x
+        ec = self.vcycle(self.restrict(l, r), l + 1, hook)
+        x = x + self.prolong(l, ec)
+        x = self.smooth(l, b, x, pre=False)
+        return x
+
+
+def lanczos_lambda_max(A, dinv, v0, steps=20):
+    """Largest Ritz value of D^{-1/2} A D^{-1/2} after ``steps`` Lanczos steps from v0
+    (which equals the largest eigenvalue estimate of D^{-1} A)."""
+    s = np.sqrt(dinv)
+    q = v0 / np.linalg.norm(v0)
+    q_prev = np.zeros_like(q)
+    alphas, betas = [], []
+    beta = 0.0
+    for k in range(steps):
+        w = s * (A @ (s * q))
+        alpha = float(q @ w)
+        w = w - alpha * q - beta * q_prev
+        alphas.append(alpha)
+        beta = float(np.linalg.norm(w))
+        if k == steps - 1 or beta == 0.0:
+            break
+        betas.append(beta)
+        q_prev, q = q, w / beta
+    T = np.diag(alphas) + np.diag(betas[:len(alphas) - 1], 1) + np.diag(betas[:len(alphas) - 1], -1)
+    return float(np.linalg.eigvalsh(T)[-1])
+
+
+def splitmix64_uniform(n, seed):
+    """Counter-based start vector: SplitMix64 (Steele, Lea, Flood 2014) of (seed + i), mapped
+    to [-1, 1) with the top 53 bits.  Both sides of the parity tests implement this
+    published generator independently."""
+    M = (1 << 64) - 1
+    out = np.empty(n)
+    for i in range(n):
+        z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & M
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M
+        z = z ^ (z >> 31)
+        out[i] = (z >> 11) * (1.0 / (1 << 53)) * 2.0 - 1.0
+    return out
+
+
+def estimate_lambdas(H, steps=20, seed=12345):
+    for l, L in enumerate(H.levels[:-1]):
+        v0 = splitmix64_uniform(L.N, seed)
+        v0[L.dn] = 0.0
+        H.set_lambda(l, lanczos_lambda_max(L.A, L.dinv, v0, steps))
+
+
+# ---- outer iterations ------------------------------------------------------------------
+def pcg(A, b, x0, prec, tol, maxit=500):
+    """Standard preconditioned CG (linear preconditioner); returns x, iterations, history."""
+    x = x0.copy()
+    r = b - A @ x
+    nb = np.linalg.norm(b)
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    hist = [np.linalg.norm(r) / nb]
+    for it in range(1, maxit + 1):
+        q = A @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= tol:
+            return x, it, hist
+        z = prec(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+    return x, maxit, hist
+
+
+def fpcg(A, b, x0, prec, tol, maxit=500):
+    """Flexible CG (Notay 2000), one-term Polak-Ribiere:
+    beta = z_{k+1}.(r_{k+1} - r_k) / (r_k . z_k) = -alpha z_{k+1}.q_k / (r_k . z_k)."""
+    x = x0.copy()
+    r = b - A @ x
+    nb = np.linalg.norm(b)
+    z = prec(r)
+    p = z.copy()
+    rz = r @ z
+    hist = [np.linalg.norm(r) / nb]
+    if hist[-1] <= tol:
+        return x, 0, hist
+    for it in range(1, maxit + 1):
+        q = A @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= tol:
+            return x, it, hist
+        z = prec(r)
+        beta = -alpha * (z @ q) / rz
+        rz = r @ z
+        p = z + beta * p
+    return x, maxit, hist
+
+
+def pdc(A, b, x0, prec, tol, maxit=500):
+    """Preconditioned defect correction x_{k+1} = x_k + B (b - A x_k) (Sec. 6.4)."""
+    x = x0.copy()
+    nb = np.linalg.norm(b)
+    r = b - A @ x
+    hist = [np.linalg.norm(r) / nb]
+    for it in range(1, maxit + 1):
+        x = x + prec(r)
+        r = b - A @ x
+        hist.append(np.linalg.norm(r) / nb)
+        if hist[-1] <= tol:
+            return x, it, hist
+    return x, maxit, hist
