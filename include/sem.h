@@ -1,0 +1,184 @@
+/*
+ * sem.h -- C ABI of the MI355X (gfx950) spectral-element pressure-Poisson solver.
+ *
+ * Problem (paper Sec. 4.2, eqs. poissonp / bcpd / bcpdneu, read in the same-stage symmetric
+ * form): find p with  -lap p = f  in the sigma-mapped fluid domain (Sec. 2.2, eq. sigtrans),
+ * p = g_D on the free surface (top), n . grad p = g_N on walls and bottom.  Discretised with
+ * nodal GLL spectral elements (Sec. 5, eqs. fglobal / flocal / flocal2 with GLL collocation)
+ * and solved by geometric p-multigrid (Sec. 6: order hierarchy eq. gridcoars read as
+ * ceil(P/2), interpolation/restriction of Sec. 6.2, V-cycle of Sec. 6) inside an FP64
+ * flexible CG or preconditioned defect-correction loop (Sec. 6.4).
+ *
+ * Conventions common to every call
+ *  - Global vectors are FP64, contiguous, on the context's device, length n_global:
+ *      2D  g = ix (Nz P + 1) + iz,          ix in [0, Nx P], iz in [0, Nz P]
+ *      3D  g = (ix (Ny P + 1) + iy)(Nz P + 1) + iz
+ *    (vertical/sigma index fastest; iz = Nz P is the free surface).
+ *  - Device pointers are caller-owned; the library never frees or retains them.  Host arrays
+ *    are copied during the call.  Every internal buffer is allocated by sem_mesh_setup and
+ *    released by sem_destroy.
+ *  - All work is enqueued on the context's stream (sem_mesh_desc.stream, a hipStream_t, or the
+ *    null stream).  Calls that return values on the host synchronise that stream.
+ *  - Every call returns a sem_status and never aborts; no C++ exception crosses the ABI.
+ *    sem_last_error() gives the text of the last failure of a context.  SEM_ERR_HIP is sticky:
+ *    after it the context only accepts sem_destroy.
+ *  - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef SEM_H
+#define SEM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sem_ctx sem_ctx;
+
+typedef enum {
+  SEM_OK = 0,
+  SEM_ERR_ARG = 1,           /* invalid argument or unsupported size                     */
+  SEM_ERR_ALLOC = 2,         /* device or host allocation failed                         */
+  SEM_ERR_HIP = 3,           /* a HIP runtime call failed (sticky)                       */
+  SEM_ERR_NOT_CONVERGED = 4, /* maxit reached; x holds the last iterate                  */
+  SEM_ERR_BREAKDOWN = 5,     /* non-finite residual or p.Ap <= 0 in the outer iteration  */
+  SEM_ERR_STATE = 6          /* call not valid in the context's current state            */
+} sem_status;
+
+/* inner (V-cycle) precision */
+enum { SEM_F64 = 0, SEM_F32 = 1, SEM_F32_GBF16 = 2 };
+/* smoother on every level above the coarsest */
+enum { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_CHEBYSHEV = 1 };
+/* outer iteration */
+enum { SEM_OUTER_FPCG = 0, SEM_OUTER_PDC = 1 };
+/* Dirichlet faces bitmask */
+enum { SEM_FACE_TOP = 1 };
+
+#define SEM_MAX_LEVELS 8
+#define SEM_MAX_ORDER 12
+
+typedef struct {
+  int dim;                     /* 2 or 3                                                    */
+  int ne[3];                   /* elements along x, y, z(sigma); ne[1] ignored in 2D        */
+  int order;                   /* fine GLL order P, 1..SEM_MAX_ORDER                        */
+  int nlevels;                 /* 0: P, ceil(P/2), ..., 1; else level_order[0..nlevels-1]   */
+  int level_order[SEM_MAX_LEVELS]; /* strictly decreasing, first = order, last = 1          */
+  double len[2];               /* horizontal extents L_x, L_y (origin 0)                    */
+  const double *h;             /* host: still-water depth at the fine horizontal GLL nodes:
+                                  2D (ne[0] P + 1); 3D (ne[0] P + 1) x (ne[1] P + 1), y fastest */
+  const double *eta;           /* host: free-surface elevation, same layout as h            */
+  unsigned dirichlet_faces;    /* SEM_FACE_TOP (default) or 0 = pure Neumann (apply only)   */
+  int inner_prec;              /* SEM_F64 | SEM_F32 | SEM_F32_GBF16                         */
+  int smoother;                /* SEM_SMOOTH_*                                               */
+  int nu_pre, nu_post;         /* Jacobi sweeps                                             */
+  int cheb_degree;             /* Chebyshev degree (pre and post)                           */
+  double jacobi_omega;         /* damping, default 2/3                                      */
+  double cheb_lo, cheb_hi;     /* Chebyshev interval as fractions of lambda_hat (0.1, 1.1)  */
+  int outer;                   /* SEM_OUTER_FPCG | SEM_OUTER_PDC                            */
+  int maxit;                   /* outer iteration cap                                       */
+  int lanczos_steps;           /* steps of the lambda_hat estimate (default 20)             */
+  unsigned long long lanczos_seed; /* SplitMix64 seed of the Lanczos start vector           */
+  void *stream;                /* hipStream_t or NULL                                        */
+} sem_mesh_desc;
+
+typedef struct {
+  int iters;          /* outer iterations performed                                        */
+  int vcycles;        /* V-cycles applied                                                  */
+  int learned_skips;  /* learned-stage applications rejected by the judge                  */
+  double rel_res;     /* ||b - A x||_2 / ||b||_2 at exit (free and Dirichlet rows)          */
+  double ms;          /* wall time of the call                                             */
+  int nhist;          /* entries of hist                                                   */
+  double hist[512];   /* relative residual after each iteration (hist[0] = initial)         */
+} sem_solve_info;
+
+/* Fill *d with defaults (2D, top Dirichlet, FP64, Chebyshev(3) on [0.1, 1.1] lambda_hat,
+ * Jacobi omega 2/3, 2+2 sweeps, FPCG, maxit 500, 20 Lanczos steps, seed 12345). */
+void sem_mesh_desc_default(sem_mesh_desc *d);
+
+/* Build the level hierarchy, geometric factors, inverse diagonals, lambda_hat estimates and
+ * the exact P = 1 coarse factorisation; allocate every buffer.  *out receives the context. */
+sem_status sem_mesh_setup(const sem_mesh_desc *desc, sem_ctx **out);
+
+/* Release everything owned by the context (NULL is accepted). */
+void sem_destroy(sem_ctx *ctx);
+
+/* Sizes: assembled nodes n_global, free (non-Dirichlet) nodes n_free, element-local nodes
+ * n_local = elements (P+1)^dim.  Any pointer may be NULL. */
+sem_status sem_get_sizes(const sem_ctx *ctx, size_t *n_global, size_t *n_free, size_t *n_local);
+
+/* Number of levels of the hierarchy (0 for a NULL context). */
+int sem_num_levels(const sem_ctx *ctx);
+
+/* For level l (0 = finest): its order, node count and current lambda_hat. */
+sem_status sem_get_level(const sem_ctx *ctx, int level, int *order, size_t *n, double *lambda_hat);
+
+/* GLL nodes and weights of order P computed by the library (host arrays of P+1). */
+sem_status sem_gll(int P, double *nodes, double *weights);
+
+/* Physical coordinates of the nodes of level l (host arrays of that level's node count; y
+ * only in 3D, may be NULL in 2D). */
+sem_status sem_node_coords(const sem_ctx *ctx, int level, double *x, double *y, double *z);
+
+/* y = A x on the fine level in FP64: the assembled GLL stiffness (sum of element matrices,
+ * Sec. 5.2 eq. globallocal) of the symmetric sigma-Laplacian, restricted to free rows and
+ * columns, with identity rows on Dirichlet nodes (pure Neumann if dirichlet_faces = 0).
+ * x, y: device, n_global doubles, must not alias. */
+sem_status sem_apply_laplacian(sem_ctx *ctx, const double *x, double *y);
+
+/* The same operator on level l in the context's inner precision (x is rounded to it, the
+ * result widened to FP64).  Test hook for the inner-precision apply. */
+sem_status sem_apply_level(sem_ctx *ctx, int level, const double *x, double *y);
+
+/* z = B r: one p-multigrid V-cycle (Sec. 6) from a zero initial guess in the inner precision:
+ * pre-smoothing on every level above the coarsest, residual, restriction R = P^T (Sec. 6.2),
+ * exact FP64 solve on P = 1, prolongation by interpolation, post-smoothing.  r, z: device,
+ * n_global doubles; r must be zero on Dirichlet rows (z is then zero there). */
+sem_status sem_pmg_vcycle(sem_ctx *ctx, const double *r, double *z);
+
+/* Solve A x = rhs to ||rhs - A x||_2 <= tol ||rhs||_2 with the outer loop chosen at setup
+ * (flexible CG or defect correction, each preconditioned by one V-cycle), all outer vectors,
+ * the outer operator and inner products in FP64.  rhs must hold g_D on Dirichlet rows (see
+ * sem_assemble_rhs).  x: initial guess on entry, solution on exit.  rhs and x are device
+ * n_global doubles and must not alias.  info may be NULL.  Returns SEM_ERR_NOT_CONVERGED
+ * (x = last iterate) or SEM_ERR_BREAKDOWN (x = last finite iterate) on failure. */
+sem_status sem_poisson_solve(sem_ctx *ctx, const double *rhs, double *x, double tol,
+                             sem_solve_info *info);
+
+/* rhs = M f + B g_N - A_fD g_D on free rows, rhs = g_D on Dirichlet rows (Sec. 5.2 eq.
+ * fsemidiscrete with the lumped GLL mass M and GLL face quadrature B).
+ *   f   : device, n_global doubles (nodal source values) or NULL for f = 0
+ *   gN  : device, per-face nodal values of n . grad p, packed faces in this order:
+ *         2D: x = 0 wall (Nz P + 1), x = L_x wall (Nz P + 1), bottom (Nx P + 1);
+ *         3D: x = 0, x = L_x [(Ny P + 1)(Nz P + 1) each, z fastest], y = 0, y = L_y
+ *         [(Nx P + 1)(Nz P + 1) each], bottom [(Nx P + 1)(Ny P + 1), y fastest]; or NULL
+ *   gD  : device, free-surface values (one per top node, in global order) or NULL for 0
+ *   rhs : device, n_global doubles (output). */
+sem_status sem_assemble_rhs(sem_ctx *ctx, const double *f, const double *gN, const double *gD,
+                            double *rhs);
+
+/* Override lambda_hat (largest eigenvalue estimate of D^{-1} A) of level l (l above the
+ * coarsest).  Parity tests inject the reference value. */
+sem_status sem_set_smoother_bounds(sem_ctx *ctx, int level, double lambda_hat);
+
+/* Test hooks for single steps of the V-cycle, FP64 device vectors of the level sizes:
+ *   sem_restrict     rc = P^T (b - A x) on level l -> l+1, coarse Dirichlet rows zeroed
+ *                    (x = NULL means x = 0, i.e. rc = P^T b)
+ *   sem_prolong_add  xf += P ec, level l+1 -> l
+ *   sem_smooth       x <- smoother(b, x) on level l (pre = 1: from x = 0, x is output only)
+ *   sem_coarse_solve x = A_1^{-1} b on the coarsest level (exact, FP64). */
+sem_status sem_restrict(sem_ctx *ctx, int level, const double *b, const double *x, double *rc);
+sem_status sem_prolong_add(sem_ctx *ctx, int level, const double *ec, double *xf);
+sem_status sem_smooth(sem_ctx *ctx, int level, int pre, const double *b, double *x);
+sem_status sem_coarse_solve(sem_ctx *ctx, const double *b, double *x);
+
+/* Text of the last error on this context ("" if none).  Valid until the next call. */
+const char *sem_last_error(const sem_ctx *ctx);
+
+/* Name of a status code. */
+const char *sem_status_string(sem_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SEM_H */

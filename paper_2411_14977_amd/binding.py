@@ -1,0 +1,320 @@
+"""ctypes marshalling for ``libsem.so`` (see include/sem.h for the meaning of every call)."""
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "libsem.so")
+
+SEM_F64, SEM_F32, SEM_F32_GBF16 = 0, 1, 2
+SEM_SMOOTH_JACOBI, SEM_SMOOTH_CHEBYSHEV = 0, 1
+SEM_OUTER_FPCG, SEM_OUTER_PDC = 0, 1
+SEM_FACE_TOP = 1
+SEM_MAX_LEVELS = 8
+
+STATUS = {0: "SEM_OK", 1: "SEM_ERR_ARG", 2: "SEM_ERR_ALLOC", 3: "SEM_ERR_HIP",
+          4: "SEM_ERR_NOT_CONVERGED", 5: "SEM_ERR_BREAKDOWN", 6: "SEM_ERR_STATE"}
+
+
+class SemError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("ne", ctypes.c_int * 3), ("order", ctypes.c_int),
+        ("nlevels", ctypes.c_int), ("level_order", ctypes.c_int * SEM_MAX_LEVELS),
+        ("len", ctypes.c_double * 2), ("h", ctypes.POINTER(ctypes.c_double)),
+        ("eta", ctypes.POINTER(ctypes.c_double)), ("dirichlet_faces", ctypes.c_uint),
+        ("inner_prec", ctypes.c_int), ("smoother", ctypes.c_int), ("nu_pre", ctypes.c_int),
+        ("nu_post", ctypes.c_int), ("cheb_degree", ctypes.c_int),
+        ("jacobi_omega", ctypes.c_double), ("cheb_lo", ctypes.c_double),
+        ("cheb_hi", ctypes.c_double), ("outer", ctypes.c_int), ("maxit", ctypes.c_int),
+        ("lanczos_steps", ctypes.c_int), ("lanczos_seed", ctypes.c_ulonglong),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class SolveInfo(ctypes.Structure):
+    _fields_ = [
+        ("iters", ctypes.c_int), ("vcycles", ctypes.c_int), ("learned_skips", ctypes.c_int),
+        ("rel_res", ctypes.c_double), ("ms", ctypes.c_double), ("nhist", ctypes.c_int),
+        ("hist", ctypes.c_double * 512),
+    ]
+
+    def history(self):
+        return list(self.hist[: self.nhist])
+
+
+_lib = None
+
+
+def lib_path():
+    return _LIB_PATH
+
+
+def lib():
+    """Load libsem.so (raises RuntimeError if it is not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise RuntimeError(f"{_LIB_PATH} is not built; run python -m paper_2411_14977_amd.build")
+    L = ctypes.CDLL(_LIB_PATH)
+    vp, dp, ip, sz = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)
+    sig = {
+        "sem_mesh_desc_default": (None, [ctypes.POINTER(MeshDesc)]),
+        "sem_mesh_setup": (ctypes.c_int, [ctypes.POINTER(MeshDesc), ctypes.POINTER(vp)]),
+        "sem_destroy": (None, [vp]),
+        "sem_get_sizes": (ctypes.c_int, [vp, sz, sz, sz]),
+        "sem_num_levels": (ctypes.c_int, [vp]),
+        "sem_get_level": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_int), sz,
+                                         ctypes.POINTER(ctypes.c_double)]),
+        "sem_gll": (ctypes.c_int, [ip, ctypes.POINTER(ctypes.c_double),
+                                   ctypes.POINTER(ctypes.c_double)]),
+        "sem_node_coords": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_double)]),
+        "sem_apply_laplacian": (ctypes.c_int, [vp, dp, dp]),
+        "sem_apply_level": (ctypes.c_int, [vp, ip, dp, dp]),
+        "sem_pmg_vcycle": (ctypes.c_int, [vp, dp, dp]),
+        "sem_poisson_solve": (ctypes.c_int, [vp, dp, dp, ctypes.c_double,
+                                             ctypes.POINTER(SolveInfo)]),
+        "sem_assemble_rhs": (ctypes.c_int, [vp, dp, dp, dp, dp]),
+        "sem_set_smoother_bounds": (ctypes.c_int, [vp, ip, ctypes.c_double]),
+        "sem_restrict": (ctypes.c_int, [vp, ip, dp, dp, dp]),
+        "sem_prolong_add": (ctypes.c_int, [vp, ip, dp, dp]),
+        "sem_smooth": (ctypes.c_int, [vp, ip, ip, dp, dp]),
+        "sem_coarse_solve": (ctypes.c_int, [vp, dp, dp]),
+        "sem_last_error": (ctypes.c_char_p, [vp]),
+        "sem_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(L, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(ctx, status):
+    if status != 0:
+        msg = lib().sem_last_error(ctx)
+        raise SemError(status, msg.decode() if msg else "")
+    return status
+
+
+def _ptr(t):
+    """Device pointer of a contiguous float64 CUDA tensor (None -> NULL)."""
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 8 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+# ---- C ABI mirrors ---------------------------------------------------------------------------
+def sem_mesh_desc_default():
+    d = MeshDesc()
+    lib().sem_mesh_desc_default(ctypes.byref(d))
+    return d
+
+
+def sem_mesh_setup(desc):
+    h = ctypes.c_void_p()
+    st = lib().sem_mesh_setup(ctypes.byref(desc), ctypes.byref(h))
+    if st != 0:
+        msg = lib().sem_last_error(None)
+        raise SemError(st, msg.decode() if msg else "")
+    return h
+
+
+def sem_destroy(ctx):
+    lib().sem_destroy(ctx)
+
+
+def sem_get_sizes(ctx):
+    a, b, c = ctypes.c_size_t(), ctypes.c_size_t(), ctypes.c_size_t()
+    _check(ctx, lib().sem_get_sizes(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+def sem_num_levels(ctx):
+    return lib().sem_num_levels(ctx)
+
+
+def sem_get_level(ctx, level):
+    o, n, lam = ctypes.c_int(), ctypes.c_size_t(), ctypes.c_double()
+    _check(ctx, lib().sem_get_level(ctx, level, ctypes.byref(o), ctypes.byref(n), ctypes.byref(lam)))
+    return o.value, n.value, lam.value
+
+
+def sem_gll(P):
+    r = (ctypes.c_double * (P + 1))()
+    w = (ctypes.c_double * (P + 1))()
+    st = lib().sem_gll(P, r, w)
+    if st != 0:
+        raise SemError(st, "bad order")
+    return np.array(r[:]), np.array(w[:])
+
+
+def sem_node_coords(ctx, level, dim=2):
+    _, n, _ = sem_get_level(ctx, level)
+    x = np.zeros(n)
+    y = np.zeros(n)
+    z = np.zeros(n)
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(ctx, lib().sem_node_coords(ctx, level, x.ctypes.data_as(dp),
+                                      y.ctypes.data_as(dp) if dim == 3 else None,
+                                      z.ctypes.data_as(dp)))
+    return (x, z) if dim == 2 else (x, y, z)
+
+
+def sem_apply_laplacian(ctx, x, y):
+    _check(ctx, lib().sem_apply_laplacian(ctx, _ptr(x), _ptr(y)))
+
+
+def sem_apply_level(ctx, level, x, y):
+    _check(ctx, lib().sem_apply_level(ctx, level, _ptr(x), _ptr(y)))
+
+
+def sem_pmg_vcycle(ctx, r, z):
+    _check(ctx, lib().sem_pmg_vcycle(ctx, _ptr(r), _ptr(z)))
+
+
+def sem_poisson_solve(ctx, rhs, x, tol, info=None, check=True):
+    info = SolveInfo() if info is None else info
+    st = lib().sem_poisson_solve(ctx, _ptr(rhs), _ptr(x), float(tol), ctypes.byref(info))
+    if check:
+        _check(ctx, st)
+    return st, info
+
+
+def sem_assemble_rhs(ctx, f, gN, gD, rhs):
+    _check(ctx, lib().sem_assemble_rhs(ctx, _ptr(f), _ptr(gN), _ptr(gD), _ptr(rhs)))
+
+
+def sem_set_smoother_bounds(ctx, level, lam):
+    _check(ctx, lib().sem_set_smoother_bounds(ctx, level, float(lam)))
+
+
+def sem_restrict(ctx, level, b, x, rc):
+    _check(ctx, lib().sem_restrict(ctx, level, _ptr(b), _ptr(x), _ptr(rc)))
+
+
+def sem_prolong_add(ctx, level, ec, xf):
+    _check(ctx, lib().sem_prolong_add(ctx, level, _ptr(ec), _ptr(xf)))
+
+
+def sem_smooth(ctx, level, pre, b, x):
+    _check(ctx, lib().sem_smooth(ctx, level, int(pre), _ptr(b), _ptr(x)))
+
+
+def sem_coarse_solve(ctx, b, x):
+    _check(ctx, lib().sem_coarse_solve(ctx, _ptr(b), _ptr(x)))
+
+
+# ---- convenience owner of one context -------------------------------------------------------
+_PREC = {"f64": SEM_F64, "f32": SEM_F32, "bf16": SEM_F32_GBF16}
+
+
+class Solver:
+    """One solver context.  Inputs h, eta: depth and surface elevation sampled at the fine
+    horizontal GLL nodes (use ``fine_x_nodes`` to get them from the library's own rule)."""
+
+    def __init__(self, dim, ne, order, length, h, eta, levels=None, prec="f64",
+                 smoother="chebyshev", nu_pre=2, nu_post=2, cheb_degree=3, jacobi_omega=2.0 / 3.0,
+                 cheb_lo=0.1, cheb_hi=1.1, outer="fpcg", maxit=500, dirichlet=True,
+                 lanczos_steps=20, lanczos_seed=12345, stream=None):
+        import torch
+        d = sem_mesh_desc_default()
+        d.dim = dim
+        for k in range(3):
+            d.ne[k] = int(ne[k])
+        d.order = int(order)
+        if levels:
+            d.nlevels = len(levels)
+            for k, p in enumerate(levels):
+                d.level_order[k] = int(p)
+        d.len[0] = float(length[0])
+        d.len[1] = float(length[1]) if len(length) > 1 else 1.0
+        self._h = np.ascontiguousarray(np.asarray(h, dtype=np.float64).ravel())
+        self._eta = np.ascontiguousarray(np.asarray(eta, dtype=np.float64).ravel())
+        dp = ctypes.POINTER(ctypes.c_double)
+        d.h = self._h.ctypes.data_as(dp)
+        d.eta = self._eta.ctypes.data_as(dp)
+        d.dirichlet_faces = SEM_FACE_TOP if dirichlet else 0
+        d.inner_prec = _PREC[prec]
+        d.smoother = SEM_SMOOTH_JACOBI if smoother == "jacobi" else SEM_SMOOTH_CHEBYSHEV
+        d.nu_pre, d.nu_post, d.cheb_degree = nu_pre, nu_post, cheb_degree
+        d.jacobi_omega, d.cheb_lo, d.cheb_hi = jacobi_omega, cheb_lo, cheb_hi
+        d.outer = SEM_OUTER_PDC if outer == "pdc" else SEM_OUTER_FPCG
+        d.maxit = maxit
+        d.lanczos_steps = lanczos_steps
+        d.lanczos_seed = lanczos_seed
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        d.stream = ctypes.c_void_p(int(stream))
+        self.dim = dim
+        self.ctx = sem_mesh_setup(d)
+        self.n_global, self.n_free, self.n_local = sem_get_sizes(self.ctx)
+        self.nlevels = sem_num_levels(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            sem_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level(self, l):
+        return sem_get_level(self.ctx, l)
+
+    def coords(self, level=0):
+        return sem_node_coords(self.ctx, level, self.dim)
+
+    def _new(self, n=None):
+        import torch
+        return torch.zeros(self.n_global if n is None else n, dtype=torch.float64, device="cuda")
+
+    def apply(self, x, y=None):
+        y = self._new() if y is None else y
+        sem_apply_laplacian(self.ctx, x, y)
+        return y
+
+    def apply_level(self, level, x, y=None):
+        y = self._new(self.level(level)[1]) if y is None else y
+        sem_apply_level(self.ctx, level, x, y)
+        return y
+
+    def vcycle(self, r, z=None):
+        z = self._new() if z is None else z
+        sem_pmg_vcycle(self.ctx, r, z)
+        return z
+
+    def solve(self, rhs, x=None, tol=1e-10, check=True):
+        x = self._new() if x is None else x
+        st, info = sem_poisson_solve(self.ctx, rhs, x, tol, check=check)
+        return x, info, st
+
+    def assemble_rhs(self, f=None, gN=None, gD=None):
+        rhs = self._new()
+        sem_assemble_rhs(self.ctx, f, gN, gD, rhs)
+        return rhs
+
+    def set_lambda(self, level, lam):
+        sem_set_smoother_bounds(self.ctx, level, lam)
+
+
+def fine_x_nodes(Ne, P, L):
+    """Horizontal GLL node coordinates of the fine level from the library's GLL rule."""
+    r, _ = sem_gll(P)
+    xe = L * (np.arange(Ne)[:, None] + (r[None, :] + 1.0) / 2.0) / Ne
+    return np.concatenate([xe[:, :-1].ravel(), [L]])

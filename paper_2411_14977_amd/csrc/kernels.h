@@ -1,0 +1,98 @@
+// Launch wrappers of the gfx950 kernels (implemented in kernels.hip).  All launches are
+// asynchronous on the given stream; sizes are validated by the caller.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace semk {
+
+constexpr int NRED = 1024;   // partial sums per reduction (fixed: deterministic results)
+constexpr int RED_THREADS = 256;
+
+enum GType { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
+
+// ---- operator --------------------------------------------------------------------------
+// 2D: one workgroup per element column; y gets lines 0..P-1 of each column (and line P of
+// the last column), S[(ex+1) * nzn + iz] the column's contribution to its right line.
+// Full (A x)[g] = y[g] + S[(ix/P) nzn + iz] when ix % P == 0 (S rows 0 and Nx stay zero).
+size_t apply2d_smem(int P, int Nz, bool dbl);
+hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
+                   const void* Dmat, int Nx, int Nz, int masked, hipStream_t st);
+
+// ---- element-wise kernels in precision T (dbl selects double, else float) ----------------
+// d = cd d + cr dinv r,  x = (from_zero ? 0 : x) + d,  r = b - (from_zero ? 0 : Ax)
+hipError_t smooth_update(bool dbl, void* x, void* d, const void* b, const void* dinv,
+                         const void* y, const void* S, unsigned N, unsigned nzn, unsigned P,
+                         double cd, double cr, int from_zero, int store_d, hipStream_t st);
+// out = (Ax)[g] with the side-buffer fix (test hook / Lanczos), widened to double if out64
+hipError_t fix_ax(bool dbl, const void* y, const void* S, void* out, int out64, unsigned N,
+                  unsigned nzn, unsigned P, hipStream_t st);
+// casts between FP64 and the inner precision
+hipError_t cast_to(bool dbl_dst, const double* src, void* dst, unsigned N, hipStream_t st);
+hipError_t cast_from(bool dbl_src, const void* src, double* dst, unsigned N, hipStream_t st);
+hipError_t fill(bool dbl, void* p, double v, size_t n, hipStream_t st);
+
+// ---- p-transfers (2D, pull form, one workgroup per element column) ------------------------
+// rc = P^T r with r = b - Ax (use_ax) or r = b; coarse Dirichlet rows zero when masked.
+size_t restrict2d_smem(int Pf, int Pc, int Nz, bool dbl);
+hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const void* S,
+                      int use_ax, void* rc, const double* J, int Nx, int Nz, int Pf, int Pc,
+                      int masked, hipStream_t st);
+size_t prolong2d_smem(int Pf, int Pc, int Nz, bool dbl);
+hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
+                     int Nz, int Pf, int Pc, hipStream_t st);
+
+// ---- exact coarse solve (block cyclic reduction, FP64, in place on b, result in x) ---------
+struct BcrLevDev { int n, stride; long long offM, offB; int neven, nodd; };
+hipError_t bcr_fwd(double* b, const double* F, int n, int stride, int neven, int bstride,
+                   const int* rowmap, int nb, hipStream_t st);
+hipError_t bcr_bwd(const double* b, double* x, const double* Bk, int n, int stride, int nodd,
+                   int bstride, const int* rowmap, int nb, hipStream_t st);
+hipError_t bcr_tail(double* b, double* x, const double* F, const double* Bk,
+                    const BcrLevDev* levs, int lfirst, int nlev, const double* last,
+                    int bstride, const int* rowmap, int nb, hipStream_t st);
+
+// ---- FP64 outer-loop kernels (deterministic two-stage reductions over NRED partials) -------
+// r = b - Ax (with fix); partial sums of r.r into prr and (if pbb) b.b into pbb
+hipError_t resid64(const double* b, const double* y, const double* S, double* r, double* prr,
+                   double* pbb, unsigned N, unsigned nzn, unsigned P, hipStream_t st);
+// q = Ax (fix); ppq = partial p.q; if rz_from/rz_to copy NRED partials (done by block 0)
+hipError_t fixdot64(const double* y, const double* S, double* q, const double* p, double* ppq,
+                    const double* rz_from, double* rz_to, unsigned N, unsigned nzn, unsigned P,
+                    hipStream_t st);
+// alpha = sum(prz)/sum(ppq); x += alpha p; r -= alpha q; prr = partial r.r
+hipError_t update_xr(double* x, double* r, const double* p, const double* q, const double* prz,
+                     const double* ppq, double* prr, unsigned N, hipStream_t st);
+// out[k] = sum of partial set k (k < nsets), one block
+hipError_t reduce_sets(const double* parts, int nsets, double* out, hipStream_t st);
+// z = (double) x0; partial z.q (if q) and r.z
+hipError_t castdot(bool dbl_src, const void* x0, double* z, const double* q, const double* r,
+                   double* pzq, double* prz, unsigned N, hipStream_t st);
+// p = z (first) or p = z + beta p with beta = -alpha sum(pzq)/sum(prz_old),
+// alpha = sum(prz_old)/sum(ppq)
+hipError_t pupdate(double* p, const double* z, const double* prz_old, const double* ppq,
+                   const double* pzq, int first, unsigned N, hipStream_t st);
+hipError_t axpy64(double* x, const double* z, double a, unsigned N, hipStream_t st);
+// x[top nodes] = src[top nodes]
+hipError_t copy_top(double* x, const double* src, unsigned ncols, unsigned nzn, hipStream_t st);
+// partial dot of two vectors in precision T (double partials)
+hipError_t dot_partial(bool dbl, const void* a, const void* b, double* part, unsigned N,
+                       hipStream_t st);
+// elementwise: out = a * s (T)
+hipError_t vmul(bool dbl, const void* a, const void* s, void* out, unsigned N, hipStream_t st);
+// out = alpha a + beta b (T), out may alias a or b
+hipError_t vaxpby(bool dbl, double alpha, const void* a, double beta, const void* b, void* out,
+                  unsigned N, hipStream_t st);
+
+// ---- right-hand side assembly -------------------------------------------------------------
+hipError_t rhs_mass(const double* mass, const double* f, double* rhs, unsigned N, hipStream_t st);
+hipError_t rhs_face(const long long* idx, const double* w, const double* g, double* rhs,
+                    unsigned n, hipStream_t st);
+// rhs -= Ax (fix) on non-top rows; rhs = gD on top rows (gD may be NULL for 0)
+hipError_t rhs_lift(double* rhs, const double* y, const double* S, const double* gD,
+                    unsigned N, unsigned nzn, unsigned P, hipStream_t st);
+hipError_t scatter_top(double* v, const double* gD, unsigned ncols, unsigned nzn, hipStream_t st);
+
+}  // namespace semk

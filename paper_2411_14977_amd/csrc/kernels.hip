@@ -1,0 +1,861 @@
+// gfx950 kernels of the spectral-element pressure-Poisson solver.
+//
+// Operator (paper Sec. 5.2, element matrices summed into the global matrix, eq. globallocal;
+// stiffness read as sum_ab D_a^T G_ab D_b with GLL collocation): applied matrix-free and
+// sum-factorised.  In 2D one workgroup owns one vertical column of Nz elements, so the faces
+// between vertically stacked elements are summed in LDS; the vertical node lines shared by
+// two columns are completed by the consumer from a side buffer (no atomics, no inter-group
+// synchronisation, bitwise deterministic).  One thread owns one vertical line segment (i, ez)
+// of an element: the sigma-direction contractions stay in registers, the x-direction ones go
+// through LDS.  The work is HBM bound (about 1.5-2.2 flop/byte in FP64), so no MFMA is used.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace semk {
+
+// ------------------------------------------------------------------------------------------
+// type helpers
+// ------------------------------------------------------------------------------------------
+template <typename T, typename TG>
+__device__ __forceinline__ T gload(const TG* p);
+template <>
+__device__ __forceinline__ double gload<double, double>(const double* p) { return *p; }
+template <>
+__device__ __forceinline__ float gload<float, float>(const float* p) { return *p; }
+template <>
+__device__ __forceinline__ float gload<float, uint16_t>(const uint16_t* p) {
+  return __uint_as_float(((uint32_t)(*p)) << 16);
+}
+
+static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+// (A x)[g] from the column output y and the side buffer S
+template <typename T>
+__device__ __forceinline__ T ax_at(const T* __restrict__ y, const T* __restrict__ S, unsigned g,
+                                   unsigned nzn, unsigned P) {
+  const unsigned ix = g / nzn;
+  const unsigned iz = g - ix * nzn;
+  T v = y[g];
+  const unsigned q = ix / P;
+  if (q * P == ix) v += S[q * nzn + iz];
+  return v;
+}
+
+// deterministic block reduction (fixed shuffle pattern, fixed LDS tree); all threads get it
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+__device__ double block_sum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < nw; ++k) s += sh[k];
+  return s;
+}
+
+// sum of NRED partials (fixed order), computed identically by every block that calls it
+__device__ double sum_partials(const double* __restrict__ p, double* sh) {
+  double v = 0.0;
+  for (int k = threadIdx.x; k < NRED; k += blockDim.x) v += p[k];
+  return block_sum(v, sh);
+}
+
+// ------------------------------------------------------------------------------------------
+// 2D operator apply
+// ------------------------------------------------------------------------------------------
+template <int P, typename T, typename TG>
+__global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __restrict__ y,
+                                                  T* __restrict__ S, const TG* __restrict__ G,
+                                                  const T* __restrict__ Dg, int Nx, int Nz,
+                                                  int masked, int remap) {
+  constexpr int NP = P + 1;
+  const int nzn = Nz * P + 1;
+  const int ncol = NP * nzn;
+  const int nthr = NP * Nz;
+  int ex = blockIdx.x;
+  if (remap) {  // consecutive columns on the same XCD (blocks are dealt round-robin to 8 XCDs)
+    const int per = gridDim.x >> 3;
+    ex = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* su = reinterpret_cast<T*>(smem_raw);  // [NP][nzn] input column, later the output column
+  T* sw = su + ncol;                        // [Nz][NP(j)][NP(i)]  w_r exchange
+  T* sD = sw + Nz * NP * NP;                // [NP][NP]
+  T* stp = sD + NP * NP;                    // [Nz][NP] element-top values
+  const size_t cbase = (size_t)ex * P * nzn;
+  for (int k = threadIdx.x; k < ncol; k += blockDim.x) su[k] = x[cbase + k];
+  for (int k = threadIdx.x; k < NP * NP; k += blockDim.x) sD[k] = Dg[k];
+  __syncthreads();
+  const int t = threadIdx.x;
+  const bool act = t < nthr;
+  const int i = act ? t % NP : 0;
+  const int ez = act ? t / NP : 0;
+  const bool topel = (ez == Nz - 1);
+  const bool mtop = masked && topel;
+  T u[NP], ws[NP];
+  T xtop = 0;
+  if (act) {
+    const T* col = su + ez * P;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) u[j] = col[i * nzn + j];
+    if (topel) xtop = u[P];
+    if (mtop) u[P] = 0;
+    const TG* Gc = G + (size_t)ex * 3 * NP * nthr + t;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      // reference derivatives at node (i, j): u_r along x through LDS, u_s along sigma in
+      // registers; then the geometric factors (w_r, w_s) = G (u_r, u_s)
+      T ur = 0, us = 0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) ur += sD[i * NP + k] * col[k * nzn + j];
+#pragma unroll
+      for (int k = 0; k < NP; ++k) us += sD[j * NP + k] * u[k];
+      if (j == P && mtop) ur = 0;
+      const T grr = gload<T, TG>(Gc + (0 * NP + j) * nthr);
+      const T grs = gload<T, TG>(Gc + (1 * NP + j) * nthr);
+      const T gss = gload<T, TG>(Gc + (2 * NP + j) * nthr);
+      sw[(ez * NP + j) * NP + i] = grr * ur + grs * us;
+      ws[j] = grs * ur + gss * us;
+    }
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {  // v = D_s^T w_s
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) s += sD[k * NP + j] * ws[k];
+      u[j] = s;
+    }
+  }
+  __syncthreads();
+  if (act) {
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {  // v += D_r^T w_r
+      T s = u[j];
+      const T* wrow = sw + (ez * NP + j) * NP;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) s += sD[k * NP + i] * wrow[k];
+      u[j] = s;
+    }
+    stp[ez * NP + i] = u[P];
+  }
+  __syncthreads();
+  if (act) {
+    if (ez > 0) u[0] += stp[(ez - 1) * NP + i];
+    T* ocol = su + i * nzn + ez * P;
+#pragma unroll
+    for (int j = 0; j < P; ++j) ocol[j] = u[j];
+    if (topel) ocol[P] = masked ? xtop : u[P];
+  }
+  __syncthreads();
+  const int nmain = P * nzn;
+  for (int k = threadIdx.x; k < nmain; k += blockDim.x) y[cbase + k] = su[k];
+  if (ex == Nx - 1) {
+    for (int k = threadIdx.x; k < nzn; k += blockDim.x) y[cbase + nmain + k] = su[nmain + k];
+  } else {
+    for (int k = threadIdx.x; k < nzn; k += blockDim.x) {
+      T v = su[nmain + k];
+      if (masked && k == nzn - 1) v = 0;
+      S[(size_t)(ex + 1) * nzn + k] = v;
+    }
+  }
+}
+
+size_t apply2d_smem(int P, int Nz, bool dbl) {
+  const int NP = P + 1;
+  const size_t n = (size_t)NP * (Nz * P + 1) + (size_t)Nz * NP * NP + NP * NP + (size_t)Nz * NP;
+  return n * (dbl ? 8 : 4);
+}
+
+template <int P, typename T, typename TG>
+static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G, const void* D,
+                                 int Nx, int Nz, int masked, hipStream_t st) {
+  const int nthr = (P + 1) * Nz;
+  const int threads = ((nthr + 63) / 64) * 64;
+  const size_t smem = apply2d_smem(P, Nz, sizeof(T) == 8);
+  const int remap = (Nx % 8 == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_apply2d<P, T, TG>), dim3(Nx), dim3(threads), smem, st,
+                     (const T*)x, (T*)y, (T*)S, (const TG*)G, (const T*)D, Nx, Nz, masked, remap);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
+                            const void* D, int Nx, int Nz, int masked, hipStream_t st) {
+  if (dbl) return launch_apply2d<P, double, double>(x, y, S, G, D, Nx, Nz, masked, st);
+  if (gt == G_BF16) return launch_apply2d<P, float, uint16_t>(x, y, S, G, D, Nx, Nz, masked, st);
+  return launch_apply2d<P, float, float>(x, y, S, G, D, Nx, Nz, masked, st);
+}
+
+hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
+                   const void* D, int Nx, int Nz, int masked, hipStream_t st) {
+  switch (P) {
+    case 1: return apply2d_p<1>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 2: return apply2d_p<2>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 3: return apply2d_p<3>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 4: return apply2d_p<4>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 5: return apply2d_p<5>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 6: return apply2d_p<6>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 7: return apply2d_p<7>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 8: return apply2d_p<8>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 9: return apply2d_p<9>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 10: return apply2d_p<10>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 11: return apply2d_p<11>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 12: return apply2d_p<12>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// element-wise kernels
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_smooth_update(T* __restrict__ x, T* __restrict__ d, const T* __restrict__ b,
+                                const T* __restrict__ dinv, const T* __restrict__ y,
+                                const T* __restrict__ S, unsigned N, unsigned nzn, unsigned P,
+                                T cd, T cr, int from_zero, int store_d) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const T r = from_zero ? b[g] : b[g] - ax_at(y, S, g, nzn, P);
+    T dn = cr * dinv[g] * r;
+    if (cd != (T)0) dn += cd * d[g];
+    if (store_d) d[g] = dn;
+    x[g] = from_zero ? dn : x[g] + dn;
+  }
+}
+
+hipError_t smooth_update(bool dbl, void* x, void* d, const void* b, const void* dinv,
+                         const void* y, const void* S, unsigned N, unsigned nzn, unsigned P,
+                         double cd, double cr, int from_zero, int store_d, hipStream_t st) {
+  const unsigned blocks = nblk(N, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_smooth_update<double>, dim3(blocks), dim3(256), 0, st, (double*)x,
+                       (double*)d, (const double*)b, (const double*)dinv, (const double*)y,
+                       (const double*)S, N, nzn, P, cd, cr, from_zero, store_d);
+  else
+    hipLaunchKernelGGL(k_smooth_update<float>, dim3(blocks), dim3(256), 0, st, (float*)x,
+                       (float*)d, (const float*)b, (const float*)dinv, (const float*)y,
+                       (const float*)S, N, nzn, P, (float)cd, (float)cr, from_zero, store_d);
+  return hipGetLastError();
+}
+
+template <typename T, typename TO>
+__global__ void k_fix_ax(const T* __restrict__ y, const T* __restrict__ S, TO* __restrict__ out,
+                         unsigned N, unsigned nzn, unsigned P) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    out[g] = (TO)ax_at(y, S, g, nzn, P);
+}
+
+hipError_t fix_ax(bool dbl, const void* y, const void* S, void* out, int out64, unsigned N,
+                  unsigned nzn, unsigned P, hipStream_t st) {
+  const unsigned blocks = nblk(N, 256);
+  if (dbl)
+    hipLaunchKernelGGL((k_fix_ax<double, double>), dim3(blocks), dim3(256), 0, st,
+                       (const double*)y, (const double*)S, (double*)out, N, nzn, P);
+  else if (out64)
+    hipLaunchKernelGGL((k_fix_ax<float, double>), dim3(blocks), dim3(256), 0, st,
+                       (const float*)y, (const float*)S, (double*)out, N, nzn, P);
+  else
+    hipLaunchKernelGGL((k_fix_ax<float, float>), dim3(blocks), dim3(256), 0, st,
+                       (const float*)y, (const float*)S, (float*)out, N, nzn, P);
+  return hipGetLastError();
+}
+
+template <typename TS, typename TD>
+__global__ void k_cast(const TS* __restrict__ s, TD* __restrict__ d, unsigned N) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    d[g] = (TD)s[g];
+}
+
+hipError_t cast_to(bool dbl_dst, const double* src, void* dst, unsigned N, hipStream_t st) {
+  if (dbl_dst)
+    hipLaunchKernelGGL((k_cast<double, double>), dim3(nblk(N, 256)), dim3(256), 0, st, src,
+                       (double*)dst, N);
+  else
+    hipLaunchKernelGGL((k_cast<double, float>), dim3(nblk(N, 256)), dim3(256), 0, st, src,
+                       (float*)dst, N);
+  return hipGetLastError();
+}
+
+hipError_t cast_from(bool dbl_src, const void* src, double* dst, unsigned N, hipStream_t st) {
+  if (dbl_src)
+    hipLaunchKernelGGL((k_cast<double, double>), dim3(nblk(N, 256)), dim3(256), 0, st,
+                       (const double*)src, dst, N);
+  else
+    hipLaunchKernelGGL((k_cast<float, double>), dim3(nblk(N, 256)), dim3(256), 0, st,
+                       (const float*)src, dst, N);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_fill(T* __restrict__ p, T v, size_t n) {
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x)
+    p[g] = v;
+}
+
+hipError_t fill(bool dbl, void* p, double v, size_t n, hipStream_t st) {
+  const unsigned blocks = (unsigned)(n < (1u << 20) * 256ull ? nblk(n, 256) : (1u << 20));
+  if (n == 0) return hipSuccess;
+  if (dbl)
+    hipLaunchKernelGGL(k_fill<double>, dim3(blocks), dim3(256), 0, st, (double*)p, v, n);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(blocks), dim3(256), 0, st, (float*)p, (float)v, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// p-transfers (paper Sec. 6.2): prolongation = coarse Lagrange basis at fine GLL nodes
+// (I_Pp = Phi V^{-1}) per direction; restriction = its transpose on assembled vectors.
+// Both in pull form: every output node sums its own inputs, each shared input counted once.
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T pull1d(const T* __restrict__ v, int vstride, int c, int Ne, int Pf,
+                                    int Pc, const T* __restrict__ J) {
+  // coarse node c of a 1D line (Ne elements): sum_f P1[f][c] v[f]
+  int ea = c / Pc;
+  if (ea > Ne - 1) ea = Ne - 1;
+  const int ka = c - ea * Pc;
+  T s = 0;
+  for (int jf = 0; jf <= Pf; ++jf) s += J[jf * (Pc + 1) + ka] * v[(ea * Pf + jf) * vstride];
+  if (ka == 0 && ea > 0)
+    for (int jf = 0; jf < Pf; ++jf) s += J[jf * (Pc + 1) + Pc] * v[((ea - 1) * Pf + jf) * vstride];
+  return s;
+}
+
+template <typename T, typename TC>
+__global__ void k_restrict2d(const T* __restrict__ b, const T* __restrict__ y,
+                             const T* __restrict__ S, int use_ax, TC* __restrict__ rc,
+                             const double* __restrict__ Jg, int Nx, int Nz, int Pf, int Pc,
+                             int masked) {
+  const int ex = blockIdx.x;
+  const int nzf = Nz * Pf + 1, nzc = Nz * Pc + 1;
+  const int L0 = ex > 0 ? (ex - 1) * Pf : 0;
+  const int L1 = ex * Pf + Pf;
+  const int nl = L1 - L0 + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sJ = reinterpret_cast<T*>(smem_raw);  // (Pf+1)(Pc+1)
+  T* rf = sJ + (Pf + 1) * (Pc + 1);        // [nl][nzf]
+  T* tv = rf + nl * nzf;                   // [nl][nzc]
+  for (int k = threadIdx.x; k < (Pf + 1) * (Pc + 1); k += blockDim.x) sJ[k] = (T)Jg[k];
+  for (int k = threadIdx.x; k < nl * nzf; k += blockDim.x) {
+    const int line = L0 + k / nzf;
+    const int iz = k - (k / nzf) * nzf;
+    const unsigned g = (unsigned)line * nzf + iz;
+    T r = b[g];
+    if (use_ax) r -= ax_at(y, S, g, (unsigned)nzf, (unsigned)Pf);
+    if (masked && iz == nzf - 1) r = 0;
+    rf[k] = r;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nl * nzc; k += blockDim.x) {
+    const int li = k / nzc, izc = k - li * nzc;
+    tv[k] = pull1d(rf + li * nzf, 1, izc, Nz, Pf, Pc, sJ);
+  }
+  __syncthreads();
+  const int nown = (ex == Nx - 1) ? Pc + 1 : Pc;
+  for (int k = threadIdx.x; k < nown * nzc; k += blockDim.x) {
+    const int kc = k / nzc, izc = k - kc * nzc;
+    const int ic = ex * Pc + kc;
+    // pull over fine lines; tv holds lines L0.. (local index = fine line - L0)
+    int ea = ic / Pc;
+    if (ea > Nx - 1) ea = Nx - 1;
+    const int ka = ic - ea * Pc;
+    T s = 0;
+    for (int i = 0; i <= Pf; ++i) s += sJ[i * (Pc + 1) + ka] * tv[(ea * Pf + i - L0) * nzc + izc];
+    if (ka == 0 && ea > 0)
+      for (int i = 0; i < Pf; ++i)
+        s += sJ[i * (Pc + 1) + Pc] * tv[((ea - 1) * Pf + i - L0) * nzc + izc];
+    if (masked && izc == nzc - 1) s = 0;
+    rc[(size_t)ic * nzc + izc] = (TC)s;
+  }
+}
+
+size_t restrict2d_smem(int Pf, int Pc, int Nz, bool dbl) {
+  const int nl = 2 * Pf + 1;
+  const size_t n = (size_t)(Pf + 1) * (Pc + 1) + (size_t)nl * (Nz * Pf + 1) + (size_t)nl * (Nz * Pc + 1);
+  return n * (dbl ? 8 : 4);
+}
+
+hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const void* S,
+                      int use_ax, void* rc, const double* J, int Nx, int Nz, int Pf, int Pc,
+                      int masked, hipStream_t st) {
+  const size_t smem = restrict2d_smem(Pf, Pc, Nz, dbl);
+  if (dbl)
+    hipLaunchKernelGGL((k_restrict2d<double, double>), dim3(Nx), dim3(256), smem, st,
+                       (const double*)b, (const double*)y, (const double*)S, use_ax,
+                       (double*)rc, J, Nx, Nz, Pf, Pc, masked);
+  else if (dbl_c)
+    hipLaunchKernelGGL((k_restrict2d<float, double>), dim3(Nx), dim3(256), smem, st,
+                       (const float*)b, (const float*)y, (const float*)S, use_ax, (double*)rc,
+                       J, Nx, Nz, Pf, Pc, masked);
+  else
+    hipLaunchKernelGGL((k_restrict2d<float, float>), dim3(Nx), dim3(256), smem, st,
+                       (const float*)b, (const float*)y, (const float*)S, use_ax, (float*)rc,
+                       J, Nx, Nz, Pf, Pc, masked);
+  return hipGetLastError();
+}
+
+template <typename T, typename TC>
+__global__ void k_prolong2d(const TC* __restrict__ ec, T* __restrict__ xf,
+                            const double* __restrict__ Jg, int Nx, int Nz, int Pf, int Pc) {
+  const int ex = blockIdx.x;
+  const int nzf = Nz * Pf + 1, nzc = Nz * Pc + 1;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sJ = reinterpret_cast<T*>(smem_raw);  // (Pf+1)(Pc+1)
+  T* ce = sJ + (Pf + 1) * (Pc + 1);        // [Pc+1][nzc]
+  T* tv = ce + (Pc + 1) * nzc;             // [Pc+1][nzf]
+  for (int k = threadIdx.x; k < (Pf + 1) * (Pc + 1); k += blockDim.x) sJ[k] = (T)Jg[k];
+  const size_t cb = (size_t)ex * Pc * nzc;
+  for (int k = threadIdx.x; k < (Pc + 1) * nzc; k += blockDim.x) ce[k] = (T)ec[cb + k];
+  __syncthreads();
+  for (int k = threadIdx.x; k < (Pc + 1) * nzf; k += blockDim.x) {
+    const int kc = k / nzf, izf = k - kc * nzf;
+    int e = izf / Pf;
+    if (e > Nz - 1) e = Nz - 1;
+    const int jf = izf - e * Pf;
+    T s = 0;
+    for (int q = 0; q <= Pc; ++q) s += sJ[jf * (Pc + 1) + q] * ce[kc * nzc + e * Pc + q];
+    tv[k] = s;
+  }
+  __syncthreads();
+  const int nown = (ex == Nx - 1) ? Pf + 1 : Pf;
+  const size_t fb = (size_t)ex * Pf * nzf;
+  for (int k = threadIdx.x; k < nown * nzf; k += blockDim.x) {
+    const int i = k / nzf, izf = k - i * nzf;
+    T s = 0;
+    for (int q = 0; q <= Pc; ++q) s += sJ[i * (Pc + 1) + q] * tv[q * nzf + izf];
+    xf[fb + k] += s;
+  }
+}
+
+size_t prolong2d_smem(int Pf, int Pc, int Nz, bool dbl) {
+  const size_t n = (size_t)(Pf + 1) * (Pc + 1) + (size_t)(Pc + 1) * (Nz * Pc + 1) +
+                   (size_t)(Pc + 1) * (Nz * Pf + 1);
+  return n * (dbl ? 8 : 4);
+}
+
+hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
+                     int Nz, int Pf, int Pc, hipStream_t st) {
+  const size_t smem = prolong2d_smem(Pf, Pc, Nz, dbl);
+  if (dbl)
+    hipLaunchKernelGGL((k_prolong2d<double, double>), dim3(Nx), dim3(256), smem, st,
+                       (const double*)ec, (double*)xf, J, Nx, Nz, Pf, Pc);
+  else if (dbl_c)
+    hipLaunchKernelGGL((k_prolong2d<float, double>), dim3(Nx), dim3(256), smem, st,
+                       (const double*)ec, (float*)xf, J, Nx, Nz, Pf, Pc);
+  else
+    hipLaunchKernelGGL((k_prolong2d<float, float>), dim3(Nx), dim3(256), smem, st,
+                       (const float*)ec, (float*)xf, J, Nx, Nz, Pf, Pc);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// exact coarse solve by block cyclic reduction (FP64)
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ void bcr_fwd_item(double* __restrict__ b, const double* __restrict__ F,
+                                             int n, int stride, int bstride,
+                                             const int* __restrict__ rowmap, int nb, int idx) {
+  const int kk = idx / nb, row = idx - kk * nb;
+  const int k = 2 * kk;
+  const size_t i = (size_t)k * stride;
+  const size_t nn = (size_t)nb * nb;
+  const double* Mm = F + (size_t)kk * 2 * nn + (size_t)row * nb;
+  const double* Mp = Mm + nn;
+  double s = b[i * bstride + rowmap[row]];
+  if (k > 0) {
+    const double* bl = b + (i - stride) * bstride;
+    for (int c = 0; c < nb; ++c) s -= Mm[c] * bl[rowmap[c]];
+  }
+  if (k + 1 < n) {
+    const double* br = b + (i + stride) * bstride;
+    for (int c = 0; c < nb; ++c) s -= Mp[c] * br[rowmap[c]];
+  }
+  b[i * bstride + rowmap[row]] = s;
+}
+
+__device__ __forceinline__ void bcr_bwd_item(const double* __restrict__ b, double* __restrict__ x,
+                                             const double* __restrict__ Bk, int n, int stride,
+                                             int bstride, const int* __restrict__ rowmap, int nb,
+                                             int idx) {
+  const int kk = idx / nb, row = idx - kk * nb;
+  const int k = 2 * kk + 1;
+  const size_t i = (size_t)k * stride;
+  const size_t nn = (size_t)nb * nb;
+  const double* DO = Bk + (size_t)kk * 3 * nn + (size_t)row * nb;
+  const double* DL = DO + nn;
+  const double* DU = DL + nn;
+  const double* bi = b + i * bstride;
+  const double* xl = x + (i - stride) * bstride;
+  double s = 0;
+  for (int c = 0; c < nb; ++c) s += DO[c] * bi[rowmap[c]] - DL[c] * xl[rowmap[c]];
+  if (k + 1 < n) {
+    const double* xr = x + (i + stride) * bstride;
+    for (int c = 0; c < nb; ++c) s -= DU[c] * xr[rowmap[c]];
+  }
+  x[i * bstride + rowmap[row]] = s;
+}
+
+__global__ void k_bcr_fwd(double* b, const double* F, int n, int stride, int total, int bstride,
+                          const int* rowmap, int nb) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < total) bcr_fwd_item(b, F, n, stride, bstride, rowmap, nb, idx);
+}
+
+__global__ void k_bcr_bwd(const double* b, double* x, const double* Bk, int n, int stride,
+                          int total, int bstride, const int* rowmap, int nb) {
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < total) bcr_bwd_item(b, x, Bk, n, stride, bstride, rowmap, nb, idx);
+}
+
+__global__ __launch_bounds__(1024) void k_bcr_tail(double* b, double* x, const double* F,
+                                                   const double* Bk, const BcrLevDev* levs,
+                                                   int lfirst, int nlev, const double* last,
+                                                   int bstride, const int* rowmap, int nb) {
+  for (int l = lfirst; l < nlev; ++l) {
+    const BcrLevDev L = levs[l];
+    const int total = L.neven * nb;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x)
+      bcr_fwd_item(b, F + L.offM, L.n, L.stride, bstride, rowmap, nb, idx);
+    __syncthreads();
+  }
+  for (int row = threadIdx.x; row < nb; row += blockDim.x) {
+    double s = 0;
+    for (int c = 0; c < nb; ++c) s += last[row * nb + c] * b[rowmap[c]];
+    x[rowmap[row]] = s;
+  }
+  __syncthreads();
+  for (int l = nlev - 1; l >= lfirst; --l) {
+    const BcrLevDev L = levs[l];
+    const int total = L.nodd * nb;
+    for (int idx = threadIdx.x; idx < total; idx += blockDim.x)
+      bcr_bwd_item(b, x, Bk + L.offB, L.n, L.stride, bstride, rowmap, nb, idx);
+    __syncthreads();
+  }
+}
+
+hipError_t bcr_fwd(double* b, const double* F, int n, int stride, int neven, int bstride,
+                   const int* rowmap, int nb, hipStream_t st) {
+  const int total = neven * nb;
+  hipLaunchKernelGGL(k_bcr_fwd, dim3(nblk(total, 256)), dim3(256), 0, st, b, F, n, stride,
+                     total, bstride, rowmap, nb);
+  return hipGetLastError();
+}
+
+hipError_t bcr_bwd(const double* b, double* x, const double* Bk, int n, int stride, int nodd,
+                   int bstride, const int* rowmap, int nb, hipStream_t st) {
+  const int total = nodd * nb;
+  hipLaunchKernelGGL(k_bcr_bwd, dim3(nblk(total, 256)), dim3(256), 0, st, b, x, Bk, n, stride,
+                     total, bstride, rowmap, nb);
+  return hipGetLastError();
+}
+
+hipError_t bcr_tail(double* b, double* x, const double* F, const double* Bk,
+                    const BcrLevDev* levs, int lfirst, int nlev, const double* last, int bstride,
+                    const int* rowmap, int nb, hipStream_t st) {
+  hipLaunchKernelGGL(k_bcr_tail, dim3(1), dim3(1024), 0, st, b, x, F, Bk, levs, lfirst, nlev,
+                     last, bstride, rowmap, nb);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// FP64 outer-loop kernels.  Every reduction writes NRED block partials in a fixed layout;
+// consumers sum them in a fixed order, so results are bitwise reproducible.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(RED_THREADS) void k_resid64(const double* __restrict__ b,
+                                                         const double* __restrict__ y,
+                                                         const double* __restrict__ S,
+                                                         double* __restrict__ r, double* prr,
+                                                         double* pbb, unsigned N, unsigned nzn,
+                                                         unsigned P) {
+  __shared__ double sh[16];
+  double a = 0, c = 0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const double bv = b[g];
+    const double rv = bv - ax_at(y, S, g, nzn, P);
+    r[g] = rv;
+    a += rv * rv;
+    c += bv * bv;
+  }
+  a = block_sum(a, sh);
+  if (pbb) c = block_sum(c, sh);
+  if (threadIdx.x == 0) {
+    prr[blockIdx.x] = a;
+    if (pbb) pbb[blockIdx.x] = c;
+  }
+}
+
+hipError_t resid64(const double* b, const double* y, const double* S, double* r, double* prr,
+                   double* pbb, unsigned N, unsigned nzn, unsigned P, hipStream_t st) {
+  hipLaunchKernelGGL(k_resid64, dim3(NRED), dim3(RED_THREADS), 0, st, b, y, S, r, prr, pbb, N,
+                     nzn, P);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_fixdot64(const double* __restrict__ y,
+                                                          const double* __restrict__ S,
+                                                          double* __restrict__ q,
+                                                          const double* __restrict__ p,
+                                                          double* ppq, const double* rz_from,
+                                                          double* rz_to, unsigned N,
+                                                          unsigned nzn, unsigned P) {
+  __shared__ double sh[16];
+  double a = 0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const double qv = ax_at(y, S, g, nzn, P);
+    q[g] = qv;
+    a += p[g] * qv;
+  }
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) ppq[blockIdx.x] = a;
+  if (rz_from && blockIdx.x == 0)
+    for (int k = threadIdx.x; k < NRED; k += blockDim.x) rz_to[k] = rz_from[k];
+}
+
+hipError_t fixdot64(const double* y, const double* S, double* q, const double* p, double* ppq,
+                    const double* rz_from, double* rz_to, unsigned N, unsigned nzn, unsigned P,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_fixdot64, dim3(NRED), dim3(RED_THREADS), 0, st, y, S, q, p, ppq, rz_from,
+                     rz_to, N, nzn, P);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_update_xr(double* __restrict__ x,
+                                                           double* __restrict__ r,
+                                                           const double* __restrict__ p,
+                                                           const double* __restrict__ q,
+                                                           const double* prz, const double* ppq,
+                                                           double* prr, unsigned N) {
+  __shared__ double sh[16];
+  const double rz = sum_partials(prz, sh);
+  const double pq = sum_partials(ppq, sh);
+  const double alpha = rz / pq;
+  double a = 0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    x[g] += alpha * p[g];
+    const double rv = r[g] - alpha * q[g];
+    r[g] = rv;
+    a += rv * rv;
+  }
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) prr[blockIdx.x] = a;
+}
+
+hipError_t update_xr(double* x, double* r, const double* p, const double* q, const double* prz,
+                     const double* ppq, double* prr, unsigned N, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xr, dim3(NRED), dim3(RED_THREADS), 0, st, x, r, p, q, prz, ppq,
+                     prr, N);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_reduce_sets(const double* parts, int nsets,
+                                                             double* out) {
+  __shared__ double sh[16];
+  for (int s = 0; s < nsets; ++s) {
+    const double v = sum_partials(parts + (size_t)s * NRED, sh);
+    if (threadIdx.x == 0) out[s] = v;
+    __syncthreads();
+  }
+}
+
+hipError_t reduce_sets(const double* parts, int nsets, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_reduce_sets, dim3(1), dim3(RED_THREADS), 0, st, parts, nsets, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_castdot(const T* __restrict__ x0,
+                                                         double* __restrict__ z,
+                                                         const double* __restrict__ q,
+                                                         const double* __restrict__ r,
+                                                         double* pzq, double* prz, unsigned N) {
+  __shared__ double sh[16];
+  double a = 0, c = 0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const double zv = (double)x0[g];
+    z[g] = zv;
+    if (q) a += zv * q[g];
+    c += r[g] * zv;
+  }
+  if (q) a = block_sum(a, sh);
+  c = block_sum(c, sh);
+  if (threadIdx.x == 0) {
+    if (q) pzq[blockIdx.x] = a;
+    prz[blockIdx.x] = c;
+  }
+}
+
+hipError_t castdot(bool dbl_src, const void* x0, double* z, const double* q, const double* r,
+                   double* pzq, double* prz, unsigned N, hipStream_t st) {
+  if (dbl_src)
+    hipLaunchKernelGGL(k_castdot<double>, dim3(NRED), dim3(RED_THREADS), 0, st,
+                       (const double*)x0, z, q, r, pzq, prz, N);
+  else
+    hipLaunchKernelGGL(k_castdot<float>, dim3(NRED), dim3(RED_THREADS), 0, st, (const float*)x0,
+                       z, q, r, pzq, prz, N);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(RED_THREADS) void k_pupdate(double* __restrict__ p,
+                                                         const double* __restrict__ z,
+                                                         const double* prz_old,
+                                                         const double* ppq, const double* pzq,
+                                                         int first, unsigned N) {
+  __shared__ double sh[16];
+  double beta = 0.0;
+  if (!first) {
+    const double rz = sum_partials(prz_old, sh);
+    const double pq = sum_partials(ppq, sh);
+    const double zq = sum_partials(pzq, sh);
+    const double alpha = rz / pq;
+    beta = -alpha * zq / rz;
+  }
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    p[g] = first ? z[g] : z[g] + beta * p[g];
+}
+
+hipError_t pupdate(double* p, const double* z, const double* prz_old, const double* ppq,
+                   const double* pzq, int first, unsigned N, hipStream_t st) {
+  hipLaunchKernelGGL(k_pupdate, dim3(NRED), dim3(RED_THREADS), 0, st, p, z, prz_old, ppq, pzq,
+                     first, N);
+  return hipGetLastError();
+}
+
+__global__ void k_axpy64(double* __restrict__ x, const double* __restrict__ z, double a,
+                         unsigned N) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    x[g] += a * z[g];
+}
+
+hipError_t axpy64(double* x, const double* z, double a, unsigned N, hipStream_t st) {
+  hipLaunchKernelGGL(k_axpy64, dim3(nblk(N, 256)), dim3(256), 0, st, x, z, a, N);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_top(double* __restrict__ x, const double* __restrict__ src, unsigned ncols,
+                           unsigned nzn) {
+  const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncols) x[(size_t)c * nzn + nzn - 1] = src[(size_t)c * nzn + nzn - 1];
+}
+
+hipError_t copy_top(double* x, const double* src, unsigned ncols, unsigned nzn, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_top, dim3(nblk(ncols, 256)), dim3(256), 0, st, x, src, ncols, nzn);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ __launch_bounds__(RED_THREADS) void k_dot_partial(const T* __restrict__ a,
+                                                             const T* __restrict__ b,
+                                                             double* part, unsigned N) {
+  __shared__ double sh[16];
+  double s = 0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    s += (double)a[g] * (double)b[g];
+  s = block_sum(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+hipError_t dot_partial(bool dbl, const void* a, const void* b, double* part, unsigned N,
+                       hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(k_dot_partial<double>, dim3(NRED), dim3(RED_THREADS), 0, st,
+                       (const double*)a, (const double*)b, part, N);
+  else
+    hipLaunchKernelGGL(k_dot_partial<float>, dim3(NRED), dim3(RED_THREADS), 0, st,
+                       (const float*)a, (const float*)b, part, N);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_vmul(const T* __restrict__ a, const T* __restrict__ s, T* __restrict__ o,
+                       unsigned N) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    o[g] = a[g] * s[g];
+}
+
+hipError_t vmul(bool dbl, const void* a, const void* s, void* out, unsigned N, hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(k_vmul<double>, dim3(nblk(N, 256)), dim3(256), 0, st, (const double*)a,
+                       (const double*)s, (double*)out, N);
+  else
+    hipLaunchKernelGGL(k_vmul<float>, dim3(nblk(N, 256)), dim3(256), 0, st, (const float*)a,
+                       (const float*)s, (float*)out, N);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_vaxpby(T alpha, const T* a, T beta, const T* b, T* o, unsigned N) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    o[g] = alpha * a[g] + beta * b[g];
+}
+
+hipError_t vaxpby(bool dbl, double alpha, const void* a, double beta, const void* b, void* out,
+                  unsigned N, hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(k_vaxpby<double>, dim3(nblk(N, 256)), dim3(256), 0, st, alpha,
+                       (const double*)a, beta, (const double*)b, (double*)out, N);
+  else
+    hipLaunchKernelGGL(k_vaxpby<float>, dim3(nblk(N, 256)), dim3(256), 0, st, (float)alpha,
+                       (const float*)a, (float)beta, (const float*)b, (float*)out, N);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// right-hand side
+// ------------------------------------------------------------------------------------------
+__global__ void k_rhs_mass(const double* __restrict__ m, const double* __restrict__ f,
+                           double* __restrict__ rhs, unsigned N) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    rhs[g] = f ? m[g] * f[g] : 0.0;
+}
+
+hipError_t rhs_mass(const double* mass, const double* f, double* rhs, unsigned N, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_mass, dim3(nblk(N, 256)), dim3(256), 0, st, mass, f, rhs, N);
+  return hipGetLastError();
+}
+
+__global__ void k_rhs_face(const long long* __restrict__ idx, const double* __restrict__ w,
+                           const double* __restrict__ g, double* __restrict__ rhs, unsigned n) {
+  const unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) rhs[idx[k]] += w[k] * g[k];
+}
+
+hipError_t rhs_face(const long long* idx, const double* w, const double* g, double* rhs,
+                    unsigned n, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_face, dim3(nblk(n, 256)), dim3(256), 0, st, idx, w, g, rhs, n);
+  return hipGetLastError();
+}
+
+__global__ void k_rhs_lift(double* __restrict__ rhs, const double* __restrict__ y,
+                           const double* __restrict__ S, const double* __restrict__ gD,
+                           unsigned N, unsigned nzn, unsigned P) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const unsigned col = g / nzn;
+    if (g - col * nzn == nzn - 1) rhs[g] = gD ? gD[col] : 0.0;
+    else rhs[g] -= ax_at(y, S, g, nzn, P);
+  }
+}
+
+hipError_t rhs_lift(double* rhs, const double* y, const double* S, const double* gD, unsigned N,
+                    unsigned nzn, unsigned P, hipStream_t st) {
+  hipLaunchKernelGGL(k_rhs_lift, dim3(nblk(N, 256)), dim3(256), 0, st, rhs, y, S, gD, N, nzn, P);
+  return hipGetLastError();
+}
+
+__global__ void k_scatter_top(double* __restrict__ v, const double* __restrict__ gD,
+                              unsigned ncols, unsigned nzn) {
+  const unsigned c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c < ncols) v[(size_t)c * nzn + nzn - 1] = gD ? gD[c] : 0.0;
+}
+
+hipError_t scatter_top(double* v, const double* gD, unsigned ncols, unsigned nzn, hipStream_t st) {
+  hipLaunchKernelGGL(k_scatter_top, dim3(nblk(ncols, 256)), dim3(256), 0, st, v, gD, ncols, nzn);
+  return hipGetLastError();
+}
+
+}  // namespace semk

@@ -1,0 +1,995 @@
+// C ABI, set-up and solver driver of the MI355X spectral-element pressure-Poisson solver.
+//
+// Set-up (host FP64, then upload): GLL rules and matrices per level, sigma-mapped geometric
+// factors (paper Sec. 2.2 eq. sigtrans / eq. 1_Scoef, Sec. 5.3), assembled inverse diagonals,
+// lambda_hat of D^{-1}A by Lanczos on the device, and the exact block-cyclic-reduction factors of
+// the P = 1 coarse operator.  Solve (device): V-cycles of Sec. 6 inside FP64 flexible CG or
+// defect correction (Sec. 6.4); each outer iteration is one captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sem.h"
+#include "host_math.h"
+#include "kernels.h"
+
+namespace {
+
+using semk::GType;
+
+struct DLevel {
+  int P = 1, NP = 2, Nx = 1, Ny = 1, Nz = 1, nxn = 0, nyn = 1, nzn = 0;
+  unsigned N = 0;
+  bool dbl = true;            // vector/compute type of this level (coarsest is always FP64)
+  GType gt = semk::G_F64;
+  semh::LevelGeom geo;
+  void* G = nullptr;          // factors in storage precision, device column layout
+  void* D = nullptr;          // differentiation matrix in compute precision
+  void* dinv = nullptr;       // inverse assembled diagonal
+  double* J = nullptr;        // prolongation from the next coarser level, (P+1) x (Pc+1)
+  void *x = nullptr, *b = nullptr, *d = nullptr, *y = nullptr, *S = nullptr;
+  size_t nS = 0;
+  double lam = 0.0;
+};
+
+struct Ctx {
+  sem_mesh_desc desc{};
+  int dim = 2, Nx = 1, Ny = 1, Nz = 1, masked = 1;
+  std::vector<DLevel> lev;
+  int prec = SEM_F64;
+  hipStream_t st = nullptr;       // internal stream (default priority)
+  hipStream_t ust = nullptr;      // caller's stream
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  // fine-level FP64 operator for the outer loop
+  double* G64 = nullptr;
+  double* D64 = nullptr;
+  bool G64_owned = false;
+  double *xo = nullptr, *bo = nullptr, *ro = nullptr, *po = nullptr, *qo = nullptr,
+         *zo = nullptr, *yo = nullptr, *So = nullptr, *mass = nullptr;
+  double* parts = nullptr;        // partial-sum sets
+  double* scal = nullptr;         // device scalars
+  double* hscal = nullptr;        // pinned host scalars
+  std::vector<long long*> face_idx;
+  std::vector<double*> face_w;
+  std::vector<size_t> face_n;
+  // coarse solve
+  semh::BcrPlan plan;
+  double *bcrF = nullptr, *bcrB = nullptr, *bcrLast = nullptr;
+  int* rowmap = nullptr;
+  semk::BcrLevDev* bcrLevs = nullptr;
+  int bcr_tail_first = 0;
+  // graphs
+  hipGraphExec_t g_first = nullptr, g_iter = nullptr, g_pdc = nullptr;
+  bool use_graphs = true;
+  std::string err;
+  bool sticky = false;
+  std::vector<void*> allocs;
+};
+
+enum { PS_RR = 0, PS_BB, PS_PQ, PS_RZA, PS_RZB, PS_ZQ, PS_TMP, PS_NSETS };
+
+struct HipFail {
+  hipError_t e;
+  const char* what;
+};
+
+#define HK(call)                                   \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) throw HipFail{e_, #call}; \
+  } while (0)
+
+struct ArgFail {
+  std::string msg;
+};
+
+void* dalloc(Ctx* c, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 8;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
+  c->allocs.push_back(p);
+  HK(hipMemsetAsync(p, 0, bytes, c->st));
+  return p;
+}
+
+template <typename T>
+T* upload(Ctx* c, const std::vector<T>& h) {
+  T* p = (T*)dalloc(c, h.size() * sizeof(T));
+  HK(hipMemcpyAsync(p, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, c->st));
+  HK(hipStreamSynchronize(c->st));
+  return p;
+}
+
+size_t esz(bool dbl) { return dbl ? 8 : 4; }
+
+// natural [f][e][i*NP+j] -> device [ex][f][j][ez*NP+i]
+template <typename TG, typename Conv>
+std::vector<TG> permute_G2d(const semh::LevelGeom& L, const std::vector<double>& G, Conv conv) {
+  const int NP = L.NP, Nz = L.Nz, Nx = L.Nx;
+  const size_t NL = NP * NP, nthr = (size_t)NP * Nz;
+  std::vector<TG> out((size_t)3 * L.E * NL);
+  for (int ex = 0; ex < Nx; ++ex)
+    for (int f = 0; f < 3; ++f)
+      for (int j = 0; j < NP; ++j)
+        for (int ez = 0; ez < Nz; ++ez)
+          for (int i = 0; i < NP; ++i) {
+            const size_t e = (size_t)ex * Nz + ez;
+            out[(((size_t)ex * 3 + f) * NP + j) * nthr + ez * NP + i] =
+                conv(G[f * L.E * NL + e * NL + i * NP + j]);
+          }
+  return out;
+}
+
+void set_err(Ctx* c, const std::string& s) { c->err = s; }
+
+// ------------------------------------------------------------------------------------------
+// enqueue helpers
+// ------------------------------------------------------------------------------------------
+void apply_level(Ctx* c, int l, const void* x, int masked) {
+  DLevel& L = c->lev[l];
+  HK(semk::apply2d(L.P, L.dbl, L.gt, x, L.y, L.S, L.G, L.D, L.Nx, L.Nz, masked, c->st));
+}
+
+void apply_outer(Ctx* c, const double* x, int masked) {
+  DLevel& L = c->lev[0];
+  HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, c->D64, L.Nx, L.Nz, masked,
+                   c->st));
+}
+
+void smooth(Ctx* c, int l, bool pre) {
+  DLevel& L = c->lev[l];
+  const sem_mesh_desc& d = c->desc;
+  if (d.smoother == SEM_SMOOTH_JACOBI) {
+    const int nu = pre ? d.nu_pre : d.nu_post;
+    for (int s = 0; s < nu; ++s) {
+      const bool fz = pre && s == 0;
+      if (!fz) apply_level(c, l, L.x, c->masked);
+      HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, 0.0,
+                             d.jacobi_omega, fz ? 1 : 0, 0, c->st));
+    }
+    return;
+  }
+  const double a = d.cheb_lo * L.lam, b = d.cheb_hi * L.lam;
+  const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+  const double sigma1 = theta / delta;
+  double rho = 1.0 / sigma1;
+  const int k = d.cheb_degree;
+  if (!pre) apply_level(c, l, L.x, c->masked);
+  HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, 0.0,
+                         1.0 / theta, pre ? 1 : 0, k > 1 ? 1 : 0, c->st));
+  for (int j = 1; j < k; ++j) {
+    const double rho_new = 1.0 / (2.0 * sigma1 - rho);
+    apply_level(c, l, L.x, c->masked);
+    HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P,
+                           rho_new * rho, 2.0 * rho_new / delta, 0, j + 1 < k ? 1 : 0, c->st));
+    rho = rho_new;
+  }
+}
+
+void restrict_to(Ctx* c, int l, bool use_ax) {
+  DLevel& F = c->lev[l];
+  DLevel& C = c->lev[l + 1];
+  HK(semk::restrict2d(F.dbl, C.dbl, F.b, F.y, F.S, use_ax ? 1 : 0, C.b, F.J, F.Nx, F.Nz, F.P,
+                      C.P, c->masked, c->st));
+}
+
+void prolong_from(Ctx* c, int l) {
+  DLevel& F = c->lev[l];
+  DLevel& C = c->lev[l + 1];
+  HK(semk::prolong2d(F.dbl, C.dbl, C.x, F.x, F.J, F.Nx, F.Nz, F.P, C.P, c->st));
+}
+
+void coarse_solve(Ctx* c) {
+  DLevel& L = c->lev.back();
+  double* b = (double*)L.b;
+  double* x = (double*)L.x;
+  const semh::BcrPlan& pl = c->plan;
+  const int nl = (int)pl.levs.size();
+  const int lt = c->bcr_tail_first;
+  for (int l = 0; l < lt; ++l) {
+    const auto& v = pl.levs[l];
+    HK(semk::bcr_fwd(b, c->bcrF + v.offM, v.n, v.stride, v.neven, pl.bstride, c->rowmap, pl.nb,
+                     c->st));
+  }
+  HK(semk::bcr_tail(b, x, c->bcrF, c->bcrB, c->bcrLevs, lt, nl, c->bcrLast, pl.bstride,
+                    c->rowmap, pl.nb, c->st));
+  for (int l = lt - 1; l >= 0; --l) {
+    const auto& v = pl.levs[l];
+    HK(semk::bcr_bwd(b, x, c->bcrB + v.offB, v.n, v.stride, v.nodd, pl.bstride, c->rowmap,
+                     pl.nb, c->st));
+  }
+}
+
+// z = B b on level 0 buffers: input lev[0].b, output lev[0].x
+void vcycle(Ctx* c) {
+  const int L = (int)c->lev.size();
+  if (L == 1) {
+    coarse_solve(c);
+    return;
+  }
+  for (int l = 0; l < L - 1; ++l) {
+    smooth(c, l, true);
+    apply_level(c, l, c->lev[l].x, c->masked);
+    restrict_to(c, l, true);
+  }
+  coarse_solve(c);
+  for (int l = L - 2; l >= 0; --l) {
+    prolong_from(c, l);
+    smooth(c, l, false);
+  }
+}
+
+double* pset(Ctx* c, int s) { return c->parts + (size_t)s * semk::NRED; }
+
+// one FPCG iteration (see sem.h): V-cycle on r, direction update, outer FP64 apply, x/r update
+void fpcg_iteration(Ctx* c, bool first) {
+  DLevel& L0 = c->lev[0];
+  const unsigned N = L0.N;
+  HK(semk::cast_to(L0.dbl, c->ro, L0.b, N, c->st));
+  vcycle(c);
+  HK(semk::castdot(L0.dbl, L0.x, c->zo, first ? nullptr : c->qo, c->ro, pset(c, PS_ZQ),
+                   pset(c, PS_RZB), N, c->st));
+  HK(semk::pupdate(c->po, c->zo, pset(c, PS_RZA), pset(c, PS_PQ), pset(c, PS_ZQ), first ? 1 : 0,
+                   N, c->st));
+  apply_outer(c, c->po, c->masked);
+  HK(semk::fixdot64(c->yo, c->So, c->qo, c->po, pset(c, PS_PQ), pset(c, PS_RZB), pset(c, PS_RZA),
+                    N, L0.nzn, L0.P, c->st));
+  HK(semk::update_xr(c->xo, c->ro, c->po, c->qo, pset(c, PS_RZA), pset(c, PS_PQ),
+                     pset(c, PS_RR), N, c->st));
+  HK(semk::reduce_sets(c->parts, PS_NSETS, c->scal, c->st));
+}
+
+void pdc_iteration(Ctx* c) {
+  DLevel& L0 = c->lev[0];
+  const unsigned N = L0.N;
+  HK(semk::cast_to(L0.dbl, c->ro, L0.b, N, c->st));
+  vcycle(c);
+  HK(semk::cast_from(L0.dbl, L0.x, c->zo, N, c->st));
+  HK(semk::axpy64(c->xo, c->zo, 1.0, N, c->st));
+  apply_outer(c, c->xo, c->masked);
+  HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), nullptr, N, L0.nzn, L0.P, c->st));
+  HK(semk::reduce_sets(c->parts, PS_NSETS, c->scal, c->st));
+}
+
+void drop_graphs(Ctx* c) {
+  if (c->g_first) (void)hipGraphExecDestroy(c->g_first);
+  if (c->g_iter) (void)hipGraphExecDestroy(c->g_iter);
+  if (c->g_pdc) (void)hipGraphExecDestroy(c->g_pdc);
+  c->g_first = c->g_iter = c->g_pdc = nullptr;
+}
+
+template <typename F>
+hipGraphExec_t capture(Ctx* c, F body) {
+  hipGraph_t g = nullptr;
+  HK(hipStreamBeginCapture(c->st, hipStreamCaptureModeThreadLocal));
+  try {
+    body();
+  } catch (...) {
+    hipGraph_t tmp = nullptr;
+    (void)hipStreamEndCapture(c->st, &tmp);
+    if (tmp) (void)hipGraphDestroy(tmp);
+    throw;
+  }
+  HK(hipStreamEndCapture(c->st, &g));
+  hipGraphExec_t ex = nullptr;
+  hipError_t e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  if (e != hipSuccess) throw HipFail{e, "hipGraphInstantiate"};
+  return ex;
+}
+
+// ------------------------------------------------------------------------------------------
+// set-up
+// ------------------------------------------------------------------------------------------
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  // largest eigenvalue of the symmetric tridiagonal (diag a, off-diag b) by bisection on the
+  // Sturm count
+  const int n = (int)a.size();
+  double lo = 1e300, hi = -1e300;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  auto count_below = [&](double x) {  // eigenvalues < x
+    int cnt = 0;
+    double q = a[0] - x;
+    if (q < 0) ++cnt;
+    for (int i = 1; i < n; ++i) {
+      if (q == 0.0) q = 1e-300;
+      q = a[i] - x - b[i - 1] * b[i - 1] / q;
+      if (q < 0) ++cnt;
+    }
+    return cnt;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (count_below(mid) >= n) hi = mid;
+    else lo = mid;
+  }
+  return hi;
+}
+
+double host_sum_partials(Ctx* c, int set) {
+  std::vector<double> h(semk::NRED);
+  HK(hipMemcpyAsync(h.data(), pset(c, set), semk::NRED * sizeof(double), hipMemcpyDeviceToHost,
+                    c->st));
+  HK(hipStreamSynchronize(c->st));
+  double s = 0;
+  for (double v : h) s += v;
+  return s;
+}
+
+void lanczos(Ctx* c, int l) {
+  DLevel& L = c->lev[l];
+  const unsigned N = L.N;
+  const bool dbl = L.dbl;
+  const int steps = std::max(2, c->desc.lanczos_steps);
+  // start vector: SplitMix64 on free nodes; sqrt(dinv)
+  std::vector<double> v0(N), sq(N);
+  std::vector<double> dinv_h(N);
+  void* s = dalloc(c, N * esz(dbl));
+  void* q = dalloc(c, N * esz(dbl));
+  void* qp = dalloc(c, N * esz(dbl));
+  void* w = dalloc(c, N * esz(dbl));
+  void* tmp = dalloc(c, N * esz(dbl));
+  // sqrt of dinv computed on the host from the device copy
+  if (dbl) {
+    HK(hipMemcpy(dinv_h.data(), L.dinv, N * 8, hipMemcpyDeviceToHost));
+  } else {
+    std::vector<float> f(N);
+    HK(hipMemcpy(f.data(), L.dinv, N * 4, hipMemcpyDeviceToHost));
+    for (unsigned g = 0; g < N; ++g) dinv_h[g] = f[g];
+  }
+  double nrm = 0;
+  for (unsigned g = 0; g < N; ++g) {
+    const bool top = c->masked && (g % L.nzn) == (unsigned)(L.nzn - 1);
+    v0[g] = top ? 0.0 : semh::splitmix64_uniform(c->desc.lanczos_seed, g);
+    nrm += v0[g] * v0[g];
+    sq[g] = std::sqrt(dinv_h[g]);
+  }
+  nrm = std::sqrt(nrm);
+  for (auto& v : v0) v /= nrm;
+  auto put = [&](void* dst, const std::vector<double>& h) {
+    if (dbl) {
+      HK(hipMemcpy(dst, h.data(), N * 8, hipMemcpyHostToDevice));
+    } else {
+      std::vector<float> f(h.begin(), h.end());
+      HK(hipMemcpy(dst, f.data(), N * 4, hipMemcpyHostToDevice));
+    }
+  };
+  put(s, sq);
+  put(q, v0);
+  std::vector<double> al, be;
+  double beta = 0.0;
+  for (int k = 0; k < steps; ++k) {
+    HK(semk::vmul(dbl, q, s, tmp, N, c->st));
+    apply_level(c, l, tmp, c->masked);
+    HK(semk::fix_ax(dbl, L.y, L.S, w, 0, N, L.nzn, L.P, c->st));
+    HK(semk::vmul(dbl, w, s, w, N, c->st));
+    HK(semk::dot_partial(dbl, q, w, pset(c, PS_TMP), N, c->st));
+    const double alpha = host_sum_partials(c, PS_TMP);
+    HK(semk::vaxpby(dbl, 1.0, w, -alpha, q, w, N, c->st));
+    if (k > 0) HK(semk::vaxpby(dbl, 1.0, w, -beta, qp, w, N, c->st));
+    al.push_back(alpha);
+    HK(semk::dot_partial(dbl, w, w, pset(c, PS_TMP), N, c->st));
+    beta = std::sqrt(std::max(0.0, host_sum_partials(c, PS_TMP)));
+    if (k == steps - 1 || beta == 0.0) break;
+    be.push_back(beta);
+    std::swap(qp, q);
+    HK(semk::vaxpby(dbl, 1.0 / beta, w, 0.0, w, q, N, c->st));
+  }
+  be.resize(al.size() > 0 ? al.size() - 1 : 0);
+  L.lam = tridiag_max_eig(al, be);
+  HK(hipStreamSynchronize(c->st));
+}
+
+void setup_impl(Ctx* c, const sem_mesh_desc* d) {
+  c->desc = *d;
+  c->desc.h = nullptr;
+  c->desc.eta = nullptr;
+  c->dim = d->dim;
+  if (d->dim != 2) throw ArgFail{"only dim = 2 is supported by this build of the library"};
+  c->Nx = d->ne[0];
+  c->Nz = d->ne[2];
+  c->Ny = 1;
+  if (c->Nx < 1 || c->Nz < 1) throw ArgFail{"ne must be positive"};
+  if (d->order < 1 || d->order > SEM_MAX_ORDER) throw ArgFail{"order out of range"};
+  if (!d->h || !d->eta) throw ArgFail{"h and eta are required"};
+  if (d->len[0] <= 0) throw ArgFail{"len[0] must be positive"};
+  c->masked = (d->dirichlet_faces & SEM_FACE_TOP) ? 1 : 0;
+  c->prec = d->inner_prec;
+  if (c->prec < SEM_F64 || c->prec > SEM_F32_GBF16) throw ArgFail{"bad inner_prec"};
+  if (d->smoother != SEM_SMOOTH_JACOBI && d->smoother != SEM_SMOOTH_CHEBYSHEV)
+    throw ArgFail{"bad smoother"};
+  if (d->outer != SEM_OUTER_FPCG && d->outer != SEM_OUTER_PDC) throw ArgFail{"bad outer"};
+  if (d->smoother == SEM_SMOOTH_CHEBYSHEV &&
+      (d->cheb_degree < 1 || !(d->cheb_hi > d->cheb_lo) || d->cheb_lo <= 0))
+    throw ArgFail{"bad Chebyshev parameters"};
+  if (d->smoother == SEM_SMOOTH_JACOBI && (d->nu_pre < 0 || d->nu_post < 0))
+    throw ArgFail{"bad sweep counts"};
+  std::vector<int> orders;
+  if (d->nlevels <= 0) {
+    orders.push_back(d->order);
+    while (orders.back() > 1) orders.push_back((orders.back() + 1) / 2);
+  } else {
+    if (d->nlevels > SEM_MAX_LEVELS) throw ArgFail{"too many levels"};
+    for (int k = 0; k < d->nlevels; ++k) orders.push_back(d->level_order[k]);
+    if (orders[0] != d->order) throw ArgFail{"level_order[0] must equal order"};
+    if (orders.back() != 1) throw ArgFail{"last level order must be 1"};
+    for (size_t k = 1; k < orders.size(); ++k)
+      if (orders[k] >= orders[k - 1] || orders[k] < 1) throw ArgFail{"level orders must decrease"};
+  }
+  if ((orders[0] + 1) * c->Nz > 1024) throw ArgFail{"(P+1)*ne[2] must not exceed 1024"};
+  if (c->Nz > 256) throw ArgFail{"ne[2] too large for the coarse solve"};
+  const double N64 = (double)(c->Nx * orders[0] + 1) * (c->Nz * orders[0] + 1);
+  if (N64 > 2.0e9) throw ArgFail{"problem too large"};
+
+  c->ust = (hipStream_t)d->stream;
+  HK(hipStreamCreate(&c->st));
+  HK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+  HK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  const char* ng = std::getenv("SEM_NO_GRAPH");
+  c->use_graphs = !(ng && ng[0] == '1');
+
+  const int nl = (int)orders.size();
+  c->lev.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    DLevel& L = c->lev[l];
+    semh::build_level(L.geo, 2, c->Nx, 1, c->Nz, orders[l], orders[0], d->len[0], 1.0, d->h,
+                      d->eta);
+    L.P = orders[l];
+    L.NP = L.P + 1;
+    L.Nx = c->Nx;
+    L.Nz = c->Nz;
+    L.nxn = L.geo.nxn;
+    L.nzn = L.geo.nzn;
+    L.N = (unsigned)L.geo.N;
+    const bool coarsest = (l == nl - 1);
+    L.dbl = coarsest || c->prec == SEM_F64;
+    L.gt = L.dbl ? semk::G_F64 : (c->prec == SEM_F32_GBF16 ? semk::G_BF16 : semk::G_F32);
+    // factors in storage precision; the diagonal is built from the same rounded values
+    std::vector<double> Gr = L.geo.G;
+    if (L.gt == semk::G_F32)
+      for (auto& v : Gr) v = (double)(float)v;
+    else if (L.gt == semk::G_BF16)
+      for (auto& v : Gr) v = semh::bf16_round(v);
+    if (L.gt == semk::G_F64) {
+      L.G = upload(c, permute_G2d<double>(L.geo, L.geo.G, [](double v) { return v; }));
+    } else if (L.gt == semk::G_F32) {
+      L.G = upload(c, permute_G2d<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
+    } else {
+      L.G = upload(c, permute_G2d<uint16_t>(L.geo, L.geo.G,
+                                            [](double v) { return semh::bf16_bits((float)v); }));
+    }
+    std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
+    std::vector<double> dinv(diag.size());
+    for (size_t g = 0; g < diag.size(); ++g) dinv[g] = 1.0 / diag[g];
+    if (L.dbl) {
+      L.dinv = upload(c, dinv);
+      L.D = upload(c, L.geo.D);
+    } else {
+      L.dinv = upload(c, std::vector<float>(dinv.begin(), dinv.end()));
+      L.D = upload(c, std::vector<float>(L.geo.D.begin(), L.geo.D.end()));
+    }
+    const size_t eb = esz(L.dbl);
+    L.x = dalloc(c, L.N * eb);
+    L.b = dalloc(c, L.N * eb);
+    L.d = dalloc(c, L.N * eb);
+    L.y = dalloc(c, L.N * eb);
+    L.nS = (size_t)(c->Nx + 1) * L.nzn;
+    L.S = dalloc(c, L.nS * eb);
+  }
+  for (int l = 0; l + 1 < nl; ++l) {
+    DLevel& F = c->lev[l];
+    DLevel& C = c->lev[l + 1];
+    F.J = upload(c, semh::interp_matrix(C.geo.r, F.geo.r));
+    if (semk::restrict2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024 ||
+        semk::prolong2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024)
+      throw ArgFail{"transfer kernels exceed LDS for this size"};
+  }
+  if (semk::apply2d_smem(orders[0], c->Nz, true) > 160 * 1024)
+    throw ArgFail{"operator kernel exceeds LDS for this size"};
+  // outer FP64 operator
+  DLevel& L0 = c->lev[0];
+  if (L0.dbl) {
+    c->G64 = (double*)L0.G;
+    c->D64 = (double*)L0.D;
+  } else {
+    c->G64 = upload(c, permute_G2d<double>(L0.geo, L0.geo.G, [](double v) { return v; }));
+    c->D64 = upload(c, L0.geo.D);
+  }
+  const size_t N = L0.N;
+  c->xo = (double*)dalloc(c, N * 8);
+  c->bo = (double*)dalloc(c, N * 8);
+  c->ro = (double*)dalloc(c, N * 8);
+  c->po = (double*)dalloc(c, N * 8);
+  c->qo = (double*)dalloc(c, N * 8);
+  c->zo = (double*)dalloc(c, N * 8);
+  c->yo = (double*)dalloc(c, N * 8);
+  c->So = (double*)dalloc(c, L0.nS * 8);
+  c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
+  c->scal = (double*)dalloc(c, 64 * 8);
+  HK(hipHostMalloc((void**)&c->hscal, 64 * 8, hipHostMallocDefault));
+  // lumped mass and Neumann faces of the fine level
+  {
+    std::vector<double> m(N, 0.0);
+    const semh::LevelGeom& G = L0.geo;
+    const int NP = G.NP;
+    for (size_t e = 0; e < G.E; ++e) {
+      const size_t ex = e / G.Nz, ez = e % G.Nz;
+      for (int i = 0; i < NP; ++i)
+        for (int j = 0; j < NP; ++j)
+          m[(ex * G.P + i) * G.nzn + ez * G.P + j] += G.mass[e * NP * NP + i * NP + j];
+    }
+    c->mass = upload(c, m);
+    for (size_t f = 0; f < G.face_idx.size(); ++f) {
+      std::vector<long long> idx(G.face_idx[f].begin(), G.face_idx[f].end());
+      c->face_idx.push_back(upload(c, idx));
+      c->face_w.push_back(upload(c, G.face_w[f]));
+      c->face_n.push_back(idx.size());
+    }
+  }
+  // coarse factorisation
+  {
+    DLevel& LC = c->lev.back();
+    char eb[256] = {0};
+    if (c->masked) {
+      if (!semh::build_bcr(LC.geo, LC.geo.G, c->plan, eb, sizeof eb)) throw ArgFail{eb};
+      c->bcrF = upload(c, c->plan.fwd.empty() ? std::vector<double>(1, 0.0) : c->plan.fwd);
+      c->bcrB = upload(c, c->plan.bwd.empty() ? std::vector<double>(1, 0.0) : c->plan.bwd);
+      c->bcrLast = upload(c, c->plan.last);
+      c->rowmap = upload(c, c->plan.rowmap);
+      std::vector<semk::BcrLevDev> lv;
+      int lt = (int)c->plan.levs.size();
+      for (size_t k = 0; k < c->plan.levs.size(); ++k) {
+        const auto& v = c->plan.levs[k];
+        lv.push_back({v.n, v.stride, (long long)v.offM, (long long)v.offB, v.neven, v.nodd});
+        if (v.n <= 128 && lt == (int)c->plan.levs.size()) lt = (int)k;
+      }
+      if (lv.empty()) lv.push_back({1, 1, 0, 0, 0, 0});
+      c->bcrLevs = upload(c, lv);
+      c->bcr_tail_first = lt;
+    }
+  }
+  // lambda_hat per smoothed level
+  if (c->masked)
+    for (int l = 0; l + 1 < nl; ++l) lanczos(c, l);
+  HK(hipStreamSynchronize(c->st));
+}
+
+// stream ordering with the caller
+void enter(Ctx* c) {
+  HK(hipEventRecord(c->ev_in, c->ust));
+  HK(hipStreamWaitEvent(c->st, c->ev_in, 0));
+}
+void leave(Ctx* c) {
+  HK(hipEventRecord(c->ev_out, c->st));
+  HK(hipStreamWaitEvent(c->ust, c->ev_out, 0));
+}
+
+template <typename F>
+sem_status guarded(Ctx* c, F body) {
+  if (!c) return SEM_ERR_ARG;
+  if (c->sticky) {
+    return SEM_ERR_HIP;
+  }
+  try {
+    c->err.clear();
+    return body();
+  } catch (const HipFail& f) {
+    c->sticky = true;
+    c->err = std::string("HIP error in ") + f.what + ": " + hipGetErrorString(f.e);
+    return SEM_ERR_HIP;
+  } catch (const ArgFail& a) {
+    c->err = a.msg;
+    return SEM_ERR_ARG;
+  } catch (const std::bad_alloc&) {
+    c->err = "host allocation failed";
+    return SEM_ERR_ALLOC;
+  } catch (...) {
+    c->err = "unexpected internal error";
+    return SEM_ERR_STATE;
+  }
+}
+
+void release(Ctx* c) {
+  if (!c) return;
+  if (c->st) (void)hipStreamSynchronize(c->st);
+  drop_graphs(c);
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->hscal) (void)hipHostFree(c->hscal);
+  c->hscal = nullptr;
+  if (c->ev_in) (void)hipEventDestroy(c->ev_in);
+  if (c->ev_out) (void)hipEventDestroy(c->ev_out);
+  c->ev_in = c->ev_out = nullptr;
+  if (c->st) (void)hipStreamDestroy(c->st);
+  c->st = nullptr;
+}
+
+}  // namespace
+
+struct sem_ctx {
+  Ctx c;
+};
+
+static thread_local char g_setup_err[512] = {0};
+
+static Ctx* C(sem_ctx* p) { return p ? &p->c : nullptr; }
+static const Ctx* C(const sem_ctx* p) { return p ? &p->c : nullptr; }
+
+extern "C" {
+
+void sem_mesh_desc_default(sem_mesh_desc* d) {
+  if (!d) return;
+  std::memset(d, 0, sizeof(*d));
+  d->dim = 2;
+  d->ne[0] = d->ne[1] = d->ne[2] = 1;
+  d->order = 4;
+  d->nlevels = 0;
+  d->len[0] = d->len[1] = 1.0;
+  d->dirichlet_faces = SEM_FACE_TOP;
+  d->inner_prec = SEM_F64;
+  d->smoother = SEM_SMOOTH_CHEBYSHEV;
+  d->nu_pre = 2;
+  d->nu_post = 2;
+  d->cheb_degree = 3;
+  d->jacobi_omega = 2.0 / 3.0;
+  d->cheb_lo = 0.1;
+  d->cheb_hi = 1.1;
+  d->outer = SEM_OUTER_FPCG;
+  d->maxit = 500;
+  d->lanczos_steps = 20;
+  d->lanczos_seed = 12345ull;
+  d->stream = nullptr;
+}
+
+sem_status sem_mesh_setup(const sem_mesh_desc* desc, sem_ctx** out) {
+  if (!desc || !out) return SEM_ERR_ARG;
+  *out = nullptr;
+  sem_ctx* h = nullptr;
+  g_setup_err[0] = 0;
+  try {
+    h = new sem_ctx();
+  } catch (...) {
+    return SEM_ERR_ALLOC;
+  }
+  Ctx* c = &h->c;
+  try {
+    setup_impl(c, desc);
+  } catch (const HipFail& f) {
+    std::snprintf(g_setup_err, sizeof g_setup_err, "HIP error in %s: %s", f.what,
+                  hipGetErrorString(f.e));
+    release(c);
+    delete h;
+    return SEM_ERR_HIP;
+  } catch (const ArgFail& a) {
+    std::snprintf(g_setup_err, sizeof g_setup_err, "%s", a.msg.c_str());
+    release(c);
+    delete h;
+    return SEM_ERR_ARG;
+  } catch (const std::bad_alloc&) {
+    std::snprintf(g_setup_err, sizeof g_setup_err, "host allocation failed");
+    release(c);
+    delete h;
+    return SEM_ERR_ALLOC;
+  }
+  *out = h;
+  return SEM_OK;
+}
+
+void sem_destroy(sem_ctx* ctx) {
+  if (!ctx) return;
+  release(&ctx->c);
+  delete ctx;
+}
+
+sem_status sem_get_sizes(const sem_ctx* ctx, size_t* n_global, size_t* n_free, size_t* n_local) {
+  const Ctx* c = C(ctx);
+  if (!c) return SEM_ERR_ARG;
+  const DLevel& L = c->lev[0];
+  if (n_global) *n_global = L.N;
+  if (n_free) *n_free = L.N - (c->masked ? (size_t)L.nxn * L.nyn : 0);
+  if (n_local) *n_local = L.geo.E * (size_t)std::pow(L.NP, c->dim);
+  return SEM_OK;
+}
+
+sem_status sem_get_level(const sem_ctx* ctx, int level, int* order, size_t* n, double* lam) {
+  const Ctx* c = C(ctx);
+  if (!c) return SEM_ERR_ARG;
+  if (level < 0 || level >= (int)c->lev.size()) return SEM_ERR_ARG;
+  const DLevel& L = c->lev[level];
+  if (order) *order = L.P;
+  if (n) *n = L.N;
+  if (lam) *lam = L.lam;
+  return SEM_OK;
+}
+
+int sem_num_levels(const sem_ctx* ctx) {
+  const Ctx* c = C(ctx);
+  return c ? (int)c->lev.size() : 0;
+}
+
+sem_status sem_gll(int P, double* nodes, double* weights) {
+  if (P < 1 || P > 64) return SEM_ERR_ARG;
+  std::vector<double> r, w;
+  semh::gll_rule(P, r, w);
+  if (nodes) std::memcpy(nodes, r.data(), r.size() * 8);
+  if (weights) std::memcpy(weights, w.data(), w.size() * 8);
+  return SEM_OK;
+}
+
+sem_status sem_node_coords(const sem_ctx* ctx, int level, double* x, double* y, double* z) {
+  const Ctx* c = C(ctx);
+  if (!c) return SEM_ERR_ARG;
+  if (level < 0 || level >= (int)c->lev.size()) return SEM_ERR_ARG;
+  const semh::LevelGeom& G = c->lev[level].geo;
+  if (x) std::memcpy(x, G.X.data(), G.N * 8);
+  if (z) std::memcpy(z, G.Z.data(), G.N * 8);
+  if (y && !G.Y.empty()) std::memcpy(y, G.Y.data(), G.N * 8);
+  return SEM_OK;
+}
+
+sem_status sem_apply_laplacian(sem_ctx* ctx, const double* x, double* y) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!x || !y || x == y) throw ArgFail{"x, y must be distinct device pointers"};
+    enter(c);
+    apply_outer(c, x, c->masked);
+    DLevel& L = c->lev[0];
+    HK(semk::fix_ax(true, c->yo, c->So, y, 1, L.N, L.nzn, L.P, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_apply_level(sem_ctx* ctx, int level, const double* x, double* y) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (level < 0 || level >= (int)c->lev.size()) throw ArgFail{"bad level"};
+    if (!x || !y || x == y) throw ArgFail{"x, y must be distinct device pointers"};
+    enter(c);
+    DLevel& L = c->lev[level];
+    HK(semk::cast_to(L.dbl, x, L.d, L.N, c->st));
+    apply_level(c, level, L.d, c->masked);
+    HK(semk::fix_ax(L.dbl, L.y, L.S, y, 1, L.N, L.nzn, L.P, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_pmg_vcycle(sem_ctx* ctx, const double* r, double* z) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!c->masked) return SEM_ERR_STATE;
+    if (!r || !z) throw ArgFail{"null vector"};
+    enter(c);
+    DLevel& L0 = c->lev[0];
+    HK(semk::cast_to(L0.dbl, r, L0.b, L0.N, c->st));
+    vcycle(c);
+    HK(semk::cast_from(L0.dbl, L0.x, z, L0.N, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_set_smoother_bounds(sem_ctx* ctx, int level, double lambda_hat) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (level < 0 || level + 1 >= (int)c->lev.size()) throw ArgFail{"bad level"};
+    if (!(lambda_hat > 0) || !std::isfinite(lambda_hat)) throw ArgFail{"bad lambda_hat"};
+    HK(hipStreamSynchronize(c->st));
+    c->lev[level].lam = lambda_hat;
+    drop_graphs(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_restrict(sem_ctx* ctx, int level, const double* b, const double* x, double* rc) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (level < 0 || level + 1 >= (int)c->lev.size()) throw ArgFail{"bad level"};
+    if (!b || !rc) throw ArgFail{"null vector"};
+    enter(c);
+    DLevel& F = c->lev[level];
+    DLevel& Cc = c->lev[level + 1];
+    HK(semk::cast_to(F.dbl, b, F.b, F.N, c->st));
+    if (x) {
+      HK(semk::cast_to(F.dbl, x, F.x, F.N, c->st));
+      apply_level(c, level, F.x, c->masked);
+    }
+    restrict_to(c, level, x != nullptr);
+    HK(semk::cast_from(Cc.dbl, Cc.b, rc, Cc.N, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_prolong_add(sem_ctx* ctx, int level, const double* ec, double* xf) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (level < 0 || level + 1 >= (int)c->lev.size()) throw ArgFail{"bad level"};
+    if (!ec || !xf) throw ArgFail{"null vector"};
+    enter(c);
+    DLevel& F = c->lev[level];
+    DLevel& Cc = c->lev[level + 1];
+    HK(semk::cast_to(Cc.dbl, ec, Cc.x, Cc.N, c->st));
+    HK(semk::cast_to(F.dbl, xf, F.x, F.N, c->st));
+    prolong_from(c, level);
+    HK(semk::cast_from(F.dbl, F.x, xf, F.N, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_smooth(sem_ctx* ctx, int level, int pre, const double* b, double* x) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (level < 0 || level + 1 >= (int)c->lev.size()) throw ArgFail{"bad level"};
+    if (!b || !x) throw ArgFail{"null vector"};
+    enter(c);
+    DLevel& L = c->lev[level];
+    HK(semk::cast_to(L.dbl, b, L.b, L.N, c->st));
+    if (!pre) HK(semk::cast_to(L.dbl, x, L.x, L.N, c->st));
+    smooth(c, level, pre != 0);
+    HK(semk::cast_from(L.dbl, L.x, x, L.N, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_coarse_solve(sem_ctx* ctx, const double* b, double* x) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!c->masked) return SEM_ERR_STATE;
+    if (!b || !x) throw ArgFail{"null vector"};
+    enter(c);
+    DLevel& L = c->lev.back();
+    HK(hipMemcpyAsync(L.b, b, L.N * 8, hipMemcpyDeviceToDevice, c->st));
+    coarse_solve(c);
+    HK(hipMemcpyAsync(x, L.x, L.N * 8, hipMemcpyDeviceToDevice, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_assemble_rhs(sem_ctx* ctx, const double* f, const double* gN, const double* gD,
+                            double* rhs) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!rhs) throw ArgFail{"null rhs"};
+    enter(c);
+    DLevel& L = c->lev[0];
+    const unsigned N = L.N;
+    HK(semk::rhs_mass(c->mass, f, rhs, N, c->st));
+    if (gN) {
+      size_t off = 0;
+      for (size_t k = 0; k < c->face_idx.size(); ++k) {
+        HK(semk::rhs_face(c->face_idx[k], c->face_w[k], gN + off, rhs, (unsigned)c->face_n[k],
+                          c->st));
+        off += c->face_n[k];
+      }
+    }
+    if (c->masked) {
+      if (gD) {
+        HK(semk::fill(true, c->zo, 0.0, N, c->st));
+        HK(semk::scatter_top(c->zo, gD, L.nxn, L.nzn, c->st));
+        apply_outer(c, c->zo, 0);
+        HK(semk::rhs_lift(rhs, c->yo, c->So, gD, N, L.nzn, L.P, c->st));
+      } else {
+        HK(semk::scatter_top(rhs, nullptr, L.nxn, L.nzn, c->st));
+      }
+    }
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double tol,
+                             sem_solve_info* info) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!c->masked) return SEM_ERR_STATE;
+    if (!rhs || !x || rhs == x) throw ArgFail{"rhs and x must be distinct device pointers"};
+    if (!(tol >= 0)) throw ArgFail{"bad tol"};
+    sem_solve_info loc{};
+    sem_solve_info* inf = info ? info : &loc;
+    std::memset(inf, 0, sizeof(*inf));
+    enter(c);
+    DLevel& L0 = c->lev[0];
+    const unsigned N = L0.N;
+    HK(hipMemcpyAsync(c->bo, rhs, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
+    HK(hipMemcpyAsync(c->xo, x, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
+    HK(semk::copy_top(c->xo, c->bo, L0.nxn, L0.nzn, c->st));
+    apply_outer(c, c->xo, c->masked);
+    HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn, L0.P,
+                     c->st));
+    HK(semk::reduce_sets(c->parts, PS_NSETS, c->scal, c->st));
+    HK(hipMemcpyAsync(c->hscal, c->scal, PS_NSETS * 8, hipMemcpyDeviceToHost, c->st));
+    HK(hipStreamSynchronize(c->st));
+    const double bb = c->hscal[PS_BB];
+    double rel = bb > 0 ? std::sqrt(c->hscal[PS_RR] / bb) : 0.0;
+    auto push = [&](double v) {
+      if (inf->nhist < 512) inf->hist[inf->nhist++] = v;
+    };
+    push(rel);
+    sem_status st = SEM_OK;
+    if (!(bb > 0)) {
+      // zero right-hand side: the solution is zero
+      HK(semk::fill(true, c->xo, 0.0, N, c->st));
+      rel = 0.0;
+    } else if (!std::isfinite(rel)) {
+      st = SEM_ERR_BREAKDOWN;
+      set_err(c, "non-finite initial residual");
+    }
+    const bool fpcg = c->desc.outer == SEM_OUTER_FPCG;
+    int it = 0;
+    while (st == SEM_OK && rel > tol) {
+      if (it >= c->desc.maxit) {
+        st = SEM_ERR_NOT_CONVERGED;
+        set_err(c, "maximum number of outer iterations reached");
+        break;
+      }
+      const bool first = (it == 0);
+      if (c->use_graphs) {
+        hipGraphExec_t* slot = fpcg ? (first ? &c->g_first : &c->g_iter) : &c->g_pdc;
+        if (!*slot)
+          *slot = capture(c, [&]() {
+            if (fpcg) fpcg_iteration(c, first);
+            else pdc_iteration(c);
+          });
+        HK(hipGraphLaunch(*slot, c->st));
+      } else {
+        if (fpcg) fpcg_iteration(c, first);
+        else pdc_iteration(c);
+      }
+      HK(hipMemcpyAsync(c->hscal, c->scal, PS_NSETS * 8, hipMemcpyDeviceToHost, c->st));
+      HK(hipStreamSynchronize(c->st));
+      ++it;
+      inf->vcycles++;
+      rel = std::sqrt(c->hscal[PS_RR] / bb);
+      push(rel);
+      if (!std::isfinite(rel) || (fpcg && !(c->hscal[PS_PQ] > 0))) {
+        st = SEM_ERR_BREAKDOWN;
+        set_err(c, "breakdown in the outer iteration (non-finite residual or p.Ap <= 0)");
+      }
+    }
+    HK(hipMemcpyAsync(x, c->xo, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
+    leave(c);
+    HK(hipStreamSynchronize(c->st));
+    inf->iters = it;
+    inf->rel_res = rel;
+    inf->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return st;
+  });
+}
+
+const char* sem_last_error(const sem_ctx* ctx) {
+  const Ctx* c = C(ctx);
+  return c ? c->err.c_str() : g_setup_err;
+}
+
+const char* sem_status_string(sem_status s) {
+  switch (s) {
+    case SEM_OK: return "SEM_OK";
+    case SEM_ERR_ARG: return "SEM_ERR_ARG";
+    case SEM_ERR_ALLOC: return "SEM_ERR_ALLOC";
+    case SEM_ERR_HIP: return "SEM_ERR_HIP";
+    case SEM_ERR_NOT_CONVERGED: return "SEM_ERR_NOT_CONVERGED";
+    case SEM_ERR_BREAKDOWN: return "SEM_ERR_BREAKDOWN";
+    case SEM_ERR_STATE: return "SEM_ERR_STATE";
+  }
+  return "unknown";
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and rejects bad
+descriptors before touching the GPU.  No GPU compute is called here."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import gll
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_2411_14977_amd", "libsem.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libsem.so not built")
+
+
+def declared_symbols():
+    names = set()
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names |= set(re.findall(r"\b(sem_[a-z0-9_]+)\s*\(", src))
+    return sorted(names)
+
+
+def test_exports_every_declared_symbol():
+    lib = ctypes.CDLL(LIB)
+    names = declared_symbols()
+    assert "sem_poisson_solve" in names and "sem_mesh_setup" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_bad_descriptors_are_rejected_before_gpu_use():
+    from paper_2411_14977_amd import binding as B
+    cases = []
+    d = B.sem_mesh_desc_default()
+    d.order = 0
+    cases.append(d)
+    d = B.sem_mesh_desc_default()
+    d.order = 13
+    cases.append(d)
+    d = B.sem_mesh_desc_default()   # no h / eta
+    cases.append(d)
+    h = np.ones(9)
+    for mutate in (lambda d: setattr(d, "inner_prec", 7), lambda d: setattr(d, "outer", 3),
+                   lambda d: setattr(d, "smoother", 9), lambda d: setattr(d, "cheb_lo", -1.0)):
+        d = B.sem_mesh_desc_default()
+        d.order, d.ne[0], d.ne[2] = 4, 2, 2
+        d.h = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.eta = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        mutate(d)
+        cases.append(d)
+    for d in cases:
+        with pytest.raises(B.SemError) as e:
+            B.sem_mesh_setup(d)
+        assert e.value.status == 1
+
+
+@pytest.mark.parametrize("P", [1, 2, 5, 8, 12])
+def test_library_gll_rule_matches_oracle(P):
+    from paper_2411_14977_amd import binding as B
+    r, w = B.sem_gll(P)
+    assert np.abs(r - gll.gll_nodes(P)).max() < 1e-15
+    assert np.abs(w - gll.gll_weights(P)).max() < 1e-14
