@@ -171,6 +171,19 @@ sem_status sem_prolong_add(sem_ctx *ctx, int level, const double *ec, double *xf
 sem_status sem_smooth(sem_ctx *ctx, int level, int pre, const double *b, double *x);
 sem_status sem_coarse_solve(sem_ctx *ctx, const double *b, double *x);
 
+/* Benchmark hook: launch the operator kernel of level l (outer = 1: the fine-level FP64
+ * operator of the outer loop; outer = 0: the level's inner-precision operator) reps times on
+ * the context's stream, bracketed by HIP events recorded on that stream, and return the
+ * average time per launch in *ms_avg.  flush = 1 overwrites a 512 MiB device buffer before
+ * every launch (cold caches) and times each launch separately.  Inputs are the level's own
+ * work vectors; results are discarded.  Synchronises the stream. */
+sem_status sem_time_operator(sem_ctx *ctx, int level, int outer, int reps, int flush,
+                             double *ms_avg);
+
+/* Algorithmic bytes of one operator launch on level l (vectors read + written once, every
+ * geometric factor read once), in the precision selected by outer (see sem_time_operator). */
+sem_status sem_operator_bytes(const sem_ctx *ctx, int level, int outer, double *bytes);
+
 /* Text of the last error on this context ("" if none).  Valid until the next call. */
 const char *sem_last_error(const sem_ctx *ctx);
 

@@ -12,5 +12,6 @@ from .binding import (  # noqa: F401
     sem_apply_level, sem_assemble_rhs, sem_coarse_solve, sem_destroy, sem_get_level,
     sem_get_sizes, sem_gll, sem_mesh_desc_default, sem_mesh_setup, sem_node_coords,
     sem_num_levels, sem_pmg_vcycle, sem_poisson_solve, sem_prolong_add, sem_restrict,
-    sem_set_smoother_bounds, sem_smooth, fine_x_nodes,
+    sem_set_smoother_bounds, sem_smooth, fine_x_nodes, sem_time_operator,
+    sem_operator_bytes,
 )

@@ -89,6 +89,8 @@ def lib():
         "sem_prolong_add": (ctypes.c_int, [vp, ip, dp, dp]),
         "sem_smooth": (ctypes.c_int, [vp, ip, ip, dp, dp]),
         "sem_coarse_solve": (ctypes.c_int, [vp, dp, dp]),
+        "sem_time_operator": (ctypes.c_int, [vp, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_double)]),
+        "sem_operator_bytes": (ctypes.c_int, [vp, ip, ip, ctypes.POINTER(ctypes.c_double)]),
         "sem_last_error": (ctypes.c_char_p, [vp]),
         "sem_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -215,6 +217,18 @@ def sem_smooth(ctx, level, pre, b, x):
 
 def sem_coarse_solve(ctx, b, x):
     _check(ctx, lib().sem_coarse_solve(ctx, _ptr(b), _ptr(x)))
+
+
+def sem_time_operator(ctx, level, outer, reps, flush):
+    ms = ctypes.c_double()
+    _check(ctx, lib().sem_time_operator(ctx, level, outer, reps, flush, ctypes.byref(ms)))
+    return ms.value
+
+
+def sem_operator_bytes(ctx, level, outer):
+    b = ctypes.c_double()
+    _check(ctx, lib().sem_operator_bytes(ctx, level, outer, ctypes.byref(b)))
+    return b.value
 
 
 # ---- convenience owner of one context -------------------------------------------------------

@@ -507,7 +507,7 @@ static void matmul(int n, const double* A, const double* B, double* C) {  // C =
 }
 
 bool build_bcr(const LevelGeom& L, const std::vector<double>& Gr, BcrPlan& plan, char* err,
-               size_t errlen) {
+               size_t errlen, int dense_max) {
   // Blocks = x-lines (ix).  Free rows of a block: all (iy, iz) with iz < Nz P.
   const int nb = L.dim == 2 ? (L.nzn - 1) : L.nyn * (L.nzn - 1);
   const int nblocks = L.nxn;
@@ -554,7 +554,7 @@ bool build_bcr(const LevelGeom& L, const std::vector<double>& Gr, BcrPlan& plan,
   plan.bwd.clear();
   int n = nblocks, stride = 1;
   std::vector<double> Dinv(nn), T1(nn), T2(nn);
-  while (n > 1) {
+  while (n > dense_max) {
     BcrPlan::Lev lv;
     lv.n = n;
     lv.stride = stride;
@@ -613,11 +613,24 @@ bool build_bcr(const LevelGeom& L, const std::vector<double>& Gr, BcrPlan& plan,
     n = nn2;
     stride *= 2;
   }
-  plan.last.assign(nn, 0.0);
-  if (!dense_inverse(nb, &Dg[0], plan.last.data())) {
-    snprintf(err, errlen, "singular final block in coarse reduction");
+  // explicit inverse of the remaining block tridiagonal system (n blocks)
+  const int nd = n * nb;
+  std::vector<double> Ad((size_t)nd * nd, 0.0);
+  for (int k = 0; k < n; ++k)
+    for (int r = 0; r < nb; ++r)
+      for (int q = 0; q < nb; ++q) {
+        Ad[(size_t)(k * nb + r) * nd + k * nb + q] = Dg[k * nn + r * nb + q];
+        if (k > 0) Ad[(size_t)(k * nb + r) * nd + (k - 1) * nb + q] = Lg[k * nn + r * nb + q];
+        if (k + 1 < n) Ad[(size_t)(k * nb + r) * nd + (k + 1) * nb + q] = Ug[k * nn + r * nb + q];
+      }
+  plan.dense.assign((size_t)nd * nd, 0.0);
+  if (!dense_inverse(nd, Ad.data(), plan.dense.data())) {
+    snprintf(err, errlen, "singular reduced coarse system");
     return false;
   }
+  plan.dense_n = n;
+  plan.dense_stride = stride;
+  plan.last.assign(nn, 0.0);
   return true;
 }
 

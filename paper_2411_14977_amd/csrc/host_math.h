@@ -67,12 +67,16 @@ struct BcrPlan {
   std::vector<Lev> levs;       // reduction levels (n > 1)
   std::vector<double> fwd;     // per level: neven x {Mm, Mp} nb x nb
   std::vector<double> bwd;     // per level: nodd x {DO, DL, DU} nb x nb
-  std::vector<double> last;    // inverse of the final block, nb x nb
+  std::vector<double> last;    // inverse of the final block, nb x nb (unused when dense)
+  // the reduction stops once at most `dense_max` blocks remain; the remaining reduced system
+  // (dense_n blocks, spaced dense_stride apart at level 0) is solved with its explicit inverse
+  int dense_n = 0, dense_stride = 1;
+  std::vector<double> dense;   // (dense_n nb) x (dense_n nb), row-major
   // map from block-row (b, r) to the level-vector index: b * bstride + rowmap[r]
   std::vector<int> rowmap;
 };
 bool build_bcr(const LevelGeom& L, const std::vector<double>& Gr, BcrPlan& plan, char* err,
-               size_t errlen);
+               size_t errlen, int dense_max = 65);
 
 // Counter-based SplitMix64 uniform in [-1, 1) (Steele, Lea, Flood 2014), element i of seed.
 double splitmix64_uniform(uint64_t seed, uint64_t i);

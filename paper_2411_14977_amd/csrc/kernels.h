@@ -26,6 +26,10 @@ hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, c
 hipError_t smooth_update(bool dbl, void* x, void* d, const void* b, const void* dinv,
                          const void* y, const void* S, unsigned N, unsigned nzn, unsigned P,
                          double cd, double cr, int from_zero, int store_d, hipStream_t st);
+// first step of a V-cycle's pre-smoothing from x = 0, right-hand side taken from FP64 r64
+// (stored rounded into b): d = cr dinv b, x = d
+hipError_t smooth_first64(bool dbl, void* x, void* d, void* b, const double* r64,
+                          const void* dinv, unsigned N, double cr, int store_d, hipStream_t st);
 // out = (Ax)[g] with the side-buffer fix (test hook / Lanczos), widened to double if out64
 hipError_t fix_ax(bool dbl, const void* y, const void* S, void* out, int out64, unsigned N,
                   unsigned nzn, unsigned P, hipStream_t st);
@@ -45,14 +49,13 @@ hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const doubl
                      int Nz, int Pf, int Pc, hipStream_t st);
 
 // ---- exact coarse solve (block cyclic reduction, FP64, in place on b, result in x) ---------
-struct BcrLevDev { int n, stride; long long offM, offB; int neven, nodd; };
+// unknown r of block blk sits at blk * bstride + r + r / nzf (nzf = free nodes per line)
 hipError_t bcr_fwd(double* b, const double* F, int n, int stride, int neven, int bstride,
-                   const int* rowmap, int nb, hipStream_t st);
+                   int nzf, int nb, hipStream_t st);
 hipError_t bcr_bwd(const double* b, double* x, const double* Bk, int n, int stride, int nodd,
-                   int bstride, const int* rowmap, int nb, hipStream_t st);
-hipError_t bcr_tail(double* b, double* x, const double* F, const double* Bk,
-                    const BcrLevDev* levs, int lfirst, int nlev, const double* last,
-                    int bstride, const int* rowmap, int nb, hipStream_t st);
+                   int bstride, int nzf, int nb, hipStream_t st);
+hipError_t bcr_dense(const double* Ainv, const double* b, double* x, int nd, int nb, int stride,
+                     int bstride, int nzf, hipStream_t st);
 
 // ---- FP64 outer-loop kernels (deterministic two-stage reductions over NRED partials) -------
 // r = b - Ax (with fix); partial sums of r.r into prr and (if pbb) b.b into pbb

@@ -244,6 +244,33 @@ hipError_t smooth_update(bool dbl, void* x, void* d, const void* b, const void* 
   return hipGetLastError();
 }
 
+// first smoothing step of a V-cycle from x = 0 with the right-hand side given in FP64:
+// b = (T) r64;  d = cr dinv b;  x = d
+template <typename T>
+__global__ void k_smooth_first64(T* __restrict__ x, T* __restrict__ d, T* __restrict__ b,
+                                 const double* __restrict__ r64, const T* __restrict__ dinv,
+                                 unsigned N, T cr, int store_d) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const T bv = (T)r64[g];
+    b[g] = bv;
+    const T dn = cr * dinv[g] * bv;
+    if (store_d) d[g] = dn;
+    x[g] = dn;
+  }
+}
+
+hipError_t smooth_first64(bool dbl, void* x, void* d, void* b, const double* r64,
+                          const void* dinv, unsigned N, double cr, int store_d, hipStream_t st) {
+  const unsigned blocks = nblk(N, 256);
+  if (dbl)
+    hipLaunchKernelGGL(k_smooth_first64<double>, dim3(blocks), dim3(256), 0, st, (double*)x,
+                       (double*)d, (double*)b, r64, (const double*)dinv, N, cr, store_d);
+  else
+    hipLaunchKernelGGL(k_smooth_first64<float>, dim3(blocks), dim3(256), 0, st, (float*)x,
+                       (float*)d, (float*)b, r64, (const float*)dinv, N, (float)cr, store_d);
+  return hipGetLastError();
+}
+
 template <typename T, typename TO>
 __global__ void k_fix_ax(const T* __restrict__ y, const T* __restrict__ S, TO* __restrict__ out,
                          unsigned N, unsigned nzn, unsigned P) {
@@ -458,108 +485,108 @@ hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const doubl
 // ------------------------------------------------------------------------------------------
 // exact coarse solve by block cyclic reduction (FP64)
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ void bcr_fwd_item(double* __restrict__ b, const double* __restrict__ F,
-                                             int n, int stride, int bstride,
-                                             const int* __restrict__ rowmap, int nb, int idx) {
-  const int kk = idx / nb, row = idx - kk * nb;
-  const int k = 2 * kk;
-  const size_t i = (size_t)k * stride;
-  const size_t nn = (size_t)nb * nb;
-  const double* Mm = F + (size_t)kk * 2 * nn + (size_t)row * nb;
-  const double* Mp = Mm + nn;
-  double s = b[i * bstride + rowmap[row]];
-  if (k > 0) {
-    const double* bl = b + (i - stride) * bstride;
-    for (int c = 0; c < nb; ++c) s -= Mm[c] * bl[rowmap[c]];
-  }
-  if (k + 1 < n) {
-    const double* br = b + (i + stride) * bstride;
-    for (int c = 0; c < nb; ++c) s -= Mp[c] * br[rowmap[c]];
-  }
-  b[i * bstride + rowmap[row]] = s;
+// Level-vector position of unknown r of a block: the free rows of a block skip the top
+// (Dirichlet) node of every vertical line, so r -> r + r / (nzn - 1).
+__device__ __forceinline__ size_t bpos(size_t blk, int bstride, int r, int nzf) {
+  return blk * bstride + r + r / nzf;
 }
 
-__device__ __forceinline__ void bcr_bwd_item(const double* __restrict__ b, double* __restrict__ x,
-                                             const double* __restrict__ Bk, int n, int stride,
-                                             int bstride, const int* __restrict__ rowmap, int nb,
-                                             int idx) {
-  const int kk = idx / nb, row = idx - kk * nb;
-  const int k = 2 * kk + 1;
-  const size_t i = (size_t)k * stride;
-  const size_t nn = (size_t)nb * nb;
-  const double* DO = Bk + (size_t)kk * 3 * nn + (size_t)row * nb;
-  const double* DL = DO + nn;
-  const double* DU = DL + nn;
-  const double* bi = b + i * bstride;
-  const double* xl = x + (i - stride) * bstride;
-  double s = 0;
-  for (int c = 0; c < nb; ++c) s += DO[c] * bi[rowmap[c]] - DL[c] * xl[rowmap[c]];
-  if (k + 1 < n) {
-    const double* xr = x + (i + stride) * bstride;
-    for (int c = 0; c < nb; ++c) s -= DU[c] * xr[rowmap[c]];
+// 4 lanes per (block, row): lane q sums columns q, q+4, ...; fixed-order 4-lane reduction
+__global__ __launch_bounds__(256) void k_bcr_fwd(double* __restrict__ b,
+                                                 const double* __restrict__ F, int n, int stride,
+                                                 int total, int bstride, int nzf, int nb) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = t >> 2, q = t & 3;
+  const bool act = idx < total;
+  double s = 0.0;
+  size_t self = 0;
+  if (act) {
+    const int kk = idx / nb, row = idx - kk * nb;
+    const int k = 2 * kk;
+    const size_t i = (size_t)k * stride;
+    const size_t nn = (size_t)nb * nb;
+    const double* Mm = F + (size_t)kk * 2 * nn + (size_t)row * nb;
+    const double* Mp = Mm + nn;
+    self = bpos(i, bstride, row, nzf);
+    if (k > 0)
+      for (int c = q; c < nb; c += 4) s += Mm[c] * b[bpos(i - stride, bstride, c, nzf)];
+    if (k + 1 < n)
+      for (int c = q; c < nb; c += 4) s += Mp[c] * b[bpos(i + stride, bstride, c, nzf)];
   }
-  x[i * bstride + rowmap[row]] = s;
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  if (act && q == 0) b[self] -= s;
 }
 
-__global__ void k_bcr_fwd(double* b, const double* F, int n, int stride, int total, int bstride,
-                          const int* rowmap, int nb) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < total) bcr_fwd_item(b, F, n, stride, bstride, rowmap, nb, idx);
+__global__ __launch_bounds__(256) void k_bcr_bwd(const double* __restrict__ b,
+                                                 double* __restrict__ x,
+                                                 const double* __restrict__ Bk, int n, int stride,
+                                                 int total, int bstride, int nzf, int nb) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  const int idx = t >> 2, q = t & 3;
+  const bool act = idx < total;
+  double s = 0.0;
+  size_t self = 0;
+  if (act) {
+    const int kk = idx / nb, row = idx - kk * nb;
+    const int k = 2 * kk + 1;
+    const size_t i = (size_t)k * stride;
+    const size_t nn = (size_t)nb * nb;
+    const double* DO = Bk + (size_t)kk * 3 * nn + (size_t)row * nb;
+    const double* DL = DO + nn;
+    const double* DU = DL + nn;
+    self = bpos(i, bstride, row, nzf);
+    for (int c = q; c < nb; c += 4)
+      s += DO[c] * b[bpos(i, bstride, c, nzf)] - DL[c] * x[bpos(i - stride, bstride, c, nzf)];
+    if (k + 1 < n)
+      for (int c = q; c < nb; c += 4) s -= DU[c] * x[bpos(i + stride, bstride, c, nzf)];
+  }
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  if (act && q == 0) x[self] = s;
 }
 
-__global__ void k_bcr_bwd(const double* b, double* x, const double* Bk, int n, int stride,
-                          int total, int bstride, const int* rowmap, int nb) {
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < total) bcr_bwd_item(b, x, Bk, n, stride, bstride, rowmap, nb, idx);
+// x at the reduced positions = Ainv b (one wave per row, fixed-order wave reduction)
+__global__ __launch_bounds__(256) void k_bcr_dense(const double* __restrict__ Ainv,
+                                                   const double* __restrict__ b,
+                                                   double* __restrict__ x, int nd, int nb,
+                                                   int stride, int bstride, int nzf) {
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (row >= nd) return;
+  const double* a = Ainv + (size_t)row * nd;
+  double s = 0.0;
+  for (int c = lane; c < nd; c += 64) {
+    const int k = c / nb, r = c - k * nb;
+    s += a[c] * b[bpos((size_t)k * stride, bstride, r, nzf)];
+  }
+  s = wave_sum(s);
+  if (lane == 0) {
+    const int k = row / nb, r = row - k * nb;
+    x[bpos((size_t)k * stride, bstride, r, nzf)] = s;
+  }
 }
 
-__global__ __launch_bounds__(1024) void k_bcr_tail(double* b, double* x, const double* F,
-                                                   const double* Bk, const BcrLevDev* levs,
-                                                   int lfirst, int nlev, const double* last,
-                                                   int bstride, const int* rowmap, int nb) {
-  for (int l = lfirst; l < nlev; ++l) {
-    const BcrLevDev L = levs[l];
-    const int total = L.neven * nb;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x)
-      bcr_fwd_item(b, F + L.offM, L.n, L.stride, bstride, rowmap, nb, idx);
-    __syncthreads();
-  }
-  for (int row = threadIdx.x; row < nb; row += blockDim.x) {
-    double s = 0;
-    for (int c = 0; c < nb; ++c) s += last[row * nb + c] * b[rowmap[c]];
-    x[rowmap[row]] = s;
-  }
-  __syncthreads();
-  for (int l = nlev - 1; l >= lfirst; --l) {
-    const BcrLevDev L = levs[l];
-    const int total = L.nodd * nb;
-    for (int idx = threadIdx.x; idx < total; idx += blockDim.x)
-      bcr_bwd_item(b, x, Bk + L.offB, L.n, L.stride, bstride, rowmap, nb, idx);
-    __syncthreads();
-  }
+hipError_t bcr_dense(const double* Ainv, const double* b, double* x, int nd, int nb, int stride,
+                     int bstride, int nzf, hipStream_t st) {
+  hipLaunchKernelGGL(k_bcr_dense, dim3(nblk(nd, 4)), dim3(256), 0, st, Ainv, b, x, nd, nb, stride,
+                     bstride, nzf);
+  return hipGetLastError();
 }
 
 hipError_t bcr_fwd(double* b, const double* F, int n, int stride, int neven, int bstride,
-                   const int* rowmap, int nb, hipStream_t st) {
+                   int nzf, int nb, hipStream_t st) {
   const int total = neven * nb;
-  hipLaunchKernelGGL(k_bcr_fwd, dim3(nblk(total, 256)), dim3(256), 0, st, b, F, n, stride,
-                     total, bstride, rowmap, nb);
+  hipLaunchKernelGGL(k_bcr_fwd, dim3(nblk((size_t)total * 4, 256)), dim3(256), 0, st, b, F, n,
+                     stride, total, bstride, nzf, nb);
   return hipGetLastError();
 }
 
 hipError_t bcr_bwd(const double* b, double* x, const double* Bk, int n, int stride, int nodd,
-                   int bstride, const int* rowmap, int nb, hipStream_t st) {
+                   int bstride, int nzf, int nb, hipStream_t st) {
   const int total = nodd * nb;
-  hipLaunchKernelGGL(k_bcr_bwd, dim3(nblk(total, 256)), dim3(256), 0, st, b, x, Bk, n, stride,
-                     total, bstride, rowmap, nb);
-  return hipGetLastError();
-}
-
-hipError_t bcr_tail(double* b, double* x, const double* F, const double* Bk,
-                    const BcrLevDev* levs, int lfirst, int nlev, const double* last, int bstride,
-                    const int* rowmap, int nb, hipStream_t st) {
-  hipLaunchKernelGGL(k_bcr_tail, dim3(1), dim3(1024), 0, st, b, x, F, Bk, levs, lfirst, nlev,
-                     last, bstride, rowmap, nb);
+  hipLaunchKernelGGL(k_bcr_bwd, dim3(nblk((size_t)total * 4, 256)), dim3(256), 0, st, b, x, Bk,
+                     n, stride, total, bstride, nzf, nb);
   return hipGetLastError();
 }
 

@@ -61,10 +61,10 @@ struct Ctx {
   std::vector<size_t> face_n;
   // coarse solve
   semh::BcrPlan plan;
-  double *bcrF = nullptr, *bcrB = nullptr, *bcrLast = nullptr;
+  double *bcrF = nullptr, *bcrB = nullptr, *bcrLast = nullptr, *bcrDense = nullptr;
   int* rowmap = nullptr;
-  semk::BcrLevDev* bcrLevs = nullptr;
-  int bcr_tail_first = 0;
+  // FP64 right-hand side of the next V-cycle, read by the first smoothing step of level 0
+  const double* vin64 = nullptr;
   // graphs
   hipGraphExec_t g_first = nullptr, g_iter = nullptr, g_pdc = nullptr;
   bool use_graphs = true;
@@ -151,6 +151,11 @@ void smooth(Ctx* c, int l, bool pre) {
     const int nu = pre ? d.nu_pre : d.nu_post;
     for (int s = 0; s < nu; ++s) {
       const bool fz = pre && s == 0;
+      if (fz && l == 0 && c->vin64) {
+        HK(semk::smooth_first64(L.dbl, L.x, L.d, L.b, c->vin64, L.dinv, L.N, d.jacobi_omega, 0,
+                                c->st));
+        continue;
+      }
       if (!fz) apply_level(c, l, L.x, c->masked);
       HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, 0.0,
                              d.jacobi_omega, fz ? 1 : 0, 0, c->st));
@@ -163,8 +168,12 @@ void smooth(Ctx* c, int l, bool pre) {
   double rho = 1.0 / sigma1;
   const int k = d.cheb_degree;
   if (!pre) apply_level(c, l, L.x, c->masked);
-  HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, 0.0,
-                         1.0 / theta, pre ? 1 : 0, k > 1 ? 1 : 0, c->st));
+  if (pre && l == 0 && c->vin64)
+    HK(semk::smooth_first64(L.dbl, L.x, L.d, L.b, c->vin64, L.dinv, L.N, 1.0 / theta,
+                            k > 1 ? 1 : 0, c->st));
+  else
+    HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, 0.0,
+                           1.0 / theta, pre ? 1 : 0, k > 1 ? 1 : 0, c->st));
   for (int j = 1; j < k; ++j) {
     const double rho_new = 1.0 / (2.0 * sigma1 - rho);
     apply_level(c, l, L.x, c->masked);
@@ -193,30 +202,35 @@ void coarse_solve(Ctx* c) {
   double* x = (double*)L.x;
   const semh::BcrPlan& pl = c->plan;
   const int nl = (int)pl.levs.size();
-  const int lt = c->bcr_tail_first;
-  for (int l = 0; l < lt; ++l) {
+  for (int l = 0; l < nl; ++l) {
     const auto& v = pl.levs[l];
-    HK(semk::bcr_fwd(b, c->bcrF + v.offM, v.n, v.stride, v.neven, pl.bstride, c->rowmap, pl.nb,
+    HK(semk::bcr_fwd(b, c->bcrF + v.offM, v.n, v.stride, v.neven, pl.bstride, L.nzn - 1, pl.nb,
                      c->st));
   }
-  HK(semk::bcr_tail(b, x, c->bcrF, c->bcrB, c->bcrLevs, lt, nl, c->bcrLast, pl.bstride,
-                    c->rowmap, pl.nb, c->st));
-  for (int l = lt - 1; l >= 0; --l) {
+  HK(semk::bcr_dense(c->bcrDense, b, x, pl.dense_n * pl.nb, pl.nb, pl.dense_stride, pl.bstride,
+                     L.nzn - 1, c->st));
+  for (int l = nl - 1; l >= 0; --l) {
     const auto& v = pl.levs[l];
-    HK(semk::bcr_bwd(b, x, c->bcrB + v.offB, v.n, v.stride, v.nodd, pl.bstride, c->rowmap,
+    HK(semk::bcr_bwd(b, x, c->bcrB + v.offB, v.n, v.stride, v.nodd, pl.bstride, L.nzn - 1,
                      pl.nb, c->st));
   }
 }
 
-// z = B b on level 0 buffers: input lev[0].b, output lev[0].x
-void vcycle(Ctx* c) {
+// z = B r on level 0 buffers: input r (FP64, device), output lev[0].x
+void vcycle(Ctx* c, const double* r) {
   const int L = (int)c->lev.size();
+  DLevel& L0 = c->lev[0];
+  const bool fused_entry =
+      L > 1 && (c->desc.smoother == SEM_SMOOTH_CHEBYSHEV || c->desc.nu_pre > 0);
+  if (fused_entry) c->vin64 = r;
+  else HK(semk::cast_to(L0.dbl, r, L0.b, L0.N, c->st));
   if (L == 1) {
     coarse_solve(c);
     return;
   }
   for (int l = 0; l < L - 1; ++l) {
     smooth(c, l, true);
+    if (l == 0) c->vin64 = nullptr;
     apply_level(c, l, c->lev[l].x, c->masked);
     restrict_to(c, l, true);
   }
@@ -225,6 +239,7 @@ void vcycle(Ctx* c) {
     prolong_from(c, l);
     smooth(c, l, false);
   }
+  c->vin64 = nullptr;
 }
 
 double* pset(Ctx* c, int s) { return c->parts + (size_t)s * semk::NRED; }
@@ -233,8 +248,7 @@ double* pset(Ctx* c, int s) { return c->parts + (size_t)s * semk::NRED; }
 void fpcg_iteration(Ctx* c, bool first) {
   DLevel& L0 = c->lev[0];
   const unsigned N = L0.N;
-  HK(semk::cast_to(L0.dbl, c->ro, L0.b, N, c->st));
-  vcycle(c);
+  vcycle(c, c->ro);
   HK(semk::castdot(L0.dbl, L0.x, c->zo, first ? nullptr : c->qo, c->ro, pset(c, PS_ZQ),
                    pset(c, PS_RZB), N, c->st));
   HK(semk::pupdate(c->po, c->zo, pset(c, PS_RZA), pset(c, PS_PQ), pset(c, PS_ZQ), first ? 1 : 0,
@@ -244,19 +258,28 @@ void fpcg_iteration(Ctx* c, bool first) {
                     N, L0.nzn, L0.P, c->st));
   HK(semk::update_xr(c->xo, c->ro, c->po, c->qo, pset(c, PS_RZA), pset(c, PS_PQ),
                      pset(c, PS_RR), N, c->st));
-  HK(semk::reduce_sets(c->parts, PS_NSETS, c->scal, c->st));
 }
 
 void pdc_iteration(Ctx* c) {
   DLevel& L0 = c->lev[0];
   const unsigned N = L0.N;
-  HK(semk::cast_to(L0.dbl, c->ro, L0.b, N, c->st));
-  vcycle(c);
+  vcycle(c, c->ro);
   HK(semk::cast_from(L0.dbl, L0.x, c->zo, N, c->st));
   HK(semk::axpy64(c->xo, c->zo, 1.0, N, c->st));
   apply_outer(c, c->xo, c->masked);
   HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), nullptr, N, L0.nzn, L0.P, c->st));
-  HK(semk::reduce_sets(c->parts, PS_NSETS, c->scal, c->st));
+}
+
+// copy partial-sum sets 0..2 (RR, BB, PQ) to the host and sum each in a fixed order
+void read_sums(Ctx* c, double* sums) {
+  HK(hipMemcpyAsync(c->hscal, c->parts, 3 * semk::NRED * sizeof(double), hipMemcpyDeviceToHost,
+                    c->st));
+  HK(hipStreamSynchronize(c->st));
+  for (int s = 0; s < 3; ++s) {
+    double v = 0.0;
+    for (int k = 0; k < semk::NRED; ++k) v += c->hscal[s * semk::NRED + k];
+    sums[s] = v;
+  }
 }
 
 void drop_graphs(Ctx* c) {
@@ -518,7 +541,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   c->So = (double*)dalloc(c, L0.nS * 8);
   c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
   c->scal = (double*)dalloc(c, 64 * 8);
-  HK(hipHostMalloc((void**)&c->hscal, 64 * 8, hipHostMallocDefault));
+  HK(hipHostMalloc((void**)&c->hscal, 3 * semk::NRED * 8, hipHostMallocDefault));
   // lumped mass and Neumann faces of the fine level
   {
     std::vector<double> m(N, 0.0);
@@ -547,17 +570,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       c->bcrF = upload(c, c->plan.fwd.empty() ? std::vector<double>(1, 0.0) : c->plan.fwd);
       c->bcrB = upload(c, c->plan.bwd.empty() ? std::vector<double>(1, 0.0) : c->plan.bwd);
       c->bcrLast = upload(c, c->plan.last);
+      c->bcrDense = upload(c, c->plan.dense);
       c->rowmap = upload(c, c->plan.rowmap);
-      std::vector<semk::BcrLevDev> lv;
-      int lt = (int)c->plan.levs.size();
-      for (size_t k = 0; k < c->plan.levs.size(); ++k) {
-        const auto& v = c->plan.levs[k];
-        lv.push_back({v.n, v.stride, (long long)v.offM, (long long)v.offB, v.neven, v.nodd});
-        if (v.n <= 128 && lt == (int)c->plan.levs.size()) lt = (int)k;
-      }
-      if (lv.empty()) lv.push_back({1, 1, 0, 0, 0, 0});
-      c->bcrLevs = upload(c, lv);
-      c->bcr_tail_first = lt;
     }
   }
   // lambda_hat per smoothed level
@@ -774,8 +788,7 @@ sem_status sem_pmg_vcycle(sem_ctx* ctx, const double* r, double* z) {
     if (!r || !z) throw ArgFail{"null vector"};
     enter(c);
     DLevel& L0 = c->lev[0];
-    HK(semk::cast_to(L0.dbl, r, L0.b, L0.N, c->st));
-    vcycle(c);
+    vcycle(c, r);
     HK(semk::cast_from(L0.dbl, L0.x, z, L0.N, c->st));
     leave(c);
     return SEM_OK;
@@ -914,23 +927,22 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     apply_outer(c, c->xo, c->masked);
     HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn, L0.P,
                      c->st));
-    HK(semk::reduce_sets(c->parts, PS_NSETS, c->scal, c->st));
-    HK(hipMemcpyAsync(c->hscal, c->scal, PS_NSETS * 8, hipMemcpyDeviceToHost, c->st));
-    HK(hipStreamSynchronize(c->st));
-    const double bb = c->hscal[PS_BB];
-    double rel = bb > 0 ? std::sqrt(c->hscal[PS_RR] / bb) : 0.0;
+    double sums[3];
+    read_sums(c, sums);
+    const double bb = sums[PS_BB];
+    double rel = bb > 0 ? std::sqrt(sums[PS_RR] / bb) : 0.0;
     auto push = [&](double v) {
       if (inf->nhist < 512) inf->hist[inf->nhist++] = v;
     };
     push(rel);
     sem_status st = SEM_OK;
-    if (!(bb > 0)) {
+    if (!std::isfinite(bb) || !std::isfinite(sums[PS_RR])) {
+      st = SEM_ERR_BREAKDOWN;
+      set_err(c, "non-finite right-hand side or initial residual");
+    } else if (bb == 0.0) {
       // zero right-hand side: the solution is zero
       HK(semk::fill(true, c->xo, 0.0, N, c->st));
       rel = 0.0;
-    } else if (!std::isfinite(rel)) {
-      st = SEM_ERR_BREAKDOWN;
-      set_err(c, "non-finite initial residual");
     }
     const bool fpcg = c->desc.outer == SEM_OUTER_FPCG;
     int it = 0;
@@ -953,13 +965,12 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
         if (fpcg) fpcg_iteration(c, first);
         else pdc_iteration(c);
       }
-      HK(hipMemcpyAsync(c->hscal, c->scal, PS_NSETS * 8, hipMemcpyDeviceToHost, c->st));
-      HK(hipStreamSynchronize(c->st));
+      read_sums(c, sums);
       ++it;
       inf->vcycles++;
-      rel = std::sqrt(c->hscal[PS_RR] / bb);
+      rel = std::sqrt(sums[PS_RR] / bb);
       push(rel);
-      if (!std::isfinite(rel) || (fpcg && !(c->hscal[PS_PQ] > 0))) {
+      if (!std::isfinite(rel) || (fpcg && !(sums[PS_PQ] > 0))) {
         st = SEM_ERR_BREAKDOWN;
         set_err(c, "breakdown in the outer iteration (non-finite residual or p.Ap <= 0)");
       }
@@ -972,6 +983,68 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     inf->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return st;
   });
+}
+
+sem_status sem_time_operator(sem_ctx* ctx, int level, int outer, int reps, int flush,
+                             double* ms_avg) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (level < 0 || level >= (int)c->lev.size()) throw ArgFail{"bad level"};
+    if (outer && level != 0) throw ArgFail{"the outer operator lives on level 0"};
+    if (reps < 1 || !ms_avg) throw ArgFail{"bad reps / output"};
+    DLevel& L = c->lev[level];
+    hipEvent_t e0, e1;
+    HK(hipEventCreate(&e0));
+    HK(hipEventCreate(&e1));
+    void* junk = nullptr;
+    const size_t fbytes = (size_t)512 << 20;
+    if (flush) HK(hipMalloc(&junk, fbytes));
+    double total = 0.0;
+    auto launch = [&]() {
+      if (outer) apply_outer(c, c->po, c->masked);
+      else apply_level(c, level, L.x, c->masked);
+    };
+    launch();  // warm-up
+    if (!flush) {
+      HK(hipEventRecord(e0, c->st));
+      for (int k = 0; k < reps; ++k) launch();
+      HK(hipEventRecord(e1, c->st));
+      HK(hipEventSynchronize(e1));
+      float ms = 0;
+      HK(hipEventElapsedTime(&ms, e0, e1));
+      total = ms;
+    } else {
+      for (int k = 0; k < reps; ++k) {
+        HK(semk::fill(true, junk, (double)k, fbytes / 8, c->st));
+        HK(hipEventRecord(e0, c->st));
+        launch();
+        HK(hipEventRecord(e1, c->st));
+        HK(hipEventSynchronize(e1));
+        float ms = 0;
+        HK(hipEventElapsedTime(&ms, e0, e1));
+        total += ms;
+      }
+    }
+    if (junk) HK(hipFree(junk));
+    HK(hipEventDestroy(e0));
+    HK(hipEventDestroy(e1));
+    *ms_avg = total / reps;
+    return SEM_OK;
+  });
+}
+
+sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int outer, double* bytes) {
+  const Ctx* c = C(ctx);
+  if (!c || !bytes || level < 0 || level >= (int)c->lev.size() || (outer && level != 0))
+    return SEM_ERR_ARG;
+  const DLevel& L = c->lev[level];
+  const bool dbl = outer ? true : L.dbl;
+  const semk::GType gt = outer ? semk::G_F64 : L.gt;
+  const double sv = dbl ? 8.0 : 4.0;
+  const double sg = gt == semk::G_F64 ? 8.0 : (gt == semk::G_F32 ? 4.0 : 2.0);
+  const double nloc = (double)L.geo.E * std::pow((double)L.NP, c->dim);
+  *bytes = 2.0 * sv * L.N + L.geo.nfields * sg * nloc;
+  return SEM_OK;
 }
 
 const char* sem_last_error(const sem_ctx* ctx) {
