@@ -91,6 +91,14 @@ typedef struct {
   double hist[512];   /* relative residual after each iteration (hist[0] = initial)         */
 } sem_solve_info;
 
+typedef struct {
+  int epochs;                /* passes over the training rows (default 30)                  */
+  int batch;                 /* rows per Adam step (default 1024)                          */
+  float lr;                  /* peak learning rate, cosine decay to 0 (default 1e-3)       */
+  float val_frac;            /* trailing fraction of the rows held out (default 0.1)      */
+  unsigned long long seed;   /* SplitMix64 seed of the initial weights and shuffles       */
+} sem_train_cfg;
+
 /* Fill *d with defaults (2D, top Dirichlet, FP64, Chebyshev(3) on [0.1, 1.1] lambda_hat,
  * Jacobi omega 2/3, 2+2 sweeps, FPCG, maxit 500, 20 Lanczos steps, seed 12345). */
 void sem_mesh_desc_default(sem_mesh_desc *d);
@@ -183,6 +191,59 @@ sem_status sem_time_operator(sem_ctx *ctx, int level, int outer, int reps, int f
 /* Algorithmic bytes of one operator launch on level l (vectors read + written once, every
  * geometric factor read once), in the precision selected by outer (see sem_time_operator). */
 sem_status sem_operator_bytes(const sem_ctx *ctx, int level, int outer, double *bytes);
+
+/* ---- learned smoothing stage (not in the paper; an addition beside the method) -------------
+ * An element-local MLP maps each element's restricted residual r_e = R_e r (R_e: the element
+ * restriction, the R_i of the paper's Schwarz smoother, Sec. 6.3) plus its geometric factors to a
+ * correction.  Features per element (n = (P+1)^2 nodes, local order i*(P+1)+j):
+ *   [r_e / s_e, G_rr / g_e, G_rs / g_e, G_ss / g_e, m_e / mean(m_e)],  s_e = ||r_e||_2,
+ *   g_e = mean over the element of (G_rr + G_ss);
+ * network 5n -> 128 -> 128 -> n, exact-erf GELU on the hidden layers, BF16 operands with FP32
+ * accumulation on the matrix cores; correction c = W sum_e R_e^T (s_e / a_e) y_e with a_e the
+ * mean diagonal of the element matrix and W the averaging weight of Sec. 6.3, zero on the
+ * surface.  In the V-cycle the stage runs on the finest level after pre-smoothing: q = A c,
+ * alpha = c.r / c.q (energy-optimal), accepted if alpha > 0 and finite (x += alpha c: the A-norm
+ * of the error never grows), otherwise skipped and counted in sem_solve_info.learned_skips.  Training pairs: target
+ * t_e = (a_e / s_e) R_e e for the error e; loss = mean squared error; Adam.
+ * Network blob: 64-byte header ("SEMN", version 1, sizes, seed, losses) followed by FP32
+ * W1 [nin x 128], b1, W2 [128 x 128], b2, W3 [128 x nout], b3, row-major. */
+
+/* Bytes of a network blob with nin inputs and nout outputs. */
+size_t sem_mlp_blob_size(int nin, int nout);
+
+/* Training features of the fine level (2D, P <= 8): for an assembled residual r (device FP64,
+ * n_global) write X [E x 5n] and, if T is given, targets T [E x n] (device FP32, row-major;
+ * E = elements): with an error e, t_e = (a_e / s_e) R_e e; with e = NULL, the element-block solve
+ * t_e = (a_e / s_e) (R_e A R_e^T)^{-1} R_e r (the local solve of the Schwarz smoother, Sec. 6.3;
+ * meshes up to 4096 elements). */
+sem_status sem_learned_features(sem_ctx *ctx, const double *r, const double *e, float *X,
+                                float *T);
+
+/* Train a network on device rows X [n x nin], T [n x nout] (FP32) with the library's BF16 MFMA
+ * forward/backward kernels and Adam (FP32 master weights).  blob: host buffer of
+ * sem_mlp_blob_size(nin, nout) bytes (output).  losses: host array of 2*epochs floats
+ * (training loss of the last batch, validation loss) or NULL.  No context is needed; errors are
+ * reported through sem_last_error(NULL). */
+sem_status sem_mlp_train(const float *X, const float *T, int n, int nin, int nout,
+                         const sem_train_cfg *cfg, void *blob, size_t nbytes, float *losses);
+
+/* Test hooks of the training kernels: batched forward Y [n x nout] of device rows X, and the
+ * loss and parameter gradients (host array packed like the blob parameters) of device rows
+ * X, T.  blob: host. */
+sem_status sem_mlp_forward(const void *blob, size_t nbytes, const float *X, int n, float *Y);
+sem_status sem_mlp_gradients(const void *blob, size_t nbytes, const float *X, const float *T,
+                             int n, float *grads, float *loss);
+
+/* Load a network blob (host) into the context (nin = 5n, nout = n of the fine level, P <= 8) and
+ * set where the stage acts: enable = 0 off, bit 0 (1) after the finest pre-smoothing, bit 1 (2)
+ * before the finest post-smoothing (3 = both, keeping the V-cycle close to symmetric for the
+ * flexible-CG outer loop); sem_learned_enable changes it for a loaded network. */
+sem_status sem_learned_load(sem_ctx *ctx, const void *blob, size_t nbytes, int enable);
+sem_status sem_learned_enable(sem_ctx *ctx, int enable);
+
+/* Test hook: one learned stage on the fine level for b, x (device FP64, x updated in place);
+ * *accepted = 1 if the step was taken. */
+sem_status sem_learned_stage(sem_ctx *ctx, const double *b, double *x, int *accepted);
 
 /* Text of the last error on this context ("" if none).  Valid until the next call. */
 const char *sem_last_error(const sem_ctx *ctx);

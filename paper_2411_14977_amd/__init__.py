@@ -13,5 +13,7 @@ from .binding import (  # noqa: F401
     sem_get_sizes, sem_gll, sem_mesh_desc_default, sem_mesh_setup, sem_node_coords,
     sem_num_levels, sem_pmg_vcycle, sem_poisson_solve, sem_prolong_add, sem_restrict,
     sem_set_smoother_bounds, sem_smooth, fine_x_nodes, sem_time_operator,
-    sem_operator_bytes,
+    sem_operator_bytes, sem_mlp_blob_size, sem_learned_features, sem_mlp_train, sem_mlp_forward,
+    sem_mlp_gradients, sem_learned_load, sem_learned_enable, sem_learned_stage, blob_pack,
+    blob_unpack,
 )

@@ -38,6 +38,11 @@ class MeshDesc(ctypes.Structure):
     ]
 
 
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
+                ("val_frac", ctypes.c_float), ("seed", ctypes.c_ulonglong)]
+
+
 class SolveInfo(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int), ("vcycles", ctypes.c_int), ("learned_skips", ctypes.c_int),
@@ -91,6 +96,17 @@ def lib():
         "sem_coarse_solve": (ctypes.c_int, [vp, dp, dp]),
         "sem_time_operator": (ctypes.c_int, [vp, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_double)]),
         "sem_operator_bytes": (ctypes.c_int, [vp, ip, ip, ctypes.POINTER(ctypes.c_double)]),
+        "sem_mlp_blob_size": (ctypes.c_size_t, [ip, ip]),
+        "sem_learned_features": (ctypes.c_int, [vp, dp, dp, dp, dp]),
+        "sem_mlp_train": (ctypes.c_int, [dp, dp, ip, ip, ip, ctypes.POINTER(TrainCfg), vp,
+                                         ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)]),
+        "sem_mlp_forward": (ctypes.c_int, [vp, ctypes.c_size_t, dp, ip, dp]),
+        "sem_mlp_gradients": (ctypes.c_int, [vp, ctypes.c_size_t, dp, dp, ip,
+                                             ctypes.POINTER(ctypes.c_float),
+                                             ctypes.POINTER(ctypes.c_float)]),
+        "sem_learned_load": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ip]),
+        "sem_learned_enable": (ctypes.c_int, [vp, ip]),
+        "sem_learned_stage": (ctypes.c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int)]),
         "sem_last_error": (ctypes.c_char_p, [vp]),
         "sem_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -107,6 +123,15 @@ def _check(ctx, status):
         msg = lib().sem_last_error(ctx)
         raise SemError(status, msg.decode() if msg else "")
     return status
+
+
+def _ptr32(t):
+    """Device pointer of a contiguous float32 CUDA tensor."""
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype.is_floating_point and t.element_size() == 4 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
 
 
 def _ptr(t):
@@ -231,6 +256,77 @@ def sem_operator_bytes(ctx, level, outer):
     return b.value
 
 
+def sem_mlp_blob_size(nin, nout):
+    return int(lib().sem_mlp_blob_size(nin, nout))
+
+
+def sem_learned_features(ctx, r, e, X, T):
+    _check(ctx, lib().sem_learned_features(ctx, _ptr(r), _ptr(e), _ptr32(X), _ptr32(T)))
+
+
+def sem_mlp_train(X, T, nin, nout, epochs=30, batch=1024, lr=1e-3, val_frac=0.1, seed=1234):
+    """Train on device float32 rows X [n x nin], T [n x nout]; returns (blob bytes, losses)."""
+    n = X.shape[0]
+    cfg = TrainCfg(epochs, batch, lr, val_frac, seed)
+    nb = sem_mlp_blob_size(nin, nout)
+    blob = ctypes.create_string_buffer(nb)
+    losses = (ctypes.c_float * (2 * epochs))()
+    _check(None, lib().sem_mlp_train(_ptr32(X), _ptr32(T), n, nin, nout, ctypes.byref(cfg), blob,
+                                     nb, losses))
+    return bytes(blob.raw), np.array(losses[:]).reshape(epochs, 2)
+
+
+def sem_mlp_forward(blob, X, nout):
+    import torch
+    Y = torch.zeros(X.shape[0], nout, dtype=torch.float32, device=X.device)
+    _check(None, lib().sem_mlp_forward(blob, len(blob), _ptr32(X), X.shape[0], _ptr32(Y)))
+    return Y
+
+
+def sem_mlp_gradients(blob, X, T, nparams):
+    g = np.zeros(nparams, dtype=np.float32)
+    loss = ctypes.c_float()
+    _check(None, lib().sem_mlp_gradients(blob, len(blob), _ptr32(X), _ptr32(T), X.shape[0],
+                                         g.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                         ctypes.byref(loss)))
+    return g, loss.value
+
+
+def sem_learned_load(ctx, blob, enable=True):
+    _check(ctx, lib().sem_learned_load(ctx, blob, len(blob), int(enable)))
+
+
+def sem_learned_enable(ctx, enable):
+    _check(ctx, lib().sem_learned_enable(ctx, int(enable)))
+
+
+def sem_learned_stage(ctx, b, x):
+    acc = ctypes.c_int()
+    _check(ctx, lib().sem_learned_stage(ctx, _ptr(b), _ptr(x), ctypes.byref(acc)))
+    return bool(acc.value)
+
+
+def blob_pack(nin, nout, W1, b1, W2, b2, W3, b3, seed=0):
+    """Network blob (bytes) from FP32 arrays (layout of include/sem.h)."""
+    import struct
+    hdr = struct.pack("<8IQ2f4I", 0x4E4D4553, 1, nin, 128, nout, 0, 0, 0, seed, 0.0, 0.0, 0, 0, 0, 0)
+    body = b"".join(np.ascontiguousarray(a, dtype=np.float32).tobytes() for a in (W1, b1, W2, b2, W3, b3))
+    return hdr + body
+
+
+def blob_unpack(blob):
+    import struct
+    magic, ver, nin, nh, nout = struct.unpack_from("<5I", blob, 0)
+    p = np.frombuffer(blob, dtype=np.float32, offset=64)
+    out, off = {}, 0
+    for k, shp in (("W1", (nin, nh)), ("b1", (nh,)), ("W2", (nh, nh)), ("b2", (nh,)),
+                   ("W3", (nh, nout)), ("b3", (nout,))):
+        n = int(np.prod(shp))
+        out[k] = p[off:off + n].reshape(shp).astype(np.float64)
+        off += n
+    return out
+
+
 # ---- convenience owner of one context -------------------------------------------------------
 _PREC = {"f64": SEM_F64, "f32": SEM_F32, "bf16": SEM_F32_GBF16}
 
@@ -325,6 +421,17 @@ class Solver:
 
     def set_lambda(self, level, lam):
         sem_set_smoother_bounds(self.ctx, level, lam)
+
+    def learned_load(self, blob, enable=True):
+        sem_learned_load(self.ctx, blob, enable)
+
+    def learned_enable(self, enable):
+        sem_learned_enable(self.ctx, enable)
+
+    def smooth(self, level, b, x=None, pre=True):
+        x = self._new(self.level(level)[1]) if x is None else x
+        sem_smooth(self.ctx, level, pre, b, x)
+        return x
 
 
 def fine_x_nodes(Ne, P, L):

@@ -497,6 +497,8 @@ static bool dense_inverse(int n, const double* A, double* Ainv) {
   return true;
 }
 
+bool dense_inverse_public(int n, const double* A, double* Ainv) { return dense_inverse(n, A, Ainv); }
+
 static void matmul(int n, const double* A, const double* B, double* C) {  // C = A B
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {

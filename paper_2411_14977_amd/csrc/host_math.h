@@ -51,6 +51,9 @@ std::vector<double> assembled_diag(const LevelGeom& L, const std::vector<double>
 // Dense element stiffness of element e, size NL x NL (NL = NP^dim), from factors Gr.
 void element_matrix(const LevelGeom& L, const std::vector<double>& Gr, size_t e, double* Ae);
 
+// Dense inverse by Gauss-Jordan elimination with partial pivoting (false if singular).
+bool dense_inverse_public(int n, const double* A, double* Ainv);
+
 // Round to bfloat16 (round to nearest even) and back.
 double bf16_round(double v);
 uint16_t bf16_bits(float f);

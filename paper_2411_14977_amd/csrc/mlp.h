@@ -1,0 +1,98 @@
+// Element-local MLP (learned smoothing stage): BF16 MFMA kernels with FP32 accumulation,
+// training driver (forward, backward, Adam) and the fused inference kernels of the V-cycle.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace semm {
+
+constexpr int NH = 128;  // hidden width
+
+inline int pad16(int n) { return (n + 15) / 16 * 16; }
+
+// Host copy of the network in FP32 (unpadded, row-major): W1 [nin x NH], b1, W2 [NH x NH], b2,
+// W3 [NH x nout], b3.
+struct Net {
+  int nin = 0, nout = 0;
+  uint64_t seed = 0;
+  float train_loss = 0.f, val_loss = 0.f;
+  int epochs = 0, steps = 0;
+  std::vector<float> W1, b1, W2, b2, W3, b3;
+  size_t nparams() const { return W1.size() + b1.size() + W2.size() + b2.size() + W3.size() + b3.size(); }
+};
+
+// blob = 64-byte header + parameters in the order above
+size_t blob_size(int nin, int nout);
+bool net_from_blob(const void* blob, size_t nbytes, Net& net, std::string& err);
+void net_to_blob(const Net& net, void* blob);
+void net_init(Net& net, int nin, int nout, uint64_t seed);   // U(+-1/sqrt(fan_in)), b = 0
+
+// ---- generic BF16 GEMM: C[m][n] (+)= sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak],
+// B(k,n) = B[k*sbk + n*sbn] (bf16 bits), C fp32 row-major with ldc.  M, N, K multiples of 16.
+hipError_t gemm_bf16(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
+                     float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st);
+hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_t* dst, int ldd,
+                          int dcols, const int* rowidx, hipStream_t st);
+
+hipError_t add_bias(float* Z, const float* b, int rows, int cols, hipStream_t st);
+constexpr int MAX_STAGE_OUT = 96;  // the fused inference kernel handles (P+1)^2 <= 96 (P <= 8)
+
+struct TrainCfg {
+  int epochs = 30, batch = 1024;
+  float lr = 1e-3f;
+  uint64_t seed = 1234;
+  float val_frac = 0.1f;
+};
+
+// Train on device samples X [n x nin] and T [n x nout] (fp32, row-major).  On return net holds
+// the trained FP32 weights; losses (optional) gets 2 floats per epoch (train, validation).
+bool train(const float* X, const float* T, int n, int nin, int nout, const TrainCfg& cfg, Net& net,
+           std::vector<float>* losses, hipStream_t st, std::string& err);
+
+// Batched forward with the training kernels (test hook): Y [n x nout] fp32.
+bool forward(const Net& net, const float* X, int n, float* Y, hipStream_t st, std::string& err);
+// Loss and parameter gradients for one batch (test hook); grads packed like the blob.
+bool gradients(const Net& net, const float* X, const float* T, int n, float* grads, float* loss,
+               hipStream_t st, std::string& err);
+
+// ---- inference state of one solver context (2D element columns) ----------------------------
+struct Stage {
+  bool enabled = false;
+  int nin = 0, nout = 0, P = 0, Nx = 0, Nz = 0, nzn = 0;
+  size_t E = 0;
+  // bf16, padded, stored transposed (output-major, [n][k]) so that one lane's 4 consecutive
+  // k-values of an MFMA operand are contiguous: W1r [NH][KR], W2 [NH][NH], W3 [N3][NH]
+  uint16_t *W1r = nullptr, *W2 = nullptr, *W3 = nullptr;
+  float *b2 = nullptr, *b3 = nullptr;
+  float* Z1geo = nullptr;   // [E x NH] = geometric part of layer 1 + b1
+  float* abar = nullptr;    // [E] mean of the element-matrix diagonal
+  float* CE = nullptr;      // [E x nout] element-local corrections
+  int* skips = nullptr;     // 64 B: rejection count, step (see stage_dots)
+  std::vector<void*> allocs;
+};
+
+// One learned stage on the fine level (precision dbl ? double : float):
+//   r = b - (y + S); c = W sum R^T c_e; q = A c via the caller's apply; alpha; accept; x, R.
+hipError_t stage_mlp(const Stage& s, bool dbl, const void* b, const void* y, const void* S,
+                     hipStream_t st);
+hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStream_t st);
+// Partial sums of c.r and c.q, then the accepted step into flags (see mlp.hip): flags[0]
+// rejection count, bytes 8..15 the step (0 when rejected).
+hipError_t stage_dots(bool dbl, const void* c, const void* b, const void* y, const void* S,
+                      const void* yq, const void* Sq, double* parts, int* flags, unsigned N,
+                      unsigned nzn, unsigned P, hipStream_t st);
+hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* b, const void* y,
+                        const void* S, const void* yq, const void* Sq, const int* flags, unsigned N,
+                        unsigned nzn, unsigned P, hipStream_t st);
+// Training features of an assembled residual r on a 2D mesh: X [E x 5n] fp32; targets T [E x n]
+// fp32 from the error e ((a_e/s_e) R_e e) or, if e is null, from the element-block inverses
+// Ainv [E x n x n] ((a_e/s_e) Ainv_e R_e r).
+hipError_t features(const double* r, const double* e, const double* Ainv, const float* geo,
+                    const float* abar, float* X, float* T, size_t E, int P, int Nz, int nzn,
+                    hipStream_t st);
+
+}  // namespace semm

@@ -1,0 +1,1071 @@
+// Element-local MLP of the learned smoothing stage on gfx950: BF16 MFMA (16x16x16, FP32
+// accumulate) GEMMs, exact-erf GELU, MSE loss, Adam, and the fused per-wave inference kernel
+// used inside the V-cycle.  The stage itself (features, output scaling, weighted assembly,
+// energy-optimal step and its acceptance test) is described in mlp.h / sem.h.
+#include "mlp.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "host_math.h"
+#include "kernels.h"
+
+namespace semm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
+
+__device__ __forceinline__ uint16_t f2bf(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
+         x * expf(-0.5f * x * x) * 0.39894228040143268f;
+}
+__device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// MFMA 16x16x16 operand layout (wave64): lane l holds A[l%16][4(l/16)+v] and B[4(l/16)+v][l%16]
+// for v = 0..3, and the result D[4(l/16)+v][l%16].
+
+// ------------------------------------------------------------------------------------------
+// generic GEMM (training and set-up): one wave computes a 16 x 64 block
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ A, long sam,
+                                                   long sak, const uint16_t* __restrict__ B,
+                                                   long sbk, long sbn, float* __restrict__ C,
+                                                   int ldc, int M, int N, int K, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.y * 64 + wave * 16;
+  const int n0 = blockIdx.x * 64;
+  if (m0 >= M) return;  // no block-level synchronisation in this kernel
+  const int li = lane & 15, kq = (lane >> 4) * 4;
+  f32x4 acc[4];
+  for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < K; k0 += 16) {
+    bf16x4 a;
+    const uint16_t* ap = A + (long)(m0 + li) * sam + (long)(k0 + kq) * sak;
+    for (int v = 0; v < 4; ++v) a[v] = (short)ap[v * sak];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int n = n0 + 16 * t;
+      if (n < N) {
+        bf16x4 b;
+        const uint16_t* bp = B + (long)(k0 + kq) * sbk + (long)(n + li) * sbn;
+        for (int v = 0; v < 4; ++v) b[v] = (short)bp[v * sbk];
+        acc[t] = mfma16(a, b, acc[t]);
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int n = n0 + 16 * t;
+    if (n >= N) continue;
+    for (int v = 0; v < 4; ++v) {
+      float* cp = C + (long)(m0 + kq + v) * ldc + n + li;
+      *cp = accumulate ? *cp + acc[t][v] : acc[t][v];
+    }
+  }
+}
+
+hipError_t gemm_bf16(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
+                     float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st) {
+  if (M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
+  dim3 grid(nblk(N, 64), nblk(M, 64));
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, ldc, M, N,
+                     K, accumulate);
+  return hipGetLastError();
+}
+
+__global__ void k_to_bf16_padded(const float* __restrict__ src, int rows, int cols, int lds,
+                                 uint16_t* __restrict__ dst, int ldd, int dcols,
+                                 const int* __restrict__ rowidx) {
+  const long total = (long)rows * dcols;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(t / dcols), c = (int)(t - (long)r * dcols);
+    const int sr = rowidx ? rowidx[r] : r;
+    const float v = (sr >= 0 && c < cols) ? src[(long)sr * lds + c] : 0.0f;
+    dst[(long)r * ldd + c] = f2bf(v);
+  }
+}
+
+hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_t* dst, int ldd,
+                          int dcols, const int* rowidx, hipStream_t st) {
+  const long total = (long)rows * dcols;
+  hipLaunchKernelGGL(k_to_bf16_padded, dim3(std::min<long>(nblk(total, 256), 65535)), dim3(256), 0,
+                     st, src, rows, cols, lds, dst, ldd, dcols, rowidx);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// training element-wise kernels
+// ------------------------------------------------------------------------------------------
+// Z (M x ld) += bias; H = bf16(GELU(Z))
+__global__ void k_bias_gelu(float* __restrict__ Z, const float* __restrict__ bias,
+                            uint16_t* __restrict__ H, int M, int N, int ld) {
+  const long total = (long)M * N;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(t / N), c = (int)(t - (long)r * N);
+    const float z = Z[(long)r * ld + c] + bias[c];
+    Z[(long)r * ld + c] = z;
+    H[(long)r * ld + c] = f2bf(gelu(z));
+  }
+}
+
+// y = Y + b3 on the first nout columns; d = y - t on valid rows (< nvalid); dY = 2 d / (nvalid
+// nout) (fp32 and bf16, padded columns and rows zero); Y is overwritten with y; per-block partial
+// sums of d^2 into part[blockIdx.x]
+__global__ __launch_bounds__(256) void k_loss_grad(float* __restrict__ Y, const float* __restrict__ b3,
+                                                   const float* __restrict__ T, int ldt,
+                                                   float* __restrict__ dYf,
+                                                   uint16_t* __restrict__ dYb, int M, int ldy,
+                                                   int nout, int nvalid, double* part) {
+  __shared__ double sh[8];
+  double acc = 0.0;
+  const float scale = 2.0f / ((float)nvalid * (float)nout);
+  const long total = (long)M * ldy;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(t / ldy), c = (int)(t - (long)r * ldy);
+    float g = 0.0f;
+    if (c < nout) {
+      const float y = Y[t] + b3[c];
+      Y[t] = y;
+      if (r < nvalid) {
+        const float d = y - T[(long)r * ldt + c];
+        acc += (double)d * (double)d;
+        g = scale * d;
+      }
+    }
+    dYf[t] = g;
+    dYb[t] = f2bf(g);
+  }
+  for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
+    part[blockIdx.x] = s;
+  }
+}
+
+// dZ = dH * GELU'(Z) (fp32 and bf16)
+__global__ void k_gelu_back(const float* __restrict__ dH, const float* __restrict__ Z,
+                            float* __restrict__ dZf, uint16_t* __restrict__ dZb, long n) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const float g = dH[t] * gelu_grad(Z[t]);
+    dZf[t] = g;
+    dZb[t] = f2bf(g);
+  }
+}
+
+// out[c] = sum_r D[r][c] (fixed order), c < N
+__global__ void k_colsum(const float* __restrict__ D, int M, int N, int ld, float* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= N) return;
+  float s = 0.0f;
+  for (int r = 0; r < M; ++r) s += D[(long)r * ld + c];
+  out[c] = s;
+}
+
+// Adam on FP32 master weights; wb = bf16 copy (may be null)
+__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, long n, float lr_t, float b1, float b2, float eps,
+                       float c1, float c2, uint16_t* __restrict__ wb) {
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    const float gi = g[t];
+    const float mi = b1 * m[t] + (1.0f - b1) * gi;
+    const float vi = b2 * v[t] + (1.0f - b2) * gi * gi;
+    m[t] = mi;
+    v[t] = vi;
+    const float wi = w[t] - lr_t * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[t] = wi;
+    if (wb) wb[t] = f2bf(wi);
+  }
+}
+
+__global__ void k_out_bias(const float* __restrict__ Y, int ldy, const float* __restrict__ b,
+                           int rows, int cols, float* __restrict__ out) {
+  const long total = (long)rows * cols;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(t / cols), c = (int)(t - (long)r * cols);
+    out[t] = Y[(long)r * ldy + c] + b[c];
+  }
+}
+
+// Z[r][c] += b[c]
+__global__ void k_add_bias(float* __restrict__ Z, const float* __restrict__ b, int rows, int cols) {
+  const long total = (long)rows * cols;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x)
+    Z[t] += b[t % cols];
+}
+
+hipError_t add_bias(float* Z, const float* b, int rows, int cols, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_bias, dim3(nblk((size_t)rows * cols, 256)), dim3(256), 0, st, Z, b,
+                     rows, cols);
+  return hipGetLastError();
+}
+
+__global__ void k_gather_f32(const float* __restrict__ src, int cols, const int* __restrict__ idx,
+                             int rows, float* __restrict__ dst) {
+  const long total = (long)rows * cols;
+  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
+    const int r = (int)(t / cols), c = (int)(t - (long)r * cols);
+    const int sr = idx[r];
+    dst[t] = sr >= 0 ? src[(long)sr * cols + c] : 0.0f;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// host: network container, blob, init
+// ------------------------------------------------------------------------------------------
+struct BlobHeader {
+  uint32_t magic, version, nin, nh, nout, epochs, steps, reserved;
+  uint64_t seed;
+  float train_loss, val_loss;
+  uint32_t pad[4];
+};
+static_assert(sizeof(BlobHeader) == 64, "blob header is 64 bytes");
+static const uint32_t kMagic = 0x4e4d4553u;  // "SEMN"
+
+size_t blob_size(int nin, int nout) {
+  const size_t np = (size_t)nin * NH + NH + (size_t)NH * NH + NH + (size_t)NH * nout + nout;
+  return sizeof(BlobHeader) + np * sizeof(float);
+}
+
+bool net_from_blob(const void* blob, size_t nbytes, Net& net, std::string& err) {
+  if (!blob || nbytes < sizeof(BlobHeader)) { err = "blob too small"; return false; }
+  BlobHeader h;
+  std::memcpy(&h, blob, sizeof h);
+  if (h.magic != kMagic || h.version != 1 || h.nh != (uint32_t)NH) { err = "not a network blob"; return false; }
+  if (h.nin == 0 || h.nout == 0 || h.nin > 4096 || h.nout > 4096) { err = "bad blob sizes"; return false; }
+  if (nbytes != blob_size(h.nin, h.nout)) { err = "blob size mismatch"; return false; }
+  net.nin = h.nin;
+  net.nout = h.nout;
+  net.seed = h.seed;
+  net.train_loss = h.train_loss;
+  net.val_loss = h.val_loss;
+  net.epochs = h.epochs;
+  net.steps = h.steps;
+  const float* p = (const float*)((const char*)blob + sizeof h);
+  auto take = [&](std::vector<float>& v, size_t n) { v.assign(p, p + n); p += n; };
+  take(net.W1, (size_t)h.nin * NH);
+  take(net.b1, NH);
+  take(net.W2, (size_t)NH * NH);
+  take(net.b2, NH);
+  take(net.W3, (size_t)NH * h.nout);
+  take(net.b3, h.nout);
+  return true;
+}
+
+void net_to_blob(const Net& net, void* blob) {
+  BlobHeader h{};
+  h.magic = kMagic;
+  h.version = 1;
+  h.nin = net.nin;
+  h.nh = NH;
+  h.nout = net.nout;
+  h.epochs = net.epochs;
+  h.steps = net.steps;
+  h.seed = net.seed;
+  h.train_loss = net.train_loss;
+  h.val_loss = net.val_loss;
+  std::memcpy(blob, &h, sizeof h);
+  float* p = (float*)((char*)blob + sizeof h);
+  for (const auto* v : {&net.W1, &net.b1, &net.W2, &net.b2, &net.W3, &net.b3}) {
+    std::memcpy(p, v->data(), v->size() * sizeof(float));
+    p += v->size();
+  }
+}
+
+void net_init(Net& net, int nin, int nout, uint64_t seed) {
+  net.nin = nin;
+  net.nout = nout;
+  net.seed = seed;
+  uint64_t ctr = 0;
+  auto fill = [&](std::vector<float>& W, int fan_in, size_t n) {
+    W.resize(n);
+    const double lim = 1.0 / std::sqrt((double)fan_in);
+    for (size_t i = 0; i < n; ++i) W[i] = (float)(lim * semh::splitmix64_uniform(seed, ctr++));
+  };
+  fill(net.W1, nin, (size_t)nin * NH);
+  fill(net.W2, NH, (size_t)NH * NH);
+  fill(net.W3, NH, (size_t)NH * nout);
+  net.b1.assign(NH, 0.f);
+  net.b2.assign(NH, 0.f);
+  net.b3.assign(nout, 0.f);
+}
+
+// ------------------------------------------------------------------------------------------
+// host: training driver
+// ------------------------------------------------------------------------------------------
+namespace {
+
+struct Dev {
+  std::vector<void*> ptrs;
+  hipError_t e = hipSuccess;
+  template <typename T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    hipError_t r = hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T));
+    if (r != hipSuccess) { e = r; return nullptr; }
+    ptrs.push_back(p);
+    return (T*)p;
+  }
+  ~Dev() {
+    for (void* p : ptrs) (void)hipFree(p);
+  }
+};
+
+#define CK(x)                                 \
+  do {                                        \
+    hipError_t e_ = (x);                      \
+    if (e_ != hipSuccess) {                   \
+      err = std::string(#x) + ": " + hipGetErrorString(e_); \
+      return false;                           \
+    }                                         \
+  } while (0)
+
+// padded parameter set on the device (fp32 masters + bf16 copies)
+struct Params {
+  int nin, nout, K1, N3;
+  float *W1, *b1, *W2, *b2, *W3, *b3;      // padded: W1 [K1 x NH], W3 [NH x N3], b3 [N3]
+  uint16_t *W1b, *W2b, *W3b;
+  size_t n1() const { return (size_t)K1 * NH; }
+  size_t n2() const { return (size_t)NH * NH; }
+  size_t n3() const { return (size_t)NH * N3; }
+};
+
+bool alloc_params(Dev& d, Params& p, int nin, int nout) {
+  p.nin = nin;
+  p.nout = nout;
+  p.K1 = pad16(nin);
+  p.N3 = pad16(nout);
+  p.W1 = d.alloc<float>(p.n1());
+  p.b1 = d.alloc<float>(NH);
+  p.W2 = d.alloc<float>(p.n2());
+  p.b2 = d.alloc<float>(NH);
+  p.W3 = d.alloc<float>(p.n3());
+  p.b3 = d.alloc<float>(p.N3);
+  p.W1b = d.alloc<uint16_t>(p.n1());
+  p.W2b = d.alloc<uint16_t>(p.n2());
+  p.W3b = d.alloc<uint16_t>(p.n3());
+  return d.e == hipSuccess;
+}
+
+bool upload_params(const Net& net, Params& p, hipStream_t st, std::string& err) {
+  std::vector<float> W1((size_t)p.K1 * NH, 0.f), W3((size_t)NH * p.N3, 0.f), b3(p.N3, 0.f);
+  for (int k = 0; k < net.nin; ++k)
+    for (int n = 0; n < NH; ++n) W1[(size_t)k * NH + n] = net.W1[(size_t)k * NH + n];
+  for (int k = 0; k < NH; ++k)
+    for (int n = 0; n < net.nout; ++n) W3[(size_t)k * p.N3 + n] = net.W3[(size_t)k * net.nout + n];
+  for (int n = 0; n < net.nout; ++n) b3[n] = net.b3[n];
+  CK(hipMemcpyAsync(p.W1, W1.data(), W1.size() * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(p.W2, net.W2.data(), net.W2.size() * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(p.W3, W3.data(), W3.size() * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(p.b1, net.b1.data(), NH * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(p.b2, net.b2.data(), NH * 4, hipMemcpyHostToDevice, st));
+  CK(hipMemcpyAsync(p.b3, b3.data(), p.N3 * 4, hipMemcpyHostToDevice, st));
+  CK(to_bf16_padded(p.W1, p.K1, NH, NH, p.W1b, NH, NH, nullptr, st));
+  CK(to_bf16_padded(p.W2, NH, NH, NH, p.W2b, NH, NH, nullptr, st));
+  CK(to_bf16_padded(p.W3, NH, p.N3, p.N3, p.W3b, p.N3, p.N3, nullptr, st));
+  CK(hipStreamSynchronize(st));
+  return true;
+}
+
+bool download_params(const Params& p, Net& net, hipStream_t st, std::string& err) {
+  std::vector<float> W1((size_t)p.K1 * NH), W3((size_t)NH * p.N3), b3(p.N3);
+  net.W2.resize((size_t)NH * NH);
+  net.b1.resize(NH);
+  net.b2.resize(NH);
+  CK(hipMemcpyAsync(W1.data(), p.W1, W1.size() * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(net.W2.data(), p.W2, net.W2.size() * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(W3.data(), p.W3, W3.size() * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(net.b1.data(), p.b1, NH * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(net.b2.data(), p.b2, NH * 4, hipMemcpyDeviceToHost, st));
+  CK(hipMemcpyAsync(b3.data(), p.b3, p.N3 * 4, hipMemcpyDeviceToHost, st));
+  CK(hipStreamSynchronize(st));
+  net.W1.resize((size_t)p.nin * NH);
+  net.W3.resize((size_t)NH * p.nout);
+  net.b3.resize(p.nout);
+  for (int k = 0; k < p.nin; ++k)
+    for (int n = 0; n < NH; ++n) net.W1[(size_t)k * NH + n] = W1[(size_t)k * NH + n];
+  for (int k = 0; k < NH; ++k)
+    for (int n = 0; n < p.nout; ++n) net.W3[(size_t)k * p.nout + n] = W3[(size_t)k * p.N3 + n];
+  for (int n = 0; n < p.nout; ++n) net.b3[n] = b3[n];
+  return true;
+}
+
+// activations of one batch of at most Bmax rows
+struct Acts {
+  int Bmax, K1, N3;
+  uint16_t *Xb, *H1b, *H2b, *dYb, *dZ2b, *dZ1b;
+  float *Z1, *Z2, *Y, *T, *dYf, *dH2, *dZ2f, *dH1, *dZ1f;
+  int* idx;
+  double* part;
+};
+
+bool alloc_acts(Dev& d, Acts& a, int Bmax, int K1, int N3) {
+  a.Bmax = Bmax;
+  a.K1 = K1;
+  a.N3 = N3;
+  const size_t B = Bmax;
+  a.Xb = d.alloc<uint16_t>(B * K1);
+  a.H1b = d.alloc<uint16_t>(B * NH);
+  a.H2b = d.alloc<uint16_t>(B * NH);
+  a.dYb = d.alloc<uint16_t>(B * N3);
+  a.dZ2b = d.alloc<uint16_t>(B * NH);
+  a.dZ1b = d.alloc<uint16_t>(B * NH);
+  a.Z1 = d.alloc<float>(B * NH);
+  a.Z2 = d.alloc<float>(B * NH);
+  a.Y = d.alloc<float>(B * N3);
+  a.T = d.alloc<float>(B * N3);
+  a.dYf = d.alloc<float>(B * N3);
+  a.dH2 = d.alloc<float>(B * NH);
+  a.dZ2f = d.alloc<float>(B * NH);
+  a.dH1 = d.alloc<float>(B * NH);
+  a.dZ1f = d.alloc<float>(B * NH);
+  a.idx = d.alloc<int>(B);
+  a.part = d.alloc<double>(256);
+  return d.e == hipSuccess;
+}
+
+constexpr int LOSS_BLOCKS = 64;
+
+// forward of rows idx[0..M) (M multiple of 16; idx < 0 = zero row); Y holds y on return
+bool fwd(const Params& p, Acts& a, const float* X, int M, hipStream_t st, std::string& err) {
+  CK(to_bf16_padded(X, M, p.nin, p.nin, a.Xb, p.K1, p.K1, a.idx, st));
+  CK(gemm_bf16(a.Xb, p.K1, 1, p.W1b, NH, 1, a.Z1, NH, M, NH, p.K1, 0, st));
+  hipLaunchKernelGGL(k_bias_gelu, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.Z1, p.b1,
+                     a.H1b, M, NH, NH);
+  CK(hipGetLastError());
+  CK(gemm_bf16(a.H1b, NH, 1, p.W2b, NH, 1, a.Z2, NH, M, NH, NH, 0, st));
+  hipLaunchKernelGGL(k_bias_gelu, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.Z2, p.b2,
+                     a.H2b, M, NH, NH);
+  CK(hipGetLastError());
+  CK(gemm_bf16(a.H2b, NH, 1, p.W3b, p.N3, 1, a.Y, p.N3, M, p.N3, NH, 0, st));
+  return true;
+}
+
+// loss (sum of squares over valid rows) + gradients into padded g buffers
+bool bwd(const Params& p, Acts& a, const float* Tsrc, int M, int nvalid, float* gW1, float* gb1,
+         float* gW2, float* gb2, float* gW3, float* gb3, hipStream_t st, std::string& err) {
+  hipLaunchKernelGGL(k_gather_f32, dim3(nblk((size_t)M * p.nout, 256)), dim3(256), 0, st, Tsrc,
+                     p.nout, a.idx, M, a.T);
+  CK(hipGetLastError());
+  hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, st, a.Y, p.b3, a.T, p.nout,
+                     a.dYf, a.dYb, M, p.N3, p.nout, nvalid, a.part);
+  CK(hipGetLastError());
+  // dW3 = H2^T dY, db3 = colsum dY
+  CK(gemm_bf16(a.H2b, 1, NH, a.dYb, p.N3, 1, gW3, p.N3, NH, p.N3, M, 0, st));
+  hipLaunchKernelGGL(k_colsum, dim3(nblk(p.N3, 128)), dim3(128), 0, st, a.dYf, M, p.N3, p.N3, gb3);
+  // dH2 = dY W3^T; dZ2 = dH2 * gelu'(Z2)
+  CK(gemm_bf16(a.dYb, p.N3, 1, p.W3b, 1, p.N3, a.dH2, NH, M, NH, p.N3, 0, st));
+  hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH2, a.Z2,
+                     a.dZ2f, a.dZ2b, (long)M * NH);
+  // dW2 = H1^T dZ2, db2
+  CK(gemm_bf16(a.H1b, 1, NH, a.dZ2b, NH, 1, gW2, NH, NH, NH, M, 0, st));
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, st, a.dZ2f, M, NH, NH, gb2);
+  // dH1 = dZ2 W2^T; dZ1
+  CK(gemm_bf16(a.dZ2b, NH, 1, p.W2b, 1, NH, a.dH1, NH, M, NH, NH, 0, st));
+  hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH1, a.Z1,
+                     a.dZ1f, a.dZ1b, (long)M * NH);
+  // dW1 = X^T dZ1, db1
+  CK(gemm_bf16(a.Xb, 1, p.K1, a.dZ1b, NH, 1, gW1, NH, p.K1, NH, M, 0, st));
+  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, st, a.dZ1f, M, NH, NH, gb1);
+  CK(hipGetLastError());
+  return true;
+}
+
+double read_loss(Acts& a, hipStream_t st, std::string& err, bool& ok) {
+  double h[LOSS_BLOCKS];
+  ok = hipMemcpyAsync(h, a.part, sizeof h, hipMemcpyDeviceToHost, st) == hipSuccess &&
+       hipStreamSynchronize(st) == hipSuccess;
+  if (!ok) err = "loss read-back failed";
+  double s = 0;
+  for (double v : h) s += v;
+  return s;
+}
+
+}  // namespace
+
+bool train(const float* X, const float* T, int n, int nin, int nout, const TrainCfg& cfg, Net& net,
+           std::vector<float>* losses, hipStream_t st, std::string& err) {
+  if (n < 32 || nin < 1 || nout < 1 || cfg.batch < 16 || cfg.epochs < 1) {
+    err = "bad training arguments";
+    return false;
+  }
+  const int B = (cfg.batch + 15) / 16 * 16;
+  int nval = (int)std::floor(cfg.val_frac * n);
+  if (nval < 0) nval = 0;
+  const int ntr = n - nval;
+  net_init(net, nin, nout, cfg.seed);
+  Dev d;
+  Params p;
+  Acts a;
+  if (!alloc_params(d, p, nin, nout) || !alloc_acts(d, a, B, pad16(nin), pad16(nout))) {
+    err = "device allocation failed";
+    return false;
+  }
+  const size_t np = p.n1() + NH + p.n2() + NH + p.n3() + p.N3;
+  float* g = d.alloc<float>(np);
+  float* m = d.alloc<float>(np);
+  float* v = d.alloc<float>(np);
+  if (d.e != hipSuccess) { err = "device allocation failed"; return false; }
+  CK(hipMemsetAsync(m, 0, np * 4, st));
+  CK(hipMemsetAsync(v, 0, np * 4, st));
+  if (!upload_params(net, p, st, err)) return false;
+  float* gW1 = g;
+  float* gb1 = gW1 + p.n1();
+  float* gW2 = gb1 + NH;
+  float* gb2 = gW2 + p.n2();
+  float* gW3 = gb2 + NH;
+  float* gb3 = gW3 + p.n3();
+  struct Slot { float* w; float* g; size_t n; size_t off; uint16_t* wb; };
+  const Slot slots[6] = {{p.W1, gW1, p.n1(), 0, p.W1b},
+                         {p.b1, gb1, NH, p.n1(), nullptr},
+                         {p.W2, gW2, p.n2(), p.n1() + NH, p.W2b},
+                         {p.b2, gb2, NH, p.n1() + NH + p.n2(), nullptr},
+                         {p.W3, gW3, p.n3(), p.n1() + 2 * NH + p.n2(), p.W3b},
+                         {p.b3, gb3, (size_t)p.N3, p.n1() + 2 * NH + p.n2() + p.n3(), nullptr}};
+  const int steps_per_epoch = (ntr + B - 1) / B;
+  const long total_steps = (long)steps_per_epoch * cfg.epochs;
+  std::vector<int> perm(ntr), idx(B);
+  for (int i = 0; i < ntr; ++i) perm[i] = i;
+  uint64_t ctr = 0;
+  long step = 0;
+  for (int ep = 0; ep < cfg.epochs; ++ep) {
+    // Fisher-Yates shuffle with SplitMix64 draws
+    for (int i = ntr - 1; i > 0; --i) {
+      const double u = 0.5 * (semh::splitmix64_uniform(cfg.seed ^ 0x5eedull, ctr++) + 1.0);
+      int j = (int)(u * (i + 1));
+      if (j > i) j = i;
+      std::swap(perm[i], perm[j]);
+    }
+    double ep_loss = 0.0;
+    long ep_count = 0;
+    for (int s0 = 0; s0 < ntr; s0 += B) {
+      const int nv = std::min(B, ntr - s0);
+      const int M = (nv + 15) / 16 * 16;
+      for (int r = 0; r < M; ++r) idx[r] = r < nv ? perm[s0 + r] : -1;
+      CK(hipMemcpyAsync(a.idx, idx.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+      if (!fwd(p, a, X, M, st, err)) return false;
+      if (!bwd(p, a, T, M, nv, gW1, gb1, gW2, gb2, gW3, gb3, st, err)) return false;
+      ++step;
+      const double b1 = 0.9, b2 = 0.999;
+      const float lr_t = (float)(cfg.lr * 0.5 * (1.0 + std::cos(M_PI * (double)(step - 1) / total_steps)));
+      const float c1 = (float)(1.0 - std::pow(b1, (double)step));
+      const float c2 = (float)(1.0 - std::pow(b2, (double)step));
+      for (const Slot& sl : slots)
+        hipLaunchKernelGGL(k_adam, dim3(nblk(sl.n, 256)), dim3(256), 0, st, sl.w, sl.g,
+                           m + sl.off, v + sl.off, (long)sl.n, lr_t, (float)b1, (float)b2, 1e-8f,
+                           c1, c2, sl.wb);
+      CK(hipGetLastError());
+      bool ok = true;
+      if (s0 + B >= ntr) {  // epoch loss from the last batch only (cheap); full loss below
+        ep_loss = read_loss(a, st, err, ok);
+        ep_count = (long)nv * nout;
+        if (!ok) return false;
+      }
+    }
+    // validation loss over the held-out rows (full pass)
+    double vl = 0.0;
+    long vc = 0;
+    for (int s0 = 0; s0 < nval; s0 += B) {
+      const int nv = std::min(B, nval - s0);
+      const int M = (nv + 15) / 16 * 16;
+      for (int r = 0; r < M; ++r) idx[r] = r < nv ? ntr + s0 + r : -1;
+      CK(hipMemcpyAsync(a.idx, idx.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+      if (!fwd(p, a, X, M, st, err)) return false;
+      if (!bwd(p, a, T, M, nv, gW1, gb1, gW2, gb2, gW3, gb3, st, err)) return false;  // loss
+      bool ok = true;
+      vl += read_loss(a, st, err, ok);
+      if (!ok) return false;
+      vc += (long)nv * nout;
+    }
+    net.train_loss = (float)(ep_loss / std::max<long>(1, ep_count));
+    net.val_loss = vc ? (float)(vl / vc) : 0.f;
+    if (losses) {
+      losses->push_back(net.train_loss);
+      losses->push_back(net.val_loss);
+    }
+  }
+  net.epochs = cfg.epochs;
+  net.steps = (int)step;
+  return download_params(p, net, st, err);
+}
+
+bool forward(const Net& net, const float* X, int n, float* Y, hipStream_t st, std::string& err) {
+  const int B = 1024;
+  Dev d;
+  Params p;
+  Acts a;
+  if (!alloc_params(d, p, net.nin, net.nout) || !alloc_acts(d, a, B, pad16(net.nin), pad16(net.nout))) {
+    err = "device allocation failed";
+    return false;
+  }
+  if (!upload_params(net, p, st, err)) return false;
+  std::vector<int> idx(B);
+  for (int s0 = 0; s0 < n; s0 += B) {
+    const int nv = std::min(B, n - s0);
+    const int M = (nv + 15) / 16 * 16;
+    for (int r = 0; r < M; ++r) idx[r] = r < nv ? s0 + r : -1;
+    CK(hipMemcpyAsync(a.idx, idx.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+    if (!fwd(p, a, X, M, st, err)) return false;
+    // y = Y + b3 into the caller's rows s0 .. s0 + nv
+    hipLaunchKernelGGL(k_out_bias, dim3(nblk((size_t)nv * net.nout, 256)), dim3(256), 0, st, a.Y,
+                       p.N3, p.b3, nv, net.nout, Y + (size_t)s0 * net.nout);
+    CK(hipGetLastError());
+    CK(hipStreamSynchronize(st));
+  }
+  return true;
+}
+
+bool gradients(const Net& net, const float* X, const float* T, int n, float* grads, float* loss,
+               hipStream_t st, std::string& err) {
+  const int M = (n + 15) / 16 * 16;
+  Dev d;
+  Params p;
+  Acts a;
+  if (!alloc_params(d, p, net.nin, net.nout) || !alloc_acts(d, a, M, pad16(net.nin), pad16(net.nout))) {
+    err = "device allocation failed";
+    return false;
+  }
+  if (!upload_params(net, p, st, err)) return false;
+  const size_t np = p.n1() + NH + p.n2() + NH + p.n3() + p.N3;
+  float* g = d.alloc<float>(np);
+  if (d.e != hipSuccess) { err = "device allocation failed"; return false; }
+  std::vector<int> idx(M);
+  for (int r = 0; r < M; ++r) idx[r] = r < n ? r : -1;
+  CK(hipMemcpyAsync(a.idx, idx.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+  if (!fwd(p, a, X, M, st, err)) return false;
+  float* gW1 = g;
+  float* gb1 = gW1 + p.n1();
+  float* gW2 = gb1 + NH;
+  float* gb2 = gW2 + p.n2();
+  float* gW3 = gb2 + NH;
+  float* gb3 = gW3 + p.n3();
+  if (!bwd(p, a, T, M, n, gW1, gb1, gW2, gb2, gW3, gb3, st, err)) return false;
+  bool ok = true;
+  const double l = read_loss(a, st, err, ok);
+  if (!ok) return false;
+  if (loss) *loss = (float)(l / ((double)n * net.nout));
+  std::vector<float> hg(np);
+  CK(hipMemcpy(hg.data(), g, np * 4, hipMemcpyDeviceToHost));
+  // pack like the blob (unpadded)
+  float* o = grads;
+  for (int k = 0; k < net.nin; ++k)
+    for (int c = 0; c < NH; ++c) *o++ = hg[(size_t)k * NH + c];
+  for (int c = 0; c < NH; ++c) *o++ = hg[p.n1() + c];
+  for (size_t k = 0; k < p.n2(); ++k) *o++ = hg[p.n1() + NH + k];
+  for (int c = 0; c < NH; ++c) *o++ = hg[p.n1() + NH + p.n2() + c];
+  const size_t o3 = p.n1() + 2 * NH + p.n2();
+  for (int k = 0; k < NH; ++k)
+    for (int c = 0; c < net.nout; ++c) *o++ = hg[o3 + (size_t)k * p.N3 + c];
+  for (int c = 0; c < net.nout; ++c) *o++ = hg[o3 + p.n3() + c];
+  return true;
+}
+
+// ------------------------------------------------------------------------------------------
+// inference: one wave = 16 elements; layer 1 split into the residual part (K = n, padded) and
+// the precomputed geometric part Z1geo
+// ------------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ T ax_at(const T* __restrict__ y, const T* __restrict__ S, unsigned g,
+                                   unsigned nzn, unsigned P) {
+  const unsigned ix = g / nzn;
+  const unsigned iz = g - ix * nzn;
+  T v = y[g];
+  const unsigned q = ix / P;
+  if (q * P == ix) v += S[q * nzn + iz];
+  return v;
+}
+
+// One block = 16 elements, 4 waves.  Every wave takes part in the gather and normalisation; in
+// the three layers the output columns are split over the waves (hidden tiles 2w, 2w+1; output
+// tiles w, w+4), so a block has 4 independent MFMA chains and each wave loads a quarter of the
+// weights, all of them up front so that their latency hides behind the residual gather.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_stage_mlp(
+    const T* __restrict__ b, const T* __restrict__ y, const T* __restrict__ S,
+    const uint16_t* __restrict__ W1r, const float* __restrict__ Z1geo,
+    const uint16_t* __restrict__ W2, const float* __restrict__ b2,
+    const uint16_t* __restrict__ W3, const float* __restrict__ b3,
+    const float* __restrict__ abar, float* __restrict__ CE, int E, int Nz, unsigned nzn) {
+  constexpr int NP = P + 1, n = NP * NP, KR = (n + 15) / 16 * 16, KS1 = KR / 16, NT3 = KR / 16;
+  constexpr int XS = KR + 4, HS = NH + 4;  // padded LDS rows: the 16 rows of a fragment hit
+                                           // distinct banks
+  __shared__ __align__(16) uint16_t sX[16 * XS];
+  __shared__ __align__(16) uint16_t sH1[16 * HS];
+  __shared__ __align__(16) uint16_t sH2[16 * HS];
+  __shared__ float sS[16];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int li = lane & 15, kq = (lane >> 4) * 4;
+  const int e0 = blockIdx.x * 16;
+
+  // ---- weight fragments of this wave (transposed storage: 4 consecutive k per lane)
+  bf16x4 w1[2][KS1], w2[2][8], w3[2][8];
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int t = 2 * wave + tt;
+#pragma unroll
+    for (int k = 0; k < KS1; ++k)
+      w1[tt][k] = *reinterpret_cast<const bf16x4*>(W1r + (16 * t + li) * KR + 16 * k + kq);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      w2[tt][k] = *reinterpret_cast<const bf16x4*>(W2 + (16 * t + li) * NH + 16 * k + kq);
+    const int t3 = wave + 4 * tt;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      w3[tt][k] = t3 < NT3 ? *reinterpret_cast<const bf16x4*>(W3 + (16 * t3 + li) * NH + 16 * k + kq)
+                           : (bf16x4){0, 0, 0, 0};
+  }
+
+  // layer-1 accumulators start from the precomputed geometric part (loaded before the gather)
+  f32x4 acc[2];
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int er = e0 + kq + v;
+      acc[tt][v] = er < E ? Z1geo[(long)er * NH + 16 * (2 * wave + tt) + li] : 0.f;
+    }
+
+  // ---- gather r = b - A x (A x = y + S on shared vertical lines): 16 lanes per element
+  const int el = tid >> 4, lg = tid & 15;
+  const int e = e0 + el;
+  float rv[KS1];
+  float ss = 0.f;
+  if (e < E) {
+    const int ex = e / Nz, ez = e - ex * Nz;
+    const unsigned base = (unsigned)(ex * P) * nzn + ez * P;
+    const unsigned sb = (unsigned)ex * nzn + ez * P;
+#pragma unroll
+    for (int k = 0; k < KS1; ++k) {
+      const int l = lg + 16 * k;
+      rv[k] = 0.f;
+      if (l < n) {
+        const int i = l / NP, j = l - (l / NP) * NP;
+        const unsigned g = base + i * nzn + j;
+        T ax = y[g];
+        if (i == 0) ax += S[sb + j];
+        if (i == P) ax += S[sb + nzn + j];
+        rv[k] = (float)(b[g] - ax);
+      }
+      ss += rv[k] * rv[k];
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < KS1; ++k) rv[k] = 0.f;
+  }
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, 64);
+  const float s = sqrtf(ss);
+  if (lg == 0) sS[el] = s;
+#pragma unroll
+  for (int k = 0; k < KS1; ++k) sX[el * XS + lg + 16 * k] = f2bf(s > 0.f ? rv[k] / s : 0.f);
+  __syncthreads();
+
+  // ---- layer 1: Z1 = Xr W1r + Z1geo (the geometric part of X W1 + b1 is precomputed)
+#pragma unroll
+  for (int k = 0; k < KS1; ++k) {
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(sX + li * XS + 16 * k + kq);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma16(a, w1[tt][k], acc[tt]);
+  }
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sH1[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
+  __syncthreads();
+
+  // ---- layer 2: Z2 = H1 W2 + b2
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const float bb = b2[16 * (2 * wave + tt) + li];
+    acc[tt] = (f32x4){bb, bb, bb, bb};
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH1 + li * HS + 16 * k + kq);
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma16(a, w2[tt][k], acc[tt]);
+  }
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) sH2[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
+  __syncthreads();
+
+  // ---- layer 3: Y = H2 W3 + b3; c_e = (s_e / a_e) y
+#pragma unroll
+  for (int tt = 0; tt < 2; ++tt) {
+    const int t3 = wave + 4 * tt;
+    if (t3 >= NT3) continue;  // wave-uniform
+    const int col = 16 * t3 + li;
+    const float bb = b3[col];
+    f32x4 c = (f32x4){bb, bb, bb, bb};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH2 + li * HS + 16 * k + kq);
+      c = mfma16(a, w3[tt][k], c);
+    }
+    if (col < n)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int er = e0 + kq + v;
+        if (er < E) CE[(long)er * n + col] = sS[kq + v] / abar[er] * c[v];
+      }
+  }
+}
+
+hipError_t stage_mlp(const Stage& s, bool dbl, const void* b, const void* y, const void* S,
+                     hipStream_t st) {
+  if (s.P < 1 || s.P > 8 || s.nout != (s.P + 1) * (s.P + 1)) return hipErrorInvalidValue;
+  const unsigned blocks = nblk(s.E, 16);
+#define SEM_STAGE_MLP(PP, TT)                                                                    \
+  hipLaunchKernelGGL((k_stage_mlp<PP, TT>), dim3(blocks), dim3(256), 0, st, (const TT*)b,        \
+                     (const TT*)y, (const TT*)S, s.W1r, s.Z1geo, s.W2, s.b2, s.W3, s.b3, s.abar, \
+                     s.CE, (int)s.E, s.Nz, (unsigned)s.nzn)
+#define SEM_STAGE_MLP_P(PP)          \
+  case PP:                           \
+    if (dbl) SEM_STAGE_MLP(PP, double); \
+    else SEM_STAGE_MLP(PP, float);   \
+    break;
+  switch (s.P) {
+    SEM_STAGE_MLP_P(1)
+    SEM_STAGE_MLP_P(2)
+    SEM_STAGE_MLP_P(3)
+    SEM_STAGE_MLP_P(4)
+    SEM_STAGE_MLP_P(5)
+    SEM_STAGE_MLP_P(6)
+    SEM_STAGE_MLP_P(7)
+    SEM_STAGE_MLP_P(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SEM_STAGE_MLP_P
+#undef SEM_STAGE_MLP
+  return hipGetLastError();
+}
+
+// c[g] = average of the element-local corrections of the elements holding node g (the weight
+// W = (sum R R^T)^-1), zero on the Dirichlet surface when masked.  Contributions are added in a
+// fixed order: (left, lower), (left, upper), (right, lower), (right, upper) element.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_stage_assemble(const float* __restrict__ CE,
+                                                        T* __restrict__ c, int Nx, int Nz,
+                                                        unsigned nzn, unsigned N, int masked) {
+  constexpr int NP = P + 1, n = NP * NP;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const int ix = g / nzn, iz = g - ix * nzn;
+    if (masked && iz == (int)nzn - 1) {
+      c[g] = (T)0;
+      continue;
+    }
+    const int qx = ix / P, rx = ix - qx * P, qz = iz / P, rz = iz - qz * P;
+    const bool xl = rx == 0 && qx > 0, xr = qx < Nx, zl = rz == 0 && qz > 0, zr = qz < Nz;
+    float s = 0.f;
+    int cnt = 0;
+    if (xl && zl) { s += CE[((long)(qx - 1) * Nz + qz - 1) * n + P * NP + P]; ++cnt; }
+    if (xl && zr) { s += CE[((long)(qx - 1) * Nz + qz) * n + P * NP + rz]; ++cnt; }
+    if (xr && zl) { s += CE[((long)qx * Nz + qz - 1) * n + rx * NP + P]; ++cnt; }
+    if (xr && zr) { s += CE[((long)qx * Nz + qz) * n + rx * NP + rz]; ++cnt; }
+    c[g] = (T)(s / (float)cnt);
+  }
+}
+
+hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStream_t st) {
+  const unsigned N = (unsigned)((size_t)(s.Nx * s.P + 1) * s.nzn);
+  const unsigned blocks = std::min(nblk(N, 256), 8192u);
+#define SEM_STAGE_ASM(PP, TT)                                                                   \
+  hipLaunchKernelGGL((k_stage_assemble<PP, TT>), dim3(blocks), dim3(256), 0, st, s.CE, (TT*)c, \
+                     s.Nx, s.Nz, (unsigned)s.nzn, N, masked)
+#define SEM_STAGE_ASM_P(PP)              \
+  case PP:                               \
+    if (dbl) SEM_STAGE_ASM(PP, double);  \
+    else SEM_STAGE_ASM(PP, float);       \
+    break;
+  switch (s.P) {
+    SEM_STAGE_ASM_P(1)
+    SEM_STAGE_ASM_P(2)
+    SEM_STAGE_ASM_P(3)
+    SEM_STAGE_ASM_P(4)
+    SEM_STAGE_ASM_P(5)
+    SEM_STAGE_ASM_P(6)
+    SEM_STAGE_ASM_P(7)
+    SEM_STAGE_ASM_P(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SEM_STAGE_ASM_P
+#undef SEM_STAGE_ASM
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ double wsum(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ double bsum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wsum(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < nw; ++k) s += sh[k];
+  return s;
+}
+
+// Step length of the stage.  k_stage_dots writes per-block partial sums of c.r and c.q
+// (r = b - A x, q = A c); k_stage_step adds them in block order (the result does not depend on
+// scheduling) and stores the accepted step: alpha = c.r / c.q if that is finite and positive
+// (the A-norm of the error then drops by (c.r)^2 / c.q), else 0 and the rejection is counted.
+// flags: [0] rejections, bytes 8..15 the step.
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage_dots(const T* __restrict__ c, const T* __restrict__ b,
+                                                    const T* __restrict__ y, const T* __restrict__ S,
+                                                    const T* __restrict__ yq, const T* __restrict__ Sq,
+                                                    double* parts, unsigned N, unsigned nzn,
+                                                    unsigned P) {
+  __shared__ double sh[8];
+  double a0 = 0, a1 = 0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const double r = (double)(b[g] - ax_at(y, S, g, nzn, P));
+    const double q = (double)ax_at(yq, Sq, g, nzn, P);
+    const double cv = (double)c[g];
+    a0 += cv * r;
+    a1 += cv * q;
+  }
+  const double v0 = bsum(a0, sh), v1 = bsum(a1, sh);
+  if (threadIdx.x == 0) {
+    parts[blockIdx.x] = v0;
+    parts[semk::NRED + blockIdx.x] = v1;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_stage_step(const double* __restrict__ parts, int* flags) {
+  __shared__ double sh[8];
+  double p0 = 0.0, p1 = 0.0;
+  for (int k = threadIdx.x; k < semk::NRED; k += blockDim.x) {
+    p0 += parts[k];
+    p1 += parts[semk::NRED + k];
+  }
+  const double cr = bsum(p0, sh), cq = bsum(p1, sh);
+  if (threadIdx.x == 0) {
+    const double alpha = cr / cq;
+    const bool ok = isfinite(alpha) && alpha > 0.0;
+    *reinterpret_cast<double*>(flags + 2) = ok ? alpha : 0.0;
+    if (!ok) flags[0] += 1;
+  }
+}
+
+hipError_t stage_dots(bool dbl, const void* c, const void* b, const void* y, const void* S,
+                      const void* yq, const void* Sq, double* parts, int* flags, unsigned N,
+                      unsigned nzn, unsigned P, hipStream_t st) {
+  if (dbl)
+    hipLaunchKernelGGL(k_stage_dots<double>, dim3(semk::NRED), dim3(256), 0, st, (const double*)c,
+                       (const double*)b, (const double*)y, (const double*)S, (const double*)yq,
+                       (const double*)Sq, parts, N, nzn, P);
+  else
+    hipLaunchKernelGGL(k_stage_dots<float>, dim3(semk::NRED), dim3(256), 0, st, (const float*)c,
+                       (const float*)b, (const float*)y, (const float*)S, (const float*)yq,
+                       (const float*)Sq, parts, N, nzn, P);
+  hipLaunchKernelGGL(k_stage_step, dim3(1), dim3(256), 0, st, (const double*)parts, flags);
+  return hipGetLastError();
+}
+
+// x += alpha c and R = r - alpha q with the step chosen by k_stage_dots (alpha = 0: R = r)
+template <typename T>
+__global__ __launch_bounds__(256) void k_stage_update(T* __restrict__ x, T* __restrict__ R,
+                                                      const T* __restrict__ c, const T* __restrict__ b,
+                                                      const T* __restrict__ y, const T* __restrict__ S,
+                                                      const T* __restrict__ yq, const T* __restrict__ Sq,
+                                                      const int* __restrict__ flags, unsigned N,
+                                                      unsigned nzn, unsigned P) {
+  const T al = (T)*reinterpret_cast<const double*>(flags + 2);
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const T r = b[g] - ax_at(y, S, g, nzn, P);
+    if (al != (T)0) {
+      x[g] += al * c[g];
+      R[g] = r - al * ax_at(yq, Sq, g, nzn, P);
+    } else {
+      R[g] = r;
+    }
+  }
+}
+
+hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* b, const void* y,
+                        const void* S, const void* yq, const void* Sq, const int* flags, unsigned N,
+                        unsigned nzn, unsigned P, hipStream_t st) {
+  const unsigned blocks = std::min(nblk(N, 256), 8192u);
+  if (dbl)
+    hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(256), 0, st, (double*)x,
+                       (double*)R, (const double*)c, (const double*)b, (const double*)y,
+                       (const double*)S, (const double*)yq, (const double*)Sq, flags, N, nzn, P);
+  else
+    hipLaunchKernelGGL(k_stage_update<float>, dim3(blocks), dim3(256), 0, st, (float*)x,
+                       (float*)R, (const float*)c, (const float*)b, (const float*)y,
+                       (const float*)S, (const float*)yq, (const float*)Sq, flags, N, nzn, P);
+  return hipGetLastError();
+}
+
+// training features: one block per element.  Targets: (a_e/s_e) R_e e for a given error e, or
+// (a_e/s_e) Ainv_e R_e r with the element-block inverse Ainv_e when e is null
+__global__ __launch_bounds__(128) void k_features(const double* __restrict__ r,
+                                                  const double* __restrict__ e,
+                                                  const double* __restrict__ Ainv,
+                                                  const float* __restrict__ geo,
+                                                  const float* __restrict__ abar, float* __restrict__ X,
+                                                  float* __restrict__ Tt, int P, int Nz, int nzn) {
+  __shared__ double sh[8];
+  const int el = blockIdx.x;
+  const int NP = P + 1, n = NP * NP;
+  const int ex = el / Nz, ez = el - ex * Nz;
+  double s2 = 0.0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const int i = l / NP, j = l - i * NP;
+    const double v = r[(size_t)(ex * P + i) * nzn + ez * P + j];
+    s2 += v * v;
+  }
+  const double s = sqrt(bsum(s2, sh));
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const int i = l / NP, j = l - i * NP;
+    const size_t g = (size_t)(ex * P + i) * nzn + ez * P + j;
+    X[(size_t)el * 5 * n + l] = s > 0 ? (float)(r[g] / s) : 0.f;
+    if (Tt && e) Tt[(size_t)el * n + l] = s > 0 ? (float)((double)abar[el] / s * e[g]) : 0.f;
+    if (Tt && !e) {
+      double t = 0.0;
+      const double* row = Ainv + ((size_t)el * n + l) * n;
+      for (int q = 0; q < n; ++q) {
+        const int qi = q / NP, qj = q - qi * NP;
+        t += row[q] * r[(size_t)(ex * P + qi) * nzn + ez * P + qj];
+      }
+      Tt[(size_t)el * n + l] = s > 0 ? (float)((double)abar[el] / s * t) : 0.f;
+    }
+  }
+  for (int l = threadIdx.x; l < 4 * n; l += blockDim.x)
+    X[(size_t)el * 5 * n + n + l] = geo[(size_t)el * 4 * n + l];
+}
+
+hipError_t features(const double* r, const double* e, const double* Ainv, const float* geo,
+                    const float* abar, float* X, float* T, size_t E, int P, int Nz, int nzn,
+                    hipStream_t st) {
+  hipLaunchKernelGGL(k_features, dim3((unsigned)E), dim3(128), 0, st, r, e, Ainv, geo, abar, X, T,
+                     P, Nz, nzn);
+  return hipGetLastError();
+}
+
+}  // namespace semm

@@ -9,16 +9,19 @@
 
 #include <algorithm>
 #include <chrono>
+#include <utility>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
 #include "../../include/sem.h"
 #include "host_math.h"
 #include "kernels.h"
+#include "mlp.h"
 
 namespace {
 
@@ -65,6 +68,16 @@ struct Ctx {
   int* rowmap = nullptr;
   // FP64 right-hand side of the next V-cycle, read by the first smoothing step of level 0
   const double* vin64 = nullptr;
+  // learned stage (fine level)
+  semm::Stage stage;
+  bool stage_alloc = false;
+  int stage_mode = 1;          // bit 0: after pre-smoothing, bit 1: before post-smoothing
+  void *Rbuf = nullptr, *cbuf = nullptr, *yq = nullptr, *Sq = nullptr;
+  double* stparts = nullptr;
+  std::vector<float> geo_h;    // [E x 4n] geometric features (host)
+  std::vector<float> abar_h;   // [E] mean element-matrix diagonal (host)
+  float* geo_d = nullptr;
+  double* ainv_d = nullptr;    // [E x n x n] inverses of R_e A R_e^T (training targets)
   // graphs
   hipGraphExec_t g_first = nullptr, g_iter = nullptr, g_pdc = nullptr;
   bool use_graphs = true;
@@ -216,6 +229,21 @@ void coarse_solve(Ctx* c) {
   }
 }
 
+// learned stage on level 0: reads L.b, L.x; updates L.x, writes the new residual to Rbuf
+void learned_stage(Ctx* c) {
+  DLevel& L = c->lev[0];
+  semm::Stage& s = c->stage;
+  apply_level(c, 0, L.x, c->masked);
+  HK(semm::stage_mlp(s, L.dbl, L.b, L.y, L.S, c->st));
+  HK(semm::stage_assemble(s, L.dbl, c->cbuf, c->masked, c->st));
+  HK(semk::apply2d(L.P, L.dbl, L.gt, c->cbuf, c->yq, c->Sq, L.G, L.D, L.Nx, L.Nz, c->masked,
+                   c->st));
+  HK(semm::stage_dots(L.dbl, c->cbuf, L.b, L.y, L.S, c->yq, c->Sq, c->stparts, s.skips, L.N,
+                      L.nzn, L.P, c->st));
+  HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, L.b, L.y, L.S, c->yq, c->Sq, s.skips, L.N,
+                        L.nzn, L.P, c->st));
+}
+
 // z = B r on level 0 buffers: input r (FP64, device), output lev[0].x
 void vcycle(Ctx* c, const double* r) {
   const int L = (int)c->lev.size();
@@ -231,12 +259,21 @@ void vcycle(Ctx* c, const double* r) {
   for (int l = 0; l < L - 1; ++l) {
     smooth(c, l, true);
     if (l == 0) c->vin64 = nullptr;
+    if (l == 0 && c->stage.enabled && (c->stage_mode & 1)) {
+      learned_stage(c);
+      DLevel& F = c->lev[0];
+      DLevel& C1 = c->lev[1];
+      HK(semk::restrict2d(F.dbl, C1.dbl, c->Rbuf, nullptr, nullptr, 0, C1.b, F.J, F.Nx, F.Nz, F.P,
+                          C1.P, c->masked, c->st));
+      continue;
+    }
     apply_level(c, l, c->lev[l].x, c->masked);
     restrict_to(c, l, true);
   }
   coarse_solve(c);
   for (int l = L - 2; l >= 0; --l) {
     prolong_from(c, l);
+    if (l == 0 && c->stage.enabled && (c->stage_mode & 2)) learned_stage(c);
     smooth(c, l, false);
   }
   c->vin64 = nullptr;
@@ -559,6 +596,41 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       c->face_idx.push_back(upload(c, idx));
       c->face_w.push_back(upload(c, G.face_w[f]));
       c->face_n.push_back(idx.size());
+    }
+  }
+  // learned-stage geometry (fine level): features and mean element-matrix diagonal
+  {
+    const semh::LevelGeom& G = L0.geo;
+    const int NP = G.NP, n = NP * NP;
+    const size_t E = G.E, NL = n;
+    c->geo_h.assign(E * 4 * n, 0.f);
+    c->abar_h.assign(E, 0.f);
+    const double* Dm = G.D.data();
+    for (size_t e = 0; e < E; ++e) {
+      const double* Grr = &G.G[0 * E * NL + e * NL];
+      const double* Grs = &G.G[1 * E * NL + e * NL];
+      const double* Gss = &G.G[2 * E * NL + e * NL];
+      const double* ms = &G.mass[e * NL];
+      double gsum = 0, msum = 0, dsum = 0;
+      for (int l = 0; l < n; ++l) {
+        gsum += Grr[l] + Gss[l];
+        msum += ms[l];
+        const int i = l / NP, j = l % NP;
+        double dl = 0;
+        for (int k = 0; k < NP; ++k) dl += Dm[k * NP + i] * Dm[k * NP + i] * Grr[k * NP + j];
+        dl += 2.0 * Dm[i * NP + i] * Dm[j * NP + j] * Grs[l];
+        for (int k = 0; k < NP; ++k) dl += Dm[k * NP + j] * Dm[k * NP + j] * Gss[i * NP + k];
+        dsum += dl;
+      }
+      const double g = gsum / n, mm = msum / n;
+      float* out = &c->geo_h[e * 4 * n];
+      for (int l = 0; l < n; ++l) {
+        out[l] = (float)(Grr[l] / g);
+        out[n + l] = (float)(Grs[l] / g);
+        out[2 * n + l] = (float)(Gss[l] / g);
+        out[3 * n + l] = (float)(ms[l] / mm);
+      }
+      c->abar_h[e] = (float)(dsum / n);
     }
   }
   // coarse factorisation
@@ -921,6 +993,7 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     enter(c);
     DLevel& L0 = c->lev[0];
     const unsigned N = L0.N;
+    if (c->stage_alloc) HK(hipMemsetAsync(c->stage.skips, 0, sizeof(int), c->st));
     HK(hipMemcpyAsync(c->bo, rhs, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     HK(hipMemcpyAsync(c->xo, x, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     HK(semk::copy_top(c->xo, c->bo, L0.nxn, L0.nzn, c->st));
@@ -980,8 +1053,225 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     HK(hipStreamSynchronize(c->st));
     inf->iters = it;
     inf->rel_res = rel;
+    if (c->stage_alloc && c->stage.enabled) {
+      int sk = 0;
+      HK(hipMemcpy(&sk, c->stage.skips, sizeof(int), hipMemcpyDeviceToHost));
+      inf->learned_skips = sk;
+    }
     inf->ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     return st;
+  });
+}
+
+static thread_local std::string g_mlp_err;
+
+size_t sem_mlp_blob_size(int nin, int nout) {
+  if (nin < 1 || nout < 1) return 0;
+  return semm::blob_size(nin, nout);
+}
+
+static void stage_buffers(Ctx* c) {
+  if (c->stage_alloc) return;
+  DLevel& L = c->lev[0];
+  const int n = L.NP * L.NP;
+  const size_t E = L.geo.E;
+  semm::Stage& s = c->stage;
+  s.P = L.P;
+  s.Nx = L.Nx;
+  s.Nz = L.Nz;
+  s.nzn = L.nzn;
+  s.E = E;
+  s.nout = n;
+  s.nin = 5 * n;
+  const int KR = semm::pad16(n), N3 = semm::pad16(n);
+  s.W1r = (uint16_t*)dalloc(c, (size_t)KR * semm::NH * 2);
+  s.W2 = (uint16_t*)dalloc(c, (size_t)semm::NH * semm::NH * 2);
+  s.W3 = (uint16_t*)dalloc(c, (size_t)semm::NH * N3 * 2);
+  s.b2 = (float*)dalloc(c, semm::NH * 4);
+  s.b3 = (float*)dalloc(c, (size_t)N3 * 4);
+  s.Z1geo = (float*)dalloc(c, E * semm::NH * 4);
+  s.abar = upload(c, c->abar_h);
+  s.CE = (float*)dalloc(c, E * n * 4);
+  s.skips = (int*)dalloc(c, 64);
+  const size_t eb = esz(L.dbl);
+  c->Rbuf = dalloc(c, L.N * eb);
+  c->cbuf = dalloc(c, L.N * eb);
+  c->yq = dalloc(c, L.N * eb);
+  c->Sq = dalloc(c, L.nS * eb);
+  c->stparts = (double*)dalloc(c, 2 * semk::NRED * 8);
+  c->stage_alloc = true;
+}
+
+// inverses of the element blocks R_e A R_e^T of the masked assembled fine operator (host FP64)
+static std::vector<double> element_block_inverses(Ctx* c) {
+  const semh::LevelGeom& G = c->lev[0].geo;
+  const int NP = G.NP, n = NP * NP;
+  const size_t E = G.E;
+  auto gidx = [&](size_t e, int l) {
+    const size_t ex = e / G.Nz, ez = e % G.Nz;
+    return (ex * G.P + l / NP) * (size_t)G.nzn + ez * G.P + l % NP;
+  };
+  auto top = [&](size_t g) { return c->masked && (g % G.nzn) == (size_t)(G.nzn - 1); };
+  // assembled entries between nodes of one element, keyed by (gi, gj)
+  std::vector<std::pair<uint64_t, double>> ent;
+  std::vector<double> Ae((size_t)n * n);
+  for (size_t e = 0; e < E; ++e) {
+    semh::element_matrix(G, G.G, e, Ae.data());
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        const uint64_t gi = gidx(e, a), gj = gidx(e, b);
+        ent.push_back({gi * (uint64_t)G.N + gj, Ae[(size_t)a * n + b]});
+      }
+  }
+  std::sort(ent.begin(), ent.end(), [](const auto& x, const auto& y) { return x.first < y.first; });
+  std::vector<std::pair<uint64_t, double>> asm_;
+  for (const auto& p : ent) {
+    if (!asm_.empty() && asm_.back().first == p.first) asm_.back().second += p.second;
+    else asm_.push_back(p);
+  }
+  auto lookup = [&](uint64_t key) {
+    auto it = std::lower_bound(asm_.begin(), asm_.end(), std::make_pair(key, -1e300),
+                               [](const auto& x, const auto& y) { return x.first < y.first; });
+    return (it != asm_.end() && it->first == key) ? it->second : 0.0;
+  };
+  std::vector<double> out(E * (size_t)n * n), Ab((size_t)n * n), Ai((size_t)n * n);
+  for (size_t e = 0; e < E; ++e) {
+    for (int a = 0; a < n; ++a)
+      for (int b = 0; b < n; ++b) {
+        const uint64_t gi = gidx(e, a), gj = gidx(e, b);
+        double v = lookup(gi * (uint64_t)G.N + gj);
+        if (top(gi) || top(gj)) v = (gi == gj) ? 1.0 : 0.0;
+        Ab[(size_t)a * n + b] = v;
+      }
+    if (!semh::dense_inverse_public(n, Ab.data(), Ai.data()))
+      throw ArgFail{"singular element block"};
+    std::copy(Ai.begin(), Ai.end(), out.begin() + e * (size_t)n * n);
+  }
+  return out;
+}
+
+static std::vector<uint16_t> bf16_vec(const float* p, size_t rows, size_t cols, size_t prow,
+                                      size_t pcol) {
+  std::vector<uint16_t> out(prow * pcol, 0);
+  for (size_t r = 0; r < rows; ++r)
+    for (size_t q = 0; q < cols; ++q) out[r * pcol + q] = semh::bf16_bits(p[r * cols + q]);
+  return out;
+}
+
+sem_status sem_learned_load(sem_ctx* ctx, const void* blob, size_t nbytes, int enable) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
+    semm::Net net;
+    std::string e;
+    if (!semm::net_from_blob(blob, nbytes, net, e)) throw ArgFail{e};
+    DLevel& L = c->lev[0];
+    const int n = L.NP * L.NP;
+    if (n > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
+    if (net.nin != 5 * n || net.nout != n) throw ArgFail{"network sizes do not match the mesh"};
+    if (c->lev.size() < 2) throw ArgFail{"learned stage needs at least two levels"};
+    HK(hipStreamSynchronize(c->st));
+    stage_buffers(c);
+    semm::Stage& s = c->stage;
+    const int NH = semm::NH, KR = semm::pad16(n), N3 = semm::pad16(n), K4 = semm::pad16(4 * n);
+    const size_t E = s.E, Mp = (E + 15) / 16 * 16;
+    auto put16 = [&](uint16_t* dst, const std::vector<uint16_t>& h) {
+      HK(hipMemcpy(dst, h.data(), h.size() * 2, hipMemcpyHostToDevice));
+    };
+    // transposed (output-major) copies for the inference kernel
+    auto transpose = [](const float* W, int rows, int cols) {
+      std::vector<float> T((size_t)rows * cols);
+      for (int r = 0; r < rows; ++r)
+        for (int q = 0; q < cols; ++q) T[(size_t)q * rows + r] = W[(size_t)r * cols + q];
+      return T;
+    };
+    put16(s.W1r, bf16_vec(transpose(net.W1.data(), n, NH).data(), NH, n, NH, KR));
+    put16(s.W2, bf16_vec(transpose(net.W2.data(), NH, NH).data(), NH, NH, NH, NH));
+    put16(s.W3, bf16_vec(transpose(net.W3.data(), NH, n).data(), n, NH, N3, NH));
+    HK(hipMemcpy(s.b2, net.b2.data(), NH * 4, hipMemcpyHostToDevice));
+    std::vector<float> b3(N3, 0.f);
+    std::copy(net.b3.begin(), net.b3.end(), b3.begin());
+    HK(hipMemcpy(s.b3, b3.data(), N3 * 4, hipMemcpyHostToDevice));
+    // Z1geo = Xg W1g + b1 (geometric part of layer 1), computed once per mesh on the GPU
+    std::vector<uint16_t> xg = bf16_vec(c->geo_h.data(), E, 4 * n, Mp, K4);
+    std::vector<uint16_t> w1g = bf16_vec(net.W1.data() + (size_t)n * NH, 4 * n, NH, K4, NH);
+    void *dx = nullptr, *dw = nullptr, *dz = nullptr, *db = nullptr;
+    HK(hipMalloc(&dx, xg.size() * 2));
+    HK(hipMalloc(&dw, w1g.size() * 2));
+    HK(hipMalloc(&dz, Mp * NH * 4));
+    HK(hipMalloc(&db, NH * 4));
+    HK(hipMemcpy(dx, xg.data(), xg.size() * 2, hipMemcpyHostToDevice));
+    HK(hipMemcpy(dw, w1g.data(), w1g.size() * 2, hipMemcpyHostToDevice));
+    HK(hipMemcpy(db, net.b1.data(), NH * 4, hipMemcpyHostToDevice));
+    HK(semm::gemm_bf16((const uint16_t*)dx, K4, 1, (const uint16_t*)dw, NH, 1, (float*)dz, NH,
+                       (int)Mp, NH, K4, 0, c->st));
+    HK(semm::add_bias((float*)dz, (const float*)db, (int)Mp, NH, c->st));
+    HK(hipMemcpyAsync(s.Z1geo, dz, E * NH * 4, hipMemcpyDeviceToDevice, c->st));
+    HK(hipStreamSynchronize(c->st));
+    HK(hipFree(dx));
+    HK(hipFree(dw));
+    HK(hipFree(dz));
+    HK(hipFree(db));
+    s.enabled = (enable & 3) != 0;
+    c->stage_mode = (enable & 3) ? (enable & 3) : 1;
+    drop_graphs(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_learned_enable(sem_ctx* ctx, int enable) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!c->stage_alloc) return SEM_ERR_STATE;
+    HK(hipStreamSynchronize(c->st));
+    c->stage.enabled = (enable & 3) != 0;
+    if (enable & 3) c->stage_mode = enable & 3;
+    drop_graphs(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_learned_features(sem_ctx* ctx, const double* r, const double* e, float* X,
+                                float* T) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
+    if (!r || !X) throw ArgFail{"null vector"};
+    DLevel& L = c->lev[0];
+    if (L.NP * L.NP > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
+    HK(hipStreamSynchronize(c->st));
+    stage_buffers(c);
+    if (!c->geo_d) c->geo_d = upload(c, c->geo_h);
+    if (T && !e && !c->ainv_d) {
+      if (L.geo.E > 4096) throw ArgFail{"element-block targets are for training meshes (<= 4096 elements)"};
+      c->ainv_d = upload(c, element_block_inverses(c));
+    }
+    enter(c);
+    HK(semm::features(r, e, c->ainv_d, c->geo_d, c->stage.abar, X, T, L.geo.E, L.P, L.Nz, L.nzn,
+                      c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_learned_stage(sem_ctx* ctx, const double* b, double* x, int* accepted) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!c->stage_alloc) return SEM_ERR_STATE;
+    if (!b || !x) throw ArgFail{"null vector"};
+    enter(c);
+    DLevel& L = c->lev[0];
+    int before = 0, after = 0;
+    HK(hipMemcpyAsync(&before, c->stage.skips, 4, hipMemcpyDeviceToHost, c->st));
+    HK(semk::cast_to(L.dbl, b, L.b, L.N, c->st));
+    HK(semk::cast_to(L.dbl, x, L.x, L.N, c->st));
+    learned_stage(c);
+    HK(semk::cast_from(L.dbl, L.x, x, L.N, c->st));
+    HK(hipMemcpyAsync(&after, c->stage.skips, 4, hipMemcpyDeviceToHost, c->st));
+    HK(hipStreamSynchronize(c->st));
+    leave(c);
+    if (accepted) *accepted = (after == before) ? 1 : 0;
+    return SEM_OK;
   });
 }
 
@@ -1049,7 +1339,75 @@ sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int outer, double* 
 
 const char* sem_last_error(const sem_ctx* ctx) {
   const Ctx* c = C(ctx);
-  return c ? c->err.c_str() : g_setup_err;
+  if (c) return c->err.c_str();
+  return g_mlp_err.empty() ? g_setup_err : g_mlp_err.c_str();
+}
+
+static sem_status mlp_guard(const std::function<bool(std::string&)>& body) {
+  g_mlp_err.clear();
+  try {
+    std::string e;
+    if (!body(e)) {
+      g_mlp_err = e.empty() ? "training kernels failed" : e;
+      return e.rfind("bad", 0) == 0 || e.find("mismatch") != std::string::npos ? SEM_ERR_ARG
+                                                                               : SEM_ERR_HIP;
+    }
+    return SEM_OK;
+  } catch (const std::bad_alloc&) {
+    g_mlp_err = "host allocation failed";
+    return SEM_ERR_ALLOC;
+  } catch (...) {
+    g_mlp_err = "unexpected internal error";
+    return SEM_ERR_STATE;
+  }
+}
+
+sem_status sem_mlp_train(const float* X, const float* T, int n, int nin, int nout,
+                         const sem_train_cfg* cfg, void* blob, size_t nbytes, float* losses) {
+  return mlp_guard([&](std::string& e) {
+    if (!X || !T || !blob || nin < 1 || nout < 1) { e = "bad arguments"; return false; }
+    if (nbytes != semm::blob_size(nin, nout)) { e = "bad blob size (size mismatch)"; return false; }
+    semm::TrainCfg tc;
+    if (cfg) {
+      tc.epochs = cfg->epochs;
+      tc.batch = cfg->batch;
+      tc.lr = cfg->lr;
+      tc.val_frac = cfg->val_frac;
+      tc.seed = cfg->seed;
+    }
+    if (tc.epochs < 1 || tc.epochs > 100000 || tc.batch < 16 || tc.batch > 65536 ||
+        !(tc.lr > 0) || tc.val_frac < 0 || tc.val_frac >= 1) { e = "bad training configuration"; return false; }
+    hipStream_t st = nullptr;
+    if (hipStreamCreate(&st) != hipSuccess) { e = "stream creation failed"; return false; }
+    semm::Net net;
+    std::vector<float> ls;
+    const bool ok = semm::train(X, T, n, nin, nout, tc, net, &ls, st, e);
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (!ok) return false;
+    semm::net_to_blob(net, blob);
+    if (losses) std::copy(ls.begin(), ls.end(), losses);
+    return true;
+  });
+}
+
+sem_status sem_mlp_forward(const void* blob, size_t nbytes, const float* X, int n, float* Y) {
+  return mlp_guard([&](std::string& e) {
+    semm::Net net;
+    if (!semm::net_from_blob(blob, nbytes, net, e)) { e = "bad blob: " + e; return false; }
+    if (!X || !Y || n < 1) { e = "bad arguments"; return false; }
+    return semm::forward(net, X, n, Y, nullptr, e);
+  });
+}
+
+sem_status sem_mlp_gradients(const void* blob, size_t nbytes, const float* X, const float* T,
+                             int n, float* grads, float* loss) {
+  return mlp_guard([&](std::string& e) {
+    semm::Net net;
+    if (!semm::net_from_blob(blob, nbytes, net, e)) { e = "bad blob: " + e; return false; }
+    if (!X || !T || !grads || n < 1 || n > 65536) { e = "bad arguments"; return false; }
+    return semm::gradients(net, X, T, n, grads, loss, nullptr, e);
+  });
 }
 
 const char* sem_status_string(sem_status s) {

@@ -1,0 +1,142 @@
+"""Training data and training of the learned smoothing stage, driven through the C ABI.
+
+Pairs come from the library's own plain p-multigrid (FP64, Chebyshev(3), levels 8-4-2-1).  For
+each seeded training geometry, defect-correction cycles x <- x + B(b - A x) are run; at each
+cycle, at the point where the stage acts (finest level, after pre-smoothing of the V-cycle's
+right-hand side r), the residual r_pre = r - A x_pre is turned into element features by
+sem_learned_features.  Right-hand sides: seeded smooth Gaussian sources and white noise; in
+addition raw random residuals go through the same feature map so the network sees every
+direction of the element residual space.  Targets (target="local", default): the element-local
+error the residual determines, (R_e A R_e^T)^{-1} R_e r_pre, the local solve of the Schwarz
+smoother (Sec. 6.3); target="error": the true error restricted to the element, whose smooth
+global part no element-local model can see.
+
+Geometries (layout="tank", default): windows of 64 x 16 elements of the 25.6 m wave tank at its
+test element size (dx = 0.025 m) with seeded offsets and free surfaces whose seeds are disjoint
+from the test surfaces; layout="c1": the 8 x 4 element layout on [0, 2 pi] with seeded depth, bar
+and surface.  Training runs on the GPU with the library's BF16 MFMA kernels.
+"""
+import math
+
+import numpy as np
+
+import workloads as W
+
+from .binding import Solver, fine_x_nodes, sem_learned_features, sem_mlp_train
+
+TANK_L = 25.6
+WINDOW = (64, 16)   # elements of one training window (x, z)
+
+
+def _orders(P):
+    o = [P]
+    while o[-1] > 1:
+        o.append((o[-1] + 1) // 2)
+    return o
+
+
+def training_solver(s, P=8, smoother="chebyshev", layout="tank"):
+    """FP64 solver of training geometry s, with the source term it takes: (solver, f(x, z, j))."""
+    if layout == "c1":
+        h_fn, eta_fn = W.training_geometry(s)
+        x = fine_x_nodes(8, P, 2 * math.pi)
+        sv = Solver(2, (8, 1, 4), P, (2 * math.pi,), h_fn(x), eta_fn(x), levels=_orders(P),
+                    prec="f64", smoother=smoother)
+        return sv, lambda xg, zg, j: W.training_bumps(xg, zg, s, j, h_fn, eta_fn)
+    Nx, Nz = WINDOW
+    dx = TANK_L / 1024
+    x0 = np.random.default_rng(9000 + s).uniform(0.0, TANK_L - Nx * dx)
+
+    def h_fn(a):
+        return W.bar_depth(np.asarray(a), TANK_L)
+
+    def eta_fn(a):
+        return W.surface(np.asarray(a), TANK_L, 5000 + s)
+
+    x = fine_x_nodes(Nx, P, Nx * dx)
+    sv = Solver(2, (Nx, 1, Nz), P, (Nx * dx,), h_fn(x + x0), eta_fn(x + x0), levels=_orders(P),
+                prec="f64", smoother=smoother)
+    return sv, lambda xg, zg, j: W.bumps(xg + x0, zg, TANK_L, 6000 + 7 * s + j, h_fn, eta_fn)
+
+
+def _surface_rows(sv):
+    """Boolean mask of the free-surface (Dirichlet) rows of a 2D solver's global vectors."""
+    xg, zg = sv.coords(0)
+    nzn = int(np.count_nonzero(xg == xg[0]))   # nodes of one vertical line
+    m = np.zeros(sv.n_global, dtype=bool)
+    m[nzn - 1::nzn] = True
+    return m
+
+
+def harvest(n_surfaces=40, n_bump=4, n_white=4, n_cycles=8, n_random=16, per=32, P=8,
+            smoother="chebyshev", layout="tank", target="local", max_pairs=None, log=None):
+    """Device tensors X [n x 5(P+1)^2], T [n x (P+1)^2] (float32).
+
+    per: elements drawn (seeded) from each residual; 0 keeps all of them."""
+    import torch
+    n = (P + 1) ** 2
+    g = torch.Generator(device="cuda")
+    g.manual_seed(0)
+    Xs, Ts = [], []
+    total = 0
+
+    def take(sv, rpre, err):
+        nonlocal total
+        E = sv.n_local // n
+        X = torch.zeros(E, 5 * n, dtype=torch.float32, device="cuda")
+        T = torch.zeros(E, n, dtype=torch.float32, device="cuda")
+        sem_learned_features(sv.ctx, rpre, err, X, T)
+        if per and per < E:
+            idx = torch.randperm(E, generator=g, device="cuda")[:per]
+            X, T = X[idx], T[idx]
+        Xs.append(X)
+        Ts.append(T)
+        total += X.shape[0]
+
+    def dev(a):
+        return torch.tensor(a, dtype=torch.float64, device="cuda")
+
+    for s in range(n_surfaces):
+        sv, source = training_solver(s, P, smoother, layout)
+        top = _surface_rows(sv)
+        xg, zg = sv.coords(0)
+        for j in range(n_bump + n_white):
+            if j < n_bump:
+                b = sv.assemble_rhs(f=dev(source(xg, zg, j)))
+            else:
+                bb = np.random.default_rng(8000 + 31 * s + j).standard_normal(sv.n_global)
+                bb[top] = 0.0
+                b = dev(bb)
+            x = torch.zeros_like(b)
+            for _ in range(n_cycles):
+                r = b - sv.apply(x)
+                xpre = sv.smooth(0, r, pre=True)
+                rpre = r - sv.apply(xpre)
+                err = None
+                if target == "error":
+                    xs, _, _ = sv.solve(r, tol=1e-13)
+                    err = xs - xpre
+                take(sv, rpre, err)
+                x = x + sv.vcycle(r)
+        if target == "local":
+            for j in range(n_random):
+                rr = np.random.default_rng(12000 + 53 * s + j).standard_normal(sv.n_global)
+                rr[top] = 0.0   # residuals of the correction problem vanish on the surface
+                take(sv, dev(rr), None)
+        sv.close()
+        if log:
+            log(f"[harvest] geometry {s}: {total} pairs")
+        if max_pairs and total >= max_pairs:
+            break
+    X = torch.cat(Xs)
+    T = torch.cat(Ts)
+    if max_pairs:
+        X, T = X[:max_pairs], T[:max_pairs]
+    return X.contiguous(), T.contiguous()
+
+
+def train(X, T, epochs=600, batch=512, lr=2e-3, seed=1234, val_frac=0.1):
+    """Blob of the trained network and its per-epoch (train, validation) losses."""
+    nin, nout = X.shape[1], T.shape[1]
+    return sem_mlp_train(X, T, nin, nout, epochs=epochs, batch=batch, lr=lr, val_frac=val_frac,
+                         seed=seed)

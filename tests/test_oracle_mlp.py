@@ -1,0 +1,141 @@
+"""Pins of the oracle's learned-stage pieces: GELU, BF16 rounding, gradients, Adam, features,
+the assembled correction (checked against the additive-Schwarz formula of Sec. 6.3) and the
+energy behaviour of the accepted step."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import assemble, mlp
+from tests import oracle_cases as oc
+
+
+def test_gelu_closed_forms():
+    x = np.linspace(-4, 4, 41)
+    assert mlp.gelu(np.array([0.0]))[0] == 0.0
+    assert np.allclose(mlp.gelu(x) - mlp.gelu(-x), x, atol=1e-15)      # Phi(x) + Phi(-x) = 1
+    assert abs(mlp.gelu_grad(np.array([0.0]))[0] - 0.5) < 1e-16
+    h = 1e-6
+    fd = (mlp.gelu(x + h) - mlp.gelu(x - h)) / (2 * h)
+    assert np.abs(fd - mlp.gelu_grad(x)).max() < 1e-8
+
+
+def test_bf16_rounding():
+    e = 2.0 ** -7                                      # bf16 spacing at 1 (7 stored bits)
+    assert mlp.bf16(1.0) == 1.0
+    assert mlp.bf16(1.0 + e / 2) == 1.0                 # halfway: ties to even
+    assert mlp.bf16(1.0 + e + e / 2) == 1.0 + 2 * e     # halfway above an odd mantissa: up
+    assert mlp.bf16(1.0 + e / 2 + 2.0 ** -20) == 1.0 + e
+    assert mlp.bf16(-3.0) == -3.0
+    x = np.random.default_rng(0).standard_normal(1000)
+    assert np.abs(mlp.bf16(x) - x).max() <= np.abs(x).max() * 2.0 ** -8
+
+
+def test_gradients_against_central_differences():
+    rng = np.random.default_rng(3)
+    p = mlp.init_params(20, 7, seed=5)
+    for k in p:
+        if k.startswith("b"):
+            p[k] = rng.standard_normal(p[k].shape) * 0.1
+    X = rng.standard_normal((9, 20))
+    T = rng.standard_normal((9, 7))
+    Y, cache = mlp.forward(p, X)
+    loss, dY = mlp.mse(Y, T)
+    g = mlp.backward(p, cache, dY)
+    h = 1e-6
+    for k in p:
+        flat = p[k].ravel()
+        for idx in rng.choice(flat.size, size=min(12, flat.size), replace=False):
+            old = flat[idx]
+            flat[idx] = old + h
+            lp, _ = mlp.mse(mlp.forward(p, X)[0], T)
+            flat[idx] = old - h
+            lm, _ = mlp.mse(mlp.forward(p, X)[0], T)
+            flat[idx] = old
+            fd = (lp - lm) / (2 * h)
+            assert abs(fd - g[k].ravel()[idx]) <= 1e-6 * max(1e-3, abs(fd)), (k, idx)
+
+
+def test_adam_first_step_closed_form():
+    p = {"w": np.array([1.0, -2.0, 0.5])}
+    g = {"w": np.array([0.3, -4.0, 1e-3])}
+    z = {"w": np.zeros(3)}
+    p1, m, v = mlp.adam(p, g, z, z, 1, lr=0.01)
+    # bias-corrected moments equal g and g^2: the step is -lr g / (|g| + eps)
+    assert np.allclose(p1["w"], p["w"] - 0.01 * g["w"] / (np.abs(g["w"]) + 1e-8), rtol=0, atol=1e-15)
+
+
+def _tank():
+    wl = W.tank(4, 2, 3, Lx=0.4)
+    m = oc.fine_mesh(wl)
+    A = assemble.assemble_operator(m)
+    return wl, m, A
+
+
+def test_features_scale_invariance_and_linearity():
+    wl, m, A = _tank()
+    p = mlp.init_params(5 * m.NP ** 2, m.NP ** 2, seed=1)
+    r = W.random_vector(m.N, 2)
+    r[m.dirichlet_nodes()] = 0
+    X1, s1 = mlp.features(m, r)
+    X2, s2 = mlp.features(m, 3.5 * r)
+    assert np.abs(X1 - X2).max() < 1e-14 and np.allclose(s2, 3.5 * s1)
+    c1 = mlp.correction(m, p, r, emulate=False)
+    c2 = mlp.correction(m, p, 3.5 * r, emulate=False)
+    assert np.abs(c2 - 3.5 * c1).max() < 1e-12 * np.abs(c2).max()
+
+
+def test_zero_network_is_skipped():
+    wl, m, A = _tank()
+    p = {k: np.zeros_like(v) for k, v in mlp.init_params(5 * m.NP ** 2, m.NP ** 2, 0).items()}
+    b = W.random_vector(m.N, 4)
+    b[m.dirichlet_nodes()] = 0
+    x0 = np.zeros(m.N)
+    x1, ok = mlp.stage(A, m, p, b, x0)
+    assert not ok and np.array_equal(x1, x0)
+
+
+def test_exact_local_solves_reproduce_additive_schwarz():
+    """With the network replaced by the exact element solve y_e = (a_e/s_e) (R_e A R_e^T)^{-1} r_e,
+    the gather / scaling / weighted assembly plumbing gives W sum_e R_e^T (R_e A R_e^T)^{-1} R_e r,
+    the non-overlapping Schwarz preconditioner of Sec. 6.3, computed here independently."""
+    wl, m, A = _tank()
+    Ad = A.toarray()
+    r = W.random_vector(m.N, 6)
+    r[m.dirichlet_nodes()] = 0
+    g, mm, a = mlp.element_scales(m)
+    X, s = mlp.features(m, r)
+    # "network": exact local solves
+    Y = np.zeros((m.E, m.NP ** 2))
+    for e in range(m.E):
+        idx = m.l2g[e]
+        Y[e] = (a[e] / s[e]) * np.linalg.solve(Ad[np.ix_(idx, idx)], r[idx])
+    ce = (s / a)[:, None] * Y
+    c = np.bincount(m.l2g.ravel(), weights=ce.ravel(), minlength=m.N) / mlp.multiplicity(m)
+    c[m.dirichlet_nodes()] = 0
+    # Schwarz formula with explicit 0/1 restriction matrices and W = (sum R R^T)^{-1}
+    S = np.zeros((m.N, m.N))
+    Wd = np.zeros(m.N)
+    for e in range(m.E):
+        Rm = np.zeros((m.NP ** 2, m.N))
+        Rm[np.arange(m.NP ** 2), m.l2g[e]] = 1.0
+        S += Rm.T @ np.linalg.inv(Rm @ Ad @ Rm.T) @ Rm
+        Wd += np.diag(Rm.T @ Rm)
+    ref = (S @ r) / Wd
+    ref[m.dirichlet_nodes()] = 0
+    assert np.abs(c - ref).max() < 1e-10 * np.abs(ref).max()
+
+
+def test_accepted_stage_does_not_increase_energy_error():
+    wl, m, A = _tank()
+    rng = np.random.default_rng(8)
+    xs = assemble.solve_direct(A, W.random_vector(m.N, 9))
+    b = A @ xs
+    for seed in range(5):
+        p = mlp.init_params(5 * m.NP ** 2, m.NP ** 2, seed)
+        x0 = xs + 0.1 * rng.standard_normal(m.N)
+        x0[m.dirichlet_nodes()] = xs[m.dirichlet_nodes()]
+        x1, ok = mlp.stage(A, m, p, b, x0, emulate=False)
+        e0, e1 = xs - x0, xs - x1
+        assert e1 @ (A @ e1) <= e0 @ (A @ e0) * (1 + 1e-12)

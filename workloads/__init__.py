@@ -243,5 +243,53 @@ def mms_wave(x, z, k, h0):
     return np.cos(k * x) * np.cosh(k * (z + h0))
 
 
+# ---- training geometries for the learned stage ---------------------------------------------
+def training_geometry(s):
+    """Seeded (h, eta) functions of surface s on the config-1 layout domain x in [0, 2 pi]:
+    mean depth H_s ~ U(0.5, 3) with a smooth seeded bar of relative height <= 0.6 (aspect ratios
+    of the 8 x 4 elements from about 1 to 8) and a 5-harmonic free surface, amplitude <= 0.02 H."""
+    rng = np.random.default_rng(5000 + s)
+    H = rng.uniform(0.5, 3.0)
+    frac = rng.uniform(0.0, 0.6)
+    c0 = rng.uniform(1.0, 2 * math.pi - 1.0)
+    w = rng.uniform(0.5, 2.0)
+    amps = rng.uniform(0.0, 0.02 * H / 5, 5)
+    modes = rng.integers(1, 9, 5)
+    phases = rng.uniform(0.0, 2 * math.pi, 5)
+
+    def h(x):
+        x = np.asarray(x, dtype=np.float64)
+        return H * (1.0 - frac * np.exp(-((x - c0) / w) ** 2))
+
+    def eta(x):
+        x = np.asarray(x, dtype=np.float64)
+        out = np.zeros_like(x)
+        for a, m, ph in zip(amps, modes, phases):
+            out = out + a * np.sin(m * x + ph)
+        return out
+
+    return h, eta
+
+
+def training_bumps(x, z, s, j, h_fn, eta_fn):
+    """8 seeded Gaussian sources (right-hand side j of training surface s)."""
+    L = 2 * math.pi
+    rng = np.random.default_rng(7000 + 97 * s + j)
+    x = np.asarray(x, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    f = np.zeros_like(x)
+    for _ in range(8):
+        c = rng.uniform(-1.0, 1.0)
+        xm = rng.uniform(0.05, 0.95) * L
+        sm = rng.uniform(0.2, 0.8)
+        lx = rng.uniform(0.2, 1.0)
+        hm = float(h_fn(np.array([xm]))[0])
+        em = float(eta_fn(np.array([xm]))[0])
+        zm = -hm + sm * (hm + em)
+        lz = rng.uniform(0.05, 0.2) * hm
+        f += c * np.exp(-(x - xm) ** 2 / (2 * lx * lx) - (z - zm) ** 2 / (2 * lz * lz))
+    return f
+
+
 def random_vector(n, seed):
     return np.random.default_rng(seed).standard_normal(n)
