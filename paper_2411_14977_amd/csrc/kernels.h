@@ -19,7 +19,7 @@ enum GType { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
 // Full (A x)[g] = y[g] + S[(ix/P) nzn + iz] when ix % P == 0 (S rows 0 and Nx stay zero).
 size_t apply2d_smem(int P, int Nz, bool dbl);
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
-                   const void* Dmat, int Nx, int Nz, int masked, hipStream_t st);
+                   int Nx, int Nz, int masked, hipStream_t st);
 
 // ---- element-wise kernels in precision T (dbl selects double, else float) ----------------
 // d = cd d + cr dinv r,  x = (from_zero ? 0 : x) + d,  r = b - (from_zero ? 0 : Ax)

@@ -11,6 +11,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "gll_const.h"
 #include "kernels.h"
 
 namespace semk {
@@ -71,14 +72,67 @@ __device__ double sum_partials(const double* __restrict__ p, double* sh) {
 // ------------------------------------------------------------------------------------------
 // 2D operator apply
 // ------------------------------------------------------------------------------------------
+// n contiguous LDS values into registers, in 16-byte pieces where the alignment AL (in elements,
+// known at compile time) allows
+template <int N, int AL, typename T>
+__device__ __forceinline__ void lds_get(const T* p, T (&o)[N]) {
+  constexpr int V = (AL * sizeof(T) >= 16) ? 16 / (int)sizeof(T) : ((AL * sizeof(T) >= 8) ? 8 / (int)sizeof(T) : 1);
+  int m = 0;
+  if constexpr (V == 4) {
+    typedef T v4 __attribute__((ext_vector_type(4)));
+#pragma unroll
+    for (; m + 4 <= N; m += 4) {
+      const v4 a = *reinterpret_cast<const v4*>(p + m);
+      o[m] = a[0]; o[m + 1] = a[1]; o[m + 2] = a[2]; o[m + 3] = a[3];
+    }
+  } else if constexpr (V == 2) {
+    typedef T v2 __attribute__((ext_vector_type(2)));
+#pragma unroll
+    for (; m + 2 <= N; m += 2) {
+      const v2 a = *reinterpret_cast<const v2*>(p + m);
+      o[m] = a[0]; o[m + 1] = a[1];
+    }
+  }
+#pragma unroll
+  for (; m < N; ++m) o[m] = p[m];
+}
+
+template <typename T>
+constexpr int lds_vec() { return 16 / (int)sizeof(T); }  // elements per 16-byte LDS access
+
+template <int P, typename T>
+constexpr int line_align() {  // alignment (elements) of an element's offset ez * P in a line
+  return (P % lds_vec<T>() == 0) ? lds_vec<T>() : ((P % 2 == 0) ? 2 : 1);
+}
+
+// LDS layout of the apply: input/output column [NP][nzp], two exchange arrays [Nz][NP][NPp],
+// element-top values [Nz][NP]
+inline int apply2d_nzp(int P, int Nz, bool dbl) {
+  const int V = dbl ? 2 : 4, nzn = Nz * P + 1;
+  return (nzn + V - 1) / V * V;
+}
+
+size_t apply2d_smem(int P, int Nz, bool dbl) {
+  const int NP = P + 1, V = dbl ? 2 : 4, NPp = (NP + V - 1) / V * V;
+  const size_t n = (size_t)NP * apply2d_nzp(P, Nz, dbl) + 2 * (size_t)Nz * NP * NPp + (size_t)Nz * NP;
+  return n * (dbl ? 8 : 4);
+}
+
+// One workgroup per element column; thread t = ez * NP + q has two roles in element ez: the
+// vertical line i = q (sigma-direction contractions, geometric factors) and the horizontal row
+// j = q (x-direction contractions).  The roles swap data through LDS: u_r row -> line, w_r line
+// -> row, D_r^T w_r row -> line.  All contractions run in registers against compile-time D
+// (even-odd form).
 template <int P, typename T, typename TG>
 __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __restrict__ y,
                                                   T* __restrict__ S, const TG* __restrict__ G,
-                                                  const T* __restrict__ Dg, int Nx, int Nz,
-                                                  int masked, int remap) {
+                                                  int Nx, int Nz, int masked, int remap) {
   constexpr int NP = P + 1;
+  constexpr int V = lds_vec<T>();
+  constexpr int NPp = (NP + V - 1) / V * V;
+  constexpr int AL = line_align<P, T>();
   const int nzn = Nz * P + 1;
-  const int ncol = NP * nzn;
+  const int nzp = (nzn + V - 1) / V * V;
   const int nthr = NP * Nz;
   int ex = blockIdx.x;
   if (remap) {  // consecutive columns on the same XCD (blocks are dealt round-robin to 8 XCDs)
@@ -86,128 +140,142 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
     ex = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* su = reinterpret_cast<T*>(smem_raw);  // [NP][nzn] input column, later the output column
-  T* sw = su + ncol;                        // [Nz][NP(j)][NP(i)]  w_r exchange
-  T* sD = sw + Nz * NP * NP;                // [NP][NP]
-  T* stp = sD + NP * NP;                    // [Nz][NP] element-top values
+  T* su = reinterpret_cast<T*>(smem_raw);  // [NP][nzp] input column, later the output column
+  T* X1 = su + NP * nzp;                    // [Nz][NP(i)][NPp(j)]: u_r, later D_r^T w_r
+  T* X2 = X1 + Nz * NP * NPp;               // [Nz][NP(j)][NPp(i)]: w_r
+  T* stp = X2 + Nz * NP * NPp;              // [Nz][NP] element-top values
   const size_t cbase = (size_t)ex * P * nzn;
-  for (int k = threadIdx.x; k < ncol; k += blockDim.x) su[k] = x[cbase + k];
-  for (int k = threadIdx.x; k < NP * NP; k += blockDim.x) sD[k] = Dg[k];
-  __syncthreads();
   const int t = threadIdx.x;
   const bool act = t < nthr;
-  const int i = act ? t % NP : 0;
+  const int q = act ? t % NP : 0;
   const int ez = act ? t / NP : 0;
-  const bool topel = (ez == Nz - 1);
-  const bool mtop = masked && topel;
-  T u[NP], ws[NP];
-  T xtop = 0;
+
+  // every global load of the block is issued before the first LDS store
+  T g[3][NP];
   if (act) {
-    const T* col = su + ez * P;
-#pragma unroll
-    for (int j = 0; j < NP; ++j) u[j] = col[i * nzn + j];
-    if (topel) xtop = u[P];
-    if (mtop) u[P] = 0;
     const TG* Gc = G + (size_t)ex * 3 * NP * nthr + t;
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {
-      // reference derivatives at node (i, j): u_r along x through LDS, u_s along sigma in
-      // registers; then the geometric factors (w_r, w_s) = G (u_r, u_s)
-      T ur = 0, us = 0;
+    for (int f = 0; f < 3; ++f)
 #pragma unroll
-      for (int k = 0; k < NP; ++k) ur += sD[i * NP + k] * col[k * nzn + j];
+      for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(Gc + (f * NP + j) * nthr);
+  }
+  T xin[NP];
+  if (t < nzn) {
 #pragma unroll
-      for (int k = 0; k < NP; ++k) us += sD[j * NP + k] * u[k];
-      if (j == P && mtop) ur = 0;
-      const T grr = gload<T, TG>(Gc + (0 * NP + j) * nthr);
-      const T grs = gload<T, TG>(Gc + (1 * NP + j) * nthr);
-      const T gss = gload<T, TG>(Gc + (2 * NP + j) * nthr);
-      sw[(ez * NP + j) * NP + i] = grr * ur + grs * us;
-      ws[j] = grs * ur + gss * us;
-    }
+    for (int l = 0; l < NP; ++l) xin[l] = x[cbase + (size_t)l * nzn + t];
 #pragma unroll
-    for (int j = 0; j < NP; ++j) {  // v = D_s^T w_s
-      T s = 0;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) s += sD[k * NP + j] * ws[k];
-      u[j] = s;
-    }
+    for (int l = 0; l < NP; ++l) su[l * nzp + t] = xin[l];
   }
   __syncthreads();
-  if (act) {
-#pragma unroll
-    for (int j = 0; j < NP; ++j) {  // v += D_r^T w_r
-      T s = u[j];
-      const T* wrow = sw + (ez * NP + j) * NP;
-#pragma unroll
-      for (int k = 0; k < NP; ++k) s += sD[k * NP + i] * wrow[k];
-      u[j] = s;
-    }
-    stp[ez * NP + i] = u[P];
-  }
-  __syncthreads();
-  if (act) {
-    if (ez > 0) u[0] += stp[(ez - 1) * NP + i];
-    T* ocol = su + i * nzn + ez * P;
-#pragma unroll
-    for (int j = 0; j < P; ++j) ocol[j] = u[j];
-    if (topel) ocol[P] = masked ? xtop : u[P];
-  }
-  __syncthreads();
-  const int nmain = P * nzn;
-  for (int k = threadIdx.x; k < nmain; k += blockDim.x) y[cbase + k] = su[k];
-  if (ex == Nx - 1) {
-    for (int k = threadIdx.x; k < nzn; k += blockDim.x) y[cbase + nmain + k] = su[nmain + k];
-  } else {
-    for (int k = threadIdx.x; k < nzn; k += blockDim.x) {
-      T v = su[nmain + k];
-      if (masked && k == nzn - 1) v = 0;
-      S[(size_t)(ex + 1) * nzn + k] = v;
-    }
-  }
-}
 
-size_t apply2d_smem(int P, int Nz, bool dbl) {
-  const int NP = P + 1;
-  const size_t n = (size_t)NP * (Nz * P + 1) + (size_t)Nz * NP * NP + NP * NP + (size_t)Nz * NP;
-  return n * (dbl ? 8 : 4);
+  const bool topel = (ez == Nz - 1);
+  const bool mtop = masked && topel;  // Dirichlet surface: its values enter as zero
+  T v[NP], us[NP];
+  T xtop = 0;
+  if (act) {
+    // row role (j = q): u_r(i, j) = sum_k D_ik u(k, j)
+    {
+      T r[NP], ur[NP];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) r[i] = su[i * nzp + ez * P + q];
+      if (mtop && q == P) {
+#pragma unroll
+        for (int i = 0; i < NP; ++i) r[i] = 0;
+      }
+      contract_eo<P, false>(r, ur);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) X1[(ez * NP + i) * NPp + q] = ur[i];
+    }
+    // line role (i = q): u_s(i, j) = sum_k D_jk u(i, k)
+    T u[NP];
+    lds_get<NP, AL>(su + q * nzp + ez * P, u);
+    if (topel) xtop = u[P];
+    if (mtop) u[P] = 0;
+    contract_eo<P, false>(u, us);
+  }
+  __syncthreads();
+  if (act) {
+    // line role: (w_r, w_s) = G (u_r, u_s); v = D_s^T w_s; w_r to the rows
+    T ur[NP], ws[NP];
+    lds_get<NP, V>(X1 + (ez * NP + q) * NPp, ur);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      X2[(ez * NP + j) * NPp + q] = g[0][j] * ur[j] + g[1][j] * us[j];
+      ws[j] = g[1][j] * ur[j] + g[2][j] * us[j];
+    }
+    contract_eo<P, true>(ws, v);
+  }
+  __syncthreads();
+  if (act) {
+    // row role: (D_r^T w_r)(i, j) = sum_k D_ki w_r(k, j)
+    T w[NP], vr[NP];
+    lds_get<NP, V>(X2 + (ez * NP + q) * NPp, w);
+    contract_eo<P, true>(w, vr);
+#pragma unroll
+    for (int i = 0; i < NP; ++i) X1[(ez * NP + i) * NPp + q] = vr[i];
+  }
+  __syncthreads();
+  if (act) {
+    T vr[NP];
+    lds_get<NP, V>(X1 + (ez * NP + q) * NPp, vr);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v[j] += vr[j];
+    stp[ez * NP + q] = v[P];
+  }
+  __syncthreads();
+  if (act) {
+    // sum over the face shared with the element below; output line i = q of element ez
+    if (ez > 0) v[0] += stp[(ez - 1) * NP + q];
+    T* ocol = su + q * nzp + ez * P;
+#pragma unroll
+    for (int j = 0; j < P; ++j) ocol[j] = v[j];
+    if (topel) ocol[P] = masked ? xtop : v[P];
+  }
+  __syncthreads();
+  if (t < nzn) {
+#pragma unroll
+    for (int l = 0; l < P; ++l) y[cbase + (size_t)l * nzn + t] = su[l * nzp + t];
+    const T last = su[P * nzp + t];
+    if (ex == Nx - 1) y[cbase + (size_t)P * nzn + t] = last;
+    else S[(size_t)(ex + 1) * nzn + t] = (masked && t == nzn - 1) ? (T)0 : last;
+  }
 }
 
 template <int P, typename T, typename TG>
-static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G, const void* D,
-                                 int Nx, int Nz, int masked, hipStream_t st) {
+static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G, int Nx, int Nz,
+                                 int masked, hipStream_t st) {
   const int nthr = (P + 1) * Nz;
   const int threads = ((nthr + 63) / 64) * 64;
   const size_t smem = apply2d_smem(P, Nz, sizeof(T) == 8);
   const int remap = (Nx % 8 == 0) ? 1 : 0;
-  hipLaunchKernelGGL((k_apply2d<P, T, TG>), dim3(Nx), dim3(threads), smem, st,
-                     (const T*)x, (T*)y, (T*)S, (const TG*)G, (const T*)D, Nx, Nz, masked, remap);
+  hipLaunchKernelGGL((k_apply2d<P, T, TG>), dim3(Nx), dim3(threads), smem, st, (const T*)x,
+                     (T*)y, (T*)S, (const TG*)G, Nx, Nz, masked, remap);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
-                            const void* D, int Nx, int Nz, int masked, hipStream_t st) {
-  if (dbl) return launch_apply2d<P, double, double>(x, y, S, G, D, Nx, Nz, masked, st);
-  if (gt == G_BF16) return launch_apply2d<P, float, uint16_t>(x, y, S, G, D, Nx, Nz, masked, st);
-  return launch_apply2d<P, float, float>(x, y, S, G, D, Nx, Nz, masked, st);
+                            int Nx, int Nz, int masked, hipStream_t st) {
+  if (dbl) return launch_apply2d<P, double, double>(x, y, S, G, Nx, Nz, masked, st);
+  if (gt == G_BF16) return launch_apply2d<P, float, uint16_t>(x, y, S, G, Nx, Nz, masked, st);
+  return launch_apply2d<P, float, float>(x, y, S, G, Nx, Nz, masked, st);
 }
 
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
-                   const void* D, int Nx, int Nz, int masked, hipStream_t st) {
+                   int Nx, int Nz, int masked, hipStream_t st) {
   switch (P) {
-    case 1: return apply2d_p<1>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 2: return apply2d_p<2>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 3: return apply2d_p<3>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 4: return apply2d_p<4>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 5: return apply2d_p<5>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 6: return apply2d_p<6>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 7: return apply2d_p<7>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 8: return apply2d_p<8>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 9: return apply2d_p<9>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 10: return apply2d_p<10>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 11: return apply2d_p<11>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
-    case 12: return apply2d_p<12>(dbl, gt, x, y, S, G, D, Nx, Nz, masked, st);
+    case 1: return apply2d_p<1>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 2: return apply2d_p<2>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 3: return apply2d_p<3>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 4: return apply2d_p<4>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 5: return apply2d_p<5>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 6: return apply2d_p<6>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 7: return apply2d_p<7>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 8: return apply2d_p<8>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 9: return apply2d_p<9>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 10: return apply2d_p<10>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 11: return apply2d_p<11>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+    case 12: return apply2d_p<12>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
     default: return hipErrorInvalidValue;
   }
 }

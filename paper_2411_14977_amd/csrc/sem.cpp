@@ -34,7 +34,6 @@ struct DLevel {
   GType gt = semk::G_F64;
   semh::LevelGeom geo;
   void* G = nullptr;          // factors in storage precision, device column layout
-  void* D = nullptr;          // differentiation matrix in compute precision
   void* dinv = nullptr;       // inverse assembled diagonal
   double* J = nullptr;        // prolongation from the next coarser level, (P+1) x (Pc+1)
   void *x = nullptr, *b = nullptr, *d = nullptr, *y = nullptr, *S = nullptr;
@@ -52,7 +51,6 @@ struct Ctx {
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
   // fine-level FP64 operator for the outer loop
   double* G64 = nullptr;
-  double* D64 = nullptr;
   bool G64_owned = false;
   double *xo = nullptr, *bo = nullptr, *ro = nullptr, *po = nullptr, *qo = nullptr,
          *zo = nullptr, *yo = nullptr, *So = nullptr, *mass = nullptr;
@@ -148,12 +146,12 @@ void set_err(Ctx* c, const std::string& s) { c->err = s; }
 // ------------------------------------------------------------------------------------------
 void apply_level(Ctx* c, int l, const void* x, int masked) {
   DLevel& L = c->lev[l];
-  HK(semk::apply2d(L.P, L.dbl, L.gt, x, L.y, L.S, L.G, L.D, L.Nx, L.Nz, masked, c->st));
+  HK(semk::apply2d(L.P, L.dbl, L.gt, x, L.y, L.S, L.G, L.Nx, L.Nz, masked, c->st));
 }
 
 void apply_outer(Ctx* c, const double* x, int masked) {
   DLevel& L = c->lev[0];
-  HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, c->D64, L.Nx, L.Nz, masked,
+  HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Nx, L.Nz, masked,
                    c->st));
 }
 
@@ -236,7 +234,7 @@ void learned_stage(Ctx* c) {
   apply_level(c, 0, L.x, c->masked);
   HK(semm::stage_mlp(s, L.dbl, L.b, L.y, L.S, c->st));
   HK(semm::stage_assemble(s, L.dbl, c->cbuf, c->masked, c->st));
-  HK(semk::apply2d(L.P, L.dbl, L.gt, c->cbuf, c->yq, c->Sq, L.G, L.D, L.Nx, L.Nz, c->masked,
+  HK(semk::apply2d(L.P, L.dbl, L.gt, c->cbuf, c->yq, c->Sq, L.G, L.Nx, L.Nz, c->masked,
                    c->st));
   HK(semm::stage_dots(L.dbl, c->cbuf, L.b, L.y, L.S, c->yq, c->Sq, c->stparts, s.skips, L.N,
                       L.nzn, L.P, c->st));
@@ -533,13 +531,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
     std::vector<double> dinv(diag.size());
     for (size_t g = 0; g < diag.size(); ++g) dinv[g] = 1.0 / diag[g];
-    if (L.dbl) {
-      L.dinv = upload(c, dinv);
-      L.D = upload(c, L.geo.D);
-    } else {
-      L.dinv = upload(c, std::vector<float>(dinv.begin(), dinv.end()));
-      L.D = upload(c, std::vector<float>(L.geo.D.begin(), L.geo.D.end()));
-    }
+    if (L.dbl) L.dinv = upload(c, dinv);
+    else L.dinv = upload(c, std::vector<float>(dinv.begin(), dinv.end()));
     const size_t eb = esz(L.dbl);
     L.x = dalloc(c, L.N * eb);
     L.b = dalloc(c, L.N * eb);
@@ -560,13 +553,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     throw ArgFail{"operator kernel exceeds LDS for this size"};
   // outer FP64 operator
   DLevel& L0 = c->lev[0];
-  if (L0.dbl) {
-    c->G64 = (double*)L0.G;
-    c->D64 = (double*)L0.D;
-  } else {
-    c->G64 = upload(c, permute_G2d<double>(L0.geo, L0.geo.G, [](double v) { return v; }));
-    c->D64 = upload(c, L0.geo.D);
-  }
+  if (L0.dbl) c->G64 = (double*)L0.G;
+  else c->G64 = upload(c, permute_G2d<double>(L0.geo, L0.geo.G, [](double v) { return v; }));
   const size_t N = L0.N;
   c->xo = (double*)dalloc(c, N * 8);
   c->bo = (double*)dalloc(c, N * 8);
