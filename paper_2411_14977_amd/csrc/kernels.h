@@ -17,7 +17,17 @@ enum GType { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
 // 2D: one workgroup per element column; y gets lines 0..P-1 of each column (and line P of
 // the last column), S[(ex+1) * nzn + iz] the column's contribution to its right line.
 // Full (A x)[g] = y[g] + S[(ix/P) nzn + iz] when ix % P == 0 (S rows 0 and Nx stay zero).
-size_t apply2d_smem(int P, int Nz, bool dbl);
+size_t apply2d_smem(int P, int Nz, bool dbl);   // LDS bytes per element column
+int apply2d_cpb(int P, int Nx, int Nz, bool dbl);  // element columns per workgroup
+// Device layout of the 2D operator's geometric factors: per element column, thread t owns the
+// K = 3 (P+1) values (f, j), padded to Kp (a multiple of half a 16-byte chunk); NC full chunks
+// of W = 16 / sizeof(TG) values ([c][t][W]), then a half chunk ([t][REM]) if REM > 0; columns
+// are cstride values apart.
+struct GLayout {
+  int W, Kp, NC, REM;
+  size_t cstride;
+};
+GLayout g2d_layout(int P, int Nz, size_t tgsize);
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                    int Nx, int Nz, int masked, hipStream_t st);
 

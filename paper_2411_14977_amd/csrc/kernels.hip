@@ -105,28 +105,96 @@ constexpr int line_align() {  // alignment (elements) of an element's offset ez 
   return (P % lds_vec<T>() == 0) ? lds_vec<T>() : ((P % 2 == 0) ? 2 : 1);
 }
 
-// LDS layout of the apply: input/output column [NP][nzp], two exchange arrays [Nz][NP][NPp],
-// element-top values [Nz][NP]
+// LDS layout of the apply, per element column: input/output column [NP][nzp], two exchange
+// arrays [Nz][NP][NPp], element-top values [Nz][NP]; the region is padded to 16 bytes
 inline int apply2d_nzp(int P, int Nz, bool dbl) {
   const int V = dbl ? 2 : 4, nzn = Nz * P + 1;
   return (nzn + V - 1) / V * V;
 }
 
-size_t apply2d_smem(int P, int Nz, bool dbl) {
+static size_t apply2d_slot(int P, int Nz, bool dbl) {  // elements per column
   const int NP = P + 1, V = dbl ? 2 : 4, NPp = (NP + V - 1) / V * V;
   const size_t n = (size_t)NP * apply2d_nzp(P, Nz, dbl) + 2 * (size_t)Nz * NP * NPp + (size_t)Nz * NP;
-  return n * (dbl ? 8 : 4);
+  return (n + V - 1) / V * V;
 }
 
-// One workgroup per element column; thread t = ez * NP + q has two roles in element ez: the
-// vertical line i = q (sigma-direction contractions, geometric factors) and the horizontal row
-// j = q (x-direction contractions).  The roles swap data through LDS: u_r row -> line, w_r line
-// -> row, D_r^T w_r row -> line.  All contractions run in registers against compile-time D
-// (even-odd form).
+size_t apply2d_smem(int P, int Nz, bool dbl) { return apply2d_slot(P, Nz, dbl) * (dbl ? 8 : 4); }
+
+// columns per workgroup: two when that still leaves at least 512 workgroups (a multiple of 8,
+// so the XCD-aware order applies) within 1024 threads and 64 KB of LDS, else one.  Measured on
+// the 1024 x 16 and 2048 x 16 column meshes at P = 8: two columns per workgroup with the XCD
+// order is the fastest of 1-4; three (odd wave counts per workgroup) is the slowest.
+int apply2d_cpb(int P, int Nx, int Nz, bool dbl) {
+  const int nthr = (P + 1) * Nz;
+  const int blocks2 = (Nx + 1) / 2;
+  if (2 * nthr <= 1024 && 2 * apply2d_smem(P, Nz, dbl) <= 65536 && blocks2 >= 512 &&
+      blocks2 % 8 == 0)
+    return 2;
+  return 1;
+}
+
+// geometric factors of the operator: layout in kernels.h (GLayout)
+template <int P, typename TG>
+struct G2dLayout {
+  static constexpr int K = 3 * (P + 1);
+  static constexpr int W = 16 / (int)sizeof(TG);
+  static constexpr int H = W / 2 > 0 ? W / 2 : 1;
+  static constexpr int Kp = (K + H - 1) / H * H;
+  static constexpr int NC = Kp / W;
+  static constexpr int REM = Kp - NC * W;
+};
+
+GLayout g2d_layout(int P, int Nz, size_t tgsize) {
+  GLayout L;
+  L.W = 16 / (int)tgsize;
+  const int H = L.W / 2 > 0 ? L.W / 2 : 1, K = 3 * (P + 1);
+  L.Kp = (K + H - 1) / H * H;
+  L.NC = L.Kp / L.W;
+  L.REM = L.Kp - L.NC * L.W;
+  const size_t nk = (size_t)(P + 1) * Nz * L.Kp;
+  L.cstride = (nk + L.W - 1) / L.W * L.W;
+  return L;
+}
+
+// this thread's 3 (P+1) factors (f, j) of element column ex, with 16-byte loads
+template <int P, typename T, typename TG>
+__device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int nthr, int t,
+                                         T (&g)[3][P + 1]) {
+  using Ly = G2dLayout<P, TG>;
+  constexpr int NP = P + 1, W = Ly::W, NC = Ly::NC, REM = Ly::REM, Kp = Ly::Kp;
+  typedef TG vW __attribute__((ext_vector_type(W)));
+  const size_t cstride = ((size_t)nthr * Kp + W - 1) / W * W;
+  const TG* Gc = G + (size_t)ex * cstride;
+  TG raw[Kp];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    const vW a = *reinterpret_cast<const vW*>(Gc + ((size_t)c * nthr + t) * W);
+#pragma unroll
+    for (int w = 0; w < W; ++w) raw[c * W + w] = a[w];
+  }
+  if constexpr (REM == 1) {
+    raw[NC * W] = Gc[(size_t)NC * nthr * W + t];
+  } else if constexpr (REM > 1) {
+    typedef TG vR __attribute__((ext_vector_type(REM)));
+    const vR a = *reinterpret_cast<const vR*>(Gc + (size_t)NC * nthr * W + (size_t)t * REM);
+#pragma unroll
+    for (int w = 0; w < REM; ++w) raw[NC * W + w] = a[w];
+  }
+#pragma unroll
+  for (int f = 0; f < 3; ++f)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(&raw[f * NP + j]);
+}
+
+// One workgroup per cpb element columns; within a column, thread t = ez * NP + q has two roles in
+// element ez: the vertical line i = q (sigma-direction contractions, geometric factors) and the
+// horizontal row j = q (x-direction contractions).  The roles swap data through LDS: u_r row ->
+// line, w_r line -> row, D_r^T w_r row -> line.  All contractions run in registers against
+// compile-time D (even-odd form).
 template <int P, typename T, typename TG>
 __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __restrict__ y,
                                                   T* __restrict__ S, const TG* __restrict__ G,
-                                                  int Nx, int Nz, int masked, int remap) {
+                                                  int Nx, int Nz, int masked, int cpb, int remap) {
   constexpr int NP = P + 1;
   constexpr int V = lds_vec<T>();
   constexpr int NPp = (NP + V - 1) / V * V;
@@ -134,35 +202,35 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
   const int nzn = Nz * P + 1;
   const int nzp = (nzn + V - 1) / V * V;
   const int nthr = NP * Nz;
-  int ex = blockIdx.x;
+  int bx = blockIdx.x;
   if (remap) {  // consecutive columns on the same XCD (blocks are dealt round-robin to 8 XCDs)
     const int per = gridDim.x >> 3;
-    ex = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
   }
+  const int cs = threadIdx.x / nthr;       // column slot of this thread
+  const int t = threadIdx.x - cs * nthr;   // thread within the column
+  const int ex = bx * cpb + cs;
+  const bool valid = cs < cpb && ex < Nx;  // uniform per column slot
+  const int slot = (NP * nzp + 2 * Nz * NP * NPp + Nz * NP + V - 1) / V * V;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* su = reinterpret_cast<T*>(smem_raw);  // [NP][nzp] input column, later the output column
+  T* su = reinterpret_cast<T*>(smem_raw) + (valid ? cs : 0) * slot;  // [NP][nzp] column
   T* X1 = su + NP * nzp;                    // [Nz][NP(i)][NPp(j)]: u_r, later D_r^T w_r
   T* X2 = X1 + Nz * NP * NPp;               // [Nz][NP(j)][NPp(i)]: w_r
   T* stp = X2 + Nz * NP * NPp;              // [Nz][NP] element-top values
-  const size_t cbase = (size_t)ex * P * nzn;
-  const int t = threadIdx.x;
-  const bool act = t < nthr;
-  const int q = act ? t % NP : 0;
-  const int ez = act ? t / NP : 0;
+  // column-relative 32-bit offsets from per-column base pointers
+  const T* xc = x + (size_t)(valid ? ex : 0) * P * nzn;
+  T* yc = y + (size_t)(valid ? ex : 0) * P * nzn;
+  const bool act = valid;
+  const int q = t % NP;
+  const int ez = t / NP;
 
   // every global load of the block is issued before the first LDS store
   T g[3][NP];
-  if (act) {
-    const TG* Gc = G + (size_t)ex * 3 * NP * nthr + t;
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-      for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(Gc + (f * NP + j) * nthr);
-  }
+  if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
   T xin[NP];
-  if (t < nzn) {
+  if (valid && t < nzn) {
 #pragma unroll
-    for (int l = 0; l < NP; ++l) xin[l] = x[cbase + (size_t)l * nzn + t];
+    for (int l = 0; l < NP; ++l) xin[l] = xc[l * nzn + t];
 #pragma unroll
     for (int l = 0; l < NP; ++l) su[l * nzp + t] = xin[l];
   }
@@ -232,11 +300,11 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
     if (topel) ocol[P] = masked ? xtop : v[P];
   }
   __syncthreads();
-  if (t < nzn) {
+  if (valid && t < nzn) {
 #pragma unroll
-    for (int l = 0; l < P; ++l) y[cbase + (size_t)l * nzn + t] = su[l * nzp + t];
+    for (int l = 0; l < P; ++l) yc[l * nzn + t] = su[l * nzp + t];
     const T last = su[P * nzp + t];
-    if (ex == Nx - 1) y[cbase + (size_t)P * nzn + t] = last;
+    if (ex == Nx - 1) yc[P * nzn + t] = last;
     else S[(size_t)(ex + 1) * nzn + t] = (masked && t == nzn - 1) ? (T)0 : last;
   }
 }
@@ -244,12 +312,15 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
 template <int P, typename T, typename TG>
 static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G, int Nx, int Nz,
                                  int masked, hipStream_t st) {
+  const bool dbl = sizeof(T) == 8;
   const int nthr = (P + 1) * Nz;
-  const int threads = ((nthr + 63) / 64) * 64;
-  const size_t smem = apply2d_smem(P, Nz, sizeof(T) == 8);
-  const int remap = (Nx % 8 == 0) ? 1 : 0;
-  hipLaunchKernelGGL((k_apply2d<P, T, TG>), dim3(Nx), dim3(threads), smem, st, (const T*)x,
-                     (T*)y, (T*)S, (const TG*)G, Nx, Nz, masked, remap);
+  const int cpb = apply2d_cpb(P, Nx, Nz, dbl);
+  const int threads = ((cpb * nthr + 63) / 64) * 64;
+  const int blocks = (Nx + cpb - 1) / cpb;
+  const size_t smem = apply2d_smem(P, Nz, dbl) * cpb;
+  const int remap = (blocks % 8 == 0) ? 1 : 0;
+  hipLaunchKernelGGL((k_apply2d<P, T, TG>), dim3(blocks), dim3(threads), smem, st, (const T*)x,
+                     (T*)y, (T*)S, (const TG*)G, Nx, Nz, masked, cpb, remap);
   return hipGetLastError();
 }
 

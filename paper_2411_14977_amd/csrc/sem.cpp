@@ -124,18 +124,27 @@ size_t esz(bool dbl) { return dbl ? 8 : 4; }
 // natural [f][e][i*NP+j] -> device [ex][f][j][ez*NP+i]
 template <typename TG, typename Conv>
 std::vector<TG> permute_G2d(const semh::LevelGeom& L, const std::vector<double>& G, Conv conv) {
+  // device layout of the operator's geometric factors (see semk::g2d_layout): per element
+  // column, the 3 NP values (f, j) of each thread t = ez NP + i are split into 16-byte chunks,
+  // chunk-major and thread-contiguous within a chunk, so every lane reads them with 16-byte
+  // coalesced loads; the column stride is padded to a whole chunk row
   const int NP = L.NP, Nz = L.Nz, Nx = L.Nx;
   const size_t NL = NP * NP, nthr = (size_t)NP * Nz;
-  std::vector<TG> out((size_t)3 * L.E * NL);
+  const semk::GLayout lay = semk::g2d_layout(L.P, Nz, sizeof(TG));
+  std::vector<TG> out((size_t)Nx * lay.cstride, TG(0));
   for (int ex = 0; ex < Nx; ++ex)
-    for (int f = 0; f < 3; ++f)
-      for (int j = 0; j < NP; ++j)
-        for (int ez = 0; ez < Nz; ++ez)
-          for (int i = 0; i < NP; ++i) {
-            const size_t e = (size_t)ex * Nz + ez;
-            out[(((size_t)ex * 3 + f) * NP + j) * nthr + ez * NP + i] =
-                conv(G[f * L.E * NL + e * NL + i * NP + j]);
+    for (int ez = 0; ez < Nz; ++ez)
+      for (int i = 0; i < NP; ++i) {
+        const size_t e = (size_t)ex * Nz + ez, t = (size_t)ez * NP + i;
+        for (int f = 0; f < 3; ++f)
+          for (int j = 0; j < NP; ++j) {
+            const int k = f * NP + j;
+            const int c = k / lay.W, w = k % lay.W;
+            const size_t off = c < lay.NC ? ((size_t)c * nthr + t) * lay.W + w
+                                          : (size_t)lay.NC * nthr * lay.W + t * lay.REM + (k - lay.NC * lay.W);
+            out[(size_t)ex * lay.cstride + off] = conv(G[f * L.E * NL + e * NL + i * NP + j]);
           }
+      }
   return out;
 }
 
