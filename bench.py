@@ -1,13 +1,19 @@
 """Benchmark: Poisson solves/s and GDOF/s to a 1e-10 relative residual on one MI355X.
 
 A step is one full solve (x = 0 -> ||b - A x|| <= 1e-10 ||b||) of the synthetic wave-tank
-workload, inputs resident in HBM.  The timed path is the mixed-precision p-multigrid (FP32 inner
-V-cycle with geometric factors stored in BF16 unless --prec f32, FP64 outer flexible CG); the
-plain FP64 p-multigrid on the same workload is timed beside it.  Also reported: the roofline of
+workload (1024 x 16 elements, P = 8, 1,056,897 nodes), inputs resident in HBM.  The timed path
+(``value``) is the mixed-precision p-multigrid with the learned element-local smoothing stage:
+FP32 inner V-cycle (geometric factors stored in BF16 unless --prec f32), BF16-MFMA network stage
+on the fine level before and after smoothing, FP64 outer flexible CG.  Its network is trained
+first, on the GPU, by the library's own kernels from pairs that the plain p-multigrid generates
+(outside the timed region; the training time is reported).  Beside it: the same solver without
+the stage, the plain FP64 p-multigrid, per-cycle residual reduction in defect-correction (PDC)
+mode with and without the stage, iterations and times on unseen test surfaces, the roofline of
 the dominant kernel (operator apply, live HIP-event timing on the library's stream) and the CPU
 oracle timed on a bounded sample of the same workload.
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload c4] [--prec bf16]
+                       [--no-learned] [--surfaces 4] [--no-cpu] [--no-fp64]
 """
 import argparse
 import hashlib
@@ -21,24 +27,25 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Poisson solves/s + GDOF/s to 1e-10 residual: FP32+learned p-MG vs plain FP64"
 HBM_PEAK_GBS = 8000.0
+STAGE_MODE = 3  # learned stage before pre-smoothing's restriction and before post-smoothing
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def workload(name):
+def workload(name, index=0):
     import workloads as W
     if name == "c2":
         return W.c2()
     if name == "c3":
         return W.c3()
     if name == "c4":
-        return W.c4(0)
+        return W.c4(index)
     raise SystemExit(f"unknown workload {name}")
 
 
-def describe(wl, prec):
+def describe(wl, prec, learned):
     return {"workload": f"{wl.name}: 2D sigma-mapped wave tank {wl.Nx}x{wl.Nz} elements, P={wl.P}, "
                         f"levels {'-'.join(map(str, wl.orders))}, Chebyshev({wl.cheb_degree}), "
                         f"trapezoidal bar 0.4-0.1-0.4 m, surface seed {wl.surface_seed}, "
@@ -47,13 +54,16 @@ def describe(wl, prec):
             "inner": {"bf16": "fp32 compute, geometric factors bf16",
                       "f32": "fp32 compute, geometric factors fp32"}[prec],
             "outer": "fp64 flexible CG, fp64 operator and inner products, fp64 P=1 coarse solve",
-            "learned_stage": False, "tol": 1e-10}
+            "learned_stage": ("element-local MLP 405-128-128-81 (GELU), bf16 MFMA operands, fp32 "
+                              "accumulate; fine level before pre-smoothing's restriction and before "
+                              "post-smoothing; energy-judged step") if learned else False,
+            "tol": 1e-10}
 
 
 def time_solves(s, rhs, steps, warmup, tol):
     import torch
     x = torch.zeros_like(rhs)
-    infos = []
+    info = None
     for _ in range(warmup):
         x.zero_()
         _, info, _ = s.solve(rhs, x=x, tol=tol)
@@ -62,10 +72,76 @@ def time_solves(s, rhs, steps, warmup, tol):
     for _ in range(steps):
         x.zero_()
         _, info, _ = s.solve(rhs, x=x, tol=tol)
-        infos.append(info)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    return (t1 - t0) / steps, infos[-1], x
+    return (t1 - t0) / steps, info, x
+
+
+def train_network(args):
+    """Harvest pairs with the plain p-multigrid and train the network on the GPU."""
+    import numpy as np
+
+    from paper_2411_14977_amd import learned
+    t0 = time.perf_counter()
+    X, T = learned.harvest(n_surfaces=args.train_surfaces)
+    t1 = time.perf_counter()
+    blob, losses = learned.train(X, T, epochs=args.epochs)
+    t2 = time.perf_counter()
+    losses = np.asarray(losses)
+    rec = {"pairs": int(X.shape[0]), "surfaces": args.train_surfaces, "epochs": args.epochs,
+           "harvest_s": t1 - t0, "train_s": t2 - t1,
+           "final_train_batch_loss": float(losses[-1, 0]), "final_val_loss": float(losses[-1, 1]),
+           "recipe": "64x16-element windows of the tank (dx = 0.025 m), seeded offsets and "
+                     "surfaces (seeds 5000+), smooth and white-noise sources, 8 defect-correction "
+                     "cycles each, plus random residuals; targets = element-block solves; "
+                     "Adam, cosine lr 2e-3, batch 512"}
+    log(f"[bench] trained on {rec['pairs']} pairs: harvest {rec['harvest_s']:.1f} s, "
+        f"train {rec['train_s']:.1f} s, val loss {rec['final_val_loss']:.4f}")
+    return blob, rec
+
+
+def pdc_rates(wl, prec, blob, cycles):
+    """Per-cycle residual reduction rho = (||r_k|| / ||r_0||)^(1/k) of defect correction with the
+    V-cycle, with and without the learned stage."""
+    from paper_2411_14977_amd import cases
+    out = {}
+    for tag, mode in (("plain", 0), ("learned", STAGE_MODE)):
+        if mode and blob is None:
+            continue
+        s = cases.make_solver(wl, prec=prec, outer="pdc", maxit=cycles)
+        if mode:
+            s.learned_load(blob, mode)
+        rhs = cases.make_rhs(wl, s)
+        try:
+            _, info, _ = s.solve(rhs, tol=1e-30, check=False)
+        finally:
+            s.close()
+        h = info.history()
+        k = len(h) - 1
+        out[tag] = {"cycles": k, "rho": (h[-1] / h[0]) ** (1.0 / k) if k > 0 and h[0] > 0 else None,
+                    "skips": info.learned_skips}
+    return out
+
+
+def unseen_surfaces(args, blob, n):
+    """Iterations and times to 1e-10 on test surfaces 1..n (surface seeds 1001.., never trained on)."""
+    from paper_2411_14977_amd import cases
+    rows = []
+    for i in range(1, n + 1):
+        wl = workload(args.workload, i)
+        s = cases.make_solver(wl, prec=args.prec)
+        rhs = cases.make_rhs(wl, s)
+        r = {"surface_seed": wl.surface_seed}
+        for tag, mode in (("plain", 0), ("learned", STAGE_MODE)):
+            if mode:
+                s.learned_load(blob, mode)
+            t, info, _ = time_solves(s, rhs, 1, 1, 1e-10)
+            r[tag] = {"iters": info.iters, "ms": t * 1e3, "skips": info.learned_skips}
+        s.close()
+        rows.append(r)
+        log(f"[bench] surface {wl.surface_seed}: plain {r['plain']['iters']} it "
+            f"{r['plain']['ms']:.2f} ms, learned {r['learned']['iters']} it {r['learned']['ms']:.2f} ms")
+    return rows
 
 
 def traffic_from_profiles(kernel_tag):
@@ -123,6 +199,19 @@ def cpu_baseline(wl, tol):
             "solves_per_s_sample": 1.0 / t_solve, "iters": it}
 
 
+def oracle_check(wl, x):
+    """Relative residual of the returned pressure, evaluated by the oracle (its own right-hand
+    side and matrix-free FP64 operator on the CPU)."""
+    import numpy as np
+
+    from oracle import assemble
+    from tests import oracle_cases as oc
+    m = oc.fine_mesh(wl)
+    b = oc.rhs(wl, m)
+    r = b - assemble.apply_matrix_free(m, x.cpu().numpy())
+    return float(np.linalg.norm(r) / np.linalg.norm(b))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -131,6 +220,11 @@ def main():
     ap.add_argument("--workload", default="c4")
     ap.add_argument("--prec", default="bf16", choices=["bf16", "f32"])
     ap.add_argument("--tol", type=float, default=1e-10)
+    ap.add_argument("--no-learned", action="store_true", help="time the V-cycle without the stage")
+    ap.add_argument("--train-surfaces", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=600)
+    ap.add_argument("--surfaces", type=int, default=4, help="unseen test surfaces to report")
+    ap.add_argument("--pdc-cycles", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--op-reps", type=int, default=50)
@@ -140,7 +234,6 @@ def main():
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_2411_14977_amd import binding as B
@@ -148,11 +241,26 @@ def main():
 
     torch.cuda.set_device(0)
     wl = workload(args.workload)
-    log(f"[bench] workload {wl.name} N={wl.n_global} prec={args.prec}")
+    use_learned = not args.no_learned and wl.P == 8
+    log(f"[bench] workload {wl.name} N={wl.n_global} prec={args.prec} learned={use_learned}")
+
+    blob, train_rec = (None, None)
+    if use_learned:
+        blob, train_rec = train_network(args)
+
     s = cases.make_solver(wl, prec=args.prec)
     rhs = cases.make_rhs(wl, s)
+    plain_mixed = None
+    if use_learned:
+        t_nl, info_nl, _ = time_solves(s, rhs, args.steps, args.warmup, args.tol)
+        plain_mixed = {"ms_per_solve": t_nl * 1e3, "solves_per_s": 1.0 / t_nl,
+                       "gdof_per_s": wl.n_global / t_nl / 1e9, "iters": info_nl.iters,
+                       "rel_res": info_nl.rel_res}
+        log(f"[bench] mixed without stage: {t_nl * 1e3:.3f} ms/solve, {info_nl.iters} iterations")
+        s.learned_load(blob, STAGE_MODE)
     t, info, x = time_solves(s, rhs, args.steps, args.warmup, args.tol)
-    log(f"[bench] mixed: {t * 1e3:.3f} ms/solve, {info.iters} iterations, rel_res {info.rel_res:.2e}")
+    log(f"[bench] timed path: {t * 1e3:.3f} ms/solve, {info.iters} iterations, "
+        f"rel_res {info.rel_res:.2e}, learned skips {info.learned_skips}")
 
     # dominant kernel: fine-level inner-precision operator apply
     bytes_inner = B.sem_operator_bytes(s.ctx, 0, 0)
@@ -167,25 +275,21 @@ def main():
             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic_from_profiles(kernel_tag),
             "algorithmic_bytes_per_launch": bytes_inner, "avg_launch_ms": ms_inner,
-            "cold_cache": {"avg_launch_ms": ms_inner_cold,
-                           "achieved": bytes_inner / (ms_inner_cold * 1e-3) / 1e9},
+            "timing": "HIP events around back-to-back launches on the library stream; working set "
+                      "resident in the 256 MB Infinity Cache between launches",
+            "cold_single_launch": {"avg_ms_incl_event_overhead": ms_inner_cold,
+                                   "achieved": bytes_inner / (ms_inner_cold * 1e-3) / 1e9},
             "outer_fp64_operator": {"algorithmic_bytes_per_launch": bytes_outer,
                                     "avg_launch_ms": ms_outer,
                                     "achieved": bytes_outer / (ms_outer * 1e-3) / 1e9,
                                     "cold_achieved": bytes_outer / (ms_outer_cold * 1e-3) / 1e9}}
-    log(f"[bench] operator {ms_inner * 1e3:.1f} us warm ({ach:.0f} GB/s), "
-        f"{ms_inner_cold * 1e3:.1f} us cold; fp64 {ms_outer * 1e3:.1f} us")
+    log(f"[bench] operator {ms_inner * 1e3:.2f} us ({ach:.0f} GB/s, {100 * ach / HBM_PEAK_GBS:.1f}% "
+        f"of HBM peak); fp64 outer {ms_outer * 1e3:.2f} us")
+    s.close()
 
-    # oracle residual of the mixed-precision solution (matrix-free FP64 evaluation on the CPU)
     res_check = None
     try:
-        from oracle import assemble
-        from tests import oracle_cases as oc
-        m = oc.fine_mesh(wl)
-        xh = x.cpu().numpy()
-        bh = rhs.cpu().numpy()
-        r = bh - assemble.apply_matrix_free(m, xh)
-        res_check = float(np.linalg.norm(r) / np.linalg.norm(bh))
+        res_check = oracle_check(wl, x)
     except Exception as e:  # pragma: no cover
         log(f"[bench] oracle residual check failed: {e}")
 
@@ -196,9 +300,16 @@ def main():
         plain = {"ms_per_solve": t64 * 1e3, "solves_per_s": 1.0 / t64,
                  "gdof_per_s": wl.n_global / t64 / 1e9, "iters": info64.iters,
                  "rel_res": info64.rel_res,
-                 "mixed_vs_fp64_rel_diff": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))}
+                 "timed_path_vs_fp64_rel_diff": float(torch.linalg.norm(x - x64) / torch.linalg.norm(x64))}
         log(f"[bench] fp64: {t64 * 1e3:.3f} ms/solve, {info64.iters} iterations")
         s64.close()
+
+    pdc = surf = None
+    if use_learned:
+        pdc = pdc_rates(wl, args.prec, blob, args.pdc_cycles)
+        log(f"[bench] PDC per-cycle rate: {pdc}")
+        if args.surfaces > 0:
+            surf = unseen_surfaces(args, blob, args.surfaces)
 
     cpu = None
     if not args.no_cpu:
@@ -209,13 +320,15 @@ def main():
     out = {"metric": METRIC, "value": wl.n_global / t / 1e9, "unit": "GDOF/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "f32/f64", "data": "synthetic", "config": describe(wl, args.prec),
+           "dtype": "fp32 inner (bf16 factors and network operands) / fp64 outer",
+           "data": "synthetic", "config": describe(wl, args.prec, use_learned),
            "solves_per_s": 1.0 / t, "iters": info.iters, "rel_res": info.rel_res,
-           "oracle_rel_res": res_check, "plain_fp64": plain,
+           "learned_skips": info.learned_skips, "oracle_rel_res": res_check,
+           "mixed_without_stage": plain_mixed, "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
+           "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
-    s.close()
 
 
 if __name__ == "__main__":

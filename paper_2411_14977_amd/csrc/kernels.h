@@ -30,12 +30,20 @@ struct GLayout {
 GLayout g2d_layout(int P, int Nz, size_t tgsize);
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                    int Nx, int Nz, int masked, hipStream_t st);
+// the same, plus each workgroup's part of x . (A x) in dotp[0 .. apply2d_blocks) (P <= 8)
+hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
+                       int Nx, int Nz, int masked, double* dotp, hipStream_t st);
+int apply2d_blocks(int P, int Nx, int Nz, bool dbl);
 
 // ---- element-wise kernels in precision T (dbl selects double, else float) ----------------
 // d = cd d + cr dinv r,  x = (from_zero ? 0 : x) + d,  r = b - (from_zero ? 0 : Ax)
+// smoother step x += d, d = cd d + cr dinv r; the residual r by mode:
+enum { SU_AX = 0,      // r = b - (y + S), the column output of the preceding apply
+       SU_ZERO = 1,    // x = 0 on entry: r = b, and x = d
+       SU_RESID = 2 }; // b holds the residual of the current x
 hipError_t smooth_update(bool dbl, void* x, void* d, const void* b, const void* dinv,
                          const void* y, const void* S, unsigned N, unsigned nzn, unsigned P,
-                         double cd, double cr, int from_zero, int store_d, hipStream_t st);
+                         double cd, double cr, int mode, int store_d, hipStream_t st);
 // first step of a V-cycle's pre-smoothing from x = 0, right-hand side taken from FP64 r64
 // (stored rounded into b): d = cr dinv b, x = d
 hipError_t smooth_first64(bool dbl, void* x, void* d, void* b, const double* r64,

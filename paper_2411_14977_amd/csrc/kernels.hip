@@ -190,11 +190,14 @@ __device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int n
 // element ez: the vertical line i = q (sigma-direction contractions, geometric factors) and the
 // horizontal row j = q (x-direction contractions).  The roles swap data through LDS: u_r row ->
 // line, w_r line -> row, D_r^T w_r row -> line.  All contractions run in registers against
-// compile-time D (even-odd form).
-template <int P, typename T, typename TG>
+// compile-time D (even-odd form).  DOT: also the block's part of x . (A x) into dotp[block]
+// (each node's product counted once: its column-output part and its side-buffer part are owned
+// by different blocks, whose sum is the whole entry).
+template <int P, typename T, typename TG, bool DOT = false>
 __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __restrict__ y,
                                                   T* __restrict__ S, const TG* __restrict__ G,
-                                                  int Nx, int Nz, int masked, int cpb, int remap) {
+                                                  int Nx, int Nz, int masked, int cpb, int remap,
+                                                  double* __restrict__ dotp) {
   constexpr int NP = P + 1;
   constexpr int V = lds_vec<T>();
   constexpr int NPp = (NP + V - 1) / V * V;
@@ -300,18 +303,33 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
     if (topel) ocol[P] = masked ? xtop : v[P];
   }
   __syncthreads();
+  double part = 0.0;
   if (valid && t < nzn) {
 #pragma unroll
-    for (int l = 0; l < P; ++l) yc[l * nzn + t] = su[l * nzp + t];
-    const T last = su[P * nzp + t];
-    if (ex == Nx - 1) yc[P * nzn + t] = last;
-    else S[(size_t)(ex + 1) * nzn + t] = (masked && t == nzn - 1) ? (T)0 : last;
+    for (int l = 0; l < P; ++l) {
+      const T o = su[l * nzp + t];
+      yc[l * nzn + t] = o;
+      if constexpr (DOT) part += (double)xin[l] * (double)o;
+    }
+    T last = su[P * nzp + t];
+    if (ex == Nx - 1) {
+      yc[P * nzn + t] = last;
+    } else {
+      if (masked && t == nzn - 1) last = (T)0;
+      S[(size_t)(ex + 1) * nzn + t] = last;
+    }
+    if constexpr (DOT) part += (double)xin[P] * (double)last;
+  }
+  if constexpr (DOT) {
+    __shared__ double red[16];
+    const double tot = block_sum(part, red);
+    if (threadIdx.x == 0) dotp[blockIdx.x] = tot;
   }
 }
 
-template <int P, typename T, typename TG>
+template <int P, typename T, typename TG, bool DOT = false>
 static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G, int Nx, int Nz,
-                                 int masked, hipStream_t st) {
+                                 int masked, double* dotp, hipStream_t st) {
   const bool dbl = sizeof(T) == 8;
   const int nthr = (P + 1) * Nz;
   const int cpb = apply2d_cpb(P, Nx, Nz, dbl);
@@ -319,17 +337,18 @@ static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G,
   const int blocks = (Nx + cpb - 1) / cpb;
   const size_t smem = apply2d_smem(P, Nz, dbl) * cpb;
   const int remap = (blocks % 8 == 0) ? 1 : 0;
-  hipLaunchKernelGGL((k_apply2d<P, T, TG>), dim3(blocks), dim3(threads), smem, st, (const T*)x,
-                     (T*)y, (T*)S, (const TG*)G, Nx, Nz, masked, cpb, remap);
+  hipLaunchKernelGGL((k_apply2d<P, T, TG, DOT>), dim3(blocks), dim3(threads), smem, st,
+                     (const T*)x, (T*)y, (T*)S, (const TG*)G, Nx, Nz, masked, cpb, remap, dotp);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                             int Nx, int Nz, int masked, hipStream_t st) {
-  if (dbl) return launch_apply2d<P, double, double>(x, y, S, G, Nx, Nz, masked, st);
-  if (gt == G_BF16) return launch_apply2d<P, float, uint16_t>(x, y, S, G, Nx, Nz, masked, st);
-  return launch_apply2d<P, float, float>(x, y, S, G, Nx, Nz, masked, st);
+  if (dbl) return launch_apply2d<P, double, double>(x, y, S, G, Nx, Nz, masked, nullptr, st);
+  if (gt == G_BF16)
+    return launch_apply2d<P, float, uint16_t>(x, y, S, G, Nx, Nz, masked, nullptr, st);
+  return launch_apply2d<P, float, float>(x, y, S, G, Nx, Nz, masked, nullptr, st);
 }
 
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
@@ -351,35 +370,67 @@ hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, c
   }
 }
 
+template <int P>
+static hipError_t apply2d_dot_p(bool dbl, GType gt, const void* x, void* y, void* S,
+                                const void* G, int Nx, int Nz, int masked, double* dotp,
+                                hipStream_t st) {
+  if (dbl) return launch_apply2d<P, double, double, true>(x, y, S, G, Nx, Nz, masked, dotp, st);
+  if (gt == G_BF16)
+    return launch_apply2d<P, float, uint16_t, true>(x, y, S, G, Nx, Nz, masked, dotp, st);
+  return launch_apply2d<P, float, float, true>(x, y, S, G, Nx, Nz, masked, dotp, st);
+}
+
+hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
+                       int Nx, int Nz, int masked, double* dotp, hipStream_t st) {
+  switch (P) {
+    case 1: return apply2d_dot_p<1>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    case 2: return apply2d_dot_p<2>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    case 3: return apply2d_dot_p<3>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    case 4: return apply2d_dot_p<4>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    case 5: return apply2d_dot_p<5>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    case 6: return apply2d_dot_p<6>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    case 7: return apply2d_dot_p<7>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    case 8: return apply2d_dot_p<8>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+int apply2d_blocks(int P, int Nx, int Nz, bool dbl) {
+  const int cpb = apply2d_cpb(P, Nx, Nz, dbl);
+  return (Nx + cpb - 1) / cpb;
+}
+
 // ------------------------------------------------------------------------------------------
 // element-wise kernels
 // ------------------------------------------------------------------------------------------
+// mode SU_AX: r = b - (y + S); SU_ZERO: x starts at zero, r = b; SU_RESID: r = b is the residual
+// of the current x (given by the caller)
 template <typename T>
 __global__ void k_smooth_update(T* __restrict__ x, T* __restrict__ d, const T* __restrict__ b,
                                 const T* __restrict__ dinv, const T* __restrict__ y,
                                 const T* __restrict__ S, unsigned N, unsigned nzn, unsigned P,
-                                T cd, T cr, int from_zero, int store_d) {
+                                T cd, T cr, int mode, int store_d) {
   for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
-    const T r = from_zero ? b[g] : b[g] - ax_at(y, S, g, nzn, P);
+    const T r = mode == SU_AX ? b[g] - ax_at(y, S, g, nzn, P) : b[g];
     T dn = cr * dinv[g] * r;
     if (cd != (T)0) dn += cd * d[g];
     if (store_d) d[g] = dn;
-    x[g] = from_zero ? dn : x[g] + dn;
+    x[g] = mode == SU_ZERO ? dn : x[g] + dn;
   }
 }
 
 hipError_t smooth_update(bool dbl, void* x, void* d, const void* b, const void* dinv,
                          const void* y, const void* S, unsigned N, unsigned nzn, unsigned P,
-                         double cd, double cr, int from_zero, int store_d, hipStream_t st) {
+                         double cd, double cr, int mode, int store_d, hipStream_t st) {
   const unsigned blocks = nblk(N, 256);
   if (dbl)
     hipLaunchKernelGGL(k_smooth_update<double>, dim3(blocks), dim3(256), 0, st, (double*)x,
                        (double*)d, (const double*)b, (const double*)dinv, (const double*)y,
-                       (const double*)S, N, nzn, P, cd, cr, from_zero, store_d);
+                       (const double*)S, N, nzn, P, cd, cr, mode, store_d);
   else
     hipLaunchKernelGGL(k_smooth_update<float>, dim3(blocks), dim3(256), 0, st, (float*)x,
                        (float*)d, (const float*)b, (const float*)dinv, (const float*)y,
-                       (const float*)S, N, nzn, P, (float)cd, (float)cr, from_zero, store_d);
+                       (const float*)S, N, nzn, P, (float)cd, (float)cr, mode, store_d);
   return hipGetLastError();
 }
 

@@ -20,17 +20,25 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
-  u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-  return (uint16_t)(u >> 16);
-}
+// float -> bfloat16 bits, IEEE round to nearest even (the gfx950 conversion instruction)
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 __device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz & Stegun, Handbook of Mathematical Functions, formula 7.1.26 (after Hastings):
+// erf(x) = 1 - t (a1 + t (a2 + t (a3 + t (a4 + t a5)))) exp(-x^2), t = 1 / (1 + p x), x >= 0,
+// absolute error <= 1.5e-7, far below the bfloat16 rounding (2^-9 relative) that every hidden
+// activation goes through next
+__device__ __forceinline__ float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.3275911f, ax, 1.0f));
+  const float poly =
+      t * fmaf(fmaf(fmaf(fmaf(1.061405429f, t, -1.453152027f), t, 1.421413741f), t, -0.284496736f), t,
+               0.254829592f);
+  return copysignf(1.0f - poly * __expf(-ax * ax), x);
+}
+__device__ __forceinline__ float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ __forceinline__ float gelu_grad(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) +
-         x * expf(-0.5f * x * x) * 0.39894228040143268f;
+  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) +
+         x * __expf(-0.5f * x * x) * 0.39894228040143268f;
 }
 __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
@@ -692,156 +700,239 @@ __device__ __forceinline__ T ax_at(const T* __restrict__ y, const T* __restrict_
   return v;
 }
 
-// One block = 16 elements, 4 waves.  Every wave takes part in the gather and normalisation; in
-// the three layers the output columns are split over the waves (hidden tiles 2w, 2w+1; output
-// tiles w, w+4), so a block has 4 independent MFMA chains and each wave loads a quarter of the
-// weights, all of them up front so that their latency hides behind the residual gather.
+// deterministic block sum (fixed shuffle pattern and LDS order)
+__device__ __forceinline__ double wsum(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ double bsum(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wsum(v);
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double s = 0.0;
+  for (int k = 0; k < nw; ++k) s += sh[k];
+  return s;
+}
+
+// Persistent form: one workgroup of 1024 threads per compute unit holds the whole network in LDS
+// (BF16, transposed, rows padded against bank conflicts), staged once with coalesced 16-byte
+// loads, and walks over groups of four 16-element tiles, one per 256 threads, in lockstep
+// (shared barriers).  Within a tile every wave takes part in the
+// gather and normalisation; in the three layers the output columns are split over its 4 waves
+// (hidden tiles 2w, 2w+1; output tiles w, w+4).  The workgroup also writes its part of c . r to
+// pcr[workgroup]: with c = W sum_e R_e^T c_e, c . r = sum_e sum_l c_e[l] r_g / m_g (g the global
+// node of (e, l), m_g its multiplicity, weight 0 on the Dirichlet surface when masked), which
+// needs only the workgroup's own r_e and c_e.
+constexpr int MLP_GROUPS = 4;  // 16-element tiles in flight per workgroup
+constexpr int MLP_THREADS = 256 * MLP_GROUPS;
+constexpr int MLP_MAX_BLOCKS = 256;
+
+template <int P>
+struct MlpShape {
+  static constexpr int NP = P + 1, n = NP * NP, KR = (n + 15) / 16 * 16, KS1 = KR / 16,
+                       NT3 = KR / 16;
+  static constexpr int W1S = KR + 8, WHS = NH + 8;  // LDS row strides of the weights
+  static constexpr int XS = KR + 4, HS = NH + 4;    // LDS row strides of the activations
+};
+
 template <int P, typename T>
-__global__ __launch_bounds__(256) void k_stage_mlp(
+__global__ __launch_bounds__(MLP_THREADS) void k_stage_mlp(
     const T* __restrict__ b, const T* __restrict__ y, const T* __restrict__ S,
     const uint16_t* __restrict__ W1r, const float* __restrict__ Z1geo,
     const uint16_t* __restrict__ W2, const float* __restrict__ b2,
     const uint16_t* __restrict__ W3, const float* __restrict__ b3,
-    const float* __restrict__ abar, float* __restrict__ CE, int E, int Nz, unsigned nzn) {
-  constexpr int NP = P + 1, n = NP * NP, KR = (n + 15) / 16 * 16, KS1 = KR / 16, NT3 = KR / 16;
-  constexpr int XS = KR + 4, HS = NH + 4;  // padded LDS rows: the 16 rows of a fragment hit
-                                           // distinct banks
-  __shared__ __align__(16) uint16_t sX[16 * XS];
-  __shared__ __align__(16) uint16_t sH1[16 * HS];
-  __shared__ __align__(16) uint16_t sH2[16 * HS];
-  __shared__ float sS[16];
-  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const float* __restrict__ abar, float* __restrict__ CE, int E, int Nx, int Nz, unsigned nzn,
+    int masked, double* __restrict__ pcr) {
+  using Sh = MlpShape<P>;
+  constexpr int NP = Sh::NP, n = Sh::n, KR = Sh::KR, KS1 = Sh::KS1, NT3 = Sh::NT3;
+  constexpr int W1S = Sh::W1S, WHS = Sh::WHS, XS = Sh::XS, HS = Sh::HS;
+  __shared__ __align__(16) uint16_t sW1[NH * W1S];
+  __shared__ __align__(16) uint16_t sW2[NH * WHS];
+  __shared__ __align__(16) uint16_t sW3[KR * WHS];
+  __shared__ __align__(16) uint16_t sXa[MLP_GROUPS][16 * XS];
+  __shared__ __align__(16) uint16_t sH1a[MLP_GROUPS][16 * HS];
+  __shared__ __align__(16) uint16_t sH2a[MLP_GROUPS][16 * HS];
+  __shared__ float sRa[MLP_GROUPS][16 * n];  // r_e (fp32) for the c . r partial
+  __shared__ float sSca[MLP_GROUPS][16];     // s_e / a_e
+  __shared__ double sred[MLP_THREADS / 64];
+  const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
+  const int wave = gt >> 6, lane = gt & 63;
   const int li = lane & 15, kq = (lane >> 4) * 4;
-  const int e0 = blockIdx.x * 16;
+  uint16_t* sX = sXa[grp];
+  uint16_t* sH1 = sH1a[grp];
+  uint16_t* sH2 = sH2a[grp];
+  float* sR = sRa[grp];
+  float* sSc = sSca[grp];
 
-  // ---- weight fragments of this wave (transposed storage: 4 consecutive k per lane)
-  bf16x4 w1[2][KS1], w2[2][8], w3[2][8];
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt) {
-    const int t = 2 * wave + tt;
-#pragma unroll
-    for (int k = 0; k < KS1; ++k)
-      w1[tt][k] = *reinterpret_cast<const bf16x4*>(W1r + (16 * t + li) * KR + 16 * k + kq);
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      w2[tt][k] = *reinterpret_cast<const bf16x4*>(W2 + (16 * t + li) * NH + 16 * k + kq);
-    const int t3 = wave + 4 * tt;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-      w3[tt][k] = t3 < NT3 ? *reinterpret_cast<const bf16x4*>(W3 + (16 * t3 + li) * NH + 16 * k + kq)
-                           : (bf16x4){0, 0, 0, 0};
-  }
-
-  // layer-1 accumulators start from the precomputed geometric part (loaded before the gather)
-  f32x4 acc[2];
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int er = e0 + kq + v;
-      acc[tt][v] = er < E ? Z1geo[(long)er * NH + 16 * (2 * wave + tt) + li] : 0.f;
+  // ---- the network into LDS: 16-byte chunks, row-padded
+  {
+    constexpr int c1 = KR / 8, c2 = NH / 8;
+    for (int k = tid; k < NH * c1; k += MLP_THREADS) {
+      const int r = k / c1, q = k - r * c1;
+      *reinterpret_cast<uint4*>(sW1 + r * W1S + 8 * q) = *reinterpret_cast<const uint4*>(W1r + r * KR + 8 * q);
     }
-
-  // ---- gather r = b - A x (A x = y + S on shared vertical lines): 16 lanes per element
-  const int el = tid >> 4, lg = tid & 15;
-  const int e = e0 + el;
-  float rv[KS1];
-  float ss = 0.f;
-  if (e < E) {
-    const int ex = e / Nz, ez = e - ex * Nz;
-    const unsigned base = (unsigned)(ex * P) * nzn + ez * P;
-    const unsigned sb = (unsigned)ex * nzn + ez * P;
-#pragma unroll
-    for (int k = 0; k < KS1; ++k) {
-      const int l = lg + 16 * k;
-      rv[k] = 0.f;
-      if (l < n) {
-        const int i = l / NP, j = l - (l / NP) * NP;
-        const unsigned g = base + i * nzn + j;
-        T ax = y[g];
-        if (i == 0) ax += S[sb + j];
-        if (i == P) ax += S[sb + nzn + j];
-        rv[k] = (float)(b[g] - ax);
-      }
-      ss += rv[k] * rv[k];
+    for (int k = tid; k < NH * c2; k += MLP_THREADS) {
+      const int r = k / c2, q = k - r * c2;
+      *reinterpret_cast<uint4*>(sW2 + r * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W2 + r * NH + 8 * q);
     }
-  } else {
-#pragma unroll
-    for (int k = 0; k < KS1; ++k) rv[k] = 0.f;
-  }
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, 64);
-  const float s = sqrtf(ss);
-  if (lg == 0) sS[el] = s;
-#pragma unroll
-  for (int k = 0; k < KS1; ++k) sX[el * XS + lg + 16 * k] = f2bf(s > 0.f ? rv[k] / s : 0.f);
-  __syncthreads();
-
-  // ---- layer 1: Z1 = Xr W1r + Z1geo (the geometric part of X W1 + b1 is precomputed)
-#pragma unroll
-  for (int k = 0; k < KS1; ++k) {
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(sX + li * XS + 16 * k + kq);
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma16(a, w1[tt][k], acc[tt]);
-  }
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sH1[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
-  __syncthreads();
-
-  // ---- layer 2: Z2 = H1 W2 + b2
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt) {
-    const float bb = b2[16 * (2 * wave + tt) + li];
-    acc[tt] = (f32x4){bb, bb, bb, bb};
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH1 + li * HS + 16 * k + kq);
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) acc[tt] = mfma16(a, w2[tt][k], acc[tt]);
-  }
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) sH2[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
-  __syncthreads();
-
-  // ---- layer 3: Y = H2 W3 + b3; c_e = (s_e / a_e) y
-#pragma unroll
-  for (int tt = 0; tt < 2; ++tt) {
-    const int t3 = wave + 4 * tt;
-    if (t3 >= NT3) continue;  // wave-uniform
-    const int col = 16 * t3 + li;
-    const float bb = b3[col];
-    f32x4 c = (f32x4){bb, bb, bb, bb};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH2 + li * HS + 16 * k + kq);
-      c = mfma16(a, w3[tt][k], c);
+    for (int k = tid; k < KR * c2; k += MLP_THREADS) {
+      const int r = k / c2, q = k - r * c2;
+      *reinterpret_cast<uint4*>(sW3 + r * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W3 + r * NH + 8 * q);
     }
-    if (col < n)
+  }
+  const float b2v[2] = {b2[16 * (2 * wave) + li], b2[16 * (2 * wave + 1) + li]};
+  const float b3v[2] = {wave < NT3 ? b3[16 * wave + li] : 0.f,
+                        wave + 4 < NT3 ? b3[16 * (wave + 4) + li] : 0.f};
+
+  const int ntiles = (E + 15) / 16;
+  const int iters = (ntiles + MLP_GROUPS * gridDim.x - 1) / (MLP_GROUPS * gridDim.x);  // same everywhere
+  double part = 0.0;
+  for (int it = 0; it < iters; ++it) {
+    const int tile = (it * gridDim.x + blockIdx.x) * MLP_GROUPS + grp;
+    const int e0 = tile * 16;  // e0 >= E: this group idles through the barriers
+
+    // layer-1 accumulators start from the precomputed geometric part
+    f32x4 acc[2];
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int er = e0 + kq + v;
-        if (er < E) CE[(long)er * n + col] = sS[kq + v] / abar[er] * c[v];
+        acc[tt][v] = er < E ? Z1geo[(long)er * NH + 16 * (2 * wave + tt) + li] : 0.f;
       }
+
+    // gather r = b - A x (A x = y + S on shared vertical lines): 16 lanes per element
+    const int el = gt >> 4, lg = gt & 15;
+    const int e = e0 + el;
+    float rv[KS1];
+    float ss = 0.f;
+    if (e < E) {
+      const int ex = e / Nz, ez = e - ex * Nz;
+      const unsigned base = (unsigned)(ex * P) * nzn + ez * P;
+      const unsigned sb = (unsigned)ex * nzn + ez * P;
+#pragma unroll
+      for (int k = 0; k < KS1; ++k) {
+        const int l = lg + 16 * k;
+        rv[k] = 0.f;
+        if (l < n) {
+          const int i = l / NP, j = l - (l / NP) * NP;
+          const unsigned g = base + i * nzn + j;
+          T ax = y[g];
+          if (i == 0) ax += S[sb + j];
+          if (i == P) ax += S[sb + nzn + j];
+          rv[k] = (float)(b[g] - ax);
+        }
+        ss += rv[k] * rv[k];
+        if (l < n) sR[el * n + l] = rv[k];
+      }
+    } else {
+#pragma unroll
+      for (int k = 0; k < KS1; ++k) rv[k] = 0.f;
+    }
+#pragma unroll
+    for (int o = 8; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, 64);
+    const float s = sqrtf(ss);
+    if (lg == 0) sSc[el] = e < E ? s / abar[e] : 0.f;
+    const float sinv = s > 0.f ? 1.0f / s : 0.f;
+#pragma unroll
+    for (int k = 0; k < KS1; ++k) sX[el * XS + lg + 16 * k] = f2bf(rv[k] * sinv);
+    __syncthreads();
+
+    // layer 1: Z1 = Xr W1r + Z1geo (the geometric part of X W1 + b1 is precomputed)
+#pragma unroll
+    for (int k = 0; k < KS1; ++k) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sX + li * XS + 16 * k + kq);
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        const bf16x4 w = *reinterpret_cast<const bf16x4*>(sW1 + (16 * (2 * wave + tt) + li) * W1S + 16 * k + kq);
+        acc[tt] = mfma16(a, w, acc[tt]);
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sH1[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
+    __syncthreads();
+
+    // layer 2: Z2 = H1 W2 + b2
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) acc[tt] = (f32x4){b2v[tt], b2v[tt], b2v[tt], b2v[tt]};
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH1 + li * HS + 16 * k + kq);
+#pragma unroll
+      for (int tt = 0; tt < 2; ++tt) {
+        const bf16x4 w = *reinterpret_cast<const bf16x4*>(sW2 + (16 * (2 * wave + tt) + li) * WHS + 16 * k + kq);
+        acc[tt] = mfma16(a, w, acc[tt]);
+      }
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sH2[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
+    __syncthreads();
+
+    // layer 3: Y = H2 W3 + b3; c_e = (s_e / a_e) y
+    int exv[4], ezv[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int er = e0 + kq + v;
+      exv[v] = er / Nz;
+      ezv[v] = er - exv[v] * Nz;
+    }
+#pragma unroll
+    for (int tt = 0; tt < 2; ++tt) {
+      const int t3 = wave + 4 * tt;
+      if (t3 >= NT3) continue;  // wave-uniform
+      const int col = 16 * t3 + li;
+      f32x4 c = (f32x4){b3v[tt], b3v[tt], b3v[tt], b3v[tt]};
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH2 + li * HS + 16 * k + kq);
+        const bf16x4 w = *reinterpret_cast<const bf16x4*>(sW3 + col * WHS + 16 * k + kq);
+        c = mfma16(a, w, c);
+      }
+      if (col < n) {
+        const int i = col / NP, j = col - (col / NP) * NP;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int er = e0 + kq + v;
+          if (er < E) {
+            const float ce = sSc[kq + v] * c[v];
+            CE[(long)er * n + col] = ce;
+            const int mx = ((i == 0 && exv[v] > 0) || (i == P && exv[v] < Nx - 1)) ? 2 : 1;
+            const int mz = ((j == 0 && ezv[v] > 0) || (j == P && ezv[v] < Nz - 1)) ? 2 : 1;
+            const bool top = masked && j == P && ezv[v] == Nz - 1;
+            if (!top) part += (double)ce * (double)sR[(kq + v) * n + col] / (double)(mx * mz);
+          }
+        }
+      }
+    }
+    __syncthreads();  // sX, sR, sSc are rewritten by the next tile
   }
+  const double tot = bsum(part, sred);
+  if (tid == 0) pcr[blockIdx.x] = tot;
+}
+
+int stage_mlp_blocks(size_t E) {
+  const int groups = (int)((E + 16 * MLP_GROUPS - 1) / (16 * MLP_GROUPS));
+  return groups < MLP_MAX_BLOCKS ? groups : MLP_MAX_BLOCKS;
 }
 
 hipError_t stage_mlp(const Stage& s, bool dbl, const void* b, const void* y, const void* S,
-                     hipStream_t st) {
+                     int masked, double* pcr, hipStream_t st) {
   if (s.P < 1 || s.P > 8 || s.nout != (s.P + 1) * (s.P + 1)) return hipErrorInvalidValue;
-  const unsigned blocks = nblk(s.E, 16);
+  const unsigned blocks = (unsigned)stage_mlp_blocks(s.E);
 #define SEM_STAGE_MLP(PP, TT)                                                                    \
-  hipLaunchKernelGGL((k_stage_mlp<PP, TT>), dim3(blocks), dim3(256), 0, st, (const TT*)b,        \
-                     (const TT*)y, (const TT*)S, s.W1r, s.Z1geo, s.W2, s.b2, s.W3, s.b3, s.abar, \
-                     s.CE, (int)s.E, s.Nz, (unsigned)s.nzn)
-#define SEM_STAGE_MLP_P(PP)          \
-  case PP:                           \
+  hipLaunchKernelGGL((k_stage_mlp<PP, TT>), dim3(blocks), dim3(MLP_THREADS), 0, st,             \
+                     (const TT*)b, (const TT*)y, (const TT*)S, s.W1r, s.Z1geo, s.W2, s.b2, s.W3, \
+                     s.b3, s.abar, s.CE, (int)s.E, s.Nx, s.Nz, (unsigned)s.nzn, masked, pcr)
+#define SEM_STAGE_MLP_P(PP)             \
+  case PP:                              \
     if (dbl) SEM_STAGE_MLP(PP, double); \
-    else SEM_STAGE_MLP(PP, float);   \
+    else SEM_STAGE_MLP(PP, float);      \
     break;
   switch (s.P) {
     SEM_STAGE_MLP_P(1)
@@ -914,111 +1005,82 @@ hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStre
   return hipGetLastError();
 }
 
-__device__ __forceinline__ double wsum(double v) {
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-__device__ double bsum(double v, double* sh) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
-  v = wsum(v);
-  __syncthreads();
-  if (lane == 0) sh[wid] = v;
-  __syncthreads();
-  double s = 0.0;
-  for (int k = 0; k < nw; ++k) s += sh[k];
-  return s;
-}
+// Step of the stage: alpha = c.r / c.q from the block partials of the network kernel (c.r) and of
+// the apply of c (c.q), added in block order by every block (the same value everywhere,
+// independent of scheduling).  Accepted if finite and positive (the A-norm of the error then
+// drops by (c.r)^2 / c.q): x += alpha c and R = r - alpha q; otherwise R = r and the rejection
+// is counted.  Each thread first loads r, q and c of its first UPD_IT nodes, so that the loads
+// are in flight during the reduction.
+constexpr int UPD_IT = 4;
 
-// Step length of the stage.  k_stage_dots writes per-block partial sums of c.r and c.q
-// (r = b - A x, q = A c); k_stage_step adds them in block order (the result does not depend on
-// scheduling) and stores the accepted step: alpha = c.r / c.q if that is finite and positive
-// (the A-norm of the error then drops by (c.r)^2 / c.q), else 0 and the rejection is counted.
-// flags: [0] rejections, bytes 8..15 the step.
 template <typename T>
-__global__ __launch_bounds__(256) void k_stage_dots(const T* __restrict__ c, const T* __restrict__ b,
-                                                    const T* __restrict__ y, const T* __restrict__ S,
-                                                    const T* __restrict__ yq, const T* __restrict__ Sq,
-                                                    double* parts, unsigned N, unsigned nzn,
-                                                    unsigned P) {
-  __shared__ double sh[8];
-  double a0 = 0, a1 = 0;
-  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
-    const double r = (double)(b[g] - ax_at(y, S, g, nzn, P));
-    const double q = (double)ax_at(yq, Sq, g, nzn, P);
-    const double cv = (double)c[g];
-    a0 += cv * r;
-    a1 += cv * q;
+__global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __restrict__ R,
+                                                       const T* __restrict__ c, const T* __restrict__ b,
+                                                       const T* __restrict__ y, const T* __restrict__ S,
+                                                       const T* __restrict__ yq, const T* __restrict__ Sq,
+                                                       const double* __restrict__ pcr, int ncr,
+                                                       const double* __restrict__ pcq, int ncq,
+                                                       int* skips, unsigned N, unsigned nzn, unsigned P) {
+  __shared__ double sh[16];
+  const unsigned stride = gridDim.x * blockDim.x;
+  const unsigned g0 = blockIdx.x * blockDim.x + threadIdx.x;
+  T rr[UPD_IT], qq[UPD_IT], cc[UPD_IT];
+#pragma unroll
+  for (int k = 0; k < UPD_IT; ++k) {
+    const unsigned g = g0 + k * stride;
+    if (g < N) {
+      rr[k] = b[g] - ax_at(y, S, g, nzn, P);
+      qq[k] = ax_at(yq, Sq, g, nzn, P);
+      cc[k] = c[g];
+    }
   }
-  const double v0 = bsum(a0, sh), v1 = bsum(a1, sh);
-  if (threadIdx.x == 0) {
-    parts[blockIdx.x] = v0;
-    parts[semk::NRED + blockIdx.x] = v1;
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = threadIdx.x; k < ncr; k += blockDim.x) a0 += pcr[k];
+  for (int k = threadIdx.x; k < ncq; k += blockDim.x) a1 += pcq[k];
+  const double cr = bsum(a0, sh);
+  const double cq = bsum(a1, sh);
+  const double alpha = cr / cq;
+  const bool ok = isfinite(alpha) && alpha > 0.0;
+  const T al = ok ? (T)alpha : (T)0;
+#pragma unroll
+  for (int k = 0; k < UPD_IT; ++k) {
+    const unsigned g = g0 + k * stride;
+    if (g < N) {
+      if (ok) {
+        x[g] += al * cc[k];
+        R[g] = rr[k] - al * qq[k];
+      } else {
+        R[g] = rr[k];
+      }
+    }
   }
-}
-
-__global__ __launch_bounds__(256) void k_stage_step(const double* __restrict__ parts, int* flags) {
-  __shared__ double sh[8];
-  double p0 = 0.0, p1 = 0.0;
-  for (int k = threadIdx.x; k < semk::NRED; k += blockDim.x) {
-    p0 += parts[k];
-    p1 += parts[semk::NRED + k];
-  }
-  const double cr = bsum(p0, sh), cq = bsum(p1, sh);
-  if (threadIdx.x == 0) {
-    const double alpha = cr / cq;
-    const bool ok = isfinite(alpha) && alpha > 0.0;
-    *reinterpret_cast<double*>(flags + 2) = ok ? alpha : 0.0;
-    if (!ok) flags[0] += 1;
-  }
-}
-
-hipError_t stage_dots(bool dbl, const void* c, const void* b, const void* y, const void* S,
-                      const void* yq, const void* Sq, double* parts, int* flags, unsigned N,
-                      unsigned nzn, unsigned P, hipStream_t st) {
-  if (dbl)
-    hipLaunchKernelGGL(k_stage_dots<double>, dim3(semk::NRED), dim3(256), 0, st, (const double*)c,
-                       (const double*)b, (const double*)y, (const double*)S, (const double*)yq,
-                       (const double*)Sq, parts, N, nzn, P);
-  else
-    hipLaunchKernelGGL(k_stage_dots<float>, dim3(semk::NRED), dim3(256), 0, st, (const float*)c,
-                       (const float*)b, (const float*)y, (const float*)S, (const float*)yq,
-                       (const float*)Sq, parts, N, nzn, P);
-  hipLaunchKernelGGL(k_stage_step, dim3(1), dim3(256), 0, st, (const double*)parts, flags);
-  return hipGetLastError();
-}
-
-// x += alpha c and R = r - alpha q with the step chosen by k_stage_dots (alpha = 0: R = r)
-template <typename T>
-__global__ __launch_bounds__(256) void k_stage_update(T* __restrict__ x, T* __restrict__ R,
-                                                      const T* __restrict__ c, const T* __restrict__ b,
-                                                      const T* __restrict__ y, const T* __restrict__ S,
-                                                      const T* __restrict__ yq, const T* __restrict__ Sq,
-                                                      const int* __restrict__ flags, unsigned N,
-                                                      unsigned nzn, unsigned P) {
-  const T al = (T)*reinterpret_cast<const double*>(flags + 2);
-  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+  for (unsigned g = g0 + UPD_IT * stride; g < N; g += stride) {
     const T r = b[g] - ax_at(y, S, g, nzn, P);
-    if (al != (T)0) {
+    if (ok) {
       x[g] += al * c[g];
       R[g] = r - al * ax_at(yq, Sq, g, nzn, P);
     } else {
       R[g] = r;
     }
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) skips[0] += 1;
 }
 
 hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* b, const void* y,
-                        const void* S, const void* yq, const void* Sq, const int* flags, unsigned N,
-                        unsigned nzn, unsigned P, hipStream_t st) {
-  const unsigned blocks = std::min(nblk(N, 256), 8192u);
+                        const void* S, const void* yq, const void* Sq, const double* pcr, int ncr,
+                        const double* pcq, int ncq, int* skips, unsigned N, unsigned nzn,
+                        unsigned P, hipStream_t st) {
+  const unsigned blocks = nblk(N, 1024 * UPD_IT);
   if (dbl)
-    hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(256), 0, st, (double*)x,
+    hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(1024), 0, st, (double*)x,
                        (double*)R, (const double*)c, (const double*)b, (const double*)y,
-                       (const double*)S, (const double*)yq, (const double*)Sq, flags, N, nzn, P);
+                       (const double*)S, (const double*)yq, (const double*)Sq, pcr, ncr, pcq,
+                       ncq, skips, N, nzn, P);
   else
-    hipLaunchKernelGGL(k_stage_update<float>, dim3(blocks), dim3(256), 0, st, (float*)x,
+    hipLaunchKernelGGL(k_stage_update<float>, dim3(blocks), dim3(1024), 0, st, (float*)x,
                        (float*)R, (const float*)c, (const float*)b, (const float*)y,
-                       (const float*)S, (const float*)yq, (const float*)Sq, flags, N, nzn, P);
+                       (const float*)S, (const float*)yq, (const float*)Sq, pcr, ncr, pcq, ncq,
+                       skips, N, nzn, P);
   return hipGetLastError();
 }
 

@@ -164,7 +164,9 @@ void apply_outer(Ctx* c, const double* x, int masked) {
                    c->st));
 }
 
-void smooth(Ctx* c, int l, bool pre) {
+// pre- or post-smoothing on level l; resid (post-smoothing only): the residual of the current x,
+// already known to the caller, which saves the first operator apply
+void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
   DLevel& L = c->lev[l];
   const sem_mesh_desc& d = c->desc;
   if (d.smoother == SEM_SMOOTH_JACOBI) {
@@ -176,9 +178,11 @@ void smooth(Ctx* c, int l, bool pre) {
                                 c->st));
         continue;
       }
-      if (!fz) apply_level(c, l, L.x, c->masked);
-      HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, 0.0,
-                             d.jacobi_omega, fz ? 1 : 0, 0, c->st));
+      const bool given = !pre && s == 0 && resid;
+      if (!fz && !given) apply_level(c, l, L.x, c->masked);
+      HK(semk::smooth_update(L.dbl, L.x, L.d, given ? resid : L.b, L.dinv, L.y, L.S, L.N, L.nzn,
+                             L.P, 0.0, d.jacobi_omega,
+                             fz ? semk::SU_ZERO : (given ? semk::SU_RESID : semk::SU_AX), 0, c->st));
     }
     return;
   }
@@ -187,18 +191,22 @@ void smooth(Ctx* c, int l, bool pre) {
   const double sigma1 = theta / delta;
   double rho = 1.0 / sigma1;
   const int k = d.cheb_degree;
-  if (!pre) apply_level(c, l, L.x, c->masked);
+  const bool given = !pre && resid;
+  if (!pre && !given) apply_level(c, l, L.x, c->masked);
   if (pre && l == 0 && c->vin64)
     HK(semk::smooth_first64(L.dbl, L.x, L.d, L.b, c->vin64, L.dinv, L.N, 1.0 / theta,
                             k > 1 ? 1 : 0, c->st));
   else
-    HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, 0.0,
-                           1.0 / theta, pre ? 1 : 0, k > 1 ? 1 : 0, c->st));
+    HK(semk::smooth_update(L.dbl, L.x, L.d, given ? resid : L.b, L.dinv, L.y, L.S, L.N, L.nzn,
+                           L.P, 0.0, 1.0 / theta,
+                           pre ? semk::SU_ZERO : (given ? semk::SU_RESID : semk::SU_AX),
+                           k > 1 ? 1 : 0, c->st));
   for (int j = 1; j < k; ++j) {
     const double rho_new = 1.0 / (2.0 * sigma1 - rho);
     apply_level(c, l, L.x, c->masked);
     HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P,
-                           rho_new * rho, 2.0 * rho_new / delta, 0, j + 1 < k ? 1 : 0, c->st));
+                           rho_new * rho, 2.0 * rho_new / delta, semk::SU_AX, j + 1 < k ? 1 : 0,
+                           c->st));
     rho = rho_new;
   }
 }
@@ -240,15 +248,17 @@ void coarse_solve(Ctx* c) {
 void learned_stage(Ctx* c) {
   DLevel& L = c->lev[0];
   semm::Stage& s = c->stage;
+  const int ncr = semm::stage_mlp_blocks(s.E);
+  double* pcr = c->stparts;
+  double* pcq = c->stparts + ncr;
   apply_level(c, 0, L.x, c->masked);
-  HK(semm::stage_mlp(s, L.dbl, L.b, L.y, L.S, c->st));
+  HK(semm::stage_mlp(s, L.dbl, L.b, L.y, L.S, c->masked, pcr, c->st));
   HK(semm::stage_assemble(s, L.dbl, c->cbuf, c->masked, c->st));
-  HK(semk::apply2d(L.P, L.dbl, L.gt, c->cbuf, c->yq, c->Sq, L.G, L.Nx, L.Nz, c->masked,
-                   c->st));
-  HK(semm::stage_dots(L.dbl, c->cbuf, L.b, L.y, L.S, c->yq, c->Sq, c->stparts, s.skips, L.N,
-                      L.nzn, L.P, c->st));
-  HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, L.b, L.y, L.S, c->yq, c->Sq, s.skips, L.N,
-                        L.nzn, L.P, c->st));
+  HK(semk::apply2d_dot(L.P, L.dbl, L.gt, c->cbuf, c->yq, c->Sq, L.G, L.Nx, L.Nz, c->masked, pcq,
+                       c->st));
+  HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, L.b, L.y, L.S, c->yq, c->Sq, pcr, ncr, pcq,
+                        semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl), s.skips, L.N, L.nzn, L.P,
+                        c->st));
 }
 
 // z = B r on level 0 buffers: input r (FP64, device), output lev[0].x
@@ -280,7 +290,11 @@ void vcycle(Ctx* c, const double* r) {
   coarse_solve(c);
   for (int l = L - 2; l >= 0; --l) {
     prolong_from(c, l);
-    if (l == 0 && c->stage.enabled && (c->stage_mode & 2)) learned_stage(c);
+    if (l == 0 && c->stage.enabled && (c->stage_mode & 2)) {
+      learned_stage(c);
+      smooth(c, l, false, c->Rbuf);  // starts from the stage's updated residual
+      continue;
+    }
     smooth(c, l, false);
   }
   c->vin64 = nullptr;
@@ -1095,7 +1109,8 @@ static void stage_buffers(Ctx* c) {
   c->cbuf = dalloc(c, L.N * eb);
   c->yq = dalloc(c, L.N * eb);
   c->Sq = dalloc(c, L.nS * eb);
-  c->stparts = (double*)dalloc(c, 2 * semk::NRED * 8);
+  c->stparts = (double*)dalloc(
+      c, ((size_t)semm::stage_mlp_blocks(E) + semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl)) * 8);
   c->stage_alloc = true;
 }
 

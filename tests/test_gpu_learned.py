@@ -179,7 +179,10 @@ def test_learned_stage_matches_oracle(Nx, Nz, P, Lx, scale, seed, prec):
     s.close()
 
 
-def test_zero_network_leaves_vcycle_unchanged():
+@pytest.mark.parametrize("mode", [1, 2, 3])
+def test_zero_network_leaves_vcycle_unchanged(mode):
+    # c = 0 -> the step is rejected (0/0) and the V-cycle continues from the unchanged residual,
+    # bit for bit, in every placement
     wl = W.tank(16, 4, 8, Lx=1.6, name="tank8")
     s = cases.make_solver(wl, prec="f32")
     r = W.random_vector(s.n_global, 11)
@@ -187,7 +190,7 @@ def test_zero_network_leaves_vcycle_unchanged():
     r[nzn - 1::nzn] = 0.0
     z0 = H(s.vcycle(T64(r)))
     p = {k: np.zeros_like(v) for k, v in params(1).items()}
-    s.learned_load(blob(p), enable=True)
+    s.learned_load(blob(p), enable=mode)
     z1 = H(s.vcycle(T64(r)))
     assert np.array_equal(z0, z1)
     s.close()
