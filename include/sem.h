@@ -79,6 +79,11 @@ typedef struct {
   int lanczos_steps;           /* steps of the lambda_hat estimate (default 20)             */
   unsigned long long lanczos_seed; /* SplitMix64 seed of the Lanczos start vector           */
   void *stream;                /* hipStream_t or NULL                                        */
+  int coarse_dense_max;        /* 3D: below P = 1 the mesh is coarsened in x and y (linear
+                                  transfers, same smoother) until a level has at most this many
+                                  nodes, which is solved exactly with its dense FP64 inverse
+                                  (default 1200).  2D solves P = 1 exactly by block cyclic
+                                  reduction and ignores it.                                   */
 } sem_mesh_desc;
 
 typedef struct {
@@ -100,7 +105,8 @@ typedef struct {
 } sem_train_cfg;
 
 /* Fill *d with defaults (2D, top Dirichlet, FP64, Chebyshev(3) on [0.1, 1.1] lambda_hat,
- * Jacobi omega 2/3, 2+2 sweeps, FPCG, maxit 500, 20 Lanczos steps, seed 12345). */
+ * Jacobi omega 2/3, 2+2 sweeps, FPCG, maxit 500, 20 Lanczos steps, seed 12345, 3D dense
+ * coarse level of at most 1200 nodes). */
 void sem_mesh_desc_default(sem_mesh_desc *d);
 
 /* Build the level hierarchy, geometric factors, inverse diagonals, lambda_hat estimates and

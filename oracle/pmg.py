@@ -10,7 +10,12 @@ Sec. 6 of the paper:
   (Sec. 6.3, V-cycle of Sec. 6); the smoothers here are damped Jacobi and Chebyshev
   acceleration of Jacobi (polynomials in D^{-1} A), with the paper's additive Schwarz smoother
   kept in ``asm_element_solve``;
-* the coarsest (P = 1) problem solved exactly (sparse direct);
+* the coarsest (P = 1) problem solved exactly (sparse direct).  In 3D the paper's P = 1 grid is
+  too large for an exact solve at the benchmark size; the hierarchy is continued below it by
+  coarsening the mesh by 2 in x and y (P = 1, linear interpolation in x and y, identity in
+  sigma, coarse operators re-discretised from h and eta at the coarse vertices) until a level
+  has at most ``coarse_dense_max`` nodes, which is solved exactly.  (The paper is silent on the
+  coarse solver; this reading is stated where it is used.)
 * coarse operators re-discretised with the same formula at the coarse order;
 * outer iterations: preconditioned defect correction x += B(b - A x) (Sec. 6.4) and flexible
   conjugate gradients (one-term Polak-Ribiere beta) with B as preconditioner.
@@ -36,6 +41,19 @@ def coarsen_orders(P):
     while out[-1] > 1:
         out.append((out[-1] + 1) // 2)
     return out
+
+
+def prolongation_1d_linear(Nc):
+    """Linear interpolation from Nc to 2 Nc intervals: even fine nodes coincide with coarse
+    nodes, odd ones take the mean of their two neighbours."""
+    M = sp.lil_matrix((2 * Nc + 1, Nc + 1))
+    for f in range(2 * Nc + 1):
+        if f % 2 == 0:
+            M[f, f // 2] = 1.0
+        else:
+            M[f, (f - 1) // 2] = 0.5
+            M[f, (f + 1) // 2] = 0.5
+    return M.tocsr()
 
 
 def prolongation_1d(Ne, Pc, Pf):
@@ -69,7 +87,8 @@ class Hierarchy:
     """Levels 0 (finest) .. L-1 (P = 1), prolongations P_l : level l+1 -> level l."""
 
     def __init__(self, mesh_args, orders, smoother="chebyshev", nu_pre=2, nu_post=2,
-                 cheb_degree=3, jacobi_omega=2.0 / 3.0, cheb_lo=0.1, cheb_hi=1.1):
+                 cheb_degree=3, jacobi_omega=2.0 / 3.0, cheb_lo=0.1, cheb_hi=1.1,
+                 coarse_dense_max=1200):
         self.dim = mesh_args["dim"]
         self.orders = list(orders)
         if self.orders[-1] != 1:
@@ -96,6 +115,22 @@ class Hierarchy:
                 Py = prolongation_1d(mesh_args["Ny"], pc, pf)
                 Pm = sp.kron(sp.kron(Px, Py), Pz)
             self.P.append(Pm.tocsr())
+        if self.dim == 3:
+            # h-levels below P = 1 (x, y halved; vertices of the coarse mesh are fine vertices)
+            Nx, Ny, Nz = mesh_args["Nx"], mesh_args["Ny"], mesh_args["Nz"]
+            h, eta = np.asarray(mesh_args["h"]), np.asarray(mesh_args["eta"])
+            nx, ny = Nx, Ny
+            while (self.levels[-1].N > coarse_dense_max and nx % 2 == 0 and ny % 2 == 0
+                   and len(self.levels) < 16):
+                ncx, ncy = nx // 2, ny // 2
+                f = (Nx // ncx) * Pf
+                m = Mesh3D(ncx, ncy, Nz, 1, mesh_args["Lx"], mesh_args["Ly"], h[::f, ::f],
+                           eta[::f, ::f], P_fine=1)
+                self.levels.append(Level(m))
+                Pm = sp.kron(sp.kron(prolongation_1d_linear(ncx), prolongation_1d_linear(ncy)),
+                             sp.identity(Nz + 1))
+                self.P.append(Pm.tocsr())
+                nx, ny = ncx, ncy
         last = self.levels[-1]
         last.lu = spla.splu(sp.csc_matrix(last.A))
         self.smoother = smoother

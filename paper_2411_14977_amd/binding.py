@@ -34,7 +34,7 @@ class MeshDesc(ctypes.Structure):
         ("jacobi_omega", ctypes.c_double), ("cheb_lo", ctypes.c_double),
         ("cheb_hi", ctypes.c_double), ("outer", ctypes.c_int), ("maxit", ctypes.c_int),
         ("lanczos_steps", ctypes.c_int), ("lanczos_seed", ctypes.c_ulonglong),
-        ("stream", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p), ("coarse_dense_max", ctypes.c_int),
     ]
 
 
@@ -338,7 +338,7 @@ class Solver:
     def __init__(self, dim, ne, order, length, h, eta, levels=None, prec="f64",
                  smoother="chebyshev", nu_pre=2, nu_post=2, cheb_degree=3, jacobi_omega=2.0 / 3.0,
                  cheb_lo=0.1, cheb_hi=1.1, outer="fpcg", maxit=500, dirichlet=True,
-                 lanczos_steps=20, lanczos_seed=12345, stream=None):
+                 lanczos_steps=20, lanczos_seed=12345, coarse_dense_max=1200, stream=None):
         import torch
         d = sem_mesh_desc_default()
         d.dim = dim
@@ -365,6 +365,7 @@ class Solver:
         d.maxit = maxit
         d.lanczos_steps = lanczos_steps
         d.lanczos_seed = lanczos_seed
+        d.coarse_dense_max = int(coarse_dense_max)
         if stream is None:
             stream = torch.cuda.current_stream().cuda_stream
         d.stream = ctypes.c_void_p(int(stream))

@@ -367,7 +367,7 @@ void build_level(LevelGeom& L, int dim, int Nx, int Ny, int Nz, int P, int Pf, d
 }
 
 // --------------------------------------------------------------------------------------------
-static inline size_t local_to_global(const LevelGeom& L, size_t e, int l) {
+size_t local_to_global(const LevelGeom& L, size_t e, int l) {
   const int NP = L.NP, P = L.P;
   if (L.dim == 2) {
     const size_t ex = e / L.Nz, ez = e % L.Nz;

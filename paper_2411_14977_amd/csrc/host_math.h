@@ -44,6 +44,9 @@ struct LevelGeom {
 void build_level(LevelGeom& L, int dim, int Nx, int Ny, int Nz, int P, int Pf, double Lx,
                  double Ly, const double* h_fine, const double* eta_fine);
 
+// Global node of local node l (2D i*NP + j; 3D (i*NP + m)*NP + j) of element e.
+size_t local_to_global(const LevelGeom& L, size_t e, int l);
+
 // Assembled diagonal of the masked operator from (possibly rounded) factors Gr (same layout
 // as L.G).  Dirichlet rows get 1 when masked.
 std::vector<double> assembled_diag(const LevelGeom& L, const std::vector<double>& Gr, bool masked);

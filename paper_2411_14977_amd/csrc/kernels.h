@@ -34,6 +34,20 @@ hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, c
 hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                        int Nx, int Nz, int masked, double* dotp, hipStream_t st);
 int apply2d_blocks(int P, int Nx, int Nz, bool dbl);
+// 3D operator (element columns (ex, ey) of Nz hexahedra, P <= 8): y = A x complete on return
+// (side buffers Sx, Sy, Sxy are full-size scratch vectors); G in the layout of g3d_layout.
+size_t apply3d_smem(int P, int Nz, bool dbl);
+GLayout g3d_layout(int P, int Nz, size_t tgsize);
+hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
+                   void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st);
+// one 1D operator (CSR rows over the output index) along the middle axis of [outer][n][inner]
+// arrays; in2 (optional) is subtracted from in; mask_nzn > 0 zeroes every mask_nzn-th output
+// (the Dirichlet surface rows when inner is the vertical axis)
+hipError_t axis_apply(int in_dbl, int out_dbl, const void* in, const void* in2, void* out,
+                      int accumulate, unsigned n_outer, unsigned nin, unsigned nout,
+                      unsigned n_inner, const int* rowptr, const int* cols, const double* w,
+                      unsigned mask_nzn, hipStream_t st);
+hipError_t dense_gemv(const double* Ainv, const double* b, double* x, int n, hipStream_t st);
 
 // ---- element-wise kernels in precision T (dbl selects double, else float) ----------------
 // d = cd d + cr dinv r,  x = (from_zero ? 0 : x) + d,  r = b - (from_zero ? 0 : Ax)

@@ -32,10 +32,11 @@ __device__ __forceinline__ float gload<float, uint16_t>(const uint16_t* p) {
 
 static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-// (A x)[g] from the column output y and the side buffer S
+// (A x)[g] from the column output y and the side buffer S (2D; S null: y is complete)
 template <typename T>
 __device__ __forceinline__ T ax_at(const T* __restrict__ y, const T* __restrict__ S, unsigned g,
                                    unsigned nzn, unsigned P) {
+  if (!S) return y[g];  // complete column output (3D, after the face fix-up)
   const unsigned ix = g / nzn;
   const unsigned iz = g - ix * nzn;
   T v = y[g];
@@ -398,6 +399,374 @@ hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* 
 int apply2d_blocks(int P, int Nx, int Nz, bool dbl) {
   const int cpb = apply2d_cpb(P, Nx, Nz, dbl);
   return (Nx + cpb - 1) / cpb;
+}
+
+// ------------------------------------------------------------------------------------------
+// 3D operator apply (sigma-mapped hexahedra; element matrices as in 2D with the five factors
+// G_rr, G_tt, G_rs, G_ts, G_ss; G_rt = 0 because x and y are affine and independent)
+// ------------------------------------------------------------------------------------------
+// LDS per element column: input/output column [NP(i)][NP(m)][nzp], four exchange arrays
+// [Nz][NP][NP][NPp], element-top values [Nz][NP][NP]
+static size_t apply3d_slot(int P, int Nz, bool dbl) {
+  const int NP = P + 1, V = dbl ? 2 : 4, NPp = (NP + V - 1) / V * V;
+  const int nzp = (Nz * P + 1 + V - 1) / V * V;
+  const size_t n = (size_t)NP * NP * nzp + 4 * (size_t)Nz * NP * NP * NPp + (size_t)Nz * NP * NP;
+  return (n + V - 1) / V * V;
+}
+
+size_t apply3d_smem(int P, int Nz, bool dbl) { return apply3d_slot(P, Nz, dbl) * (dbl ? 8 : 4); }
+
+// this thread's 5 (P+1) factors (f, j) of element column c (3D layout: GLayout with K = 5 (P+1))
+template <int P, typename T, typename TG>
+__device__ __forceinline__ void load_g3d(const TG* __restrict__ G, int c, int nthr, int t,
+                                         T (&g)[5][P + 1]) {
+  constexpr int NP = P + 1, K = 5 * NP, W = 16 / (int)sizeof(TG), H = W / 2 > 0 ? W / 2 : 1;
+  constexpr int Kp = (K + H - 1) / H * H, NC = Kp / W, REM = Kp - NC * W;
+  typedef TG vW __attribute__((ext_vector_type(W)));
+  const size_t cstride = ((size_t)nthr * Kp + W - 1) / W * W;
+  const TG* Gc = G + (size_t)c * cstride;
+  TG raw[Kp];
+#pragma unroll
+  for (int q = 0; q < NC; ++q) {
+    const vW a = *reinterpret_cast<const vW*>(Gc + ((size_t)q * nthr + t) * W);
+#pragma unroll
+    for (int w = 0; w < W; ++w) raw[q * W + w] = a[w];
+  }
+  if constexpr (REM == 1) {
+    raw[NC * W] = Gc[(size_t)NC * nthr * W + t];
+  } else if constexpr (REM > 1) {
+    typedef TG vR __attribute__((ext_vector_type(REM)));
+    const vR a = *reinterpret_cast<const vR*>(Gc + (size_t)NC * nthr * W + (size_t)t * REM);
+#pragma unroll
+    for (int w = 0; w < REM; ++w) raw[NC * W + w] = a[w];
+  }
+#pragma unroll
+  for (int f = 0; f < 5; ++f)
+#pragma unroll
+    for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(&raw[f * NP + j]);
+}
+
+GLayout g3d_layout(int P, int Nz, size_t tgsize) {
+  GLayout L;
+  L.W = 16 / (int)tgsize;
+  const int H = L.W / 2 > 0 ? L.W / 2 : 1, K = 5 * (P + 1);
+  L.Kp = (K + H - 1) / H * H;
+  L.NC = L.Kp / L.W;
+  L.REM = L.Kp - L.NC * L.W;
+  const size_t nk = (size_t)(P + 1) * (P + 1) * Nz * L.Kp;
+  L.cstride = (nk + L.W - 1) / L.W * L.W;
+  return L;
+}
+
+// One workgroup per element column (ex, ey) of Nz hexahedra; thread t = (ez NP + a) NP + b has
+// three roles in element ez: the vertical line (i, m) = (a, b) (sigma contractions, factors),
+// the x-row (m, j) = (a, b) and the y-row (i, j) = (a, b).  u_r and u_t go row -> line through
+// LDS, w_r and w_t line -> row, D^T w back row -> line.  Outputs: nodes the column owns (its
+// i < P, m < P lines, and the last lines of the domain) into y; its parts of lines shared with
+// the next column in x, in y or in both into Sx, Sy, Sxy (full-size arrays indexed like y),
+// which k_fix3d adds afterwards.  Deterministic, no atomics.
+template <int P, typename T, typename TG>
+__global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __restrict__ y,
+                                                  T* __restrict__ Sx, T* __restrict__ Sy,
+                                                  T* __restrict__ Sxy, const TG* __restrict__ G,
+                                                  int Nx, int Ny, int Nz, int masked) {
+  constexpr int NP = P + 1, NL = NP * NP;
+  constexpr int V = lds_vec<T>();
+  constexpr int NPp = (NP + V - 1) / V * V;
+  constexpr int AL = line_align<P, T>();
+  const int nzn = Nz * P + 1, nyn = Ny * P + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int nthr = NL * Nz;
+  const int col = blockIdx.x;
+  const int ex = col / Ny, ey = col - ex * Ny;
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* su = reinterpret_cast<T*>(smem_raw);  // [NP(i)][NP(m)][nzp]
+  T* A1 = su + NL * nzp;                    // [Nz][i][m][j]: u_r, later D_r^T w_r
+  T* A2 = A1 + Nz * NL * NPp;               // [Nz][i][m][j]: u_t, later D_t^T w_t
+  T* B1 = A2 + Nz * NL * NPp;               // [Nz][m][j][i]: w_r
+  T* B2 = B1 + Nz * NL * NPp;               // [Nz][i][j][m]: w_t
+  T* stp = B2 + Nz * NL * NPp;              // [Nz][i][m] element-top values
+  const int t = threadIdx.x;
+  const bool act = t < nthr;
+  const int ez = t / NL, ab = t - (t / NL) * NL;
+  const int a = ab / NP, b = ab - (ab / NP) * NP;
+  const size_t gx0 = (size_t)ex * P, gy0 = (size_t)ey * P;
+
+  T g[5][NP];
+  if (act) load_g3d<P, T, TG>(G, col, nthr, t, g);
+  // the column: NP*NP lines of nzn values, one coalesced pass per (line group)
+  {
+    const int total = NL * nzn;
+    T xin[NP + 1];
+#pragma unroll
+    for (int r = 0; r <= NP; ++r) {
+      const int k = t + r * blockDim.x;
+      if (k < total) {
+        const int line = k / nzn, iz = k - (k / nzn) * nzn;
+        const int i = line / NP, m = line - (line / NP) * NP;
+        xin[r] = x[((gx0 + i) * nyn + gy0 + m) * nzn + iz];
+      }
+    }
+#pragma unroll
+    for (int r = 0; r <= NP; ++r) {
+      const int k = t + r * blockDim.x;
+      if (k < total) {
+        const int line = k / nzn, iz = k - (k / nzn) * nzn;
+        su[line * nzp + iz] = xin[r];
+      }
+    }
+  }
+  __syncthreads();
+
+  const bool topel = (ez == Nz - 1);
+  const bool mtop = masked && topel;
+  T v[NP], us[NP];
+  T xtop = 0;
+  if (act) {
+    const int zo = ez * P;
+    {  // x-row role (m, j) = (a, b): u_r(i, m, j) = sum_k D_ik u(k, m, j)
+      T r[NP], o[NP];
+#pragma unroll
+      for (int i = 0; i < NP; ++i) r[i] = (mtop && b == P) ? (T)0 : su[(i * NP + a) * nzp + zo + b];
+      contract_eo<P, false>(r, o);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) A1[((ez * NP + i) * NP + a) * NPp + b] = o[i];
+    }
+    {  // y-row role (i, j) = (a, b): u_t(i, m, j) = sum_k D_mk u(i, k, j)
+      T r[NP], o[NP];
+#pragma unroll
+      for (int m = 0; m < NP; ++m) r[m] = (mtop && b == P) ? (T)0 : su[(a * NP + m) * nzp + zo + b];
+      contract_eo<P, false>(r, o);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) A2[((ez * NP + a) * NP + m) * NPp + b] = o[m];
+    }
+    // line role (i, m) = (a, b): u_s
+    T u[NP];
+    lds_get<NP, AL>(su + ab * nzp + zo, u);
+    if (topel) xtop = u[P];
+    if (mtop) u[P] = 0;
+    contract_eo<P, false>(u, us);
+  }
+  __syncthreads();
+  if (act) {
+    T ur[NP], ut[NP], ws[NP];
+    lds_get<NP, V>(A1 + (ez * NL + ab) * NPp, ur);
+    lds_get<NP, V>(A2 + (ez * NL + ab) * NPp, ut);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      B1[((ez * NP + b) * NP + j) * NPp + a] = g[0][j] * ur[j] + g[2][j] * us[j];
+      B2[((ez * NP + a) * NP + j) * NPp + b] = g[1][j] * ut[j] + g[3][j] * us[j];
+      ws[j] = g[2][j] * ur[j] + g[3][j] * ut[j] + g[4][j] * us[j];
+    }
+    contract_eo<P, true>(ws, v);
+  }
+  __syncthreads();
+  if (act) {
+    {  // x-row (m, j) = (a, b): (D_r^T w_r)(i, m, j)
+      T w[NP], o[NP];
+      lds_get<NP, V>(B1 + ((ez * NP + a) * NP + b) * NPp, w);
+      contract_eo<P, true>(w, o);
+#pragma unroll
+      for (int i = 0; i < NP; ++i) A1[((ez * NP + i) * NP + a) * NPp + b] = o[i];
+    }
+    {  // y-row (i, j) = (a, b): (D_t^T w_t)(i, m, j)
+      T w[NP], o[NP];
+      lds_get<NP, V>(B2 + ((ez * NP + a) * NP + b) * NPp, w);
+      contract_eo<P, true>(w, o);
+#pragma unroll
+      for (int m = 0; m < NP; ++m) A2[((ez * NP + a) * NP + m) * NPp + b] = o[m];
+    }
+  }
+  __syncthreads();
+  if (act) {
+    T o1[NP], o2[NP];
+    lds_get<NP, V>(A1 + (ez * NL + ab) * NPp, o1);
+    lds_get<NP, V>(A2 + (ez * NL + ab) * NPp, o2);
+#pragma unroll
+    for (int j = 0; j < NP; ++j) v[j] += o1[j] + o2[j];
+    stp[ez * NL + ab] = v[P];
+  }
+  __syncthreads();
+  if (act) {
+    if (ez > 0) v[0] += stp[(ez - 1) * NL + ab];
+    T* ocol = su + ab * nzp + ez * P;
+#pragma unroll
+    for (int j = 0; j < P; ++j) ocol[j] = v[j];
+    if (topel) ocol[P] = masked ? xtop : v[P];
+  }
+  __syncthreads();
+  {
+    const int total = NL * nzn;
+    for (int k = t; k < total; k += blockDim.x) {
+      const int line = k / nzn, iz = k - (k / nzn) * nzn;
+      const int i = line / NP, m = line - (line / NP) * NP;
+      const size_t gg = ((gx0 + i) * nyn + gy0 + m) * nzn + iz;
+      const bool dx = i == P && ex < Nx - 1, dy = m == P && ey < Ny - 1;
+      T val = su[line * nzp + iz];
+      if (!dx && !dy) {
+        y[gg] = val;
+      } else {
+        if (masked && iz == nzn - 1) val = (T)0;
+        T* dst = dx ? (dy ? Sxy : Sx) : Sy;
+        dst[gg] = val;
+      }
+    }
+  }
+}
+
+// y += the side-buffer parts on lines shared between columns: every node of an interior x-plane
+// (Sx, plus Sy and Sxy where it also lies on an interior y-plane), then the nodes of interior
+// y-planes that are not on an x-plane (Sy).  Each node is written by one thread.
+template <typename T>
+__global__ void k_fix3d(T* __restrict__ y, const T* __restrict__ Sx, const T* __restrict__ Sy,
+                        const T* __restrict__ Sxy, int Nx, int Ny, int P, unsigned nyn,
+                        unsigned nzn) {
+  const unsigned nxn = (unsigned)Nx * P + 1;
+  const size_t nxp = (size_t)(Nx - 1) * nyn * nzn;
+  const size_t nyp = (size_t)(Ny - 1) * nxn * nzn;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nxp + nyp;
+       k += (size_t)gridDim.x * blockDim.x) {
+    if (k < nxp) {
+      const size_t q = k / ((size_t)nyn * nzn), rem = k - q * nyn * nzn;
+      const unsigned iy = (unsigned)(rem / nzn), iz = (unsigned)(rem - (size_t)iy * nzn);
+      const size_t g = (((q + 1) * P) * nyn + iy) * nzn + iz;
+      T v = Sx[g];
+      const unsigned qy = iy / P;
+      if (qy * P == iy && qy > 0 && qy < (unsigned)Ny) v += Sy[g] + Sxy[g];
+      y[g] += v;
+    } else {
+      const size_t k2 = k - nxp;
+      const size_t q = k2 / ((size_t)nxn * nzn), rem = k2 - q * nxn * nzn;
+      const unsigned ix = (unsigned)(rem / nzn), iz = (unsigned)(rem - (size_t)ix * nzn);
+      const unsigned qx = ix / P;
+      if (qx * P == ix && qx > 0 && qx < (unsigned)Nx) continue;  // done by the x-plane pass
+      const size_t g = ((size_t)ix * nyn + (q + 1) * P) * nzn + iz;
+      y[g] += Sy[g];
+    }
+  }
+}
+
+template <int P, typename T, typename TG>
+static hipError_t launch_apply3d(const void* x, void* y, void* Sx, void* Sy, void* Sxy,
+                                 const void* G, int Nx, int Ny, int Nz, int masked,
+                                 hipStream_t st) {
+  const bool dbl = sizeof(T) == 8;
+  const int nthr = (P + 1) * (P + 1) * Nz;
+  const int threads = ((nthr + 63) / 64) * 64;
+  hipLaunchKernelGGL((k_apply3d<P, T, TG>), dim3(Nx * Ny), dim3(threads), apply3d_smem(P, Nz, dbl),
+                     st, (const T*)x, (T*)y, (T*)Sx, (T*)Sy, (T*)Sxy, (const TG*)G, Nx, Ny, Nz,
+                     masked);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (Nx > 1 || Ny > 1) {
+    const unsigned nyn = Ny * P + 1, nzn = Nz * P + 1;
+    const size_t tot = (size_t)(Nx - 1) * nyn * nzn + (size_t)(Ny - 1) * (Nx * P + 1) * nzn;
+    const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_fix3d<T>, dim3(blocks), dim3(256), 0, st, (T*)y, (const T*)Sx,
+                       (const T*)Sy, (const T*)Sxy, Nx, Ny, P, nyn, nzn);
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t apply3d_p(bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
+                            void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked,
+                            hipStream_t st) {
+  if (dbl) return launch_apply3d<P, double, double>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+  if (gt == G_BF16)
+    return launch_apply3d<P, float, uint16_t>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+  return launch_apply3d<P, float, float>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+}
+
+hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
+                   void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st) {
+  switch (P) {
+    case 1: return apply3d_p<1>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 2: return apply3d_p<2>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 3: return apply3d_p<3>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 4: return apply3d_p<4>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 5: return apply3d_p<5>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 6: return apply3d_p<6>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 7: return apply3d_p<7>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 8: return apply3d_p<8>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// 3D transfers as three 1D passes: out[o][k][i] (+)= sum_e w_e (in[o][col_e][i] - in2[...])
+// over the CSR row k of a 1D operator along the middle axis (outer o, inner i)
+// ------------------------------------------------------------------------------------------
+template <typename TI, typename TO>
+__global__ void k_axis(const TI* __restrict__ in, const TI* __restrict__ in2,
+                       TO* __restrict__ out, int accumulate, unsigned n_outer, unsigned nin,
+                       unsigned nout, unsigned n_inner, const int* __restrict__ rowptr,
+                       const int* __restrict__ cols, const double* __restrict__ w,
+                       unsigned mask_nzn) {
+  const size_t total = (size_t)n_outer * nout * n_inner;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const size_t ii = k % n_inner, rest = k / n_inner;
+    const unsigned ko = (unsigned)(rest % nout);
+    const size_t o = rest / nout;
+    double s = 0.0;
+    for (int e = rowptr[ko]; e < rowptr[ko + 1]; ++e) {
+      const size_t src = (o * nin + cols[e]) * n_inner + ii;
+      double v = (double)in[src];
+      if (in2) v -= (double)in2[src];
+      s += w[e] * v;
+    }
+    if (mask_nzn && (k % mask_nzn) == mask_nzn - 1) s = 0.0;  // Dirichlet surface rows
+    out[k] = accumulate ? (TO)((double)out[k] + s) : (TO)s;
+  }
+}
+
+template <typename TI, typename TO>
+static hipError_t axis_t(const void* in, const void* in2, void* out, int accumulate,
+                         unsigned n_outer, unsigned nin, unsigned nout, unsigned n_inner,
+                         const int* rowptr, const int* cols, const double* w, unsigned mask_nzn,
+                         hipStream_t st) {
+  const size_t total = (size_t)n_outer * nout * n_inner;
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
+  hipLaunchKernelGGL((k_axis<TI, TO>), dim3(blocks), dim3(256), 0, st, (const TI*)in,
+                     (const TI*)in2, (TO*)out, accumulate, n_outer, nin, nout, n_inner, rowptr,
+                     cols, w, mask_nzn);
+  return hipGetLastError();
+}
+
+hipError_t axis_apply(int in_dbl, int out_dbl, const void* in, const void* in2, void* out,
+                      int accumulate, unsigned n_outer, unsigned nin, unsigned nout,
+                      unsigned n_inner, const int* rowptr, const int* cols, const double* w,
+                      unsigned mask_nzn, hipStream_t st) {
+  if (in_dbl && out_dbl)
+    return axis_t<double, double>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
+                                  cols, w, mask_nzn, st);
+  if (in_dbl)
+    return axis_t<double, float>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
+                                 cols, w, mask_nzn, st);
+  if (out_dbl)
+    return axis_t<float, double>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
+                                 cols, w, mask_nzn, st);
+  return axis_t<float, float>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
+                              cols, w, mask_nzn, st);
+}
+
+// coarsest level: x = Ainv b (dense FP64 inverse of the masked operator), one wave per row
+__global__ __launch_bounds__(256) void k_dense_gemv(const double* __restrict__ Ainv,
+                                                    const double* __restrict__ b,
+                                                    double* __restrict__ x, int n) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= n) return;  // wave-uniform; no barrier below
+  const double* a = Ainv + (size_t)row * n;
+  double s = 0.0;
+  for (int k = lane; k < n; k += 64) s += a[k] * b[k];
+  s = wave_sum(s);
+  if (lane == 0) x[row] = s;
+}
+
+hipError_t dense_gemv(const double* Ainv, const double* b, double* x, int n, hipStream_t st) {
+  hipLaunchKernelGGL(k_dense_gemv, dim3((n + 3) / 4), dim3(256), 0, st, Ainv, b, x, n);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------

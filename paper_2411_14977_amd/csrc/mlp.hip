@@ -692,6 +692,7 @@ bool gradients(const Net& net, const float* X, const float* T, int n, float* gra
 template <typename T>
 __device__ __forceinline__ T ax_at(const T* __restrict__ y, const T* __restrict__ S, unsigned g,
                                    unsigned nzn, unsigned P) {
+  if (!S) return y[g];  // complete column output (3D, after the face fix-up)
   const unsigned ix = g / nzn;
   const unsigned iz = g - ix * nzn;
   T v = y[g];

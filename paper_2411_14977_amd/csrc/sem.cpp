@@ -39,6 +39,14 @@ struct DLevel {
   void *x = nullptr, *b = nullptr, *d = nullptr, *y = nullptr, *S = nullptr;
   size_t nS = 0;
   double lam = 0.0;
+  // 3D: side buffers of the operator (completed into y by the face fix-up; S stays null) and
+  // the 1D transfer operators from the next coarser level (x, y, z; P coarse->fine, R = P^T)
+  void *Sx = nullptr, *Sy = nullptr, *Sxy = nullptr;
+  struct Op1 {
+    int* rp = nullptr;
+    int* ci = nullptr;
+    double* w = nullptr;
+  } P1[3], R1[3];
 };
 
 struct Ctx {
@@ -60,6 +68,11 @@ struct Ctx {
   std::vector<long long*> face_idx;
   std::vector<double*> face_w;
   std::vector<size_t> face_n;
+  // 3D: outer side buffers, transfer temporaries, dense inverse of the coarsest level
+  double *Sxo = nullptr, *Syo = nullptr, *Sxyo = nullptr;
+  double *tA = nullptr, *tB = nullptr;
+  double* Ainv = nullptr;
+  int nAinv = 0;
   // coarse solve
   semh::BcrPlan plan;
   double *bcrF = nullptr, *bcrB = nullptr, *bcrLast = nullptr, *bcrDense = nullptr;
@@ -155,13 +168,20 @@ void set_err(Ctx* c, const std::string& s) { c->err = s; }
 // ------------------------------------------------------------------------------------------
 void apply_level(Ctx* c, int l, const void* x, int masked) {
   DLevel& L = c->lev[l];
-  HK(semk::apply2d(L.P, L.dbl, L.gt, x, L.y, L.S, L.G, L.Nx, L.Nz, masked, c->st));
+  if (c->dim == 3)
+    HK(semk::apply3d(L.P, L.dbl, L.gt, x, L.y, L.Sx, L.Sy, L.Sxy, L.G, L.Nx, L.Ny, L.Nz, masked,
+                     c->st));
+  else
+    HK(semk::apply2d(L.P, L.dbl, L.gt, x, L.y, L.S, L.G, L.Nx, L.Nz, masked, c->st));
 }
 
 void apply_outer(Ctx* c, const double* x, int masked) {
   DLevel& L = c->lev[0];
-  HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Nx, L.Nz, masked,
-                   c->st));
+  if (c->dim == 3)
+    HK(semk::apply3d(L.P, true, semk::G_F64, x, c->yo, c->Sxo, c->Syo, c->Sxyo, c->G64, L.Nx, L.Ny,
+                     L.Nz, masked, c->st));
+  else
+    HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Nx, L.Nz, masked, c->st));
 }
 
 // pre- or post-smoothing on level l; resid (post-smoothing only): the residual of the current x,
@@ -214,6 +234,16 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
 void restrict_to(Ctx* c, int l, bool use_ax) {
   DLevel& F = c->lev[l];
   DLevel& C = c->lev[l + 1];
+  if (c->dim == 3) {  // b_c = (R_x R_y R_z)(b - A x): z, then y, then x; Dirichlet rows zeroed
+    const unsigned nxf = F.nxn, nyf = F.nyn, nzf = F.nzn, nxc = C.nxn, nyc = C.nyn, nzc = C.nzn;
+    HK(semk::axis_apply(F.dbl, 1, F.b, use_ax ? F.y : nullptr, c->tA, 0, nxf * nyf, nzf, nzc, 1,
+                        F.R1[2].rp, F.R1[2].ci, F.R1[2].w, 0, c->st));
+    HK(semk::axis_apply(1, 1, c->tA, nullptr, c->tB, 0, nxf, nyf, nyc, nzc, F.R1[1].rp,
+                        F.R1[1].ci, F.R1[1].w, 0, c->st));
+    HK(semk::axis_apply(1, C.dbl, c->tB, nullptr, C.b, 0, 1, nxf, nxc, nyc * nzc, F.R1[0].rp,
+                        F.R1[0].ci, F.R1[0].w, c->masked ? nzc : 0, c->st));
+    return;
+  }
   HK(semk::restrict2d(F.dbl, C.dbl, F.b, F.y, F.S, use_ax ? 1 : 0, C.b, F.J, F.Nx, F.Nz, F.P,
                       C.P, c->masked, c->st));
 }
@@ -221,6 +251,16 @@ void restrict_to(Ctx* c, int l, bool use_ax) {
 void prolong_from(Ctx* c, int l) {
   DLevel& F = c->lev[l];
   DLevel& C = c->lev[l + 1];
+  if (c->dim == 3) {  // x_f += (P_x P_y P_z) x_c: x, then y, then z
+    const unsigned nxf = F.nxn, nyf = F.nyn, nzf = F.nzn, nxc = C.nxn, nyc = C.nyn, nzc = C.nzn;
+    HK(semk::axis_apply(C.dbl, 1, C.x, nullptr, c->tB, 0, 1, nxc, nxf, nyc * nzc, F.P1[0].rp,
+                        F.P1[0].ci, F.P1[0].w, 0, c->st));
+    HK(semk::axis_apply(1, 1, c->tB, nullptr, c->tA, 0, nxf, nyc, nyf, nzc, F.P1[1].rp,
+                        F.P1[1].ci, F.P1[1].w, 0, c->st));
+    HK(semk::axis_apply(1, F.dbl, c->tA, nullptr, F.x, 1, nxf * nyf, nzc, nzf, 1, F.P1[2].rp,
+                        F.P1[2].ci, F.P1[2].w, 0, c->st));
+    return;
+  }
   HK(semk::prolong2d(F.dbl, C.dbl, C.x, F.x, F.J, F.Nx, F.Nz, F.P, C.P, c->st));
 }
 
@@ -228,6 +268,10 @@ void coarse_solve(Ctx* c) {
   DLevel& L = c->lev.back();
   double* b = (double*)L.b;
   double* x = (double*)L.x;
+  if (c->Ainv) {  // 3D: dense inverse of the (masked) coarsest operator
+    HK(semk::dense_gemv(c->Ainv, b, x, c->nAinv, c->st));
+    return;
+  }
   const semh::BcrPlan& pl = c->plan;
   const int nl = (int)pl.levs.size();
   for (int l = 0; l < nl; ++l) {
@@ -473,12 +517,283 @@ void lanczos(Ctx* c, int l) {
   HK(hipStreamSynchronize(c->st));
 }
 
+// ---------------------------------------------------------------------------------------------
+// 3D set-up: p-levels as in 2D, then (below P = 1) levels coarsened by 2 in x and y with linear
+// transfers until at most desc.coarse_dense_max nodes remain; that level is solved exactly with
+// the dense inverse of its masked operator.
+// ---------------------------------------------------------------------------------------------
+template <typename TG, typename Conv>
+std::vector<TG> permute_G3d(const semh::LevelGeom& L, Conv conv) {
+  // per element column (ex, ey): thread t = (ez NP + i) NP + m owns the 5 NP values (f, j) of its
+  // vertical line, chunked as in the 2D layout (semk::g3d_layout)
+  const int NP = L.NP, Nz = L.Nz;
+  const size_t NL3 = (size_t)NP * NP * NP, nthr = (size_t)NP * NP * Nz;
+  const size_t ncol = (size_t)L.Nx * L.Ny;
+  const semk::GLayout lay = semk::g3d_layout(L.P, Nz, sizeof(TG));
+  std::vector<TG> out(ncol * lay.cstride, TG(0));
+  for (size_t col = 0; col < ncol; ++col)
+    for (int ez = 0; ez < Nz; ++ez)
+      for (int i = 0; i < NP; ++i)
+        for (int m = 0; m < NP; ++m) {
+          const size_t e = col * Nz + ez, t = ((size_t)ez * NP + i) * NP + m;
+          for (int f = 0; f < 5; ++f)
+            for (int j = 0; j < NP; ++j) {
+              const int k = f * NP + j, q = k / lay.W, w = k % lay.W;
+              const size_t off = q < lay.NC ? ((size_t)q * nthr + t) * lay.W + w
+                                            : (size_t)lay.NC * nthr * lay.W + t * lay.REM +
+                                                  (size_t)(k - lay.NC * lay.W);
+              out[col * lay.cstride + off] =
+                  conv(L.G[f * L.E * NL3 + e * NL3 + ((size_t)i * NP + m) * NP + j]);
+            }
+        }
+  return out;
+}
+
+typedef std::vector<std::vector<std::pair<int, double>>> Rows1;
+
+// 1D prolongation between GLL orders Pf > Pc on Ne elements: coarse Lagrange basis at the fine
+// nodes (J, (Pf+1) x (Pc+1)); a node shared by two elements gets one row (J's end rows are
+// exact unit rows, so both elements agree)
+Rows1 prol1d_p(int Ne, int Pf, int Pc, const std::vector<double>& J) {
+  Rows1 r((size_t)Ne * Pf + 1);
+  for (int e = 0; e < Ne; ++e)
+    for (int a = 0; a <= Pf; ++a) {
+      auto& row = r[(size_t)e * Pf + a];
+      if (!row.empty()) continue;
+      for (int b = 0; b <= Pc; ++b) {
+        const double v = J[(size_t)a * (Pc + 1) + b];
+        if (v != 0.0) row.push_back({e * Pc + b, v});
+      }
+    }
+  return r;
+}
+
+// 1D linear interpolation from Nc to 2 Nc intervals (P = 1 nodes)
+Rows1 prol1d_h(int Nc) {
+  Rows1 r((size_t)2 * Nc + 1);
+  for (int f = 0; f <= 2 * Nc; ++f) {
+    if (f % 2 == 0) r[f].push_back({f / 2, 1.0});
+    else {
+      r[f].push_back({(f - 1) / 2, 0.5});
+      r[f].push_back({(f + 1) / 2, 0.5});
+    }
+  }
+  return r;
+}
+
+Rows1 ident1d(int n) {
+  Rows1 r(n);
+  for (int k = 0; k < n; ++k) r[k].push_back({k, 1.0});
+  return r;
+}
+
+Rows1 transpose1d(const Rows1& r, int ncols) {
+  Rows1 t(ncols);
+  for (size_t f = 0; f < r.size(); ++f)
+    for (const auto& e : r[f]) t[e.first].push_back({(int)f, e.second});
+  return t;
+}
+
+void upload_op(Ctx* c, const Rows1& r, DLevel::Op1& op) {
+  std::vector<int> rp(1, 0), ci;
+  std::vector<double> w;
+  for (const auto& row : r) {
+    for (const auto& e : row) {
+      ci.push_back(e.first);
+      w.push_back(e.second);
+    }
+    rp.push_back((int)ci.size());
+  }
+  op.rp = upload(c, rp);
+  op.ci = upload(c, ci);
+  op.w = upload(c, w);
+}
+
+void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders) {
+  c->Nx = d->ne[0];
+  c->Ny = d->ne[1];
+  c->Nz = d->ne[2];
+  if (c->Nx < 1 || c->Ny < 1 || c->Nz < 1) throw ArgFail{"ne must be positive"};
+  if (d->len[1] <= 0) throw ArgFail{"len[1] must be positive"};
+  if (orders[0] > 8) throw ArgFail{"3D supports orders up to 8"};
+  const int NPf = orders[0] + 1;
+  if (NPf * NPf * c->Nz > 1024) throw ArgFail{"(P+1)^2 * ne[2] must not exceed 1024 in 3D"};
+  if (semk::apply3d_smem(orders[0], c->Nz, true) > 160 * 1024)
+    throw ArgFail{"3D operator kernel exceeds LDS for this size"};
+  const double N64 = (double)(c->Nx * orders[0] + 1) * (c->Ny * orders[0] + 1) *
+                     (c->Nz * orders[0] + 1);
+  if (N64 > 2.0e9) throw ArgFail{"problem too large"};
+  const int cdm = d->coarse_dense_max > 0 ? d->coarse_dense_max : 1200;
+
+  // level list: (order, Nx, Ny)
+  struct LD { int P, Nx, Ny; };
+  std::vector<LD> lds;
+  for (int p : orders) lds.push_back({p, c->Nx, c->Ny});
+  auto nodes = [&](const LD& l) {
+    return (double)(l.Nx * l.P + 1) * (l.Ny * l.P + 1) * (c->Nz * l.P + 1);
+  };
+  while (c->masked && nodes(lds.back()) > cdm && lds.back().Nx % 2 == 0 && lds.back().Ny % 2 == 0 &&
+         lds.size() < 16)
+    lds.push_back({1, lds.back().Nx / 2, lds.back().Ny / 2});
+  if (c->masked && nodes(lds.back()) > 20000)
+    throw ArgFail{"3D coarse level too large for a dense solve (make ne[0], ne[1] divisible by "
+                  "powers of 2)"};
+  const int nl = (int)lds.size();
+  const int Pf = orders[0];
+  const int nyf = c->Ny * Pf + 1;
+  c->lev.resize(nl);
+  for (int l = 0; l < nl; ++l) {
+    DLevel& L = c->lev[l];
+    const LD& ld = lds[l];
+    if (ld.Nx == c->Nx) {
+      semh::build_level(L.geo, 3, c->Nx, c->Ny, c->Nz, ld.P, Pf, d->len[0], d->len[1], d->h,
+                        d->eta);
+    } else {  // h-coarsened P = 1 level: h, eta at its vertices (a subset of the fine samples)
+      const int f = c->Nx / ld.Nx;
+      std::vector<double> hs((size_t)(ld.Nx + 1) * (ld.Ny + 1)), es(hs.size());
+      for (int ix = 0; ix <= ld.Nx; ++ix)
+        for (int iy = 0; iy <= ld.Ny; ++iy) {
+          const size_t src = (size_t)(ix * f * Pf) * nyf + (size_t)iy * f * Pf;
+          hs[(size_t)ix * (ld.Ny + 1) + iy] = d->h[src];
+          es[(size_t)ix * (ld.Ny + 1) + iy] = d->eta[src];
+        }
+      semh::build_level(L.geo, 3, ld.Nx, ld.Ny, c->Nz, 1, 1, d->len[0], d->len[1], hs.data(),
+                        es.data());
+    }
+    L.P = ld.P;
+    L.NP = L.P + 1;
+    L.Nx = ld.Nx;
+    L.Ny = ld.Ny;
+    L.Nz = c->Nz;
+    L.nxn = L.geo.nxn;
+    L.nyn = L.geo.nyn;
+    L.nzn = L.geo.nzn;
+    L.N = (unsigned)L.geo.N;
+    const bool coarsest = (l == nl - 1);
+    L.dbl = coarsest || c->prec == SEM_F64;
+    L.gt = L.dbl ? semk::G_F64 : (c->prec == SEM_F32_GBF16 ? semk::G_BF16 : semk::G_F32);
+    std::vector<double> Gr = L.geo.G;
+    if (L.gt == semk::G_F32)
+      for (auto& v : Gr) v = (double)(float)v;
+    else if (L.gt == semk::G_BF16)
+      for (auto& v : Gr) v = semh::bf16_round(v);
+    if (L.gt == semk::G_F64)
+      L.G = upload(c, permute_G3d<double>(L.geo, [](double v) { return v; }));
+    else if (L.gt == semk::G_F32)
+      L.G = upload(c, permute_G3d<float>(L.geo, [](double v) { return (float)v; }));
+    else
+      L.G = upload(c, permute_G3d<uint16_t>(L.geo, [](double v) { return semh::bf16_bits((float)v); }));
+    std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
+    std::vector<double> dinv(diag.size());
+    for (size_t g = 0; g < diag.size(); ++g) dinv[g] = 1.0 / diag[g];
+    if (L.dbl) L.dinv = upload(c, dinv);
+    else L.dinv = upload(c, std::vector<float>(dinv.begin(), dinv.end()));
+    const size_t eb = esz(L.dbl);
+    L.x = dalloc(c, L.N * eb);
+    L.b = dalloc(c, L.N * eb);
+    L.d = dalloc(c, L.N * eb);
+    L.y = dalloc(c, L.N * eb);
+    L.Sx = dalloc(c, L.N * eb);
+    L.Sy = dalloc(c, L.N * eb);
+    L.Sxy = dalloc(c, L.N * eb);
+    L.S = nullptr;
+    L.nS = 0;
+  }
+  // transfers and their temporaries
+  size_t tmax = 1;
+  for (int l = 0; l + 1 < nl; ++l) {
+    DLevel& F = c->lev[l];
+    DLevel& C = c->lev[l + 1];
+    Rows1 px, py, pz;
+    if (F.Nx == C.Nx) {
+      const std::vector<double> J = semh::interp_matrix(C.geo.r, F.geo.r);
+      px = prol1d_p(F.Nx, F.P, C.P, J);
+      py = prol1d_p(F.Ny, F.P, C.P, J);
+      pz = prol1d_p(F.Nz, F.P, C.P, J);
+    } else {
+      px = prol1d_h(C.Nx);
+      py = prol1d_h(C.Ny);
+      pz = ident1d(F.nzn);
+    }
+    upload_op(c, px, F.P1[0]);
+    upload_op(c, py, F.P1[1]);
+    upload_op(c, pz, F.P1[2]);
+    upload_op(c, transpose1d(px, C.nxn), F.R1[0]);
+    upload_op(c, transpose1d(py, C.nyn), F.R1[1]);
+    upload_op(c, transpose1d(pz, C.nzn), F.R1[2]);
+    tmax = std::max(tmax, (size_t)F.nxn * F.nyn * C.nzn);
+    tmax = std::max(tmax, (size_t)F.nxn * C.nyn * C.nzn);
+  }
+  c->tA = (double*)dalloc(c, tmax * 8);
+  c->tB = (double*)dalloc(c, tmax * 8);
+  // outer FP64 operator
+  DLevel& L0 = c->lev[0];
+  if (L0.dbl) c->G64 = (double*)L0.G;
+  else c->G64 = upload(c, permute_G3d<double>(L0.geo, [](double v) { return v; }));
+  const size_t N = L0.N;
+  c->xo = (double*)dalloc(c, N * 8);
+  c->bo = (double*)dalloc(c, N * 8);
+  c->ro = (double*)dalloc(c, N * 8);
+  c->po = (double*)dalloc(c, N * 8);
+  c->qo = (double*)dalloc(c, N * 8);
+  c->zo = (double*)dalloc(c, N * 8);
+  c->yo = (double*)dalloc(c, N * 8);
+  c->Sxo = (double*)dalloc(c, N * 8);
+  c->Syo = (double*)dalloc(c, N * 8);
+  c->Sxyo = (double*)dalloc(c, N * 8);
+  c->So = nullptr;
+  c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
+  c->scal = (double*)dalloc(c, 64 * 8);
+  HK(hipHostMalloc((void**)&c->hscal, 3 * semk::NRED * 8, hipHostMallocDefault));
+  {  // lumped mass and Neumann faces of the fine level
+    const semh::LevelGeom& G = L0.geo;
+    const size_t NL3 = (size_t)G.NP * G.NP * G.NP;
+    std::vector<double> m(N, 0.0);
+    for (size_t e = 0; e < G.E; ++e)
+      for (size_t l = 0; l < NL3; ++l) m[semh::local_to_global(G, e, (int)l)] += G.mass[e * NL3 + l];
+    c->mass = upload(c, m);
+    for (size_t f = 0; f < G.face_idx.size(); ++f) {
+      std::vector<long long> idx(G.face_idx[f].begin(), G.face_idx[f].end());
+      c->face_idx.push_back(upload(c, idx));
+      c->face_w.push_back(upload(c, G.face_w[f]));
+      c->face_n.push_back(idx.size());
+    }
+  }
+  if (c->masked) {  // dense inverse of the masked coarsest operator
+    DLevel& LC = c->lev.back();
+    const semh::LevelGeom& G = LC.geo;
+    const int n = (int)G.N;
+    const size_t NL3 = (size_t)G.NP * G.NP * G.NP;
+    std::vector<double> A((size_t)n * n, 0.0), Ae(NL3 * NL3);
+    for (size_t e = 0; e < G.E; ++e) {
+      semh::element_matrix(G, G.G, e, Ae.data());
+      for (size_t a = 0; a < NL3; ++a) {
+        const size_t ga = semh::local_to_global(G, e, (int)a);
+        for (size_t b = 0; b < NL3; ++b)
+          A[ga * n + semh::local_to_global(G, e, (int)b)] += Ae[a * NL3 + b];
+      }
+    }
+    for (int g = 0; g < n; ++g)
+      if (g % G.nzn == G.nzn - 1) {
+        for (int k = 0; k < n; ++k) A[(size_t)g * n + k] = A[(size_t)k * n + g] = 0.0;
+        A[(size_t)g * n + g] = 1.0;
+      }
+    std::vector<double> Ai((size_t)n * n);
+    if (!semh::dense_inverse_public(n, A.data(), Ai.data()))
+      throw ArgFail{"coarse operator is singular"};
+    c->Ainv = upload(c, Ai);
+    c->nAinv = n;
+    for (int l = 0; l + 1 < nl; ++l) lanczos(c, l);
+  }
+  HK(hipStreamSynchronize(c->st));
+}
+
 void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   c->desc = *d;
   c->desc.h = nullptr;
   c->desc.eta = nullptr;
   c->dim = d->dim;
-  if (d->dim != 2) throw ArgFail{"only dim = 2 is supported by this build of the library"};
+  if (d->dim != 2 && d->dim != 3) throw ArgFail{"dim must be 2 or 3"};
   c->Nx = d->ne[0];
   c->Nz = d->ne[2];
   c->Ny = 1;
@@ -508,6 +823,16 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     if (orders.back() != 1) throw ArgFail{"last level order must be 1"};
     for (size_t k = 1; k < orders.size(); ++k)
       if (orders[k] >= orders[k - 1] || orders[k] < 1) throw ArgFail{"level orders must decrease"};
+  }
+  if (d->dim == 3) {
+    c->ust = (hipStream_t)d->stream;
+    HK(hipStreamCreate(&c->st));
+    HK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
+    HK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    const char* ng = std::getenv("SEM_NO_GRAPH");
+    c->use_graphs = !(ng && ng[0] == '1');
+    setup3d_impl(c, d, orders);
+    return;
   }
   if ((orders[0] + 1) * c->Nz > 1024) throw ArgFail{"(P+1)*ne[2] must not exceed 1024"};
   if (c->Nz > 256) throw ArgFail{"ne[2] too large for the coarse solve"};
@@ -748,6 +1073,7 @@ void sem_mesh_desc_default(sem_mesh_desc* d) {
   d->lanczos_steps = 20;
   d->lanczos_seed = 12345ull;
   d->stream = nullptr;
+  d->coarse_dense_max = 1200;
 }
 
 sem_status sem_mesh_setup(const sem_mesh_desc* desc, sem_ctx** out) {
@@ -978,11 +1304,11 @@ sem_status sem_assemble_rhs(sem_ctx* ctx, const double* f, const double* gN, con
     if (c->masked) {
       if (gD) {
         HK(semk::fill(true, c->zo, 0.0, N, c->st));
-        HK(semk::scatter_top(c->zo, gD, L.nxn, L.nzn, c->st));
+        HK(semk::scatter_top(c->zo, gD, L.nxn * L.nyn, L.nzn, c->st));
         apply_outer(c, c->zo, 0);
         HK(semk::rhs_lift(rhs, c->yo, c->So, gD, N, L.nzn, L.P, c->st));
       } else {
-        HK(semk::scatter_top(rhs, nullptr, L.nxn, L.nzn, c->st));
+        HK(semk::scatter_top(rhs, nullptr, L.nxn * L.nyn, L.nzn, c->st));
       }
     }
     leave(c);
@@ -1007,7 +1333,7 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     if (c->stage_alloc) HK(hipMemsetAsync(c->stage.skips, 0, sizeof(int), c->st));
     HK(hipMemcpyAsync(c->bo, rhs, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     HK(hipMemcpyAsync(c->xo, x, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
-    HK(semk::copy_top(c->xo, c->bo, L0.nxn, L0.nzn, c->st));
+    HK(semk::copy_top(c->xo, c->bo, L0.nxn * L0.nyn, L0.nzn, c->st));
     apply_outer(c, c->xo, c->masked);
     HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn, L0.P,
                      c->st));

@@ -172,3 +172,70 @@ def test_pdc_converges():
     x, it, hist = pmg.pdc(L.A, b, np.zeros(L.N), H.vcycle, 1e-10)
     assert hist[-1] <= 1e-10 and it < 60
     assert np.linalg.norm(x - assemble.solve_direct(L.A, b)) < 1e-8 * np.linalg.norm(x)
+
+
+# ---- 3D: levels below P = 1 (mesh coarsened in x and y) --------------------------------------
+def _tank3d(Nx=4, Ny=4, Nz=2, P=2, **kw):
+    wl = W.tank3d(Nx, Ny, Nz, P, L=0.8)
+    return wl, oc.hierarchy(wl, **kw)
+
+
+def test_linear_prolongation_reproduces_linear_functions():
+    for Nc in (1, 2, 5):
+        Pl = pmg.prolongation_1d_linear(Nc).toarray()
+        xc = np.linspace(0.0, 1.0, Nc + 1)
+        xf = np.linspace(0.0, 1.0, 2 * Nc + 1)
+        for f in (np.ones_like, lambda t: t, lambda t: 3.0 * t - 1.0):
+            assert np.abs(Pl @ f(xc) - f(xf)).max() < 1e-15
+        # exactly one unit entry per even row, two halves per odd row
+        assert np.allclose(Pl.sum(axis=1), 1.0)
+
+
+def test_h_levels_3d_structure_and_linear_reproduction():
+    wl, H = _tank3d(coarse_dense_max=40, smoother="jacobi")
+    # P = 2 (405 nodes), P = 1 (75 > 40) -> one h-level 2 x 2 x 2 at P = 1 (27 nodes)
+    assert [L.mesh.P for L in H.levels] == [2, 1, 1]
+    assert [L.N for L in H.levels] == [405, 75, 27]
+    mf, mc = H.levels[1].mesh, H.levels[2].mesh
+    # the coarse vertices are fine vertices: same coordinates there
+    xf, yf, zf = mf.node_coords()
+    xc, yc, zc = mc.node_coords()
+    sel = np.array([((2 * ix) * mf.ny_nodes + 2 * iy) * mf.nz_nodes + iz
+                    for ix in range(mc.nx_nodes) for iy in range(mc.ny_nodes)
+                    for iz in range(mc.nz_nodes)])
+    assert np.abs(xf[sel] - xc).max() < 1e-14 and np.abs(yf[sel] - yc).max() < 1e-14
+    assert np.abs(zf[sel] - zc).max() < 1e-14
+    # prolongation of a function linear in (x, y) and arbitrary in sigma-level index is exact
+    for a, b in ((1.0, 0.0), (0.3, -2.0)):
+        kz = np.arange(mc.nz_nodes)
+        fc = (a * xc + b * yc) * (1 + kz[np.arange(mc.N) % mc.nz_nodes])
+        kf = np.arange(mf.N) % mf.nz_nodes
+        ff = (a * xf + b * yf) * (1 + kf)
+        assert np.abs(H.prolong(1, fc) - ff).max() < 1e-13
+
+
+def test_h_levels_3d_no_smoothing_is_composed_coarse_correction():
+    wl, H = _tank3d(Nx=2, Ny=2, Nz=1, P=2, coarse_dense_max=10, smoother="jacobi", nu_pre=0,
+                    nu_post=0)
+    assert len(H.levels) == 3
+    P0, P1 = H.P[0].toarray(), H.P[1].toarray()
+    Ac = H.levels[2].A.toarray()
+    Z1 = np.eye(H.levels[1].N)
+    Z1[H.levels[1].dn, H.levels[1].dn] = 0.0
+    Z2 = np.eye(Ac.shape[0])
+    Z2[H.levels[2].dn, H.levels[2].dn] = 0.0
+    B_ref = P0 @ P1 @ np.linalg.solve(Ac, Z2 @ P1.T @ Z1 @ P0.T)
+    assert np.abs(dense_B(H) - B_ref).max() < 1e-12 * np.abs(B_ref).max()
+
+
+def test_h_levels_3d_vcycle_symmetric_and_solve_matches_direct():
+    wl, H = _tank3d(coarse_dense_max=40)
+    pmg.estimate_lambdas(H)
+    B = dense_B(H)
+    assert np.abs(B - B.T).max() < 1e-10 * np.abs(B).max()
+    assert np.linalg.eigvalsh(0.5 * (B + B.T)).min() > 0
+    m = H.levels[0].mesh
+    b = oc.rhs(wl, m)
+    x, it, _ = pmg.fpcg(H.levels[0].A, b, np.zeros(m.N), H.vcycle, 1e-12)
+    xd = assemble.solve_direct(H.levels[0].A, b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
