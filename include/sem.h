@@ -130,8 +130,21 @@ sem_status sem_get_level(const sem_ctx *ctx, int level, int *order, size_t *n, d
 sem_status sem_gll(int P, double *nodes, double *weights);
 
 /* Physical coordinates of the nodes of level l (host arrays of that level's node count; y
- * only in 3D, may be NULL in 2D). */
+ * only in 3D, may be NULL in 2D).  Level 0 gives the current surface (after
+ * sem_mesh_update_surface); coarser levels the geometry their V-cycle operators were built on. */
 sem_status sem_node_coords(const sem_ctx *ctx, int level, double *x, double *y, double *z);
+
+/* New free surface for a time series.  The sigma transform follows eta (Sec. 2.2, eq. sigtrans),
+ * so the operator's geometric factors change with it; the paper keeps the multigrid
+ * preconditioner time-constant (Sec. 6.4).  eta: host array in the layout of sem_mesh_desc.eta
+ * (copied).  The FP64 outer operator (sem_apply_laplacian, the outer iteration of
+ * sem_poisson_solve), the lumped mass and the wall-face weights (sem_assemble_rhs) are rebuilt
+ * for the new surface (in 3D on the device).  refresh_precond = 0 keeps every V-cycle level as
+ * it is (frozen preconditioner; FPCG converges to the new operator's solution); 1 rebuilds
+ * every level too (factors, inverse diagonals, coarse solve, lambda_hat estimates and the
+ * learned stage's geometry; host work of the order of the set-up).  Errors: SEM_ERR_ARG if eta is
+ * NULL or h + eta <= 0 anywhere (the context is left unchanged). */
+sem_status sem_mesh_update_surface(sem_ctx *ctx, const double *eta, int refresh_precond);
 
 /* y = A x on the fine level in FP64: the assembled GLL stiffness (sum of element matrices,
  * Sec. 5.2 eq. globallocal) of the symmetric sigma-Laplacian, restricted to free rows and

@@ -105,6 +105,7 @@ def lib():
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
         "sem_learned_load": (ctypes.c_int, [vp, vp, ctypes.c_size_t, ip]),
+        "sem_mesh_update_surface": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
         "sem_learned_enable": (ctypes.c_int, [vp, ip]),
         "sem_learned_stage": (ctypes.c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int)]),
         "sem_last_error": (ctypes.c_char_p, [vp]),
@@ -292,6 +293,13 @@ def sem_mlp_gradients(blob, X, T, nparams):
     return g, loss.value
 
 
+def sem_mesh_update_surface(ctx, eta, refresh=False):
+    """New free surface (host array in the layout of the set-up's eta)."""
+    e = np.ascontiguousarray(np.asarray(eta, dtype=np.float64).ravel())
+    _check(ctx, lib().sem_mesh_update_surface(ctx, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                             1 if refresh else 0))
+
+
 def sem_learned_load(ctx, blob, enable=True):
     _check(ctx, lib().sem_learned_load(ctx, blob, len(blob), int(enable)))
 
@@ -422,6 +430,9 @@ class Solver:
 
     def set_lambda(self, level, lam):
         sem_set_smoother_bounds(self.ctx, level, lam)
+
+    def update_surface(self, eta, refresh=False):
+        sem_mesh_update_surface(self.ctx, eta, refresh)
 
     def learned_load(self, blob, enable=True):
         sem_learned_load(self.ctx, blob, enable)

@@ -48,6 +48,13 @@ hipError_t axis_apply(int in_dbl, int out_dbl, const void* in, const void* in2, 
                       unsigned n_inner, const int* rowptr, const int* cols, const double* w,
                       unsigned mask_nzn, hipStream_t st);
 hipError_t dense_gemv(const double* Ainv, const double* b, double* x, int n, hipStream_t st);
+// surface update (3D, fine level, FP64): factors G (g3d_layout) and lumped mass from the fine
+// column samples hf, ef ((Nx P + 1) x (Ny P + 1), y fastest); r, w: GLL nodes and weights
+hipError_t geom3d(int P, const double* hf, const double* ef, const double* r, const double* w,
+                  double* G, int Nx, int Ny, int Nz, double dx, double dy, hipStream_t st);
+hipError_t mass3d(const double* hf, const double* ef, const double* Wx, const double* Wy,
+                  const double* Wz, double* mass, unsigned nyn, unsigned nzn, size_t N,
+                  double scale, hipStream_t st);
 
 // ---- element-wise kernels in precision T (dbl selects double, else float) ----------------
 // d = cd d + cr dinv r,  x = (from_zero ? 0 : x) + d,  r = b - (from_zero ? 0 : Ax)

@@ -770,6 +770,106 @@ hipError_t dense_gemv(const double* Ainv, const double* b, double* x, int n, hip
 }
 
 // ------------------------------------------------------------------------------------------
+// Surface update (sigma mapping moves with eta): fine-level FP64 factors and lumped mass of the
+// outer operator from the column samples h, eta at the fine horizontal GLL nodes
+// ------------------------------------------------------------------------------------------
+// One thread per (column, ez, i, m) vertical line segment of the fine level; writes its 5 (P+1)
+// factors in the operator's chunked layout (g3d_layout).  Formulas as the set-up's: d = h + eta,
+// h_x, h_y, d_x, d_y by spectral differentiation within the element, sigma_x = (h_x - sigma
+// d_x) / d, and G = w_i w_m w_j |J| (metric products).
+template <int P>
+__global__ void k_geom3d(const double* __restrict__ hf, const double* __restrict__ ef,
+                         const double* __restrict__ r, const double* __restrict__ w,
+                         double* __restrict__ G, int Nx, int Ny, int Nz, double dx, double dy) {
+  constexpr int NP = P + 1, K = 5 * NP, W = 2, Kp = K, NC = Kp / W, REM = Kp - NC * W;
+  const int nthr = NP * NP * Nz;
+  const size_t cstride = ((size_t)nthr * Kp + W - 1) / W * W;
+  const int nyf = Ny * P + 1;
+  const double dsig = 1.0 / Nz, rx = 2.0 / dx, ty = 2.0 / dy, ss = 2.0 / dsig;
+  const size_t total = (size_t)Nx * Ny * nthr;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const int t = (int)(k % nthr);
+    const size_t col = k / nthr;
+    const int ex = (int)(col / Ny), ey = (int)(col - (size_t)ex * Ny);
+    const int ez = t / (NP * NP), i = (t / NP) % NP, m = t % NP;
+    auto H = [&](int a, int b) { return hf[(size_t)(ex * P + a) * nyf + ey * P + b]; };
+    auto Dd = [&](int a, int b) { return H(a, b) + ef[(size_t)(ex * P + a) * nyf + ey * P + b]; };
+    double hx = 0, dxd = 0, hy = 0, dyd = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const double Di = gllc::tab<P>.D[i][q], Dm = gllc::tab<P>.D[m][q];
+      hx += Di * H(q, m);
+      dxd += Di * Dd(q, m);
+      hy += Dm * H(i, q);
+      dyd += Dm * Dd(i, q);
+    }
+    hx *= rx;
+    dxd *= rx;
+    hy *= ty;
+    dyd *= ty;
+    const double d = Dd(i, m);
+    double* Gc = G + col * cstride;
+#pragma unroll
+    for (int j = 0; j < NP; ++j) {
+      const double sig = (ez + (r[j] + 1.0) / 2.0) / Nz;
+      const double sx = (hx - sig * dxd) / d, sy = (hy - sig * dyd) / d;
+      const double wj = w[i] * w[m] * w[j] * (dx / 2.0) * (dy / 2.0) * (d * dsig / 2.0);
+      const double v[5] = {wj * rx * rx, wj * ty * ty, wj * rx * ss * sx, wj * ty * ss * sy,
+                           wj * ss * ss * (sx * sx + sy * sy + 1.0 / (d * d))};
+#pragma unroll
+      for (int f = 0; f < 5; ++f) {
+        const int kk = f * NP + j, q = kk / W, ww = kk - q * W;
+        const size_t off = q < NC ? ((size_t)q * nthr + t) * W + ww
+                                  : (size_t)NC * nthr * W + (size_t)t * REM + (kk - NC * W);
+        Gc[off] = v[f];
+      }
+    }
+  }
+}
+
+hipError_t geom3d(int P, const double* hf, const double* ef, const double* r, const double* w,
+                  double* G, int Nx, int Ny, int Nz, double dx, double dy, hipStream_t st) {
+  const size_t total = (size_t)Nx * Ny * (P + 1) * (P + 1) * Nz;
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
+#define SEM_GEOM(PP) \
+  case PP:           \
+    hipLaunchKernelGGL(k_geom3d<PP>, dim3(blocks), dim3(256), 0, st, hf, ef, r, w, G, Nx, Ny, Nz, dx, dy); \
+    break;
+  switch (P) {
+    SEM_GEOM(1) SEM_GEOM(2) SEM_GEOM(3) SEM_GEOM(4) SEM_GEOM(5) SEM_GEOM(6) SEM_GEOM(7) SEM_GEOM(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SEM_GEOM
+  return hipGetLastError();
+}
+
+// assembled lumped mass: m_g = (dx dy dsig / 8) d(ix, iy) Wx[ix] Wy[iy] Wz[iz], W the sum of the
+// GLL weights of the elements sharing the 1D node (the mass is separable on sigma meshes)
+__global__ void k_mass3d(const double* __restrict__ hf, const double* __restrict__ ef,
+                         const double* __restrict__ Wx, const double* __restrict__ Wy,
+                         const double* __restrict__ Wz, double* __restrict__ mass, unsigned nyn,
+                         unsigned nzn, size_t N, double scale) {
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < N;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const size_t col = g / nzn;
+    const unsigned iz = (unsigned)(g - col * nzn);
+    const unsigned ix = (unsigned)(col / nyn), iy = (unsigned)(col - (size_t)ix * nyn);
+    mass[g] = scale * (hf[col] + ef[col]) * Wx[ix] * Wy[iy] * Wz[iz];
+  }
+}
+
+hipError_t mass3d(const double* hf, const double* ef, const double* Wx, const double* Wy,
+                  const double* Wz, double* mass, unsigned nyn, unsigned nzn, size_t N,
+                  double scale, hipStream_t st) {
+  const unsigned blocks = (unsigned)std::min<size_t>((N + 255) / 256, 65535);
+  hipLaunchKernelGGL(k_mass3d, dim3(blocks), dim3(256), 0, st, hf, ef, Wx, Wy, Wz, mass, nyn, nzn,
+                     N, scale);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 // element-wise kernels
 // ------------------------------------------------------------------------------------------
 // mode SU_AX: r = b - (y + S); SU_ZERO: x starts at zero, r = b; SU_RESID: r = b is the residual

@@ -73,6 +73,13 @@ struct Ctx {
   double *tA = nullptr, *tB = nullptr;
   double* Ainv = nullptr;
   int nAinv = 0;
+  // surface update: fine column samples (host copies; device copies for the 3D kernels)
+  std::vector<double> hf_h, ef_h;
+  int Pf = 1;
+  double len0 = 1.0, len1 = 1.0;
+  double *hf_d = nullptr, *ef_d = nullptr, *r_d = nullptr, *w_d = nullptr;
+  double *Wx_d = nullptr, *Wy_d = nullptr, *Wz_d = nullptr;
+  std::vector<uint8_t> stage_blob;  // the loaded network, to rebuild the stage's geometry
   // coarse solve
   semh::BcrPlan plan;
   double *bcrF = nullptr, *bcrB = nullptr, *bcrLast = nullptr, *bcrDense = nullptr;
@@ -517,6 +524,43 @@ void lanczos(Ctx* c, int l) {
   HK(hipStreamSynchronize(c->st));
 }
 
+// learned-stage geometry of the fine level (2D): per-element features and mean element-matrix
+// diagonal, from the level's current geometry
+void learned_geometry(Ctx* c) {
+  const semh::LevelGeom& G = c->lev[0].geo;
+  const int NP = G.NP, n = NP * NP;
+  const size_t E = G.E, NL = n;
+  c->geo_h.assign(E * 4 * n, 0.f);
+  c->abar_h.assign(E, 0.f);
+  const double* Dm = G.D.data();
+  for (size_t e = 0; e < E; ++e) {
+    const double* Grr = &G.G[0 * E * NL + e * NL];
+    const double* Grs = &G.G[1 * E * NL + e * NL];
+    const double* Gss = &G.G[2 * E * NL + e * NL];
+    const double* ms = &G.mass[e * NL];
+    double gsum = 0, msum = 0, dsum = 0;
+    for (int l = 0; l < n; ++l) {
+      gsum += Grr[l] + Gss[l];
+      msum += ms[l];
+      const int i = l / NP, j = l % NP;
+      double dl = 0;
+      for (int k = 0; k < NP; ++k) dl += Dm[k * NP + i] * Dm[k * NP + i] * Grr[k * NP + j];
+      dl += 2.0 * Dm[i * NP + i] * Dm[j * NP + j] * Grs[l];
+      for (int k = 0; k < NP; ++k) dl += Dm[k * NP + j] * Dm[k * NP + j] * Gss[i * NP + k];
+      dsum += dl;
+    }
+    const double g = gsum / n, mm = msum / n;
+    float* out = &c->geo_h[e * 4 * n];
+    for (int l = 0; l < n; ++l) {
+      out[l] = (float)(Grr[l] / g);
+      out[n + l] = (float)(Grs[l] / g);
+      out[2 * n + l] = (float)(Gss[l] / g);
+      out[3 * n + l] = (float)(ms[l] / mm);
+    }
+    c->abar_h[e] = (float)(dsum / n);
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // 3D set-up: p-levels as in 2D, then (below P = 1) levels coarsened by 2 in x and y with linear
 // transfers until at most desc.coarse_dense_max nodes remain; that level is solved exactly with
@@ -824,6 +868,15 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     for (size_t k = 1; k < orders.size(); ++k)
       if (orders[k] >= orders[k - 1] || orders[k] < 1) throw ArgFail{"level orders must decrease"};
   }
+  {
+    const size_t nh = d->dim == 2 ? (size_t)d->ne[0] * orders[0] + 1
+                                  : ((size_t)d->ne[0] * orders[0] + 1) * ((size_t)d->ne[1] * orders[0] + 1);
+    c->hf_h.assign(d->h, d->h + nh);
+    c->ef_h.assign(d->eta, d->eta + nh);
+    c->Pf = orders[0];
+    c->len0 = d->len[0];
+    c->len1 = d->dim == 3 ? d->len[1] : 1.0;
+  }
   if (d->dim == 3) {
     c->ust = (hipStream_t)d->stream;
     HK(hipStreamCreate(&c->st));
@@ -934,41 +987,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       c->face_n.push_back(idx.size());
     }
   }
-  // learned-stage geometry (fine level): features and mean element-matrix diagonal
-  {
-    const semh::LevelGeom& G = L0.geo;
-    const int NP = G.NP, n = NP * NP;
-    const size_t E = G.E, NL = n;
-    c->geo_h.assign(E * 4 * n, 0.f);
-    c->abar_h.assign(E, 0.f);
-    const double* Dm = G.D.data();
-    for (size_t e = 0; e < E; ++e) {
-      const double* Grr = &G.G[0 * E * NL + e * NL];
-      const double* Grs = &G.G[1 * E * NL + e * NL];
-      const double* Gss = &G.G[2 * E * NL + e * NL];
-      const double* ms = &G.mass[e * NL];
-      double gsum = 0, msum = 0, dsum = 0;
-      for (int l = 0; l < n; ++l) {
-        gsum += Grr[l] + Gss[l];
-        msum += ms[l];
-        const int i = l / NP, j = l % NP;
-        double dl = 0;
-        for (int k = 0; k < NP; ++k) dl += Dm[k * NP + i] * Dm[k * NP + i] * Grr[k * NP + j];
-        dl += 2.0 * Dm[i * NP + i] * Dm[j * NP + j] * Grs[l];
-        for (int k = 0; k < NP; ++k) dl += Dm[k * NP + j] * Dm[k * NP + j] * Gss[i * NP + k];
-        dsum += dl;
-      }
-      const double g = gsum / n, mm = msum / n;
-      float* out = &c->geo_h[e * 4 * n];
-      for (int l = 0; l < n; ++l) {
-        out[l] = (float)(Grr[l] / g);
-        out[n + l] = (float)(Grs[l] / g);
-        out[2 * n + l] = (float)(Gss[l] / g);
-        out[3 * n + l] = (float)(ms[l] / mm);
-      }
-      c->abar_h[e] = (float)(dsum / n);
-    }
-  }
+  learned_geometry(c);
   // coarse factorisation
   {
     DLevel& LC = c->lev.back();
@@ -1157,8 +1176,19 @@ sem_status sem_node_coords(const sem_ctx* ctx, int level, double* x, double* y, 
   if (level < 0 || level >= (int)c->lev.size()) return SEM_ERR_ARG;
   const semh::LevelGeom& G = c->lev[level].geo;
   if (x) std::memcpy(x, G.X.data(), G.N * 8);
-  if (z) std::memcpy(z, G.Z.data(), G.N * 8);
   if (y && !G.Y.empty()) std::memcpy(y, G.Y.data(), G.N * 8);
+  if (z && level > 0) std::memcpy(z, G.Z.data(), G.N * 8);
+  if (z && level == 0) {  // current surface: z = -h + sigma (h + eta) on each vertical line
+    const int P = G.P, nzn = G.nzn;
+    std::vector<double> sig(nzn);
+    for (int iz = 0; iz < nzn; ++iz) {
+      const int ez = iz == nzn - 1 ? G.Nz - 1 : iz / P, j = iz - ez * P;
+      sig[iz] = (ez + (G.r[j] + 1.0) / 2.0) / G.Nz;
+    }
+    for (size_t col = 0; col < c->hf_h.size(); ++col)
+      for (int iz = 0; iz < nzn; ++iz)
+        z[col * nzn + iz] = -c->hf_h[col] + sig[iz] * (c->hf_h[col] + c->ef_h[col]);
+  }
   return SEM_OK;
 }
 
@@ -1496,63 +1526,274 @@ static std::vector<uint16_t> bf16_vec(const float* p, size_t rows, size_t cols, 
   return out;
 }
 
+}  // extern "C"
+
+// internal: load a network into the stage (see sem_learned_load); keeps a copy of the blob
+static void learned_load_impl(Ctx* c, const void* blob, size_t nbytes, int enable) {
+  if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
+  semm::Net net;
+  std::string e;
+  if (!semm::net_from_blob(blob, nbytes, net, e)) throw ArgFail{e};
+  DLevel& L = c->lev[0];
+  const int n = L.NP * L.NP;
+  if (n > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
+  if (net.nin != 5 * n || net.nout != n) throw ArgFail{"network sizes do not match the mesh"};
+  if (c->lev.size() < 2) throw ArgFail{"learned stage needs at least two levels"};
+  HK(hipStreamSynchronize(c->st));
+  stage_buffers(c);
+  semm::Stage& s = c->stage;
+  const int NH = semm::NH, KR = semm::pad16(n), N3 = semm::pad16(n), K4 = semm::pad16(4 * n);
+  const size_t E = s.E, Mp = (E + 15) / 16 * 16;
+  auto put16 = [&](uint16_t* dst, const std::vector<uint16_t>& h) {
+    HK(hipMemcpy(dst, h.data(), h.size() * 2, hipMemcpyHostToDevice));
+  };
+  // transposed (output-major) copies for the inference kernel
+  auto transpose = [](const float* W, int rows, int cols) {
+    std::vector<float> T((size_t)rows * cols);
+    for (int r = 0; r < rows; ++r)
+      for (int q = 0; q < cols; ++q) T[(size_t)q * rows + r] = W[(size_t)r * cols + q];
+    return T;
+  };
+  put16(s.W1r, bf16_vec(transpose(net.W1.data(), n, NH).data(), NH, n, NH, KR));
+  put16(s.W2, bf16_vec(transpose(net.W2.data(), NH, NH).data(), NH, NH, NH, NH));
+  put16(s.W3, bf16_vec(transpose(net.W3.data(), NH, n).data(), n, NH, N3, NH));
+  HK(hipMemcpy(s.b2, net.b2.data(), NH * 4, hipMemcpyHostToDevice));
+  std::vector<float> b3(N3, 0.f);
+  std::copy(net.b3.begin(), net.b3.end(), b3.begin());
+  HK(hipMemcpy(s.b3, b3.data(), N3 * 4, hipMemcpyHostToDevice));
+  // Z1geo = Xg W1g + b1 (geometric part of layer 1), computed once per mesh on the GPU
+  std::vector<uint16_t> xg = bf16_vec(c->geo_h.data(), E, 4 * n, Mp, K4);
+  std::vector<uint16_t> w1g = bf16_vec(net.W1.data() + (size_t)n * NH, 4 * n, NH, K4, NH);
+  void *dx = nullptr, *dw = nullptr, *dz = nullptr, *db = nullptr;
+  HK(hipMalloc(&dx, xg.size() * 2));
+  HK(hipMalloc(&dw, w1g.size() * 2));
+  HK(hipMalloc(&dz, Mp * NH * 4));
+  HK(hipMalloc(&db, NH * 4));
+  HK(hipMemcpy(dx, xg.data(), xg.size() * 2, hipMemcpyHostToDevice));
+  HK(hipMemcpy(dw, w1g.data(), w1g.size() * 2, hipMemcpyHostToDevice));
+  HK(hipMemcpy(db, net.b1.data(), NH * 4, hipMemcpyHostToDevice));
+  HK(semm::gemm_bf16((const uint16_t*)dx, K4, 1, (const uint16_t*)dw, NH, 1, (float*)dz, NH,
+                     (int)Mp, NH, K4, 0, c->st));
+  HK(semm::add_bias((float*)dz, (const float*)db, (int)Mp, NH, c->st));
+  HK(hipMemcpyAsync(s.Z1geo, dz, E * NH * 4, hipMemcpyDeviceToDevice, c->st));
+  HK(hipStreamSynchronize(c->st));
+  HK(hipFree(dx));
+  HK(hipFree(dw));
+  HK(hipFree(dz));
+  HK(hipFree(db));
+  s.enabled = (enable & 3) != 0;
+  c->stage_mode = (enable & 3) ? (enable & 3) : 1;
+  drop_graphs(c);
+  c->stage_blob.assign((const uint8_t*)blob, (const uint8_t*)blob + nbytes);
+}
+
+
+// ---------------------------------------------------------------------------------------------
+// surface update
+// ---------------------------------------------------------------------------------------------
+// sum of the GLL weights of the elements sharing each 1D node (Ne elements of order P)
+static std::vector<double> shared_weights(int Ne, int P, const std::vector<double>& w) {
+  std::vector<double> W((size_t)Ne * P + 1, 0.0);
+  for (int e = 0; e < Ne; ++e)
+    for (int a = 0; a <= P; ++a) W[(size_t)e * P + a] += w[a];
+  return W;
+}
+
+// geometry of level l for the current column samples
+static void level_geometry(Ctx* c, int l, semh::LevelGeom& geo) {
+  DLevel& L = c->lev[l];
+  if (c->dim == 2) {
+    semh::build_level(geo, 2, c->Nx, 1, c->Nz, L.P, c->Pf, c->len0, 1.0, c->hf_h.data(),
+                      c->ef_h.data());
+    return;
+  }
+  if (L.Nx == c->Nx) {
+    semh::build_level(geo, 3, c->Nx, c->Ny, c->Nz, L.P, c->Pf, c->len0, c->len1, c->hf_h.data(),
+                      c->ef_h.data());
+    return;
+  }
+  const int f = c->Nx / L.Nx, nyf = c->Ny * c->Pf + 1;
+  std::vector<double> hs((size_t)(L.Nx + 1) * (L.Ny + 1)), es(hs.size());
+  for (int ix = 0; ix <= L.Nx; ++ix)
+    for (int iy = 0; iy <= L.Ny; ++iy) {
+      const size_t src = (size_t)(ix * f * c->Pf) * nyf + (size_t)iy * f * c->Pf;
+      hs[(size_t)ix * (L.Ny + 1) + iy] = c->hf_h[src];
+      es[(size_t)ix * (L.Ny + 1) + iy] = c->ef_h[src];
+    }
+  semh::build_level(geo, 3, L.Nx, L.Ny, c->Nz, 1, 1, c->len0, c->len1, hs.data(), es.data());
+}
+
+template <typename T>
+static void copy_to(Ctx* c, void* dst, const std::vector<T>& h) {
+  HK(hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+// the outer FP64 operator, the lumped mass and the wall-face weights of the fine level for the
+// current surface (the V-cycle keeps its own factors)
+static void update_outer(Ctx* c) {
+  DLevel& L0 = c->lev[0];
+  const size_t N = L0.N;
+  if ((void*)c->G64 == L0.G) {  // FP64 inner levels share the fine factors: split them
+    const size_t n = c->dim == 2 ? semk::g2d_layout(L0.P, c->Nz, 8).cstride * c->Nx
+                                 : semk::g3d_layout(L0.P, c->Nz, 8).cstride * (size_t)c->Nx * c->Ny;
+    c->G64 = (double*)dalloc(c, n * 8);
+  }
+  const std::vector<double>& w = L0.geo.w;
+  const double dsig = 1.0 / c->Nz;
+  const std::vector<double> Wz = shared_weights(c->Nz, L0.P, w);
+  if (c->dim == 2) {
+    semh::LevelGeom geo;
+    level_geometry(c, 0, geo);
+    copy_to(c, c->G64, permute_G2d<double>(geo, geo.G, [](double v) { return v; }));
+    std::vector<double> m(N, 0.0);
+    const size_t NL = (size_t)geo.NP * geo.NP;
+    for (size_t e = 0; e < geo.E; ++e)
+      for (size_t l = 0; l < NL; ++l) m[semh::local_to_global(geo, e, (int)l)] += geo.mass[e * NL + l];
+    copy_to(c, c->mass, m);
+    for (size_t f = 0; f < geo.face_w.size() && f < c->face_w.size(); ++f)
+      copy_to(c, c->face_w[f], geo.face_w[f]);
+    return;
+  }
+  // 3D: on the device from the column samples
+  const size_t nh = c->hf_h.size();
+  if (!c->hf_d) {
+    c->hf_d = upload(c, c->hf_h);
+    c->ef_d = (double*)dalloc(c, nh * 8);
+    c->r_d = upload(c, L0.geo.r);
+    c->w_d = upload(c, w);
+    c->Wx_d = upload(c, shared_weights(c->Nx, L0.P, w));
+    c->Wy_d = upload(c, shared_weights(c->Ny, L0.P, w));
+    c->Wz_d = upload(c, Wz);
+  }
+  copy_to(c, c->ef_d, c->ef_h);
+  const double dx = c->len0 / c->Nx, dy = c->len1 / c->Ny;
+  HK(semk::geom3d(L0.P, c->hf_d, c->ef_d, c->r_d, c->w_d, c->G64, c->Nx, c->Ny, c->Nz, dx, dy,
+                  c->st));
+  HK(semk::mass3d(c->hf_d, c->ef_d, c->Wx_d, c->Wy_d, c->Wz_d, c->mass, L0.nyn, L0.nzn, N,
+                  dx * dy * dsig / 8.0, c->st));
+  // wall faces (x = 0, x = Lx: [iy][iz]; y = 0, y = Ly: [ix][iz]); the bottom depends on h only
+  const std::vector<double> Wx = shared_weights(c->Nx, L0.P, w), Wy = shared_weights(c->Ny, L0.P, w);
+  const int nxn = L0.nxn, nyn = L0.nyn, nzn = L0.nzn;
+  auto dcol = [&](int ix, int iy) { return c->hf_h[(size_t)ix * nyn + iy] + c->ef_h[(size_t)ix * nyn + iy]; };
+  for (int f = 0; f < 2 && f < (int)c->face_w.size(); ++f) {
+    const int ix = f == 0 ? 0 : nxn - 1;
+    std::vector<double> fw((size_t)nyn * nzn);
+    for (int iy = 0; iy < nyn; ++iy)
+      for (int iz = 0; iz < nzn; ++iz)
+        fw[(size_t)iy * nzn + iz] = (dy / 2.0) * (dsig / 2.0) * dcol(ix, iy) * Wy[iy] * Wz[iz];
+    copy_to(c, c->face_w[f], fw);
+  }
+  for (int f = 0; f < 2 && 2 + f < (int)c->face_w.size(); ++f) {
+    const int iy = f == 0 ? 0 : nyn - 1;
+    std::vector<double> fw((size_t)nxn * nzn);
+    for (int ix = 0; ix < nxn; ++ix)
+      for (int iz = 0; iz < nzn; ++iz)
+        fw[(size_t)ix * nzn + iz] = (dx / 2.0) * (dsig / 2.0) * dcol(ix, iy) * Wx[ix] * Wz[iz];
+    copy_to(c, c->face_w[2 + f], fw);
+  }
+}
+
+// every level of the V-cycle rebuilt for the current surface: factors, inverse diagonals, the
+// coarse solve, lambda_hat (and the learned stage's geometry, when a network is loaded)
+static void rebuild_levels(Ctx* c) {
+  const int nl = (int)c->lev.size();
+  for (int l = 0; l < nl; ++l) {
+    DLevel& L = c->lev[l];
+    semh::LevelGeom geo;
+    level_geometry(c, l, geo);
+    L.geo = std::move(geo);
+    std::vector<double> Gr = L.geo.G;
+    if (L.gt == semk::G_F32)
+      for (auto& v : Gr) v = (double)(float)v;
+    else if (L.gt == semk::G_BF16)
+      for (auto& v : Gr) v = semh::bf16_round(v);
+    if (c->dim == 2) {
+      if (L.gt == semk::G_F64) copy_to(c, L.G, permute_G2d<double>(L.geo, L.geo.G, [](double v) { return v; }));
+      else if (L.gt == semk::G_F32) copy_to(c, L.G, permute_G2d<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
+      else copy_to(c, L.G, permute_G2d<uint16_t>(L.geo, L.geo.G, [](double v) { return semh::bf16_bits((float)v); }));
+    } else {
+      if (L.gt == semk::G_F64) copy_to(c, L.G, permute_G3d<double>(L.geo, [](double v) { return v; }));
+      else if (L.gt == semk::G_F32) copy_to(c, L.G, permute_G3d<float>(L.geo, [](double v) { return (float)v; }));
+      else copy_to(c, L.G, permute_G3d<uint16_t>(L.geo, [](double v) { return semh::bf16_bits((float)v); }));
+    }
+    std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
+    std::vector<double> dinv(diag.size());
+    for (size_t g = 0; g < diag.size(); ++g) dinv[g] = 1.0 / diag[g];
+    if (L.dbl) copy_to(c, L.dinv, dinv);
+    else copy_to(c, L.dinv, std::vector<float>(dinv.begin(), dinv.end()));
+  }
+  if (c->masked) {
+    DLevel& LC = c->lev.back();
+    if (c->dim == 2) {
+      semh::BcrPlan plan;
+      char eb[256] = {0};
+      if (!semh::build_bcr(LC.geo, LC.geo.G, plan, eb, sizeof eb)) throw ArgFail{eb};
+      if (plan.fwd.size() != c->plan.fwd.size() || plan.bwd.size() != c->plan.bwd.size() ||
+          plan.dense.size() != c->plan.dense.size() || plan.last.size() != c->plan.last.size())
+        throw ArgFail{"coarse factorisation changed shape"};
+      if (!plan.fwd.empty()) copy_to(c, c->bcrF, plan.fwd);
+      if (!plan.bwd.empty()) copy_to(c, c->bcrB, plan.bwd);
+      copy_to(c, c->bcrLast, plan.last);
+      copy_to(c, c->bcrDense, plan.dense);
+      c->plan = std::move(plan);
+    } else {
+      const semh::LevelGeom& G = LC.geo;
+      const int n = (int)G.N;
+      const size_t NL3 = (size_t)G.NP * G.NP * G.NP;
+      std::vector<double> A((size_t)n * n, 0.0), Ae(NL3 * NL3);
+      for (size_t e = 0; e < G.E; ++e) {
+        semh::element_matrix(G, G.G, e, Ae.data());
+        for (size_t a = 0; a < NL3; ++a) {
+          const size_t ga = semh::local_to_global(G, e, (int)a);
+          for (size_t b = 0; b < NL3; ++b)
+            A[ga * n + semh::local_to_global(G, e, (int)b)] += Ae[a * NL3 + b];
+        }
+      }
+      for (int g = 0; g < n; ++g)
+        if (g % G.nzn == G.nzn - 1) {
+          for (int k = 0; k < n; ++k) A[(size_t)g * n + k] = A[(size_t)k * n + g] = 0.0;
+          A[(size_t)g * n + g] = 1.0;
+        }
+      std::vector<double> Ai((size_t)n * n);
+      if (!semh::dense_inverse_public(n, A.data(), Ai.data())) throw ArgFail{"coarse operator is singular"};
+      copy_to(c, c->Ainv, Ai);
+    }
+    for (int l = 0; l + 1 < nl; ++l) lanczos(c, l);
+  }
+  if (c->dim == 2) {
+    learned_geometry(c);
+    c->geo_d = nullptr;   // re-uploaded (and element-block inverses recomputed) on next use
+    c->ainv_d = nullptr;
+    if (c->stage_alloc) copy_to(c, c->stage.abar, c->abar_h);
+    if (c->stage_alloc && !c->stage_blob.empty()) {
+      const std::vector<uint8_t> blob = c->stage_blob;
+      learned_load_impl(c, blob.data(), blob.size(), c->stage.enabled ? c->stage_mode : 0);
+    }
+  }
+}
+
+extern "C" {
+
+sem_status sem_mesh_update_surface(sem_ctx* ctx, const double* eta, int refresh_precond) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!eta) throw ArgFail{"null eta"};
+    for (size_t k = 0; k < c->ef_h.size(); ++k)
+      if (!(c->hf_h[k] + eta[k] > 0.0)) throw ArgFail{"h + eta must stay positive"};
+    HK(hipStreamSynchronize(c->st));
+    std::copy(eta, eta + c->ef_h.size(), c->ef_h.begin());
+    update_outer(c);
+    if (refresh_precond) rebuild_levels(c);
+    drop_graphs(c);
+    HK(hipStreamSynchronize(c->st));
+    return SEM_OK;
+  });
+}
+
 sem_status sem_learned_load(sem_ctx* ctx, const void* blob, size_t nbytes, int enable) {
   Ctx* c = C(ctx);
   return guarded(c, [&]() {
-    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
-    semm::Net net;
-    std::string e;
-    if (!semm::net_from_blob(blob, nbytes, net, e)) throw ArgFail{e};
-    DLevel& L = c->lev[0];
-    const int n = L.NP * L.NP;
-    if (n > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
-    if (net.nin != 5 * n || net.nout != n) throw ArgFail{"network sizes do not match the mesh"};
-    if (c->lev.size() < 2) throw ArgFail{"learned stage needs at least two levels"};
-    HK(hipStreamSynchronize(c->st));
-    stage_buffers(c);
-    semm::Stage& s = c->stage;
-    const int NH = semm::NH, KR = semm::pad16(n), N3 = semm::pad16(n), K4 = semm::pad16(4 * n);
-    const size_t E = s.E, Mp = (E + 15) / 16 * 16;
-    auto put16 = [&](uint16_t* dst, const std::vector<uint16_t>& h) {
-      HK(hipMemcpy(dst, h.data(), h.size() * 2, hipMemcpyHostToDevice));
-    };
-    // transposed (output-major) copies for the inference kernel
-    auto transpose = [](const float* W, int rows, int cols) {
-      std::vector<float> T((size_t)rows * cols);
-      for (int r = 0; r < rows; ++r)
-        for (int q = 0; q < cols; ++q) T[(size_t)q * rows + r] = W[(size_t)r * cols + q];
-      return T;
-    };
-    put16(s.W1r, bf16_vec(transpose(net.W1.data(), n, NH).data(), NH, n, NH, KR));
-    put16(s.W2, bf16_vec(transpose(net.W2.data(), NH, NH).data(), NH, NH, NH, NH));
-    put16(s.W3, bf16_vec(transpose(net.W3.data(), NH, n).data(), n, NH, N3, NH));
-    HK(hipMemcpy(s.b2, net.b2.data(), NH * 4, hipMemcpyHostToDevice));
-    std::vector<float> b3(N3, 0.f);
-    std::copy(net.b3.begin(), net.b3.end(), b3.begin());
-    HK(hipMemcpy(s.b3, b3.data(), N3 * 4, hipMemcpyHostToDevice));
-    // Z1geo = Xg W1g + b1 (geometric part of layer 1), computed once per mesh on the GPU
-    std::vector<uint16_t> xg = bf16_vec(c->geo_h.data(), E, 4 * n, Mp, K4);
-    std::vector<uint16_t> w1g = bf16_vec(net.W1.data() + (size_t)n * NH, 4 * n, NH, K4, NH);
-    void *dx = nullptr, *dw = nullptr, *dz = nullptr, *db = nullptr;
-    HK(hipMalloc(&dx, xg.size() * 2));
-    HK(hipMalloc(&dw, w1g.size() * 2));
-    HK(hipMalloc(&dz, Mp * NH * 4));
-    HK(hipMalloc(&db, NH * 4));
-    HK(hipMemcpy(dx, xg.data(), xg.size() * 2, hipMemcpyHostToDevice));
-    HK(hipMemcpy(dw, w1g.data(), w1g.size() * 2, hipMemcpyHostToDevice));
-    HK(hipMemcpy(db, net.b1.data(), NH * 4, hipMemcpyHostToDevice));
-    HK(semm::gemm_bf16((const uint16_t*)dx, K4, 1, (const uint16_t*)dw, NH, 1, (float*)dz, NH,
-                       (int)Mp, NH, K4, 0, c->st));
-    HK(semm::add_bias((float*)dz, (const float*)db, (int)Mp, NH, c->st));
-    HK(hipMemcpyAsync(s.Z1geo, dz, E * NH * 4, hipMemcpyDeviceToDevice, c->st));
-    HK(hipStreamSynchronize(c->st));
-    HK(hipFree(dx));
-    HK(hipFree(dw));
-    HK(hipFree(dz));
-    HK(hipFree(db));
-    s.enabled = (enable & 3) != 0;
-    c->stage_mode = (enable & 3) ? (enable & 3) : 1;
-    drop_graphs(c);
+    learned_load_impl(c, blob, nbytes, enable);
     return SEM_OK;
   });
 }
