@@ -12,8 +12,11 @@ mode with and without the stage, iterations and times on unseen test surfaces, t
 the dominant kernel (operator apply, live HIP-event timing on the library's stream) and the CPU
 oracle timed on a bounded sample of the same workload.
 
+A 3D time series (64 x 64 x 8, P = 6, moving surface, warm starts, frozen preconditioner) is
+reported beside it (--c5-steps, 0 to skip).
+
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload c4] [--prec bf16]
-                       [--no-learned] [--surfaces 4] [--no-cpu] [--no-fp64]
+                       [--no-learned] [--surfaces 4] [--c5-steps 20] [--no-cpu] [--no-fp64]
 """
 import argparse
 import hashlib
@@ -144,6 +147,65 @@ def unseen_surfaces(args, blob, n):
     return rows
 
 
+def c5_series(steps, log_every=5):
+    """3D time series (64 x 64 x 8 hexahedra, P = 6, 7.26M nodes): each step moves the free
+    surface (sem_mesh_update_surface, preconditioner frozen at t = 0), re-evaluates the drifting
+    source at the moved nodes and solves to 1e-10 warm-started from the previous pressure.
+    Mixed precision (FP32 inner, BF16 factors) and plain FP64; solve time timed per step."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2411_14977_amd import binding as B
+    from paper_2411_14977_amd import cases
+    wl = W.c5()
+    xs = B.fine_x_nodes(wl.Nx, wl.P, wl.Lx)
+    ys = B.fine_x_nodes(wl.Ny, wl.P, wl.Ly)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    hfn = lambda a, b: W.bar_depth_3d(a, b, wl.Lx, wl.surface_seed)
+    out = {"workload": "c5: 3D sigma-mapped tank 64x64x8 hexahedra, P=6, levels 6-3-1 then "
+                       "h-levels 32x32, 16x16, 8x8 at P=1 (dense exact), dt = 0.01 s",
+           "n_global": wl.n_global, "steps": steps}
+    for prec in ("bf16", "f64"):
+        t0 = time.perf_counter()
+        s = cases.make_solver(wl, prec=prec)
+        t_setup = time.perf_counter() - t0
+        ms_op = B.sem_time_operator(s.ctx, 0, 0, 20, 0)
+        by_op = B.sem_operator_bytes(s.ctx, 0, 0)
+        x = torch.zeros(s.n_global, dtype=torch.float64, device="cuda")
+        solve_ms, iters, upd_ms = [], [], []
+        for k in range(steps):
+            t = 0.01 * k
+            eta = W.surface_3d(X, Y, t, wl.Lx, wl.surface_seed)
+            torch.cuda.synchronize()
+            u0 = time.perf_counter()
+            s.update_surface(eta)
+            upd_ms.append((time.perf_counter() - u0) * 1e3)
+            xg, yg, zg = s.coords(0)
+            f = W.bumps_3d(xg, yg, zg, t, wl.Lx, wl.rhs_seed, hfn,
+                           lambda a, b: W.surface_3d(a, b, t, wl.Lx, wl.surface_seed))
+            b = s.assemble_rhs(f=torch.tensor(f, dtype=torch.float64, device="cuda"))
+            torch.cuda.synchronize()
+            a0 = time.perf_counter()
+            _, info, _ = s.solve(b, x=x, tol=1e-10)
+            torch.cuda.synchronize()
+            solve_ms.append((time.perf_counter() - a0) * 1e3)
+            iters.append(info.iters)
+            if log_every and k % log_every == 0:
+                log(f"[bench] c5 {prec} step {k}: {info.iters} iterations, {solve_ms[-1]:.1f} ms")
+        s.close()
+        ms = float(np.mean(solve_ms[1:] if steps > 1 else solve_ms))
+        out[prec] = {"setup_s": t_setup, "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
+                     "gdof_per_s": wl.n_global / (ms * 1e-3) / 1e9,
+                     "iters_mean": float(np.mean(iters)), "iters_first": iters[0],
+                     "surface_update_ms": float(np.mean(upd_ms)),
+                     "operator_us": ms_op * 1e3,
+                     "operator_gb_per_s": by_op / (ms_op * 1e-3) / 1e9}
+    out["speedup_mixed_vs_fp64"] = out["f64"]["ms_per_solve"] / out["bf16"]["ms_per_solve"]
+    out["learned_stage"] = "not built for 3D (the stage is 2D; 343-node elements need a wider network)"
+    return out
+
+
 def traffic_from_profiles(kernel_tag):
     """HBM traffic per launch measured by rocprofv3 PMC passes (profiles/*.json), only if
     the kernel source is unchanged since the counters were taken."""
@@ -228,6 +290,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--op-reps", type=int, default=50)
+    ap.add_argument("--c5-steps", type=int, default=20, help="3D time-series steps (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -311,6 +374,13 @@ def main():
         if args.surfaces > 0:
             surf = unseen_surfaces(args, blob, args.surfaces)
 
+    c5 = None
+    if args.c5_steps > 0:
+        c5 = c5_series(args.c5_steps)
+        log(f"[bench] c5 series: mixed {c5['bf16']['ms_per_solve']:.1f} ms "
+            f"({c5['bf16']['iters_mean']:.1f} it), fp64 {c5['f64']['ms_per_solve']:.1f} ms "
+            f"({c5['f64']['iters_mean']:.1f} it)")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample ...")
@@ -326,7 +396,7 @@ def main():
            "learned_skips": info.learned_skips, "oracle_rel_res": res_check,
            "mixed_without_stage": plain_mixed, "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
-           "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,
+           "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf, "c5_series": c5,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
