@@ -349,6 +349,14 @@ def main():
     log(f"[bench] operator {ms_inner * 1e3:.2f} us ({ach:.0f} GB/s, {100 * ach / HBM_PEAK_GBS:.1f}% "
         f"of HBM peak); fp64 outer {ms_outer * 1e3:.2f} us")
     s.close()
+    # calibration for hardware byte counters: three plain 256 MiB device copies (a profiler
+    # reading FETCH_SIZE / WRITE_SIZE of this command scales the operator's counts by these)
+    ca = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+    cb = torch.empty_like(ca)
+    for _ in range(3):
+        cb.copy_(ca)
+    torch.cuda.synchronize()
+    del ca, cb
 
     res_check = None
     try:
