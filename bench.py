@@ -13,7 +13,8 @@ the dominant kernel (operator apply, live HIP-event timing on the library's stre
 oracle timed on a bounded sample of the same workload.
 
 A 3D time series (64 x 64 x 8, P = 6, moving surface, warm starts, frozen preconditioner) is
-reported beside it (--c5-steps, 0 to skip).
+reported beside it (--c5-steps, 0 to skip), and the mixed-precision error table of the
+2048 x 16 tank at tolerances 1e-6, 1e-8, 1e-10 (--no-c3 to skip).
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload c4] [--prec bf16]
                        [--no-learned] [--surfaces 4] [--c5-steps 20] [--no-cpu] [--no-fp64]
@@ -206,6 +207,39 @@ def c5_series(steps, log_every=5):
     return out
 
 
+def c3_error_table():
+    """Mixed-precision error table on the 2048 x 16, P = 8 tank (2.11M nodes): relative error of
+    the FP32-inner solution (factors FP32 and BF16) at tolerances 1e-6, 1e-8, 1e-10 against the
+    FP64 solve to 1e-12, whose own residual is evaluated by the oracle (matrix-free, CPU)."""
+    import torch
+
+    import workloads as W
+    from paper_2411_14977_amd import cases
+    wl = W.c3()
+    s64 = cases.make_solver(wl, prec="f64")
+    rhs = cases.make_rhs(wl, s64)
+    xr, info_r, _ = s64.solve(rhs, tol=1e-12, check=False)
+    out = {"workload": f"{wl.name}: 2D tank {wl.Nx}x{wl.Nz}, P={wl.P}, {wl.n_global} nodes",
+           "reference": {"prec": "f64", "tol": 1e-12, "iters": info_r.iters,
+                         "rel_res": info_r.rel_res}}
+    s64.close()
+    try:
+        out["reference"]["oracle_rel_res"] = oracle_check(wl, xr)
+    except Exception as e:  # pragma: no cover
+        log(f"[bench] oracle check of the c3 reference failed: {e}")
+    nr = float(torch.linalg.norm(xr))
+    for prec in ("f32", "bf16"):
+        s = cases.make_solver(wl, prec=prec)
+        rows = {}
+        for tol in (1e-6, 1e-8, 1e-10):
+            x, info, _ = s.solve(rhs, tol=tol)
+            rows[f"{tol:g}"] = {"iters": info.iters, "rel_res": info.rel_res,
+                                "rel_error_vs_fp64": float(torch.linalg.norm(x - xr)) / nr}
+        out[prec] = rows
+        s.close()
+    return out
+
+
 def traffic_from_profiles(kernel_tag):
     """HBM traffic per launch measured by rocprofv3 PMC passes (profiles/*.json), only if
     the kernel source is unchanged since the counters were taken."""
@@ -291,6 +325,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--c5-steps", type=int, default=20, help="3D time-series steps (0: skip)")
+    ap.add_argument("--no-c3", action="store_true", help="skip the c3 mixed-precision error table")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -382,6 +417,12 @@ def main():
         if args.surfaces > 0:
             surf = unseen_surfaces(args, blob, args.surfaces)
 
+    c3 = None
+    if not args.no_c3:
+        c3 = c3_error_table()
+        log(f"[bench] c3 errors: f32 {[v['rel_error_vs_fp64'] for v in c3['f32'].values()]}, "
+            f"bf16 {[v['rel_error_vs_fp64'] for v in c3['bf16'].values()]}")
+
     c5 = None
     if args.c5_steps > 0:
         c5 = c5_series(args.c5_steps)
@@ -404,7 +445,7 @@ def main():
            "learned_skips": info.learned_skips, "oracle_rel_res": res_check,
            "mixed_without_stage": plain_mixed, "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
-           "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf, "c5_series": c5,
+           "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf, "c3_error_table": c3, "c5_series": c5,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

@@ -178,13 +178,27 @@ __global__ void k_gelu_back(const float* __restrict__ dH, const float* __restric
   }
 }
 
-// out[c] = sum_r D[r][c] (fixed order), c < N
-__global__ void k_colsum(const float* __restrict__ D, int M, int N, int ld, float* __restrict__ out) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= N) return;
+// out[c] = sum_r D[r][c], c < N: 64 columns per block (coalesced rows), 16 row groups summed in
+// a fixed order
+__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ D, int M, int N, int ld,
+                                                 float* __restrict__ out) {
+  __shared__ float part[16][64];
+  const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
+  const int c = blockIdx.x * 64 + cl;
   float s = 0.0f;
-  for (int r = 0; r < M; ++r) s += D[(long)r * ld + c];
-  out[c] = s;
+  if (c < N)
+    for (int r = rg; r < M; r += 16) s += D[(long)r * ld + c];
+  part[rg][cl] = s;
+  __syncthreads();
+  if (rg == 0 && c < N) {
+    float t = 0.0f;
+    for (int k = 0; k < 16; ++k) t += part[k][cl];
+    out[c] = t;
+  }
+}
+
+static void colsum(const float* D, int M, int N, int ld, float* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_colsum, dim3(nblk(N, 64)), dim3(1024), 0, st, D, M, N, ld, out);
 }
 
 // Adam on FP32 master weights; wb = bf16 copy (may be null)
@@ -477,21 +491,21 @@ bool bwd(const Params& p, Acts& a, const float* Tsrc, int M, int nvalid, float* 
   CK(hipGetLastError());
   // dW3 = H2^T dY, db3 = colsum dY
   CK(gemm_bf16(a.H2b, 1, NH, a.dYb, p.N3, 1, gW3, p.N3, NH, p.N3, M, 0, st));
-  hipLaunchKernelGGL(k_colsum, dim3(nblk(p.N3, 128)), dim3(128), 0, st, a.dYf, M, p.N3, p.N3, gb3);
+  colsum(a.dYf, M, p.N3, p.N3, gb3, st);
   // dH2 = dY W3^T; dZ2 = dH2 * gelu'(Z2)
   CK(gemm_bf16(a.dYb, p.N3, 1, p.W3b, 1, p.N3, a.dH2, NH, M, NH, p.N3, 0, st));
   hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH2, a.Z2,
                      a.dZ2f, a.dZ2b, (long)M * NH);
   // dW2 = H1^T dZ2, db2
   CK(gemm_bf16(a.H1b, 1, NH, a.dZ2b, NH, 1, gW2, NH, NH, NH, M, 0, st));
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, st, a.dZ2f, M, NH, NH, gb2);
+  colsum(a.dZ2f, M, NH, NH, gb2, st);
   // dH1 = dZ2 W2^T; dZ1
   CK(gemm_bf16(a.dZ2b, NH, 1, p.W2b, 1, NH, a.dH1, NH, M, NH, NH, 0, st));
   hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH1, a.Z1,
                      a.dZ1f, a.dZ1b, (long)M * NH);
   // dW1 = X^T dZ1, db1
   CK(gemm_bf16(a.Xb, 1, p.K1, a.dZ1b, NH, 1, gW1, NH, p.K1, NH, M, 0, st));
-  hipLaunchKernelGGL(k_colsum, dim3(1), dim3(128), 0, st, a.dZ1f, M, NH, NH, gb1);
+  colsum(a.dZ1f, M, NH, NH, gb1, st);
   CK(hipGetLastError());
   return true;
 }
