@@ -198,18 +198,21 @@ sem_status sem_prolong_add(sem_ctx *ctx, int level, const double *ec, double *xf
 sem_status sem_smooth(sem_ctx *ctx, int level, int pre, const double *b, double *x);
 sem_status sem_coarse_solve(sem_ctx *ctx, const double *b, double *x);
 
-/* Benchmark hook: launch the operator kernel of level l (outer = 1: the fine-level FP64
- * operator of the outer loop; outer = 0: the level's inner-precision operator) reps times on
- * the context's stream, bracketed by HIP events recorded on that stream, and return the
- * average time per launch in *ms_avg.  flush = 1 overwrites a 512 MiB device buffer before
- * every launch (cold caches) and times each launch separately.  Inputs are the level's own
- * work vectors; results are discarded.  Synchronises the stream. */
-sem_status sem_time_operator(sem_ctx *ctx, int level, int outer, int reps, int flush,
+/* Benchmark hook: launch a kernel of level l reps times on the context's stream, bracketed by
+ * HIP events recorded on that stream, and return the average time per launch in *ms_avg.
+ * kind 0: the level's inner-precision operator; kind 1: the fine-level FP64 operator of the
+ * outer loop (level 0 only); kind 2: the level's fused smoother step (operator and Chebyshev
+ * update in one kernel, 2D levels where it fits, else SEM_ERR_ARG), with d read and written.
+ * flush = 1 overwrites a 512 MiB device buffer before every launch (cold caches) and times
+ * each launch separately.  Inputs are the level's own work vectors, which are overwritten;
+ * results are discarded.  Synchronises the stream. */
+sem_status sem_time_operator(sem_ctx *ctx, int level, int kind, int reps, int flush,
                              double *ms_avg);
 
-/* Algorithmic bytes of one operator launch on level l (vectors read + written once, every
- * geometric factor read once), in the precision selected by outer (see sem_time_operator). */
-sem_status sem_operator_bytes(const sem_ctx *ctx, int level, int outer, double *bytes);
+/* Algorithmic bytes of one launch of sem_time_operator's kernel (every vector read or written
+ * once, every geometric factor read once): kind 0, 1: x read, y written; kind 2: x, b, dinv, d
+ * read, x, d written; plus the factors in their storage precision. */
+sem_status sem_operator_bytes(const sem_ctx *ctx, int level, int kind, double *bytes);
 
 /* ---- learned smoothing stage (not in the paper; an addition beside the method) -------------
  * An element-local MLP maps each element's restricted residual r_e = R_e r (R_e: the element

@@ -245,15 +245,15 @@ def sem_coarse_solve(ctx, b, x):
     _check(ctx, lib().sem_coarse_solve(ctx, _ptr(b), _ptr(x)))
 
 
-def sem_time_operator(ctx, level, outer, reps, flush):
+def sem_time_operator(ctx, level, kind, reps, flush):
     ms = ctypes.c_double()
-    _check(ctx, lib().sem_time_operator(ctx, level, outer, reps, flush, ctypes.byref(ms)))
+    _check(ctx, lib().sem_time_operator(ctx, level, kind, reps, flush, ctypes.byref(ms)))
     return ms.value
 
 
-def sem_operator_bytes(ctx, level, outer):
+def sem_operator_bytes(ctx, level, kind):
     b = ctypes.c_double()
-    _check(ctx, lib().sem_operator_bytes(ctx, level, outer, ctypes.byref(b)))
+    _check(ctx, lib().sem_operator_bytes(ctx, level, kind, ctypes.byref(b)))
     return b.value
 
 

@@ -34,6 +34,14 @@ hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, c
 hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                        int Nx, int Nz, int masked, double* dotp, hipStream_t st);
 int apply2d_blocks(int P, int Nx, int Nz, bool dbl);
+// 2D smoother step fused with the operator (P <= 8):  r = b - A xi;  dn = cr dinv r (+ cd d when
+// cd != 0);  d = dn (store_d);  xo = xi + dn, all nodes complete; xi and xo must differ.
+// cheb2d_cpb returns 0 when the fused form does not fit this mesh (then use apply2d and
+// smooth_update).
+int cheb2d_cpb(int P, int Nx, int Nz, bool dbl);
+hipError_t cheb2d(int P, bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
+                  const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
+                  double cr, int store_d, hipStream_t st);
 // 3D operator (element columns (ex, ey) of Nz hexahedra, P <= 8): y = A x complete on return
 // (side buffers Sx, Sy, Sxy are full-size scratch vectors); G in the layout of g3d_layout.
 size_t apply3d_smem(int P, int Nz, bool dbl);

@@ -32,6 +32,14 @@ __device__ __forceinline__ float gload<float, uint16_t>(const uint16_t* p) {
 
 static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
+// dynamic LDS above 64 KB (gfx950: 160 KB per workgroup) needs the kernel's limit raised
+template <typename K>
+static hipError_t allow_lds(K kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
 // (A x)[g] from the column output y and the side buffer S (2D; S null: y is complete)
 template <typename T>
 __device__ __forceinline__ T ax_at(const T* __restrict__ y, const T* __restrict__ S, unsigned g,
@@ -106,17 +114,23 @@ constexpr int line_align() {  // alignment (elements) of an element's offset ez 
   return (P % lds_vec<T>() == 0) ? lds_vec<T>() : ((P % 2 == 0) ? 2 : 1);
 }
 
-// LDS layout of the apply, per element column: input/output column [NP][nzp], two exchange
-// arrays [Nz][NP][NPp], element-top values [Nz][NP]; the region is padded to 16 bytes
+// LDS layout of the apply, per element column: exchange array X1 [Nz][NP][NPp], then exchange
+// array X2 [Nz][NP][NPp] whose space also holds, at other times, the input/output column
+// [NP][nzp] and after it the element-top values [Nz][NP]; the slot is padded to 16 bytes
 inline int apply2d_nzp(int P, int Nz, bool dbl) {
   const int V = dbl ? 2 : 4, nzn = Nz * P + 1;
   return (nzn + V - 1) / V * V;
 }
 
+template <typename I>
+__host__ __device__ constexpr I slot2d_elems(I NP, I Nz, I nzp, I V) {
+  const I NPp = (NP + V - 1) / V * V, ex = Nz * NP * NPp;
+  const I col = NP * nzp + Nz * NP;
+  return (ex + (col > ex ? col : ex) + V - 1) / V * V;
+}
+
 static size_t apply2d_slot(int P, int Nz, bool dbl) {  // elements per column
-  const int NP = P + 1, V = dbl ? 2 : 4, NPp = (NP + V - 1) / V * V;
-  const size_t n = (size_t)NP * apply2d_nzp(P, Nz, dbl) + 2 * (size_t)Nz * NP * NPp + (size_t)Nz * NP;
-  return (n + V - 1) / V * V;
+  return slot2d_elems<size_t>(P + 1, Nz, apply2d_nzp(P, Nz, dbl), dbl ? 2 : 4);
 }
 
 size_t apply2d_smem(int P, int Nz, bool dbl) { return apply2d_slot(P, Nz, dbl) * (dbl ? 8 : 4); }
@@ -187,52 +201,33 @@ __device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int n
     for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(&raw[f * NP + j]);
 }
 
-// One workgroup per cpb element columns; within a column, thread t = ez * NP + q has two roles in
-// element ez: the vertical line i = q (sigma-direction contractions, geometric factors) and the
-// horizontal row j = q (x-direction contractions).  The roles swap data through LDS: u_r row ->
-// line, w_r line -> row, D_r^T w_r row -> line.  All contractions run in registers against
-// compile-time D (even-odd form).  DOT: also the block's part of x . (A x) into dotp[block]
-// (each node's product counted once: its column-output part and its side-buffer part are owned
-// by different blocks, whose sum is the whole entry).
-template <int P, typename T, typename TG, bool DOT = false>
-__global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __restrict__ y,
-                                                  T* __restrict__ S, const TG* __restrict__ G,
-                                                  int Nx, int Nz, int masked, int cpb, int remap,
-                                                  double* __restrict__ dotp) {
+// The operator on one element column (slot) of a workgroup.  Thread t = ez * NP + q of the slot
+// has two roles in element ez: the vertical line i = q (sigma-direction contractions, geometric
+// factors) and the horizontal row j = q (x-direction contractions).  The roles swap data through
+// LDS: u_r row -> line, w_r line -> row, D_r^T w_r row -> line.  All contractions run in
+// registers against compile-time D (even-odd form).  On return (after a barrier) the slot's LDS
+// column su[l * nzp + iz] holds the column's part of (A x) on its lines l = 0..P, with the faces
+// between vertically stacked elements summed and, when masked, the Dirichlet top node equal to
+// x; xin[l] holds x(line l, node t) for t < nzn.  Every thread of the block calls this.
+template <int P, typename T, typename TG>
+__device__ __forceinline__ void column_apply(const T* __restrict__ xc, const TG* __restrict__ G,
+                                             int ex, int nthr, int t, bool act, int Nz, int nzn,
+                                             int nzp, int masked, T* base, T (&xin)[P + 1]) {
   constexpr int NP = P + 1;
   constexpr int V = lds_vec<T>();
   constexpr int NPp = (NP + V - 1) / V * V;
   constexpr int AL = line_align<P, T>();
-  const int nzn = Nz * P + 1;
-  const int nzp = (nzn + V - 1) / V * V;
-  const int nthr = NP * Nz;
-  int bx = blockIdx.x;
-  if (remap) {  // consecutive columns on the same XCD (blocks are dealt round-robin to 8 XCDs)
-    const int per = gridDim.x >> 3;
-    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  }
-  const int cs = threadIdx.x / nthr;       // column slot of this thread
-  const int t = threadIdx.x - cs * nthr;   // thread within the column
-  const int ex = bx * cpb + cs;
-  const bool valid = cs < cpb && ex < Nx;  // uniform per column slot
-  const int slot = (NP * nzp + 2 * Nz * NP * NPp + Nz * NP + V - 1) / V * V;
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* su = reinterpret_cast<T*>(smem_raw) + (valid ? cs : 0) * slot;  // [NP][nzp] column
-  T* X1 = su + NP * nzp;                    // [Nz][NP(i)][NPp(j)]: u_r, later D_r^T w_r
-  T* X2 = X1 + Nz * NP * NPp;               // [Nz][NP(j)][NPp(i)]: w_r
-  T* stp = X2 + Nz * NP * NPp;              // [Nz][NP] element-top values
-  // column-relative 32-bit offsets from per-column base pointers
-  const T* xc = x + (size_t)(valid ? ex : 0) * P * nzn;
-  T* yc = y + (size_t)(valid ? ex : 0) * P * nzn;
-  const bool act = valid;
   const int q = t % NP;
   const int ez = t / NP;
+  T* X1 = base;                    // [Nz][NP(i)][NPp(j)]: u_r, later D_r^T w_r
+  T* X2 = X1 + Nz * NP * NPp;      // [Nz][NP(j)][NPp(i)]: w_r (phases 3-4)
+  T* su = X2;                      // [NP][nzp] column: input (phases 1-2), output (phase 6)
+  T* stp = X2 + NP * nzp;          // [Nz][NP] element-top values (phases 5-6)
 
   // every global load of the block is issued before the first LDS store
   T g[3][NP];
   if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
-  T xin[NP];
-  if (valid && t < nzn) {
+  if (act && t < nzn) {
 #pragma unroll
     for (int l = 0; l < NP; ++l) xin[l] = xc[l * nzn + t];
 #pragma unroll
@@ -304,6 +299,43 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
     if (topel) ocol[P] = masked ? xtop : v[P];
   }
   __syncthreads();
+}
+
+// One workgroup per cpb element columns (column_apply per slot).  Output: lines 0..P-1 of each
+// column to y, line P to the side buffer S of the right neighbour (to y for the last column).
+// DOT: also the block's part of x . (A x) into dotp[block] (each node's product counted once:
+// its column-output part and its side-buffer part are owned by different blocks, whose sum is
+// the whole entry).
+template <int P, typename T, typename TG, bool DOT = false>
+__global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __restrict__ y,
+                                                  T* __restrict__ S, const TG* __restrict__ G,
+                                                  int Nx, int Nz, int masked, int cpb, int remap,
+                                                  double* __restrict__ dotp) {
+  constexpr int NP = P + 1;
+  constexpr int V = lds_vec<T>();
+  constexpr int NPp = (NP + V - 1) / V * V;
+  const int nzn = Nz * P + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int nthr = NP * Nz;
+  int bx = blockIdx.x;
+  if (remap) {  // consecutive columns on the same XCD (blocks are dealt round-robin to 8 XCDs)
+    const int per = gridDim.x >> 3;
+    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int cs = threadIdx.x / nthr;       // column slot of this thread
+  const int t = threadIdx.x - cs * nthr;   // thread within the column
+  const int ex = bx * cpb + cs;
+  const bool valid = cs < cpb && ex < Nx;  // uniform per column slot
+  const int slot = slot2d_elems<int>(NP, Nz, nzp, V);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* base = reinterpret_cast<T*>(smem_raw) + (valid ? cs : 0) * slot;
+  const T* su = base + Nz * NP * NPp;  // output column of this slot
+  // column-relative 32-bit offsets from per-column base pointers
+  const T* xc = x + (size_t)(valid ? ex : 0) * P * nzn;
+  T* yc = y + (size_t)(valid ? ex : 0) * P * nzn;
+  T xin[NP];
+  column_apply<P, T, TG>(xc, G, ex, nthr, t, valid, Nz, nzn, nzp, masked, base, xin);
+
   double part = 0.0;
   if (valid && t < nzn) {
 #pragma unroll
@@ -328,6 +360,129 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
   }
 }
 
+// One smoother step fused with the operator (2D):  r = b - A xi;  dn = cr dinv r (+ cd d);
+// d = dn (store_d);  xo = xi + dn.  Workgroup bx owns element columns bx cpb .. bx cpb + cpb - 1
+// (slots 1..cpb) and recomputes the column to their left (slot 0, the halo), so the vertical
+// line shared with it is summed in LDS and every owned node gets its whole (A x) without a side
+// buffer or a second kernel.  A column owns its lines 0..P-1, the last column also line P.
+// xi and xo must be different vectors (other workgroups still read xi).
+template <int P, typename T, typename TG>
+__global__ __launch_bounds__(1024) void k_cheb2d(const T* __restrict__ xi, T* __restrict__ xo,
+                                                 T* __restrict__ d, const T* __restrict__ b,
+                                                 const T* __restrict__ dinv,
+                                                 const TG* __restrict__ G, int Nx, int Nz,
+                                                 int masked, int cpb, int remap, T cd, T cr,
+                                                 int store_d) {
+  constexpr int NP = P + 1;
+  constexpr int V = lds_vec<T>();
+  constexpr int NPp = (NP + V - 1) / V * V;
+  const int nzn = Nz * P + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int nthr = NP * Nz;
+  int bx = blockIdx.x;
+  if (remap) {
+    const int per = gridDim.x >> 3;
+    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int cs = threadIdx.x / nthr;  // slot 0: halo column, slots 1..cpb: owned columns
+  const int t = threadIdx.x - cs * nthr;
+  const int ex = bx * cpb + cs - 1;
+  const bool valid = cs <= cpb && ex >= 0 && ex < Nx;
+  const int slot = slot2d_elems<int>(NP, Nz, nzp, V);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* base = reinterpret_cast<T*>(smem_raw) + (valid ? cs : 0) * slot;
+  const T* xc = xi + (size_t)(valid ? ex : 0) * P * nzn;
+  T xin[NP];
+  column_apply<P, T, TG>(xc, G, valid ? ex : 0, nthr, t, valid, Nz, nzn, nzp, masked, base, xin);
+
+  if (cs >= 1 && valid && t < nzn) {
+    const T* su = base + Nz * NP * NPp;  // this column's part of A x
+    const T* sl = su - slot;             // the left column's (slot cs - 1, valid when ex > 0)
+    const bool left = ex > 0 && !(masked && t == nzn - 1);
+    const size_t g0 = (size_t)ex * P * nzn + t;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      if (l == P && ex != Nx - 1) break;
+      T ax = su[l * nzp + t];
+      if (l == 0 && left) ax += sl[P * nzp + t];
+      const size_t g = g0 + (size_t)l * nzn;
+      const T r = b[g] - ax;
+      T dn = cr * dinv[g] * r;
+      if (cd != (T)0) dn += cd * d[g];
+      if (store_d) d[g] = dn;
+      xo[g] = xin[l] + dn;
+    }
+  }
+}
+
+// owned columns per workgroup of the fused step.  Measured on the 1024 x 16 and 2048 x 16 column
+// meshes (P = 8, 4, 2): four owned columns when two such workgroups fit a CU's 160 KB of LDS and
+// the workgroup count is a multiple of 8 (XCD-aware order) and at least 256, else two (FP64 at
+// P = 8: 2 is faster than 4); odd counts (no XCD order) are the slowest.  One owned column (the
+// halo doubles the work) still beats operator + update.  0: the fused form does not fit.
+int cheb2d_cpb(int P, int Nx, int Nz, bool dbl) {
+  const int nthr = (P + 1) * Nz;
+  const size_t sm = apply2d_smem(P, Nz, dbl), lds = 160 * 1024;
+  auto fits = [&](int c) { return (c + 1) * nthr <= 1024 && (c + 1) * sm <= lds; };
+  const int b4 = (Nx + 3) / 4;
+  if (fits(4) && 2 * 5 * sm <= lds && b4 % 8 == 0 && b4 >= 256) return 4;
+  if (fits(2)) return 2;
+  if (fits(1)) return 1;
+  return 0;
+}
+
+template <int P, typename T, typename TG>
+static hipError_t launch_cheb2d(const void* xi, void* xo, void* d, const void* b, const void* dinv,
+                                const void* G, int Nx, int Nz, int masked, double cd, double cr,
+                                int store_d, int cpb, hipStream_t st) {
+  const bool dbl = sizeof(T) == 8;
+  if (cpb <= 0) return hipErrorInvalidValue;
+  const int nthr = (P + 1) * Nz;
+  const int threads = (((cpb + 1) * nthr + 63) / 64) * 64;
+  const int blocks = (Nx + cpb - 1) / cpb;
+  const size_t smem = apply2d_smem(P, Nz, dbl) * (cpb + 1);
+  if (threads > 1024 || smem > 160 * 1024) return hipErrorInvalidValue;
+  const int remap = (blocks % 8 == 0) ? 1 : 0;
+  hipError_t e = allow_lds(k_cheb2d<P, T, TG>, smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cheb2d<P, T, TG>), dim3(blocks), dim3(threads), smem, st, (const T*)xi,
+                     (T*)xo, (T*)d, (const T*)b, (const T*)dinv, (const TG*)G, Nx, Nz, masked, cpb,
+                     remap, (T)cd, (T)cr, store_d);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t cheb2d_p(bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
+                           const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
+                           double cr, int store_d, int cpb, hipStream_t st) {
+  if (dbl)
+    return launch_cheb2d<P, double, double>(xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr,
+                                            store_d, cpb, st);
+  if (gt == G_BF16)
+    return launch_cheb2d<P, float, uint16_t>(xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr,
+                                             store_d, cpb, st);
+  return launch_cheb2d<P, float, float>(xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d,
+                                        cpb, st);
+}
+
+hipError_t cheb2d(int P, bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
+                  const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
+                  double cr, int store_d, hipStream_t st) {
+  const int cpb = cheb2d_cpb(P, Nx, Nz, dbl);
+  if (xi == xo) return hipErrorInvalidValue;
+  switch (P) {
+    case 1: return cheb2d_p<1>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    case 2: return cheb2d_p<2>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    case 3: return cheb2d_p<3>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    case 4: return cheb2d_p<4>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    case 5: return cheb2d_p<5>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    case 6: return cheb2d_p<6>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    case 7: return cheb2d_p<7>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    case 8: return cheb2d_p<8>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int P, typename T, typename TG, bool DOT = false>
 static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G, int Nx, int Nz,
                                  int masked, double* dotp, hipStream_t st) {
@@ -338,6 +493,8 @@ static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G,
   const int blocks = (Nx + cpb - 1) / cpb;
   const size_t smem = apply2d_smem(P, Nz, dbl) * cpb;
   const int remap = (blocks % 8 == 0) ? 1 : 0;
+  hipError_t e = allow_lds(k_apply2d<P, T, TG, DOT>, smem);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_apply2d<P, T, TG, DOT>), dim3(blocks), dim3(threads), smem, st,
                      (const T*)x, (T*)y, (T*)S, (const TG*)G, Nx, Nz, masked, cpb, remap, dotp);
   return hipGetLastError();
@@ -653,10 +810,12 @@ static hipError_t launch_apply3d(const void* x, void* y, void* Sx, void* Sy, voi
   const bool dbl = sizeof(T) == 8;
   const int nthr = (P + 1) * (P + 1) * Nz;
   const int threads = ((nthr + 63) / 64) * 64;
+  hipError_t e = allow_lds(k_apply3d<P, T, TG>, apply3d_smem(P, Nz, dbl));
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_apply3d<P, T, TG>), dim3(Nx * Ny), dim3(threads), apply3d_smem(P, Nz, dbl),
                      st, (const T*)x, (T*)y, (T*)Sx, (T*)Sy, (T*)Sxy, (const TG*)G, Nx, Ny, Nz,
                      masked);
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (Nx > 1 || Ny > 1) {
     const unsigned nyn = Ny * P + 1, nzn = Nz * P + 1;
@@ -1072,6 +1231,10 @@ hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const 
                       int use_ax, void* rc, const double* J, int Nx, int Nz, int Pf, int Pc,
                       int masked, hipStream_t st) {
   const size_t smem = restrict2d_smem(Pf, Pc, Nz, dbl);
+  const hipError_t e = dbl     ? allow_lds(k_restrict2d<double, double>, smem)
+                       : dbl_c ? allow_lds(k_restrict2d<float, double>, smem)
+                               : allow_lds(k_restrict2d<float, float>, smem);
+  if (e != hipSuccess) return e;
   if (dbl)
     hipLaunchKernelGGL((k_restrict2d<double, double>), dim3(Nx), dim3(256), smem, st,
                        (const double*)b, (const double*)y, (const double*)S, use_ax,
@@ -1129,6 +1292,10 @@ size_t prolong2d_smem(int Pf, int Pc, int Nz, bool dbl) {
 hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
                      int Nz, int Pf, int Pc, hipStream_t st) {
   const size_t smem = prolong2d_smem(Pf, Pc, Nz, dbl);
+  const hipError_t e = dbl     ? allow_lds(k_prolong2d<double, double>, smem)
+                       : dbl_c ? allow_lds(k_prolong2d<float, double>, smem)
+                               : allow_lds(k_prolong2d<float, float>, smem);
+  if (e != hipSuccess) return e;
   if (dbl)
     hipLaunchKernelGGL((k_prolong2d<double, double>), dim3(Nx), dim3(256), smem, st,
                        (const double*)ec, (double*)xf, J, Nx, Nz, Pf, Pc);

@@ -37,6 +37,9 @@ struct DLevel {
   void* dinv = nullptr;       // inverse assembled diagonal
   double* J = nullptr;        // prolongation from the next coarser level, (P+1) x (Pc+1)
   void *x = nullptr, *b = nullptr, *d = nullptr, *y = nullptr, *S = nullptr;
+  // 2D smoothed levels where the fused smoother step fits: the second solution vector; each
+  // fused step reads x and writes xalt, then the two swap (x is always the current iterate)
+  void* xalt = nullptr;
   size_t nS = 0;
   double lam = 0.0;
   // 3D: side buffers of the operator (completed into y by the face fix-up; S stays null) and
@@ -191,6 +194,20 @@ void apply_outer(Ctx* c, const double* x, int masked) {
     HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Nx, L.Nz, masked, c->st));
 }
 
+// one smoother step from the current x:  r = b - A x;  d = cd d + cr dinv r;  x += d
+void smooth_step(Ctx* c, int l, double cd, double cr, int store_d) {
+  DLevel& L = c->lev[l];
+  if (L.xalt) {  // operator and update in one kernel, into the other vector
+    HK(semk::cheb2d(L.P, L.dbl, L.gt, L.x, L.xalt, L.d, L.b, L.dinv, L.G, L.Nx, L.Nz, c->masked,
+                    cd, cr, store_d, c->st));
+    std::swap(L.x, L.xalt);
+    return;
+  }
+  apply_level(c, l, L.x, c->masked);
+  HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P, cd, cr,
+                         semk::SU_AX, store_d, c->st));
+}
+
 // pre- or post-smoothing on level l; resid (post-smoothing only): the residual of the current x,
 // already known to the caller, which saves the first operator apply
 void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
@@ -206,10 +223,13 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
         continue;
       }
       const bool given = !pre && s == 0 && resid;
-      if (!fz && !given) apply_level(c, l, L.x, c->masked);
+      if (!fz && !given) {
+        smooth_step(c, l, 0.0, d.jacobi_omega, 0);
+        continue;
+      }
       HK(semk::smooth_update(L.dbl, L.x, L.d, given ? resid : L.b, L.dinv, L.y, L.S, L.N, L.nzn,
-                             L.P, 0.0, d.jacobi_omega,
-                             fz ? semk::SU_ZERO : (given ? semk::SU_RESID : semk::SU_AX), 0, c->st));
+                             L.P, 0.0, d.jacobi_omega, fz ? semk::SU_ZERO : semk::SU_RESID, 0,
+                             c->st));
     }
     return;
   }
@@ -219,21 +239,18 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
   double rho = 1.0 / sigma1;
   const int k = d.cheb_degree;
   const bool given = !pre && resid;
-  if (!pre && !given) apply_level(c, l, L.x, c->masked);
-  if (pre && l == 0 && c->vin64)
+  if (!pre && !given)
+    smooth_step(c, l, 0.0, 1.0 / theta, k > 1 ? 1 : 0);
+  else if (pre && l == 0 && c->vin64)
     HK(semk::smooth_first64(L.dbl, L.x, L.d, L.b, c->vin64, L.dinv, L.N, 1.0 / theta,
                             k > 1 ? 1 : 0, c->st));
   else
     HK(semk::smooth_update(L.dbl, L.x, L.d, given ? resid : L.b, L.dinv, L.y, L.S, L.N, L.nzn,
-                           L.P, 0.0, 1.0 / theta,
-                           pre ? semk::SU_ZERO : (given ? semk::SU_RESID : semk::SU_AX),
+                           L.P, 0.0, 1.0 / theta, pre ? semk::SU_ZERO : semk::SU_RESID,
                            k > 1 ? 1 : 0, c->st));
   for (int j = 1; j < k; ++j) {
     const double rho_new = 1.0 / (2.0 * sigma1 - rho);
-    apply_level(c, l, L.x, c->masked);
-    HK(semk::smooth_update(L.dbl, L.x, L.d, L.b, L.dinv, L.y, L.S, L.N, L.nzn, L.P,
-                           rho_new * rho, 2.0 * rho_new / delta, semk::SU_AX, j + 1 < k ? 1 : 0,
-                           c->st));
+    smooth_step(c, l, rho_new * rho, 2.0 * rho_new / delta, j + 1 < k ? 1 : 0);
     rho = rho_new;
   }
 }
@@ -941,6 +958,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     L.y = dalloc(c, L.N * eb);
     L.nS = (size_t)(c->Nx + 1) * L.nzn;
     L.S = dalloc(c, L.nS * eb);
+    if (!coarsest && L.P <= 8 && semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl) > 0)
+      L.xalt = dalloc(c, L.N * eb);
   }
   for (int l = 0; l + 1 < nl; ++l) {
     DLevel& F = c->lev[l];
@@ -1854,14 +1873,16 @@ sem_status sem_learned_stage(sem_ctx* ctx, const double* b, double* x, int* acce
   });
 }
 
-sem_status sem_time_operator(sem_ctx* ctx, int level, int outer, int reps, int flush,
+sem_status sem_time_operator(sem_ctx* ctx, int level, int kind, int reps, int flush,
                              double* ms_avg) {
   Ctx* c = C(ctx);
   return guarded(c, [&]() {
     if (level < 0 || level >= (int)c->lev.size()) throw ArgFail{"bad level"};
-    if (outer && level != 0) throw ArgFail{"the outer operator lives on level 0"};
+    if (kind < 0 || kind > 2) throw ArgFail{"bad kind"};
+    if (kind == 1 && level != 0) throw ArgFail{"the outer operator lives on level 0"};
     if (reps < 1 || !ms_avg) throw ArgFail{"bad reps / output"};
     DLevel& L = c->lev[level];
+    if (kind == 2 && !L.xalt) throw ArgFail{"this level has no fused smoother step"};
     hipEvent_t e0, e1;
     HK(hipEventCreate(&e0));
     HK(hipEventCreate(&e1));
@@ -1870,7 +1891,8 @@ sem_status sem_time_operator(sem_ctx* ctx, int level, int outer, int reps, int f
     if (flush) HK(hipMalloc(&junk, fbytes));
     double total = 0.0;
     auto launch = [&]() {
-      if (outer) apply_outer(c, c->po, c->masked);
+      if (kind == 1) apply_outer(c, c->po, c->masked);
+      else if (kind == 2) smooth_step(c, level, 0.5, 1e-3, 1);
       else apply_level(c, level, L.x, c->masked);
     };
     launch();  // warm-up
@@ -1902,17 +1924,20 @@ sem_status sem_time_operator(sem_ctx* ctx, int level, int outer, int reps, int f
   });
 }
 
-sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int outer, double* bytes) {
+sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int kind, double* bytes) {
   const Ctx* c = C(ctx);
-  if (!c || !bytes || level < 0 || level >= (int)c->lev.size() || (outer && level != 0))
+  if (!c || !bytes || level < 0 || level >= (int)c->lev.size() || kind < 0 || kind > 2 ||
+      (kind == 1 && level != 0))
     return SEM_ERR_ARG;
   const DLevel& L = c->lev[level];
-  const bool dbl = outer ? true : L.dbl;
-  const semk::GType gt = outer ? semk::G_F64 : L.gt;
+  if (kind == 2 && !L.xalt) return SEM_ERR_ARG;
+  const bool dbl = kind == 1 ? true : L.dbl;
+  const semk::GType gt = kind == 1 ? semk::G_F64 : L.gt;
   const double sv = dbl ? 8.0 : 4.0;
   const double sg = gt == semk::G_F64 ? 8.0 : (gt == semk::G_F32 ? 4.0 : 2.0);
   const double nloc = (double)L.geo.E * std::pow((double)L.NP, c->dim);
-  *bytes = 2.0 * sv * L.N + L.geo.nfields * sg * nloc;
+  const double nvec = kind == 2 ? 6.0 : 2.0;  // step: x, b, dinv, d read; x, d written
+  *bytes = nvec * sv * L.N + L.geo.nfields * sg * nloc;
   return SEM_OK;
 }
 

@@ -45,6 +45,9 @@ CASES = {
     "c2": W.c2(),                                                         # 256 x 8, P = 6
     "single_col": W.tank(1, 2, 4, Lx=0.3, name="single_col"),
     "one_layer": W.tank(9, 1, 6, Lx=0.9, name="one_layer"),
+    # tall columns: at P = 8 a workgroup holds only one column (no fused smoother step, LDS
+    # above 64 KB); the coarser levels use the fused step with two owned columns
+    "tall": W.tank(3, 60, 8, Lx=0.3, name="tall"),
 }
 
 _oracle = {}
@@ -136,9 +139,9 @@ def test_coarse_solve_exact(name):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["tank8", "ragged", "tall"])
 @pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
-def test_smoothers(smoother):
-    name = "tank8"
+def test_smoothers(smoother, name):
     wl = CASES[name]
     H_ = oc.hierarchy(wl, smoother=smoother)
     pmg.estimate_lambdas(H_)
@@ -168,7 +171,7 @@ def test_lanczos_estimate(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "ragged", "tank8", "c2"])
+@pytest.mark.parametrize("name", ["c1", "ragged", "tank8", "c2", "tall"])
 def test_vcycle(name):
     print(f"[gpu] vcycle parity {name}", flush=True)
     H_ = oracle_h(name)
@@ -309,3 +312,28 @@ def test_single_level_hierarchy():
     assert info.iters <= 2   # the V-cycle is the exact inverse
     assert rel(H(x), assemble.solve_direct(A, b)) < 1e-11
     s.close()
+
+
+def test_benchmark_hooks():
+    wl = CASES["tank8"]
+    s = lib_solver("tank8", prec="bf16")
+    N, E, n = s.n_global, wl.Nx * wl.Nz, (wl.P + 1) ** 2
+    assert B.sem_operator_bytes(s.ctx, 0, 0) == 2 * 4 * N + 3 * 2 * E * n
+    assert B.sem_operator_bytes(s.ctx, 0, 2) == 6 * 4 * N + 3 * 2 * E * n
+    assert B.sem_operator_bytes(s.ctx, 0, 1) == 2 * 8 * N + 3 * 8 * E * n
+    for kind in (0, 1, 2):
+        assert B.sem_time_operator(s.ctx, 0, kind, 3, 0) > 0
+    with pytest.raises(B.SemError):
+        B.sem_time_operator(s.ctx, 1, 1, 1, 0)   # the outer operator lives on level 0
+    # the hooks overwrite work vectors only: a solve afterwards is unaffected
+    m = oc.fine_mesh(wl)
+    b = oc.rhs(wl, m)
+    x, info, _ = s.solve(T(b), tol=1e-10)
+    assert np.linalg.norm(H(x) - assemble.solve_direct(assemble.assemble_operator(m), b)) \
+        <= 1e-8 * np.linalg.norm(H(x))
+    s.close()
+    t = lib_solver("tall")
+    with pytest.raises(B.SemError):
+        B.sem_time_operator(t.ctx, 0, 2, 1, 0)   # P = 8 columns of 60 elements: no fused step
+    assert B.sem_time_operator(t.ctx, 1, 2, 1, 0) > 0
+    t.close()
