@@ -42,6 +42,22 @@ int cheb2d_cpb(int P, int Nx, int Nz, bool dbl);
 hipError_t cheb2d(int P, bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
                   const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
                   double cr, int store_d, hipStream_t st);
+int cheb2d_blocks(int P, int Nx, int Nz, bool dbl);  // workgroups of the fused kernels (0: none)
+// Element-local corrections of the learned stage, line-major per element column: value (i, j)
+// of element (ex, ez) at [((ex (P+1) + i) Nz + ez) (P+1) + j], so that the values along a
+// vertical node line of a column are contiguous.
+__host__ __device__ inline long ce_index(int ex, int i, int ez, int j, int Nz, int NP) {
+  return (((long)ex * NP + i) * Nz + ez) * NP + j;
+}
+// learned stage (2D, where cheb2d_cpb > 0): c = average of the element corrections CE (layout
+// of ce_index) at every node (0 on the Dirichlet surface when masked), q = A c complete, and
+// each workgroup's part of c . q in dotp[0 .. cheb2d_blocks)
+hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* q, const void* G,
+                     int Nx, int Nz, int masked, double* dotp, hipStream_t st);
+// residual r = b - A x, complete at every node (2D); fused with the operator where cheb2d_cpb
+// allows, else apply2d into the scratch y, S and an element-wise pass.  r must differ from x.
+hipError_t resid2d(int P, bool dbl, GType gt, const void* x, void* r, const void* b,
+                   const void* G, int Nx, int Nz, int masked, void* y, void* S, hipStream_t st);
 // 3D operator (element columns (ex, ey) of Nz hexahedra, P <= 8): y = A x complete on return
 // (side buffers Sx, Sy, Sxy are full-size scratch vectors); G in the layout of g3d_layout.
 size_t apply3d_smem(int P, int Nz, bool dbl);

@@ -208,11 +208,12 @@ __device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int n
 // registers against compile-time D (even-odd form).  On return (after a barrier) the slot's LDS
 // column su[l * nzp + iz] holds the column's part of (A x) on its lines l = 0..P, with the faces
 // between vertically stacked elements summed and, when masked, the Dirichlet top node equal to
-// x; xin[l] holds x(line l, node t) for t < nzn.  Every thread of the block calls this.
-template <int P, typename T, typename TG>
-__device__ __forceinline__ void column_apply(const T* __restrict__ xc, const TG* __restrict__ G,
-                                             int ex, int nthr, int t, bool act, int Nz, int nzn,
-                                             int nzp, int masked, T* base, T (&xin)[P + 1]) {
+// x; xin[l] holds x(line l, node t) for t < nzn, as filled by ldx(xin) (called when act and
+// t < nzn).  Every thread of the block calls this.
+template <int P, typename T, typename TG, typename Ldx, typename Pre>
+__device__ __forceinline__ void column_apply(Ldx&& ldx, const TG* __restrict__ G, int ex,
+                                             int nthr, int t, bool act, int Nz, int nzn, int nzp,
+                                             int masked, T* base, T (&xin)[P + 1], Pre&& pre) {
   constexpr int NP = P + 1;
   constexpr int V = lds_vec<T>();
   constexpr int NPp = (NP + V - 1) / V * V;
@@ -224,12 +225,13 @@ __device__ __forceinline__ void column_apply(const T* __restrict__ xc, const TG*
   T* su = X2;                      // [NP][nzp] column: input (phases 1-2), output (phase 6)
   T* stp = X2 + NP * nzp;          // [Nz][NP] element-top values (phases 5-6)
 
-  // every global load of the block is issued before the first LDS store
+  // every global load of the block (the caller's through pre()) is issued before the first LDS
+  // store
   T g[3][NP];
   if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
+  if (act && t < nzn) ldx(xin);
+  pre();
   if (act && t < nzn) {
-#pragma unroll
-    for (int l = 0; l < NP; ++l) xin[l] = xc[l * nzn + t];
 #pragma unroll
     for (int l = 0; l < NP; ++l) su[l * nzp + t] = xin[l];
   }
@@ -334,7 +336,12 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
   const T* xc = x + (size_t)(valid ? ex : 0) * P * nzn;
   T* yc = y + (size_t)(valid ? ex : 0) * P * nzn;
   T xin[NP];
-  column_apply<P, T, TG>(xc, G, ex, nthr, t, valid, Nz, nzn, nzp, masked, base, xin);
+  column_apply<P, T, TG>(
+      [&](T(&v)[NP]) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) v[l] = xc[l * nzn + t];
+      },
+      G, ex, nthr, t, valid, Nz, nzn, nzp, masked, base, xin, [] {});
 
   double part = 0.0;
   if (valid && t < nzn) {
@@ -365,8 +372,9 @@ __global__ __launch_bounds__(1024) void k_apply2d(const T* __restrict__ x, T* __
 // (slots 1..cpb) and recomputes the column to their left (slot 0, the halo), so the vertical
 // line shared with it is summed in LDS and every owned node gets its whole (A x) without a side
 // buffer or a second kernel.  A column owns its lines 0..P-1, the last column also line P.
-// xi and xo must be different vectors (other workgroups still read xi).
-template <int P, typename T, typename TG>
+// xi and xo must be different vectors (other workgroups still read xi).  MODE 1 computes only
+// the residual: xo = b - A xi (dinv, d, cd, cr unused).
+template <int P, typename T, typename TG, int MODE = 0>
 __global__ __launch_bounds__(1024) void k_cheb2d(const T* __restrict__ xi, T* __restrict__ xo,
                                                  T* __restrict__ d, const T* __restrict__ b,
                                                  const T* __restrict__ dinv,
@@ -392,25 +400,59 @@ __global__ __launch_bounds__(1024) void k_cheb2d(const T* __restrict__ xi, T* __
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* base = reinterpret_cast<T*>(smem_raw) + (valid ? cs : 0) * slot;
   const T* xc = xi + (size_t)(valid ? ex : 0) * P * nzn;
+  // FP32: the owned nodes' b, dinv, d are loaded together with the operator's inputs (in FP64
+  // the extra registers would spill; there they are loaded in the epilogue)
+  constexpr bool PF = sizeof(T) == 4;
+  const bool own = cs >= 1 && valid && t < nzn;
+  const int nl = (ex == Nx - 1) ? NP : P;  // owned lines of this column
+  const size_t g0 = (size_t)(valid ? ex : 0) * P * nzn + t;
+  T pb[NP], pdi[NP], pd[NP];
+  auto load_own = [&] {
+    if (own) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        if (l < nl) {
+          const size_t g = g0 + (size_t)l * nzn;
+          pb[l] = b[g];
+          if constexpr (MODE == 0) {
+            pdi[l] = dinv[g];
+            pd[l] = cd != (T)0 ? d[g] : (T)0;
+          }
+        }
+      }
+    }
+  };
   T xin[NP];
-  column_apply<P, T, TG>(xc, G, valid ? ex : 0, nthr, t, valid, Nz, nzn, nzp, masked, base, xin);
+  column_apply<P, T, TG>(
+      [&](T(&v)[NP]) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) v[l] = xc[l * nzn + t];
+      },
+      G, valid ? ex : 0, nthr, t, valid, Nz, nzn, nzp, masked, base, xin, [&] {
+                           if constexpr (PF) load_own();
+                         });
+  if constexpr (!PF) load_own();
 
-  if (cs >= 1 && valid && t < nzn) {
+  if (own) {
     const T* su = base + Nz * NP * NPp;  // this column's part of A x
     const T* sl = su - slot;             // the left column's (slot cs - 1, valid when ex > 0)
     const bool left = ex > 0 && !(masked && t == nzn - 1);
-    const size_t g0 = (size_t)ex * P * nzn + t;
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
-      if (l == P && ex != Nx - 1) break;
-      T ax = su[l * nzp + t];
-      if (l == 0 && left) ax += sl[P * nzp + t];
-      const size_t g = g0 + (size_t)l * nzn;
-      const T r = b[g] - ax;
-      T dn = cr * dinv[g] * r;
-      if (cd != (T)0) dn += cd * d[g];
-      if (store_d) d[g] = dn;
-      xo[g] = xin[l] + dn;
+      if (l < nl) {
+        T ax = su[l * nzp + t];
+        if (l == 0 && left) ax += sl[P * nzp + t];
+        const size_t g = g0 + (size_t)l * nzn;
+        const T r = pb[l] - ax;
+        if constexpr (MODE == 1) {
+          xo[g] = r;
+        } else {
+          T dn = cr * pdi[l] * r;
+          if (cd != (T)0) dn += cd * pd[l];
+          if (store_d) d[g] = dn;
+          xo[g] = xin[l] + dn;
+        }
+      }
     }
   }
 }
@@ -431,7 +473,7 @@ int cheb2d_cpb(int P, int Nx, int Nz, bool dbl) {
   return 0;
 }
 
-template <int P, typename T, typename TG>
+template <int P, typename T, typename TG, int MODE = 0>
 static hipError_t launch_cheb2d(const void* xi, void* xo, void* d, const void* b, const void* dinv,
                                 const void* G, int Nx, int Nz, int masked, double cd, double cr,
                                 int store_d, int cpb, hipStream_t st) {
@@ -443,9 +485,9 @@ static hipError_t launch_cheb2d(const void* xi, void* xo, void* d, const void* b
   const size_t smem = apply2d_smem(P, Nz, dbl) * (cpb + 1);
   if (threads > 1024 || smem > 160 * 1024) return hipErrorInvalidValue;
   const int remap = (blocks % 8 == 0) ? 1 : 0;
-  hipError_t e = allow_lds(k_cheb2d<P, T, TG>, smem);
+  hipError_t e = allow_lds(k_cheb2d<P, T, TG, MODE>, smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_cheb2d<P, T, TG>), dim3(blocks), dim3(threads), smem, st, (const T*)xi,
+  hipLaunchKernelGGL((k_cheb2d<P, T, TG, MODE>), dim3(blocks), dim3(threads), smem, st, (const T*)xi,
                      (T*)xo, (T*)d, (const T*)b, (const T*)dinv, (const TG*)G, Nx, Nz, masked, cpb,
                      remap, (T)cd, (T)cr, store_d);
   return hipGetLastError();
@@ -481,6 +523,190 @@ hipError_t cheb2d(int P, bool dbl, GType gt, const void* xi, void* xo, void* d, 
     case 8: return cheb2d_p<8>(dbl, gt, xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr, store_d, cpb, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+// Assembly of the element-local corrections of the learned stage fused with the operator:
+// c[g] = average of CE[e][local(g)] over the elements e holding node g (zero on the Dirichlet
+// surface when masked; contributions added in the order (left, lower), (left, upper),
+// (right, lower), (right, upper) element, as stage_assemble does), q = A c complete at every
+// node, and each workgroup's part of c . q in dotp[workgroup].  Halo layout as in k_cheb2d; CE in
+// the layout of ce_index.
+template <int P, typename T, typename TG>
+__global__ __launch_bounds__(1024) void k_stagecq2d(const float* __restrict__ CE,
+                                                    T* __restrict__ c, T* __restrict__ q,
+                                                    const TG* __restrict__ G, int Nx, int Nz,
+                                                    int masked, int cpb, int remap,
+                                                    double* __restrict__ dotp) {
+  constexpr int NP = P + 1;
+  constexpr int V = lds_vec<T>();
+  constexpr int NPp = (NP + V - 1) / V * V;
+  const int nzn = Nz * P + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int nthr = NP * Nz;
+  int bx = blockIdx.x;
+  if (remap) {
+    const int per = gridDim.x >> 3;
+    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int cs = threadIdx.x / nthr;
+  const int t = threadIdx.x - cs * nthr;
+  const int ex = bx * cpb + cs - 1;
+  const bool valid = cs <= cpb && ex >= 0 && ex < Nx;
+  const int slot = slot2d_elems<int>(NP, Nz, nzp, V);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* base = reinterpret_cast<T*>(smem_raw) + (valid ? cs : 0) * slot;
+  T xin[NP];
+  column_apply<P, T, TG>(
+      [&](T(&v)[NP]) {
+        const int qz = t / P, rz = t - qz * P;
+        const bool zl = rz == 0 && qz > 0, zr = qz < Nz;
+        const bool top = masked && t == nzn - 1;
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          // element columns left and right of line l of column ex, with their local line
+          const bool xl = l == 0 ? ex > 0 : l == P;
+          const bool xr = l == P ? ex + 1 < Nx : true;
+          const int cl = l == 0 ? ex - 1 : ex, il = P;
+          const int cr = l == P ? ex + 1 : ex, ir = l == P ? 0 : l;
+          float sacc = 0.f;
+          int cnt = 0;
+          if (xl && zl) { sacc += CE[ce_index(cl, il, qz - 1, P, Nz, NP)]; ++cnt; }
+          if (xl && zr) { sacc += CE[ce_index(cl, il, qz, rz, Nz, NP)]; ++cnt; }
+          if (xr && zl) { sacc += CE[ce_index(cr, ir, qz - 1, P, Nz, NP)]; ++cnt; }
+          if (xr && zr) { sacc += CE[ce_index(cr, ir, qz, rz, Nz, NP)]; ++cnt; }
+          v[l] = top ? (T)0 : (T)(sacc / (float)cnt);
+        }
+      },
+      G, valid ? ex : 0, nthr, t, valid, Nz, nzn, nzp, masked, base, xin, [] {});
+
+  double part = 0.0;
+  if (cs >= 1 && valid && t < nzn) {
+    const T* su = base + Nz * NP * NPp;
+    const T* sl = su - slot;
+    const bool left = ex > 0 && !(masked && t == nzn - 1);
+    const int nl = (ex == Nx - 1) ? NP : P;
+    const size_t g0 = (size_t)ex * P * nzn + t;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      if (l < nl) {
+        T ax = su[l * nzp + t];
+        if (l == 0 && left) ax += sl[P * nzp + t];
+        const size_t g = g0 + (size_t)l * nzn;
+        c[g] = xin[l];
+        q[g] = ax;
+        part += (double)xin[l] * (double)ax;
+      }
+    }
+  }
+  __shared__ double red[16];
+  const double tot = block_sum(part, red);
+  if (threadIdx.x == 0) dotp[blockIdx.x] = tot;
+}
+
+template <int P, typename T, typename TG>
+static hipError_t launch_stagecq2d(const float* CE, void* c, void* q, const void* G, int Nx,
+                                   int Nz, int masked, double* dotp, int cpb, hipStream_t st) {
+  const bool dbl = sizeof(T) == 8;
+  const int nthr = (P + 1) * Nz;
+  const int threads = (((cpb + 1) * nthr + 63) / 64) * 64;
+  const int blocks = (Nx + cpb - 1) / cpb;
+  const size_t smem = apply2d_smem(P, Nz, dbl) * (cpb + 1);
+  if (cpb <= 0 || threads > 1024 || smem > 160 * 1024) return hipErrorInvalidValue;
+  const int remap = (blocks % 8 == 0) ? 1 : 0;
+  hipError_t e = allow_lds(k_stagecq2d<P, T, TG>, smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_stagecq2d<P, T, TG>), dim3(blocks), dim3(threads), smem, st, CE, (T*)c,
+                     (T*)q, (const TG*)G, Nx, Nz, masked, cpb, remap, dotp);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t stagecq2d_p(bool dbl, GType gt, const float* CE, void* c, void* q,
+                              const void* G, int Nx, int Nz, int masked, double* dotp, int cpb,
+                              hipStream_t st) {
+  if (dbl) return launch_stagecq2d<P, double, double>(CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+  if (gt == G_BF16)
+    return launch_stagecq2d<P, float, uint16_t>(CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+  return launch_stagecq2d<P, float, float>(CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+}
+
+int cheb2d_blocks(int P, int Nx, int Nz, bool dbl) {
+  const int cpb = cheb2d_cpb(P, Nx, Nz, dbl);
+  return cpb > 0 ? (Nx + cpb - 1) / cpb : 0;
+}
+
+hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* q, const void* G,
+                     int Nx, int Nz, int masked, double* dotp, hipStream_t st) {
+  const int cpb = P <= 8 ? cheb2d_cpb(P, Nx, Nz, dbl) : 0;
+  if (cpb <= 0) return hipErrorInvalidValue;
+  switch (P) {
+    case 1: return stagecq2d_p<1>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    case 2: return stagecq2d_p<2>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    case 3: return stagecq2d_p<3>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    case 4: return stagecq2d_p<4>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    case 5: return stagecq2d_p<5>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    case 6: return stagecq2d_p<6>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    case 7: return stagecq2d_p<7>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    case 8: return stagecq2d_p<8>(dbl, gt, CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename T>
+__global__ void k_resid_fix(const T* __restrict__ b, const T* __restrict__ y,
+                            const T* __restrict__ S, T* __restrict__ r, unsigned N, unsigned nzn,
+                            unsigned P) {
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    r[g] = b[g] - ax_at(y, S, g, nzn, P);
+}
+
+template <int P>
+static hipError_t resid2d_p(bool dbl, GType gt, const void* x, void* r, const void* b,
+                            const void* G, int Nx, int Nz, int masked, int cpb, hipStream_t st) {
+  if (dbl)
+    return launch_cheb2d<P, double, double, 1>(x, r, nullptr, b, nullptr, G, Nx, Nz, masked, 0.0,
+                                               0.0, 0, cpb, st);
+  if (gt == G_BF16)
+    return launch_cheb2d<P, float, uint16_t, 1>(x, r, nullptr, b, nullptr, G, Nx, Nz, masked, 0.0,
+                                                0.0, 0, cpb, st);
+  return launch_cheb2d<P, float, float, 1>(x, r, nullptr, b, nullptr, G, Nx, Nz, masked, 0.0, 0.0,
+                                           0, cpb, st);
+}
+
+hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
+                   int Nx, int Nz, int masked, hipStream_t st);
+
+hipError_t resid2d(int P, bool dbl, GType gt, const void* x, void* r, const void* b,
+                   const void* G, int Nx, int Nz, int masked, void* y, void* S, hipStream_t st) {
+  if (x == r) return hipErrorInvalidValue;
+  const int cpb = P <= 8 ? cheb2d_cpb(P, Nx, Nz, dbl) : 0;
+  if (cpb > 0) {
+    switch (P) {
+      case 1: return resid2d_p<1>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      case 2: return resid2d_p<2>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      case 3: return resid2d_p<3>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      case 4: return resid2d_p<4>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      case 5: return resid2d_p<5>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      case 6: return resid2d_p<6>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      case 7: return resid2d_p<7>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      case 8: return resid2d_p<8>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  // columns too tall for the fused form: operator with side buffer, then r = b - (y + S)
+  hipError_t e = apply2d(P, dbl, gt, x, y, S, G, Nx, Nz, masked, st);
+  if (e != hipSuccess) return e;
+  const unsigned N = (unsigned)((size_t)(Nx * P + 1) * (Nz * P + 1));
+  const unsigned blocks = std::min(nblk(N, 256), 8192u);
+  if (dbl)
+    hipLaunchKernelGGL(k_resid_fix<double>, dim3(blocks), dim3(256), 0, st, (const double*)b,
+                       (const double*)y, (const double*)S, (double*)r, N, (unsigned)(Nz * P + 1),
+                       (unsigned)P);
+  else
+    hipLaunchKernelGGL(k_resid_fix<float>, dim3(blocks), dim3(256), 0, st, (const float*)b,
+                       (const float*)y, (const float*)S, (float*)r, N, (unsigned)(Nz * P + 1),
+                       (unsigned)P);
+  return hipGetLastError();
 }
 
 template <int P, typename T, typename TG, bool DOT = false>

@@ -70,27 +70,28 @@ struct Stage {
   float *b2 = nullptr, *b3 = nullptr;
   float* Z1geo = nullptr;   // [E x NH] = geometric part of layer 1 + b1
   float* abar = nullptr;    // [E] mean of the element-matrix diagonal
-  float* CE = nullptr;      // [E x nout] element-local corrections
+  float* CE = nullptr;      // [E x nout] element-local corrections (layout semk::ce_index)
   int* skips = nullptr;     // device counter of rejected stages
   std::vector<void*> allocs;
 };
 
 // One learned stage on the fine level (precision dbl ? double : float), driven by the caller:
-//   stage_mlp (c_e from r = b - (y + S)), stage_assemble (c, c.r), the caller's apply of c with
-//   c.q partials, stage_update (alpha, x, R).
-// c_e for every element from r = b - (y + S), and each block's part of c . r (c the assembled
-// correction, zero on the Dirichlet surface when masked) in pcr[0 .. stage_mlp_blocks)
-hipError_t stage_mlp(const Stage& s, bool dbl, const void* b, const void* y, const void* S,
-                     int masked, double* pcr, hipStream_t st);
+//   the residual r = b - A x (semk::resid2d), stage_mlp (c_e, c.r), stage_assemble (c), the
+//   caller's apply of c with c.q partials, stage_update (alpha, x, R).
+// c_e for every element from the complete residual vector r, and each block's part of c . r
+// (c the assembled correction, zero on the Dirichlet surface when masked) in
+// pcr[0 .. stage_mlp_blocks)
+hipError_t stage_mlp(const Stage& s, bool dbl, const void* r, int masked, double* pcr,
+                     hipStream_t st);
 int stage_mlp_blocks(size_t E);  // workgroups of stage_mlp (entries of its c . r partials)
 // c = W sum_e R_e^T c_e, zero on the Dirichlet surface when masked
 hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStream_t st);
-// alpha = c.r / c.q from the partials (ncr of c.r, ncq of c.q); if accepted x += alpha c and
-// R = r - alpha q, else R = r and skips[0] += 1
-hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* b, const void* y,
-                        const void* S, const void* yq, const void* Sq, const double* pcr, int ncr,
-                        const double* pcq, int ncq, int* skips, unsigned N, unsigned nzn,
-                        unsigned P, hipStream_t st);
+// alpha = c.r / c.q from the partials (ncr of c.r, ncq of c.q); R holds r on entry; if accepted
+// x += alpha c and R = r - alpha q (q = yq + Sq, the side-buffer form of A c), else R = r and
+// skips[0] += 1
+hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* yq, const void* Sq,
+                        const double* pcr, int ncr, const double* pcq, int ncq, int* skips,
+                        unsigned N, unsigned nzn, unsigned P, hipStream_t st);
 // Training features of an assembled residual r on a 2D mesh: X [E x 5n] fp32; targets T [E x n]
 // fp32 from the error e ((a_e/s_e) R_e e) or, if e is null, from the element-block inverses
 // Ainv [E x n x n] ((a_e/s_e) Ainv_e R_e r).

@@ -731,219 +731,170 @@ __device__ double bsum(double v, double* sh) {
   return s;
 }
 
-// Persistent form: one workgroup of 1024 threads per compute unit holds the whole network in LDS
-// (BF16, transposed, rows padded against bank conflicts), staged once with coalesced 16-byte
-// loads, and walks over groups of four 16-element tiles, one per 256 threads, in lockstep
-// (shared barriers).  Within a tile every wave takes part in the
-// gather and normalisation; in the three layers the output columns are split over its 4 waves
-// (hidden tiles 2w, 2w+1; output tiles w, w+4).  The workgroup also writes its part of c . r to
-// pcr[workgroup]: with c = W sum_e R_e^T c_e, c . r = sum_e sum_l c_e[l] r_g / m_g (g the global
-// node of (e, l), m_g its multiplicity, weight 0 on the Dirichlet surface when masked), which
-// needs only the workgroup's own r_e and c_e.
-constexpr int MLP_GROUPS = 4;  // 16-element tiles in flight per workgroup
-constexpr int MLP_THREADS = 256 * MLP_GROUPS;
-constexpr int MLP_MAX_BLOCKS = 256;
+// One wave carries 16 elements through the whole network in registers.  Every layer is computed
+// transposed, Z^T = W^T X^T: the weights (stored output-major, staged once per workgroup into
+// LDS with padded rows while the residual is being gathered) are the MFMA A operand, and the
+// activations the B operand.  The result of a 16x16x16 MFMA (lane l holds
+// rows 4(l/16)+v of column l%16) is then exactly the B operand of the next layer's k-step for
+// the same 16 rows, so the hidden activations never leave the registers and no workgroup
+// barrier is needed.  Per lane: element le = l%16 of the tile and, in every 16-block of
+// features, the slice kq..kq+3 (kq = 4 (l/16)); the residual gathered for layer 1 sits in the
+// same slices as the layer-3 output, so each lane also forms its part of c . r:
+// with c = W sum_e R_e^T c_e, c . r = sum_e sum_l c_e[l] r_g / m_g (g the global node of (e, l),
+// m_g its multiplicity, weight 0 on the Dirichlet surface when masked).  The workgroup's sum
+// goes to pcr[workgroup].
+// acc[t] += W^T(tile t) . xb, K = 16 KS: the weight fragments of k-step k + 1 are read from LDS
+// while the MFMAs of k-step k run (one wave per SIMD hides no latency otherwise)
+template <int NTT, int KS>
+__device__ __forceinline__ void layer_mfma(const uint16_t* __restrict__ sW, int ld, int le, int kq,
+                                           const bf16x4 (&xb)[KS], f32x4 (&acc)[NTT]) {
+  bf16x4 w[2][NTT];
+#pragma unroll
+  for (int t = 0; t < NTT; ++t)
+    w[0][t] = *reinterpret_cast<const bf16x4*>(sW + (16 * t + le) * ld + kq);
+#pragma unroll
+  for (int k = 0; k < KS; ++k) {
+    if (k + 1 < KS) {
+#pragma unroll
+      for (int t = 0; t < NTT; ++t)
+        w[(k + 1) & 1][t] = *reinterpret_cast<const bf16x4*>(sW + (16 * t + le) * ld + 16 * (k + 1) + kq);
+    }
+#pragma unroll
+    for (int t = 0; t < NTT; ++t) acc[t] = mfma16(w[k & 1][t], xb[k], acc[t]);
+  }
+}
 
-template <int P>
-struct MlpShape {
-  static constexpr int NP = P + 1, n = NP * NP, KR = (n + 15) / 16 * 16, KS1 = KR / 16,
-                       NT3 = KR / 16;
-  static constexpr int W1S = KR + 8, WHS = NH + 8;  // LDS row strides of the weights
-  static constexpr int XS = KR + 4, HS = NH + 4;    // LDS row strides of the activations
-};
+constexpr int MLP_WAVES = 4;  // waves (16-element tiles) per workgroup
+constexpr int MLP_THREADS = 64 * MLP_WAVES;
 
 template <int P, typename T>
-__global__ __launch_bounds__(MLP_THREADS) void k_stage_mlp(
-    const T* __restrict__ b, const T* __restrict__ y, const T* __restrict__ S,
-    const uint16_t* __restrict__ W1r, const float* __restrict__ Z1geo,
+__global__ __launch_bounds__(MLP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_mlp(
+    const T* __restrict__ r, const uint16_t* __restrict__ W1r, const float* __restrict__ Z1geo,
     const uint16_t* __restrict__ W2, const float* __restrict__ b2,
     const uint16_t* __restrict__ W3, const float* __restrict__ b3,
     const float* __restrict__ abar, float* __restrict__ CE, int E, int Nx, int Nz, unsigned nzn,
     int masked, double* __restrict__ pcr) {
-  using Sh = MlpShape<P>;
-  constexpr int NP = Sh::NP, n = Sh::n, KR = Sh::KR, KS1 = Sh::KS1, NT3 = Sh::NT3;
-  constexpr int W1S = Sh::W1S, WHS = Sh::WHS, XS = Sh::XS, HS = Sh::HS;
+  constexpr int NP = P + 1, n = NP * NP, KR = (n + 15) / 16 * 16, KS = KR / 16, NT = NH / 16;
+  constexpr int W1S = KR + 8, WHS = NH + 8;  // LDS row strides (bf16) against bank conflicts
   __shared__ __align__(16) uint16_t sW1[NH * W1S];
   __shared__ __align__(16) uint16_t sW2[NH * WHS];
   __shared__ __align__(16) uint16_t sW3[KR * WHS];
-  __shared__ __align__(16) uint16_t sXa[MLP_GROUPS][16 * XS];
-  __shared__ __align__(16) uint16_t sH1a[MLP_GROUPS][16 * HS];
-  __shared__ __align__(16) uint16_t sH2a[MLP_GROUPS][16 * HS];
-  __shared__ float sRa[MLP_GROUPS][16 * n];  // r_e (fp32) for the c . r partial
-  __shared__ float sSca[MLP_GROUPS][16];     // s_e / a_e
-  __shared__ double sred[MLP_THREADS / 64];
-  const int tid = threadIdx.x, grp = tid >> 8, gt = tid & 255;
-  const int wave = gt >> 6, lane = gt & 63;
-  const int li = lane & 15, kq = (lane >> 4) * 4;
-  uint16_t* sX = sXa[grp];
-  uint16_t* sH1 = sH1a[grp];
-  uint16_t* sH2 = sH2a[grp];
-  float* sR = sRa[grp];
-  float* sSc = sSca[grp];
+  __shared__ double sred[MLP_WAVES];
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int le = lane & 15, kq = (lane >> 4) * 4;
+  const int e = (blockIdx.x * MLP_WAVES + wave) * 16 + le;
+  const bool ve = e < E;
+  const int ex = ve ? e / Nz : 0, ez = ve ? e - ex * Nz : 0;
+  const unsigned base = (unsigned)(ex * P) * nzn + ez * P;
 
-  // ---- the network into LDS: 16-byte chunks, row-padded
-  {
-    constexpr int c1 = KR / 8, c2 = NH / 8;
-    for (int k = tid; k < NH * c1; k += MLP_THREADS) {
-      const int r = k / c1, q = k - r * c1;
-      *reinterpret_cast<uint4*>(sW1 + r * W1S + 8 * q) = *reinterpret_cast<const uint4*>(W1r + r * KR + 8 * q);
-    }
-    for (int k = tid; k < NH * c2; k += MLP_THREADS) {
-      const int r = k / c2, q = k - r * c2;
-      *reinterpret_cast<uint4*>(sW2 + r * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W2 + r * NH + 8 * q);
-    }
-    for (int k = tid; k < KR * c2; k += MLP_THREADS) {
-      const int r = k / c2, q = k - r * c2;
-      *reinterpret_cast<uint4*>(sW3 + r * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W3 + r * NH + 8 * q);
-    }
-  }
-  const float b2v[2] = {b2[16 * (2 * wave) + li], b2[16 * (2 * wave + 1) + li]};
-  const float b3v[2] = {wave < NT3 ? b3[16 * wave + li] : 0.f,
-                        wave + 4 < NT3 ? b3[16 * (wave + 4) + li] : 0.f};
-
-  const int ntiles = (E + 15) / 16;
-  const int iters = (ntiles + MLP_GROUPS * gridDim.x - 1) / (MLP_GROUPS * gridDim.x);  // same everywhere
-  double part = 0.0;
-  for (int it = 0; it < iters; ++it) {
-    const int tile = (it * gridDim.x + blockIdx.x) * MLP_GROUPS + grp;
-    const int e0 = tile * 16;  // e0 >= E: this group idles through the barriers
-
-    // layer-1 accumulators start from the precomputed geometric part
-    f32x4 acc[2];
+  // residual of this lane's slices (fp32), element norm over the 4 lanes of the element
+  float rv[KS][4];
+  float ss = 0.f;
 #pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int er = e0 + kq + v;
-        acc[tt][v] = er < E ? Z1geo[(long)er * NH + 16 * (2 * wave + tt) + li] : 0.f;
-      }
-
-    // gather r = b - A x (A x = y + S on shared vertical lines): 16 lanes per element
-    const int el = gt >> 4, lg = gt & 15;
-    const int e = e0 + el;
-    float rv[KS1];
-    float ss = 0.f;
-    if (e < E) {
-      const int ex = e / Nz, ez = e - ex * Nz;
-      const unsigned base = (unsigned)(ex * P) * nzn + ez * P;
-      const unsigned sb = (unsigned)ex * nzn + ez * P;
-#pragma unroll
-      for (int k = 0; k < KS1; ++k) {
-        const int l = lg + 16 * k;
-        rv[k] = 0.f;
-        if (l < n) {
-          const int i = l / NP, j = l - (l / NP) * NP;
-          const unsigned g = base + i * nzn + j;
-          T ax = y[g];
-          if (i == 0) ax += S[sb + j];
-          if (i == P) ax += S[sb + nzn + j];
-          rv[k] = (float)(b[g] - ax);
-        }
-        ss += rv[k] * rv[k];
-        if (l < n) sR[el * n + l] = rv[k];
-      }
-    } else {
-#pragma unroll
-      for (int k = 0; k < KS1; ++k) rv[k] = 0.f;
-    }
-#pragma unroll
-    for (int o = 8; o >= 1; o >>= 1) ss += __shfl_xor(ss, o, 64);
-    const float s = sqrtf(ss);
-    if (lg == 0) sSc[el] = e < E ? s / abar[e] : 0.f;
-    const float sinv = s > 0.f ? 1.0f / s : 0.f;
-#pragma unroll
-    for (int k = 0; k < KS1; ++k) sX[el * XS + lg + 16 * k] = f2bf(rv[k] * sinv);
-    __syncthreads();
-
-    // layer 1: Z1 = Xr W1r + Z1geo (the geometric part of X W1 + b1 is precomputed)
-#pragma unroll
-    for (int k = 0; k < KS1; ++k) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sX + li * XS + 16 * k + kq);
-#pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        const bf16x4 w = *reinterpret_cast<const bf16x4*>(sW1 + (16 * (2 * wave + tt) + li) * W1S + 16 * k + kq);
-        acc[tt] = mfma16(a, w, acc[tt]);
-      }
-    }
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sH1[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
-    __syncthreads();
-
-    // layer 2: Z2 = H1 W2 + b2
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) acc[tt] = (f32x4){b2v[tt], b2v[tt], b2v[tt], b2v[tt]};
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH1 + li * HS + 16 * k + kq);
-#pragma unroll
-      for (int tt = 0; tt < 2; ++tt) {
-        const bf16x4 w = *reinterpret_cast<const bf16x4*>(sW2 + (16 * (2 * wave + tt) + li) * WHS + 16 * k + kq);
-        acc[tt] = mfma16(a, w, acc[tt]);
-      }
-    }
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) sH2[(kq + v) * HS + 16 * (2 * wave + tt) + li] = f2bf(gelu(acc[tt][v]));
-    __syncthreads();
-
-    // layer 3: Y = H2 W3 + b3; c_e = (s_e / a_e) y
-    int exv[4], ezv[4];
+  for (int k = 0; k < KS; ++k)
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
-      const int er = e0 + kq + v;
-      exv[v] = er / Nz;
-      ezv[v] = er - exv[v] * Nz;
-    }
-#pragma unroll
-    for (int tt = 0; tt < 2; ++tt) {
-      const int t3 = wave + 4 * tt;
-      if (t3 >= NT3) continue;  // wave-uniform
-      const int col = 16 * t3 + li;
-      f32x4 c = (f32x4){b3v[tt], b3v[tt], b3v[tt], b3v[tt]};
-#pragma unroll
-      for (int k = 0; k < 8; ++k) {
-        const bf16x4 a = *reinterpret_cast<const bf16x4*>(sH2 + li * HS + 16 * k + kq);
-        const bf16x4 w = *reinterpret_cast<const bf16x4*>(sW3 + col * WHS + 16 * k + kq);
-        c = mfma16(a, w, c);
+      const int loc = 16 * k + kq + v;
+      rv[k][v] = 0.f;
+      if (ve && loc < n) {
+        const int i = loc / NP, j = loc - (loc / NP) * NP;
+        rv[k][v] = (float)r[base + i * nzn + j];
       }
-      if (col < n) {
-        const int i = col / NP, j = col - (col / NP) * NP;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int er = e0 + kq + v;
-          if (er < E) {
-            const float ce = sSc[kq + v] * c[v];
-            CE[(long)er * n + col] = ce;
-            const int mx = ((i == 0 && exv[v] > 0) || (i == P && exv[v] < Nx - 1)) ? 2 : 1;
-            const int mz = ((j == 0 && ezv[v] > 0) || (j == P && ezv[v] < Nz - 1)) ? 2 : 1;
-            const bool top = masked && j == P && ezv[v] == Nz - 1;
-            if (!top) part += (double)ce * (double)sR[(kq + v) * n + col] / (double)(mx * mz);
-          }
-        }
-      }
+      ss += rv[k][v] * rv[k][v];
     }
-    __syncthreads();  // sX, sR, sSc are rewritten by the next tile
+  // the network into LDS (16-byte chunks), issued behind the residual loads
+  {
+    constexpr int c1 = KR / 8, c2 = NH / 8;
+    for (int k = threadIdx.x; k < NH * c1; k += MLP_THREADS) {
+      const int rw = k / c1, q = k - rw * c1;
+      *reinterpret_cast<uint4*>(sW1 + rw * W1S + 8 * q) = *reinterpret_cast<const uint4*>(W1r + rw * KR + 8 * q);
+    }
+    for (int k = threadIdx.x; k < NH * c2; k += MLP_THREADS) {
+      const int rw = k / c2, q = k - rw * c2;
+      *reinterpret_cast<uint4*>(sW2 + rw * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W2 + rw * NH + 8 * q);
+    }
+    for (int k = threadIdx.x; k < KR * c2; k += MLP_THREADS) {
+      const int rw = k / c2, q = k - rw * c2;
+      *reinterpret_cast<uint4*>(sW3 + rw * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W3 + rw * NH + 8 * q);
+    }
   }
-  const double tot = bsum(part, sred);
-  if (tid == 0) pcr[blockIdx.x] = tot;
+  ss += __shfl_xor(ss, 16, 64);
+  ss += __shfl_xor(ss, 32, 64);
+  const float sn = sqrtf(ss);
+  const float sinv = sn > 0.f ? 1.0f / sn : 0.f;
+  bf16x4 xb[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xb[k][v] = (short)f2bf(rv[k][v] * sinv);
+
+  // layer 1: Z1 = Xr W1r + Z1geo (the geometric part of X W1 + b1 is precomputed)
+  f32x4 acc[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+    acc[t] = ve ? *reinterpret_cast<const f32x4*>(Z1geo + (long)e * NH + 16 * t + kq)
+                : (f32x4){0.f, 0.f, 0.f, 0.f};
+  __syncthreads();
+  layer_mfma<NT, KS>(sW1, W1S, le, kq, xb, acc);
+  bf16x4 hb[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) hb[t][v] = (short)f2bf(gelu(acc[t][v]));
+
+  // layer 2: Z2 = H1 W2 + b2
+#pragma unroll
+  for (int t = 0; t < NT; ++t) acc[t] = *reinterpret_cast<const f32x4*>(b2 + 16 * t + kq);
+  layer_mfma<NT, NT>(sW2, WHS, le, kq, hb, acc);
+#pragma unroll
+  for (int t = 0; t < NT; ++t)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) hb[t][v] = (short)f2bf(gelu(acc[t][v]));
+
+  // layer 3: Y = H2 W3 + b3; c_e = (s_e / a_e) y, and this lane's part of c . r
+  const float sc = ve ? sn / abar[e] : 0.f;
+  f32x4 out[KS];
+#pragma unroll
+  for (int t = 0; t < KS; ++t) out[t] = *reinterpret_cast<const f32x4*>(b3 + 16 * t + kq);
+  layer_mfma<KS, NT>(sW3, WHS, le, kq, hb, out);
+  double part = 0.0;
+#pragma unroll
+  for (int t = 0; t < KS; ++t) {
+    const f32x4 c = out[t];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int loc = 16 * t + kq + v;
+      if (ve && loc < n) {
+        const float ce = sc * c[v];
+        const int i = loc / NP, j = loc - (loc / NP) * NP;
+        CE[semk::ce_index(ex, i, ez, j, Nz, NP)] = ce;
+        const int mx = ((i == 0 && ex > 0) || (i == P && ex < Nx - 1)) ? 2 : 1;
+        const int mz = ((j == 0 && ez > 0) || (j == P && ez < Nz - 1)) ? 2 : 1;
+        const bool top = masked && j == P && ez == Nz - 1;
+        if (!top) part += (double)ce * (double)rv[t][v] / (double)(mx * mz);
+      }
+    }
+  }
+  part = wsum(part);
+  if (lane == 0) sred[wave] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < MLP_WAVES; ++w) tot += sred[w];
+    pcr[blockIdx.x] = tot;
+  }
 }
 
-int stage_mlp_blocks(size_t E) {
-  const int groups = (int)((E + 16 * MLP_GROUPS - 1) / (16 * MLP_GROUPS));
-  return groups < MLP_MAX_BLOCKS ? groups : MLP_MAX_BLOCKS;
-}
+int stage_mlp_blocks(size_t E) { return (int)((E + 16 * MLP_WAVES - 1) / (16 * MLP_WAVES)); }
 
-hipError_t stage_mlp(const Stage& s, bool dbl, const void* b, const void* y, const void* S,
-                     int masked, double* pcr, hipStream_t st) {
+hipError_t stage_mlp(const Stage& s, bool dbl, const void* r, int masked, double* pcr,
+                     hipStream_t st) {
   if (s.P < 1 || s.P > 8 || s.nout != (s.P + 1) * (s.P + 1)) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)stage_mlp_blocks(s.E);
 #define SEM_STAGE_MLP(PP, TT)                                                                    \
   hipLaunchKernelGGL((k_stage_mlp<PP, TT>), dim3(blocks), dim3(MLP_THREADS), 0, st,             \
-                     (const TT*)b, (const TT*)y, (const TT*)S, s.W1r, s.Z1geo, s.W2, s.b2, s.W3, \
-                     s.b3, s.abar, s.CE, (int)s.E, s.Nx, s.Nz, (unsigned)s.nzn, masked, pcr)
+                     (const TT*)r, s.W1r, s.Z1geo, s.W2, s.b2, s.W3, s.b3, s.abar, s.CE,         \
+                     (int)s.E, s.Nx, s.Nz, (unsigned)s.nzn, masked, pcr)
 #define SEM_STAGE_MLP_P(PP)             \
   case PP:                              \
     if (dbl) SEM_STAGE_MLP(PP, double); \
@@ -984,10 +935,10 @@ __global__ __launch_bounds__(256) void k_stage_assemble(const float* __restrict_
     const bool xl = rx == 0 && qx > 0, xr = qx < Nx, zl = rz == 0 && qz > 0, zr = qz < Nz;
     float s = 0.f;
     int cnt = 0;
-    if (xl && zl) { s += CE[((long)(qx - 1) * Nz + qz - 1) * n + P * NP + P]; ++cnt; }
-    if (xl && zr) { s += CE[((long)(qx - 1) * Nz + qz) * n + P * NP + rz]; ++cnt; }
-    if (xr && zl) { s += CE[((long)qx * Nz + qz - 1) * n + rx * NP + P]; ++cnt; }
-    if (xr && zr) { s += CE[((long)qx * Nz + qz) * n + rx * NP + rz]; ++cnt; }
+    if (xl && zl) { s += CE[semk::ce_index(qx - 1, P, qz - 1, P, Nz, NP)]; ++cnt; }
+    if (xl && zr) { s += CE[semk::ce_index(qx - 1, P, qz, rz, Nz, NP)]; ++cnt; }
+    if (xr && zl) { s += CE[semk::ce_index(qx, rx, qz - 1, P, Nz, NP)]; ++cnt; }
+    if (xr && zr) { s += CE[semk::ce_index(qx, rx, qz, rz, Nz, NP)]; ++cnt; }
     c[g] = (T)(s / (float)cnt);
   }
 }
@@ -1023,15 +974,14 @@ hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStre
 // Step of the stage: alpha = c.r / c.q from the block partials of the network kernel (c.r) and of
 // the apply of c (c.q), added in block order by every block (the same value everywhere,
 // independent of scheduling).  Accepted if finite and positive (the A-norm of the error then
-// drops by (c.r)^2 / c.q): x += alpha c and R = r - alpha q; otherwise R = r and the rejection
-// is counted.  Each thread first loads r, q and c of its first UPD_IT nodes, so that the loads
-// are in flight during the reduction.
+// drops by (c.r)^2 / c.q): x += alpha c and R = r - alpha q in place (R holds r on entry);
+// otherwise R stays r and the rejection is counted.  Each thread first loads r, q and c of its
+// first UPD_IT nodes, so that the loads are in flight during the reduction.
 constexpr int UPD_IT = 4;
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __restrict__ R,
-                                                       const T* __restrict__ c, const T* __restrict__ b,
-                                                       const T* __restrict__ y, const T* __restrict__ S,
+                                                       const T* __restrict__ c,
                                                        const T* __restrict__ yq, const T* __restrict__ Sq,
                                                        const double* __restrict__ pcr, int ncr,
                                                        const double* __restrict__ pcq, int ncq,
@@ -1044,7 +994,7 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
   for (int k = 0; k < UPD_IT; ++k) {
     const unsigned g = g0 + k * stride;
     if (g < N) {
-      rr[k] = b[g] - ax_at(y, S, g, nzn, P);
+      rr[k] = R[g];
       qq[k] = ax_at(yq, Sq, g, nzn, P);
       cc[k] = c[g];
     }
@@ -1057,45 +1007,35 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
   const double alpha = cr / cq;
   const bool ok = isfinite(alpha) && alpha > 0.0;
   const T al = ok ? (T)alpha : (T)0;
+  if (ok) {
 #pragma unroll
-  for (int k = 0; k < UPD_IT; ++k) {
-    const unsigned g = g0 + k * stride;
-    if (g < N) {
-      if (ok) {
+    for (int k = 0; k < UPD_IT; ++k) {
+      const unsigned g = g0 + k * stride;
+      if (g < N) {
         x[g] += al * cc[k];
         R[g] = rr[k] - al * qq[k];
-      } else {
-        R[g] = rr[k];
       }
     }
-  }
-  for (unsigned g = g0 + UPD_IT * stride; g < N; g += stride) {
-    const T r = b[g] - ax_at(y, S, g, nzn, P);
-    if (ok) {
+    for (unsigned g = g0 + UPD_IT * stride; g < N; g += stride) {
       x[g] += al * c[g];
-      R[g] = r - al * ax_at(yq, Sq, g, nzn, P);
-    } else {
-      R[g] = r;
+      R[g] = R[g] - al * ax_at(yq, Sq, g, nzn, P);
     }
   }
   if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) skips[0] += 1;
 }
 
-hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* b, const void* y,
-                        const void* S, const void* yq, const void* Sq, const double* pcr, int ncr,
-                        const double* pcq, int ncq, int* skips, unsigned N, unsigned nzn,
-                        unsigned P, hipStream_t st) {
+hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* yq, const void* Sq,
+                        const double* pcr, int ncr, const double* pcq, int ncq, int* skips,
+                        unsigned N, unsigned nzn, unsigned P, hipStream_t st) {
   const unsigned blocks = nblk(N, 1024 * UPD_IT);
   if (dbl)
     hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(1024), 0, st, (double*)x,
-                       (double*)R, (const double*)c, (const double*)b, (const double*)y,
-                       (const double*)S, (const double*)yq, (const double*)Sq, pcr, ncr, pcq,
-                       ncq, skips, N, nzn, P);
+                       (double*)R, (const double*)c, (const double*)yq, (const double*)Sq, pcr,
+                       ncr, pcq, ncq, skips, N, nzn, P);
   else
     hipLaunchKernelGGL(k_stage_update<float>, dim3(blocks), dim3(1024), 0, st, (float*)x,
-                       (float*)R, (const float*)c, (const float*)b, (const float*)y,
-                       (const float*)S, (const float*)yq, (const float*)Sq, pcr, ncr, pcq, ncq,
-                       skips, N, nzn, P);
+                       (float*)R, (const float*)c, (const float*)yq, (const float*)Sq, pcr, ncr,
+                       pcq, ncq, skips, N, nzn, P);
   return hipGetLastError();
 }
 

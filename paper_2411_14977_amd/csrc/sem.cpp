@@ -60,6 +60,7 @@ struct Ctx {
   hipStream_t st = nullptr;       // internal stream (default priority)
   hipStream_t ust = nullptr;      // caller's stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  hipEvent_t ev_it[2] = {nullptr, nullptr};  // per-iteration partial sums copied to the host
   // fine-level FP64 operator for the outer loop
   double* G64 = nullptr;
   bool G64_owned = false;
@@ -67,7 +68,7 @@ struct Ctx {
          *zo = nullptr, *yo = nullptr, *So = nullptr, *mass = nullptr;
   double* parts = nullptr;        // partial-sum sets
   double* scal = nullptr;         // device scalars
-  double* hscal = nullptr;        // pinned host scalars
+  double* hscal = nullptr;        // pinned host scalars: two sets of 3 NRED partials
   std::vector<long long*> face_idx;
   std::vector<double*> face_w;
   std::vector<size_t> face_n;
@@ -319,12 +320,21 @@ void learned_stage(Ctx* c) {
   const int ncr = semm::stage_mlp_blocks(s.E);
   double* pcr = c->stparts;
   double* pcq = c->stparts + ncr;
-  apply_level(c, 0, L.x, c->masked);
-  HK(semm::stage_mlp(s, L.dbl, L.b, L.y, L.S, c->masked, pcr, c->st));
+  HK(semk::resid2d(L.P, L.dbl, L.gt, L.x, c->Rbuf, L.b, L.G, L.Nx, L.Nz, c->masked, L.y, L.S,
+                   c->st));
+  HK(semm::stage_mlp(s, L.dbl, c->Rbuf, c->masked, pcr, c->st));
+  const int nfused = semk::cheb2d_blocks(L.P, L.Nx, L.Nz, L.dbl);
+  if (nfused > 0) {  // assembly fused with the apply of c: q complete, no side buffer
+    HK(semk::stagecq2d(L.P, L.dbl, L.gt, s.CE, c->cbuf, c->yq, L.G, L.Nx, L.Nz, c->masked, pcq,
+                       c->st));
+    HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, c->yq, nullptr, pcr, ncr, pcq, nfused,
+                          s.skips, L.N, L.nzn, L.P, c->st));
+    return;
+  }
   HK(semm::stage_assemble(s, L.dbl, c->cbuf, c->masked, c->st));
   HK(semk::apply2d_dot(L.P, L.dbl, L.gt, c->cbuf, c->yq, c->Sq, L.G, L.Nx, L.Nz, c->masked, pcq,
                        c->st));
-  HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, L.b, L.y, L.S, c->yq, c->Sq, pcr, ncr, pcq,
+  HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, c->yq, c->Sq, pcr, ncr, pcq,
                         semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl), s.skips, L.N, L.nzn, L.P,
                         c->st));
 }
@@ -805,7 +815,7 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
   c->So = nullptr;
   c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
   c->scal = (double*)dalloc(c, 64 * 8);
-  HK(hipHostMalloc((void**)&c->hscal, 3 * semk::NRED * 8, hipHostMallocDefault));
+  HK(hipHostMalloc((void**)&c->hscal, 2 * 3 * semk::NRED * 8, hipHostMallocDefault));
   {  // lumped mass and Neumann faces of the fine level
     const semh::LevelGeom& G = L0.geo;
     const size_t NL3 = (size_t)G.NP * G.NP * G.NP;
@@ -899,6 +909,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     HK(hipStreamCreate(&c->st));
     HK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+    for (auto& e : c->ev_it) HK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  for (auto& e : c->ev_it) HK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const char* ng = std::getenv("SEM_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
     setup3d_impl(c, d, orders);
@@ -913,6 +925,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   HK(hipStreamCreate(&c->st));
   HK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
   HK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
+  for (auto& e : c->ev_it) HK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
   const char* ng = std::getenv("SEM_NO_GRAPH");
   c->use_graphs = !(ng && ng[0] == '1');
 
@@ -986,7 +999,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   c->So = (double*)dalloc(c, L0.nS * 8);
   c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
   c->scal = (double*)dalloc(c, 64 * 8);
-  HK(hipHostMalloc((void**)&c->hscal, 3 * semk::NRED * 8, hipHostMallocDefault));
+  HK(hipHostMalloc((void**)&c->hscal, 2 * 3 * semk::NRED * 8, hipHostMallocDefault));
   // lumped mass and Neumann faces of the fine level
   {
     std::vector<double> m(N, 0.0);
@@ -1072,6 +1085,10 @@ void release(Ctx* c) {
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   c->ev_in = c->ev_out = nullptr;
+  for (auto& e : c->ev_it) {
+    if (e) (void)hipEventDestroy(e);
+    e = nullptr;
+  }
   if (c->st) (void)hipStreamDestroy(c->st);
   c->st = nullptr;
 }
@@ -1404,14 +1421,14 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
       rel = 0.0;
     }
     const bool fpcg = c->desc.outer == SEM_OUTER_FPCG;
-    int it = 0;
-    while (st == SEM_OK && rel > tol) {
-      if (it >= c->desc.maxit) {
-        st = SEM_ERR_NOT_CONVERGED;
-        set_err(c, "maximum number of outer iterations reached");
-        break;
-      }
-      const bool first = (it == 0);
+    // Each iteration's partial sums go to pinned host memory behind an event.  While the
+    // residual trend says the iteration in flight cannot reach tol (its predicted residual is
+    // above twice tol), the next iteration is enqueued before the host waits, so the GPU does not
+    // idle between iterations.  A wrong guess runs one more iteration, which only improves x;
+    // the reported count is the number executed and the loop stops only with rel <= tol.
+    const size_t nset = 3 * (size_t)semk::NRED;
+    auto enqueue = [&](int k) {
+      const bool first = (k == 0);
       if (c->use_graphs) {
         hipGraphExec_t* slot = fpcg ? (first ? &c->g_first : &c->g_iter) : &c->g_pdc;
         if (!*slot)
@@ -1424,15 +1441,48 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
         if (fpcg) fpcg_iteration(c, first);
         else pdc_iteration(c);
       }
-      read_sums(c, sums);
+      HK(hipMemcpyAsync(c->hscal + (k & 1) * nset, c->parts, nset * sizeof(double),
+                        hipMemcpyDeviceToHost, c->st));
+      HK(hipEventRecord(c->ev_it[k & 1], c->st));
+    };
+    auto collect = [&](int k) {
+      HK(hipEventSynchronize(c->ev_it[k & 1]));
+      const double* h = c->hscal + (k & 1) * nset;
+      for (int s = 0; s < 3; ++s) {
+        double v = 0.0;
+        for (int j = 0; j < semk::NRED; ++j) v += h[s * semk::NRED + j];
+        sums[s] = v;
+      }
+    };
+    int it = 0, launched = 0;
+    double rel_prev = -1.0;  // residual one iteration back (for the rate), < 0: unknown
+    while (st == SEM_OK && (rel > tol || launched > it)) {
+      if (rel > tol) {
+        if (it >= c->desc.maxit) {
+          st = SEM_ERR_NOT_CONVERGED;
+          set_err(c, "maximum number of outer iterations reached");
+          break;
+        }
+        if (launched == it) enqueue(launched++);
+        if (launched == it + 1 && launched < c->desc.maxit && rel_prev > 0.0 &&
+            rel * (rel / rel_prev) > 2.0 * tol)
+          enqueue(launched++);
+      }
+      collect(it);
       ++it;
       inf->vcycles++;
+      rel_prev = rel;
       rel = std::sqrt(sums[PS_RR] / bb);
       push(rel);
       if (!std::isfinite(rel) || (fpcg && !(sums[PS_PQ] > 0))) {
         st = SEM_ERR_BREAKDOWN;
         set_err(c, "breakdown in the outer iteration (non-finite residual or p.Ap <= 0)");
       }
+    }
+    while (launched > it) {  // after a breakdown: let the iteration in flight finish
+      collect(it);
+      ++it;
+      inf->vcycles++;
     }
     HK(hipMemcpyAsync(x, c->xo, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     leave(c);
@@ -1485,7 +1535,10 @@ static void stage_buffers(Ctx* c) {
   c->yq = dalloc(c, L.N * eb);
   c->Sq = dalloc(c, L.nS * eb);
   c->stparts = (double*)dalloc(
-      c, ((size_t)semm::stage_mlp_blocks(E) + semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl)) * 8);
+      c, ((size_t)semm::stage_mlp_blocks(E) +
+          std::max(semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl),
+                   semk::cheb2d_blocks(L.P, L.Nx, L.Nz, L.dbl))) *
+             8);
   c->stage_alloc = true;
 }
 

@@ -140,12 +140,16 @@ def params_p(P, seed, scale=1.0, bias=0.1):
 
 STAGE_CASES = [
     # (Nx, Nz, P, Lx, weight scale, seed): 64 elements (4 full tiles of 16) at P = 8 with
-    # positive, negative (always rejected) and small weights; ragged tiles at P = 4 and P = 3
+    # positive, negative (always rejected) and small weights; ragged tiles at P = 4 and P = 3;
+    # the fused kernels (residual, assembly with the apply of c) wherever the columns fit
     (16, 4, 8, 1.6, 1.0, 7),
     (16, 4, 8, 1.6, -1.0, 8),
     (16, 4, 8, 1.6, 0.3, 9),
     (5, 3, 4, 0.5, 1.0, 10),
     (7, 2, 3, 0.7, 0.5, 11),
+    # columns of 60 elements at P = 8: too tall for the fused kernels (operator with side
+    # buffer, separate assembly)
+    (2, 60, 8, 0.2, 1.0, 12),
 ]
 
 
