@@ -11,6 +11,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+
 #include "gll_const.h"
 #include "kernels.h"
 
@@ -32,12 +35,22 @@ __device__ __forceinline__ float gload<float, uint16_t>(const uint16_t* p) {
 
 static inline unsigned nblk(size_t n, unsigned t) { return (unsigned)((n + t - 1) / t); }
 
-// dynamic LDS above 64 KB (gfx950: 160 KB per workgroup) needs the kernel's limit raised
+// dynamic LDS above 64 KB (gfx950: 160 KB per workgroup) needs the kernel's limit raised; the
+// limit is raised once per kernel to the largest size asked for (the host call stays out of the
+// launch path afterwards)
 template <typename K>
 static hipError_t allow_lds(K kernel, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  static std::mutex mu;
+  static std::map<const void*, size_t> done;
+  const void* key = reinterpret_cast<const void*>(kernel);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = done.find(key);
+  if (it != done.end() && it->second >= bytes) return hipSuccess;
+  const hipError_t e =
+      hipFuncSetAttribute(key, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e == hipSuccess) done[key] = bytes;
+  return e;
 }
 
 // (A x)[g] from the column output y and the side buffer S (2D; S null: y is complete)
