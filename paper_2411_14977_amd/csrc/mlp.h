@@ -64,8 +64,9 @@ struct Stage {
   bool enabled = false;
   int nin = 0, nout = 0, P = 0, Nx = 0, Nz = 0, nzn = 0;
   size_t E = 0;
-  // bf16, padded, stored transposed (output-major, [n][k]) so that one lane's 4 consecutive
-  // k-values of an MFMA operand are contiguous: W1r [NH][KR], W2 [NH][NH], W3 [N3][NH]
+  // bf16, padded, transposed (output-major) and stored in MFMA A-operand fragment order:
+  // fragment (t, k) of an [M][K] matrix holds rows 16t.., columns 16k.. as 64 lanes x 4 values
+  // (lane l: row 16t + l%16, columns 16k + 4(l/16) + 0..3); W1r [NH][KR], W2 [NH][NH], W3 [N3][NH]
   uint16_t *W1r = nullptr, *W2 = nullptr, *W3 = nullptr;
   float *b2 = nullptr, *b3 = nullptr;
   float* Z1geo = nullptr;   // [E x NH] = geometric part of layer 1 + b1
@@ -87,11 +88,13 @@ int stage_mlp_blocks(size_t E);  // workgroups of stage_mlp (entries of its c . 
 // c = W sum_e R_e^T c_e, zero on the Dirichlet surface when masked
 hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStream_t st);
 // alpha = c.r / c.q from the partials (ncr of c.r, ncq of c.q); R holds r on entry; if accepted
-// x += alpha c and R = r - alpha q (q = yq + Sq, the side-buffer form of A c), else R = r and
-// skips[0] += 1
+// x += alpha c and R = r - alpha q (q = yq + Sq, the side-buffer form of A c; Sq null: q = yq
+// complete), else R = r and skips[0] += 1.  With dinv (post-smoothing follows): also the first
+// smoothing step from the stage's residual, dn = sr dinv R, d = dn (store_d), x += dn.
 hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* yq, const void* Sq,
                         const double* pcr, int ncr, const double* pcq, int ncq, int* skips,
-                        unsigned N, unsigned nzn, unsigned P, hipStream_t st);
+                        unsigned N, unsigned nzn, unsigned P, const void* dinv, void* d,
+                        double sr, int store_d, hipStream_t st);
 // Training features of an assembled residual r on a 2D mesh: X [E x 5n] fp32; targets T [E x n]
 // fp32 from the error e ((a_e/s_e) R_e e) or, if e is null, from the element-block inverses
 // Ainv [E x n x n] ((a_e/s_e) Ainv_e R_e r).

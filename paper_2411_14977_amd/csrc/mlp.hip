@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "host_math.h"
 #include "kernels.h"
@@ -731,63 +732,68 @@ __device__ double bsum(double v, double* sh) {
   return s;
 }
 
-// One wave carries 16 elements through the whole network in registers.  Every layer is computed
-// transposed, Z^T = W^T X^T: the weights (stored output-major, staged once per workgroup into
-// LDS with padded rows while the residual is being gathered) are the MFMA A operand, and the
-// activations the B operand.  The result of a 16x16x16 MFMA (lane l holds
-// rows 4(l/16)+v of column l%16) is then exactly the B operand of the next layer's k-step for
-// the same 16 rows, so the hidden activations never leave the registers and no workgroup
-// barrier is needed.  Per lane: element le = l%16 of the tile and, in every 16-block of
-// features, the slice kq..kq+3 (kq = 4 (l/16)); the residual gathered for layer 1 sits in the
-// same slices as the layer-3 output, so each lane also forms its part of c . r:
-// with c = W sum_e R_e^T c_e, c . r = sum_e sum_l c_e[l] r_g / m_g (g the global node of (e, l),
-// m_g its multiplicity, weight 0 on the Dirichlet surface when masked).  The workgroup's sum
-// goes to pcr[workgroup].
-// acc[t] += W^T(tile t) . xb, K = 16 KS: the weight fragments of k-step k + 1 are read from LDS
-// while the MFMAs of k-step k run (one wave per SIMD hides no latency otherwise)
+// acc[t] += W^T(tile t0 + t) . xb over KS k-steps, weights in fragment order (F[(tile KS + k) 64 +
+// lane]): the fragments of k-step k + 1 are read from LDS while the MFMAs of k-step k run
 template <int NTT, int KS>
-__device__ __forceinline__ void layer_mfma(const uint16_t* __restrict__ sW, int ld, int le, int kq,
+__device__ __forceinline__ void layer_mfma(const bf16x4* __restrict__ F, int t0, int lane,
                                            const bf16x4 (&xb)[KS], f32x4 (&acc)[NTT]) {
   bf16x4 w[2][NTT];
 #pragma unroll
-  for (int t = 0; t < NTT; ++t)
-    w[0][t] = *reinterpret_cast<const bf16x4*>(sW + (16 * t + le) * ld + kq);
+  for (int t = 0; t < NTT; ++t) w[0][t] = F[((t0 + t) * KS) * 64 + lane];
 #pragma unroll
   for (int k = 0; k < KS; ++k) {
     if (k + 1 < KS) {
 #pragma unroll
-      for (int t = 0; t < NTT; ++t)
-        w[(k + 1) & 1][t] = *reinterpret_cast<const bf16x4*>(sW + (16 * t + le) * ld + 16 * (k + 1) + kq);
+      for (int t = 0; t < NTT; ++t) w[(k + 1) & 1][t] = F[((t0 + t) * KS + k + 1) * 64 + lane];
     }
 #pragma unroll
     for (int t = 0; t < NTT; ++t) acc[t] = mfma16(w[k & 1][t], xb[k], acc[t]);
   }
 }
 
-constexpr int MLP_WAVES = 4;  // waves (16-element tiles) per workgroup
-constexpr int MLP_THREADS = 64 * MLP_WAVES;
+// Two waves carry a 16-element tile through the network, each computing half of every layer's
+// outputs.  Every layer is computed transposed, Z^T = W^T X^T: the weights (stored output-major,
+// staged once per workgroup into LDS with padded rows while the residual is being gathered) are
+// the MFMA A operand and the activations the B operand.  The result of a 16x16x16 MFMA (lane l
+// holds rows 4(l/16)+v of column l%16) is exactly the B operand of the next layer's k-step for
+// the same 16 rows, so a wave's half of the hidden activations goes to its partner through one
+// 8-byte LDS slot per lane and k-step (double-buffered between the layers, one barrier each).
+// Per lane: element le = l%16 of the tile and, in every 16-block of features, the slice
+// kq..kq+3 (kq = 4 (l/16)); the residual gathered for layer 1 sits in the same slices as the
+// layer-3 output, so each wave also forms its part of c . r for its output half:
+// with c = W sum_e R_e^T c_e, c . r = sum_e sum_l c_e[l] r_g / m_g (g the global node of (e, l),
+// m_g its multiplicity, weight 0 on the Dirichlet surface when masked).  The workgroup's sum
+// goes to pcr[workgroup].
+constexpr int MLP_TILES = 4;  // 16-element tiles per workgroup, two waves each
+constexpr int MLP_THREADS = 128 * MLP_TILES;
 
 template <int P, typename T>
-__global__ __launch_bounds__(MLP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 1))) void k_stage_mlp(
+__global__ __launch_bounds__(MLP_THREADS) void k_stage_mlp(
     const T* __restrict__ r, const uint16_t* __restrict__ W1r, const float* __restrict__ Z1geo,
     const uint16_t* __restrict__ W2, const float* __restrict__ b2,
     const uint16_t* __restrict__ W3, const float* __restrict__ b3,
     const float* __restrict__ abar, float* __restrict__ CE, int E, int Nx, int Nz, unsigned nzn,
     int masked, double* __restrict__ pcr) {
   constexpr int NP = P + 1, n = NP * NP, KR = (n + 15) / 16 * 16, KS = KR / 16, NT = NH / 16;
-  constexpr int W1S = KR + 8, WHS = NH + 8;  // LDS row strides (bf16) against bank conflicts
-  __shared__ __align__(16) uint16_t sW1[NH * W1S];
-  __shared__ __align__(16) uint16_t sW2[NH * WHS];
-  __shared__ __align__(16) uint16_t sW3[KR * WHS];
-  __shared__ double sred[MLP_WAVES];
+  constexpr int NTH = NT / 2;          // hidden tiles per wave
+  constexpr int K3 = (KS + 1) / 2;     // output tiles per wave (the second may have fewer)
+  // the network in LDS, in fragment order: every A-operand read is 64 lanes x 8 contiguous bytes
+  __shared__ __align__(16) uint16_t sW[(NH * KR + NH * NH + KR * NH)];
+  __shared__ bf16x4 sH[2][MLP_TILES][NT][64];  // exchanged hidden fragments (two buffers)
+  const bf16x4* F1 = reinterpret_cast<const bf16x4*>(sW);
+  const bf16x4* F2 = reinterpret_cast<const bf16x4*>(sW + NH * KR);
+  const bf16x4* F3 = reinterpret_cast<const bf16x4*>(sW + NH * KR + NH * NH);
+  __shared__ double sred[MLP_THREADS / 64];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = wave >> 1, h = wave & 1;
   const int le = lane & 15, kq = (lane >> 4) * 4;
-  const int e = (blockIdx.x * MLP_WAVES + wave) * 16 + le;
+  const int e = (blockIdx.x * MLP_TILES + tile) * 16 + le;
   const bool ve = e < E;
   const int ex = ve ? e / Nz : 0, ez = ve ? e - ex * Nz : 0;
   const unsigned base = (unsigned)(ex * P) * nzn + ez * P;
 
-  // residual of this lane's slices (fp32), element norm over the 4 lanes of the element
+  // residual of this lane's slices (fp32; both waves of a tile gather it), element norm over the
+  // 4 lanes of the element
   float rv[KS][4];
   float ss = 0.f;
 #pragma unroll
@@ -802,21 +808,13 @@ __global__ __launch_bounds__(MLP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
       }
       ss += rv[k][v] * rv[k][v];
     }
-  // the network into LDS (16-byte chunks), issued behind the residual loads
+  // the network into LDS (straight 16-byte copies), issued behind the residual loads
   {
-    constexpr int c1 = KR / 8, c2 = NH / 8;
-    for (int k = threadIdx.x; k < NH * c1; k += MLP_THREADS) {
-      const int rw = k / c1, q = k - rw * c1;
-      *reinterpret_cast<uint4*>(sW1 + rw * W1S + 8 * q) = *reinterpret_cast<const uint4*>(W1r + rw * KR + 8 * q);
-    }
-    for (int k = threadIdx.x; k < NH * c2; k += MLP_THREADS) {
-      const int rw = k / c2, q = k - rw * c2;
-      *reinterpret_cast<uint4*>(sW2 + rw * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W2 + rw * NH + 8 * q);
-    }
-    for (int k = threadIdx.x; k < KR * c2; k += MLP_THREADS) {
-      const int rw = k / c2, q = k - rw * c2;
-      *reinterpret_cast<uint4*>(sW3 + rw * WHS + 8 * q) = *reinterpret_cast<const uint4*>(W3 + rw * NH + 8 * q);
-    }
+    constexpr int c1 = NH * KR / 8, c2 = NH * NH / 8, c3 = KR * NH / 8;
+    uint4* d = reinterpret_cast<uint4*>(sW);
+    for (int k = threadIdx.x; k < c1; k += MLP_THREADS) d[k] = reinterpret_cast<const uint4*>(W1r)[k];
+    for (int k = threadIdx.x; k < c2; k += MLP_THREADS) d[c1 + k] = reinterpret_cast<const uint4*>(W2)[k];
+    for (int k = threadIdx.x; k < c3; k += MLP_THREADS) d[c1 + c2 + k] = reinterpret_cast<const uint4*>(W3)[k];
   }
   ss += __shfl_xor(ss, 16, 64);
   ss += __shfl_xor(ss, 32, 64);
@@ -828,64 +826,87 @@ __global__ __launch_bounds__(MLP_THREADS) __attribute__((amdgpu_waves_per_eu(1, 
 #pragma unroll
     for (int v = 0; v < 4; ++v) xb[k][v] = (short)f2bf(rv[k][v] * sinv);
 
-  // layer 1: Z1 = Xr W1r + Z1geo (the geometric part of X W1 + b1 is precomputed)
-  f32x4 acc[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-    acc[t] = ve ? *reinterpret_cast<const f32x4*>(Z1geo + (long)e * NH + 16 * t + kq)
-                : (f32x4){0.f, 0.f, 0.f, 0.f};
-  __syncthreads();
-  layer_mfma<NT, KS>(sW1, W1S, le, kq, xb, acc);
-  bf16x4 hb[NT];
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) hb[t][v] = (short)f2bf(gelu(acc[t][v]));
-
-  // layer 2: Z2 = H1 W2 + b2
-#pragma unroll
-  for (int t = 0; t < NT; ++t) acc[t] = *reinterpret_cast<const f32x4*>(b2 + 16 * t + kq);
-  layer_mfma<NT, NT>(sW2, WHS, le, kq, hb, acc);
-#pragma unroll
-  for (int t = 0; t < NT; ++t)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) hb[t][v] = (short)f2bf(gelu(acc[t][v]));
-
-  // layer 3: Y = H2 W3 + b3; c_e = (s_e / a_e) y, and this lane's part of c . r
-  const float sc = ve ? sn / abar[e] : 0.f;
-  f32x4 out[KS];
-#pragma unroll
-  for (int t = 0; t < KS; ++t) out[t] = *reinterpret_cast<const f32x4*>(b3 + 16 * t + kq);
-  layer_mfma<KS, NT>(sW3, WHS, le, kq, hb, out);
+  // three phases per half, with the half index a compile-time constant inside each (register
+  // arrays stay statically indexed); the barriers sit between the phases, outside any branch
   double part = 0.0;
+  f32x4 acc[NTH];
+  bf16x4 hb[NT];
+  auto layer1 = [&](auto hc) {  // Z1 = Xr W1r + Z1geo on hidden tiles NTH H ..
+    constexpr int H = decltype(hc)::value;
+    layer_mfma<NTH, KS>(F1, NTH * H, lane, xb, acc);
 #pragma unroll
-  for (int t = 0; t < KS; ++t) {
-    const f32x4 c = out[t];
+    for (int t = 0; t < NTH; ++t) {
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int loc = 16 * t + kq + v;
-      if (ve && loc < n) {
-        const float ce = sc * c[v];
-        const int i = loc / NP, j = loc - (loc / NP) * NP;
-        CE[semk::ce_index(ex, i, ez, j, Nz, NP)] = ce;
-        const int mx = ((i == 0 && ex > 0) || (i == P && ex < Nx - 1)) ? 2 : 1;
-        const int mz = ((j == 0 && ez > 0) || (j == P && ez < Nz - 1)) ? 2 : 1;
-        const bool top = masked && j == P && ez == Nz - 1;
-        if (!top) part += (double)ce * (double)rv[t][v] / (double)(mx * mz);
+      for (int v = 0; v < 4; ++v) hb[NTH * H + t][v] = (short)f2bf(gelu(acc[t][v]));
+      sH[0][tile][NTH * H + t][lane] = hb[NTH * H + t];
+    }
+  };
+  auto layer2 = [&](auto hc) {  // Z2 = H1 W2 + b2
+    constexpr int H = decltype(hc)::value;
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) hb[NTH * (1 - H) + t] = sH[0][tile][NTH * (1 - H) + t][lane];
+#pragma unroll
+    for (int t = 0; t < NTH; ++t)
+      acc[t] = *reinterpret_cast<const f32x4*>(b2 + 16 * (NTH * H + t) + kq);
+    layer_mfma<NTH, NT>(F2, NTH * H, lane, hb, acc);
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) hb[NTH * H + t][v] = (short)f2bf(gelu(acc[t][v]));
+      sH[1][tile][NTH * H + t][lane] = hb[NTH * H + t];
+    }
+  };
+  auto layer3 = [&](auto hc) {  // Y = H2 W3 + b3 on output tiles K3 H ..; c_e, c . r part
+    constexpr int H = decltype(hc)::value;
+    constexpr int T0 = K3 * H;
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) hb[NTH * (1 - H) + t] = sH[1][tile][NTH * (1 - H) + t][lane];
+    const float sc = ve ? sn / abar[e] : 0.f;
+#pragma unroll
+    for (int t = 0; t < K3; ++t) {
+      const int t3 = T0 + t;
+      if (T0 + t >= KS) break;
+      f32x4 c[1] = {*reinterpret_cast<const f32x4*>(b3 + 16 * t3 + kq)};
+      layer_mfma<1, NT>(F3, t3, lane, hb, c);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int loc = 16 * t3 + kq + v;
+        if (ve && loc < n) {
+          const float ce = sc * c[0][v];
+          const int i = loc / NP, j = loc - (loc / NP) * NP;
+          CE[semk::ce_index(ex, i, ez, j, Nz, NP)] = ce;
+          // 1 / multiplicity, exact: 1, 1/2 or 1/4
+          const double wx = ((i == 0 && ex > 0) || (i == P && ex < Nx - 1)) ? 0.5 : 1.0;
+          const double wz = ((j == 0 && ez > 0) || (j == P && ez < Nz - 1)) ? 0.5 : 1.0;
+          const bool top = masked && j == P && ez == Nz - 1;
+          if (!top) part += (double)ce * (double)rv[t3][v] * (wx * wz);
+        }
       }
     }
-  }
+  };
+  using H0 = std::integral_constant<int, 0>;
+  using H1 = std::integral_constant<int, 1>;
+#pragma unroll
+  for (int t = 0; t < NTH; ++t)
+    acc[t] = ve ? *reinterpret_cast<const f32x4*>(Z1geo + (long)e * NH + 16 * (NTH * h + t) + kq)
+                : (f32x4){0.f, 0.f, 0.f, 0.f};
+  __syncthreads();  // the network is in LDS
+  if (h == 0) layer1(H0{}); else layer1(H1{});
+  __syncthreads();
+  if (h == 0) layer2(H0{}); else layer2(H1{});
+  __syncthreads();
+  if (h == 0) layer3(H0{}); else layer3(H1{});
   part = wsum(part);
   if (lane == 0) sred[wave] = part;
   __syncthreads();
   if (threadIdx.x == 0) {
     double tot = 0.0;
-    for (int w = 0; w < MLP_WAVES; ++w) tot += sred[w];
+    for (int w = 0; w < MLP_THREADS / 64; ++w) tot += sred[w];
     pcr[blockIdx.x] = tot;
   }
 }
 
-int stage_mlp_blocks(size_t E) { return (int)((E + 16 * MLP_WAVES - 1) / (16 * MLP_WAVES)); }
+int stage_mlp_blocks(size_t E) { return (int)((E + 16 * MLP_TILES - 1) / (16 * MLP_TILES)); }
 
 hipError_t stage_mlp(const Stage& s, bool dbl, const void* r, int masked, double* pcr,
                      hipStream_t st) {
@@ -985,7 +1006,9 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
                                                        const T* __restrict__ yq, const T* __restrict__ Sq,
                                                        const double* __restrict__ pcr, int ncr,
                                                        const double* __restrict__ pcq, int ncq,
-                                                       int* skips, unsigned N, unsigned nzn, unsigned P) {
+                                                       int* skips, unsigned N, unsigned nzn, unsigned P,
+                                                       const T* __restrict__ dinv, T* __restrict__ d,
+                                                       T sr, int store_d) {
   __shared__ double sh[16];
   const unsigned stride = gridDim.x * blockDim.x;
   const unsigned g0 = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1007,35 +1030,47 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
   const double alpha = cr / cq;
   const bool ok = isfinite(alpha) && alpha > 0.0;
   const T al = ok ? (T)alpha : (T)0;
-  if (ok) {
+  // node g: x += alpha c, R = r - alpha q (accepted step); then, with dinv, the first smoothing
+  // step from that residual: dn = sr dinv R, d = dn (store_d), x += dn
+  auto node = [&](unsigned g, T r, T q, T cv) {
+    T xv = x[g];
+    if (ok) {
+      xv += al * cv;
+      r = r - al * q;
+      R[g] = r;
+    }
+    if (dinv) {
+      const T dn = sr * dinv[g] * r;
+      if (store_d) d[g] = dn;
+      xv += dn;
+    }
+    if (ok || dinv) x[g] = xv;
+  };
 #pragma unroll
-    for (int k = 0; k < UPD_IT; ++k) {
-      const unsigned g = g0 + k * stride;
-      if (g < N) {
-        x[g] += al * cc[k];
-        R[g] = rr[k] - al * qq[k];
-      }
-    }
-    for (unsigned g = g0 + UPD_IT * stride; g < N; g += stride) {
-      x[g] += al * c[g];
-      R[g] = R[g] - al * ax_at(yq, Sq, g, nzn, P);
-    }
+  for (int k = 0; k < UPD_IT; ++k) {
+    const unsigned g = g0 + k * stride;
+    if (g < N) node(g, rr[k], qq[k], cc[k]);
   }
+  for (unsigned g = g0 + UPD_IT * stride; g < N; g += stride)
+    node(g, R[g], ax_at(yq, Sq, g, nzn, P), c[g]);
   if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) skips[0] += 1;
 }
 
 hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* yq, const void* Sq,
                         const double* pcr, int ncr, const double* pcq, int ncq, int* skips,
-                        unsigned N, unsigned nzn, unsigned P, hipStream_t st) {
+                        unsigned N, unsigned nzn, unsigned P, const void* dinv, void* d,
+                        double sr, int store_d, hipStream_t st) {
   const unsigned blocks = nblk(N, 1024 * UPD_IT);
   if (dbl)
     hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(1024), 0, st, (double*)x,
                        (double*)R, (const double*)c, (const double*)yq, (const double*)Sq, pcr,
-                       ncr, pcq, ncq, skips, N, nzn, P);
+                       ncr, pcq, ncq, skips, N, nzn, P, (const double*)dinv, (double*)d, sr,
+                       store_d);
   else
     hipLaunchKernelGGL(k_stage_update<float>, dim3(blocks), dim3(1024), 0, st, (float*)x,
                        (float*)R, (const float*)c, (const float*)yq, (const float*)Sq, pcr, ncr,
-                       pcq, ncq, skips, N, nzn, P);
+                       pcq, ncq, skips, N, nzn, P, (const float*)dinv, (float*)d, (float)sr,
+                       store_d);
   return hipGetLastError();
 }
 

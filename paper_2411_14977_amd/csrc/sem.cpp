@@ -209,9 +209,24 @@ void smooth_step(Ctx* c, int l, double cd, double cr, int store_d) {
                          semk::SU_AX, store_d, c->st));
 }
 
+// coefficient and d-store flag of the first post-smoothing step taken from a known residual
+// (x += cr dinv r, d = that step when more steps follow)
+void first_post_step(const Ctx* c, int l, double* cr, int* store_d) {
+  const sem_mesh_desc& d = c->desc;
+  if (d.smoother == SEM_SMOOTH_JACOBI) {
+    *cr = d.jacobi_omega;
+    *store_d = 0;
+    return;
+  }
+  const double lam = c->lev[l].lam;
+  *cr = 1.0 / (0.5 * (d.cheb_hi * lam + d.cheb_lo * lam));
+  *store_d = d.cheb_degree > 1 ? 1 : 0;
+}
+
 // pre- or post-smoothing on level l; resid (post-smoothing only): the residual of the current x,
-// already known to the caller, which saves the first operator apply
-void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
+// already known to the caller, which saves the first operator apply; first_done: the caller has
+// already taken the first step from resid (first_post_step)
+void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr, bool first_done = false) {
   DLevel& L = c->lev[l];
   const sem_mesh_desc& d = c->desc;
   if (d.smoother == SEM_SMOOTH_JACOBI) {
@@ -224,6 +239,7 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
         continue;
       }
       const bool given = !pre && s == 0 && resid;
+      if (given && first_done) continue;
       if (!fz && !given) {
         smooth_step(c, l, 0.0, d.jacobi_omega, 0);
         continue;
@@ -242,6 +258,8 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr) {
   const bool given = !pre && resid;
   if (!pre && !given)
     smooth_step(c, l, 0.0, 1.0 / theta, k > 1 ? 1 : 0);
+  else if (given && first_done)
+    ;  // taken by the caller with the same coefficient (first_post_step)
   else if (pre && l == 0 && c->vin64)
     HK(semk::smooth_first64(L.dbl, L.x, L.d, L.b, c->vin64, L.dinv, L.N, 1.0 / theta,
                             k > 1 ? 1 : 0, c->st));
@@ -313,8 +331,9 @@ void coarse_solve(Ctx* c) {
   }
 }
 
-// learned stage on level 0: reads L.b, L.x; updates L.x, writes the new residual to Rbuf
-void learned_stage(Ctx* c) {
+// learned stage on level 0: reads L.b, L.x; updates L.x, writes the new residual to Rbuf.  post:
+// post-smoothing follows, and its first step from Rbuf is taken in the stage's update kernel
+void learned_stage(Ctx* c, bool post = false) {
   DLevel& L = c->lev[0];
   semm::Stage& s = c->stage;
   const int ncr = semm::stage_mlp_blocks(s.E);
@@ -323,12 +342,16 @@ void learned_stage(Ctx* c) {
   HK(semk::resid2d(L.P, L.dbl, L.gt, L.x, c->Rbuf, L.b, L.G, L.Nx, L.Nz, c->masked, L.y, L.S,
                    c->st));
   HK(semm::stage_mlp(s, L.dbl, c->Rbuf, c->masked, pcr, c->st));
+  double sr = 0.0;
+  int store_d = 0;
+  if (post) first_post_step(c, 0, &sr, &store_d);
+  const void* dinv = post ? L.dinv : nullptr;
   const int nfused = semk::cheb2d_blocks(L.P, L.Nx, L.Nz, L.dbl);
   if (nfused > 0) {  // assembly fused with the apply of c: q complete, no side buffer
     HK(semk::stagecq2d(L.P, L.dbl, L.gt, s.CE, c->cbuf, c->yq, L.G, L.Nx, L.Nz, c->masked, pcq,
                        c->st));
     HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, c->yq, nullptr, pcr, ncr, pcq, nfused,
-                          s.skips, L.N, L.nzn, L.P, c->st));
+                          s.skips, L.N, L.nzn, L.P, dinv, L.d, sr, store_d, c->st));
     return;
   }
   HK(semm::stage_assemble(s, L.dbl, c->cbuf, c->masked, c->st));
@@ -336,7 +359,7 @@ void learned_stage(Ctx* c) {
                        c->st));
   HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, c->yq, c->Sq, pcr, ncr, pcq,
                         semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl), s.skips, L.N, L.nzn, L.P,
-                        c->st));
+                        dinv, L.d, sr, store_d, c->st));
 }
 
 // z = B r on level 0 buffers: input r (FP64, device), output lev[0].x
@@ -369,8 +392,8 @@ void vcycle(Ctx* c, const double* r) {
   for (int l = L - 2; l >= 0; --l) {
     prolong_from(c, l);
     if (l == 0 && c->stage.enabled && (c->stage_mode & 2)) {
-      learned_stage(c);
-      smooth(c, l, false, c->Rbuf);  // starts from the stage's updated residual
+      learned_stage(c, true);             // also the first post-smoothing step from its residual
+      smooth(c, l, false, c->Rbuf, true);
       continue;
     }
     smooth(c, l, false);
@@ -1626,9 +1649,22 @@ static void learned_load_impl(Ctx* c, const void* blob, size_t nbytes, int enabl
       for (int q = 0; q < cols; ++q) T[(size_t)q * rows + r] = W[(size_t)r * cols + q];
     return T;
   };
-  put16(s.W1r, bf16_vec(transpose(net.W1.data(), n, NH).data(), NH, n, NH, KR));
-  put16(s.W2, bf16_vec(transpose(net.W2.data(), NH, NH).data(), NH, NH, NH, NH));
-  put16(s.W3, bf16_vec(transpose(net.W3.data(), NH, n).data(), n, NH, N3, NH));
+  // MFMA A-operand fragment order of an output-major [M][K] matrix (M, K multiples of 16):
+  // fragment (t, k) = rows 16t.., columns 16k.., as 64 lanes x 4 values, lane l holding row
+  // 16t + l%16, columns 16k + 4(l/16) + 0..3 (one contiguous 8-byte read per lane)
+  auto frag = [](const std::vector<uint16_t>& W, int M, int K) {
+    std::vector<uint16_t> F(W.size());
+    size_t o = 0;
+    for (int t = 0; t < M / 16; ++t)
+      for (int k = 0; k < K / 16; ++k)
+        for (int l = 0; l < 64; ++l)
+          for (int v = 0; v < 4; ++v)
+            F[o++] = W[(size_t)(16 * t + l % 16) * K + 16 * k + 4 * (l / 16) + v];
+    return F;
+  };
+  put16(s.W1r, frag(bf16_vec(transpose(net.W1.data(), n, NH).data(), NH, n, NH, KR), NH, KR));
+  put16(s.W2, frag(bf16_vec(transpose(net.W2.data(), NH, NH).data(), NH, NH, NH, NH), NH, NH));
+  put16(s.W3, frag(bf16_vec(transpose(net.W3.data(), NH, n).data(), n, NH, N3, NH), N3, NH));
   HK(hipMemcpy(s.b2, net.b2.data(), NH * 4, hipMemcpyHostToDevice));
   std::vector<float> b3(N3, 0.f);
   std::copy(net.b3.begin(), net.b3.end(), b3.begin());
