@@ -14,8 +14,9 @@ stream; the plain operator apply beside it) and the CPU
 oracle timed on a bounded sample of the same workload.
 
 A 3D time series (64 x 64 x 8, P = 6, moving surface, warm starts, frozen preconditioner) is
-reported beside it (--c5-steps, 0 to skip), and the mixed-precision error table of the
-2048 x 16 tank at tolerances 1e-6, 1e-8, 1e-10 (--no-c3 to skip).
+reported beside it (--c5-steps, 0 to skip), the mixed-precision error table of the 2048 x 16
+tank at tolerances 1e-6, 1e-8, 1e-10 (--no-c3 to skip), and the same solve with the paper's
+additive Schwarz smoother in place of Chebyshev (--no-schwarz to skip).
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload c4] [--prec bf16]
                        [--no-learned] [--surfaces 4] [--c5-steps 20] [--no-cpu] [--no-fp64]
@@ -241,6 +242,25 @@ def c3_error_table():
     return out
 
 
+def schwarz_rows(wl, rhs, prec, steps):
+    """The paper's additive Schwarz smoother (element blocks, Sec. 6.3) in place of Chebyshev on
+    every level, same workload, precision and outer loop, 1 and 2 sweeps before and after."""
+    import torch
+
+    from paper_2411_14977_amd import cases
+    out = {}
+    for nu in (1, 2):
+        t0 = time.perf_counter()
+        s = cases.make_solver(wl, prec=prec, smoother="asm", nu_pre=nu, nu_post=nu)
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        t, info, _ = time_solves(s, rhs, steps, 1, 1e-10)
+        out[f"sweeps_{nu}"] = {"ms_per_solve": t * 1e3, "iters": info.iters,
+                               "rel_res": info.rel_res, "setup_s": t_setup}
+        s.close()
+    return out
+
+
 def traffic_from_profiles(kernel_tag):
     """HBM traffic per launch measured by rocprofv3 PMC passes (profiles/*.json), only if
     the kernel source is unchanged since the counters were taken."""
@@ -327,6 +347,7 @@ def main():
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--c5-steps", type=int, default=20, help="3D time-series steps (0: skip)")
     ap.add_argument("--no-c3", action="store_true", help="skip the c3 mixed-precision error table")
+    ap.add_argument("--no-schwarz", action="store_true", help="skip the Schwarz-smoother rows")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -433,6 +454,11 @@ def main():
         if args.surfaces > 0:
             surf = unseen_surfaces(args, blob, args.surfaces)
 
+    schwarz = None
+    if not args.no_schwarz:
+        schwarz = schwarz_rows(wl, rhs, args.prec, max(2, args.steps))
+        log(f"[bench] Schwarz smoother: {schwarz}")
+
     c3 = None
     if not args.no_c3:
         c3 = c3_error_table()
@@ -461,7 +487,8 @@ def main():
            "learned_skips": info.learned_skips, "oracle_rel_res": res_check,
            "mixed_without_stage": plain_mixed, "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
-           "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf, "c3_error_table": c3, "c5_series": c5,
+           "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,
+           "schwarz_smoother": schwarz, "c3_error_table": c3, "c5_series": c5,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 

@@ -47,8 +47,12 @@ typedef enum {
 
 /* inner (V-cycle) precision */
 enum { SEM_F64 = 0, SEM_F32 = 1, SEM_F32_GBF16 = 2 };
-/* smoother on every level above the coarsest */
-enum { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_CHEBYSHEV = 1 };
+/* smoother on every level above the coarsest.  SEM_SMOOTH_SCHWARZ: the additive Schwarz
+ * method of Sec. 6.3 with element blocks, nu_pre / nu_post sweeps of
+ * x += W sum_i R_i^T (R_i A R_i^T)^{-1} R_i (b - A x), W = (sum_i R_i^T R_i)^{-1}; 2D meshes with
+ * fine order P <= 8 only; the inverses of the element blocks are built at set-up (host FP64)
+ * and stored per level in the inner precision (E (P_l+1)^4 values). */
+enum { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_CHEBYSHEV = 1, SEM_SMOOTH_SCHWARZ = 2 };
 /* outer iteration */
 enum { SEM_OUTER_FPCG = 0, SEM_OUTER_PDC = 1 };
 /* Dirichlet faces bitmask */
@@ -70,7 +74,7 @@ typedef struct {
   unsigned dirichlet_faces;    /* SEM_FACE_TOP (default) or 0 = pure Neumann (apply only)   */
   int inner_prec;              /* SEM_F64 | SEM_F32 | SEM_F32_GBF16                         */
   int smoother;                /* SEM_SMOOTH_*                                               */
-  int nu_pre, nu_post;         /* Jacobi sweeps                                             */
+  int nu_pre, nu_post;         /* Jacobi and Schwarz sweeps                                 */
   int cheb_degree;             /* Chebyshev degree (pre and post)                           */
   double jacobi_omega;         /* damping, default 2/3                                      */
   double cheb_lo, cheb_hi;     /* Chebyshev interval as fractions of lambda_hat (0.1, 1.1)  */

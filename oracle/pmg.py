@@ -7,9 +7,13 @@ Sec. 6 of the paper:
 * prolongation from interpolation, I_{Pp} = Phi^p V^{-1}, applied per element and per
   direction (tensor product), and restriction R = P^T (Sec. 6.2);
 * a fixed number of smoothing steps on every level before and after the coarse correction
-  (Sec. 6.3, V-cycle of Sec. 6); the smoothers here are damped Jacobi and Chebyshev
-  acceleration of Jacobi (polynomials in D^{-1} A), with the paper's additive Schwarz smoother
-  kept in ``asm_element_solve``;
+  (Sec. 6.3, V-cycle of Sec. 6); the smoothers here are damped Jacobi, Chebyshev acceleration
+  of Jacobi (polynomials in D^{-1} A) and the paper's additive Schwarz smoother (Sec. 6.3):
+  x <- x + S^{-1}(b - A x), S^{-1} = W sum_i R_i^T (R_i A R_i^T)^{-1} R_i,
+  W = (sum_i R_i R_i^T)^{-1}.  Its subdomains are read as the element blocks (each element's
+  (P+1)^d nodes; blocks of neighbouring elements share their face nodes, and no further overlap
+  nodes are added); 2D only (3D blocks of 343 nodes would need 31 GB of local inverses at the
+  64x64x8 benchmark size);
 * the coarsest (P = 1) problem solved exactly (sparse direct).  In 3D the paper's P = 1 grid is
   too large for an exact solve at the benchmark size; the hierarchy is continued below it by
   coarsening the mesh by 2 in x and y (P = 1, linear interpolation in x and y, identity in
@@ -81,6 +85,25 @@ class Level:
         self.N = mesh.N
         self.lam = None          # largest eigenvalue estimate of D^{-1} A
         self.lu = None
+        self._blocks = None
+
+    def schwarz_blocks(self):
+        """Inverses of the element blocks R_i A R_i^T (A the masked assembled matrix) and the
+        weights W = (sum_i R_i R_i^T)^{-1} (one over the number of blocks holding a node)."""
+        if self._blocks is None:
+            A = self.A.tocsr()
+            inv = [np.linalg.inv(A[idx][:, idx].toarray()) for idx in self.mesh.l2g]
+            w = 1.0 / np.bincount(self.mesh.l2g.ravel(), minlength=self.N)
+            self._blocks = (inv, w)
+        return self._blocks
+
+    def schwarz(self, r, weighted=True):
+        """S^{-1} r = W sum_i R_i^T (R_i A R_i^T)^{-1} R_i r (weighted=False: without W)."""
+        inv, w = self.schwarz_blocks()
+        z = np.zeros(self.N)
+        for Ai, idx in zip(inv, self.mesh.l2g):
+            np.add.at(z, idx, Ai @ r[idx])
+        return w * z if weighted else z
 
 
 class Hierarchy:
@@ -168,9 +191,18 @@ class Hierarchy:
             x = x + d
         return x
 
+    def schwarz_sweeps(self, l, b, x, sweeps):
+        """Additive Schwarz smoothing (Sec. 6.3): x <- x - S^{-1}(A x - b), ``sweeps`` times."""
+        L = self.levels[l]
+        for _ in range(sweeps):
+            x = x + L.schwarz(b - L.A @ x)
+        return x
+
     def smooth(self, l, b, x, pre):
         if self.smoother == "jacobi":
             return self.jacobi(l, b, x, self.nu_pre if pre else self.nu_post)
+        if self.smoother == "asm":
+            return self.schwarz_sweeps(l, b, x, self.nu_pre if pre else self.nu_post)
         return self.chebyshev(l, b, x, self.cheb_degree)
 
     # ---- V-cycle -----------------------------------------------------------------------

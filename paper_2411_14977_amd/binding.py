@@ -8,7 +8,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libsem.so")
 
 SEM_F64, SEM_F32, SEM_F32_GBF16 = 0, 1, 2
-SEM_SMOOTH_JACOBI, SEM_SMOOTH_CHEBYSHEV = 0, 1
+SEM_SMOOTH_JACOBI, SEM_SMOOTH_CHEBYSHEV, SEM_SMOOTH_SCHWARZ = 0, 1, 2
 SEM_OUTER_FPCG, SEM_OUTER_PDC = 0, 1
 SEM_FACE_TOP = 1
 SEM_MAX_LEVELS = 8
@@ -366,7 +366,8 @@ class Solver:
         d.eta = self._eta.ctypes.data_as(dp)
         d.dirichlet_faces = SEM_FACE_TOP if dirichlet else 0
         d.inner_prec = _PREC[prec]
-        d.smoother = SEM_SMOOTH_JACOBI if smoother == "jacobi" else SEM_SMOOTH_CHEBYSHEV
+        d.smoother = {"jacobi": SEM_SMOOTH_JACOBI, "chebyshev": SEM_SMOOTH_CHEBYSHEV,
+                      "asm": SEM_SMOOTH_SCHWARZ}[smoother]
         d.nu_pre, d.nu_post, d.cheb_degree = nu_pre, nu_post, cheb_degree
         d.jacobi_omega, d.cheb_lo, d.cheb_hi = jacobi_omega, cheb_lo, cheb_hi
         d.outer = SEM_OUTER_PDC if outer == "pdc" else SEM_OUTER_FPCG

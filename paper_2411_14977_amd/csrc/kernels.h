@@ -54,6 +54,12 @@ __host__ __device__ inline long ce_index(int ex, int i, int ez, int j, int Nz, i
 // each workgroup's part of c . q in dotp[0 .. cheb2d_blocks)
 hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* q, const void* G,
                      int Nx, int Nz, int masked, double* dotp, hipStream_t st);
+// additive Schwarz sweep tail (2D, P <= 8): z_e = Ainv_e R_e r for every element (Ainv
+// [E][(P+1)^2][(P+1)^2], symmetric, element e = ex Nz + ez; z in the layout of ce_index), then
+// x = (set ? 0 : x) + W sum_e R_e^T z_e (W: one over the number of elements holding a node); the
+// Dirichlet surface is left alone (set: zeroed) when masked
+hipError_t asm_sweep(int P, bool dbl, const void* r, const void* Ainv, void* z, void* x, int Nx,
+                     int Nz, int masked, int set, hipStream_t st);
 // residual r = b - A x, complete at every node (2D); fused with the operator where cheb2d_cpb
 // allows, else apply2d into the scratch y, S and an element-wise pass.  r must differ from x.
 hipError_t resid2d(int P, bool dbl, GType gt, const void* x, void* r, const void* b,

@@ -665,6 +665,97 @@ hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* 
   }
 }
 
+// ------------------------------------------------------------------------------------------
+// additive Schwarz smoothing (Sec. 6.3), element blocks
+// ------------------------------------------------------------------------------------------
+// z_e = (R_e A R_e^T)^{-1} R_e r for every element: one thread per row of an element block,
+// 256 / (P+1)^2 elements per workgroup; the element's residual is staged in LDS and the
+// (symmetric) inverse read column by column, so consecutive rows read consecutive addresses.
+// Ainv: [E][n][n] (element e = ex Nz + ez); z in the layout of ce_index.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_asm_local(const T* __restrict__ r,
+                                                   const T* __restrict__ Ainv, T* __restrict__ z,
+                                                   int E, int Nz, int nzn) {
+  constexpr int NP = P + 1, n = NP * NP, EPB = 256 / n;
+  __shared__ T sr[EPB][n];
+  const int el = threadIdx.x / n, row = threadIdx.x - el * n;
+  const int e = blockIdx.x * EPB + el;
+  const bool act = el < EPB && e < E;
+  const int ex = act ? e / Nz : 0, ez = act ? e - ex * Nz : 0;
+  const int i = row / NP, j = row - (row / NP) * NP;
+  if (act) sr[el][row] = r[(size_t)(ex * P + i) * nzn + ez * P + j];
+  __syncthreads();
+  if (!act) return;
+  const T* Ae = Ainv + (size_t)e * n * n + row;
+  T acc = 0;
+#pragma unroll 9
+  for (int k = 0; k < n; ++k) acc += Ae[(size_t)k * n] * sr[el][k];
+  z[ce_index(ex, i, ez, j, Nz, NP)] = acc;
+}
+
+// x = (set ? 0 : x) + W sum_e R_e^T z_e: at every node the average of the block results of the
+// elements holding it (fixed order: (left, lower), (left, upper), (right, lower), (right,
+// upper)); the Dirichlet surface keeps x (zero there in the V-cycle) when masked.
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_asm_add(const T* __restrict__ z, T* __restrict__ x,
+                                                 int Nx, int Nz, unsigned nzn, unsigned N,
+                                                 int masked, int set) {
+  constexpr int NP = P + 1;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const int ix = g / nzn, iz = g - ix * nzn;
+    if (masked && iz == (int)nzn - 1) {
+      if (set) x[g] = (T)0;
+      continue;
+    }
+    const int qx = ix / P, rx = ix - qx * P, qz = iz / P, rz = iz - qz * P;
+    const bool xl = rx == 0 && qx > 0, xr = qx < Nx, zl = rz == 0 && qz > 0, zr = qz < Nz;
+    T s = 0;
+    int cnt = 0;
+    if (xl && zl) { s += z[ce_index(qx - 1, P, qz - 1, P, Nz, NP)]; ++cnt; }
+    if (xl && zr) { s += z[ce_index(qx - 1, P, qz, rz, Nz, NP)]; ++cnt; }
+    if (xr && zl) { s += z[ce_index(qx, rx, qz - 1, P, Nz, NP)]; ++cnt; }
+    if (xr && zr) { s += z[ce_index(qx, rx, qz, rz, Nz, NP)]; ++cnt; }
+    const T c = s / (T)cnt;
+    x[g] = set ? c : x[g] + c;
+  }
+}
+
+template <int P>
+static hipError_t asm_p(bool dbl, const void* r, const void* Ainv, void* z, void* x, int Nx,
+                        int Nz, int masked, int set, hipStream_t st) {
+  constexpr int n = (P + 1) * (P + 1), EPB = 256 / n;
+  const int E = Nx * Nz, nzn = Nz * P + 1;
+  const unsigned N = (unsigned)((size_t)(Nx * P + 1) * nzn);
+  const unsigned b1 = (unsigned)((E + EPB - 1) / EPB), b2 = std::min(nblk(N, 256), 8192u);
+  if (dbl) {
+    hipLaunchKernelGGL((k_asm_local<P, double>), dim3(b1), dim3(256), 0, st, (const double*)r,
+                       (const double*)Ainv, (double*)z, E, Nz, nzn);
+    hipLaunchKernelGGL((k_asm_add<P, double>), dim3(b2), dim3(256), 0, st, (const double*)z,
+                       (double*)x, Nx, Nz, (unsigned)nzn, N, masked, set);
+  } else {
+    hipLaunchKernelGGL((k_asm_local<P, float>), dim3(b1), dim3(256), 0, st, (const float*)r,
+                       (const float*)Ainv, (float*)z, E, Nz, nzn);
+    hipLaunchKernelGGL((k_asm_add<P, float>), dim3(b2), dim3(256), 0, st, (const float*)z,
+                       (float*)x, Nx, Nz, (unsigned)nzn, N, masked, set);
+  }
+  return hipGetLastError();
+}
+
+hipError_t asm_sweep(int P, bool dbl, const void* r, const void* Ainv, void* z, void* x, int Nx,
+                     int Nz, int masked, int set, hipStream_t st) {
+  switch (P) {
+    case 1: return asm_p<1>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    case 2: return asm_p<2>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    case 3: return asm_p<3>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    case 4: return asm_p<4>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    case 5: return asm_p<5>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    case 6: return asm_p<6>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    case 7: return asm_p<7>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    case 8: return asm_p<8>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <typename T>
 __global__ void k_resid_fix(const T* __restrict__ b, const T* __restrict__ y,
                             const T* __restrict__ S, T* __restrict__ r, unsigned N, unsigned nzn,

@@ -8,6 +8,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <exception>
+#include <functional>
+#include <thread>
 #include <chrono>
 #include <utility>
 #include <cmath>
@@ -40,6 +43,8 @@ struct DLevel {
   // 2D smoothed levels where the fused smoother step fits: the second solution vector; each
   // fused step reads x and writes xalt, then the two swap (x is always the current iterate)
   void* xalt = nullptr;
+  // Schwarz smoother: inverses of the element blocks [E][n][n] and the element results [E][n]
+  void *Ainv_s = nullptr, *Zs = nullptr;
   size_t nS = 0;
   double lam = 0.0;
   // 3D: side buffers of the operator (completed into y by the face fix-up; S stays null) and
@@ -172,6 +177,77 @@ std::vector<TG> permute_G2d(const semh::LevelGeom& L, const std::vector<double>&
   return out;
 }
 
+// run f(lo, hi) over [0, n) on up to 16 host threads (set-up work only)
+void parallel_ranges(size_t n, const std::function<void(size_t, size_t)>& f) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t T = std::min<size_t>(std::min(16u, hw), std::max<size_t>(1, n / 64));
+  if (T <= 1) {
+    f(0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  std::vector<std::exception_ptr> errs(T);
+  for (size_t t = 0; t < T; ++t)
+    th.emplace_back([&, t]() {
+      try {
+        f(n * t / T, n * (t + 1) / T);
+      } catch (...) {
+        errs[t] = std::current_exception();
+      }
+    });
+  for (auto& x : th) x.join();
+  for (auto& e : errs)
+    if (e) std::rethrow_exception(e);
+}
+
+// Inverses of the element blocks R_e A R_e^T of the masked assembled operator of a 2D level
+// (the local matrices of the Schwarz smoother, Sec. 6.3), from factors Gr in the level's
+// storage precision: each block is the element's own matrix plus, on the nodes it shares with
+// its (up to eight) neighbours, their element matrices' entries between those nodes; rows and
+// columns of Dirichlet surface nodes are identity when masked.  Output [E][n][n], host FP64.
+std::vector<double> schwarz_inverses(const semh::LevelGeom& G, const std::vector<double>& Gr,
+                                     bool masked) {
+  const int P = G.P, NP = G.NP, n = NP * NP, Nx = G.Nx, Nz = G.Nz;
+  const size_t E = G.E, nn = (size_t)n * n;
+  std::vector<double> Aall(E * nn);
+  parallel_ranges(E, [&](size_t lo, size_t hi) {
+    for (size_t e = lo; e < hi; ++e) semh::element_matrix(G, Gr, e, &Aall[e * nn]);
+  });
+  std::vector<double> out(E * nn);
+  parallel_ranges(E, [&](size_t lo, size_t hi) {
+    std::vector<double> B(nn), Bi(nn);
+    std::vector<std::pair<int, int>> sh;  // (neighbour local node, this element's local node)
+    for (size_t e = lo; e < hi; ++e) {
+      const int ex = (int)(e / Nz), ez = (int)(e % Nz);
+      std::copy(&Aall[e * nn], &Aall[e * nn] + nn, B.begin());
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dz = -1; dz <= 1; ++dz) {
+          const int nx = ex + dx, nz = ez + dz;
+          if ((dx == 0 && dz == 0) || nx < 0 || nx >= Nx || nz < 0 || nz >= Nz) continue;
+          sh.clear();
+          for (int i = 0; i < NP; ++i)
+            for (int j = 0; j < NP; ++j) {
+              const int li = nx * P + i - ex * P, lj = nz * P + j - ez * P;
+              if (li >= 0 && li <= P && lj >= 0 && lj <= P) sh.push_back({i * NP + j, li * NP + lj});
+            }
+          const double* An = &Aall[((size_t)nx * Nz + nz) * nn];
+          for (const auto& a : sh)
+            for (const auto& b : sh) B[(size_t)a.second * n + b.second] += An[(size_t)a.first * n + b.first];
+        }
+      if (masked && ez == Nz - 1)
+        for (int i = 0; i < NP; ++i) {  // local nodes (i, P) lie on the surface
+          const int t = i * NP + P;
+          for (int k = 0; k < n; ++k) B[(size_t)t * n + k] = B[(size_t)k * n + t] = 0.0;
+          B[(size_t)t * n + t] = 1.0;
+        }
+      if (!semh::dense_inverse_public(n, B.data(), Bi.data()))
+        throw ArgFail{"singular element block in the Schwarz smoother"};
+      std::copy(Bi.begin(), Bi.end(), out.begin() + e * nn);
+    }
+  });
+  return out;
+}
+
 void set_err(Ctx* c, const std::string& s) { c->err = s; }
 
 // ------------------------------------------------------------------------------------------
@@ -229,6 +305,26 @@ void first_post_step(const Ctx* c, int l, double* cr, int* store_d) {
 void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr, bool first_done = false) {
   DLevel& L = c->lev[l];
   const sem_mesh_desc& d = c->desc;
+  if (d.smoother == SEM_SMOOTH_SCHWARZ) {
+    const int nu = pre ? d.nu_pre : d.nu_post;
+    for (int s = 0; s < nu; ++s) {
+      const bool fz = pre && s == 0;  // x = 0 on entry: r = b
+      const void* r = nullptr;
+      if (fz) {
+        if (l == 0 && c->vin64) HK(semk::cast_to(L.dbl, c->vin64, L.b, L.N, c->st));
+        r = L.b;
+      } else if (!pre && s == 0 && resid) {
+        r = resid;
+      } else {  // residual of the current x into the level's d vector (unused by this smoother)
+        HK(semk::resid2d(L.P, L.dbl, L.gt, L.x, L.d, L.b, L.G, L.Nx, L.Nz, c->masked, L.y, L.S,
+                         c->st));
+        r = L.d;
+      }
+      HK(semk::asm_sweep(L.P, L.dbl, r, L.Ainv_s, L.Zs, L.x, L.Nx, L.Nz, c->masked, fz ? 1 : 0,
+                         c->st));
+    }
+    return;
+  }
   if (d.smoother == SEM_SMOOTH_JACOBI) {
     const int nu = pre ? d.nu_pre : d.nu_post;
     for (int s = 0; s < nu; ++s) {
@@ -392,8 +488,9 @@ void vcycle(Ctx* c, const double* r) {
   for (int l = L - 2; l >= 0; --l) {
     prolong_from(c, l);
     if (l == 0 && c->stage.enabled && (c->stage_mode & 2)) {
-      learned_stage(c, true);             // also the first post-smoothing step from its residual
-      smooth(c, l, false, c->Rbuf, true);
+      const bool fold = c->desc.smoother != SEM_SMOOTH_SCHWARZ;
+      learned_stage(c, fold);  // with fold, also the first post-smoothing step from its residual
+      smooth(c, l, false, c->Rbuf, fold);
       continue;
     }
     smooth(c, l, false);
@@ -898,13 +995,16 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   c->masked = (d->dirichlet_faces & SEM_FACE_TOP) ? 1 : 0;
   c->prec = d->inner_prec;
   if (c->prec < SEM_F64 || c->prec > SEM_F32_GBF16) throw ArgFail{"bad inner_prec"};
-  if (d->smoother != SEM_SMOOTH_JACOBI && d->smoother != SEM_SMOOTH_CHEBYSHEV)
+  if (d->smoother != SEM_SMOOTH_JACOBI && d->smoother != SEM_SMOOTH_CHEBYSHEV &&
+      d->smoother != SEM_SMOOTH_SCHWARZ)
     throw ArgFail{"bad smoother"};
+  if (d->smoother == SEM_SMOOTH_SCHWARZ && (d->dim != 2 || d->order > 8))
+    throw ArgFail{"the Schwarz smoother is built for 2D meshes with order <= 8"};
   if (d->outer != SEM_OUTER_FPCG && d->outer != SEM_OUTER_PDC) throw ArgFail{"bad outer"};
   if (d->smoother == SEM_SMOOTH_CHEBYSHEV &&
       (d->cheb_degree < 1 || !(d->cheb_hi > d->cheb_lo) || d->cheb_lo <= 0))
     throw ArgFail{"bad Chebyshev parameters"};
-  if (d->smoother == SEM_SMOOTH_JACOBI && (d->nu_pre < 0 || d->nu_post < 0))
+  if (d->smoother != SEM_SMOOTH_CHEBYSHEV && (d->nu_pre < 0 || d->nu_post < 0))
     throw ArgFail{"bad sweep counts"};
   std::vector<int> orders;
   if (d->nlevels <= 0) {
@@ -996,6 +1096,13 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     L.S = dalloc(c, L.nS * eb);
     if (!coarsest && L.P <= 8 && semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl) > 0)
       L.xalt = dalloc(c, L.N * eb);
+    if (!coarsest && d->smoother == SEM_SMOOTH_SCHWARZ) {
+      const size_t n = (size_t)L.NP * L.NP;
+      std::vector<double> inv = schwarz_inverses(L.geo, Gr, c->masked != 0);
+      if (L.dbl) L.Ainv_s = upload(c, inv);
+      else L.Ainv_s = upload(c, std::vector<float>(inv.begin(), inv.end()));
+      L.Zs = dalloc(c, L.geo.E * n * eb);
+    }
   }
   for (int l = 0; l + 1 < nl; ++l) {
     DLevel& F = c->lev[l];

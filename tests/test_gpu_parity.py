@@ -140,7 +140,7 @@ def test_coarse_solve_exact(name):
 
 
 @pytest.mark.parametrize("name", ["tank8", "ragged", "tall"])
-@pytest.mark.parametrize("smoother", ["jacobi", "chebyshev"])
+@pytest.mark.parametrize("smoother", ["jacobi", "chebyshev", "asm"])
 def test_smoothers(smoother, name):
     wl = CASES[name]
     H_ = oc.hierarchy(wl, smoother=smoother)
@@ -337,3 +337,38 @@ def test_benchmark_hooks():
         B.sem_time_operator(t.ctx, 0, 2, 1, 0)   # P = 8 columns of 60 elements: no fused step
     assert B.sem_time_operator(t.ctx, 1, 2, 1, 0) > 0
     t.close()
+
+
+# ---- additive Schwarz smoother (Sec. 6.3) -------------------------------------------------
+@pytest.mark.parametrize("name", ["tank8", "ragged", "c2"])
+def test_vcycle_schwarz(name):
+    wl = CASES[name]
+    H_ = oc.hierarchy(wl, smoother="asm")
+    s = lib_solver(name, smoother="asm")
+    L0 = H_.levels[0]
+    r = W.random_vector(L0.N, 901)
+    r[L0.dn] = 0.0
+    assert rel(H(s.vcycle(T(r))), H_.vcycle(r)) < 1e-12
+    s.close()
+
+
+@pytest.mark.parametrize("prec,bar", [("f64", 1e-9), ("f32", 1e-8), ("bf16", 1e-8)])
+@pytest.mark.parametrize("name", ["tank8", "c2"])
+def test_solve_schwarz_matches_direct(name, prec, bar):
+    wl = CASES[name]
+    m = oc.fine_mesh(wl)
+    A = assemble.assemble_operator(m)
+    b = oc.rhs(wl, m)
+    xd = assemble.solve_direct(A, b)
+    s = lib_solver(name, prec=prec, smoother="asm", nu_pre=1, nu_post=1)
+    x, info, _ = s.solve(T(b), tol=1e-10)
+    err = np.linalg.norm(H(x) - xd) / np.linalg.norm(xd)
+    print(f"[gpu] Schwarz solve {name} {prec}: {info.iters} iterations, error {err:.2e}", flush=True)
+    assert info.rel_res <= 1e-10 and err <= bar
+    s.close()
+
+
+def test_schwarz_rejects_3d():
+    wl = W.tank3d(2, 2, 2, 2, L=0.4, name="t3s")
+    with pytest.raises(B.SemError):
+        cases.make_solver(wl, smoother="asm")
