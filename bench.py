@@ -15,8 +15,9 @@ oracle timed on a bounded sample of the same workload.
 
 A 3D time series (64 x 64 x 8, P = 6, moving surface, warm starts, frozen preconditioner) is
 reported beside it (--c5-steps, 0 to skip), the mixed-precision error table of the 2048 x 16
-tank at tolerances 1e-6, 1e-8, 1e-10 (--no-c3 to skip), and the same solve with the paper's
-additive Schwarz smoother in place of Chebyshev (--no-schwarz to skip).
+tank at tolerances 1e-6, 1e-8, 1e-10 (--no-c3 to skip), the same solve with the paper's
+additive Schwarz smoother in place of Chebyshev (--no-schwarz), and the paper's multigrid
+iteration table and scaling sweeps rerun on tank meshes with two element layers (--no-context).
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload c4] [--prec bf16]
                        [--no-learned] [--surfaces 4] [--c5-steps 20] [--no-cpu] [--no-fp64]
@@ -261,6 +262,42 @@ def schwarz_rows(wl, rhs, prec, steps):
     return out
 
 
+def paper_context(prec):
+    """The paper's multigrid-efficiency experiments (Sec. 7, table of iterations per tolerance
+    and the scaling figure) rerun with this solver on the synthetic tank: N_z = 2, P = 8,
+    N_x = 102 at tolerances 1e-4, 1e-6, 1e-8 (PDC and FPCG), then at 1e-6 the iterations and
+    time against N_x (P = 8, element width fixed at 0.25 m) and against P (N_x = 200).  Inner
+    precision as the timed path, Chebyshev(3) smoothing; context, not the headline."""
+    import torch
+
+    import workloads as W
+    from paper_2411_14977_amd import cases
+
+    def run(Nx, P, outer, tols):
+        wl = W.tank(Nx, 2, P, Lx=0.25 * Nx, name=f"ctx{Nx}p{P}")
+        s = cases.make_solver(wl, prec=prec, outer=outer)
+        rhs = cases.make_rhs(wl, s)
+        rows = {}
+        for tol in tols:
+            t, info, _ = time_solves(s, rhs, 2, 1, tol)
+            rows[f"{tol:g}"] = {"iters": info.iters, "ms": t * 1e3}
+        s.close()
+        return wl.n_global, rows
+
+    out = {"table": {}, "scaling_nx": [], "scaling_p": []}
+    for outer in ("pdc", "fpcg"):
+        n, rows = run(102, 8, outer, (1e-4, 1e-6, 1e-8))
+        out["table"][outer] = {"n_global": n, **rows}
+    for Nx in (25, 50, 100, 200, 400, 800):
+        n, rows = run(Nx, 8, "fpcg", (1e-6,))
+        out["scaling_nx"].append({"Nx": Nx, "P": 8, "n_global": n, **rows["1e-06"]})
+    for P in (2, 3, 4, 5, 6, 7, 8):
+        n, rows = run(200, P, "fpcg", (1e-6,))
+        out["scaling_p"].append({"Nx": 200, "P": P, "n_global": n, **rows["1e-06"]})
+    torch.cuda.synchronize()
+    return out
+
+
 def traffic_from_profiles(kernel_tag):
     """HBM traffic per launch measured by rocprofv3 PMC passes (profiles/*.json), only if
     the kernel source is unchanged since the counters were taken."""
@@ -348,6 +385,8 @@ def main():
     ap.add_argument("--c5-steps", type=int, default=20, help="3D time-series steps (0: skip)")
     ap.add_argument("--no-c3", action="store_true", help="skip the c3 mixed-precision error table")
     ap.add_argument("--no-schwarz", action="store_true", help="skip the Schwarz-smoother rows")
+    ap.add_argument("--no-context", action="store_true",
+                    help="skip the paper-shaped iteration table and scaling sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
@@ -454,6 +493,11 @@ def main():
         if args.surfaces > 0:
             surf = unseen_surfaces(args, blob, args.surfaces)
 
+    context = None
+    if not args.no_context:
+        context = paper_context(args.prec)
+        log(f"[bench] paper-shaped runs: {context['table']}")
+
     schwarz = None
     if not args.no_schwarz:
         schwarz = schwarz_rows(wl, rhs, args.prec, max(2, args.steps))
@@ -488,7 +532,8 @@ def main():
            "mixed_without_stage": plain_mixed, "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
            "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,
-           "schwarz_smoother": schwarz, "c3_error_table": c3, "c5_series": c5,
+           "schwarz_smoother": schwarz, "paper_context": context, "c3_error_table": c3,
+           "c5_series": c5,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
