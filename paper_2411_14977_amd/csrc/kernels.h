@@ -108,14 +108,29 @@ hipError_t cast_from(bool dbl_src, const void* src, double* dst, unsigned N, hip
 hipError_t fill(bool dbl, void* p, double v, size_t n, hipStream_t st);
 
 // ---- p-transfers (2D, pull form, one workgroup per element column) ------------------------
-// rc = P^T r with r = b - Ax (use_ax) or r = b; coarse Dirichlet rows zero when masked.
+// The learned stage's step folded into the transfers around the coarse correction (fine level,
+// stage before the restriction): alpha = c.r / c.q from its partial sums (0 if not finite and
+// positive; the restriction counts the rejection in skips[0]); the restriction takes the fine
+// residual b - alpha q, the prolongation adds alpha c with the correction.  Null q / c: no fold.
+struct StageFold {
+  const void* q = nullptr;
+  const void* c = nullptr;
+  const double* pcr = nullptr;
+  int ncr = 0;
+  const double* pcq = nullptr;
+  int ncq = 0;
+  int* skips = nullptr;
+};
+// rc = P^T r with r = b - Ax (use_ax), r = b - alpha q (f.q) or r = b; coarse Dirichlet rows
+// zero when masked.
 size_t restrict2d_smem(int Pf, int Pc, int Nz, bool dbl);
 hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const void* S,
                       int use_ax, void* rc, const double* J, int Nx, int Nz, int Pf, int Pc,
-                      int masked, hipStream_t st);
+                      int masked, hipStream_t st, StageFold f = StageFold());
+// xf += P ec (+ alpha c with f.c)
 size_t prolong2d_smem(int Pf, int Pc, int Nz, bool dbl);
 hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
-                     int Nz, int Pf, int Pc, hipStream_t st);
+                     int Nz, int Pf, int Pc, hipStream_t st, StageFold f = StageFold());
 
 // ---- exact coarse solve (block cyclic reduction, FP64, in place on b, result in x) ---------
 // unknown r of block blk sits at blk * bstride + r + r / nzf (nzf = free nodes per line)

@@ -91,6 +91,20 @@ __device__ double sum_partials(const double* __restrict__ p, double* sh) {
   return block_sum(v, sh);
 }
 
+// step length of the learned stage, alpha = c.r / c.q from its two partial-sum sets (fixed
+// order, the same value in every block); 0 when not finite and positive (step rejected)
+__device__ double stage_alpha(const double* __restrict__ pcr, int ncr,
+                              const double* __restrict__ pcq, int ncq, double* sh, bool* ok) {
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = threadIdx.x; k < ncr; k += blockDim.x) a0 += pcr[k];
+  for (int k = threadIdx.x; k < ncq; k += blockDim.x) a1 += pcq[k];
+  const double cr = block_sum(a0, sh);
+  const double cq = block_sum(a1, sh);
+  const double alpha = cr / cq;
+  *ok = isfinite(alpha) && alpha > 0.0;
+  return *ok ? alpha : 0.0;
+}
+
 // ------------------------------------------------------------------------------------------
 // 2D operator apply
 // ------------------------------------------------------------------------------------------
@@ -1507,8 +1521,17 @@ template <typename T, typename TC>
 __global__ void k_restrict2d(const T* __restrict__ b, const T* __restrict__ y,
                              const T* __restrict__ S, int use_ax, TC* __restrict__ rc,
                              const double* __restrict__ Jg, int Nx, int Nz, int Pf, int Pc,
-                             int masked) {
+                             int masked, StageFold f) {
   const int ex = blockIdx.x;
+  // learned-stage fold: the fine residual is b - alpha q (the stage's updated residual)
+  T al = 0;
+  const T* fq = static_cast<const T*>(f.q);
+  if (fq) {
+    __shared__ double sh[8];
+    bool ok;
+    al = (T)stage_alpha(f.pcr, f.ncr, f.pcq, f.ncq, sh, &ok);
+    if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) f.skips[0] += 1;
+  }
   const int nzf = Nz * Pf + 1, nzc = Nz * Pc + 1;
   const int L0 = ex > 0 ? (ex - 1) * Pf : 0;
   const int L1 = ex * Pf + Pf;
@@ -1523,7 +1546,8 @@ __global__ void k_restrict2d(const T* __restrict__ b, const T* __restrict__ y,
     const int iz = k - (k / nzf) * nzf;
     const unsigned g = (unsigned)line * nzf + iz;
     T r = b[g];
-    if (use_ax) r -= ax_at(y, S, g, (unsigned)nzf, (unsigned)Pf);
+    if (fq) r = r - al * fq[g];
+    else if (use_ax) r -= ax_at(y, S, g, (unsigned)nzf, (unsigned)Pf);
     if (masked && iz == nzf - 1) r = 0;
     rf[k] = r;
   }
@@ -1559,7 +1583,7 @@ size_t restrict2d_smem(int Pf, int Pc, int Nz, bool dbl) {
 
 hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const void* S,
                       int use_ax, void* rc, const double* J, int Nx, int Nz, int Pf, int Pc,
-                      int masked, hipStream_t st) {
+                      int masked, hipStream_t st, StageFold f) {
   const size_t smem = restrict2d_smem(Pf, Pc, Nz, dbl);
   const hipError_t e = dbl     ? allow_lds(k_restrict2d<double, double>, smem)
                        : dbl_c ? allow_lds(k_restrict2d<float, double>, smem)
@@ -1568,22 +1592,31 @@ hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const 
   if (dbl)
     hipLaunchKernelGGL((k_restrict2d<double, double>), dim3(Nx), dim3(256), smem, st,
                        (const double*)b, (const double*)y, (const double*)S, use_ax,
-                       (double*)rc, J, Nx, Nz, Pf, Pc, masked);
+                       (double*)rc, J, Nx, Nz, Pf, Pc, masked, f);
   else if (dbl_c)
     hipLaunchKernelGGL((k_restrict2d<float, double>), dim3(Nx), dim3(256), smem, st,
                        (const float*)b, (const float*)y, (const float*)S, use_ax, (double*)rc,
-                       J, Nx, Nz, Pf, Pc, masked);
+                       J, Nx, Nz, Pf, Pc, masked, f);
   else
     hipLaunchKernelGGL((k_restrict2d<float, float>), dim3(Nx), dim3(256), smem, st,
                        (const float*)b, (const float*)y, (const float*)S, use_ax, (float*)rc,
-                       J, Nx, Nz, Pf, Pc, masked);
+                       J, Nx, Nz, Pf, Pc, masked, f);
   return hipGetLastError();
 }
 
 template <typename T, typename TC>
 __global__ void k_prolong2d(const TC* __restrict__ ec, T* __restrict__ xf,
-                            const double* __restrict__ Jg, int Nx, int Nz, int Pf, int Pc) {
+                            const double* __restrict__ Jg, int Nx, int Nz, int Pf, int Pc,
+                            StageFold f) {
   const int ex = blockIdx.x;
+  // learned-stage fold: the stage's step alpha c is added together with the correction
+  T al = 0;
+  const T* fc = static_cast<const T*>(f.c);
+  if (fc) {
+    __shared__ double sh[8];
+    bool ok;
+    al = (T)stage_alpha(f.pcr, f.ncr, f.pcq, f.ncq, sh, &ok);
+  }
   const int nzf = Nz * Pf + 1, nzc = Nz * Pc + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sJ = reinterpret_cast<T*>(smem_raw);  // (Pf+1)(Pc+1)
@@ -1609,7 +1642,9 @@ __global__ void k_prolong2d(const TC* __restrict__ ec, T* __restrict__ xf,
     const int i = k / nzf, izf = k - i * nzf;
     T s = 0;
     for (int q = 0; q <= Pc; ++q) s += sJ[i * (Pc + 1) + q] * tv[q * nzf + izf];
-    xf[fb + k] += s;
+    T xv = xf[fb + k];
+    if (fc) xv += al * fc[fb + k];
+    xf[fb + k] = xv + s;
   }
 }
 
@@ -1620,7 +1655,7 @@ size_t prolong2d_smem(int Pf, int Pc, int Nz, bool dbl) {
 }
 
 hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
-                     int Nz, int Pf, int Pc, hipStream_t st) {
+                     int Nz, int Pf, int Pc, hipStream_t st, StageFold f) {
   const size_t smem = prolong2d_smem(Pf, Pc, Nz, dbl);
   const hipError_t e = dbl     ? allow_lds(k_prolong2d<double, double>, smem)
                        : dbl_c ? allow_lds(k_prolong2d<float, double>, smem)
@@ -1628,13 +1663,13 @@ hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const doubl
   if (e != hipSuccess) return e;
   if (dbl)
     hipLaunchKernelGGL((k_prolong2d<double, double>), dim3(Nx), dim3(256), smem, st,
-                       (const double*)ec, (double*)xf, J, Nx, Nz, Pf, Pc);
+                       (const double*)ec, (double*)xf, J, Nx, Nz, Pf, Pc, f);
   else if (dbl_c)
     hipLaunchKernelGGL((k_prolong2d<float, double>), dim3(Nx), dim3(256), smem, st,
-                       (const double*)ec, (float*)xf, J, Nx, Nz, Pf, Pc);
+                       (const double*)ec, (float*)xf, J, Nx, Nz, Pf, Pc, f);
   else
     hipLaunchKernelGGL((k_prolong2d<float, float>), dim3(Nx), dim3(256), smem, st,
-                       (const float*)ec, (float*)xf, J, Nx, Nz, Pf, Pc);
+                       (const float*)ec, (float*)xf, J, Nx, Nz, Pf, Pc, f);
   return hipGetLastError();
 }
 

@@ -428,8 +428,11 @@ void coarse_solve(Ctx* c) {
 }
 
 // learned stage on level 0: reads L.b, L.x; updates L.x, writes the new residual to Rbuf.  post:
-// post-smoothing follows, and its first step from Rbuf is taken in the stage's update kernel
-void learned_stage(Ctx* c, bool post = false) {
+// post-smoothing follows, and its first step from Rbuf is taken in the stage's update kernel.
+// fold (pre-smoothing position): where the fused kernels apply, the update is left to the
+// restriction (residual r - alpha q) and the prolongation (x += alpha c): *f is filled and Rbuf
+// keeps r; otherwise f->q stays null and the update runs here
+void learned_stage(Ctx* c, bool post = false, semk::StageFold* f = nullptr) {
   DLevel& L = c->lev[0];
   semm::Stage& s = c->stage;
   const int ncr = semm::stage_mlp_blocks(s.E);
@@ -446,6 +449,16 @@ void learned_stage(Ctx* c, bool post = false) {
   if (nfused > 0) {  // assembly fused with the apply of c: q complete, no side buffer
     HK(semk::stagecq2d(L.P, L.dbl, L.gt, s.CE, c->cbuf, c->yq, L.G, L.Nx, L.Nz, c->masked, pcq,
                        c->st));
+    if (f) {
+      f->q = c->yq;
+      f->c = c->cbuf;
+      f->pcr = pcr;
+      f->ncr = ncr;
+      f->pcq = pcq;
+      f->ncq = nfused;
+      f->skips = s.skips;
+      return;
+    }
     HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, c->yq, nullptr, pcr, ncr, pcq, nfused,
                           s.skips, L.N, L.nzn, L.P, dinv, L.d, sr, store_d, c->st));
     return;
@@ -470,15 +483,16 @@ void vcycle(Ctx* c, const double* r) {
     coarse_solve(c);
     return;
   }
+  semk::StageFold fold;  // the pre-smoothing stage's step, when folded into the transfers
   for (int l = 0; l < L - 1; ++l) {
     smooth(c, l, true);
     if (l == 0) c->vin64 = nullptr;
     if (l == 0 && c->stage.enabled && (c->stage_mode & 1)) {
-      learned_stage(c);
+      learned_stage(c, false, &fold);  // the step goes into the transfers when fold.q is set
       DLevel& F = c->lev[0];
       DLevel& C1 = c->lev[1];
       HK(semk::restrict2d(F.dbl, C1.dbl, c->Rbuf, nullptr, nullptr, 0, C1.b, F.J, F.Nx, F.Nz, F.P,
-                          C1.P, c->masked, c->st));
+                          C1.P, c->masked, c->st, fold));
       continue;
     }
     apply_level(c, l, c->lev[l].x, c->masked);
@@ -486,7 +500,13 @@ void vcycle(Ctx* c, const double* r) {
   }
   coarse_solve(c);
   for (int l = L - 2; l >= 0; --l) {
-    prolong_from(c, l);
+    if (l == 0 && fold.c) {
+      DLevel& F = c->lev[0];
+      DLevel& C1 = c->lev[1];
+      HK(semk::prolong2d(F.dbl, C1.dbl, C1.x, F.x, F.J, F.Nx, F.Nz, F.P, C1.P, c->st, fold));
+    } else {
+      prolong_from(c, l);
+    }
     if (l == 0 && c->stage.enabled && (c->stage_mode & 2)) {
       const bool fold = c->desc.smoother != SEM_SMOOTH_SCHWARZ;
       learned_stage(c, fold);  // with fold, also the first post-smoothing step from its residual
