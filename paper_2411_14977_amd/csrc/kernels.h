@@ -142,6 +142,20 @@ hipError_t bcr_dense(const double* Ainv, const double* b, double* x, int nd, int
                      int bstride, int nzf, hipStream_t st);
 
 // ---- FP64 outer-loop kernels (deterministic two-stage reductions over NRED partials) -------
+// FPCG direction step fused with the FP64 operator (2D where the fused layout fits with at most
+// NRED workgroups): q = A (z + beta p) complete (first: q = A z), partials of p.q into ppq_new
+// (entries beyond the workgroup count are left alone: keep them zero), beta into *beta_out;
+// then update_xrp: p = z + beta p, x += alpha p, r -= alpha q with alpha = sum(prz_new) /
+// sum(ppq_new), r.r partials, and the partial sets moved to prz_old / ppq_old.
+bool fpcg2d_fits(int P, int Nx, int Nz);
+hipError_t fpcg2d(int P, const double* z, const double* p, double* q, const double* G, int Nx,
+                  int Nz, int masked, const double* prz_old, const double* ppq_old,
+                  const double* pzq, int first, double* ppq_new, double* beta_out,
+                  hipStream_t st);
+hipError_t update_xrp(double* x, double* r, double* p, const double* z, const double* q,
+                      const double* beta, int first, const double* prz_new,
+                      const double* ppq_new, double* prz_old, double* ppq_old, double* prr,
+                      unsigned N, hipStream_t st);
 // r = b - Ax (with fix); partial sums of r.r into prr and (if pbb) b.b into pbb
 hipError_t resid64(const double* b, const double* y, const double* S, double* r, double* prr,
                    double* pbb, unsigned N, unsigned nzn, unsigned P, hipStream_t st);

@@ -770,6 +770,161 @@ hipError_t asm_sweep(int P, bool dbl, const void* r, const void* Ainv, void* z, 
   }
 }
 
+// One FPCG direction step of the outer loop fused with the FP64 operator (2D, halo layout of
+// k_cheb2d): every node's p = z + beta p_old (first: p = z) is formed while loading, with
+// beta = -alpha_old (z.q_old) / (r.z)_old and alpha_old = (r.z)_old / (p.q)_old from the partial
+// sets prz_old, ppq_old, pzq; then q = A p, complete at every owned node, and each workgroup's
+// part of p . q into ppq_new.  p itself is not written here (other workgroups still read the old
+// p); block 0 stores beta in *beta_out for the update kernel.
+template <int P>
+__global__ __launch_bounds__(1024) void k_fpcg2d(const double* __restrict__ z,
+                                                 const double* __restrict__ p,
+                                                 double* __restrict__ q,
+                                                 const double* __restrict__ G, int Nx, int Nz,
+                                                 int masked, int cpb, int remap,
+                                                 const double* __restrict__ prz_old,
+                                                 const double* __restrict__ ppq_old,
+                                                 const double* __restrict__ pzq, int first,
+                                                 double* __restrict__ ppq_new,
+                                                 double* __restrict__ beta_out) {
+  constexpr int NP = P + 1;
+  constexpr int V = lds_vec<double>();
+  constexpr int NPp = (NP + V - 1) / V * V;
+  const int nzn = Nz * P + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int nthr = NP * Nz;
+  __shared__ double sh[16];
+  double beta = 0.0;
+  if (!first) {
+    const double rz = sum_partials(prz_old, sh);
+    const double pq = sum_partials(ppq_old, sh);
+    const double zq = sum_partials(pzq, sh);
+    beta = -(rz / pq) * zq / rz;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = beta;
+  int bx = blockIdx.x;
+  if (remap) {
+    const int per = gridDim.x >> 3;
+    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int cs = threadIdx.x / nthr;
+  const int t = threadIdx.x - cs * nthr;
+  const int ex = bx * cpb + cs - 1;
+  const bool valid = cs <= cpb && ex >= 0 && ex < Nx;
+  const int slot = slot2d_elems<int>(NP, Nz, nzp, V);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  double* base = reinterpret_cast<double*>(smem_raw) + (valid ? cs : 0) * slot;
+  const size_t cb = (size_t)(valid ? ex : 0) * P * nzn + t;
+  double xin[NP];
+  column_apply<P, double, double>(
+      [&](double(&v)[NP]) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          const size_t g = cb + (size_t)l * nzn;
+          v[l] = first ? z[g] : fma(beta, p[g], z[g]);
+        }
+      },
+      G, valid ? ex : 0, nthr, t, valid, Nz, nzn, nzp, masked, base, xin, [] {});
+  double part = 0.0;
+  if (cs >= 1 && valid && t < nzn) {
+    const double* su = base + Nz * NP * NPp;
+    const double* sl = su - slot;
+    const bool left = ex > 0 && !(masked && t == nzn - 1);
+    const int nl = (ex == Nx - 1) ? NP : P;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      if (l < nl) {
+        double ax = su[l * nzp + t];
+        if (l == 0 && left) ax += sl[P * nzp + t];
+        q[cb + (size_t)l * nzn] = ax;
+        part += xin[l] * ax;
+      }
+    }
+  }
+  const double tot = block_sum(part, sh);
+  if (threadIdx.x == 0) ppq_new[blockIdx.x] = tot;
+}
+
+template <int P>
+static hipError_t launch_fpcg2d(const double* z, const double* p, double* q, const double* G,
+                                int Nx, int Nz, int masked, const double* prz_old,
+                                const double* ppq_old, const double* pzq, int first,
+                                double* ppq_new, double* beta_out, hipStream_t st) {
+  const int cpb = cheb2d_cpb(P, Nx, Nz, true);
+  if (cpb <= 0) return hipErrorInvalidValue;
+  const int nthr = (P + 1) * Nz;
+  const int threads = (((cpb + 1) * nthr + 63) / 64) * 64;
+  const int blocks = (Nx + cpb - 1) / cpb;
+  const size_t smem = apply2d_smem(P, Nz, true) * (cpb + 1);
+  if (threads > 1024 || smem > 160 * 1024 || blocks > NRED) return hipErrorInvalidValue;
+  const int remap = (blocks % 8 == 0) ? 1 : 0;
+  hipError_t e = allow_lds(k_fpcg2d<P>, smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_fpcg2d<P>), dim3(blocks), dim3(threads), smem, st, z, p, q, G, Nx, Nz,
+                     masked, cpb, remap, prz_old, ppq_old, pzq, first, ppq_new, beta_out);
+  return hipGetLastError();
+}
+
+bool fpcg2d_fits(int P, int Nx, int Nz) {
+  return P >= 1 && P <= 8 && cheb2d_blocks(P, Nx, Nz, true) > 0 &&
+         cheb2d_blocks(P, Nx, Nz, true) <= NRED;
+}
+
+hipError_t fpcg2d(int P, const double* z, const double* p, double* q, const double* G, int Nx,
+                  int Nz, int masked, const double* prz_old, const double* ppq_old,
+                  const double* pzq, int first, double* ppq_new, double* beta_out,
+                  hipStream_t st) {
+  switch (P) {
+#define SEM_FPCG2D(PP) \
+  case PP: return launch_fpcg2d<PP>(z, p, q, G, Nx, Nz, masked, prz_old, ppq_old, pzq, first, ppq_new, beta_out, st);
+    SEM_FPCG2D(1) SEM_FPCG2D(2) SEM_FPCG2D(3) SEM_FPCG2D(4)
+    SEM_FPCG2D(5) SEM_FPCG2D(6) SEM_FPCG2D(7) SEM_FPCG2D(8)
+#undef SEM_FPCG2D
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// the FPCG update after k_fpcg2d: p = z + beta p (first: p = z, beta from k_fpcg2d, the same
+// fused multiply-add), alpha = (r.z) / (p.q) from prz_new and ppq_new; x += alpha p,
+// r -= alpha q, partials of r.r into prr; block 0 moves the partial sets for the next
+// iteration (prz_new -> prz_old, ppq_new -> ppq_old)
+__global__ __launch_bounds__(RED_THREADS) void k_update_xrp(
+    double* __restrict__ x, double* __restrict__ r, double* __restrict__ p,
+    const double* __restrict__ z, const double* __restrict__ q, const double* __restrict__ beta_in,
+    int first, const double* prz_new, const double* ppq_new, double* prz_old, double* ppq_old,
+    double* prr, unsigned N) {
+  __shared__ double sh[16];
+  const double rz = sum_partials(prz_new, sh);
+  const double pq = sum_partials(ppq_new, sh);
+  const double alpha = rz / pq;
+  const double beta = *beta_in;
+  double a = 0;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
+    const double pv = first ? z[g] : fma(beta, p[g], z[g]);
+    p[g] = pv;
+    x[g] += alpha * pv;
+    const double rv = r[g] - alpha * q[g];
+    r[g] = rv;
+    a += rv * rv;
+  }
+  a = block_sum(a, sh);
+  if (threadIdx.x == 0) prr[blockIdx.x] = a;
+  if (blockIdx.x == 0)
+    for (int k = threadIdx.x; k < NRED; k += blockDim.x) {
+      prz_old[k] = prz_new[k];
+      ppq_old[k] = ppq_new[k];
+    }
+}
+
+hipError_t update_xrp(double* x, double* r, double* p, const double* z, const double* q,
+                      const double* beta, int first, const double* prz_new,
+                      const double* ppq_new, double* prz_old, double* ppq_old, double* prr,
+                      unsigned N, hipStream_t st) {
+  hipLaunchKernelGGL(k_update_xrp, dim3(NRED), dim3(RED_THREADS), 0, st, x, r, p, z, q, beta,
+                     first, prz_new, ppq_new, prz_old, ppq_old, prr, N);
+  return hipGetLastError();
+}
+
 template <typename T>
 __global__ void k_resid_fix(const T* __restrict__ b, const T* __restrict__ y,
                             const T* __restrict__ S, T* __restrict__ r, unsigned N, unsigned nzn,

@@ -113,7 +113,7 @@ struct Ctx {
   std::vector<void*> allocs;
 };
 
-enum { PS_RR = 0, PS_BB, PS_PQ, PS_RZA, PS_RZB, PS_ZQ, PS_TMP, PS_NSETS };
+enum { PS_RR = 0, PS_BB, PS_PQ, PS_RZA, PS_RZB, PS_ZQ, PS_TMP, PS_PQ2, PS_NSETS };
 
 struct HipFail {
   hipError_t e;
@@ -527,6 +527,16 @@ void fpcg_iteration(Ctx* c, bool first) {
   vcycle(c, c->ro);
   HK(semk::castdot(L0.dbl, L0.x, c->zo, first ? nullptr : c->qo, c->ro, pset(c, PS_ZQ),
                    pset(c, PS_RZB), N, c->st));
+  if (c->dim == 2 && semk::fpcg2d_fits(L0.P, L0.Nx, L0.Nz)) {
+    // direction update fused with the FP64 operator, then the x / r update (beta in scal[8])
+    double* beta = c->scal + 8;
+    HK(semk::fpcg2d(L0.P, c->zo, c->po, c->qo, c->G64, L0.Nx, L0.Nz, c->masked, pset(c, PS_RZA),
+                    pset(c, PS_PQ), pset(c, PS_ZQ), first ? 1 : 0, pset(c, PS_PQ2), beta, c->st));
+    HK(semk::update_xrp(c->xo, c->ro, c->po, c->zo, c->qo, beta, first ? 1 : 0,
+                        pset(c, PS_RZB), pset(c, PS_PQ2), pset(c, PS_RZA), pset(c, PS_PQ),
+                        pset(c, PS_RR), N, c->st));
+    return;
+  }
   HK(semk::pupdate(c->po, c->zo, pset(c, PS_RZA), pset(c, PS_PQ), pset(c, PS_ZQ), first ? 1 : 0,
                    N, c->st));
   apply_outer(c, c->po, c->masked);
