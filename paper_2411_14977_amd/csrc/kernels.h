@@ -42,6 +42,12 @@ int cheb2d_cpb(int P, int Nx, int Nz, bool dbl);
 hipError_t cheb2d(int P, bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
                   const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
                   double cr, int store_d, hipStream_t st);
+// the first two steps of a pre-smoothing from x = 0 in one fused kernel (where cheb2d_cpb > 0):
+// x1 = d1 = cr0 dinv b; r = b - A x1; dn = cr dinv r (+ cd d1); d = dn (store_d); x = x1 + dn.
+// r64 (optional): FP64 right-hand side, rounded into b.  x, d, b written in place.
+hipError_t cheb2d_first(int P, bool dbl, GType gt, void* x, void* d, void* b, const double* r64,
+                        const void* dinv, const void* G, int Nx, int Nz, int masked, double cr0,
+                        double cd, double cr, int store_d, hipStream_t st);
 int cheb2d_blocks(int P, int Nx, int Nz, bool dbl);  // workgroups of the fused kernels (0: none)
 // Element-local corrections of the learned stage, line-major per element column: value (i, j)
 // of element (ex, ez) at [((ex (P+1) + i) Nz + ez) (P+1) + j], so that the values along a

@@ -484,6 +484,89 @@ __global__ __launch_bounds__(1024) void k_cheb2d(const T* __restrict__ xi, T* __
   }
 }
 
+// The first two smoother steps of a pre-smoothing from x = 0 in one kernel: step 0,
+// x1 = d1 = cr0 dinv b, is formed while loading (for the halo column too); then step 1 as in
+// k_cheb2d: r = b - A x1, dn = cr dinv r (+ cd d1), d = dn (store_d), x = x1 + dn.  With r64
+// the right-hand side arrives in FP64 and is rounded into b here (owned nodes written).  x and
+// d are written in place: no workgroup reads them.
+template <int P, typename T, typename TG>
+__global__ __launch_bounds__(1024) void k_cheb2d_first(T* __restrict__ x, T* __restrict__ d,
+                                                       T* __restrict__ b,
+                                                       const double* __restrict__ r64,
+                                                       const T* __restrict__ dinv,
+                                                       const TG* __restrict__ G, int Nx, int Nz,
+                                                       int masked, int cpb, int remap, T cr0,
+                                                       T cd, T cr, int store_d) {
+  constexpr int NP = P + 1;
+  constexpr int V = lds_vec<T>();
+  constexpr int NPp = (NP + V - 1) / V * V;
+  const int nzn = Nz * P + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int nthr = NP * Nz;
+  int bx = blockIdx.x;
+  if (remap) {
+    const int per = gridDim.x >> 3;
+    bx = (blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  }
+  const int cs = threadIdx.x / nthr;
+  const int t = threadIdx.x - cs * nthr;
+  const int ex = bx * cpb + cs - 1;
+  const bool valid = cs <= cpb && ex >= 0 && ex < Nx;
+  const int slot = slot2d_elems<int>(NP, Nz, nzp, V);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* base = reinterpret_cast<T*>(smem_raw) + (valid ? cs : 0) * slot;
+  const size_t g0 = (size_t)(valid ? ex : 0) * P * nzn + t;
+  // FP32 keeps b and dinv of its lines in registers for the update; FP64 (where they would
+  // spill) reads them again after the apply
+  constexpr bool KEEP = sizeof(T) == 4;
+  T bl[NP], dl[NP], xin[NP];
+  column_apply<P, T, TG>(
+      [&](T(&v)[NP]) {
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          const size_t g = g0 + (size_t)l * nzn;
+          const T bv = r64 ? (T)r64[g] : b[g];
+          const T dv = dinv[g];
+          if constexpr (KEEP) {
+            bl[l] = bv;
+            dl[l] = dv;
+          }
+          v[l] = cr0 * dv * bv;
+        }
+      },
+      G, valid ? ex : 0, nthr, t, valid, Nz, nzn, nzp, masked, base, xin, [] {});
+  if constexpr (!KEEP) {
+    if (cs >= 1 && valid && t < nzn) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        const size_t g = g0 + (size_t)l * nzn;
+        bl[l] = r64 ? (T)r64[g] : b[g];
+        dl[l] = dinv[g];
+      }
+    }
+  }
+  if (cs >= 1 && valid && t < nzn) {
+    const T* su = base + Nz * NP * NPp;
+    const T* sl = su - slot;
+    const bool left = ex > 0 && !(masked && t == nzn - 1);
+    const int nl = (ex == Nx - 1) ? NP : P;
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      if (l < nl) {
+        T ax = su[l * nzp + t];
+        if (l == 0 && left) ax += sl[P * nzp + t];
+        const size_t g = g0 + (size_t)l * nzn;
+        const T r = bl[l] - ax;
+        T dn = cr * dl[l] * r;
+        if (cd != (T)0) dn += cd * xin[l];
+        if (store_d) d[g] = dn;
+        x[g] = xin[l] + dn;
+        if (r64) b[g] = bl[l];
+      }
+    }
+  }
+}
+
 // owned columns per workgroup of the fused step.  Measured on the 1024 x 16 and 2048 x 16 column
 // meshes (P = 8, 4, 2): four owned columns when two such workgroups fit a CU's 160 KB of LDS and
 // the workgroup count is a multiple of 8 (XCD-aware order) and at least 256, else two (FP64 at
@@ -931,6 +1014,58 @@ __global__ void k_resid_fix(const T* __restrict__ b, const T* __restrict__ y,
                             unsigned P) {
   for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
     r[g] = b[g] - ax_at(y, S, g, nzn, P);
+}
+
+template <int P, typename T, typename TG>
+static hipError_t launch_cheb2d_first(void* x, void* d, void* b, const double* r64,
+                                      const void* dinv, const void* G, int Nx, int Nz,
+                                      int masked, double cr0, double cd, double cr, int store_d,
+                                      hipStream_t st) {
+  const bool dbl = sizeof(T) == 8;
+  const int cpb = cheb2d_cpb(P, Nx, Nz, dbl);
+  if (cpb <= 0) return hipErrorInvalidValue;
+  const int nthr = (P + 1) * Nz;
+  const int threads = (((cpb + 1) * nthr + 63) / 64) * 64;
+  const int blocks = (Nx + cpb - 1) / cpb;
+  const size_t smem = apply2d_smem(P, Nz, dbl) * (cpb + 1);
+  if (threads > 1024 || smem > 160 * 1024) return hipErrorInvalidValue;
+  const int remap = (blocks % 8 == 0) ? 1 : 0;
+  hipError_t e = allow_lds(k_cheb2d_first<P, T, TG>, smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_cheb2d_first<P, T, TG>), dim3(blocks), dim3(threads), smem, st, (T*)x,
+                     (T*)d, (T*)b, r64, (const T*)dinv, (const TG*)G, Nx, Nz, masked, cpb,
+                     remap, (T)cr0, (T)cd, (T)cr, store_d);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t cheb2d_first_p(bool dbl, GType gt, void* x, void* d, void* b,
+                                 const double* r64, const void* dinv, const void* G, int Nx,
+                                 int Nz, int masked, double cr0, double cd, double cr,
+                                 int store_d, hipStream_t st) {
+  if (dbl)
+    return launch_cheb2d_first<P, double, double>(x, d, b, r64, dinv, G, Nx, Nz, masked, cr0,
+                                                  cd, cr, store_d, st);
+  if (gt == G_BF16)
+    return launch_cheb2d_first<P, float, uint16_t>(x, d, b, r64, dinv, G, Nx, Nz, masked, cr0,
+                                                   cd, cr, store_d, st);
+  return launch_cheb2d_first<P, float, float>(x, d, b, r64, dinv, G, Nx, Nz, masked, cr0, cd,
+                                              cr, store_d, st);
+}
+
+hipError_t cheb2d_first(int P, bool dbl, GType gt, void* x, void* d, void* b, const double* r64,
+                        const void* dinv, const void* G, int Nx, int Nz, int masked, double cr0,
+                        double cd, double cr, int store_d, hipStream_t st) {
+  switch (P) {
+#define SEM_CHEB_FIRST(PP)                                                                  \
+  case PP:                                                                                  \
+    return cheb2d_first_p<PP>(dbl, gt, x, d, b, r64, dinv, G, Nx, Nz, masked, cr0, cd, cr, \
+                              store_d, st);
+    SEM_CHEB_FIRST(1) SEM_CHEB_FIRST(2) SEM_CHEB_FIRST(3) SEM_CHEB_FIRST(4)
+    SEM_CHEB_FIRST(5) SEM_CHEB_FIRST(6) SEM_CHEB_FIRST(7) SEM_CHEB_FIRST(8)
+#undef SEM_CHEB_FIRST
+    default: return hipErrorInvalidValue;
+  }
 }
 
 template <int P>

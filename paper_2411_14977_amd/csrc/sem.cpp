@@ -327,7 +327,14 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr, bool first_don
   }
   if (d.smoother == SEM_SMOOTH_JACOBI) {
     const int nu = pre ? d.nu_pre : d.nu_post;
-    for (int s = 0; s < nu; ++s) {
+    int s0 = 0;
+    if (pre && nu > 1 && L.xalt) {  // sweeps 0 (from x = 0) and 1 in one fused kernel
+      HK(semk::cheb2d_first(L.P, L.dbl, L.gt, L.x, L.d, L.b, l == 0 ? c->vin64 : nullptr, L.dinv,
+                            L.G, L.Nx, L.Nz, c->masked, d.jacobi_omega, 0.0, d.jacobi_omega, 0,
+                            c->st));
+      s0 = 2;
+    }
+    for (int s = s0; s < nu; ++s) {
       const bool fz = pre && s == 0;
       if (fz && l == 0 && c->vin64) {
         HK(semk::smooth_first64(L.dbl, L.x, L.d, L.b, c->vin64, L.dinv, L.N, d.jacobi_omega, 0,
@@ -352,18 +359,26 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr, bool first_don
   double rho = 1.0 / sigma1;
   const int k = d.cheb_degree;
   const bool given = !pre && resid;
-  if (!pre && !given)
+  int j0 = 1;
+  if (!pre && !given) {
     smooth_step(c, l, 0.0, 1.0 / theta, k > 1 ? 1 : 0);
-  else if (given && first_done)
-    ;  // taken by the caller with the same coefficient (first_post_step)
-  else if (pre && l == 0 && c->vin64)
+  } else if (given && first_done) {
+    // taken by the caller with the same coefficient (first_post_step)
+  } else if (pre && k > 1 && L.xalt) {  // steps 0 (from x = 0) and 1 in one fused kernel
+    const double rho_new = 1.0 / (2.0 * sigma1 - rho);
+    HK(semk::cheb2d_first(L.P, L.dbl, L.gt, L.x, L.d, L.b, l == 0 ? c->vin64 : nullptr, L.dinv,
+                          L.G, L.Nx, L.Nz, c->masked, 1.0 / theta, rho_new * rho,
+                          2.0 * rho_new / delta, k > 2 ? 1 : 0, c->st));
+    rho = rho_new;
+    j0 = 2;
+  } else if (pre && l == 0 && c->vin64)
     HK(semk::smooth_first64(L.dbl, L.x, L.d, L.b, c->vin64, L.dinv, L.N, 1.0 / theta,
                             k > 1 ? 1 : 0, c->st));
   else
     HK(semk::smooth_update(L.dbl, L.x, L.d, given ? resid : L.b, L.dinv, L.y, L.S, L.N, L.nzn,
                            L.P, 0.0, 1.0 / theta, pre ? semk::SU_ZERO : semk::SU_RESID,
                            k > 1 ? 1 : 0, c->st));
-  for (int j = 1; j < k; ++j) {
+  for (int j = j0; j < k; ++j) {
     const double rho_new = 1.0 / (2.0 * sigma1 - rho);
     smooth_step(c, l, rho_new * rho, 2.0 * rho_new / delta, j + 1 < k ? 1 : 0);
     rho = rho_new;
