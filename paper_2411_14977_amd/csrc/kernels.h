@@ -74,8 +74,20 @@ hipError_t resid2d(int P, bool dbl, GType gt, const void* x, void* r, const void
 // (side buffers Sx, Sy, Sxy are full-size scratch vectors); G in the layout of g3d_layout.
 size_t apply3d_smem(int P, int Nz, bool dbl);
 GLayout g3d_layout(int P, int Nz, size_t tgsize);
+// With st3.b set the launch is a smoother step instead: with r = b - A x at every node,
+// dn = cr dinv r (+ cd d when cd != 0), d = dn (store_d), x += dn, in place (x is read by other
+// columns only on the shared planes, which are finished by the face fix-up after every column
+// has read them); y then holds only the partial sums of the shared-plane lines.
+struct Step3 {
+  const void* b = nullptr;
+  const void* dinv = nullptr;
+  void* d = nullptr;
+  double cd = 0.0, cr = 0.0;
+  int store_d = 0;
+};
 hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
-                   void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st);
+                   void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st,
+                   Step3 st3 = Step3());
 // one 1D operator (CSR rows over the output index) along the middle axis of [outer][n][inner]
 // arrays; in2 (optional) is subtracted from in; mask_nzn > 0 zeroes every mask_nzn-th output
 // (the Dirichlet surface rows when inner is the vertical axis)

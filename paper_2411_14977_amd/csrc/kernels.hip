@@ -1260,7 +1260,8 @@ template <int P, typename T, typename TG>
 __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __restrict__ y,
                                                   T* __restrict__ Sx, T* __restrict__ Sy,
                                                   T* __restrict__ Sxy, const TG* __restrict__ G,
-                                                  int Nx, int Ny, int Nz, int masked) {
+                                                  int Nx, int Ny, int Nz, int masked,
+                                                  Step3 st3) {
   constexpr int NP = P + 1, NL = NP * NP;
   constexpr int V = lds_vec<T>();
   constexpr int NPp = (NP + V - 1) / V * V;
@@ -1395,7 +1396,19 @@ __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __
       const bool dx = i == P && ex < Nx - 1, dy = m == P && ey < Ny - 1;
       T val = su[line * nzp + iz];
       if (!dx && !dy) {
-        y[gg] = val;
+        // smoother step (st3.b set): lines read by this column only are complete here and are
+        // updated in place; the lines shared with the left / front column wait for k_fix3d
+        if (st3.b && !(i == 0 && ex > 0) && !(m == 0 && ey > 0)) {
+          T* xs = const_cast<T*>(x);
+          T* d = static_cast<T*>(st3.d);
+          const T r = static_cast<const T*>(st3.b)[gg] - val;
+          T dn = (T)st3.cr * static_cast<const T*>(st3.dinv)[gg] * r;
+          if (st3.cd != 0.0) dn += (T)st3.cd * d[gg];
+          if (st3.store_d) d[gg] = dn;
+          xs[gg] = xs[gg] + dn;
+        } else {
+          y[gg] = val;
+        }
       } else {
         if (masked && iz == nzn - 1) val = (T)0;
         T* dst = dx ? (dy ? Sxy : Sx) : Sy;
@@ -1411,10 +1424,24 @@ __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __
 template <typename T>
 __global__ void k_fix3d(T* __restrict__ y, const T* __restrict__ Sx, const T* __restrict__ Sy,
                         const T* __restrict__ Sxy, int Nx, int Ny, int P, unsigned nyn,
-                        unsigned nzn) {
+                        unsigned nzn, Step3 st3, T* __restrict__ x) {
   const unsigned nxn = (unsigned)Nx * P + 1;
   const size_t nxp = (size_t)(Nx - 1) * nyn * nzn;
   const size_t nyp = (size_t)(Ny - 1) * nxn * nzn;
+  // complete node g with its side-buffer part v: y, or (smoother step) the update of x, d
+  auto finish = [&](size_t g, T v) {
+    const T ax = y[g] + v;
+    if (!st3.b) {
+      y[g] = ax;
+      return;
+    }
+    T* d = static_cast<T*>(st3.d);
+    const T r = static_cast<const T*>(st3.b)[g] - ax;
+    T dn = (T)st3.cr * static_cast<const T*>(st3.dinv)[g] * r;
+    if (st3.cd != 0.0) dn += (T)st3.cd * d[g];
+    if (st3.store_d) d[g] = dn;
+    x[g] = x[g] + dn;
+  };
   for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nxp + nyp;
        k += (size_t)gridDim.x * blockDim.x) {
     if (k < nxp) {
@@ -1424,7 +1451,7 @@ __global__ void k_fix3d(T* __restrict__ y, const T* __restrict__ Sx, const T* __
       T v = Sx[g];
       const unsigned qy = iy / P;
       if (qy * P == iy && qy > 0 && qy < (unsigned)Ny) v += Sy[g] + Sxy[g];
-      y[g] += v;
+      finish(g, v);
     } else {
       const size_t k2 = k - nxp;
       const size_t q = k2 / ((size_t)nxn * nzn), rem = k2 - q * nxn * nzn;
@@ -1432,7 +1459,7 @@ __global__ void k_fix3d(T* __restrict__ y, const T* __restrict__ Sx, const T* __
       const unsigned qx = ix / P;
       if (qx * P == ix && qx > 0 && qx < (unsigned)Nx) continue;  // done by the x-plane pass
       const size_t g = ((size_t)ix * nyn + (q + 1) * P) * nzn + iz;
-      y[g] += Sy[g];
+      finish(g, Sy[g]);
     }
   }
 }
@@ -1440,7 +1467,7 @@ __global__ void k_fix3d(T* __restrict__ y, const T* __restrict__ Sx, const T* __
 template <int P, typename T, typename TG>
 static hipError_t launch_apply3d(const void* x, void* y, void* Sx, void* Sy, void* Sxy,
                                  const void* G, int Nx, int Ny, int Nz, int masked,
-                                 hipStream_t st) {
+                                 hipStream_t st, Step3 st3) {
   const bool dbl = sizeof(T) == 8;
   const int nthr = (P + 1) * (P + 1) * Nz;
   const int threads = ((nthr + 63) / 64) * 64;
@@ -1448,7 +1475,7 @@ static hipError_t launch_apply3d(const void* x, void* y, void* Sx, void* Sy, voi
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_apply3d<P, T, TG>), dim3(Nx * Ny), dim3(threads), apply3d_smem(P, Nz, dbl),
                      st, (const T*)x, (T*)y, (T*)Sx, (T*)Sy, (T*)Sxy, (const TG*)G, Nx, Ny, Nz,
-                     masked);
+                     masked, st3);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (Nx > 1 || Ny > 1) {
@@ -1456,7 +1483,7 @@ static hipError_t launch_apply3d(const void* x, void* y, void* Sx, void* Sy, voi
     const size_t tot = (size_t)(Nx - 1) * nyn * nzn + (size_t)(Ny - 1) * (Nx * P + 1) * nzn;
     const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 16384);
     hipLaunchKernelGGL(k_fix3d<T>, dim3(blocks), dim3(256), 0, st, (T*)y, (const T*)Sx,
-                       (const T*)Sy, (const T*)Sxy, Nx, Ny, P, nyn, nzn);
+                       (const T*)Sy, (const T*)Sxy, Nx, Ny, P, nyn, nzn, st3, (T*)x);
   }
   return hipGetLastError();
 }
@@ -1464,24 +1491,26 @@ static hipError_t launch_apply3d(const void* x, void* y, void* Sx, void* Sy, voi
 template <int P>
 static hipError_t apply3d_p(bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
                             void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked,
-                            hipStream_t st) {
-  if (dbl) return launch_apply3d<P, double, double>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+                            hipStream_t st, Step3 st3) {
+  if (dbl)
+    return launch_apply3d<P, double, double>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
   if (gt == G_BF16)
-    return launch_apply3d<P, float, uint16_t>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-  return launch_apply3d<P, float, float>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    return launch_apply3d<P, float, uint16_t>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+  return launch_apply3d<P, float, float>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
 }
 
 hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
-                   void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st) {
+                   void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st,
+                   Step3 st3) {
   switch (P) {
-    case 1: return apply3d_p<1>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-    case 2: return apply3d_p<2>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-    case 3: return apply3d_p<3>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-    case 4: return apply3d_p<4>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-    case 5: return apply3d_p<5>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-    case 6: return apply3d_p<6>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-    case 7: return apply3d_p<7>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
-    case 8: return apply3d_p<8>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st);
+    case 1: return apply3d_p<1>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+    case 2: return apply3d_p<2>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+    case 3: return apply3d_p<3>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+    case 4: return apply3d_p<4>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+    case 5: return apply3d_p<5>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+    case 6: return apply3d_p<6>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+    case 7: return apply3d_p<7>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
+    case 8: return apply3d_p<8>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
     default: return hipErrorInvalidValue;
   }
 }

@@ -274,6 +274,18 @@ void apply_outer(Ctx* c, const double* x, int masked) {
 // one smoother step from the current x:  r = b - A x;  d = cd d + cr dinv r;  x += d
 void smooth_step(Ctx* c, int l, double cd, double cr, int store_d) {
   DLevel& L = c->lev[l];
+  if (c->dim == 3) {  // the update rides in the operator and its face fix-up, in place
+    semk::Step3 s3;
+    s3.b = L.b;
+    s3.dinv = L.dinv;
+    s3.d = L.d;
+    s3.cd = cd;
+    s3.cr = cr;
+    s3.store_d = store_d;
+    HK(semk::apply3d(L.P, L.dbl, L.gt, L.x, L.y, L.Sx, L.Sy, L.Sxy, L.G, L.Nx, L.Ny, L.Nz,
+                     c->masked, c->st, s3));
+    return;
+  }
   if (L.xalt) {  // operator and update in one kernel, into the other vector
     HK(semk::cheb2d(L.P, L.dbl, L.gt, L.x, L.xalt, L.d, L.b, L.dinv, L.G, L.Nx, L.Nz, c->masked,
                     cd, cr, store_d, c->st));
