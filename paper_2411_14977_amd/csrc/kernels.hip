@@ -1196,12 +1196,15 @@ int apply2d_blocks(int P, int Nx, int Nz, bool dbl) {
 // 3D operator apply (sigma-mapped hexahedra; element matrices as in 2D with the five factors
 // G_rr, G_tt, G_rs, G_ts, G_ss; G_rt = 0 because x and y are affine and independent)
 // ------------------------------------------------------------------------------------------
-// LDS per element column: input/output column [NP(i)][NP(m)][nzp], four exchange arrays
-// [Nz][NP][NP][NPp], element-top values [Nz][NP][NP]
+// LDS per element column: four exchange arrays [Nz][NP][NP][NPp]; the space of the last two
+// also holds the input/output column [NP(i)][NP(m)][nzp] and the element-top values
+// [Nz][NP][NP] in the phases where they are dead
 static size_t apply3d_slot(int P, int Nz, bool dbl) {
   const int NP = P + 1, V = dbl ? 2 : 4, NPp = (NP + V - 1) / V * V;
   const int nzp = (Nz * P + 1 + V - 1) / V * V;
-  const size_t n = (size_t)NP * NP * nzp + 4 * (size_t)Nz * NP * NP * NPp + (size_t)Nz * NP * NP;
+  const size_t ex = (size_t)Nz * NP * NP * NPp;  // one exchange array
+  const size_t col = (size_t)NP * NP * nzp + (size_t)Nz * NP * NP;
+  const size_t n = 2 * ex + std::max(2 * ex, col);
   return (n + V - 1) / V * V;
 }
 
@@ -1272,12 +1275,14 @@ __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __
   const int col = blockIdx.x;
   const int ex = col / Ny, ey = col - ex * Ny;
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* su = reinterpret_cast<T*>(smem_raw);  // [NP(i)][NP(m)][nzp]
-  T* A1 = su + NL * nzp;                    // [Nz][i][m][j]: u_r, later D_r^T w_r
+  // A1, A2 live through phases 2-5; the space after them holds B1, B2 in phases 3-4 and, in the
+  // other phases, the column su (input in 1-2, output in 6) and the element-top values stp (5-6)
+  T* A1 = reinterpret_cast<T*>(smem_raw);  // [Nz][i][m][j]: u_r, later D_r^T w_r
   T* A2 = A1 + Nz * NL * NPp;               // [Nz][i][m][j]: u_t, later D_t^T w_t
   T* B1 = A2 + Nz * NL * NPp;               // [Nz][m][j][i]: w_r
   T* B2 = B1 + Nz * NL * NPp;               // [Nz][i][j][m]: w_t
-  T* stp = B2 + Nz * NL * NPp;              // [Nz][i][m] element-top values
+  T* su = B1;                               // [NP(i)][NP(m)][nzp]
+  T* stp = su + NL * nzp;                   // [Nz][i][m] element-top values
   const int t = threadIdx.x;
   const bool act = t < nthr;
   const int ez = t / NL, ab = t - (t / NL) * NL;
