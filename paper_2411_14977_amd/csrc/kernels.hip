@@ -671,19 +671,31 @@ __global__ __launch_bounds__(1024) void k_stagecq2d(const float* __restrict__ CE
         const int qz = t / P, rz = t - qz * P;
         const bool zl = rz == 0 && qz > 0, zr = qz < Nz;
         const bool top = masked && t == nzn - 1;
+        // every candidate is loaded unconditionally (indices clamped into the array) so that all
+        // loads are in flight together; absent ones enter as exact zeros, in the same order
+        const int zlo = zl ? qz - 1 : 0, zhi = zr ? qz : Nz - 1;
+        float cv[NP][4];
 #pragma unroll
         for (int l = 0; l < NP; ++l) {
-          // element columns left and right of line l of column ex, with their local line
+          const int cl = l == 0 ? (ex > 0 ? ex - 1 : 0) : ex;
+          const int cr = l == P ? (ex + 1 < Nx ? ex + 1 : ex) : ex, ir = l == P ? 0 : l;
+          cv[l][0] = CE[ce_index(cl, P, zlo, P, Nz, NP)];
+          cv[l][1] = CE[ce_index(cl, P, zhi, zr ? rz : 0, Nz, NP)];
+          cv[l][2] = CE[ce_index(cr, ir, zlo, P, Nz, NP)];
+          cv[l][3] = CE[ce_index(cr, ir, zhi, zr ? rz : 0, Nz, NP)];
+        }
+#pragma unroll
+        for (int l = 0; l < NP; ++l) {
+          // element columns left and right of line l of column ex
           const bool xl = l == 0 ? ex > 0 : l == P;
           const bool xr = l == P ? ex + 1 < Nx : true;
-          const int cl = l == 0 ? ex - 1 : ex, il = P;
-          const int cr = l == P ? ex + 1 : ex, ir = l == P ? 0 : l;
+          const bool m0 = xl && zl, m1 = xl && zr, m2 = xr && zl, m3 = xr && zr;
           float sacc = 0.f;
-          int cnt = 0;
-          if (xl && zl) { sacc += CE[ce_index(cl, il, qz - 1, P, Nz, NP)]; ++cnt; }
-          if (xl && zr) { sacc += CE[ce_index(cl, il, qz, rz, Nz, NP)]; ++cnt; }
-          if (xr && zl) { sacc += CE[ce_index(cr, ir, qz - 1, P, Nz, NP)]; ++cnt; }
-          if (xr && zr) { sacc += CE[ce_index(cr, ir, qz, rz, Nz, NP)]; ++cnt; }
+          sacc += m0 ? cv[l][0] : 0.f;
+          sacc += m1 ? cv[l][1] : 0.f;
+          sacc += m2 ? cv[l][2] : 0.f;
+          sacc += m3 ? cv[l][3] : 0.f;
+          const int cnt = (int)m0 + (int)m1 + (int)m2 + (int)m3;
           v[l] = top ? (T)0 : (T)(sacc / (float)cnt);
         }
       },
