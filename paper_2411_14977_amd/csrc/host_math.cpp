@@ -608,6 +608,16 @@ bool build_bcr(const LevelGeom& L, const std::vector<double>& Gr, BcrPlan& plan,
         }
       }
     }
+    // the kernels read the factors column by column (entry (r, c) at c nb + r)
+    auto transpose_all = [&](double* M, size_t count) {
+      for (size_t m = 0; m < count; ++m) {
+        double* A = M + m * nn;
+        for (int r = 0; r < nb; ++r)
+          for (int q = r + 1; q < nb; ++q) std::swap(A[r * nb + q], A[q * nb + r]);
+      }
+    };
+    transpose_all(F, (size_t)lv.neven * 2);
+    transpose_all(B, (size_t)lv.nodd * 3);
     plan.levs.push_back(lv);
     Dg.swap(Dn);
     Lg.swap(Ln);

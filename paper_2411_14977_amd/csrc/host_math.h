@@ -71,8 +71,8 @@ struct BcrPlan {
   int nblocks = 0;     // blocks at level 0
   struct Lev { int n, stride; size_t offM, offB; int neven, nodd; };
   std::vector<Lev> levs;       // reduction levels (n > 1)
-  std::vector<double> fwd;     // per level: neven x {Mm, Mp} nb x nb
-  std::vector<double> bwd;     // per level: nodd x {DO, DL, DU} nb x nb
+  std::vector<double> fwd;     // per level: neven x {Mm, Mp} nb x nb, column-major
+  std::vector<double> bwd;     // per level: nodd x {DO, DL, DU} nb x nb, column-major
   std::vector<double> last;    // inverse of the final block, nb x nb (unused when dense)
   // the reduction stops once at most `dense_max` blocks remain; the remaining reduced system
   // (dense_n blocks, spaced dense_stride apart at level 0) is solved with its explicit inverse
@@ -82,7 +82,7 @@ struct BcrPlan {
   std::vector<int> rowmap;
 };
 bool build_bcr(const LevelGeom& L, const std::vector<double>& Gr, BcrPlan& plan, char* err,
-               size_t errlen, int dense_max = 65);
+               size_t errlen, int dense_max = 33);
 
 // Counter-based SplitMix64 uniform in [-1, 1) (Steele, Lea, Flood 2014), element i of seed.
 double splitmix64_uniform(uint64_t seed, uint64_t i);

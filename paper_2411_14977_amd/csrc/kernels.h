@@ -158,6 +158,22 @@ hipError_t bcr_bwd(const double* b, double* x, const double* Bk, int n, int stri
                    int bstride, int nzf, int nb, hipStream_t st);
 hipError_t bcr_dense(const double* Ainv, const double* b, double* x, int nd, int nb, int stride,
                      int bstride, int nzf, hipStream_t st);
+// all reduction levels in one launch each way: fwd reads b and writes the reduced right-hand
+// side to bred (every block); the dense step then solves the blocks that are multiples of
+// 2^nl from bred into x, and bwd fills in the remaining blocks of x.  LDS per workgroup:
+// bcr_{fwd,bwd}_all_smem (the host falls back to the per-level kernels beyond its limit).
+constexpr int BCR_MAXL = 16;
+struct BcrLevels {
+  int nl = 0;
+  long long offM[BCR_MAXL] = {0};
+  long long offB[BCR_MAXL] = {0};
+};
+size_t bcr_fwd_all_smem(int nl, int nb);
+size_t bcr_bwd_all_smem(int nl, int nb);
+hipError_t bcr_fwd_all(const double* b, double* bred, const double* F, const BcrLevels& lv,
+                       int nblocks, int bstride, int nzf, int nb, hipStream_t st);
+hipError_t bcr_bwd_all(const double* bred, double* x, const double* Bk, const BcrLevels& lv,
+                       int nblocks, int bstride, int nzf, int nb, hipStream_t st);
 
 // ---- FP64 outer-loop kernels (deterministic two-stage reductions over NRED partials) -------
 // FPCG direction step fused with the FP64 operator (2D where the fused layout fits with at most

@@ -989,18 +989,53 @@ __global__ __launch_bounds__(RED_THREADS) void k_update_xrp(
     int first, const double* prz_new, const double* ppq_new, double* prz_old, double* ppq_old,
     double* prr, unsigned N) {
   __shared__ double sh[16];
-  const double rz = sum_partials(prz_new, sh);
-  const double pq = sum_partials(ppq_new, sh);
-  const double alpha = rz / pq;
+  // the partial sums and the first batch of vector values are loaded together; elements are
+  // visited in the grid-stride order (U per batch), so every sum keeps its order
+  constexpr int U = 8, NP = NRED / RED_THREADS;
+  double hz[NP], hq[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) {
+    hz[k] = prz_new[threadIdx.x + k * RED_THREADS];
+    hq[k] = ppq_new[threadIdx.x + k * RED_THREADS];
+  }
   const double beta = *beta_in;
-  double a = 0;
-  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
-    const double pv = first ? z[g] : fma(beta, p[g], z[g]);
-    p[g] = pv;
-    x[g] += alpha * pv;
-    const double rv = r[g] - alpha * q[g];
-    r[g] = rv;
-    a += rv * rv;
+  const unsigned stride = gridDim.x * blockDim.x;
+  double alpha = 0.0, a = 0.0;
+  for (size_t g0 = 0; g0 < N; g0 += (size_t)U * stride) {  // uniform trip count
+    double zv[U], pv[U], xv[U], rv[U], qv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t g = g0 + blockIdx.x * blockDim.x + threadIdx.x + (size_t)u * stride;
+      const bool ok = g < N;
+      zv[u] = ok ? z[g] : 0.0;
+      pv[u] = (ok && !first) ? p[g] : 0.0;
+      xv[u] = ok ? x[g] : 0.0;
+      rv[u] = ok ? r[g] : 0.0;
+      qv[u] = ok ? q[g] : 0.0;
+    }
+    if (g0 == 0) {
+      double sz = 0.0, sq = 0.0;
+#pragma unroll
+      for (int k = 0; k < NP; ++k) {
+        sz += hz[k];
+        sq += hq[k];
+      }
+      const double rz = block_sum(sz, sh);
+      const double pq = block_sum(sq, sh);
+      alpha = rz / pq;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t g = g0 + blockIdx.x * blockDim.x + threadIdx.x + (size_t)u * stride;
+      if (g < N) {
+        const double pn = first ? zv[u] : fma(beta, pv[u], zv[u]);
+        p[g] = pn;
+        x[g] = xv[u] + alpha * pn;
+        const double rn = rv[u] - alpha * qv[u];
+        r[g] = rn;
+        a += rn * rn;
+      }
+    }
   }
   a = block_sum(a, sh);
   if (threadIdx.x == 0) prr[blockIdx.x] = a;
@@ -1839,35 +1874,37 @@ hipError_t fill(bool dbl, void* p, double v, size_t n, hipStream_t st) {
 // (I_Pp = Phi V^{-1}) per direction; restriction = its transpose on assembled vectors.
 // Both in pull form: every output node sums its own inputs, each shared input counted once.
 // ------------------------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ T pull1d(const T* __restrict__ v, int vstride, int c, int Ne, int Pf,
-                                    int Pc, const T* __restrict__ J) {
-  // coarse node c of a 1D line (Ne elements): sum_f P1[f][c] v[f]
+template <typename T, int PF = 0, int PC = 0>
+__device__ __forceinline__ T pull1d(const T* __restrict__ v, int vstride, int c, int Ne, int Pf_rt,
+                                    int Pc_rt, const T* __restrict__ J) {
+  // coarse node c of a 1D line (Ne elements): sum_f P1[f][c] v[f]; PF, PC > 0 fix the orders
+  // at compile time (loops unrolled, every LDS read of a node issued together)
+  const int Pf = PF > 0 ? PF : Pf_rt, Pc = PC > 0 ? PC : Pc_rt;
   int ea = c / Pc;
   if (ea > Ne - 1) ea = Ne - 1;
   const int ka = c - ea * Pc;
   T s = 0;
+#pragma unroll
   for (int jf = 0; jf <= Pf; ++jf) s += J[jf * (Pc + 1) + ka] * v[(ea * Pf + jf) * vstride];
-  if (ka == 0 && ea > 0)
+  if (ka == 0 && ea > 0) {
+#pragma unroll
     for (int jf = 0; jf < Pf; ++jf) s += J[jf * (Pc + 1) + Pc] * v[((ea - 1) * Pf + jf) * vstride];
+  }
   return s;
 }
 
-template <typename T, typename TC>
+template <typename T, typename TC, int PF = 0, int PC = 0>
 __global__ void k_restrict2d(const T* __restrict__ b, const T* __restrict__ y,
                              const T* __restrict__ S, int use_ax, TC* __restrict__ rc,
-                             const double* __restrict__ Jg, int Nx, int Nz, int Pf, int Pc,
+                             const double* __restrict__ Jg, int Nx, int Nz, int Pf_rt, int Pc_rt,
                              int masked, StageFold f) {
+  const int Pf = PF > 0 ? PF : Pf_rt, Pc = PC > 0 ? PC : Pc_rt;
   const int ex = blockIdx.x;
-  // learned-stage fold: the fine residual is b - alpha q (the stage's updated residual)
+  // learned-stage fold: the fine residual is b - alpha q (the stage's updated residual); alpha
+  // is formed while the first batch of loads is in flight
   T al = 0;
   const T* fq = static_cast<const T*>(f.q);
-  if (fq) {
-    __shared__ double sh[8];
-    bool ok;
-    al = (T)stage_alpha(f.pcr, f.ncr, f.pcq, f.ncq, sh, &ok);
-    if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) f.skips[0] += 1;
-  }
+  __shared__ double sh[8];
   const int nzf = Nz * Pf + 1, nzc = Nz * Pc + 1;
   const int L0 = ex > 0 ? (ex - 1) * Pf : 0;
   const int L1 = ex * Pf + Pf;
@@ -1877,87 +1914,136 @@ __global__ void k_restrict2d(const T* __restrict__ b, const T* __restrict__ y,
   T* rf = sJ + (Pf + 1) * (Pc + 1);        // [nl][nzf]
   T* tv = rf + nl * nzf;                   // [nl][nzc]
   for (int k = threadIdx.x; k < (Pf + 1) * (Pc + 1); k += blockDim.x) sJ[k] = (T)Jg[k];
-  for (int k = threadIdx.x; k < nl * nzf; k += blockDim.x) {
-    const int line = L0 + k / nzf;
-    const int iz = k - (k / nzf) * nzf;
-    const unsigned g = (unsigned)line * nzf + iz;
-    T r = b[g];
-    if (fq) r = r - al * fq[g];
-    else if (use_ax) r -= ax_at(y, S, g, (unsigned)nzf, (unsigned)Pf);
-    if (masked && iz == nzf - 1) r = 0;
-    rf[k] = r;
+  // TU values per thread loaded together before any is stored (one memory latency per batch)
+  constexpr int TU = 8;
+  const int nrf = nl * nzf;
+  for (int k0 = 0; k0 < nrf; k0 += TU * (int)blockDim.x) {  // uniform trip count
+    T v[TU], w[TU];
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+      const int k = k0 + (int)threadIdx.x + u * (int)blockDim.x;
+      v[u] = 0;
+      w[u] = 0;
+      if (k < nrf) {
+        const unsigned g = (unsigned)L0 * nzf + k;
+        v[u] = b[g];
+        if (fq) w[u] = fq[g];
+        else if (use_ax) v[u] -= ax_at(y, S, g, (unsigned)nzf, (unsigned)Pf);
+      }
+    }
+    if (fq && k0 == 0) {
+      bool ok;
+      al = (T)stage_alpha(f.pcr, f.ncr, f.pcq, f.ncq, sh, &ok);
+      if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) f.skips[0] += 1;
+    }
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+      const int k = k0 + (int)threadIdx.x + u * (int)blockDim.x;
+      if (k < nrf) rf[k] = (masked && k % nzf == nzf - 1) ? (T)0 : v[u] - al * w[u];
+    }
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < nl * nzc; k += blockDim.x) {
-    const int li = k / nzc, izc = k - li * nzc;
-    tv[k] = pull1d(rf + li * nzf, 1, izc, Nz, Pf, Pc, sJ);
-  }
-  __syncthreads();
+  // along x first, onto the owned coarse lines only (the left neighbour's fine lines feed the
+  // shared coarse line alone), then along z; tv holds the x-contracted lines [kc][nzf]
   const int nown = (ex == Nx - 1) ? Pc + 1 : Pc;
-  for (int k = threadIdx.x; k < nown * nzc; k += blockDim.x) {
-    const int kc = k / nzc, izc = k - kc * nzc;
+  for (int k = threadIdx.x; k < nown * nzf; k += blockDim.x) {
+    const int kc = k / nzf, izf = k - kc * nzf;
     const int ic = ex * Pc + kc;
-    // pull over fine lines; tv holds lines L0.. (local index = fine line - L0)
     int ea = ic / Pc;
     if (ea > Nx - 1) ea = Nx - 1;
     const int ka = ic - ea * Pc;
+    // rf holds the fine lines from L0 (local index = fine line - L0)
     T s = 0;
-    for (int i = 0; i <= Pf; ++i) s += sJ[i * (Pc + 1) + ka] * tv[(ea * Pf + i - L0) * nzc + izc];
-    if (ka == 0 && ea > 0)
+#pragma unroll
+    for (int i = 0; i <= Pf; ++i) s += sJ[i * (Pc + 1) + ka] * rf[(ea * Pf + i - L0) * nzf + izf];
+    if (ka == 0 && ea > 0) {
+#pragma unroll
       for (int i = 0; i < Pf; ++i)
-        s += sJ[i * (Pc + 1) + Pc] * tv[((ea - 1) * Pf + i - L0) * nzc + izc];
+        s += sJ[i * (Pc + 1) + Pc] * rf[((ea - 1) * Pf + i - L0) * nzf + izf];
+    }
+    tv[k] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < nown * nzc; k += blockDim.x) {
+    const int kc = k / nzc, izc = k - kc * nzc;
+    T s = pull1d<T, PF, PC>(tv + kc * nzf, 1, izc, Nz, Pf, Pc, sJ);
     if (masked && izc == nzc - 1) s = 0;
-    rc[(size_t)ic * nzc + izc] = (TC)s;
+    rc[(size_t)(ex * Pc + kc) * nzc + izc] = (TC)s;
   }
 }
 
 size_t restrict2d_smem(int Pf, int Pc, int Nz, bool dbl) {
   const int nl = 2 * Pf + 1;
-  const size_t n = (size_t)(Pf + 1) * (Pc + 1) + (size_t)nl * (Nz * Pf + 1) + (size_t)nl * (Nz * Pc + 1);
+  const size_t n = (size_t)(Pf + 1) * (Pc + 1) + (size_t)nl * (Nz * Pf + 1) +
+                   (size_t)(Pc + 1) * (Nz * Pf + 1);
   return n * (dbl ? 8 : 4);
+}
+
+template <typename T, typename TC, int PF, int PC>
+static hipError_t restrict2d_t(const void* b, const void* y, const void* S, int use_ax, void* rc,
+                               const double* J, int Nx, int Nz, int Pf, int Pc, int masked,
+                               size_t smem, hipStream_t st, StageFold f) {
+  const hipError_t e = allow_lds(k_restrict2d<T, TC, PF, PC>, smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_restrict2d<T, TC, PF, PC>), dim3(Nx), dim3(256), smem, st, (const T*)b,
+                     (const T*)y, (const T*)S, use_ax, (TC*)rc, J, Nx, Nz, Pf, Pc, masked, f);
+  return hipGetLastError();
+}
+
+// the level pairs of the usual order sequences get unrolled kernels; others the generic one
+template <typename T, typename TC>
+static hipError_t restrict2d_p(const void* b, const void* y, const void* S, int use_ax, void* rc,
+                               const double* J, int Nx, int Nz, int Pf, int Pc, int masked,
+                               size_t smem, hipStream_t st, StageFold f) {
+#define SEM_R2(a, c)                                                                           \
+  if (Pf == a && Pc == c)                                                                      \
+    return restrict2d_t<T, TC, a, c>(b, y, S, use_ax, rc, J, Nx, Nz, Pf, Pc, masked, smem, st, f);
+  SEM_R2(8, 4) SEM_R2(4, 2) SEM_R2(2, 1) SEM_R2(6, 3) SEM_R2(3, 1)
+#undef SEM_R2
+  return restrict2d_t<T, TC, 0, 0>(b, y, S, use_ax, rc, J, Nx, Nz, Pf, Pc, masked, smem, st, f);
 }
 
 hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const void* S,
                       int use_ax, void* rc, const double* J, int Nx, int Nz, int Pf, int Pc,
                       int masked, hipStream_t st, StageFold f) {
   const size_t smem = restrict2d_smem(Pf, Pc, Nz, dbl);
-  const hipError_t e = dbl     ? allow_lds(k_restrict2d<double, double>, smem)
-                       : dbl_c ? allow_lds(k_restrict2d<float, double>, smem)
-                               : allow_lds(k_restrict2d<float, float>, smem);
-  if (e != hipSuccess) return e;
   if (dbl)
-    hipLaunchKernelGGL((k_restrict2d<double, double>), dim3(Nx), dim3(256), smem, st,
-                       (const double*)b, (const double*)y, (const double*)S, use_ax,
-                       (double*)rc, J, Nx, Nz, Pf, Pc, masked, f);
-  else if (dbl_c)
-    hipLaunchKernelGGL((k_restrict2d<float, double>), dim3(Nx), dim3(256), smem, st,
-                       (const float*)b, (const float*)y, (const float*)S, use_ax, (double*)rc,
-                       J, Nx, Nz, Pf, Pc, masked, f);
-  else
-    hipLaunchKernelGGL((k_restrict2d<float, float>), dim3(Nx), dim3(256), smem, st,
-                       (const float*)b, (const float*)y, (const float*)S, use_ax, (float*)rc,
-                       J, Nx, Nz, Pf, Pc, masked, f);
-  return hipGetLastError();
+    return restrict2d_p<double, double>(b, y, S, use_ax, rc, J, Nx, Nz, Pf, Pc, masked, smem, st, f);
+  if (dbl_c)
+    return restrict2d_p<float, double>(b, y, S, use_ax, rc, J, Nx, Nz, Pf, Pc, masked, smem, st, f);
+  return restrict2d_p<float, float>(b, y, S, use_ax, rc, J, Nx, Nz, Pf, Pc, masked, smem, st, f);
 }
 
-template <typename T, typename TC>
+template <typename T, typename TC, int PF = 0, int PC = 0>
 __global__ void k_prolong2d(const TC* __restrict__ ec, T* __restrict__ xf,
-                            const double* __restrict__ Jg, int Nx, int Nz, int Pf, int Pc,
+                            const double* __restrict__ Jg, int Nx, int Nz, int Pf_rt, int Pc_rt,
                             StageFold f) {
+  const int Pf = PF > 0 ? PF : Pf_rt, Pc = PC > 0 ? PC : Pc_rt;
   const int ex = blockIdx.x;
   // learned-stage fold: the stage's step alpha c is added together with the correction
   T al = 0;
   const T* fc = static_cast<const T*>(f.c);
-  if (fc) {
-    __shared__ double sh[8];
-    bool ok;
-    al = (T)stage_alpha(f.pcr, f.ncr, f.pcq, f.ncq, sh, &ok);
-  }
+  __shared__ double sh[8];
   const int nzf = Nz * Pf + 1, nzc = Nz * Pc + 1;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sJ = reinterpret_cast<T*>(smem_raw);  // (Pf+1)(Pc+1)
   T* ce = sJ + (Pf + 1) * (Pc + 1);        // [Pc+1][nzc]
   T* tv = ce + (Pc + 1) * nzc;             // [Pc+1][nzf]
+  // the first batch of fine values (TU per thread) is requested before anything else
+  const int nown = (ex == Nx - 1) ? Pf + 1 : Pf;
+  const size_t fb = (size_t)ex * Pf * nzf;
+  constexpr int TU = 5;
+  const int nout = nown * nzf;
+  T xv[TU], cv[TU];
+  auto load_batch = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+      const int k = k0 + (int)threadIdx.x + u * (int)blockDim.x;
+      xv[u] = k < nout ? xf[fb + k] : (T)0;
+      cv[u] = (k < nout && fc) ? fc[fb + k] : (T)0;
+    }
+  };
+  load_batch(0);
   for (int k = threadIdx.x; k < (Pf + 1) * (Pc + 1); k += blockDim.x) sJ[k] = (T)Jg[k];
   const size_t cb = (size_t)ex * Pc * nzc;
   for (int k = threadIdx.x; k < (Pc + 1) * nzc; k += blockDim.x) ce[k] = (T)ec[cb + k];
@@ -1968,19 +2054,29 @@ __global__ void k_prolong2d(const TC* __restrict__ ec, T* __restrict__ xf,
     if (e > Nz - 1) e = Nz - 1;
     const int jf = izf - e * Pf;
     T s = 0;
+#pragma unroll
     for (int q = 0; q <= Pc; ++q) s += sJ[jf * (Pc + 1) + q] * ce[kc * nzc + e * Pc + q];
     tv[k] = s;
   }
   __syncthreads();
-  const int nown = (ex == Nx - 1) ? Pf + 1 : Pf;
-  const size_t fb = (size_t)ex * Pf * nzf;
-  for (int k = threadIdx.x; k < nown * nzf; k += blockDim.x) {
-    const int i = k / nzf, izf = k - i * nzf;
-    T s = 0;
-    for (int q = 0; q <= Pc; ++q) s += sJ[i * (Pc + 1) + q] * tv[q * nzf + izf];
-    T xv = xf[fb + k];
-    if (fc) xv += al * fc[fb + k];
-    xf[fb + k] = xv + s;
+  if (fc) {
+    bool ok;
+    al = (T)stage_alpha(f.pcr, f.ncr, f.pcq, f.ncq, sh, &ok);
+  }
+  for (int k0 = 0; k0 < nout; k0 += TU * (int)blockDim.x) {  // uniform trip count
+    if (k0 > 0) load_batch(k0);
+#pragma unroll
+    for (int u = 0; u < TU; ++u) {
+      const int k = k0 + (int)threadIdx.x + u * (int)blockDim.x;
+      if (k < nout) {
+        xv[u] += al * cv[u];
+        const int i = k / nzf, izf = k - i * nzf;
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q <= Pc; ++q) s += sJ[i * (Pc + 1) + q] * tv[q * nzf + izf];
+        xf[fb + k] = xv[u] + s;
+      }
+    }
   }
 }
 
@@ -1990,23 +2086,32 @@ size_t prolong2d_smem(int Pf, int Pc, int Nz, bool dbl) {
   return n * (dbl ? 8 : 4);
 }
 
+template <typename T, typename TC, int PF, int PC>
+static hipError_t prolong2d_t(const void* ec, void* xf, const double* J, int Nx, int Nz, int Pf,
+                              int Pc, size_t smem, hipStream_t st, StageFold f) {
+  const hipError_t e = allow_lds(k_prolong2d<T, TC, PF, PC>, smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_prolong2d<T, TC, PF, PC>), dim3(Nx), dim3(256), smem, st, (const TC*)ec,
+                     (T*)xf, J, Nx, Nz, Pf, Pc, f);
+  return hipGetLastError();
+}
+
+template <typename T, typename TC>
+static hipError_t prolong2d_p(const void* ec, void* xf, const double* J, int Nx, int Nz, int Pf,
+                              int Pc, size_t smem, hipStream_t st, StageFold f) {
+#define SEM_P2(a, c) \
+  if (Pf == a && Pc == c) return prolong2d_t<T, TC, a, c>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
+  SEM_P2(8, 4) SEM_P2(4, 2) SEM_P2(2, 1) SEM_P2(6, 3) SEM_P2(3, 1)
+#undef SEM_P2
+  return prolong2d_t<T, TC, 0, 0>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
+}
+
 hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
                      int Nz, int Pf, int Pc, hipStream_t st, StageFold f) {
   const size_t smem = prolong2d_smem(Pf, Pc, Nz, dbl);
-  const hipError_t e = dbl     ? allow_lds(k_prolong2d<double, double>, smem)
-                       : dbl_c ? allow_lds(k_prolong2d<float, double>, smem)
-                               : allow_lds(k_prolong2d<float, float>, smem);
-  if (e != hipSuccess) return e;
-  if (dbl)
-    hipLaunchKernelGGL((k_prolong2d<double, double>), dim3(Nx), dim3(256), smem, st,
-                       (const double*)ec, (double*)xf, J, Nx, Nz, Pf, Pc, f);
-  else if (dbl_c)
-    hipLaunchKernelGGL((k_prolong2d<float, double>), dim3(Nx), dim3(256), smem, st,
-                       (const double*)ec, (float*)xf, J, Nx, Nz, Pf, Pc, f);
-  else
-    hipLaunchKernelGGL((k_prolong2d<float, float>), dim3(Nx), dim3(256), smem, st,
-                       (const float*)ec, (float*)xf, J, Nx, Nz, Pf, Pc, f);
-  return hipGetLastError();
+  if (dbl) return prolong2d_p<double, double>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
+  if (dbl_c) return prolong2d_p<float, double>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
+  return prolong2d_p<float, float>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -2032,13 +2137,13 @@ __global__ __launch_bounds__(256) void k_bcr_fwd(double* __restrict__ b,
     const int k = 2 * kk;
     const size_t i = (size_t)k * stride;
     const size_t nn = (size_t)nb * nb;
-    const double* Mm = F + (size_t)kk * 2 * nn + (size_t)row * nb;
+    const double* Mm = F + (size_t)kk * 2 * nn + row;
     const double* Mp = Mm + nn;
     self = bpos(i, bstride, row, nzf);
     if (k > 0)
-      for (int c = q; c < nb; c += 4) s += Mm[c] * b[bpos(i - stride, bstride, c, nzf)];
+      for (int c = q; c < nb; c += 4) s += Mm[(size_t)c * nb] * b[bpos(i - stride, bstride, c, nzf)];
     if (k + 1 < n)
-      for (int c = q; c < nb; c += 4) s += Mp[c] * b[bpos(i + stride, bstride, c, nzf)];
+      for (int c = q; c < nb; c += 4) s += Mp[(size_t)c * nb] * b[bpos(i + stride, bstride, c, nzf)];
   }
   s += __shfl_xor(s, 1, 64);
   s += __shfl_xor(s, 2, 64);
@@ -2059,14 +2164,15 @@ __global__ __launch_bounds__(256) void k_bcr_bwd(const double* __restrict__ b,
     const int k = 2 * kk + 1;
     const size_t i = (size_t)k * stride;
     const size_t nn = (size_t)nb * nb;
-    const double* DO = Bk + (size_t)kk * 3 * nn + (size_t)row * nb;
+    const double* DO = Bk + (size_t)kk * 3 * nn + row;
     const double* DL = DO + nn;
     const double* DU = DL + nn;
     self = bpos(i, bstride, row, nzf);
     for (int c = q; c < nb; c += 4)
-      s += DO[c] * b[bpos(i, bstride, c, nzf)] - DL[c] * x[bpos(i - stride, bstride, c, nzf)];
+      s += DO[(size_t)c * nb] * b[bpos(i, bstride, c, nzf)] -
+           DL[(size_t)c * nb] * x[bpos(i - stride, bstride, c, nzf)];
     if (k + 1 < n)
-      for (int c = q; c < nb; c += 4) s -= DU[c] * x[bpos(i + stride, bstride, c, nzf)];
+      for (int c = q; c < nb; c += 4) s -= DU[(size_t)c * nb] * x[bpos(i + stride, bstride, c, nzf)];
   }
   s += __shfl_xor(s, 1, 64);
   s += __shfl_xor(s, 2, 64);
@@ -2099,6 +2205,206 @@ hipError_t bcr_dense(const double* Ainv, const double* b, double* x, int nd, int
   hipLaunchKernelGGL(k_bcr_dense, dim3(nblk(nd, 4)), dim3(256), 0, st, Ainv, b, x, nd, nb, stride,
                      bstride, nzf);
   return hipGetLastError();
+}
+
+// Every level of the forward reduction in one launch.  Workgroup w owns the level-0 blocks
+// [w C, (w+1) C) and keeps in LDS a window that extends S - 1 = 2^nl - 1 blocks to either side:
+// a block's value after nl levels depends on the original right-hand side within that distance
+// only, so each workgroup recomputes the reductions of its margin instead of waiting for its
+// neighbours (values the window cannot complete are computed too but never leave it).  The
+// reduced right-hand side goes to bred, so no workgroup reads a value another one has updated.
+// Thread (task, row): the rows of one task read consecutive entries of the column-major factor
+// columns; NB > 0 fixes the block size at compile time, so that all of a task's factor loads are
+// in flight together (NB = 0: any size).
+template <int NB>
+__global__ __launch_bounds__(1024) void k_bcr_fwd_all(const double* __restrict__ b,
+                                                      double* __restrict__ bred,
+                                                      const double* __restrict__ F, BcrLevels lv,
+                                                      int nblocks, int C, int bstride, int nzf,
+                                                      int nb_rt) {
+  extern __shared__ double sb[];  // [window][nb]
+  const int nb = NB > 0 ? NB : nb_rt;
+  const int S = 1 << lv.nl;
+  const int ws = (int)blockIdx.x * C - (S - 1);
+  const int Wn = C + 2 * (S - 1);
+  const int we = ws + Wn;  // exclusive
+  for (int t = threadIdx.x; t < Wn * nb; t += blockDim.x) {
+    const int p = t / nb, r = t - p * nb;
+    const int g = ws + p;
+    sb[t] = (g >= 0 && g < nblocks) ? b[bpos(g, bstride, r, nzf)] : 0.0;
+  }
+  __syncthreads();
+  const size_t nn = (size_t)nb * nb;
+  for (int l = 0; l < lv.nl; ++l) {
+    const int s = 1 << l, s2 = 2 * s;
+    // blocks reduced at this level: multiples of 2s in the window with their neighbours in it
+    int g0 = ws + s > 0 ? ws + s : 0;
+    g0 = (g0 + s2 - 1) / s2 * s2;
+    const int gl = (we - 1 < nblocks - 1 ? we - 1 : nblocks - 1);
+    const int ncand = gl >= g0 ? (gl - g0) / s2 + 1 : 0;
+    for (int t = threadIdx.x; t < ncand * nb; t += blockDim.x) {
+      const int j = t / nb, row = t - j * nb;
+      const int g = g0 + j * s2;
+      const bool right = g + s < nblocks;
+      if (right && g + s >= we) continue;
+      const double* Mm = F + lv.offM[l] + (size_t)(g >> (l + 1)) * 2 * nn + row;
+      const double* Mp = Mm + nn;
+      const double* vl = sb + (size_t)(g - s - ws) * nb;
+      const double* vr = sb + (size_t)(g + s - ws) * nb;
+      const bool left = g > 0;
+      double acc = 0.0;
+      if constexpr (NB > 0) {
+        double fm[NB], fp[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          fm[c] = left ? Mm[c * NB] : 0.0;
+          fp[c] = right ? Mp[c * NB] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          if (left) acc += fm[c] * vl[c];
+          if (right) acc += fp[c] * vr[c];
+        }
+      } else {
+        if (left)
+          for (int c = 0; c < nb; ++c) acc += Mm[(size_t)c * nb] * vl[c];
+        if (right)
+          for (int c = 0; c < nb; ++c) acc += Mp[(size_t)c * nb] * vr[c];
+      }
+      sb[(size_t)(g - ws) * nb + row] -= acc;
+    }
+    __syncthreads();
+  }
+  const int o0 = (int)blockIdx.x * C;
+  for (int t = threadIdx.x; t < C * nb; t += blockDim.x) {
+    const int p = t / nb, r = t - p * nb;
+    const int g = o0 + p;
+    if (g < nblocks) bred[bpos(g, bstride, r, nzf)] = sb[(size_t)(g - ws) * nb + r];
+  }
+}
+
+// Every level of the back substitution in one launch.  Workgroup w owns the blocks
+// [w C, (w+1) C) with C a multiple of S = 2^nl: the blocks that are multiples of S (solved by
+// the dense step) bound the chunk, and every other block of it follows from them and from the
+// chunk's reduced right-hand side alone.
+template <int NB>
+__global__ __launch_bounds__(256) void k_bcr_bwd_all(const double* __restrict__ bred,
+                                                     double* __restrict__ x,
+                                                     const double* __restrict__ Bk, BcrLevels lv,
+                                                     int nblocks, int C, int bstride, int nzf,
+                                                     int nb_rt) {
+  extern __shared__ double sm[];
+  const int nb = NB > 0 ? NB : nb_rt;
+  double* sx = sm;                         // [C + 1][nb]
+  double* sv = sm + (size_t)(C + 1) * nb;  // [C][nb]
+  const int S = 1 << lv.nl;
+  const int g0 = (int)blockIdx.x * C;
+  for (int t = threadIdx.x; t < C * nb; t += blockDim.x) {
+    const int p = t / nb, r = t - p * nb;
+    const int g = g0 + p;
+    sv[t] = g < nblocks ? bred[bpos(g, bstride, r, nzf)] : 0.0;
+  }
+  const int nd = C / S + 1;
+  for (int t = threadIdx.x; t < nd * nb; t += blockDim.x) {
+    const int m = t / nb, r = t - m * nb;
+    const int g = g0 + m * S;
+    sx[(size_t)m * S * nb + r] = g < nblocks ? x[bpos(g, bstride, r, nzf)] : 0.0;
+  }
+  __syncthreads();
+  const size_t nn = (size_t)nb * nb;
+  for (int l = lv.nl - 1; l >= 0; --l) {
+    const int s = 1 << l, s2 = 2 * s;
+    const int ncand = C / s2;  // blocks g0 + s + j 2s
+    for (int t = threadIdx.x; t < ncand * nb; t += blockDim.x) {
+      const int j = t / nb, row = t - j * nb;
+      const int g = g0 + s + j * s2;
+      if (g >= nblocks) continue;
+      const double* DO = Bk + lv.offB[l] + (size_t)(g >> (l + 1)) * 3 * nn + row;
+      const double* DL = DO + nn;
+      const double* DU = DL + nn;
+      const double* vb = sv + (size_t)(g - g0) * nb;
+      const double* xl = sx + (size_t)(g - s - g0) * nb;
+      const double* xr = sx + (size_t)(g + s - g0) * nb;
+      const bool right = g + s < nblocks;
+      double acc = 0.0;
+      if constexpr (NB > 0) {
+        double fo[NB], fl[NB], fu[NB];
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          fo[c] = DO[c * NB];
+          fl[c] = DL[c * NB];
+          fu[c] = right ? DU[c * NB] : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+          acc += fo[c] * vb[c] - fl[c] * xl[c];
+          if (right) acc -= fu[c] * xr[c];
+        }
+      } else {
+        for (int c = 0; c < nb; ++c)
+          acc += DO[(size_t)c * nb] * vb[c] - DL[(size_t)c * nb] * xl[c];
+        if (right)
+          for (int c = 0; c < nb; ++c) acc -= DU[(size_t)c * nb] * xr[c];
+      }
+      sx[(size_t)(g - g0) * nb + row] = acc;
+    }
+    __syncthreads();
+  }
+  for (int t = threadIdx.x; t < C * nb; t += blockDim.x) {
+    const int p = t / nb, r = t - p * nb;
+    const int g = g0 + p;
+    if (g < nblocks && (p & (S - 1)) != 0) x[bpos(g, bstride, r, nzf)] = sx[t];
+  }
+}
+
+static int bcr_chunk(int nl) { return (1 << nl) > 16 ? (1 << nl) : 16; }
+size_t bcr_fwd_all_smem(int nl, int nb) {
+  return (size_t)(bcr_chunk(nl) + 2 * ((1 << nl) - 1)) * nb * sizeof(double);
+}
+size_t bcr_bwd_all_smem(int nl, int nb) {
+  return (size_t)(2 * bcr_chunk(nl) + 1) * nb * sizeof(double);
+}
+
+template <int NB>
+static hipError_t bcr_all_launch(bool fwd, const double* in, double* out, const double* M,
+                                 const BcrLevels& lv, int nblocks, int bstride, int nzf, int nb,
+                                 hipStream_t st) {
+  const int C = bcr_chunk(lv.nl);
+  if (fwd) {
+    const size_t smem = bcr_fwd_all_smem(lv.nl, nb);
+    const hipError_t e = allow_lds(k_bcr_fwd_all<NB>, smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bcr_fwd_all<NB>), dim3(nblk(nblocks, C)), dim3(1024), smem, st, in, out,
+                       M, lv, nblocks, C, bstride, nzf, nb);
+  } else {
+    const size_t smem = bcr_bwd_all_smem(lv.nl, nb);
+    const hipError_t e = allow_lds(k_bcr_bwd_all<NB>, smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_bcr_bwd_all<NB>), dim3(nblk(nblocks, C)), dim3(256), smem, st, in, out,
+                       M, lv, nblocks, C, bstride, nzf, nb);
+  }
+  return hipGetLastError();
+}
+
+static hipError_t bcr_all(bool fwd, const double* in, double* out, const double* M,
+                          const BcrLevels& lv, int nblocks, int bstride, int nzf, int nb,
+                          hipStream_t st) {
+  switch (nb) {
+    case 4: return bcr_all_launch<4>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
+    case 8: return bcr_all_launch<8>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
+    case 16: return bcr_all_launch<16>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
+    default: return bcr_all_launch<0>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
+  }
+}
+
+hipError_t bcr_fwd_all(const double* b, double* bred, const double* F, const BcrLevels& lv,
+                       int nblocks, int bstride, int nzf, int nb, hipStream_t st) {
+  return bcr_all(true, b, bred, F, lv, nblocks, bstride, nzf, nb, st);
+}
+
+hipError_t bcr_bwd_all(const double* bred, double* x, const double* Bk, const BcrLevels& lv,
+                       int nblocks, int bstride, int nzf, int nb, hipStream_t st) {
+  return bcr_all(false, bred, x, Bk, lv, nblocks, bstride, nzf, nb, st);
 }
 
 hipError_t bcr_fwd(double* b, const double* F, int n, int stride, int neven, int bstride,
@@ -2230,11 +2536,28 @@ __global__ __launch_bounds__(RED_THREADS) void k_castdot(const T* __restrict__ x
                                                          double* pzq, double* prz, unsigned N) {
   __shared__ double sh[16];
   double a = 0, c = 0;
-  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x) {
-    const double zv = (double)x0[g];
-    z[g] = zv;
-    if (q) a += zv * q[g];
-    c += r[g] * zv;
+  // U elements per batch, all loads issued before the stores (grid-stride order kept)
+  constexpr int U = 8;
+  const unsigned stride = gridDim.x * blockDim.x;
+  for (size_t g0 = 0; g0 < N; g0 += (size_t)U * stride) {
+    double zv[U], qv[U], rv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t g = g0 + blockIdx.x * blockDim.x + threadIdx.x + (size_t)u * stride;
+      const bool ok = g < N;
+      zv[u] = ok ? (double)x0[g] : 0.0;
+      qv[u] = (ok && q) ? q[g] : 0.0;
+      rv[u] = ok ? r[g] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const size_t g = g0 + blockIdx.x * blockDim.x + threadIdx.x + (size_t)u * stride;
+      if (g < N) {
+        z[g] = zv[u];
+        if (q) a += zv[u] * qv[u];
+        c += rv[u] * zv[u];
+      }
+    }
   }
   if (q) a = block_sum(a, sh);
   c = block_sum(c, sh);

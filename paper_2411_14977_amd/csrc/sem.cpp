@@ -92,6 +92,8 @@ struct Ctx {
   // coarse solve
   semh::BcrPlan plan;
   double *bcrF = nullptr, *bcrB = nullptr, *bcrLast = nullptr, *bcrDense = nullptr;
+  double* bcrRed = nullptr;  // reduced right-hand side of the one-launch reduction
+  semk::BcrLevels bcrLv;     // its level table (nl = -1: per-level kernels)
   int* rowmap = nullptr;
   // FP64 right-hand side of the next V-cycle, read by the first smoothing step of level 0
   const double* vin64 = nullptr;
@@ -440,6 +442,20 @@ void coarse_solve(Ctx* c) {
   }
   const semh::BcrPlan& pl = c->plan;
   const int nl = (int)pl.levs.size();
+  if (c->bcrLv.nl >= 0) {
+    const double* br = b;
+    if (nl > 0) {
+      HK(semk::bcr_fwd_all(b, c->bcrRed, c->bcrF, c->bcrLv, pl.nblocks, pl.bstride, L.nzn - 1,
+                           pl.nb, c->st));
+      br = c->bcrRed;
+    }
+    HK(semk::bcr_dense(c->bcrDense, br, x, pl.dense_n * pl.nb, pl.nb, pl.dense_stride,
+                       pl.bstride, L.nzn - 1, c->st));
+    if (nl > 0)
+      HK(semk::bcr_bwd_all(br, x, c->bcrB, c->bcrLv, pl.nblocks, pl.bstride, L.nzn - 1, pl.nb,
+                           c->st));
+    return;
+  }
   for (int l = 0; l < nl; ++l) {
     const auto& v = pl.levs[l];
     HK(semk::bcr_fwd(b, c->bcrF + v.offM, v.n, v.stride, v.neven, pl.bstride, L.nzn - 1, pl.nb,
@@ -1218,6 +1234,18 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       c->bcrLast = upload(c, c->plan.last);
       c->bcrDense = upload(c, c->plan.dense);
       c->rowmap = upload(c, c->plan.rowmap);
+      // one launch per direction where the level table and the LDS windows fit
+      const int nlv = (int)c->plan.levs.size();
+      c->bcrLv.nl = -1;
+      if (nlv <= semk::BCR_MAXL && semk::bcr_fwd_all_smem(nlv, c->plan.nb) <= 65536 &&
+          semk::bcr_bwd_all_smem(nlv, c->plan.nb) <= 65536) {
+        c->bcrLv.nl = nlv;
+        for (int l = 0; l < nlv; ++l) {
+          c->bcrLv.offM[l] = (long long)c->plan.levs[l].offM;
+          c->bcrLv.offB[l] = (long long)c->plan.levs[l].offB;
+        }
+        c->bcrRed = (double*)dalloc(c, (size_t)LC.N * sizeof(double));
+      }
     }
   }
   // lambda_hat per smoothed level
