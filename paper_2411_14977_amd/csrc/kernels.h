@@ -150,6 +150,29 @@ size_t prolong2d_smem(int Pf, int Pc, int Nz, bool dbl);
 hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
                      int Nz, int Pf, int Pc, hipStream_t st, StageFold f = StageFold());
 
+// ---- a coarse level's smoothing sequence in one kernel (2D) --------------------------------
+// step s of the sequence: d = cd[s] d + cr[s] dinv (b - A x); x += d.  PRE: x = 0 on entry (the
+// first step needs no operator), then the residual is restricted to the next level: rc = R r
+// (top node zero when masked), x written to xo.  POST: x_in + P ec (the next level's correction)
+// is smoothed and written to xo (xo != x_in).  b, dinv, G: the level's; J: its prolongation
+// matrix from the next level; TC of rc / ec: FP64 when dbl_c.  The plan (coarse2d_plan) fixes
+// the window; W = 0: the level does not fit, use the per-step kernels.
+constexpr int CO_MAXS = 8;
+struct CoarseSeq {
+  int ns = 0;
+  double cd[CO_MAXS] = {0}, cr[CO_MAXS] = {0};
+};
+struct CoarsePlan {
+  int W = 0, HL = 0, nslot = 0;
+  size_t smem = 0;
+};
+CoarsePlan coarse2d_plan(int P, int PC, int Nz, bool dbl, bool pre, int applies);
+bool coarse2d_supported(int P, int PC);
+hipError_t coarse2d(bool pre, const CoarsePlan& pl, int P, int PC, bool dbl, GType gt, bool dbl_c,
+                    const void* x, void* xo, const void* b, const void* dinv, const void* G,
+                    const void* ec, void* rc, const double* J, int Nx, int Nz, int masked,
+                    const CoarseSeq& sq, hipStream_t st);
+
 // ---- exact coarse solve (block cyclic reduction, FP64, in place on b, result in x) ---------
 // unknown r of block blk sits at blk * bstride + r + r / nzf (nzf = free nodes per line)
 hipError_t bcr_fwd(double* b, const double* F, int n, int stride, int neven, int bstride,

@@ -237,10 +237,27 @@ __device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int n
 // between vertically stacked elements summed and, when masked, the Dirichlet top node equal to
 // x; xin[l] holds x(line l, node t) for t < nzn, as filled by ldx(xin) (called when act and
 // t < nzn).  Every thread of the block calls this.
+// column_apply with the factors already in registers (g as load_g2d gives them)
+template <int P, typename T, typename Ldx, typename Pre>
+__device__ __forceinline__ void column_apply_g(const T (&g)[3][P + 1], Ldx&& ldx, int t, bool act,
+                                               int Nz, int nzn, int nzp, int masked, T* base,
+                                               T (&xin)[P + 1], Pre&& pre);
+
 template <int P, typename T, typename TG, typename Ldx, typename Pre>
 __device__ __forceinline__ void column_apply(Ldx&& ldx, const TG* __restrict__ G, int ex,
                                              int nthr, int t, bool act, int Nz, int nzn, int nzp,
                                              int masked, T* base, T (&xin)[P + 1], Pre&& pre) {
+  // every global load of the block (the caller's through pre()) is issued before the first LDS
+  // store
+  T g[3][P + 1];
+  if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
+  column_apply_g<P, T>(g, ldx, t, act, Nz, nzn, nzp, masked, base, xin, pre);
+}
+
+template <int P, typename T, typename Ldx, typename Pre>
+__device__ __forceinline__ void column_apply_g(const T (&g)[3][P + 1], Ldx&& ldx, int t, bool act,
+                                               int Nz, int nzn, int nzp, int masked, T* base,
+                                               T (&xin)[P + 1], Pre&& pre) {
   constexpr int NP = P + 1;
   constexpr int V = lds_vec<T>();
   constexpr int NPp = (NP + V - 1) / V * V;
@@ -251,11 +268,6 @@ __device__ __forceinline__ void column_apply(Ldx&& ldx, const TG* __restrict__ G
   T* X2 = X1 + Nz * NP * NPp;      // [Nz][NP(j)][NPp(i)]: w_r (phases 3-4)
   T* su = X2;                      // [NP][nzp] column: input (phases 1-2), output (phase 6)
   T* stp = X2 + NP * nzp;          // [Nz][NP] element-top values (phases 5-6)
-
-  // every global load of the block (the caller's through pre()) is issued before the first LDS
-  // store
-  T g[3][NP];
-  if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
   if (act && t < nzn) ldx(xin);
   pre();
   if (act && t < nzn) {
@@ -2112,6 +2124,295 @@ hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const doubl
   if (dbl) return prolong2d_p<double, double>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
   if (dbl_c) return prolong2d_p<float, double>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
   return prolong2d_p<float, float>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
+}
+
+// ------------------------------------------------------------------------------------------
+// A coarse level's whole smoothing sequence in one kernel (2D)
+// ------------------------------------------------------------------------------------------
+// PRE: the pre-smoothing from x = 0, the residual and its restriction to the next level (rc);
+// POST: the prolongation of the next level's correction (ec) into x and the post-smoothing.
+// Workgroup w owns the element columns [w W, (w+1) W) and holds nslot column slots: the owned
+// columns and HL columns to their left, the rest to their right.  Values stay exact only where
+// every element they depend on is in the window, which moves in by one column per operator
+// apply on either side; the margins (the number of applies, PRE one more on the left, whose
+// fine lines feed the shared coarse line of the first owned column) keep the owned columns
+// exact, and everything outside them is computed but never stored.  A thread keeps its nodes'
+// x, d, b and dinv in registers for the whole sequence and the factors of its element too;
+// each apply exchanges x through the window array WX and runs the column operator per slot.
+// POST reads x and writes xo (another vector: other workgroups still read x).
+template <int P, int PC, typename T, typename TG, typename TC, bool PRE>
+__global__ __launch_bounds__(1024) void k_coarse2d(const T* __restrict__ x, T* __restrict__ xo,
+                                                   const T* __restrict__ b,
+                                                   const T* __restrict__ dinv,
+                                                   const TG* __restrict__ G,
+                                                   const TC* __restrict__ ec, TC* __restrict__ rc,
+                                                   const double* __restrict__ Jg, int Nx, int Nz,
+                                                   int masked, int W, int HL, int nslot,
+                                                   CoarseSeq sq) {
+  constexpr int NP = P + 1, NPC = PC + 1;
+  constexpr int V = lds_vec<T>();
+  constexpr int JP = (NP * NPC + V - 1) / V * V;
+  const int nzn = Nz * P + 1, nzc = Nz * PC + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int nthr = NP * Nz;
+  const int cs = threadIdx.x / nthr;
+  const int t = threadIdx.x - cs * nthr;
+  const int c0 = (int)blockIdx.x * W;
+  const int ex = c0 - HL + cs;
+  const bool valid = cs < nslot && ex >= 0 && ex < Nx;
+  const bool nodes = valid && t < nzn;
+  const bool owned = valid && cs >= HL && cs < HL + W;
+  const int nl = (ex == Nx - 1) ? NP : P;  // lines of this column (the last one also line P)
+  const int slot = slot2d_elems<int>(NP, Nz, nzp, V);
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sJ = reinterpret_cast<T*>(smem_raw);              // [NP][NPC]
+  T* WX = sJ + JP;                                     // window lines [nslot P + 1][nzp]
+  T* slots = WX + (size_t)(nslot * P + 1) * nzp;
+  T* base = slots + (size_t)(valid ? cs : 0) * slot;   // this column's apply space
+  const size_t g0 = (size_t)(valid ? ex : 0) * P * nzn + t;
+
+  // every global load first: factors, b, dinv (and x, the coarse correction for POST)
+  T g[3][NP], xr[NP], dr[NP], br[NP], di[NP];
+  if (valid) load_g2d<P, T, TG>(G, ex, nthr, t, g);
+#pragma unroll
+  for (int l = 0; l < NP; ++l) {
+    xr[l] = 0;
+    dr[l] = 0;
+    br[l] = 0;
+    di[l] = 0;
+    if (nodes && l < nl) {
+      br[l] = b[g0 + (size_t)l * nzn];
+      di[l] = dinv[g0 + (size_t)l * nzn];
+      if constexpr (!PRE) xr[l] = x[g0 + (size_t)l * nzn];
+    }
+  }
+  for (int k = threadIdx.x; k < NP * NPC; k += blockDim.x) sJ[k] = (T)Jg[k];
+  for (int k = threadIdx.x; k < (nslot * P + 1) * nzp; k += blockDim.x) WX[k] = (T)0;
+  T* sce = base;                 // POST: coarse lines of the column [NPC][nzc]
+  T* stv = base + NPC * nzc;     // POST: interpolated along z [NPC][nzn]
+  if constexpr (!PRE) {
+    if (valid) {
+      const size_t cb = (size_t)ex * PC * nzc;
+      for (int k = t; k < NPC * nzc; k += nthr) sce[k] = (T)ec[cb + k];
+    }
+  }
+  __syncthreads();
+  if constexpr (!PRE) {  // x += P ec on the window: along z, then along x
+    if (valid) {
+      for (int k = t; k < NPC * nzn; k += nthr) {
+        const int kc = k / nzn, izf = k - kc * nzn;
+        int e = izf / P;
+        if (e > Nz - 1) e = Nz - 1;
+        const int jf = izf - e * P;
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < NPC; ++q) s += sJ[jf * NPC + q] * sce[kc * nzc + e * PC + q];
+        stv[k] = s;
+      }
+    }
+    __syncthreads();
+    if (nodes) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        if (l < nl) {
+          T s = 0;
+#pragma unroll
+          for (int q = 0; q < NPC; ++q) s += sJ[l * NPC + q] * stv[q * nzn + t];
+          xr[l] += s;
+        }
+      }
+    }
+    __syncthreads();  // the apply space is reused below
+  }
+
+  const bool mtop = masked && t == nzn - 1;  // Dirichlet node: its residual is zero
+  // one operator apply of the window's x: ax[l] = (A x)(line l of this column, node t)
+  auto apply = [&](T (&ax)[NP]) {
+    if (nodes) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l)
+        if (l < nl) WX[(size_t)(cs * P + l) * nzp + t] = xr[l];
+    }
+    __syncthreads();
+    T xin[NP];
+    column_apply_g<P, T>(
+        g,
+        [&](T(&v)[NP]) {
+#pragma unroll
+          for (int l = 0; l < NP; ++l) v[l] = WX[(size_t)(cs * P + l) * nzp + t];
+        },
+        t, valid, Nz, nzn, nzp, masked, base, xin, [] {});
+    if (nodes) {
+      const T* su = base + Nz * NP * ((NP + V - 1) / V * V);
+      const T* sl = su - slot;
+      const bool left = ex > 0 && cs > 0 && !mtop;
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        T a = 0;
+        if (l < nl) {
+          a = su[l * nzp + t];
+          if (l == 0 && left) a += sl[P * nzp + t];
+        }
+        ax[l] = a;
+      }
+    }
+    __syncthreads();  // the apply space is written again by the next apply
+  };
+
+  for (int st = 0; st < sq.ns; ++st) {
+    const T cd = (T)sq.cd[st], cr = (T)sq.cr[st];
+    T ax[NP];
+#pragma unroll
+    for (int l = 0; l < NP; ++l) ax[l] = 0;
+    if (!(PRE && st == 0)) apply(ax);  // PRE starts from x = 0: A x = 0
+    if (nodes) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l) {
+        if (l < nl) {
+          const T r = mtop ? (T)0 : br[l] - ax[l];
+          const T dn = cr * di[l] * r + cd * dr[l];
+          dr[l] = dn;
+          xr[l] += dn;
+        }
+      }
+    }
+  }
+
+  if constexpr (PRE) {
+    // residual of the smoothed x, into WX (lines of each column), then its restriction onto
+    // the owned coarse lines: along x first, then along z
+    T ax[NP];
+    apply(ax);
+    if (nodes) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l)
+        if (l < nl) WX[(size_t)(cs * P + l) * nzp + t] = mtop ? (T)0 : br[l] - ax[l];
+    }
+    __syncthreads();
+    const int nown = (ex == Nx - 1) ? NPC : PC;
+    T* sxs = base;  // [NPC][nzn]
+    if (owned) {
+      for (int k = t; k < nown * nzn; k += nthr) {
+        const int kc = k / nzn, izf = k - kc * nzn;
+        const int ka = (kc == PC) ? PC : kc;  // kc == PC only for the last column
+        T s = 0;
+#pragma unroll
+        for (int i = 0; i < NP; ++i) s += sJ[i * NPC + ka] * WX[(size_t)(cs * P + i) * nzp + izf];
+        if (ka == 0 && ex > 0) {
+#pragma unroll
+          for (int i = 0; i < P; ++i)
+            s += sJ[i * NPC + PC] * WX[(size_t)((cs - 1) * P + i) * nzp + izf];
+        }
+        sxs[k] = s;
+      }
+    }
+    __syncthreads();
+    if (owned) {
+      for (int k = t; k < nown * nzc; k += nthr) {
+        const int kc = k / nzc, izc = k - kc * nzc;
+        T s = pull1d<T, P, PC>(sxs + kc * nzn, 1, izc, Nz, P, PC, sJ);
+        if (masked && izc == nzc - 1) s = 0;
+        rc[(size_t)(ex * PC + kc) * nzc + izc] = (TC)s;
+      }
+    }
+    if (owned && t < nzn) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l)
+        if (l < nl) xo[g0 + (size_t)l * nzn] = xr[l];
+    }
+  } else {
+    if (owned && t < nzn) {
+#pragma unroll
+      for (int l = 0; l < NP; ++l)
+        if (l < nl) xo[g0 + (size_t)l * nzn] = xr[l];
+    }
+  }
+}
+
+// window shape of a coarse-level kernel: columns per workgroup and margins, 0 when it does not
+// fit one workgroup (1024 threads) or its LDS
+CoarsePlan coarse2d_plan(int P, int PC, int Nz, bool dbl, bool pre, int applies) {
+  CoarsePlan pl;
+  const int nthr = (P + 1) * Nz;
+  const int V = dbl ? 2 : 4;
+  const int nzn = Nz * P + 1, nzc = Nz * PC + 1;
+  const int nzp = (nzn + V - 1) / V * V;
+  const int HL = applies + (pre ? 1 : 0), HR = applies;
+  const int maxs = 1024 / nthr;
+  const int W = maxs - HL - HR;
+  if (W < 1) return pl;
+  const size_t slot = slot2d_elems<size_t>(P + 1, Nz, nzp, V);
+  const size_t scratch = pre ? (size_t)(PC + 1) * nzn : (size_t)(PC + 1) * (nzc + nzn);
+  if (scratch > slot) return pl;
+  const int nslot = W + HL + HR;
+  const size_t JP = ((size_t)(P + 1) * (PC + 1) + V - 1) / V * V;
+  const size_t elems = JP + (size_t)(nslot * P + 1) * nzp + (size_t)nslot * slot;
+  const size_t bytes = elems * (dbl ? 8 : 4);
+  if (bytes > 160 * 1024) return pl;
+  pl.W = W;
+  pl.HL = HL;
+  pl.nslot = nslot;
+  pl.smem = bytes;
+  return pl;
+}
+
+template <int P, int PC, typename T, typename TG, typename TC, bool PRE>
+static hipError_t coarse2d_t(const CoarsePlan& pl, const void* x, void* xo, const void* b,
+                             const void* dinv, const void* G, const void* ec, void* rc,
+                             const double* J, int Nx, int Nz, int masked, const CoarseSeq& sq,
+                             hipStream_t st) {
+  const hipError_t e = allow_lds(k_coarse2d<P, PC, T, TG, TC, PRE>, pl.smem);
+  if (e != hipSuccess) return e;
+  const unsigned blocks = (unsigned)((Nx + pl.W - 1) / pl.W);
+  const int nthr = (P + 1) * Nz;
+  hipLaunchKernelGGL((k_coarse2d<P, PC, T, TG, TC, PRE>), dim3(blocks), dim3(pl.nslot * nthr),
+                     pl.smem, st, (const T*)x, (T*)xo, (const T*)b, (const T*)dinv,
+                     (const TG*)G, (const TC*)ec, (TC*)rc, J, Nx, Nz, masked, pl.W, pl.HL,
+                     pl.nslot, sq);
+  return hipGetLastError();
+}
+
+template <int P, int PC, bool PRE>
+static hipError_t coarse2d_ty(const CoarsePlan& pl, bool dbl, GType gt, bool dbl_c, const void* x,
+                              void* xo, const void* b, const void* dinv, const void* G,
+                              const void* ec, void* rc, const double* J, int Nx, int Nz,
+                              int masked, const CoarseSeq& sq, hipStream_t st) {
+  if (dbl)
+    return coarse2d_t<P, PC, double, double, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx,
+                                                          Nz, masked, sq, st);
+  if (gt == G_BF16) {
+    if (dbl_c)
+      return coarse2d_t<P, PC, float, uint16_t, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J,
+                                                             Nx, Nz, masked, sq, st);
+    return coarse2d_t<P, PC, float, uint16_t, float, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx,
+                                                          Nz, masked, sq, st);
+  }
+  if (dbl_c)
+    return coarse2d_t<P, PC, float, float, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx, Nz,
+                                                        masked, sq, st);
+  return coarse2d_t<P, PC, float, float, float, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx, Nz,
+                                                     masked, sq, st);
+}
+
+bool coarse2d_supported(int P, int PC) {
+  return (P == 4 && (PC == 2 || PC == 1)) || (P == 3 && (PC == 2 || PC == 1)) ||
+         (P == 2 && PC == 1);
+}
+
+hipError_t coarse2d(bool pre, const CoarsePlan& pl, int P, int PC, bool dbl, GType gt, bool dbl_c,
+                    const void* x, void* xo, const void* b, const void* dinv, const void* G,
+                    const void* ec, void* rc, const double* J, int Nx, int Nz, int masked,
+                    const CoarseSeq& sq, hipStream_t st) {
+  if (pl.W < 1 || sq.ns < 1 || sq.ns > CO_MAXS) return hipErrorInvalidValue;
+#define SEM_CO(a, c)                                                                            \
+  if (P == a && PC == c)                                                                        \
+    return pre ? coarse2d_ty<a, c, true>(pl, dbl, gt, dbl_c, x, xo, b, dinv, G, ec, rc, J, Nx,  \
+                                         Nz, masked, sq, st)                                    \
+               : coarse2d_ty<a, c, false>(pl, dbl, gt, dbl_c, x, xo, b, dinv, G, ec, rc, J, Nx, \
+                                          Nz, masked, sq, st);
+  SEM_CO(4, 2) SEM_CO(4, 1) SEM_CO(3, 2) SEM_CO(3, 1) SEM_CO(2, 1)
+#undef SEM_CO
+  return hipErrorInvalidValue;
 }
 
 // ------------------------------------------------------------------------------------------

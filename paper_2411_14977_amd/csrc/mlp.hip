@@ -1012,7 +1012,7 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
   __shared__ double sh[16];
   const unsigned stride = gridDim.x * blockDim.x;
   const unsigned g0 = blockIdx.x * blockDim.x + threadIdx.x;
-  T rr[UPD_IT], qq[UPD_IT], cc[UPD_IT];
+  T rr[UPD_IT], qq[UPD_IT], cc[UPD_IT], xx[UPD_IT], di[UPD_IT];
 #pragma unroll
   for (int k = 0; k < UPD_IT; ++k) {
     const unsigned g = g0 + k * stride;
@@ -1020,6 +1020,8 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
       rr[k] = R[g];
       qq[k] = ax_at(yq, Sq, g, nzn, P);
       cc[k] = c[g];
+      xx[k] = x[g];
+      di[k] = dinv ? dinv[g] : (T)0;
     }
   }
   double a0 = 0.0, a1 = 0.0;
@@ -1032,15 +1034,14 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
   const T al = ok ? (T)alpha : (T)0;
   // node g: x += alpha c, R = r - alpha q (accepted step); then, with dinv, the first smoothing
   // step from that residual: dn = sr dinv R, d = dn (store_d), x += dn
-  auto node = [&](unsigned g, T r, T q, T cv) {
-    T xv = x[g];
+  auto node = [&](unsigned g, T r, T q, T cv, T xv, T dg) {
     if (ok) {
       xv += al * cv;
       r = r - al * q;
       R[g] = r;
     }
     if (dinv) {
-      const T dn = sr * dinv[g] * r;
+      const T dn = sr * dg * r;
       if (store_d) d[g] = dn;
       xv += dn;
     }
@@ -1049,10 +1050,10 @@ __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __r
 #pragma unroll
   for (int k = 0; k < UPD_IT; ++k) {
     const unsigned g = g0 + k * stride;
-    if (g < N) node(g, rr[k], qq[k], cc[k]);
+    if (g < N) node(g, rr[k], qq[k], cc[k], xx[k], di[k]);
   }
   for (unsigned g = g0 + UPD_IT * stride; g < N; g += stride)
-    node(g, R[g], ax_at(yq, Sq, g, nzn, P), c[g]);
+    node(g, R[g], ax_at(yq, Sq, g, nzn, P), c[g], x[g], dinv ? dinv[g] : (T)0);
   if (blockIdx.x == 0 && threadIdx.x == 0 && !ok) skips[0] += 1;
 }
 

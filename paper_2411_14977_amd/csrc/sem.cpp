@@ -43,6 +43,8 @@ struct DLevel {
   // 2D smoothed levels where the fused smoother step fits: the second solution vector; each
   // fused step reads x and writes xalt, then the two swap (x is always the current iterate)
   void* xalt = nullptr;
+  // 2D coarse levels: the pre- and post-smoothing sequences as one kernel each (W = 0: no)
+  semk::CoarsePlan cpre, cpost;
   // Schwarz smoother: inverses of the element blocks [E][n][n] and the element results [E][n]
   void *Ainv_s = nullptr, *Zs = nullptr;
   size_t nS = 0;
@@ -515,6 +517,65 @@ void learned_stage(Ctx* c, bool post = false, semk::StageFold* f = nullptr) {
 }
 
 // z = B r on level 0 buffers: input r (FP64, device), output lev[0].x
+// the step coefficients of level l's smoothing sequence (as smooth() takes them) and the number
+// of operator applies of its one-kernel form; false when that form does not apply
+bool coarse_seq(const Ctx* c, int l, bool pre, semk::CoarseSeq* sq, int* applies) {
+  const sem_mesh_desc& d = c->desc;
+  const DLevel& L = c->lev[l];
+  if (d.smoother == SEM_SMOOTH_CHEBYSHEV) {
+    const int k = d.cheb_degree;
+    if (k < 1 || k > semk::CO_MAXS) return false;
+    const double a = d.cheb_lo * L.lam, b = d.cheb_hi * L.lam;
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+    const double sigma1 = theta / delta;
+    double rho = 1.0 / sigma1;
+    sq->ns = k;
+    sq->cd[0] = 0.0;
+    sq->cr[0] = 1.0 / theta;
+    for (int j = 1; j < k; ++j) {
+      const double rho_new = 1.0 / (2.0 * sigma1 - rho);
+      sq->cd[j] = rho_new * rho;
+      sq->cr[j] = 2.0 * rho_new / delta;
+      rho = rho_new;
+    }
+    *applies = k;
+    return true;
+  }
+  if (d.smoother == SEM_SMOOTH_JACOBI) {
+    const int nu = pre ? d.nu_pre : d.nu_post;
+    if (nu < 1 || nu > semk::CO_MAXS) return false;
+    sq->ns = nu;
+    for (int j = 0; j < nu; ++j) {
+      sq->cd[j] = 0.0;
+      sq->cr[j] = d.jacobi_omega;
+    }
+    *applies = nu;
+    return true;
+  }
+  return false;
+}
+
+// level l >= 1 (2D): pre-smoothing + residual + restriction, or prolongation + post-smoothing,
+// in one kernel; false when the level keeps the per-step kernels
+bool coarse_fused(Ctx* c, int l, bool pre) {
+  DLevel& L = c->lev[l];
+  const semk::CoarsePlan& pl = pre ? L.cpre : L.cpost;
+  if (pl.W < 1) return false;
+  semk::CoarseSeq sq;
+  int applies = 0;
+  if (!coarse_seq(c, l, pre, &sq, &applies)) return false;
+  DLevel& C = c->lev[l + 1];
+  if (pre) {
+    HK(semk::coarse2d(true, pl, L.P, C.P, L.dbl, L.gt, C.dbl, nullptr, L.x, L.b, L.dinv, L.G,
+                      nullptr, C.b, L.J, L.Nx, L.Nz, c->masked, sq, c->st));
+  } else {
+    HK(semk::coarse2d(false, pl, L.P, C.P, L.dbl, L.gt, C.dbl, L.x, L.xalt, L.b, L.dinv, L.G,
+                      C.x, nullptr, L.J, L.Nx, L.Nz, c->masked, sq, c->st));
+    std::swap(L.x, L.xalt);
+  }
+  return true;
+}
+
 void vcycle(Ctx* c, const double* r) {
   const int L = (int)c->lev.size();
   DLevel& L0 = c->lev[0];
@@ -528,6 +589,7 @@ void vcycle(Ctx* c, const double* r) {
   }
   semk::StageFold fold;  // the pre-smoothing stage's step, when folded into the transfers
   for (int l = 0; l < L - 1; ++l) {
+    if (l >= 1 && coarse_fused(c, l, true)) continue;
     smooth(c, l, true);
     if (l == 0) c->vin64 = nullptr;
     if (l == 0 && c->stage.enabled && (c->stage_mode & 1)) {
@@ -543,6 +605,7 @@ void vcycle(Ctx* c, const double* r) {
   }
   coarse_solve(c);
   for (int l = L - 2; l >= 0; --l) {
+    if (l >= 1 && coarse_fused(c, l, false)) continue;
     if (l == 0 && fold.c) {
       DLevel& F = c->lev[0];
       DLevel& C1 = c->lev[1];
@@ -1184,6 +1247,21 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     if (semk::restrict2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024 ||
         semk::prolong2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024)
       throw ArgFail{"transfer kernels exceed LDS for this size"};
+  }
+  // coarse levels whose smoothing sequences run as one kernel each (SEM_NO_COARSE_FUSED=1: none)
+  {
+    const char* nf = std::getenv("SEM_NO_COARSE_FUSED");
+    const bool off = nf && nf[0] == '1';
+    for (int l = 1; !off && l + 1 < nl; ++l) {
+      DLevel& L = c->lev[l];
+      const DLevel& C = c->lev[l + 1];
+      if (!L.xalt || !semk::coarse2d_supported(L.P, C.P)) continue;
+      semk::CoarseSeq sq;
+      int apre = 0, apost = 0;
+      if (!coarse_seq(c, l, true, &sq, &apre) || !coarse_seq(c, l, false, &sq, &apost)) continue;
+      L.cpre = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, true, apre);
+      L.cpost = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, false, apost);
+    }
   }
   if (semk::apply2d_smem(orders[0], c->Nz, true) > 160 * 1024)
     throw ArgFail{"operator kernel exceeds LDS for this size"};
