@@ -82,7 +82,7 @@ struct BcrPlan {
   std::vector<int> rowmap;
 };
 bool build_bcr(const LevelGeom& L, const std::vector<double>& Gr, BcrPlan& plan, char* err,
-               size_t errlen, int dense_max = 33);
+               size_t errlen, int dense_max = 65);
 
 // Counter-based SplitMix64 uniform in [-1, 1) (Steele, Lea, Flood 2014), element i of seed.
 double splitmix64_uniform(uint64_t seed, uint64_t i);

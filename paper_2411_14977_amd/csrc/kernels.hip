@@ -2480,19 +2480,50 @@ __global__ __launch_bounds__(256) void k_bcr_bwd(const double* __restrict__ b,
   if (act && q == 0) x[self] = s;
 }
 
-// x at the reduced positions = Ainv b (one wave per row, fixed-order wave reduction)
+// x at the reduced positions = Ainv b: the block gathers b into LDS, then one wave per row
+// (lanes stride the row, 8 loads in flight each; fixed-order wave reduction)
 __global__ __launch_bounds__(256) void k_bcr_dense(const double* __restrict__ Ainv,
                                                    const double* __restrict__ b,
                                                    double* __restrict__ x, int nd, int nb,
                                                    int stride, int bstride, int nzf) {
+  extern __shared__ double sbv[];  // [nd]
+  constexpr int UG = 4, UR = 8;
+  for (int c0 = 0; c0 < nd; c0 += UG * (int)blockDim.x) {
+    double v[UG];
+#pragma unroll
+    for (int u = 0; u < UG; ++u) {
+      const int c = c0 + (int)threadIdx.x + u * (int)blockDim.x;
+      if (c < nd) {
+        const int k = c / nb, r = c - k * nb;
+        v[u] = b[bpos((size_t)k * stride, bstride, r, nzf)];
+      } else {
+        v[u] = 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UG; ++u) {
+      const int c = c0 + (int)threadIdx.x + u * (int)blockDim.x;
+      if (c < nd) sbv[c] = v[u];
+    }
+  }
+  __syncthreads();
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (row >= nd) return;
   const double* a = Ainv + (size_t)row * nd;
   double s = 0.0;
-  for (int c = lane; c < nd; c += 64) {
-    const int k = c / nb, r = c - k * nb;
-    s += a[c] * b[bpos((size_t)k * stride, bstride, r, nzf)];
+  for (int c0 = 0; c0 < nd; c0 += UR * 64) {
+    double av[UR];
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const int c = c0 + lane + u * 64;
+      av[u] = c < nd ? a[c] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UR; ++u) {
+      const int c = c0 + lane + u * 64;
+      if (c < nd) s += av[u] * sbv[c];
+    }
   }
   s = wave_sum(s);
   if (lane == 0) {
@@ -2503,8 +2534,11 @@ __global__ __launch_bounds__(256) void k_bcr_dense(const double* __restrict__ Ai
 
 hipError_t bcr_dense(const double* Ainv, const double* b, double* x, int nd, int nb, int stride,
                      int bstride, int nzf, hipStream_t st) {
-  hipLaunchKernelGGL(k_bcr_dense, dim3(nblk(nd, 4)), dim3(256), 0, st, Ainv, b, x, nd, nb, stride,
-                     bstride, nzf);
+  const size_t smem = (size_t)nd * sizeof(double);
+  const hipError_t e = allow_lds(k_bcr_dense, smem);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_bcr_dense, dim3(nblk(nd, 4)), dim3(256), smem, st, Ainv, b, x, nd, nb,
+                     stride, bstride, nzf);
   return hipGetLastError();
 }
 
@@ -2514,66 +2548,113 @@ hipError_t bcr_dense(const double* Ainv, const double* b, double* x, int nd, int
 // only, so each workgroup recomputes the reductions of its margin instead of waiting for its
 // neighbours (values the window cannot complete are computed too but never leave it).  The
 // reduced right-hand side goes to bred, so no workgroup reads a value another one has updated.
-// Thread (task, row): the rows of one task read consecutive entries of the column-major factor
-// columns; NB > 0 fixes the block size at compile time, so that all of a task's factor loads are
-// in flight together (NB = 0: any size).
+// Tasks (block, row) of all levels are numbered level after level and task k goes to thread
+// k mod blockDim: every thread requests the factor row of its first task at the start, so the
+// levels wait for one memory latency in all (tasks beyond blockDim load theirs when they run).
+// The rows of one task read consecutive entries of the column-major factor columns.  NB > 0
+// fixes the block size at compile time (NB = 0: any size).
 template <int NB>
-__global__ __launch_bounds__(1024) void k_bcr_fwd_all(const double* __restrict__ b,
-                                                      double* __restrict__ bred,
-                                                      const double* __restrict__ F, BcrLevels lv,
-                                                      int nblocks, int C, int bstride, int nzf,
-                                                      int nb_rt) {
+__global__ __launch_bounds__(512) void k_bcr_fwd_all(const double* __restrict__ b,
+                                                     double* __restrict__ bred,
+                                                     const double* __restrict__ F, BcrLevels lv,
+                                                     int nblocks, int C, int bstride, int nzf,
+                                                     int nb_rt) {
   extern __shared__ double sb[];  // [window][nb]
   const int nb = NB > 0 ? NB : nb_rt;
+  constexpr int NBR = NB > 0 ? NB : 1;
   const int S = 1 << lv.nl;
   const int ws = (int)blockIdx.x * C - (S - 1);
   const int Wn = C + 2 * (S - 1);
   const int we = ws + Wn;  // exclusive
+  const int gl = (we - 1 < nblocks - 1 ? we - 1 : nblocks - 1);
+  const size_t nn = (size_t)nb * nb;
+  // blocks reduced at level l: multiples of 2s in the window (their neighbours checked below)
+  auto level_range = [&](int l, int* g0, int* ncand) {
+    const int s = 1 << l, s2 = 2 * s;
+    int g = ws + s > 0 ? ws + s : 0;
+    g = (g + s2 - 1) / s2 * s2;
+    *g0 = g;
+    *ncand = gl >= g ? (gl - g) / s2 + 1 : 0;
+  };
+  // task number k (over all levels, level 0 first) -> level, block, row; false past the end
+  auto task_of = [&](int k, int* tl, int* tg, int* trow) {
+    int tb = 0;
+    for (int l = 0; l < lv.nl; ++l) {
+      int g0, nc;
+      level_range(l, &g0, &nc);
+      const int j = k - tb;
+      if (j >= 0 && j < nc * nb) {
+        *tl = l;
+        *tg = g0 + (j / nb) * (2 << l);
+        *trow = j - (j / nb) * nb;
+        return true;
+      }
+      tb += nc * nb;
+    }
+    return false;
+  };
+  // one task: sb[g][row] -= Mm row . sb[g - s] + Mp row . sb[g + s]; fm, fp: its factor rows
+  auto task_rows = [&](int l, int g, int row, double* fm, double* fp) {
+    const int s = 1 << l;
+    const double* Mm = F + lv.offM[l] + (size_t)(g >> (l + 1)) * 2 * nn + row;
+    const double* Mp = Mm + nn;
+    const bool left = g > 0, right = g + s < nblocks;
+    for (int c = 0; c < nb; ++c) {
+      fm[c] = left ? Mm[(size_t)c * nb] : 0.0;
+      fp[c] = right ? Mp[(size_t)c * nb] : 0.0;
+    }
+  };
+  auto task_apply = [&](int l, int g, int row, const double* fm, const double* fp) {
+    const int s = 1 << l;
+    const bool left = g > 0, right = g + s < nblocks;
+    if (right && g + s >= we) return;  // right neighbour outside the window: not needed
+    const double* vl = sb + (size_t)(g - s - ws) * nb;
+    const double* vr = sb + (size_t)(g + s - ws) * nb;
+    double acc = 0.0;
+    for (int c = 0; c < nb; ++c) {
+      if (left) acc += fm[c] * vl[c];
+      if (right) acc += fp[c] * vr[c];
+    }
+    sb[(size_t)(g - ws) * nb + row] -= acc;
+  };
+  // this thread's first two tasks (k = tid, tid + blockDim): their factor rows are requested
+  // before anything else
+  double fmA[NBR], fpA[NBR], fmB[NBR], fpB[NBR];
+  if constexpr (NB > 0) {
+    int l, g, row;
+    if (task_of((int)threadIdx.x, &l, &g, &row)) task_rows(l, g, row, fmA, fpA);
+    if (task_of((int)(threadIdx.x + blockDim.x), &l, &g, &row)) task_rows(l, g, row, fmB, fpB);
+  }
   for (int t = threadIdx.x; t < Wn * nb; t += blockDim.x) {
     const int p = t / nb, r = t - p * nb;
     const int g = ws + p;
     sb[t] = (g >= 0 && g < nblocks) ? b[bpos(g, bstride, r, nzf)] : 0.0;
   }
   __syncthreads();
-  const size_t nn = (size_t)nb * nb;
+  int tb = 0;
   for (int l = 0; l < lv.nl; ++l) {
-    const int s = 1 << l, s2 = 2 * s;
-    // blocks reduced at this level: multiples of 2s in the window with their neighbours in it
-    int g0 = ws + s > 0 ? ws + s : 0;
-    g0 = (g0 + s2 - 1) / s2 * s2;
-    const int gl = (we - 1 < nblocks - 1 ? we - 1 : nblocks - 1);
-    const int ncand = gl >= g0 ? (gl - g0) / s2 + 1 : 0;
-    for (int t = threadIdx.x; t < ncand * nb; t += blockDim.x) {
-      const int j = t / nb, row = t - j * nb;
-      const int g = g0 + j * s2;
-      const bool right = g + s < nblocks;
-      if (right && g + s >= we) continue;
-      const double* Mm = F + lv.offM[l] + (size_t)(g >> (l + 1)) * 2 * nn + row;
-      const double* Mp = Mm + nn;
-      const double* vl = sb + (size_t)(g - s - ws) * nb;
-      const double* vr = sb + (size_t)(g + s - ws) * nb;
-      const bool left = g > 0;
-      double acc = 0.0;
+    int g0, nc;
+    level_range(l, &g0, &nc);
+    const int s2 = 2 << l;
+    for (int k = (int)threadIdx.x - tb; k < nc * nb; k += blockDim.x) {
+      if (k < 0) continue;
+      const int g = g0 + (k / nb) * s2, row = k - (k / nb) * nb;
       if constexpr (NB > 0) {
-        double fm[NB], fp[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          fm[c] = left ? Mm[c * NB] : 0.0;
-          fp[c] = right ? Mp[c * NB] : 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          if (left) acc += fm[c] * vl[c];
-          if (right) acc += fp[c] * vr[c];
+        const int kk = k + tb;  // task number
+        if (kk == (int)threadIdx.x) {
+          task_apply(l, g, row, fmA, fpA);
+        } else {
+          // the second task was prefetched; later ones (after it) reuse its registers
+          if (kk != (int)(threadIdx.x + blockDim.x)) task_rows(l, g, row, fmB, fpB);
+          task_apply(l, g, row, fmB, fpB);
         }
       } else {
-        if (left)
-          for (int c = 0; c < nb; ++c) acc += Mm[(size_t)c * nb] * vl[c];
-        if (right)
-          for (int c = 0; c < nb; ++c) acc += Mp[(size_t)c * nb] * vr[c];
+        double fm[64], fp[64];  // nb <= 64 on this path (host check)
+        task_rows(l, g, row, fm, fp);
+        task_apply(l, g, row, fm, fp);
       }
-      sb[(size_t)(g - ws) * nb + row] -= acc;
     }
+    tb += nc * nb;
     __syncthreads();
   }
   const int o0 = (int)blockIdx.x * C;
@@ -2587,7 +2668,8 @@ __global__ __launch_bounds__(1024) void k_bcr_fwd_all(const double* __restrict__
 // Every level of the back substitution in one launch.  Workgroup w owns the blocks
 // [w C, (w+1) C) with C a multiple of S = 2^nl: the blocks that are multiples of S (solved by
 // the dense step) bound the chunk, and every other block of it follows from them and from the
-// chunk's reduced right-hand side alone.
+// chunk's reduced right-hand side alone.  As in the forward kernel, the tasks of all levels are
+// numbered level after level (coarsest first) and every thread prefetches its first task's rows.
 template <int NB>
 __global__ __launch_bounds__(256) void k_bcr_bwd_all(const double* __restrict__ bred,
                                                      double* __restrict__ x,
@@ -2596,10 +2678,68 @@ __global__ __launch_bounds__(256) void k_bcr_bwd_all(const double* __restrict__ 
                                                      int nb_rt) {
   extern __shared__ double sm[];
   const int nb = NB > 0 ? NB : nb_rt;
+  constexpr int NBR = NB > 0 ? NB : 1;
   double* sx = sm;                         // [C + 1][nb]
   double* sv = sm + (size_t)(C + 1) * nb;  // [C][nb]
   const int S = 1 << lv.nl;
   const int g0 = (int)blockIdx.x * C;
+  const size_t nn = (size_t)nb * nb;
+  auto task_rows = [&](int l, int g, int row, double* fo, double* fl, double* fu) {
+    const int s = 1 << l;
+    const double* DO = Bk + lv.offB[l] + (size_t)(g >> (l + 1)) * 3 * nn + row;
+    const double* DL = DO + nn;
+    const double* DU = DL + nn;
+    const bool ok = g < nblocks, right = g + s < nblocks;
+    for (int c = 0; c < nb; ++c) {
+      fo[c] = ok ? DO[(size_t)c * nb] : 0.0;
+      fl[c] = ok ? DL[(size_t)c * nb] : 0.0;
+      fu[c] = (ok && right) ? DU[(size_t)c * nb] : 0.0;
+    }
+  };
+  auto task_apply = [&](int l, int g, int row, const double* fo, const double* fl,
+                        const double* fu) {
+    const int s = 1 << l;
+    if (g >= nblocks) return;
+    const bool right = g + s < nblocks;
+    const double* vb = sv + (size_t)(g - g0) * nb;
+    const double* xl = sx + (size_t)(g - s - g0) * nb;
+    const double* xr = sx + (size_t)(g + s - g0) * nb;
+    double acc = 0.0;
+    for (int c = 0; c < nb; ++c) {
+      acc += fo[c] * vb[c] - fl[c] * xl[c];
+      if (right) acc -= fu[c] * xr[c];
+    }
+    sx[(size_t)(g - g0) * nb + row] = acc;
+  };
+  // this thread's first task (levels nl - 1 down to 0; level l has C / 2^(l+1) blocks)
+  int my_l = -1, my_g = 0, my_row = 0;
+  {
+    int tb = 0;
+    for (int l = lv.nl - 1; l >= 0; --l) {
+      const int nc = C >> (l + 1);
+      const int k = (int)threadIdx.x - tb;
+      if (my_l < 0 && k >= 0 && k < nc * nb) {
+        my_l = l;
+        my_g = g0 + (1 << l) + (k / nb) * (2 << l);
+        my_row = k - (k / nb) * nb;
+      }
+      tb += nc * nb;
+    }
+  }
+  double fo0[NBR], fl0[NBR], fu0[NBR];
+  if constexpr (NB > 0) {
+    if (my_l >= 0) {
+      const int s = 1 << my_l;
+      const double* DO = Bk + lv.offB[my_l] + (size_t)(my_g >> (my_l + 1)) * 3 * nn + my_row;
+      const bool ok = my_g < nblocks, right = my_g + s < nblocks;
+#pragma unroll
+      for (int c = 0; c < NB; ++c) {
+        fo0[c] = ok ? DO[c * NB] : 0.0;
+        fl0[c] = ok ? DO[nn + c * NB] : 0.0;
+        fu0[c] = (ok && right) ? DO[2 * nn + c * NB] : 0.0;
+      }
+    }
+  }
   for (int t = threadIdx.x; t < C * nb; t += blockDim.x) {
     const int p = t / nb, r = t - p * nb;
     const int g = g0 + p;
@@ -2612,43 +2752,23 @@ __global__ __launch_bounds__(256) void k_bcr_bwd_all(const double* __restrict__ 
     sx[(size_t)m * S * nb + r] = g < nblocks ? x[bpos(g, bstride, r, nzf)] : 0.0;
   }
   __syncthreads();
-  const size_t nn = (size_t)nb * nb;
+  int tb = 0;
   for (int l = lv.nl - 1; l >= 0; --l) {
+    const int nc = C >> (l + 1);
     const int s = 1 << l, s2 = 2 * s;
-    const int ncand = C / s2;  // blocks g0 + s + j 2s
-    for (int t = threadIdx.x; t < ncand * nb; t += blockDim.x) {
-      const int j = t / nb, row = t - j * nb;
-      const int g = g0 + s + j * s2;
-      if (g >= nblocks) continue;
-      const double* DO = Bk + lv.offB[l] + (size_t)(g >> (l + 1)) * 3 * nn + row;
-      const double* DL = DO + nn;
-      const double* DU = DL + nn;
-      const double* vb = sv + (size_t)(g - g0) * nb;
-      const double* xl = sx + (size_t)(g - s - g0) * nb;
-      const double* xr = sx + (size_t)(g + s - g0) * nb;
-      const bool right = g + s < nblocks;
-      double acc = 0.0;
+    for (int k = (int)threadIdx.x - tb; k < nc * nb; k += blockDim.x) {
+      if (k < 0) continue;
+      const int g = g0 + s + (k / nb) * s2, row = k - (k / nb) * nb;
       if constexpr (NB > 0) {
-        double fo[NB], fl[NB], fu[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          fo[c] = DO[c * NB];
-          fl[c] = DL[c * NB];
-          fu[c] = right ? DU[c * NB] : 0.0;
-        }
-#pragma unroll
-        for (int c = 0; c < NB; ++c) {
-          acc += fo[c] * vb[c] - fl[c] * xl[c];
-          if (right) acc -= fu[c] * xr[c];
-        }
+        if (k + tb != (int)threadIdx.x) task_rows(l, g, row, fo0, fl0, fu0);
+        task_apply(l, g, row, fo0, fl0, fu0);
       } else {
-        for (int c = 0; c < nb; ++c)
-          acc += DO[(size_t)c * nb] * vb[c] - DL[(size_t)c * nb] * xl[c];
-        if (right)
-          for (int c = 0; c < nb; ++c) acc -= DU[(size_t)c * nb] * xr[c];
+        double fo[64], fl[64], fu[64];
+        task_rows(l, g, row, fo, fl, fu);
+        task_apply(l, g, row, fo, fl, fu);
       }
-      sx[(size_t)(g - g0) * nb + row] = acc;
     }
+    tb += nc * nb;
     __syncthreads();
   }
   for (int t = threadIdx.x; t < C * nb; t += blockDim.x) {
@@ -2657,6 +2777,7 @@ __global__ __launch_bounds__(256) void k_bcr_bwd_all(const double* __restrict__ 
     if (g < nblocks && (p & (S - 1)) != 0) x[bpos(g, bstride, r, nzf)] = sx[t];
   }
 }
+
 
 static int bcr_chunk(int nl) { return (1 << nl) > 16 ? (1 << nl) : 16; }
 size_t bcr_fwd_all_smem(int nl, int nb) {
@@ -2675,7 +2796,7 @@ static hipError_t bcr_all_launch(bool fwd, const double* in, double* out, const 
     const size_t smem = bcr_fwd_all_smem(lv.nl, nb);
     const hipError_t e = allow_lds(k_bcr_fwd_all<NB>, smem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_bcr_fwd_all<NB>), dim3(nblk(nblocks, C)), dim3(1024), smem, st, in, out,
+    hipLaunchKernelGGL((k_bcr_fwd_all<NB>), dim3(nblk(nblocks, C)), dim3(512), smem, st, in, out,
                        M, lv, nblocks, C, bstride, nzf, nb);
   } else {
     const size_t smem = bcr_bwd_all_smem(lv.nl, nb);
@@ -2694,7 +2815,9 @@ static hipError_t bcr_all(bool fwd, const double* in, double* out, const double*
     case 4: return bcr_all_launch<4>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
     case 8: return bcr_all_launch<8>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
     case 16: return bcr_all_launch<16>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
-    default: return bcr_all_launch<0>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
+    default:
+      if (nb > 64) return hipErrorInvalidValue;
+      return bcr_all_launch<0>(fwd, in, out, M, lv, nblocks, bstride, nzf, nb, st);
   }
 }
 

@@ -1315,7 +1315,9 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       // one launch per direction where the level table and the LDS windows fit
       const int nlv = (int)c->plan.levs.size();
       c->bcrLv.nl = -1;
-      if (nlv <= semk::BCR_MAXL && semk::bcr_fwd_all_smem(nlv, c->plan.nb) <= 65536 &&
+      const int nbp = c->plan.nb;
+      const bool nb_ok = nbp == 4 || nbp == 8 || nbp == 16 || nbp <= 64;
+      if (nb_ok && nlv <= semk::BCR_MAXL && semk::bcr_fwd_all_smem(nlv, c->plan.nb) <= 65536 &&
           semk::bcr_bwd_all_smem(nlv, c->plan.nb) <= 65536) {
         c->bcrLv.nl = nlv;
         for (int l = 0; l < nlv; ++l) {
