@@ -1316,7 +1316,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       const int nlv = (int)c->plan.levs.size();
       c->bcrLv.nl = -1;
       const int nbp = c->plan.nb;
-      const bool nb_ok = nbp == 4 || nbp == 8 || nbp == 16 || nbp <= 64;
+      const char* nf = std::getenv("SEM_NO_BCR_FUSED");  // 1: the per-level kernels
+      const bool nb_ok = !(nf && nf[0] == '1') && nbp <= 64;
       if (nb_ok && nlv <= semk::BCR_MAXL && semk::bcr_fwd_all_smem(nlv, c->plan.nb) <= 65536 &&
           semk::bcr_bwd_all_smem(nlv, c->plan.nb) <= 65536) {
         c->bcrLv.nl = nlv;

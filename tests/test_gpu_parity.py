@@ -372,3 +372,32 @@ def test_schwarz_rejects_3d():
     wl = W.tank3d(2, 2, 2, 2, L=0.4, name="t3s")
     with pytest.raises(B.SemError):
         cases.make_solver(wl, smoother="asm")
+
+
+@pytest.mark.parametrize("name", ["tank8", "c2", "ragged"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+def test_vcycle_one_kernel_levels(name, prec, monkeypatch):
+    """The one-kernel coarse-level smoothing and the three-launch coarse solve against the
+    per-step kernels and the per-level reduction (switched off by environment variables read at
+    set-up): the same V-cycle, so the results agree to the rounding of the inner precision."""
+    print(f"[gpu] one-kernel coarse levels {name} {prec}", flush=True)
+    wl = CASES[name]
+    L0N = oracle_h(name).levels[0].N
+    r = W.random_vector(L0N, 901)
+    r[oracle_h(name).levels[0].dn] = 0.0
+    lams = [L.lam for L in oracle_h(name).levels[:-1]]
+
+    def run():
+        s = cases.make_solver(wl, prec=prec)
+        for l, lam in enumerate(lams):
+            s.set_lambda(l, lam)
+        z = H(s.vcycle(T(r)))
+        s.close()
+        return z
+
+    fused = run()
+    monkeypatch.setenv("SEM_NO_COARSE_FUSED", "1")
+    monkeypatch.setenv("SEM_NO_BCR_FUSED", "1")
+    plain = run()
+    tol = 1e-12 if prec == "f64" else 2e-5
+    assert rel(fused, plain) < tol, (name, prec, rel(fused, plain))
