@@ -901,14 +901,6 @@ __global__ __launch_bounds__(1024) void k_fpcg2d(const double* __restrict__ z,
   const int nzp = (nzn + V - 1) / V * V;
   const int nthr = NP * Nz;
   __shared__ double sh[16];
-  double beta = 0.0;
-  if (!first) {
-    const double rz = sum_partials(prz_old, sh);
-    const double pq = sum_partials(ppq_old, sh);
-    const double zq = sum_partials(pzq, sh);
-    beta = -(rz / pq) * zq / rz;
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = beta;
   int bx = blockIdx.x;
   if (remap) {
     const int per = gridDim.x >> 3;
@@ -922,16 +914,43 @@ __global__ __launch_bounds__(1024) void k_fpcg2d(const double* __restrict__ z,
   extern __shared__ __align__(16) unsigned char smem_raw[];
   double* base = reinterpret_cast<double*>(smem_raw) + (valid ? cs : 0) * slot;
   const size_t cb = (size_t)(valid ? ex : 0) * P * nzn + t;
+  // every global input is requested before beta is formed: the factors, z and p of this
+  // thread's nodes and the three partial-sum sets (each summed in the order sum_partials uses)
+  double g[3][NP], zr[NP], pr[NP];
+  if (valid) load_g2d<P, double, double>(G, valid ? ex : 0, nthr, t, g);
+  if (valid && t < nzn) {
+#pragma unroll
+    for (int l = 0; l < NP; ++l) {
+      zr[l] = z[cb + (size_t)l * nzn];
+      pr[l] = first ? 0.0 : p[cb + (size_t)l * nzn];
+    }
+  }
+  double beta = 0.0;
+  if (!first) {
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0;
+#pragma unroll
+    for (int u = 0; u < NRED / 64; ++u) {
+      const int k = (int)threadIdx.x + u * (int)blockDim.x;
+      if (k < NRED) {
+        a0 += prz_old[k];
+        a1 += ppq_old[k];
+        a2 += pzq[k];
+      }
+    }
+    const double rz = block_sum(a0, sh);
+    const double pq = block_sum(a1, sh);
+    const double zq = block_sum(a2, sh);
+    beta = -(rz / pq) * zq / rz;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *beta_out = beta;
   double xin[NP];
-  column_apply<P, double, double>(
+  column_apply_g<P, double>(
+      g,
       [&](double(&v)[NP]) {
 #pragma unroll
-        for (int l = 0; l < NP; ++l) {
-          const size_t g = cb + (size_t)l * nzn;
-          v[l] = first ? z[g] : fma(beta, p[g], z[g]);
-        }
+        for (int l = 0; l < NP; ++l) v[l] = first ? zr[l] : fma(beta, pr[l], zr[l]);
       },
-      G, valid ? ex : 0, nthr, t, valid, Nz, nzn, nzp, masked, base, xin, [] {});
+      t, valid, Nz, nzn, nzp, masked, base, xin, [] {});
   double part = 0.0;
   if (cs >= 1 && valid && t < nzn) {
     const double* su = base + Nz * NP * NPp;
