@@ -67,7 +67,9 @@ struct Ctx {
   hipStream_t st = nullptr;       // internal stream (default priority)
   hipStream_t ust = nullptr;      // caller's stream
   hipEvent_t ev_in = nullptr, ev_out = nullptr;
-  hipEvent_t ev_it[2] = {nullptr, nullptr};  // per-iteration partial sums copied to the host
+  // per-iteration partial sums copied to the host (two alternating slots; slot 2: the initial
+  // residual's)
+  hipEvent_t ev_it[3] = {nullptr, nullptr, nullptr};
   // fine-level FP64 operator for the outer loop
   double* G64 = nullptr;
   bool G64_owned = false;
@@ -110,7 +112,8 @@ struct Ctx {
   float* geo_d = nullptr;
   double* ainv_d = nullptr;    // [E x n x n] inverses of R_e A R_e^T (training targets)
   // graphs
-  hipGraphExec_t g_first = nullptr, g_iter = nullptr, g_pdc = nullptr;
+  // iteration graphs (each ends with the copy of its partial sums into host slot 0 or 1)
+  hipGraphExec_t g_first = nullptr, g_iter[2] = {nullptr, nullptr}, g_pdc[2] = {nullptr, nullptr};
   bool use_graphs = true;
   std::string err;
   bool sticky = false;
@@ -676,9 +679,12 @@ void read_sums(Ctx* c, double* sums) {
 
 void drop_graphs(Ctx* c) {
   if (c->g_first) (void)hipGraphExecDestroy(c->g_first);
-  if (c->g_iter) (void)hipGraphExecDestroy(c->g_iter);
-  if (c->g_pdc) (void)hipGraphExecDestroy(c->g_pdc);
-  c->g_first = c->g_iter = c->g_pdc = nullptr;
+  c->g_first = nullptr;
+  for (int k = 0; k < 2; ++k) {
+    if (c->g_iter[k]) (void)hipGraphExecDestroy(c->g_iter[k]);
+    if (c->g_pdc[k]) (void)hipGraphExecDestroy(c->g_pdc[k]);
+    c->g_iter[k] = c->g_pdc[k] = nullptr;
+  }
 }
 
 template <typename F>
@@ -1071,7 +1077,7 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
   c->So = nullptr;
   c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
   c->scal = (double*)dalloc(c, 64 * 8);
-  HK(hipHostMalloc((void**)&c->hscal, 2 * 3 * semk::NRED * 8, hipHostMallocDefault));
+  HK(hipHostMalloc((void**)&c->hscal, 3 * 3 * semk::NRED * 8, hipHostMallocDefault));
   {  // lumped mass and Neumann faces of the fine level
     const semh::LevelGeom& G = L0.geo;
     const size_t NL3 = (size_t)G.NP * G.NP * G.NP;
@@ -1169,7 +1175,6 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     HK(hipEventCreateWithFlags(&c->ev_in, hipEventDisableTiming));
     HK(hipEventCreateWithFlags(&c->ev_out, hipEventDisableTiming));
     for (auto& e : c->ev_it) HK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-  for (auto& e : c->ev_it) HK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     const char* ng = std::getenv("SEM_NO_GRAPH");
     c->use_graphs = !(ng && ng[0] == '1');
     setup3d_impl(c, d, orders);
@@ -1280,7 +1285,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   c->So = (double*)dalloc(c, L0.nS * 8);
   c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
   c->scal = (double*)dalloc(c, 64 * 8);
-  HK(hipHostMalloc((void**)&c->hscal, 2 * 3 * semk::NRED * 8, hipHostMallocDefault));
+  HK(hipHostMalloc((void**)&c->hscal, 3 * 3 * semk::NRED * 8, hipHostMallocDefault));
   // lumped mass and Neumann faces of the fine level
   {
     std::vector<double> m(N, 0.0);
@@ -1699,47 +1704,38 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     apply_outer(c, c->xo, c->masked);
     HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn, L0.P,
                      c->st));
-    double sums[3];
-    read_sums(c, sums);
-    const double bb = sums[PS_BB];
-    double rel = bb > 0 ? std::sqrt(sums[PS_RR] / bb) : 0.0;
-    auto push = [&](double v) {
-      if (inf->nhist < 512) inf->hist[inf->nhist++] = v;
-    };
-    push(rel);
-    sem_status st = SEM_OK;
-    if (!std::isfinite(bb) || !std::isfinite(sums[PS_RR])) {
-      st = SEM_ERR_BREAKDOWN;
-      set_err(c, "non-finite right-hand side or initial residual");
-    } else if (bb == 0.0) {
-      // zero right-hand side: the solution is zero
-      HK(semk::fill(true, c->xo, 0.0, N, c->st));
-      rel = 0.0;
-    }
     const bool fpcg = c->desc.outer == SEM_OUTER_FPCG;
+    const size_t nset = 3 * (size_t)semk::NRED;
+    double sums[3];
+    // the initial residual's partial sums go to the host behind an event, and the first two
+    // iterations are enqueued before the host looks at them (no GPU idle time at the start);
+    // when the initial guess turns out to satisfy the tolerance already (or the right-hand side
+    // is zero or not finite), their results are discarded: x keeps the caller's values
+    double* hinit = c->hscal + 2 * nset;
+    HK(hipMemcpyAsync(hinit, c->parts, nset * sizeof(double), hipMemcpyDeviceToHost, c->st));
+    HK(hipEventRecord(c->ev_it[2], c->st));
     // Each iteration's partial sums go to pinned host memory behind an event.  While the
     // residual trend says the iteration in flight cannot reach tol (its predicted residual is
     // above twice tol), the next iteration is enqueued before the host waits, so the GPU does not
     // idle between iterations.  A wrong guess runs one more iteration, which only improves x;
     // the reported count is the number executed and the loop stops only with rel <= tol.
-    const size_t nset = 3 * (size_t)semk::NRED;
     auto enqueue = [&](int k) {
       const bool first = (k == 0);
-      if (c->use_graphs) {
-        hipGraphExec_t* slot = fpcg ? (first ? &c->g_first : &c->g_iter) : &c->g_pdc;
-        if (!*slot)
-          *slot = capture(c, [&]() {
-            if (fpcg) fpcg_iteration(c, first);
-            else pdc_iteration(c);
-          });
-        HK(hipGraphLaunch(*slot, c->st));
-      } else {
+      const int hs = k & 1;  // host slot of this iteration's partial sums
+      auto body = [&]() {
         if (fpcg) fpcg_iteration(c, first);
         else pdc_iteration(c);
+        HK(hipMemcpyAsync(c->hscal + hs * nset, c->parts, nset * sizeof(double),
+                          hipMemcpyDeviceToHost, c->st));
+      };
+      if (c->use_graphs) {
+        hipGraphExec_t* slot = fpcg ? (first ? &c->g_first : &c->g_iter[hs]) : &c->g_pdc[hs];
+        if (!*slot) *slot = capture(c, body);
+        HK(hipGraphLaunch(*slot, c->st));
+      } else {
+        body();
       }
-      HK(hipMemcpyAsync(c->hscal + (k & 1) * nset, c->parts, nset * sizeof(double),
-                        hipMemcpyDeviceToHost, c->st));
-      HK(hipEventRecord(c->ev_it[k & 1], c->st));
+      HK(hipEventRecord(c->ev_it[hs], c->st));
     };
     auto collect = [&](int k) {
       HK(hipEventSynchronize(c->ev_it[k & 1]));
@@ -1751,6 +1747,40 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
       }
     };
     int it = 0, launched = 0;
+    const int spec = std::min(2, std::max(0, c->desc.maxit));
+    while (launched < spec) enqueue(launched++);
+    HK(hipEventSynchronize(c->ev_it[2]));
+    for (int q = 0; q < 3; ++q) {
+      double v = 0.0;
+      for (int j = 0; j < semk::NRED; ++j) v += hinit[q * semk::NRED + j];
+      sums[q] = v;
+    }
+    const double bb = sums[PS_BB];
+    double rel = bb > 0 ? std::sqrt(sums[PS_RR] / bb) : 0.0;
+    auto push = [&](double v) {
+      if (inf->nhist < 512) inf->hist[inf->nhist++] = v;
+    };
+    push(rel);
+    sem_status st = SEM_OK;
+    bool keep_x = false;  // the caller's x is the answer: discard the iterations in flight
+    if (!std::isfinite(bb) || !std::isfinite(sums[PS_RR])) {
+      st = SEM_ERR_BREAKDOWN;
+      set_err(c, "non-finite right-hand side or initial residual");
+      keep_x = true;
+    } else if (bb == 0.0 || rel <= tol) {
+      keep_x = true;  // converged initial guess; zero right-hand side: zero solution below
+    }
+    if (st != SEM_OK || keep_x) {
+      for (int k = 0; k < launched; ++k) HK(hipEventSynchronize(c->ev_it[k & 1]));
+      launched = 0;
+      if (bb == 0.0 && st == SEM_OK) {
+        HK(semk::fill(true, c->xo, 0.0, N, c->st));
+        rel = 0.0;
+        keep_x = false;  // x = 0 is copied out below
+      } else if (c->stage_alloc) {
+        HK(hipMemsetAsync(c->stage.skips, 0, sizeof(int), c->st));
+      }
+    }
     double rel_prev = -1.0;  // residual one iteration back (for the rate), < 0: unknown
     while (st == SEM_OK && (rel > tol || launched > it)) {
       if (rel > tol) {
@@ -1780,7 +1810,7 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
       ++it;
       inf->vcycles++;
     }
-    HK(hipMemcpyAsync(x, c->xo, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
+    if (!keep_x) HK(hipMemcpyAsync(x, c->xo, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
     leave(c);
     HK(hipStreamSynchronize(c->st));
     inf->iters = it;
