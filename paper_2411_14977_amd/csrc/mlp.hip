@@ -999,6 +999,7 @@ hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStre
 // otherwise R stays r and the rejection is counted.  Each thread first loads r, q and c of its
 // first UPD_IT nodes, so that the loads are in flight during the reduction.
 constexpr int UPD_IT = 4;
+constexpr int UPD_THREADS = 256;  // small blocks: the step length's block reduction is short
 
 template <typename T>
 __global__ __launch_bounds__(1024) void k_stage_update(T* __restrict__ x, T* __restrict__ R,
@@ -1061,14 +1062,14 @@ hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* y
                         const double* pcr, int ncr, const double* pcq, int ncq, int* skips,
                         unsigned N, unsigned nzn, unsigned P, const void* dinv, void* d,
                         double sr, int store_d, hipStream_t st) {
-  const unsigned blocks = nblk(N, 1024 * UPD_IT);
+  const unsigned blocks = nblk(N, UPD_THREADS * UPD_IT);
   if (dbl)
-    hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(1024), 0, st, (double*)x,
+    hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(UPD_THREADS), 0, st, (double*)x,
                        (double*)R, (const double*)c, (const double*)yq, (const double*)Sq, pcr,
                        ncr, pcq, ncq, skips, N, nzn, P, (const double*)dinv, (double*)d, sr,
                        store_d);
   else
-    hipLaunchKernelGGL(k_stage_update<float>, dim3(blocks), dim3(1024), 0, st, (float*)x,
+    hipLaunchKernelGGL(k_stage_update<float>, dim3(blocks), dim3(UPD_THREADS), 0, st, (float*)x,
                        (float*)R, (const float*)c, (const float*)yq, (const float*)Sq, pcr, ncr,
                        pcq, ncq, skips, N, nzn, P, (const float*)dinv, (float*)d, (float)sr,
                        store_d);
