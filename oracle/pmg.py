@@ -21,8 +21,12 @@ Sec. 6 of the paper:
   has at most ``coarse_dense_max`` nodes, which is solved exactly.  (The paper is silent on the
   coarse solver; this reading is stated where it is used.)
 * coarse operators re-discretised with the same formula at the coarse order;
-* outer iterations: preconditioned defect correction x += B(b - A x) (Sec. 6.4) and flexible
-  conjugate gradients (one-term Polak-Ribiere beta) with B as preconditioner.
+* outer iterations: preconditioned defect correction x += B(b - A x) (Sec. 6.4), flexible
+  conjugate gradients (one-term Polak-Ribiere beta) with B as preconditioner, and GMRES with B
+  as right preconditioner (Sec. 6.4 names GMRES, Saad and Schultz 1986): restarted every m
+  steps, the k-th iterate of a cycle minimises ||b - A x|| over x0 + span{B v_1 .. B v_k} with
+  v_1 .. v_k the Arnoldi basis (the flexible form, Saad 1993, which equals right-preconditioned
+  GMRES for the fixed linear B of a V-cycle).
 
 Chebyshev smoothing follows the classical three-term recurrence on the interval
 [lo, hi] = [a, b] lambda_hat of D^{-1} A (Saad, "Iterative Methods for Sparse Linear Systems",
@@ -342,3 +346,44 @@ def pdc(A, b, x0, prec, tol, maxit=500):
         if hist[-1] <= tol:
             return x, it, hist
     return x, maxit, hist
+
+
+def gmres(A, b, x0, prec, tol, restart=30, maxit=500):
+    """Right-preconditioned (flexible) GMRES(m): every step z_j = B v_j, w = A z_j orthogonalised
+    against v_1 .. v_j (modified Gram-Schmidt) gives column j of the Hessenberg matrix H; the
+    iterate x0 + Z y minimises ||beta e_1 - H y|| (least squares solved directly, no rotations).
+    hist: relative residual norms ||b - A x|| / ||b|| of every iterate, computed from x."""
+    x = x0.copy()
+    nb = np.linalg.norm(b)
+    r = b - A @ x
+    hist = [np.linalg.norm(r) / nb]
+    if hist[-1] <= tol:
+        return x, 0, hist
+    it = 0
+    while it < maxit:
+        beta = np.linalg.norm(r)
+        V = [r / beta]
+        Z = []
+        H = np.zeros((restart + 1, restart))
+        x_start = x.copy()
+        for j in range(restart):
+            z = prec(V[j])
+            Z.append(z)
+            w = A @ z
+            for i in range(j + 1):
+                H[i, j] = w @ V[i]
+                w = w - H[i, j] * V[i]
+            H[j + 1, j] = np.linalg.norm(w)
+            V.append(w / H[j + 1, j] if H[j + 1, j] > 0 else w)
+            g = np.zeros(j + 2)
+            g[0] = beta
+            y = np.linalg.lstsq(H[:j + 2, :j + 1], g, rcond=None)[0]
+            x = x_start + np.column_stack(Z) @ y
+            r = b - A @ x
+            it += 1
+            hist.append(np.linalg.norm(r) / nb)
+            if hist[-1] <= tol or it >= maxit or H[j + 1, j] == 0:
+                break
+        if hist[-1] <= tol:
+            return x, it, hist
+    return x, it, hist

@@ -2,6 +2,7 @@
 import numpy as np
 import numpy.polynomial.chebyshev as npcheb
 import pytest
+import scipy.sparse.linalg as spla
 
 import workloads as W
 from oracle import assemble, pmg
@@ -299,3 +300,65 @@ def test_schwarz_preconditioned_solve_matches_direct():
     xd = assemble.solve_direct(L.A, b)
     assert np.linalg.norm(x - xd) <= 1e-8 * np.linalg.norm(xd)
     assert it <= 30
+
+
+def _small_system(n=40, seed=3):
+    rng = np.random.default_rng(seed)
+    Q = rng.standard_normal((n, n))
+    A = Q @ Q.T + n * np.eye(n)          # SPD
+    N = rng.standard_normal((n, n))
+    Bm = np.diag(1.0 / np.diag(A)) + 0.01 * (N + N.T) / n   # a fixed linear preconditioner
+    b = rng.standard_normal(n)
+    return A, Bm, b
+
+
+def test_gmres_minimises_residual_over_krylov_space():
+    """Pin (definition): the k-th GMRES iterate is the minimum-residual point of
+    x0 + span{B r0, (B A) B r0, ..} = x0 + B K_k(A B, r0), here built explicitly and solved by
+    least squares."""
+    A, Bm, b = _small_system()
+    x0 = np.zeros_like(b)
+    r0 = b - A @ x0
+    for k in range(1, 7):
+        xg, it, _ = pmg.gmres(A, b, x0, lambda v: Bm @ v, 1e-30, restart=30, maxit=k)
+        assert it == k
+        K = [r0]
+        for _ in range(k - 1):
+            K.append(A @ (Bm @ K[-1]))
+        Zk = Bm @ np.column_stack(K)
+        y = np.linalg.lstsq(A @ Zk, r0, rcond=None)[0]
+        xb = x0 + Zk @ y
+        assert np.linalg.norm(xg - xb) <= 1e-9 * np.linalg.norm(xb)
+
+
+def test_gmres_exact_preconditioner_and_restart():
+    """With B = A^-1 one step is exact; restarted GMRES(2) never increases the residual and
+    converges; zero initial residual returns at once."""
+    A, Bm, b = _small_system()
+    Ainv = np.linalg.inv(A)
+    x, it, hist = pmg.gmres(A, b, np.zeros_like(b), lambda v: Ainv @ v, 1e-12)
+    assert it == 1 and hist[-1] <= 1e-12
+    x, it, hist = pmg.gmres(A, b, np.zeros_like(b), lambda v: Bm @ v, 1e-10, restart=2, maxit=400)
+    assert hist[-1] <= 1e-10
+    assert all(h2 <= h1 * (1 + 1e-12) for h1, h2 in zip(hist, hist[1:]))
+    xs = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xs) <= 1e-8 * np.linalg.norm(xs)
+    x, it, hist = pmg.gmres(A, b, xs, lambda v: Bm @ v, 1e-8)
+    assert it == 0
+
+
+def test_gmres_with_vcycle_on_tank():
+    """GMRES-MG on a small sigma-mapped tank reaches the direct solution; with the same V-cycle
+    it needs no more iterations than flexible CG (GMRES minimises the residual norm)."""
+    wl = W.tank(16, 4, 4, Lx=1.6, name="gm")
+    H_ = oc.hierarchy(wl)
+    pmg.estimate_lambdas(H_)
+    L0 = H_.levels[0]
+    b = W.random_vector(L0.N, 77)
+    b[L0.dn] = 0.0
+    xs = spla.spsolve(L0.A.tocsc(), b)
+    xg, itg, hg = pmg.gmres(L0.A, b, np.zeros(L0.N), H_.vcycle, 1e-10)
+    xc, itc, hc = pmg.fpcg(L0.A, b, np.zeros(L0.N), H_.vcycle, 1e-10)
+    assert hg[-1] <= 1e-10
+    assert np.linalg.norm(xg - xs) <= 1e-8 * np.linalg.norm(xs)
+    assert itg <= itc
