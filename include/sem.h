@@ -54,7 +54,7 @@ enum { SEM_F64 = 0, SEM_F32 = 1, SEM_F32_GBF16 = 2 };
  * and stored per level in the inner precision (E (P_l+1)^4 values). */
 enum { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_CHEBYSHEV = 1, SEM_SMOOTH_SCHWARZ = 2 };
 /* outer iteration */
-enum { SEM_OUTER_FPCG = 0, SEM_OUTER_PDC = 1 };
+enum { SEM_OUTER_FPCG = 0, SEM_OUTER_PDC = 1, SEM_OUTER_GMRES = 2 };
 /* Dirichlet faces bitmask */
 enum { SEM_FACE_TOP = 1 };
 
@@ -78,7 +78,7 @@ typedef struct {
   int cheb_degree;             /* Chebyshev degree (pre and post)                           */
   double jacobi_omega;         /* damping, default 2/3                                      */
   double cheb_lo, cheb_hi;     /* Chebyshev interval as fractions of lambda_hat (0.1, 1.1)  */
-  int outer;                   /* SEM_OUTER_FPCG | SEM_OUTER_PDC                            */
+  int outer;                   /* SEM_OUTER_FPCG | SEM_OUTER_PDC | SEM_OUTER_GMRES          */
   int maxit;                   /* outer iteration cap                                       */
   int lanczos_steps;           /* steps of the lambda_hat estimate (default 20)             */
   unsigned long long lanczos_seed; /* SplitMix64 seed of the Lanczos start vector           */
@@ -88,6 +88,13 @@ typedef struct {
                                   nodes, which is solved exactly with its dense FP64 inverse
                                   (default 1200).  2D solves P = 1 exactly by block cyclic
                                   reduction and ignores it.                                   */
+  int gmres_restart;           /* SEM_OUTER_GMRES (2D): Arnoldi steps per cycle, 1..64
+                                  (default 30).  Right-preconditioned GMRES (Sec. 6.4 of the
+                                  paper names GMRES beside defect correction): per step one
+                                  V-cycle z = B v, one FP64 operator apply and classical
+                                  Gram-Schmidt applied twice; x += Z y at the end of a cycle;
+                                  sem_solve_info.hist holds the Givens residual estimates of the
+                                  steps and, at the end of each cycle, the true residual.      */
 } sem_mesh_desc;
 
 typedef struct {

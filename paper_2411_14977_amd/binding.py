@@ -9,7 +9,7 @@ _LIB_PATH = os.path.join(HERE, "libsem.so")
 
 SEM_F64, SEM_F32, SEM_F32_GBF16 = 0, 1, 2
 SEM_SMOOTH_JACOBI, SEM_SMOOTH_CHEBYSHEV, SEM_SMOOTH_SCHWARZ = 0, 1, 2
-SEM_OUTER_FPCG, SEM_OUTER_PDC = 0, 1
+SEM_OUTER_FPCG, SEM_OUTER_PDC, SEM_OUTER_GMRES = 0, 1, 2
 SEM_FACE_TOP = 1
 SEM_MAX_LEVELS = 8
 
@@ -35,6 +35,7 @@ class MeshDesc(ctypes.Structure):
         ("cheb_hi", ctypes.c_double), ("outer", ctypes.c_int), ("maxit", ctypes.c_int),
         ("lanczos_steps", ctypes.c_int), ("lanczos_seed", ctypes.c_ulonglong),
         ("stream", ctypes.c_void_p), ("coarse_dense_max", ctypes.c_int),
+        ("gmres_restart", ctypes.c_int),
     ]
 
 
@@ -346,7 +347,8 @@ class Solver:
     def __init__(self, dim, ne, order, length, h, eta, levels=None, prec="f64",
                  smoother="chebyshev", nu_pre=2, nu_post=2, cheb_degree=3, jacobi_omega=2.0 / 3.0,
                  cheb_lo=0.1, cheb_hi=1.1, outer="fpcg", maxit=500, dirichlet=True,
-                 lanczos_steps=20, lanczos_seed=12345, coarse_dense_max=1200, stream=None):
+                 lanczos_steps=20, lanczos_seed=12345, coarse_dense_max=1200, stream=None,
+                 gmres_restart=30):
         import torch
         d = sem_mesh_desc_default()
         d.dim = dim
@@ -370,7 +372,8 @@ class Solver:
                       "asm": SEM_SMOOTH_SCHWARZ}[smoother]
         d.nu_pre, d.nu_post, d.cheb_degree = nu_pre, nu_post, cheb_degree
         d.jacobi_omega, d.cheb_lo, d.cheb_hi = jacobi_omega, cheb_lo, cheb_hi
-        d.outer = SEM_OUTER_PDC if outer == "pdc" else SEM_OUTER_FPCG
+        d.outer = {"fpcg": SEM_OUTER_FPCG, "pdc": SEM_OUTER_PDC, "gmres": SEM_OUTER_GMRES}[outer]
+        d.gmres_restart = int(gmres_restart)
         d.maxit = maxit
         d.lanczos_steps = lanczos_steps
         d.lanczos_seed = lanczos_seed

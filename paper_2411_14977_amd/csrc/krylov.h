@@ -1,0 +1,30 @@
+// Vector kernels of the GMRES outer iteration (FP64, deterministic two-stage reductions over
+// semk::NRED workgroups): the Arnoldi step's operator result, classical Gram-Schmidt against
+// the basis (applied twice) and the solution update.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstddef>
+
+namespace semk {
+
+constexpr int KRY_MAX = 64;  // longest restart cycle
+struct KryCoef {
+  double h[KRY_MAX];
+};
+
+// w = (A z) from the column output y and side buffer S (S null: y complete; nzn nodes per
+// vertical line, order P), then part[i NRED + block] = block partial of w . V_i, i < nv, with
+// V_i = V + i ldv.  N nodes.
+hipError_t kry_first(const double* y, const double* S, double* w, const double* V, size_t ldv,
+                     int nv, double* part, unsigned N, unsigned nzn, unsigned P, hipStream_t st);
+// w -= sum_{i < nv} h_i V_i; then (dots) partials of w . V_i (i < nv) into part[i NRED + .],
+// and always of w . w into part[nv NRED + .]
+hipError_t kry_sub(double* w, const double* V, size_t ldv, int nv, const KryCoef& h, int dots,
+                   double* part, unsigned N, hipStream_t st);
+// w *= s
+hipError_t kry_scale(double* w, double s, unsigned N, hipStream_t st);
+// x += sum_{i < k} y_i Z_i
+hipError_t kry_update(double* x, const double* Z, size_t ldz, int k, const KryCoef& y,
+                      unsigned N, hipStream_t st);
+
+}  // namespace semk

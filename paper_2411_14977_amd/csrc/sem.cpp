@@ -24,6 +24,7 @@
 #include "../../include/sem.h"
 #include "host_math.h"
 #include "kernels.h"
+#include "krylov.h"
 #include "mlp.h"
 
 namespace {
@@ -97,6 +98,8 @@ struct Ctx {
   semh::BcrPlan plan;
   double *bcrF = nullptr, *bcrB = nullptr, *bcrLast = nullptr, *bcrDense = nullptr;
   double* bcrRed = nullptr;  // reduced right-hand side of the one-launch reduction
+  // GMRES: Arnoldi basis V (m + 1 vectors), preconditioned basis Z (m), reduction partials
+  double *kV = nullptr, *kZ = nullptr, *kpart = nullptr, *hkpart = nullptr;
   semk::BcrLevels bcrLv;     // its level table (nl = -1: per-level kernels)
   int* rowmap = nullptr;
   // FP64 right-hand side of the next V-cycle, read by the first smoothing step of level 0
@@ -1142,7 +1145,11 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     throw ArgFail{"bad smoother"};
   if (d->smoother == SEM_SMOOTH_SCHWARZ && (d->dim != 2 || d->order > 8))
     throw ArgFail{"the Schwarz smoother is built for 2D meshes with order <= 8"};
-  if (d->outer != SEM_OUTER_FPCG && d->outer != SEM_OUTER_PDC) throw ArgFail{"bad outer"};
+  if (d->outer != SEM_OUTER_FPCG && d->outer != SEM_OUTER_PDC && d->outer != SEM_OUTER_GMRES)
+    throw ArgFail{"bad outer"};
+  if (d->outer == SEM_OUTER_GMRES &&
+      (d->dim != 2 || d->gmres_restart < 1 || d->gmres_restart > semk::KRY_MAX))
+    throw ArgFail{"GMRES: 2D meshes, restart 1..64"};
   if (d->smoother == SEM_SMOOTH_CHEBYSHEV &&
       (d->cheb_degree < 1 || !(d->cheb_hi > d->cheb_lo) || d->cheb_lo <= 0))
     throw ArgFail{"bad Chebyshev parameters"};
@@ -1383,6 +1390,8 @@ void release(Ctx* c) {
   c->allocs.clear();
   if (c->hscal) (void)hipHostFree(c->hscal);
   c->hscal = nullptr;
+  if (c->hkpart) (void)hipHostFree(c->hkpart);
+  c->hkpart = nullptr;
   if (c->ev_in) (void)hipEventDestroy(c->ev_in);
   if (c->ev_out) (void)hipEventDestroy(c->ev_out);
   c->ev_in = c->ev_out = nullptr;
@@ -1430,6 +1439,7 @@ void sem_mesh_desc_default(sem_mesh_desc* d) {
   d->lanczos_seed = 12345ull;
   d->stream = nullptr;
   d->coarse_dense_max = 1200;
+  d->gmres_restart = 30;
 }
 
 sem_status sem_mesh_setup(const sem_mesh_desc* desc, sem_ctx** out) {
@@ -1747,7 +1757,8 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
       }
     };
     int it = 0, launched = 0;
-    const int spec = std::min(2, std::max(0, c->desc.maxit));
+    const bool gmres = c->desc.outer == SEM_OUTER_GMRES;
+    const int spec = gmres ? 0 : std::min(2, std::max(0, c->desc.maxit));
     while (launched < spec) enqueue(launched++);
     HK(hipEventSynchronize(c->ev_it[2]));
     for (int q = 0; q < 3; ++q) {
@@ -1781,8 +1792,113 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
         HK(hipMemsetAsync(c->stage.skips, 0, sizeof(int), c->st));
       }
     }
+    // restarted right-preconditioned GMRES: Arnoldi steps z_j = B v_j, w = A z_j, classical
+    // Gram-Schmidt against V twice, Givens rotations on the host; x += Z y closes a cycle, and
+    // the cycle's true residual decides whether another one follows
+    auto gmres_run = [&]() {
+      const int m = c->desc.gmres_restart;
+      const size_t Nn = N;
+      constexpr int NR = semk::NRED;
+      if (!c->kV) {
+        c->kV = (double*)dalloc(c, (size_t)(m + 1) * Nn * 8);
+        c->kZ = (double*)dalloc(c, (size_t)m * Nn * 8);
+        c->kpart = (double*)dalloc(c, (size_t)(m + 2) * NR * 8);
+        HK(hipHostMalloc((void**)&c->hkpart, (size_t)(m + 2) * NR * 8, hipHostMallocDefault));
+      }
+      // sums of the partial sets s0 .. s0 + n - 1 (each NR partials, fixed order)
+      auto read_parts = [&](int s0, int n, double* out) {
+        HK(hipMemcpyAsync(c->hkpart, c->kpart + (size_t)s0 * NR, (size_t)n * NR * 8,
+                          hipMemcpyDeviceToHost, c->st));
+        HK(hipStreamSynchronize(c->st));
+        for (int i = 0; i < n; ++i) {
+          double v = 0.0;
+          for (int q = 0; q < NR; ++q) v += c->hkpart[(size_t)i * NR + q];
+          out[i] = v;
+        }
+      };
+      const double nb = std::sqrt(bb);
+      double beta = rel * nb;
+      std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
+      auto H = [&](int i, int j) -> double& { return Hm[(size_t)i * m + j]; };
+      while (st == SEM_OK && rel > tol && it < c->desc.maxit) {
+        HK(hipMemcpyAsync(c->kV, c->ro, Nn * 8, hipMemcpyDeviceToDevice, c->st));
+        HK(semk::kry_scale(c->kV, 1.0 / beta, N, c->st));
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        for (int j = 0; j < m && it < c->desc.maxit; ++j) {
+          double* vj = c->kV + (size_t)j * Nn;
+          double* zj = c->kZ + (size_t)j * Nn;
+          double* w = c->kV + (size_t)(j + 1) * Nn;
+          vcycle(c, vj);
+          HK(semk::castdot(L0.dbl, L0.x, zj, nullptr, vj, pset(c, PS_ZQ), pset(c, PS_RZB), N,
+                           c->st));
+          apply_outer(c, zj, c->masked);
+          HK(semk::kry_first(c->yo, c->So, w, c->kV, Nn, j + 1, c->kpart, N, L0.nzn, L0.P,
+                             c->st));
+          double h1[semk::KRY_MAX + 1], h2[semk::KRY_MAX + 1], ww = 0.0;
+          read_parts(0, j + 1, h1);
+          semk::KryCoef co;
+          for (int i = 0; i <= j; ++i) co.h[i] = h1[i];
+          HK(semk::kry_sub(w, c->kV, Nn, j + 1, co, 1, c->kpart, N, c->st));
+          read_parts(0, j + 1, h2);
+          for (int i = 0; i <= j; ++i) co.h[i] = h2[i];
+          HK(semk::kry_sub(w, c->kV, Nn, j + 1, co, 0, c->kpart, N, c->st));
+          read_parts(j + 1, 1, &ww);
+          const double hn = std::sqrt(ww);
+          for (int i = 0; i <= j; ++i) H(i, j) = h1[i] + h2[i];
+          H(j + 1, j) = hn;
+          if (!std::isfinite(hn)) {
+            st = SEM_ERR_BREAKDOWN;
+            set_err(c, "breakdown in GMRES (non-finite Arnoldi vector)");
+            return;
+          }
+          if (hn > 0.0) HK(semk::kry_scale(w, 1.0 / hn, N, c->st));
+          for (int i = 0; i < j; ++i) {  // earlier rotations on the new column
+            const double t = cs[i] * H(i, j) + sn[i] * H(i + 1, j);
+            H(i + 1, j) = -sn[i] * H(i, j) + cs[i] * H(i + 1, j);
+            H(i, j) = t;
+          }
+          const double den = std::hypot(H(j, j), H(j + 1, j));
+          cs[j] = den > 0.0 ? H(j, j) / den : 1.0;
+          sn[j] = den > 0.0 ? H(j + 1, j) / den : 0.0;
+          H(j, j) = den;
+          H(j + 1, j) = 0.0;
+          g[j + 1] = -sn[j] * g[j];
+          g[j] = cs[j] * g[j];
+          ++it;
+          ++k;
+          inf->vcycles++;
+          push(std::fabs(g[j + 1]) / nb);
+          if (std::fabs(g[j + 1]) / nb <= tol || hn == 0.0) break;
+        }
+        semk::KryCoef yc;
+        for (int i = k - 1; i >= 0; --i) {  // y = R^-1 g
+          double v = g[i];
+          for (int q = i + 1; q < k; ++q) v -= H(i, q) * yc.h[q];
+          yc.h[i] = H(i, i) != 0.0 ? v / H(i, i) : 0.0;
+        }
+        HK(semk::kry_update(c->xo, c->kZ, Nn, k, yc, N, c->st));
+        apply_outer(c, c->xo, c->masked);
+        HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn,
+                         L0.P, c->st));
+        read_sums(c, sums);
+        rel = std::sqrt(sums[PS_RR] / bb);
+        beta = std::sqrt(sums[PS_RR]);
+        if (inf->nhist > 0) inf->hist[inf->nhist - 1] = rel;  // the cycle's true residual
+        if (!std::isfinite(rel)) {
+          st = SEM_ERR_BREAKDOWN;
+          set_err(c, "breakdown in GMRES (non-finite residual)");
+        }
+      }
+      if (st == SEM_OK && rel > tol) {
+        st = SEM_ERR_NOT_CONVERGED;
+        set_err(c, "maximum number of outer iterations reached");
+      }
+    };
+    if (gmres && st == SEM_OK && !keep_x && rel > tol) gmres_run();
     double rel_prev = -1.0;  // residual one iteration back (for the rate), < 0: unknown
-    while (st == SEM_OK && (rel > tol || launched > it)) {
+    while (!gmres && st == SEM_OK && (rel > tol || launched > it)) {
       if (rel > tol) {
         if (it >= c->desc.maxit) {
           st = SEM_ERR_NOT_CONVERGED;
