@@ -265,8 +265,9 @@ def schwarz_rows(wl, rhs, prec, steps):
 def paper_context(prec):
     """The paper's multigrid-efficiency experiments (Sec. 7, table of iterations per tolerance
     and the scaling figure) rerun with this solver on the synthetic tank: N_z = 2, P = 8,
-    N_x = 102 at tolerances 1e-4, 1e-6, 1e-8 (PDC and FPCG), then at 1e-6 the iterations and
-    time against N_x (P = 8, element width fixed at 0.25 m) and against P (N_x = 200).  Inner
+    N_x = 102 at tolerances 1e-4, 1e-6, 1e-8 (PDC, FPCG and GMRES, the paper's two outer
+    methods and this solver's default), then at 1e-6 the iterations and time against N_x
+    (P = 8, element width fixed at 0.25 m) and against P (N_x = 200) for FPCG and GMRES.  Inner
     precision as the timed path, Chebyshev(3) smoothing; context, not the headline."""
     import torch
 
@@ -285,15 +286,18 @@ def paper_context(prec):
         return wl.n_global, rows
 
     out = {"table": {}, "scaling_nx": [], "scaling_p": []}
-    for outer in ("pdc", "fpcg"):
+    for outer in ("pdc", "fpcg", "gmres"):
         n, rows = run(102, 8, outer, (1e-4, 1e-6, 1e-8))
         out["table"][outer] = {"n_global": n, **rows}
-    for Nx in (25, 50, 100, 200, 400, 800):
-        n, rows = run(Nx, 8, "fpcg", (1e-6,))
-        out["scaling_nx"].append({"Nx": Nx, "P": 8, "n_global": n, **rows["1e-06"]})
-    for P in (2, 3, 4, 5, 6, 7, 8):
-        n, rows = run(200, P, "fpcg", (1e-6,))
-        out["scaling_p"].append({"Nx": 200, "P": P, "n_global": n, **rows["1e-06"]})
+    for outer in ("fpcg", "gmres"):
+        for Nx in (25, 50, 100, 200, 400, 800):
+            n, rows = run(Nx, 8, outer, (1e-6,))
+            out["scaling_nx"].append({"outer": outer, "Nx": Nx, "P": 8, "n_global": n,
+                                      **rows["1e-06"]})
+        for P in (2, 3, 4, 5, 6, 7, 8):
+            n, rows = run(200, P, outer, (1e-6,))
+            out["scaling_p"].append({"outer": outer, "Nx": 200, "P": P, "n_global": n,
+                                     **rows["1e-06"]})
     torch.cuda.synchronize()
     return out
 
