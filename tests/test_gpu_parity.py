@@ -48,6 +48,9 @@ CASES = {
     # tall columns: at P = 8 a workgroup holds only one column (no fused smoother step, LDS
     # above 64 KB); the coarser levels use the fused step with two owned columns
     "tall": W.tank(3, 60, 8, Lx=0.3, name="tall"),
+    # 101 coarse x-lines of 3 free nodes: one block-reduction level before the dense step, with
+    # the block size not among the compiled ones (the generic reduction kernels)
+    "wide3": W.tank(100, 3, 4, Lx=10.0, name="wide3"),
 }
 
 _oracle = {}
@@ -171,7 +174,7 @@ def test_lanczos_estimate(name):
     s.close()
 
 
-@pytest.mark.parametrize("name", ["c1", "ragged", "tank8", "c2", "tall"])
+@pytest.mark.parametrize("name", ["c1", "ragged", "tank8", "c2", "tall", "wide3"])
 def test_vcycle(name):
     print(f"[gpu] vcycle parity {name}", flush=True)
     H_ = oracle_h(name)
@@ -374,7 +377,7 @@ def test_schwarz_rejects_3d():
         cases.make_solver(wl, smoother="asm")
 
 
-@pytest.mark.parametrize("name", ["tank8", "c2", "ragged"])
+@pytest.mark.parametrize("name", ["tank8", "c2", "ragged", "wide3"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
 def test_vcycle_one_kernel_levels(name, prec, monkeypatch):
     """The one-kernel coarse-level smoothing and the three-launch coarse solve against the
