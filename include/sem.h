@@ -88,7 +88,7 @@ typedef struct {
                                   nodes, which is solved exactly with its dense FP64 inverse
                                   (default 1200).  2D solves P = 1 exactly by block cyclic
                                   reduction and ignores it.                                   */
-  int gmres_restart;           /* SEM_OUTER_GMRES (2D): Arnoldi steps per cycle, 1..64
+  int gmres_restart;           /* SEM_OUTER_GMRES: Arnoldi steps per cycle, 1..64
                                   (default 30).  Right-preconditioned GMRES (Sec. 6.4 of the
                                   paper names GMRES beside defect correction): per step one
                                   V-cycle z = B v, one FP64 operator apply and classical

@@ -1147,9 +1147,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     throw ArgFail{"the Schwarz smoother is built for 2D meshes with order <= 8"};
   if (d->outer != SEM_OUTER_FPCG && d->outer != SEM_OUTER_PDC && d->outer != SEM_OUTER_GMRES)
     throw ArgFail{"bad outer"};
-  if (d->outer == SEM_OUTER_GMRES &&
-      (d->dim != 2 || d->gmres_restart < 1 || d->gmres_restart > semk::KRY_MAX))
-    throw ArgFail{"GMRES: 2D meshes, restart 1..64"};
+  if (d->outer == SEM_OUTER_GMRES && (d->gmres_restart < 1 || d->gmres_restart > semk::KRY_MAX))
+    throw ArgFail{"GMRES restart must be 1..64"};
   if (d->smoother == SEM_SMOOTH_CHEBYSHEV &&
       (d->cheb_degree < 1 || !(d->cheb_hi > d->cheb_lo) || d->cheb_lo <= 0))
     throw ArgFail{"bad Chebyshev parameters"};

@@ -75,3 +75,29 @@ def test_gmres_mixed_precision_and_edge_cases():
     s2.close()
     with pytest.raises(Exception):
         cases.make_solver(wl, outer="gmres", gmres_restart=65)
+
+
+@pytest.mark.parametrize("name,cdm", [("t3a", 1200), ("t3h", 40)])
+def test_gmres_3d_matches_oracle(name, cdm):
+    """3D (p-levels, and an h-level below P = 1): the same parity as in 2D."""
+    print(f"[gpu] GMRES 3D {name}", flush=True)
+    wl = {"t3a": W.tank3d(4, 3, 2, 4, L=0.8, name="t3a"),
+          "t3h": W.tank3d(4, 4, 2, 2, L=0.8, name="t3h")}[name]
+    Hh = oc.hierarchy(wl, coarse_dense_max=cdm)
+    pmg.estimate_lambdas(Hh)
+    L0 = Hh.levels[0]
+    s = cases.make_solver(wl, coarse_dense_max=cdm, outer="gmres", gmres_restart=30)
+    for l, L in enumerate(Hh.levels[:-1]):
+        s.set_lambda(l, L.lam)
+    b = cases.make_rhs(wl, s)
+    bh = H(b)
+    x, info, st = s.solve(b, tol=1e-10)
+    assert st == 0 and info.rel_res <= 1e-10
+    xo, it_o, hist_o = pmg.gmres(L0.A, bh, np.zeros(L0.N), Hh.vcycle, 1e-10, restart=30)
+    assert info.iters == it_o, (info.iters, it_o)
+    hist = np.array(info.hist[:info.nhist])
+    ho = np.array(hist_o)
+    assert np.all(np.abs(hist - ho) <= 1e-6 * ho + 1e-13), (hist, ho)
+    xd = assemble.solve_direct(L0.A, bh)
+    assert np.linalg.norm(H(x) - xd) <= 1e-8 * np.linalg.norm(xd)
+    s.close()
