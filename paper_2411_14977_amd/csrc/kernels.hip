@@ -1626,12 +1626,159 @@ __global__ void k_axis(const TI* __restrict__ in, const TI* __restrict__ in2,
   }
 }
 
+// Stride-1 axis (n_inner == 1): B whole lines per block are staged in LDS (as FP64, with in2
+// already subtracted) together with the 1D operator, then every output of those lines is a dot
+// product out of LDS.  Reads and writes are contiguous spans of B*nin and B*nout values; the
+// per-thread gathers with their dependent index loads stay on chip.  Same sums, same order, as
+// k_axis.
+template <typename TI, typename TO, bool SUB>
+__global__ __launch_bounds__(256) void k_axis_lines(const TI* __restrict__ in,
+                                                    const TI* __restrict__ in2,
+                                                    TO* __restrict__ out, int accumulate,
+                                                    unsigned n_outer, unsigned nin, unsigned nout,
+                                                    const int* __restrict__ rowptr,
+                                                    const int* __restrict__ cols,
+                                                    const double* __restrict__ w, unsigned nnz,
+                                                    unsigned B, unsigned mask_nzn) {
+  extern __shared__ double lds_axis[];
+  double* xs = lds_axis;              // B * nin line values
+  double* ws = xs + (size_t)B * nin;  // nnz weights
+  int* cs = (int*)(ws + nnz);         // nnz columns
+  int* rs = cs + nnz;                 // nout + 1 row offsets
+  const unsigned o0 = blockIdx.x * B;
+  const unsigned nb = min(B, n_outer - o0);
+  const unsigned nvin = nb * nin, g0 = o0 * nin;
+  for (unsigned i = threadIdx.x; i < nvin; i += 1024u) {
+    TI a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned q = i + 256u * u;
+      a[u] = (TI)0;
+      b[u] = (TI)0;
+      if (q < nvin) {
+        a[u] = in[g0 + q];
+        if (SUB) b[u] = in2[g0 + q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const unsigned q = i + 256u * u;
+      if (q < nvin) xs[q] = SUB ? (double)a[u] - (double)b[u] : (double)a[u];
+    }
+  }
+  for (unsigned i = threadIdx.x; i < nnz; i += 256u) {
+    ws[i] = w[i];
+    cs[i] = cols[i];
+  }
+  for (unsigned i = threadIdx.x; i <= nout; i += 256u) rs[i] = rowptr[i];
+  __syncthreads();
+  const unsigned nvout = nb * nout, h0 = o0 * nout;
+  for (unsigned i = threadIdx.x; i < nvout; i += 256u) {
+    const unsigned oo = i / nout, ko = i - oo * nout;
+    const double* xl = xs + oo * nin;
+    double s = 0.0;
+    for (int e = rs[ko]; e < rs[ko + 1]; ++e) s += ws[e] * xl[cs[e]];
+    const unsigned k = h0 + i;
+    if (mask_nzn && (k % mask_nzn) == mask_nzn - 1) s = 0.0;
+    out[k] = accumulate ? (TO)((double)out[k] + s) : (TO)s;
+  }
+}
+
+// Strided axes: one output per thread as in k_axis, with 32-bit indices and the row's entries
+// unrolled to a bound R >= the longest row, so that every gather of the row is issued before
+// the (unchanged, in-order) sum.
+template <typename TI, typename TO, int R, bool SUB>
+__global__ __launch_bounds__(256) void k_axis_rows(const TI* __restrict__ in,
+                                                   const TI* __restrict__ in2,
+                                                   TO* __restrict__ out, int accumulate,
+                                                   unsigned total, unsigned nin, unsigned nout,
+                                                   unsigned n_inner,
+                                                   const int* __restrict__ rowptr,
+                                                   const int* __restrict__ cols,
+                                                   const double* __restrict__ w,
+                                                   unsigned mask_nzn) {
+  const unsigned k = blockIdx.x * 256u + threadIdx.x;
+  if (k >= total) return;
+  const unsigned ii = k % n_inner, rest = k / n_inner;
+  const unsigned ko = rest % nout, o = rest / nout;
+  const unsigned base = o * nin * n_inner + ii;
+  const int e0 = rowptr[ko], n = rowptr[ko + 1] - e0;
+  double v[R], ww[R];
+#pragma unroll
+  for (int j = 0; j < R; ++j) {
+    v[j] = 0.0;
+    ww[j] = 0.0;
+    if (j < n) {
+      const unsigned src = base + (unsigned)cols[e0 + j] * n_inner;
+      ww[j] = w[e0 + j];
+      v[j] = (double)in[src];
+      if (SUB) v[j] -= (double)in2[src];
+    }
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int j = 0; j < R; ++j)
+    if (j < n) s += ww[j] * v[j];
+  if (mask_nzn && (k % mask_nzn) == mask_nzn - 1) s = 0.0;
+  out[k] = accumulate ? (TO)((double)out[k] + s) : (TO)s;
+}
+
+template <typename TI, typename TO, int R>
+static void axis_rows_launch(const void* in, const void* in2, void* out, int accumulate,
+                             unsigned total, unsigned nin, unsigned nout, unsigned n_inner,
+                             const int* rowptr, const int* cols, const double* w,
+                             unsigned mask_nzn, hipStream_t st) {
+  const unsigned blocks = (total + 255u) / 256u;
+  if (in2)
+    hipLaunchKernelGGL((k_axis_rows<TI, TO, R, true>), dim3(blocks), dim3(256), 0, st,
+                       (const TI*)in, (const TI*)in2, (TO*)out, accumulate, total, nin, nout,
+                       n_inner, rowptr, cols, w, mask_nzn);
+  else
+    hipLaunchKernelGGL((k_axis_rows<TI, TO, R, false>), dim3(blocks), dim3(256), 0, st,
+                       (const TI*)in, (const TI*)in2, (TO*)out, accumulate, total, nin, nout,
+                       n_inner, rowptr, cols, w, mask_nzn);
+}
+
+constexpr unsigned AXIS_LINES = 32;           // lines per block of k_axis_lines
+constexpr size_t AXIS_LINES_SMEM = 64 * 1024;  // its LDS limit
+
 template <typename TI, typename TO>
 static hipError_t axis_t(const void* in, const void* in2, void* out, int accumulate,
                          unsigned n_outer, unsigned nin, unsigned nout, unsigned n_inner,
-                         const int* rowptr, const int* cols, const double* w, unsigned mask_nzn,
-                         hipStream_t st) {
+                         const int* rowptr, const int* cols, const double* w, unsigned nnz,
+                         int maxr, unsigned mask_nzn, hipStream_t st) {
   const size_t total = (size_t)n_outer * nout * n_inner;
+  if (total == 0) return hipSuccess;
+  const bool small = total < (1ull << 32) && (size_t)n_outer * nin * n_inner < (1ull << 32);
+  if (small && n_inner == 1) {
+    const unsigned B = AXIS_LINES;
+    const size_t smem = (size_t)B * nin * 8 + (size_t)nnz * 12 + (size_t)(nout + 1) * 4;
+    if (smem <= AXIS_LINES_SMEM) {
+      const unsigned blocks = (n_outer + B - 1) / B;
+      if (in2)
+        hipLaunchKernelGGL((k_axis_lines<TI, TO, true>), dim3(blocks), dim3(256), smem, st,
+                           (const TI*)in, (const TI*)in2, (TO*)out, accumulate, n_outer, nin,
+                           nout, rowptr, cols, w, nnz, B, mask_nzn);
+      else
+        hipLaunchKernelGGL((k_axis_lines<TI, TO, false>), dim3(blocks), dim3(256), smem, st,
+                           (const TI*)in, (const TI*)in2, (TO*)out, accumulate, n_outer, nin,
+                           nout, rowptr, cols, w, nnz, B, mask_nzn);
+      return hipGetLastError();
+    }
+  }
+  if (small && maxr >= 0 && maxr <= 16) {
+    const unsigned t = (unsigned)total;
+    if (maxr <= 4)
+      axis_rows_launch<TI, TO, 4>(in, in2, out, accumulate, t, nin, nout, n_inner, rowptr, cols,
+                                  w, mask_nzn, st);
+    else if (maxr <= 8)
+      axis_rows_launch<TI, TO, 8>(in, in2, out, accumulate, t, nin, nout, n_inner, rowptr, cols,
+                                  w, mask_nzn, st);
+    else
+      axis_rows_launch<TI, TO, 16>(in, in2, out, accumulate, t, nin, nout, n_inner, rowptr,
+                                   cols, w, mask_nzn, st);
+    return hipGetLastError();
+  }
   const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
   hipLaunchKernelGGL((k_axis<TI, TO>), dim3(blocks), dim3(256), 0, st, (const TI*)in,
                      (const TI*)in2, (TO*)out, accumulate, n_outer, nin, nout, n_inner, rowptr,
@@ -1642,18 +1789,18 @@ static hipError_t axis_t(const void* in, const void* in2, void* out, int accumul
 hipError_t axis_apply(int in_dbl, int out_dbl, const void* in, const void* in2, void* out,
                       int accumulate, unsigned n_outer, unsigned nin, unsigned nout,
                       unsigned n_inner, const int* rowptr, const int* cols, const double* w,
-                      unsigned mask_nzn, hipStream_t st) {
+                      unsigned nnz, int maxr, unsigned mask_nzn, hipStream_t st) {
   if (in_dbl && out_dbl)
     return axis_t<double, double>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                                  cols, w, mask_nzn, st);
+                                  cols, w, nnz, maxr, mask_nzn, st);
   if (in_dbl)
     return axis_t<double, float>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                                 cols, w, mask_nzn, st);
+                                 cols, w, nnz, maxr, mask_nzn, st);
   if (out_dbl)
     return axis_t<float, double>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                                 cols, w, mask_nzn, st);
+                                 cols, w, nnz, maxr, mask_nzn, st);
   return axis_t<float, float>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                              cols, w, mask_nzn, st);
+                              cols, w, nnz, maxr, mask_nzn, st);
 }
 
 // coarsest level: x = Ainv b (dense FP64 inverse of the masked operator), one wave per row

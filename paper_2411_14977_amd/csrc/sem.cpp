@@ -57,6 +57,8 @@ struct DLevel {
     int* rp = nullptr;
     int* ci = nullptr;
     double* w = nullptr;
+    unsigned nnz = 0;
+    int maxr = 0;  // longest row
   } P1[3], R1[3];
 };
 
@@ -413,11 +415,12 @@ void restrict_to(Ctx* c, int l, bool use_ax) {
   if (c->dim == 3) {  // b_c = (R_x R_y R_z)(b - A x): z, then y, then x; Dirichlet rows zeroed
     const unsigned nxf = F.nxn, nyf = F.nyn, nzf = F.nzn, nxc = C.nxn, nyc = C.nyn, nzc = C.nzn;
     HK(semk::axis_apply(F.dbl, 1, F.b, use_ax ? F.y : nullptr, c->tA, 0, nxf * nyf, nzf, nzc, 1,
-                        F.R1[2].rp, F.R1[2].ci, F.R1[2].w, 0, c->st));
+                        F.R1[2].rp, F.R1[2].ci, F.R1[2].w, F.R1[2].nnz, F.R1[2].maxr, 0, c->st));
     HK(semk::axis_apply(1, 1, c->tA, nullptr, c->tB, 0, nxf, nyf, nyc, nzc, F.R1[1].rp,
-                        F.R1[1].ci, F.R1[1].w, 0, c->st));
+                        F.R1[1].ci, F.R1[1].w, F.R1[1].nnz, F.R1[1].maxr, 0, c->st));
     HK(semk::axis_apply(1, C.dbl, c->tB, nullptr, C.b, 0, 1, nxf, nxc, nyc * nzc, F.R1[0].rp,
-                        F.R1[0].ci, F.R1[0].w, c->masked ? nzc : 0, c->st));
+                        F.R1[0].ci, F.R1[0].w, F.R1[0].nnz, F.R1[0].maxr,
+                        c->masked ? nzc : 0, c->st));
     return;
   }
   HK(semk::restrict2d(F.dbl, C.dbl, F.b, F.y, F.S, use_ax ? 1 : 0, C.b, F.J, F.Nx, F.Nz, F.P,
@@ -430,11 +433,11 @@ void prolong_from(Ctx* c, int l) {
   if (c->dim == 3) {  // x_f += (P_x P_y P_z) x_c: x, then y, then z
     const unsigned nxf = F.nxn, nyf = F.nyn, nzf = F.nzn, nxc = C.nxn, nyc = C.nyn, nzc = C.nzn;
     HK(semk::axis_apply(C.dbl, 1, C.x, nullptr, c->tB, 0, 1, nxc, nxf, nyc * nzc, F.P1[0].rp,
-                        F.P1[0].ci, F.P1[0].w, 0, c->st));
+                        F.P1[0].ci, F.P1[0].w, F.P1[0].nnz, F.P1[0].maxr, 0, c->st));
     HK(semk::axis_apply(1, 1, c->tB, nullptr, c->tA, 0, nxf, nyc, nyf, nzc, F.P1[1].rp,
-                        F.P1[1].ci, F.P1[1].w, 0, c->st));
+                        F.P1[1].ci, F.P1[1].w, F.P1[1].nnz, F.P1[1].maxr, 0, c->st));
     HK(semk::axis_apply(1, F.dbl, c->tA, nullptr, F.x, 1, nxf * nyf, nzc, nzf, 1, F.P1[2].rp,
-                        F.P1[2].ci, F.P1[2].w, 0, c->st));
+                        F.P1[2].ci, F.P1[2].w, F.P1[2].nnz, F.P1[2].maxr, 0, c->st));
     return;
   }
   HK(semk::prolong2d(F.dbl, C.dbl, C.x, F.x, F.J, F.Nx, F.Nz, F.P, C.P, c->st));
@@ -939,7 +942,9 @@ void upload_op(Ctx* c, const Rows1& r, DLevel::Op1& op) {
       w.push_back(e.second);
     }
     rp.push_back((int)ci.size());
+    op.maxr = std::max(op.maxr, (int)row.size());
   }
+  op.nnz = (unsigned)ci.size();
   op.rp = upload(c, rp);
   op.ci = upload(c, ci);
   op.w = upload(c, w);
