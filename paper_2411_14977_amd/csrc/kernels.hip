@@ -1503,16 +1503,17 @@ __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __
 
 // y += the side-buffer parts on lines shared between columns: every node of an interior x-plane
 // (Sx, plus Sy and Sxy where it also lies on an interior y-plane), then the nodes of interior
-// y-planes that are not on an x-plane (Sy).  Each node is written by one thread.
-template <typename T>
+// y-planes that are not on an x-plane (Sy).  Each node is written by one thread.  I is the
+// index type: 32-bit whenever the grid fits, which keeps the per-node divisions 32-bit.
+template <typename T, typename I>
 __global__ void k_fix3d(T* __restrict__ y, const T* __restrict__ Sx, const T* __restrict__ Sy,
                         const T* __restrict__ Sxy, int Nx, int Ny, int P, unsigned nyn,
                         unsigned nzn, Step3 st3, T* __restrict__ x) {
-  const unsigned nxn = (unsigned)Nx * P + 1;
-  const size_t nxp = (size_t)(Nx - 1) * nyn * nzn;
-  const size_t nyp = (size_t)(Ny - 1) * nxn * nzn;
+  const I nxn = (I)Nx * P + 1;
+  const I nxp = (I)(Nx - 1) * nyn * nzn;
+  const I nyp = (I)(Ny - 1) * nxn * nzn;
   // complete node g with its side-buffer part v: y, or (smoother step) the update of x, d
-  auto finish = [&](size_t g, T v) {
+  auto finish = [&](I g, T v) {
     const T ax = y[g] + v;
     if (!st3.b) {
       y[g] = ax;
@@ -1525,23 +1526,24 @@ __global__ void k_fix3d(T* __restrict__ y, const T* __restrict__ Sx, const T* __
     if (st3.store_d) d[g] = dn;
     x[g] = x[g] + dn;
   };
-  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < nxp + nyp;
-       k += (size_t)gridDim.x * blockDim.x) {
+  const I pyz = (I)nyn * nzn, pxz = nxn * (I)nzn;
+  for (I k = blockIdx.x * (I)blockDim.x + threadIdx.x; k < nxp + nyp;
+       k += (I)gridDim.x * blockDim.x) {
     if (k < nxp) {
-      const size_t q = k / ((size_t)nyn * nzn), rem = k - q * nyn * nzn;
-      const unsigned iy = (unsigned)(rem / nzn), iz = (unsigned)(rem - (size_t)iy * nzn);
-      const size_t g = (((q + 1) * P) * nyn + iy) * nzn + iz;
+      const I q = k / pyz, rem = k - q * pyz;
+      const unsigned iy = (unsigned)(rem / nzn), iz = (unsigned)(rem - (I)iy * nzn);
+      const I g = (((q + 1) * P) * nyn + iy) * nzn + iz;
       T v = Sx[g];
       const unsigned qy = iy / P;
       if (qy * P == iy && qy > 0 && qy < (unsigned)Ny) v += Sy[g] + Sxy[g];
       finish(g, v);
     } else {
-      const size_t k2 = k - nxp;
-      const size_t q = k2 / ((size_t)nxn * nzn), rem = k2 - q * nxn * nzn;
-      const unsigned ix = (unsigned)(rem / nzn), iz = (unsigned)(rem - (size_t)ix * nzn);
+      const I k2 = k - nxp;
+      const I q = k2 / pxz, rem = k2 - q * pxz;
+      const unsigned ix = (unsigned)(rem / nzn), iz = (unsigned)(rem - (I)ix * nzn);
       const unsigned qx = ix / P;
       if (qx * P == ix && qx > 0 && qx < (unsigned)Nx) continue;  // done by the x-plane pass
-      const size_t g = ((size_t)ix * nyn + (q + 1) * P) * nzn + iz;
+      const I g = ((I)ix * nyn + (q + 1) * P) * nzn + iz;
       finish(g, Sy[g]);
     }
   }
@@ -1565,8 +1567,15 @@ static hipError_t launch_apply3d(const void* x, void* y, void* Sx, void* Sy, voi
     const unsigned nyn = Ny * P + 1, nzn = Nz * P + 1;
     const size_t tot = (size_t)(Nx - 1) * nyn * nzn + (size_t)(Ny - 1) * (Nx * P + 1) * nzn;
     const unsigned blocks = (unsigned)std::min<size_t>((tot + 255) / 256, 16384);
-    hipLaunchKernelGGL(k_fix3d<T>, dim3(blocks), dim3(256), 0, st, (T*)y, (const T*)Sx,
-                       (const T*)Sy, (const T*)Sxy, Nx, Ny, P, nyn, nzn, st3, (T*)x);
+    const size_t nodes = ((size_t)Nx * P + 1) * nyn * nzn;
+    if (nodes < (1ull << 32) && tot + (size_t)blocks * 256 < (1ull << 32))
+      hipLaunchKernelGGL((k_fix3d<T, unsigned>), dim3(blocks), dim3(256), 0, st, (T*)y,
+                         (const T*)Sx, (const T*)Sy, (const T*)Sxy, Nx, Ny, P, nyn, nzn, st3,
+                         (T*)x);
+    else
+      hipLaunchKernelGGL((k_fix3d<T, size_t>), dim3(blocks), dim3(256), 0, st, (T*)y,
+                         (const T*)Sx, (const T*)Sy, (const T*)Sxy, Nx, Ny, P, nyn, nzn, st3,
+                         (T*)x);
   }
   return hipGetLastError();
 }
