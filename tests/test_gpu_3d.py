@@ -30,6 +30,8 @@ CASES3 = {
     "t3hh": (W.tank3d(8, 4, 1, 2, L=0.8, name="t3hh"), 20),           # two h-levels
     "t3p6": (W.tank3d(2, 2, 2, 6, L=0.8, orders=[6, 3, 1], name="t3p6"), 1200),
     "t3odd": (W.tank3d(3, 2, 3, 3, L=0.8, name="t3odd"), 1200),       # odd P, odd counts
+    # P = 8 -> 4: restriction rows of 17 entries take the general transfer kernel
+    "t3p8": (W.tank3d(2, 1, 1, 8, L=0.8, name="t3p8"), 1200),
 }
 
 _oracle = {}
