@@ -91,11 +91,14 @@ hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, 
 // one 1D operator (CSR rows over the output index) along the middle axis of [outer][n][inner]
 // arrays; in2 (optional) is subtracted from in; mask_nzn > 0 zeroes every mask_nzn-th output
 // (the Dirichlet surface rows when inner is the vertical axis)
-// nnz = entries of the CSR operator (nout rows); maxr = its longest row (-1: unknown)
+// nnz = entries of the CSR operator (nout rows).  The same operator as bands: band holds one
+// int4 {first column, length, offset into wband, 0} per row, wband the weights dense over each
+// band; bandmax = the longest band (null band or bandmax < 0: not available)
 hipError_t axis_apply(int in_dbl, int out_dbl, const void* in, const void* in2, void* out,
                       int accumulate, unsigned n_outer, unsigned nin, unsigned nout,
                       unsigned n_inner, const int* rowptr, const int* cols, const double* w,
-                      unsigned nnz, int maxr, unsigned mask_nzn, hipStream_t st);
+                      unsigned nnz, const int* band, const double* wband, int bandmax,
+                      unsigned mask_nzn, hipStream_t st);
 hipError_t dense_gemv(const double* Ainv, const double* b, double* x, int n, hipStream_t st);
 // surface update (3D, fine level, FP64): factors G (g3d_layout) and lumped mass from the fine
 // column samples hf, ef ((Nx P + 1) x (Ny P + 1), y fastest); r, w: GLL nodes and weights

@@ -1693,33 +1693,34 @@ __global__ __launch_bounds__(256) void k_axis_lines(const TI* __restrict__ in,
   }
 }
 
-// Strided axes: one output per thread as in k_axis, with 32-bit indices and the row's entries
-// unrolled to a bound R >= the longest row, so that every gather of the row is issued before
-// the (unchanged, in-order) sum.
+// Strided axes: one output per thread as in k_axis, with 32-bit indices and the row as a band:
+// one int4 {first column, length, offset into wband, 0} per row and the weights dense over the
+// band (zeros where the CSR row has no entry), unrolled to R >= the longest band.  The data
+// addresses then depend on one index load instead of two, and every gather of the row is issued
+// before the sum (ascending columns).
 template <typename TI, typename TO, int R, bool SUB>
-__global__ __launch_bounds__(256) void k_axis_rows(const TI* __restrict__ in,
+__global__ __launch_bounds__(256) void k_axis_band(const TI* __restrict__ in,
                                                    const TI* __restrict__ in2,
                                                    TO* __restrict__ out, int accumulate,
                                                    unsigned total, unsigned nin, unsigned nout,
                                                    unsigned n_inner,
-                                                   const int* __restrict__ rowptr,
-                                                   const int* __restrict__ cols,
-                                                   const double* __restrict__ w,
+                                                   const int4* __restrict__ band,
+                                                   const double* __restrict__ wband,
                                                    unsigned mask_nzn) {
   const unsigned k = blockIdx.x * 256u + threadIdx.x;
   if (k >= total) return;
   const unsigned ii = k % n_inner, rest = k / n_inner;
   const unsigned ko = rest % nout, o = rest / nout;
-  const unsigned base = o * nin * n_inner + ii;
-  const int e0 = rowptr[ko], n = rowptr[ko + 1] - e0;
+  const int4 bd = band[ko];
+  const unsigned base = (o * nin + (unsigned)bd.x) * n_inner + ii;
   double v[R], ww[R];
 #pragma unroll
   for (int j = 0; j < R; ++j) {
     v[j] = 0.0;
     ww[j] = 0.0;
-    if (j < n) {
-      const unsigned src = base + (unsigned)cols[e0 + j] * n_inner;
-      ww[j] = w[e0 + j];
+    if (j < bd.y) {
+      const unsigned src = base + (unsigned)j * n_inner;
+      ww[j] = wband[bd.z + j];
       v[j] = (double)in[src];
       if (SUB) v[j] -= (double)in2[src];
     }
@@ -1727,25 +1728,25 @@ __global__ __launch_bounds__(256) void k_axis_rows(const TI* __restrict__ in,
   double s = 0.0;
 #pragma unroll
   for (int j = 0; j < R; ++j)
-    if (j < n) s += ww[j] * v[j];
+    if (j < bd.y) s += ww[j] * v[j];
   if (mask_nzn && (k % mask_nzn) == mask_nzn - 1) s = 0.0;
   out[k] = accumulate ? (TO)((double)out[k] + s) : (TO)s;
 }
 
 template <typename TI, typename TO, int R>
-static void axis_rows_launch(const void* in, const void* in2, void* out, int accumulate,
+static void axis_band_launch(const void* in, const void* in2, void* out, int accumulate,
                              unsigned total, unsigned nin, unsigned nout, unsigned n_inner,
-                             const int* rowptr, const int* cols, const double* w,
-                             unsigned mask_nzn, hipStream_t st) {
+                             const int* band, const double* wband, unsigned mask_nzn,
+                             hipStream_t st) {
   const unsigned blocks = (total + 255u) / 256u;
   if (in2)
-    hipLaunchKernelGGL((k_axis_rows<TI, TO, R, true>), dim3(blocks), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_axis_band<TI, TO, R, true>), dim3(blocks), dim3(256), 0, st,
                        (const TI*)in, (const TI*)in2, (TO*)out, accumulate, total, nin, nout,
-                       n_inner, rowptr, cols, w, mask_nzn);
+                       n_inner, (const int4*)band, wband, mask_nzn);
   else
-    hipLaunchKernelGGL((k_axis_rows<TI, TO, R, false>), dim3(blocks), dim3(256), 0, st,
+    hipLaunchKernelGGL((k_axis_band<TI, TO, R, false>), dim3(blocks), dim3(256), 0, st,
                        (const TI*)in, (const TI*)in2, (TO*)out, accumulate, total, nin, nout,
-                       n_inner, rowptr, cols, w, mask_nzn);
+                       n_inner, (const int4*)band, wband, mask_nzn);
 }
 
 constexpr unsigned AXIS_LINES = 32;           // lines per block of k_axis_lines
@@ -1755,7 +1756,8 @@ template <typename TI, typename TO>
 static hipError_t axis_t(const void* in, const void* in2, void* out, int accumulate,
                          unsigned n_outer, unsigned nin, unsigned nout, unsigned n_inner,
                          const int* rowptr, const int* cols, const double* w, unsigned nnz,
-                         int maxr, unsigned mask_nzn, hipStream_t st) {
+                         const int* band, const double* wband, int bandmax, unsigned mask_nzn,
+                         hipStream_t st) {
   const size_t total = (size_t)n_outer * nout * n_inner;
   if (total == 0) return hipSuccess;
   const bool small = total < (1ull << 32) && (size_t)n_outer * nin * n_inner < (1ull << 32);
@@ -1775,17 +1777,17 @@ static hipError_t axis_t(const void* in, const void* in2, void* out, int accumul
       return hipGetLastError();
     }
   }
-  if (small && maxr >= 0 && maxr <= 16) {
+  if (small && band && wband && bandmax >= 0 && bandmax <= 16) {
     const unsigned t = (unsigned)total;
-    if (maxr <= 4)
-      axis_rows_launch<TI, TO, 4>(in, in2, out, accumulate, t, nin, nout, n_inner, rowptr, cols,
-                                  w, mask_nzn, st);
-    else if (maxr <= 8)
-      axis_rows_launch<TI, TO, 8>(in, in2, out, accumulate, t, nin, nout, n_inner, rowptr, cols,
-                                  w, mask_nzn, st);
+    if (bandmax <= 4)
+      axis_band_launch<TI, TO, 4>(in, in2, out, accumulate, t, nin, nout, n_inner, band, wband,
+                                  mask_nzn, st);
+    else if (bandmax <= 8)
+      axis_band_launch<TI, TO, 8>(in, in2, out, accumulate, t, nin, nout, n_inner, band, wband,
+                                  mask_nzn, st);
     else
-      axis_rows_launch<TI, TO, 16>(in, in2, out, accumulate, t, nin, nout, n_inner, rowptr,
-                                   cols, w, mask_nzn, st);
+      axis_band_launch<TI, TO, 16>(in, in2, out, accumulate, t, nin, nout, n_inner, band, wband,
+                                   mask_nzn, st);
     return hipGetLastError();
   }
   const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
@@ -1798,18 +1800,19 @@ static hipError_t axis_t(const void* in, const void* in2, void* out, int accumul
 hipError_t axis_apply(int in_dbl, int out_dbl, const void* in, const void* in2, void* out,
                       int accumulate, unsigned n_outer, unsigned nin, unsigned nout,
                       unsigned n_inner, const int* rowptr, const int* cols, const double* w,
-                      unsigned nnz, int maxr, unsigned mask_nzn, hipStream_t st) {
+                      unsigned nnz, const int* band, const double* wband, int bandmax,
+                      unsigned mask_nzn, hipStream_t st) {
   if (in_dbl && out_dbl)
     return axis_t<double, double>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                                  cols, w, nnz, maxr, mask_nzn, st);
+                                  cols, w, nnz, band, wband, bandmax, mask_nzn, st);
   if (in_dbl)
     return axis_t<double, float>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                                 cols, w, nnz, maxr, mask_nzn, st);
+                                 cols, w, nnz, band, wband, bandmax, mask_nzn, st);
   if (out_dbl)
     return axis_t<float, double>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                                 cols, w, nnz, maxr, mask_nzn, st);
+                                 cols, w, nnz, band, wband, bandmax, mask_nzn, st);
   return axis_t<float, float>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
-                              cols, w, nnz, maxr, mask_nzn, st);
+                              cols, w, nnz, band, wband, bandmax, mask_nzn, st);
 }
 
 // coarsest level: x = Ainv b (dense FP64 inverse of the masked operator), one wave per row

@@ -12,6 +12,7 @@
 #include <functional>
 #include <thread>
 #include <chrono>
+#include <climits>
 #include <utility>
 #include <cmath>
 #include <cstdio>
@@ -58,7 +59,9 @@ struct DLevel {
     int* ci = nullptr;
     double* w = nullptr;
     unsigned nnz = 0;
-    int maxr = 0;  // longest row
+    int* band = nullptr;  // per row {first column, length, offset into wband, 0}
+    double* wband = nullptr;
+    int bandmax = 0;  // longest band
   } P1[3], R1[3];
 };
 
@@ -415,11 +418,14 @@ void restrict_to(Ctx* c, int l, bool use_ax) {
   if (c->dim == 3) {  // b_c = (R_x R_y R_z)(b - A x): z, then y, then x; Dirichlet rows zeroed
     const unsigned nxf = F.nxn, nyf = F.nyn, nzf = F.nzn, nxc = C.nxn, nyc = C.nyn, nzc = C.nzn;
     HK(semk::axis_apply(F.dbl, 1, F.b, use_ax ? F.y : nullptr, c->tA, 0, nxf * nyf, nzf, nzc, 1,
-                        F.R1[2].rp, F.R1[2].ci, F.R1[2].w, F.R1[2].nnz, F.R1[2].maxr, 0, c->st));
+                        F.R1[2].rp, F.R1[2].ci, F.R1[2].w, F.R1[2].nnz, F.R1[2].band,
+                        F.R1[2].wband, F.R1[2].bandmax, 0, c->st));
     HK(semk::axis_apply(1, 1, c->tA, nullptr, c->tB, 0, nxf, nyf, nyc, nzc, F.R1[1].rp,
-                        F.R1[1].ci, F.R1[1].w, F.R1[1].nnz, F.R1[1].maxr, 0, c->st));
+                        F.R1[1].ci, F.R1[1].w, F.R1[1].nnz, F.R1[1].band,
+                        F.R1[1].wband, F.R1[1].bandmax, 0, c->st));
     HK(semk::axis_apply(1, C.dbl, c->tB, nullptr, C.b, 0, 1, nxf, nxc, nyc * nzc, F.R1[0].rp,
-                        F.R1[0].ci, F.R1[0].w, F.R1[0].nnz, F.R1[0].maxr,
+                        F.R1[0].ci, F.R1[0].w, F.R1[0].nnz, F.R1[0].band,
+                        F.R1[0].wband, F.R1[0].bandmax,
                         c->masked ? nzc : 0, c->st));
     return;
   }
@@ -433,11 +439,14 @@ void prolong_from(Ctx* c, int l) {
   if (c->dim == 3) {  // x_f += (P_x P_y P_z) x_c: x, then y, then z
     const unsigned nxf = F.nxn, nyf = F.nyn, nzf = F.nzn, nxc = C.nxn, nyc = C.nyn, nzc = C.nzn;
     HK(semk::axis_apply(C.dbl, 1, C.x, nullptr, c->tB, 0, 1, nxc, nxf, nyc * nzc, F.P1[0].rp,
-                        F.P1[0].ci, F.P1[0].w, F.P1[0].nnz, F.P1[0].maxr, 0, c->st));
+                        F.P1[0].ci, F.P1[0].w, F.P1[0].nnz, F.P1[0].band,
+                        F.P1[0].wband, F.P1[0].bandmax, 0, c->st));
     HK(semk::axis_apply(1, 1, c->tB, nullptr, c->tA, 0, nxf, nyc, nyf, nzc, F.P1[1].rp,
-                        F.P1[1].ci, F.P1[1].w, F.P1[1].nnz, F.P1[1].maxr, 0, c->st));
+                        F.P1[1].ci, F.P1[1].w, F.P1[1].nnz, F.P1[1].band,
+                        F.P1[1].wband, F.P1[1].bandmax, 0, c->st));
     HK(semk::axis_apply(1, F.dbl, c->tA, nullptr, F.x, 1, nxf * nyf, nzc, nzf, 1, F.P1[2].rp,
-                        F.P1[2].ci, F.P1[2].w, F.P1[2].nnz, F.P1[2].maxr, 0, c->st));
+                        F.P1[2].ci, F.P1[2].w, F.P1[2].nnz, F.P1[2].band,
+                        F.P1[2].wband, F.P1[2].bandmax, 0, c->st));
     return;
   }
   HK(semk::prolong2d(F.dbl, C.dbl, C.x, F.x, F.J, F.Nx, F.Nz, F.P, C.P, c->st));
@@ -934,20 +943,31 @@ Rows1 transpose1d(const Rows1& r, int ncols) {
 }
 
 void upload_op(Ctx* c, const Rows1& r, DLevel::Op1& op) {
-  std::vector<int> rp(1, 0), ci;
-  std::vector<double> w;
+  std::vector<int> rp(1, 0), ci, band;
+  std::vector<double> w, wband;
   for (const auto& row : r) {
+    int lo = INT_MAX, hi = -1;
     for (const auto& e : row) {
       ci.push_back(e.first);
       w.push_back(e.second);
+      lo = std::min(lo, e.first);
+      hi = std::max(hi, e.first);
     }
     rp.push_back((int)ci.size());
-    op.maxr = std::max(op.maxr, (int)row.size());
+    // the row as a band [lo, hi] with zero weights where it has no entry
+    const int len = hi >= lo ? hi - lo + 1 : 0, off = (int)wband.size();
+    wband.resize(wband.size() + len, 0.0);
+    for (const auto& e : row) wband[off + e.first - lo] += e.second;
+    band.insert(band.end(), {len ? lo : 0, len, off, 0});
+    op.bandmax = std::max(op.bandmax, len);
   }
+  if (wband.empty()) wband.push_back(0.0);
   op.nnz = (unsigned)ci.size();
   op.rp = upload(c, rp);
   op.ci = upload(c, ci);
   op.w = upload(c, w);
+  op.band = upload(c, band);
+  op.wband = upload(c, wband);
 }
 
 void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders) {
