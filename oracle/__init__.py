@@ -23,6 +23,8 @@ nonlinear water waves"):
                   ceil(P/2)), prolongation/restriction (Sec. 6.2), smoothers,
                   V-cycle (Sec. 6), outer flexible CG and defect correction
                   (Sec. 6.4).
+* ``precision``-- rounding to FP32 / BF16 (the storage precisions of the inner V-cycle's
+                  geometric factors and of the network's GEMM operands).
 * ``mlp``      -- the element-local network used as a learned smoothing stage
                   (not in the paper; defined by its formulas only) and the
                   additive-Schwarz element solve it is checked against (Sec. 6.3).

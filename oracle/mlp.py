@@ -24,6 +24,7 @@ import numpy as np
 from scipy.special import erf
 
 from .assemble import element_matrices
+from .precision import bf16, f32  # noqa: F401  (BF16 emulation of the GEMM operands)
 
 NH = 128
 
@@ -34,19 +35,6 @@ def gelu(x):
 
 def gelu_grad(x):
     return 0.5 * (1.0 + erf(x / math.sqrt(2.0))) + x * np.exp(-0.5 * x * x) / math.sqrt(2.0 * math.pi)
-
-
-def bf16(x):
-    """Round to bfloat16 (round to nearest even), via float32 as the GPU path does."""
-    f = np.asarray(x, dtype=np.float64).astype(np.float32)
-    u = f.view(np.uint32).astype(np.uint64)
-    lsb = (u >> 16) & 1
-    u = ((u + 0x7FFF + lsb) >> 16) << 16
-    return u.astype(np.uint32).view(np.float32).astype(np.float64)
-
-
-def f32(x):
-    return np.asarray(x, dtype=np.float64).astype(np.float32).astype(np.float64)
 
 
 def init_params(n_in, n_out, seed):
@@ -107,6 +95,29 @@ def adam(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
         vh = vo[k] / (1 - b2 ** t)
         out[k] = p[k] - lr * mh / (np.sqrt(vh) + eps)
     return out, mo, vo
+
+
+def cosine_lr(lr0, step, total_steps):
+    """Learning rate of Adam step ``step`` (counted from 1) out of ``total_steps``: cosine decay
+    from lr0, lr0 (1 + cos(pi (step - 1) / total_steps)) / 2."""
+    return lr0 * 0.5 * (1.0 + math.cos(math.pi * (step - 1) / total_steps))
+
+
+def train_full_batch(p, X, T, steps, lr0, total_steps=None, emulate=True):
+    """``steps`` Adam steps on the whole set (rows in order, no shuffling) with the cosine
+    schedule over ``total_steps`` (default: steps).  Returns the parameters and the loss before
+    each step."""
+    total_steps = steps if total_steps is None else total_steps
+    m = {k: np.zeros_like(v) for k, v in p.items()}
+    v = {k: np.zeros_like(v) for k, v in p.items()}
+    losses = []
+    for t in range(1, steps + 1):
+        Y, cache = forward(p, X, emulate)
+        loss, dY = mse(Y, T)
+        losses.append(loss)
+        g = backward(p, cache, dY, emulate)
+        p, m, v = adam(p, g, m, v, t, cosine_lr(lr0, t, total_steps))
+    return p, losses
 
 
 # ---- element features and the smoothing stage ------------------------------------------------

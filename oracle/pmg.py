@@ -41,6 +41,7 @@ import scipy.sparse.linalg as spla
 from . import gll
 from .assemble import assemble_operator
 from .mesh import Mesh2D, Mesh3D
+from .precision import with_stored_factors
 
 
 def coarsen_orders(P):
@@ -80,9 +81,14 @@ def prolongation_1d(Ne, Pc, Pf):
 
 
 class Level:
-    def __init__(self, mesh):
+    """One level: its mesh (exact geometry) and the masked operator.  gstore: precision in which
+    the level's geometric factors are held ("f64", "f32" or "bf16"); the operator and its
+    diagonal are built from the rounded factors, everything else stays exact FP64."""
+
+    def __init__(self, mesh, gstore=None):
         self.mesh = mesh
-        self.A = assemble_operator(mesh, dirichlet=True)
+        self.gstore = gstore
+        self.A = assemble_operator(with_stored_factors(mesh, gstore), dirichlet=True)
         self.diag = self.A.diagonal().copy()
         self.dinv = 1.0 / self.diag
         self.dn = mesh.dirichlet_nodes()
@@ -115,14 +121,17 @@ class Hierarchy:
 
     def __init__(self, mesh_args, orders, smoother="chebyshev", nu_pre=2, nu_post=2,
                  cheb_degree=3, jacobi_omega=2.0 / 3.0, cheb_lo=0.1, cheb_hi=1.1,
-                 coarse_dense_max=1200):
+                 coarse_dense_max=1200, gstore=None):
+        """gstore: storage precision of the geometric factors on every level above the
+        coarsest (None / "f64", "f32", "bf16"); the coarsest level is always exact."""
         self.dim = mesh_args["dim"]
         self.orders = list(orders)
         if self.orders[-1] != 1:
             raise ValueError("coarsest order must be 1")
         self.levels = []
         Pf = self.orders[0]
-        for p in self.orders:
+        for li, p in enumerate(self.orders):
+            gs = gstore if li + 1 < len(self.orders) else None
             if self.dim == 2:
                 m = Mesh2D(mesh_args["Nx"], mesh_args["Nz"], p, mesh_args["Lx"],
                            mesh_args["h"], mesh_args["eta"], P_fine=Pf)
@@ -130,7 +139,7 @@ class Hierarchy:
                 m = Mesh3D(mesh_args["Nx"], mesh_args["Ny"], mesh_args["Nz"], p,
                            mesh_args["Lx"], mesh_args["Ly"], mesh_args["h"], mesh_args["eta"],
                            P_fine=Pf)
-            self.levels.append(Level(m))
+            self.levels.append(Level(m, gs))
         self.P = []
         for l in range(len(self.orders) - 1):
             pf, pc = self.orders[l], self.orders[l + 1]
@@ -158,6 +167,10 @@ class Hierarchy:
                              sp.identity(Nz + 1))
                 self.P.append(Pm.tocsr())
                 nx, ny = ncx, ncy
+        # every level above the (possibly h-coarsened) coarsest holds its factors in gstore
+        for li in range(len(self.levels) - 1):
+            if self.levels[li].gstore != gstore:
+                self.levels[li] = Level(self.levels[li].mesh, gstore)
         last = self.levels[-1]
         last.lu = spla.splu(sp.csc_matrix(last.A))
         self.smoother = smoother
@@ -221,9 +234,11 @@ class Hierarchy:
     def coarse_solve(self, b):
         return self.levels[-1].lu.solve(b)
 
-    def vcycle(self, b, l=0, hook=None):
-        """z = B b with zero initial guess.  ``hook(l, b, x)`` may add a stage after
-        pre-smoothing on level l and return the new x (used for the learned stage)."""
+    def vcycle(self, b, l=0, hook=None, hook_post=None):
+        """z = B b with zero initial guess.  Two optional stages on level l, each a map
+        (l, b, x) -> new x (used for the learned stage): ``hook`` after the pre-smoothing (before
+        the residual that is restricted), ``hook_post`` after the coarse-grid correction has been
+        added (before the post-smoothing)."""
         if l == len(self.levels) - 1:
             return self.coarse_solve(b)
         L = self.levels[l]
@@ -231,8 +246,10 @@ class Hierarchy:
         if hook is not None:
             x = hook(l, b, x)
         r = b - L.A @ x
-        ec = self.vcycle(self.restrict(l, r), l + 1, hook)
+        ec = self.vcycle(self.restrict(l, r), l + 1, hook, hook_post)
         x = x + self.prolong(l, ec)
+        if hook_post is not None:
+            x = hook_post(l, b, x)
         x = self.smooth(l, b, x, pre=False)
         return x
 

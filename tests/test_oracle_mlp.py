@@ -139,3 +139,62 @@ def test_accepted_stage_does_not_increase_energy_error():
         x1, ok = mlp.stage(A, m, p, b, x0, emulate=False)
         e0, e1 = xs - x0, xs - x1
         assert e1 @ (A @ e1) <= e0 @ (A @ e0) * (1 + 1e-12)
+
+
+def test_adam_two_steps_by_hand():
+    """Two Adam steps with gradients 1 then -2 (lr 0.01), worked by hand:
+    m1 = 0.1, v1 = 0.001, step 1 = -0.01 (1 / (1 + 1e-8));
+    m2 = 0.9 * 0.1 + 0.1 * (-2) = -0.11, v2 = 0.999 * 0.001 + 0.001 * 4 = 0.004999,
+    m2_hat = -0.11 / 0.19 = -0.578947368..., v2_hat = 0.004999 / 0.001999 = 2.500750375...,
+    sqrt(v2_hat) = 1.581376...,
+    step 2 = -0.01 * m2_hat / (sqrt(v2_hat) + 1e-8) = +0.0036610352..."""
+    p = {"w": np.array([0.5])}
+    z = {"w": np.zeros(1)}
+    p1, m1, v1 = mlp.adam(p, {"w": np.array([1.0])}, z, z, 1, lr=0.01)
+    assert abs(m1["w"][0] - 0.1) < 1e-16 and abs(v1["w"][0] - 0.001) < 1e-18
+    assert abs(p1["w"][0] - (0.5 - 0.01 / (1.0 + 1e-8))) < 1e-16
+    p2, m2, v2 = mlp.adam(p1, {"w": np.array([-2.0])}, m1, v1, 2, lr=0.01)
+    assert abs(m2["w"][0] + 0.11) < 1e-15 and abs(v2["w"][0] - 0.004999) < 1e-17
+    m2_hat = -0.11 / 0.19
+    v2_hat = 0.004999 / 0.001999
+    assert abs(m2_hat + 0.5789473684210527) < 1e-15 and abs(v2_hat - 2.5007503751875937) < 1e-14
+    step2 = 0.01 * 0.5789473684210527 / (math.sqrt(2.5007503751875937) + 1e-8)
+    assert abs(step2 - 0.0036610352) < 1e-10
+    assert abs(p2["w"][0] - (p1["w"][0] + step2)) < 1e-15
+
+
+def test_adam_constant_gradient_trajectory():
+    """With a constant gradient the bias-corrected moments are g and g^2 at every step, so t
+    steps at a fixed rate move each weight by t lr g / (|g| + eps): pins the step-dependent
+    bias corrections beyond the first step."""
+    g = {"w": np.array([0.3, -4.0, 2e-3])}
+    p0 = {"w": np.array([1.0, -2.0, 0.5])}
+    p, m, v = p0, {"w": np.zeros(3)}, {"w": np.zeros(3)}
+    for t in range(1, 13):
+        p, m, v = mlp.adam(p, g, m, v, t, lr=0.01)
+        step = 0.01 * g["w"] / (np.abs(g["w"]) + 1e-8)
+        assert np.allclose(p["w"], p0["w"] - t * step, rtol=0, atol=1e-13), t
+
+
+def test_cosine_schedule_values():
+    assert mlp.cosine_lr(2e-3, 1, 100) == 2e-3
+    assert abs(mlp.cosine_lr(2e-3, 51, 100) - 1e-3) < 1e-18          # half way: lr0 / 2
+    assert abs(mlp.cosine_lr(2e-3, 26, 100) - 1e-3 * (1 + math.sqrt(0.5))) < 1e-15
+    assert 0 < mlp.cosine_lr(2e-3, 100, 100) < 2e-3 * 1e-3
+
+
+def test_full_batch_training_lowers_the_loss():
+    rng = np.random.default_rng(4)
+    p = mlp.init_params(20, 6, seed=2)
+    X = rng.standard_normal((64, 20))
+    T = np.tanh(X[:, :6] - 0.5 * X[:, 6:12])
+    p1, losses = mlp.train_full_batch(p, X, T, 60, 3e-3, emulate=False)
+    assert losses[-1] < 0.5 * losses[0]
+    # one step equals one explicit forward / backward / Adam step at the schedule's first rate
+    q, l1 = mlp.train_full_batch(p, X, T, 1, 3e-3, total_steps=60, emulate=False)
+    Y, cache = mlp.forward(p, X)
+    loss, dY = mlp.mse(Y, T)
+    g = mlp.backward(p, cache, dY)
+    z = {k: np.zeros_like(v) for k, v in p.items()}
+    r, _, _ = mlp.adam(p, g, z, z, 1, lr=3e-3)
+    assert l1[0] == loss and all(np.array_equal(q[k], r[k]) for k in p)

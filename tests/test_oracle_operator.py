@@ -253,3 +253,142 @@ def test_3d_harmonic_reproduction():
     b = assemble.assemble_rhs(m, f=np.zeros(m.N), gN=gN, gD=u(X[dn], Y[dn], Z[dn]), A_full=A_full)
     uh = assemble.solve_direct(A, b)
     assert np.abs(uh - u(X, Y, Z)).max() < 1e-12
+
+
+# ---- 3D sigma-mapped geometry --------------------------------------------------------------
+def _wavy_3d(Nx, Ny, Nz, P, Lx=1.7, Ly=1.3, swap=False):
+    """A sigma-mapped 3D mesh whose depth and surface vary along x and y (non-zero h_x, h_y,
+    eta_x, eta_y).  swap=True builds the mirror mesh with the roles of x and y exchanged."""
+    def h(x, y):
+        return 0.6 + 0.15 * np.sin(1.3 * x + 0.4) * np.cos(0.9 * y - 0.2) + 0.05 * y
+
+    def eta(x, y):
+        return 0.04 * np.sin(2.1 * x - 1.7 * y + 0.3) + 0.02 * np.cos(3.0 * y)
+
+    if swap:
+        Nx, Ny, Lx, Ly = Ny, Nx, Ly, Lx
+        hf, ef = (lambda x, y: h(y, x)), (lambda x, y: eta(y, x))
+    else:
+        hf, ef = h, eta
+    xs = oc.fine_x_nodes(Nx, P, Lx)
+    ys = oc.fine_x_nodes(Ny, P, Ly)
+    Xh, Yh = np.meshgrid(xs, ys, indexing="ij")
+    return mesh.Mesh3D(Nx, Ny, Nz, P, Lx, Ly, hf(Xh, Yh), ef(Xh, Yh))
+
+
+def iso_factors_3d(m):
+    """w |J| (grad a . grad b) for a, b in (r, t, s) from the isoparametric map of the nodal
+    (x, y, z): the Jacobian from differentiating the nodal coordinates with D, inverted per
+    node (its rows are grad r, grad t, grad s)."""
+    D = m.D
+    sh = (m.E, m.NP, m.NP, m.NP)
+    crd = [m.X.reshape(sh), m.Y.reshape(sh), m.Z.reshape(sh)]
+    J = np.empty(sh + (3, 3))
+    for c, F in enumerate(crd):
+        J[..., c, 0] = np.einsum("ia,eamj->eimj", D, F)   # d/dr (element-local axis i)
+        J[..., c, 1] = np.einsum("ma,eiaj->eimj", D, F)   # d/dt (axis m)
+        J[..., c, 2] = np.einsum("ja,eima->eimj", D, F)   # d/ds (axis j)
+    det = np.linalg.det(J)
+    Ji = np.linalg.inv(J)            # Ji[..., a, :] = grad of reference coordinate a
+    w3 = m.w[:, None, None] * m.w[None, :, None] * m.w[None, None, :]
+    wj = w3[None] * det
+    G = {}
+    names = "rts"
+    for a in range(3):
+        for b in range(a, 3):
+            G[names[a] + names[b]] = wj * np.einsum("...k,...k->...", Ji[..., a, :], Ji[..., b, :])
+    return G, wj
+
+
+@pytest.mark.parametrize("P", [2, 4, 6])
+def test_3d_geometric_factors_match_isoparametric(P):
+    m = _wavy_3d(3, 2, 2, P)
+    # the mesh really is sigma-mapped along both horizontal directions
+    assert np.abs(m.hx).max() > 0.05 and np.abs(m.hy).max() > 0.05
+    assert np.abs(m.dxd - m.hx).max() > 0.01 and np.abs(m.dyd - m.hy).max() > 0.01
+    G, wj = iso_factors_3d(m)
+    sc = max(np.abs(m.Gss).max(), np.abs(m.Grr).max())
+    for nm, ours in (("rr", m.Grr), ("tt", m.Gtt), ("rs", m.Grs), ("ts", m.Gts), ("ss", m.Gss)):
+        assert np.abs(G[nm] - ours).max() < 1e-12 * sc, nm
+    assert np.abs(G["rt"]).max() < 1e-12 * sc          # x and y affine: no r-t coupling
+    assert np.abs(wj - m.mass).max() < 1e-14 * np.abs(m.mass).max() * 100
+
+
+def test_3d_operator_invariant_under_xy_transposition():
+    """Exchanging the roles of x and y (depth and surface mirrored) permutes the nodes and must
+    leave the operator unchanged: catches an h_x / h_y or eta_x / eta_y mix-up."""
+    Nx, Ny, Nz, P = 3, 2, 2, 3
+    a = _wavy_3d(Nx, Ny, Nz, P)
+    b = _wavy_3d(Nx, Ny, Nz, P, swap=True)
+    Aa = assemble.assemble_operator(a).toarray()
+    Ab = assemble.assemble_operator(b).toarray()
+    nx, ny, nz = a.nx_nodes, a.ny_nodes, a.nz_nodes
+    ix, iy, iz = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="ij")
+    ga = ((ix * ny + iy) * nz + iz).ravel()
+    gb = ((iy * nx + ix) * nz + iz).ravel()           # the same physical node in mesh b
+    perm = np.empty(a.N, dtype=np.int64)
+    perm[ga] = gb
+    assert np.abs(Aa - Ab[np.ix_(perm, perm)]).max() < 1e-12 * np.abs(Aa).max()
+
+
+def test_3d_y_uniform_reduces_to_2d():
+    """With depth and surface independent of y, every x-sigma section of the 3D factors is the
+    2D mesh's factor times the y quadrature weight w_m dy/2 (and the y couplings vanish)."""
+    Nx, Ny, Nz, P, Lx, Ly = 3, 2, 2, 5, 1.9, 0.8
+
+    def h(x):
+        return 0.5 + 0.2 * np.sin(1.7 * x)
+
+    def eta(x):
+        return 0.03 * np.cos(2.3 * x + 0.1)
+
+    xs = oc.fine_x_nodes(Nx, P, Lx)
+    ys = oc.fine_x_nodes(Ny, P, Ly)
+    Xh, _ = np.meshgrid(xs, ys, indexing="ij")
+    m3 = mesh.Mesh3D(Nx, Ny, Nz, P, Lx, Ly, h(Xh), eta(Xh))
+    m2 = mesh.Mesh2D(Nx, Nz, P, Lx, h(xs), eta(xs))
+    NP = P + 1
+    s3 = (Nx, Ny, Nz, NP, NP, NP)
+    wy = (m3.w * Ly / Ny / 2.0)[None, None, None, None, :, None]
+
+    def as3(g2):   # (E2, NP, NP) -> (Nx, 1, Nz, NP, 1, NP)
+        return g2.reshape(Nx, Nz, NP, NP)[:, None, :, :, None, :]
+
+    for f3, f2 in ((m3.Grr, m2.Grr), (m3.Grs, m2.Grs), (m3.Gss, m2.Gss), (m3.mass, m2.mass)):
+        ref = as3(f2) * wy
+        assert np.abs(f3.reshape(s3) - ref).max() < 1e-13 * np.abs(ref).max()
+    assert np.abs(m3.Gts).max() < 1e-14 * np.abs(m3.Gss).max()
+
+
+def test_3d_sigma_mapped_manufactured_convergence():
+    """u = cos(kx x) cos(ky y) cosh(k (z + h0)), k^2 = kx^2 + ky^2 (harmonic), on a flat-bottomed
+    box under a free surface that varies in x and y: Dirichlet data on the surface, zero normal
+    derivative on the walls (kx = pi / Lx, ky = pi / Ly) and on the bottom z = -h0; the nodal
+    error must decay geometrically in P (a wrong sigma_x or sigma_y term leaves an O(eta) error
+    that does not decay)."""
+    Lx, Ly, h0 = 2.0, 1.5, 0.5
+    kx, ky = math.pi / Lx, math.pi / Ly
+    k = math.hypot(kx, ky)
+
+    def u(x, y, z):
+        return np.cos(kx * x) * np.cos(ky * y) * np.cosh(k * (z + h0))
+
+    errs = []
+    for P in (2, 3, 4, 5, 6):
+        xs = oc.fine_x_nodes(2, P, Lx)
+        ys = oc.fine_x_nodes(2, P, Ly)
+        Xh, Yh = np.meshgrid(xs, ys, indexing="ij")
+        eta = 0.04 * np.sin(2 * math.pi * Xh / Lx + 0.3) * np.cos(2 * math.pi * Yh / Ly - 0.5)
+        m = mesh.Mesh3D(2, 2, 1, P, Lx, Ly, np.full_like(Xh, h0), eta)
+        assert np.abs(m.dxd).max() > 0.05 and np.abs(m.dyd).max() > 0.05
+        A_full = assemble.assemble_stiffness(m)
+        A = assemble.masked(A_full, m.dirichlet_nodes())
+        X, Y, Z = m.node_coords()
+        dn = m.dirichlet_nodes()
+        b = assemble.assemble_rhs(m, f=np.zeros(m.N), gD=u(X[dn], Y[dn], Z[dn]), A_full=A_full)
+        uh = assemble.solve_direct(A, b)
+        errs.append(np.abs(uh - u(X, Y, Z)).max())
+    # measured: 2.8e-2, 2.7e-3, 3.8e-4, 8.2e-5, 1.3e-5
+    assert errs[-1] < 3e-5, errs
+    assert all(errs[i + 1] < 0.3 * errs[i] for i in range(len(errs) - 1)), errs
+    assert errs[-1] < 1e-3 * errs[0], errs

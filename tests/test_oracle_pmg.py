@@ -362,3 +362,80 @@ def test_gmres_with_vcycle_on_tank():
     assert hg[-1] <= 1e-10
     assert np.linalg.norm(xg - xs) <= 1e-8 * np.linalg.norm(xs)
     assert itg <= itc
+
+
+def test_vcycle_stage_placements():
+    """The two stage positions of the V-cycle (used by the learned stage): ``hook`` acts after the
+    finest pre-smoothing, before the residual that is restricted; ``hook_post`` after the coarse
+    correction is added, before the post-smoothing.  Checked through the V-cycle's affine
+    structure: a stage that adds a fixed vector v changes the result by the post-smoothing's error
+    propagation applied to v (after the post position), or to v minus its coarse-grid correction
+    (after the pre position); a stage that returns the exact solution makes B = A^-1."""
+    wl, H = _tank(Nx=3, Nz=2, P=4)
+    pmg.estimate_lambdas(H)
+    L0 = H.levels[0]
+    rng = np.random.default_rng(3)
+    b = rng.standard_normal(L0.N)
+    b[L0.dn] = 0.0
+    v = rng.standard_normal(L0.N)
+    v[L0.dn] = 0.0
+    z0 = H.vcycle(b)
+    zero = np.zeros(L0.N)
+
+    def post_smooth_error(e):          # post-smoothing of x = e with b = 0
+        return H.smooth(0, zero, e, pre=False)
+
+    seen = {}
+
+    def add_pre(l, bb, x):
+        if l == 0:
+            seen["pre"] = x.copy()
+            return x + v
+        return x
+
+    def add_post(l, bb, x):
+        if l == 0:
+            seen["post"] = x.copy()
+            return x + v
+        return x
+
+    z_post = H.vcycle(b, hook_post=add_post)
+    assert np.abs(z_post - (z0 + post_smooth_error(v))).max() < 1e-12 * np.abs(z0).max()
+    z_pre = H.vcycle(b, hook=add_pre)
+    ec = H.vcycle(H.restrict(0, L0.A @ v), 1)
+    ref = z0 + post_smooth_error(v - H.prolong(0, ec))
+    assert np.abs(z_pre - ref).max() < 1e-12 * np.abs(z0).max()
+    assert np.abs(seen["pre"] - H.smooth(0, b, zero, pre=True)).max() < 1e-14 * np.abs(b).max()
+    # the post position sees the pre-smoothed iterate plus the prolonged coarse correction
+    xpre = H.smooth(0, b, zero, pre=True)
+    ecb = H.vcycle(H.restrict(0, b - L0.A @ xpre), 1)
+    assert np.abs(seen["post"] - (xpre + H.prolong(0, ecb))).max() < 1e-12 * np.abs(z0).max()
+    xs = spla.spsolve(L0.A.tocsc(), b)
+    for kw in ("hook", "hook_post"):
+        z = H.vcycle(b, **{kw: (lambda l, bb, x: xs if l == 0 else x)})
+        assert np.abs(z - xs).max() < 1e-10 * np.abs(xs).max(), kw
+    # identity stages leave the V-cycle unchanged
+    ident = (lambda l, bb, x: x)
+    assert np.array_equal(H.vcycle(b, hook=ident, hook_post=ident), z0)
+
+
+def test_stored_factor_rounding_levels():
+    """gstore rounds the factors of every level above the coarsest (the coarsest stays exact), and
+    the operator built from them differs from the exact one by the rounding's relative size."""
+    from oracle import precision
+    wl = W.tank(4, 2, 4, Lx=0.4)
+    He = oc.hierarchy(wl)
+    Hb = oc.hierarchy(wl, gstore="bf16")
+    Hf = oc.hierarchy(wl, gstore="f32")
+    for l in range(len(He.levels)):
+        Ae, Ab, Af = He.levels[l].A, Hb.levels[l].A, Hf.levels[l].A
+        d = abs(Ab - Ae).max() / abs(Ae).max()
+        df = abs(Af - Ae).max() / abs(Ae).max()
+        if l == len(He.levels) - 1:
+            assert d == 0 and df == 0
+        else:
+            assert 1e-5 < d < 2 ** -7 * 4 and 0 < df < 1e-6
+    m = Hb.levels[0].mesh
+    mb = precision.with_stored_factors(m, "bf16")
+    assert np.array_equal(mb.Grs, precision.bf16(m.Grs)) and mb.Grs is not m.Grs
+    assert mb.mass is m.mass and np.array_equal(m.Grs, He.levels[0].mesh.Grs)
