@@ -214,9 +214,14 @@ sem_status sem_coarse_solve(sem_ctx *ctx, const double *b, double *x);
  * kind 0: the level's inner-precision operator; kind 1: the fine-level FP64 operator of the
  * outer loop (level 0 only); kind 2: the level's fused smoother step (operator and Chebyshev
  * update in one kernel, 2D levels where it fits, else SEM_ERR_ARG), with d read and written.
- * flush = 1 overwrites a 512 MiB device buffer before every launch (cold caches) and times
- * each launch separately.  Inputs are the level's own work vectors, which are overwritten;
- * results are discarded.  Synchronises the stream. */
+ * flush = 0 times back-to-back launches on the same buffers (whose data then stays in the
+ * 256 MB Infinity Cache when it fits); flush = 1 overwrites a 512 MiB device buffer before every
+ * launch (cold caches) and times each launch separately (event overhead included); flush = 2
+ * makes R copies of every buffer the kernel reads or writes (R of them exceed 768 MiB, R <= 64;
+ * allocated for the call and freed before it returns) and times at least 2R back-to-back
+ * launches that take the copies in turn, so each launch streams its data from HBM.  Inputs are
+ * the level's own work vectors, which are overwritten; results are discarded.  Synchronises the
+ * stream. */
 sem_status sem_time_operator(sem_ctx *ctx, int level, int kind, int reps, int flush,
                              double *ms_avg);
 
@@ -224,6 +229,13 @@ sem_status sem_time_operator(sem_ctx *ctx, int level, int kind, int reps, int fl
  * once, every geometric factor read once): kind 0, 1: x read, y written; kind 2: x, b, dinv, d
  * read, x, d written; plus the factors in their storage precision. */
 sem_status sem_operator_bytes(const sem_ctx *ctx, int level, int kind, double *bytes);
+
+/* Test hook: launch shape of level l's 2D kernels.  *cols_per_block: element columns owned by
+ * one workgroup of the fused smoother step in the level's precision (0: the level has no fused
+ * step: 3D, the coarsest level, or columns too tall for one workgroup); *coarse_w: owned columns
+ * per workgroup of the one-kernel pre-smoothing of a coarse level (level >= 1; 0: per-step
+ * kernels).  Either pointer may be NULL.  SEM_ERR_ARG for a NULL context or a bad level. */
+sem_status sem_launch_shape(const sem_ctx *ctx, int level, int *cols_per_block, int *coarse_w);
 
 /* ---- learned smoothing stage (not in the paper; an addition beside the method) -------------
  * An element-local MLP maps each element's restricted residual r_e = R_e r (R_e: the element
@@ -277,6 +289,11 @@ sem_status sem_learned_enable(sem_ctx *ctx, int enable);
 /* Test hook: one learned stage on the fine level for b, x (device FP64, x updated in place);
  * *accepted = 1 if the step was taken. */
 sem_status sem_learned_stage(sem_ctx *ctx, const double *b, double *x, int *accepted);
+
+/* Number of learned-stage applications the judge rejected since the last reset (solves reset
+ * it on entry; sem_pmg_vcycle and sem_learned_stage do not).  reset != 0 sets it to zero after
+ * reading.  SEM_ERR_STATE if no network was ever loaded. */
+sem_status sem_learned_skips(sem_ctx *ctx, int *skips, int reset);
 
 /* Text of the last error on this context ("" if none).  Valid until the next call. */
 const char *sem_last_error(const sem_ctx *ctx);

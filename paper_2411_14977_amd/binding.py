@@ -109,6 +109,9 @@ def lib():
         "sem_mesh_update_surface": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]),
         "sem_learned_enable": (ctypes.c_int, [vp, ip]),
         "sem_learned_stage": (ctypes.c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int)]),
+        "sem_learned_skips": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ip]),
+        "sem_launch_shape": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_int)]),
         "sem_last_error": (ctypes.c_char_p, [vp]),
         "sem_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -313,6 +316,19 @@ def sem_learned_stage(ctx, b, x):
     acc = ctypes.c_int()
     _check(ctx, lib().sem_learned_stage(ctx, _ptr(b), _ptr(x), ctypes.byref(acc)))
     return bool(acc.value)
+
+
+def sem_learned_skips(ctx, reset=False):
+    k = ctypes.c_int()
+    _check(ctx, lib().sem_learned_skips(ctx, ctypes.byref(k), 1 if reset else 0))
+    return k.value
+
+
+def sem_launch_shape(ctx, level):
+    """(fused smoother step columns per workgroup, one-kernel coarse smoothing window)."""
+    a, b = ctypes.c_int(), ctypes.c_int()
+    _check(ctx, lib().sem_launch_shape(ctx, level, ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
 
 
 def blob_pack(nin, nout, W1, b1, W2, b2, W3, b3, seed=0):

@@ -20,6 +20,7 @@
 #include <cstring>
 #include <functional>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/sem.h"
@@ -126,6 +127,7 @@ struct Ctx {
   std::string err;
   bool sticky = false;
   std::vector<void*> allocs;
+  std::unordered_map<const void*, size_t> asize;  // bytes of every allocation in allocs
 };
 
 enum { PS_RR = 0, PS_BB, PS_PQ, PS_RZA, PS_RZB, PS_ZQ, PS_TMP, PS_PQ2, PS_NSETS };
@@ -151,6 +153,7 @@ void* dalloc(Ctx* c, size_t bytes) {
   hipError_t e = hipMalloc(&p, bytes);
   if (e != hipSuccess) throw HipFail{e, "hipMalloc"};
   c->allocs.push_back(p);
+  c->asize[p] = bytes;
   HK(hipMemsetAsync(p, 0, bytes, c->st));
   return p;
 }
@@ -1224,6 +1227,10 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   const char* ng = std::getenv("SEM_NO_GRAPH");
   c->use_graphs = !(ng && ng[0] == '1');
 
+  // SEM_NO_FUSED_STEP=1: every 2D smoother step as operator + element-wise update (the fused
+  // step, its two-step entry form and the one-kernel coarse smoothing are then not used)
+  const char* nfs = std::getenv("SEM_NO_FUSED_STEP");
+  const bool no_fused_step = nfs && nfs[0] == '1';
   const int nl = (int)orders.size();
   c->lev.resize(nl);
   for (int l = 0; l < nl; ++l) {
@@ -1266,7 +1273,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     L.y = dalloc(c, L.N * eb);
     L.nS = (size_t)(c->Nx + 1) * L.nzn;
     L.S = dalloc(c, L.nS * eb);
-    if (!coarsest && L.P <= 8 && semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl) > 0)
+    if (!coarsest && L.P <= 8 && semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl) > 0 && !no_fused_step)
       L.xalt = dalloc(c, L.N * eb);
     if (!coarsest && d->smoother == SEM_SMOOTH_SCHWARZ) {
       const size_t n = (size_t)L.NP * L.NP;
@@ -2361,6 +2368,35 @@ sem_status sem_learned_enable(sem_ctx* ctx, int enable) {
   });
 }
 
+sem_status sem_learned_skips(sem_ctx* ctx, int* skips, int reset) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!c->stage_alloc) return SEM_ERR_STATE;
+    int k = 0;
+    HK(hipMemcpyAsync(&k, c->stage.skips, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HK(hipStreamSynchronize(c->st));
+    if (skips) *skips = k;
+    if (reset) {
+      HK(hipMemsetAsync(c->stage.skips, 0, sizeof(int), c->st));
+      HK(hipStreamSynchronize(c->st));
+    }
+    return SEM_OK;
+  });
+}
+
+sem_status sem_launch_shape(const sem_ctx* ctx, int level, int* cols_per_block, int* coarse_w) {
+  const Ctx* c = C(ctx);
+  if (!c) return SEM_ERR_ARG;
+  if (level < 0 || level >= (int)c->lev.size()) return SEM_ERR_ARG;
+  const DLevel& L = c->lev[level];
+  const bool smoothed = level + 1 < (int)c->lev.size();
+  if (cols_per_block)
+    *cols_per_block = (c->dim == 2 && smoothed && L.xalt) ? semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl)
+                                                         : 0;
+  if (coarse_w) *coarse_w = (c->dim == 2 && smoothed && level >= 1) ? L.cpre.W : 0;
+  return SEM_OK;
+}
+
 sem_status sem_learned_features(sem_ctx* ctx, const double* r, const double* e, float* X,
                                 float* T) {
   Ctx* c = C(ctx);
@@ -2420,34 +2456,106 @@ sem_status sem_time_operator(sem_ctx* ctx, int level, int kind, int reps, int fl
     HK(hipEventCreate(&e1));
     void* junk = nullptr;
     const size_t fbytes = (size_t)512 << 20;
-    if (flush) HK(hipMalloc(&junk, fbytes));
+    if (flush == 1) HK(hipMalloc(&junk, fbytes));
     double total = 0.0;
     auto launch = [&]() {
       if (kind == 1) apply_outer(c, c->po, c->masked);
       else if (kind == 2) smooth_step(c, level, 0.5, 1e-3, 1);
       else apply_level(c, level, L.x, c->masked);
     };
-    launch();  // warm-up
-    if (!flush) {
-      HK(hipEventRecord(e0, c->st));
-      for (int k = 0; k < reps; ++k) launch();
-      HK(hipEventRecord(e1, c->st));
-      HK(hipEventSynchronize(e1));
-      float ms = 0;
-      HK(hipEventElapsedTime(&ms, e0, e1));
-      total = ms;
+    // flush == 2: every buffer the kernel reads or writes in R copies whose total exceeds three
+    // times the 256 MB Infinity Cache, launched back to back in turn, so each launch streams its
+    // data from HBM (the copies hold the same values, so the work is the same)
+    std::vector<void**> slots;
+    if (kind == 1) {
+      slots = {(void**)&c->po, (void**)&c->yo, (void**)&c->G64};
+      if (c->dim == 3) slots.insert(slots.end(), {(void**)&c->Sxo, (void**)&c->Syo, (void**)&c->Sxyo});
+      else slots.push_back((void**)&c->So);
+    } else if (kind == 2) {
+      slots = {&L.x, &L.xalt, &L.b, &L.dinv, &L.d, &L.G};
     } else {
-      for (int k = 0; k < reps; ++k) {
-        HK(semk::fill(true, junk, (double)k, fbytes / 8, c->st));
+      slots = {&L.x, &L.y, &L.G};
+      if (c->dim == 3) slots.insert(slots.end(), {&L.Sx, &L.Sy, &L.Sxy});
+      else slots.push_back(&L.S);
+    }
+    std::vector<void*> orig;
+    std::vector<size_t> sz;
+    size_t set_bytes = 0;
+    for (void** sl : slots) {
+      orig.push_back(*sl);
+      auto it = c->asize.find(*sl);
+      if (!*sl || it == c->asize.end()) throw ArgFail{"buffer of the timed kernel not found"};
+      sz.push_back(it->second);
+      set_bytes += it->second;
+    }
+    int R = 1;
+    std::vector<void*> rep;  // (R - 1) x slots copies
+    auto restore = [&]() {
+      for (size_t q = 0; q < slots.size(); ++q) *slots[q] = orig[q];
+    };
+    auto use = [&](int k) {
+      for (size_t q = 0; q < slots.size(); ++q)
+        *slots[q] = k == 0 ? orig[q] : rep[(size_t)(k - 1) * slots.size() + q];
+    };
+    auto free_rep = [&]() {
+      restore();
+      for (void* p : rep) (void)hipFree(p);
+      rep.clear();
+    };
+    if (flush == 2) {
+      const size_t want = (size_t)768 << 20;
+      R = (int)std::min<size_t>(64, (want + set_bytes - 1) / set_bytes);
+      R = std::max(R, 2);
+      for (int k = 1; k < R; ++k)
+        for (size_t q = 0; q < slots.size(); ++q) {
+          void* p = nullptr;
+          if (hipMalloc(&p, sz[q]) != hipSuccess) {
+            free_rep();
+            throw ArgFail{"not enough device memory for the rotated buffers"};
+          }
+          rep.push_back(p);
+          HK(hipMemcpyAsync(p, orig[q], sz[q], hipMemcpyDeviceToDevice, c->st));
+        }
+      reps = std::max(reps, 2 * R);
+    }
+    try {
+      launch();  // warm-up
+      if (flush != 1) {
+        if (flush == 2) {
+          for (int k = 0; k < R; ++k) {  // one untimed pass over every copy
+            use(k);
+            launch();
+          }
+        }
         HK(hipEventRecord(e0, c->st));
-        launch();
+        for (int k = 0; k < reps; ++k) {
+          if (flush == 2) use(k % R);
+          launch();
+        }
         HK(hipEventRecord(e1, c->st));
         HK(hipEventSynchronize(e1));
         float ms = 0;
         HK(hipEventElapsedTime(&ms, e0, e1));
-        total += ms;
+        total = ms;
+      } else {
+        for (int k = 0; k < reps; ++k) {
+          HK(semk::fill(true, junk, (double)k, fbytes / 8, c->st));
+          HK(hipEventRecord(e0, c->st));
+          launch();
+          HK(hipEventRecord(e1, c->st));
+          HK(hipEventSynchronize(e1));
+          float ms = 0;
+          HK(hipEventElapsedTime(&ms, e0, e1));
+          total += ms;
+        }
       }
+    } catch (...) {
+      HK(hipStreamSynchronize(c->st));
+      free_rep();
+      throw;
     }
+    HK(hipStreamSynchronize(c->st));
+    free_rep();
     if (junk) HK(hipFree(junk));
     HK(hipEventDestroy(e0));
     HK(hipEventDestroy(e1));
