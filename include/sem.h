@@ -279,6 +279,16 @@ sem_status sem_mlp_forward(const void *blob, size_t nbytes, const float *X, int 
 sem_status sem_mlp_gradients(const void *blob, size_t nbytes, const float *X, const float *T,
                              int n, float *grads, float *loss);
 
+/* sem_mlp_forward for callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): the same kernels and the same results, with
+ * the network and the activations of one 256-row chunk held in a fixed device array of the
+ * library (about 1.2 MB, one copy per GPU, kept until the process ends) instead of buffers
+ * allocated per call.  The call allocates nothing and frees nothing; it runs on the null stream
+ * and synchronises it.  Limits: nin <= 416 and nout <= 96 (SEM_ERR_ARG beyond), any n >= 1.
+ * Every call on one GPU uses that GPU's array: calls that overlap on one GPU race. */
+sem_status sem_mlp_forward_noalloc(const void *blob, size_t nbytes, const float *X, int n,
+                                   float *Y);
+
 /* Load a network blob (host) into the context (nin = 5n, nout = n of the fine level, P <= 8) and
  * set where the stage acts: enable = 0 off, bit 0 (1) after the finest pre-smoothing, bit 1 (2)
  * before the finest post-smoothing (3 = both, keeping the V-cycle close to symmetric for the

@@ -102,6 +102,7 @@ def lib():
         "sem_mlp_train": (ctypes.c_int, [dp, dp, ip, ip, ip, ctypes.POINTER(TrainCfg), vp,
                                          ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)]),
         "sem_mlp_forward": (ctypes.c_int, [vp, ctypes.c_size_t, dp, ip, dp]),
+        "sem_mlp_forward_noalloc": (ctypes.c_int, [vp, ctypes.c_size_t, dp, ip, dp]),
         "sem_mlp_gradients": (ctypes.c_int, [vp, ctypes.c_size_t, dp, dp, ip,
                                              ctypes.POINTER(ctypes.c_float),
                                              ctypes.POINTER(ctypes.c_float)]),
@@ -285,6 +286,15 @@ def sem_mlp_forward(blob, X, nout):
     import torch
     Y = torch.zeros(X.shape[0], nout, dtype=torch.float32, device=X.device)
     _check(None, lib().sem_mlp_forward(blob, len(blob), _ptr32(X), X.shape[0], _ptr32(Y)))
+    return Y
+
+
+def sem_mlp_forward_noalloc(blob, X, nout, Y=None):
+    """The allocation-free forward: Y [n x nout] into a caller tensor (allocated here if None)."""
+    import torch
+    if Y is None:
+        Y = torch.zeros(X.shape[0], nout, dtype=torch.float32, device=X.device)
+    _check(None, lib().sem_mlp_forward_noalloc(blob, len(blob), _ptr32(X), X.shape[0], _ptr32(Y)))
     return Y
 
 

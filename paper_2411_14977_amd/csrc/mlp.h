@@ -59,6 +59,14 @@ bool forward(const Net& net, const float* X, int n, float* Y, hipStream_t st, st
 bool gradients(const Net& net, const float* X, const float* T, int n, float* grads, float* loss,
                hipStream_t st, std::string& err);
 
+// The same forward with no device allocation: the network and the activations of one chunk of
+// 256 rows sit in a file-scope device array of forward_noalloc_bytes() bytes (one per GPU, kept
+// until the process ends).  nin <= 416, nout <= 96.  Runs on the null stream and synchronises
+// it; two calls that overlap on one GPU use the same array and race.
+bool forward_noalloc(const void* blob, size_t nbytes, const float* X, int n, float* Y,
+                     std::string& err);
+size_t forward_noalloc_bytes();
+
 // ---- inference state of one solver context (2D element columns) ----------------------------
 struct Stage {
   bool enabled = false;

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <type_traits>
 
 #include "host_math.h"
@@ -1120,6 +1121,130 @@ hipError_t features(const double* r, const double* e, const double* Ainv, const 
   hipLaunchKernelGGL(k_features, dim3((unsigned)E), dim3(128), 0, st, r, e, Ainv, geo, abar, X, T,
                      P, Nz, nzn);
   return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// batched forward without any device allocation: the network and one chunk of activations live
+// in a file-scope device array (one copy per GPU, alive until the process ends)
+// ------------------------------------------------------------------------------------------
+namespace {
+
+constexpr int NA_ROWS = 256;                  // rows per chunk
+constexpr int NA_K1 = 416, NA_N3 = 96;        // padded input / output widths at the limits
+constexpr size_t NA_BODY = (size_t)NA_K1 * NH + NH + (size_t)NH * NH + NH + (size_t)NH * NA_N3 + NA_N3;
+
+constexpr size_t na_align(size_t b) { return (b + 255) / 256 * 256; }
+// byte offsets of the regions of the array
+constexpr size_t NA_OFF_BODY = 0;                                               // fp32 parameters
+constexpr size_t NA_OFF_W1B = NA_OFF_BODY + na_align(NA_BODY * 4);              // bf16 [K1][NH]
+constexpr size_t NA_OFF_W2B = NA_OFF_W1B + na_align((size_t)NA_K1 * NH * 2);    // bf16 [NH][NH]
+constexpr size_t NA_OFF_W3B = NA_OFF_W2B + na_align((size_t)NH * NH * 2);       // bf16 [NH][N3]
+constexpr size_t NA_OFF_IDX = NA_OFF_W3B + na_align((size_t)NH * NA_N3 * 2);    // int [K1 >= rows]
+constexpr size_t NA_OFF_XB = NA_OFF_IDX + na_align((size_t)NA_K1 * 4);          // bf16 [rows][K1]
+constexpr size_t NA_OFF_Z1 = NA_OFF_XB + na_align((size_t)NA_ROWS * NA_K1 * 2); // fp32 [rows][NH]
+constexpr size_t NA_OFF_Z2 = NA_OFF_Z1 + na_align((size_t)NA_ROWS * NH * 4);
+constexpr size_t NA_OFF_H1 = NA_OFF_Z2 + na_align((size_t)NA_ROWS * NH * 4);    // bf16 [rows][NH]
+constexpr size_t NA_OFF_H2 = NA_OFF_H1 + na_align((size_t)NA_ROWS * NH * 2);
+constexpr size_t NA_OFF_Y = NA_OFF_H2 + na_align((size_t)NA_ROWS * NH * 2);     // fp32 [rows][N3]
+constexpr size_t NA_BYTES = NA_OFF_Y + na_align((size_t)NA_ROWS * NA_N3 * 4);
+static_assert(NA_K1 >= NA_ROWS, "the row-index region also holds the K1 rows of W1");
+
+// every byte a launch reads is written earlier in the same call, so nothing needs clearing
+static __device__ __align__(256) unsigned char scratch[NA_BYTES];
+
+constexpr int NA_MAX_DEV = 64;
+std::mutex na_mu;
+void* na_ptr[NA_MAX_DEV] = {nullptr};
+
+// device address of this GPU's copy of the array (looked up once per device)
+bool na_scratch(unsigned char** out, std::string& err) {
+  int dev = 0;
+  CK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NA_MAX_DEV) { err = "device index out of range"; return false; }
+  std::lock_guard<std::mutex> g(na_mu);
+  if (!na_ptr[dev]) {
+    void* p = nullptr;
+    CK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) { err = "no device address for the scratch array"; return false; }
+    na_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(na_ptr[dev]);
+  return true;
+}
+
+// idx[r] = r < nv ? first + r : -1 for r < M (r < nv rows of the chunk, the rest padding)
+__global__ void k_chunk_rows(int* __restrict__ idx, int first, int nv, int M) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < M) idx[r] = r < nv ? first + r : -1;
+}
+
+}  // namespace
+
+size_t forward_noalloc_bytes() { return NA_BYTES; }
+
+bool forward_noalloc(const void* blob, size_t nbytes, const float* X, int n, float* Y,
+                     std::string& err) {
+  if (!blob || nbytes < sizeof(BlobHeader)) { err = "bad blob (too small)"; return false; }
+  BlobHeader h;
+  std::memcpy(&h, blob, sizeof h);
+  if (h.magic != kMagic || h.version != 1 || h.nh != (uint32_t)NH) { err = "bad blob (not a network)"; return false; }
+  if (h.nin < 1 || h.nout < 1 || pad16((int)h.nin) > NA_K1 || pad16((int)h.nout) > NA_N3) {
+    err = "bad sizes: the allocation-free forward takes nin <= 416 and nout <= 96";
+    return false;
+  }
+  if (nbytes != blob_size(h.nin, h.nout)) { err = "bad blob (size mismatch)"; return false; }
+  if (!X || !Y || n < 1) { err = "bad arguments"; return false; }
+  unsigned char* base = nullptr;
+  if (!na_scratch(&base, err)) return false;
+  const hipStream_t st = nullptr;
+  Params p;
+  p.nin = (int)h.nin;
+  p.nout = (int)h.nout;
+  p.K1 = pad16(p.nin);
+  p.N3 = pad16(p.nout);
+  float* body = reinterpret_cast<float*>(base + NA_OFF_BODY);
+  // the blob's parameters as they are (unpadded): W1 [nin][NH], b1, W2, b2, W3 [NH][nout], b3
+  p.W1 = body;
+  p.b1 = p.W1 + (size_t)p.nin * NH;
+  p.W2 = p.b1 + NH;
+  p.b2 = p.W2 + (size_t)NH * NH;
+  p.W3 = p.b2 + NH;
+  p.b3 = p.W3 + (size_t)NH * p.nout;
+  p.W1b = reinterpret_cast<uint16_t*>(base + NA_OFF_W1B);
+  p.W2b = reinterpret_cast<uint16_t*>(base + NA_OFF_W2B);
+  p.W3b = reinterpret_cast<uint16_t*>(base + NA_OFF_W3B);
+  Acts a{};
+  a.Bmax = NA_ROWS;
+  a.K1 = p.K1;
+  a.N3 = p.N3;
+  a.idx = reinterpret_cast<int*>(base + NA_OFF_IDX);
+  a.Xb = reinterpret_cast<uint16_t*>(base + NA_OFF_XB);
+  a.Z1 = reinterpret_cast<float*>(base + NA_OFF_Z1);
+  a.Z2 = reinterpret_cast<float*>(base + NA_OFF_Z2);
+  a.H1b = reinterpret_cast<uint16_t*>(base + NA_OFF_H1);
+  a.H2b = reinterpret_cast<uint16_t*>(base + NA_OFF_H2);
+  a.Y = reinterpret_cast<float*>(base + NA_OFF_Y);
+  const size_t np = (size_t)p.nin * NH + NH + (size_t)NH * NH + NH + (size_t)NH * p.nout + p.nout;
+  CK(hipMemcpy(body, (const char*)blob + sizeof h, np * sizeof(float), hipMemcpyHostToDevice));
+  // bf16 copies, zero-padded: W1 rows nin .. K1 - 1 through idx = -1, W3 columns nout .. N3 - 1
+  hipLaunchKernelGGL(k_chunk_rows, dim3(nblk(p.K1, 256)), dim3(256), 0, st, a.idx, 0, p.nin,
+                     p.K1);
+  CK(hipGetLastError());
+  CK(to_bf16_padded(p.W1, p.K1, NH, NH, p.W1b, NH, NH, a.idx, st));
+  CK(to_bf16_padded(p.W2, NH, NH, NH, p.W2b, NH, NH, nullptr, st));
+  CK(to_bf16_padded(p.W3, NH, p.nout, p.nout, p.W3b, p.N3, p.N3, nullptr, st));
+  for (int s0 = 0; s0 < n; s0 += NA_ROWS) {
+    const int nv = std::min(NA_ROWS, n - s0);
+    const int M = (nv + 15) / 16 * 16;
+    hipLaunchKernelGGL(k_chunk_rows, dim3(nblk(M, 256)), dim3(256), 0, st, a.idx, s0, nv, M);
+    CK(hipGetLastError());
+    if (!fwd(p, a, X, M, st, err)) return false;
+    hipLaunchKernelGGL(k_out_bias, dim3(nblk((size_t)nv * p.nout, 256)), dim3(256), 0, st, a.Y,
+                       p.N3, p.b3, nv, p.nout, Y + (size_t)s0 * p.nout);
+    CK(hipGetLastError());
+  }
+  CK(hipStreamSynchronize(st));
+  return true;
 }
 
 }  // namespace semm

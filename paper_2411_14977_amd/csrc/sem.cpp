@@ -2644,6 +2644,21 @@ sem_status sem_mlp_forward(const void* blob, size_t nbytes, const float* X, int 
   });
 }
 
+sem_status sem_mlp_forward_noalloc(const void* blob, size_t nbytes, const float* X, int n,
+                                   float* Y) {
+  try {
+    std::string e;  // stays empty (no allocation) unless the call fails
+    if (semm::forward_noalloc(blob, nbytes, X, n, Y, e)) {
+      g_mlp_err.clear();
+      return SEM_OK;
+    }
+    g_mlp_err = e;
+    return e.rfind("bad", 0) == 0 ? SEM_ERR_ARG : SEM_ERR_HIP;
+  } catch (...) {
+    return SEM_ERR_STATE;
+  }
+}
+
 sem_status sem_mlp_gradients(const void* blob, size_t nbytes, const float* X, const float* T,
                              int n, float* grads, float* loss) {
   return mlp_guard([&](std::string& e) {
