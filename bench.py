@@ -244,7 +244,7 @@ def c3_error_table():
 
 
 def schwarz_rows(wl, rhs, prec, steps):
-    """The paper's additive Schwarz smoother (element blocks, Sec. 6.3) in place of Chebyshev on
+    """The paper's additive Schwarz smoother (element blocks, Sec. 5.3) in place of Chebyshev on
     every level, same workload, precision and outer loop, 1 and 2 sweeps before and after."""
     import torch
 
@@ -263,7 +263,7 @@ def schwarz_rows(wl, rhs, prec, steps):
 
 
 def paper_context(prec):
-    """The paper's multigrid-efficiency experiments (Sec. 7, table of iterations per tolerance
+    """The paper's multigrid-efficiency experiments (Sec. 6, table of iterations per tolerance
     and the scaling figure) rerun with this solver on the synthetic tank: N_z = 2, P = 8,
     N_x = 102 at tolerances 1e-4, 1e-6, 1e-8 (PDC, FPCG and GMRES, the paper's two outer
     methods and this solver's default), then at 1e-6 the iterations and time against N_x

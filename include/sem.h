@@ -1,13 +1,13 @@
 /*
  * sem.h -- C ABI of the MI355X (gfx950) spectral-element pressure-Poisson solver.
  *
- * Problem (paper Sec. 4.2, eqs. poissonp / bcpd / bcpdneu, read in the same-stage symmetric
+ * Problem (paper Secs. 3.1-3.2, eqs. poissonp / bcpd / bcpdneu, read in the same-stage symmetric
  * form): find p with  -lap p = f  in the sigma-mapped fluid domain (Sec. 2.2, eq. sigtrans),
  * p = g_D on the free surface (top), n . grad p = g_N on walls and bottom.  Discretised with
- * nodal GLL spectral elements (Sec. 5, eqs. fglobal / flocal / flocal2 with GLL collocation)
- * and solved by geometric p-multigrid (Sec. 6: order hierarchy eq. gridcoars read as
- * ceil(P/2), interpolation/restriction of Sec. 6.2, V-cycle of Sec. 6) inside an FP64
- * flexible CG or preconditioned defect-correction loop (Sec. 6.4).
+ * nodal GLL spectral elements (Sec. 4, eqs. fglobal / flocal / flocal2 with GLL collocation)
+ * and solved by geometric p-multigrid (Sec. 5: order hierarchy eq. gridcoars read as
+ * ceil(P/2), interpolation/restriction of Sec. 5.2, V-cycle of Sec. 5) inside an FP64
+ * flexible CG or preconditioned defect-correction loop (Sec. 5.4).
  *
  * Conventions common to every call
  *  - Global vectors are FP64, contiguous, on the context's device, length n_global:
@@ -48,7 +48,7 @@ typedef enum {
 /* inner (V-cycle) precision */
 enum { SEM_F64 = 0, SEM_F32 = 1, SEM_F32_GBF16 = 2 };
 /* smoother on every level above the coarsest.  SEM_SMOOTH_SCHWARZ: the additive Schwarz
- * method of Sec. 6.3 with element blocks, nu_pre / nu_post sweeps of
+ * method of Sec. 5.3 with element blocks, nu_pre / nu_post sweeps of
  * x += W sum_i R_i^T (R_i A R_i^T)^{-1} R_i (b - A x), W = (sum_i R_i^T R_i)^{-1}; 2D meshes with
  * fine order P <= 8 only; the inverses of the element blocks are built at set-up (host FP64)
  * and stored per level in the inner precision (E (P_l+1)^4 values). */
@@ -89,7 +89,7 @@ typedef struct {
                                   (default 1200).  2D solves P = 1 exactly by block cyclic
                                   reduction and ignores it.                                   */
   int gmres_restart;           /* SEM_OUTER_GMRES: Arnoldi steps per cycle, 1..64
-                                  (default 30).  Right-preconditioned GMRES (Sec. 6.4 of the
+                                  (default 30).  Right-preconditioned GMRES (Sec. 5.4 of the
                                   paper names GMRES beside defect correction): per step one
                                   V-cycle z = B v, one FP64 operator apply and classical
                                   Gram-Schmidt applied twice; x += Z y at the end of a cycle;
@@ -147,7 +147,7 @@ sem_status sem_node_coords(const sem_ctx *ctx, int level, double *x, double *y, 
 
 /* New free surface for a time series.  The sigma transform follows eta (Sec. 2.2, eq. sigtrans),
  * so the operator's geometric factors change with it; the paper keeps the multigrid
- * preconditioner time-constant (Sec. 6.4).  eta: host array in the layout of sem_mesh_desc.eta
+ * preconditioner time-constant (Sec. 5.4).  eta: host array in the layout of sem_mesh_desc.eta
  * (copied).  The FP64 outer operator (sem_apply_laplacian, the outer iteration of
  * sem_poisson_solve), the lumped mass and the wall-face weights (sem_assemble_rhs) are rebuilt
  * for the new surface (in 3D on the device).  refresh_precond = 0 keeps every V-cycle level as
@@ -158,7 +158,7 @@ sem_status sem_node_coords(const sem_ctx *ctx, int level, double *x, double *y, 
 sem_status sem_mesh_update_surface(sem_ctx *ctx, const double *eta, int refresh_precond);
 
 /* y = A x on the fine level in FP64: the assembled GLL stiffness (sum of element matrices,
- * Sec. 5.2 eq. globallocal) of the symmetric sigma-Laplacian, restricted to free rows and
+ * Sec. 4.2 eq. globallocal) of the symmetric sigma-Laplacian, restricted to free rows and
  * columns, with identity rows on Dirichlet nodes (pure Neumann if dirichlet_faces = 0).
  * x, y: device, n_global doubles, must not alias. */
 sem_status sem_apply_laplacian(sem_ctx *ctx, const double *x, double *y);
@@ -167,8 +167,8 @@ sem_status sem_apply_laplacian(sem_ctx *ctx, const double *x, double *y);
  * result widened to FP64).  Test hook for the inner-precision apply. */
 sem_status sem_apply_level(sem_ctx *ctx, int level, const double *x, double *y);
 
-/* z = B r: one p-multigrid V-cycle (Sec. 6) from a zero initial guess in the inner precision:
- * pre-smoothing on every level above the coarsest, residual, restriction R = P^T (Sec. 6.2),
+/* z = B r: one p-multigrid V-cycle (Sec. 5) from a zero initial guess in the inner precision:
+ * pre-smoothing on every level above the coarsest, residual, restriction R = P^T (Sec. 5.2),
  * exact FP64 solve on P = 1, prolongation by interpolation, post-smoothing.  r, z: device,
  * n_global doubles; r must be zero on Dirichlet rows (z is then zero there). */
 sem_status sem_pmg_vcycle(sem_ctx *ctx, const double *r, double *z);
@@ -182,7 +182,7 @@ sem_status sem_pmg_vcycle(sem_ctx *ctx, const double *r, double *z);
 sem_status sem_poisson_solve(sem_ctx *ctx, const double *rhs, double *x, double tol,
                              sem_solve_info *info);
 
-/* rhs = M f + B g_N - A_fD g_D on free rows, rhs = g_D on Dirichlet rows (Sec. 5.2 eq.
+/* rhs = M f + B g_N - A_fD g_D on free rows, rhs = g_D on Dirichlet rows (Sec. 4.2 eq.
  * fsemidiscrete with the lumped GLL mass M and GLL face quadrature B).
  *   f   : device, n_global doubles (nodal source values) or NULL for f = 0
  *   gN  : device, per-face nodal values of n . grad p, packed faces in this order:
@@ -239,13 +239,13 @@ sem_status sem_launch_shape(const sem_ctx *ctx, int level, int *cols_per_block, 
 
 /* ---- learned smoothing stage (not in the paper; an addition beside the method) -------------
  * An element-local MLP maps each element's restricted residual r_e = R_e r (R_e: the element
- * restriction, the R_i of the paper's Schwarz smoother, Sec. 6.3) plus its geometric factors to a
+ * restriction, the R_i of the paper's Schwarz smoother, Sec. 5.3) plus its geometric factors to a
  * correction.  Features per element (n = (P+1)^2 nodes, local order i*(P+1)+j):
  *   [r_e / s_e, G_rr / g_e, G_rs / g_e, G_ss / g_e, m_e / mean(m_e)],  s_e = ||r_e||_2,
  *   g_e = mean over the element of (G_rr + G_ss);
  * network 5n -> 128 -> 128 -> n, exact-erf GELU on the hidden layers, BF16 operands with FP32
  * accumulation on the matrix cores; correction c = W sum_e R_e^T (s_e / a_e) y_e with a_e the
- * mean diagonal of the element matrix and W the averaging weight of Sec. 6.3, zero on the
+ * mean diagonal of the element matrix and W the averaging weight of Sec. 5.3, zero on the
  * surface.  In the V-cycle the stage runs on the finest level after pre-smoothing: q = A c,
  * alpha = c.r / c.q (energy-optimal), accepted if alpha > 0 and finite (x += alpha c: the A-norm
  * of the error never grows), otherwise skipped and counted in sem_solve_info.learned_skips.  Training pairs: target
@@ -259,7 +259,7 @@ size_t sem_mlp_blob_size(int nin, int nout);
 /* Training features of the fine level (2D, P <= 8): for an assembled residual r (device FP64,
  * n_global) write X [E x 5n] and, if T is given, targets T [E x n] (device FP32, row-major;
  * E = elements): with an error e, t_e = (a_e / s_e) R_e e; with e = NULL, the element-block solve
- * t_e = (a_e / s_e) (R_e A R_e^T)^{-1} R_e r (the local solve of the Schwarz smoother, Sec. 6.3;
+ * t_e = (a_e / s_e) (R_e A R_e^T)^{-1} R_e r (the local solve of the Schwarz smoother, Sec. 5.3;
  * meshes up to 4096 elements). */
 sem_status sem_learned_features(sem_ctx *ctx, const double *r, const double *e, float *X,
                                 float *T);

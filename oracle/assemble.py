@@ -1,12 +1,12 @@
 """Oracle: element matrices, global assembly, right-hand side, direct solve (test infrastructure only).
 
-Global sparse matrices are the sum of the local dense element matrices (Sec. 5.2, eqs.
+Global sparse matrices are the sum of the local dense element matrices (Sec. 4.2, eqs.
 flocal / globallocal).  The element stiffness (the L^b matrices of eq. flocal2, read with the
 missing transpose as D^T M D and with GLL collocation for the quadrature) is, per element,
     A_e = sum_{a,b} D_a^T diag(G_ab) D_b,   a, b in {r, s} (2D) or {r, t, s} (3D),
 with D_r = D (x) I, D_s = I (x) D in the element-local ordering (i slow, j fast).
 
-Boundary value problem (Sec. 4.2): p = g_D on the free surface (top, eq. bcpd), n . grad p =
+Boundary value problem (Sec. 3.2): p = g_D on the free surface (top, eq. bcpd), n . grad p =
 g_N on walls and bottom (eq. bcpdneu), -lap p = f inside.  The discrete system solved is
     [A_ff 0; 0 I] [p_f; p_D] = [M f + B g_N - A_fD g_D ; g_D]
 ("masked" operator: the free block on free rows, identity on Dirichlet rows), M the assembled

@@ -1,19 +1,19 @@
 """Oracle: 1D spectral building blocks (test infrastructure only; see oracle/__init__).
 
-Follows Sec. 5.3 ("Element construction in 2D") of the paper:
+Follows Sec. 4.3 ("Element construction in 2D") of the paper:
 * orthonormal Legendre polynomials from the three-term recurrence with
   a_k = sqrt(k^2 / ((2k+1)(2k-1))), P~0 = 1/sqrt(2), P~1 = sqrt(3/2) x;
 * Legendre-Gauss-Lobatto (GLL) nodes;
 * generalized Vandermonde V_ij = psi_j(r_i), V_r = d psi_j / dr (r_i);
 * differentiation matrix D_r = V_r V^{-1};
-and Sec. 6.2 ("Transfer operators"): I_{Pp} = Phi^p V^{-1}.
+and Sec. 5.2 ("Transfer operators"): I_{Pp} = Phi^p V^{-1}.
 """
 import numpy as np
 import numpy.polynomial.legendre as npleg
 
 
 def _a(k):
-    # recurrence coefficient a_k of Sec. 5.3
+    # recurrence coefficient a_k of Sec. 4.3
     return np.sqrt(k * k / ((2.0 * k + 1.0) * (2.0 * k - 1.0)))
 
 
@@ -94,7 +94,7 @@ def vandermonde_deriv(N, r):
 
 
 def diff_matrix(P):
-    """D_r = V_r V^{-1} at the GLL nodes of order P (Sec. 5.3)."""
+    """D_r = V_r V^{-1} at the GLL nodes of order P (Sec. 4.3)."""
     r = gll_nodes(P)
     V = vandermonde(P, r)
     Vr = vandermonde_deriv(P, r)
@@ -119,7 +119,7 @@ def diff_matrix_closed_form(P):
 
 
 def transfer_matrix(P_from, P_to):
-    """I_{P_from -> P_to} = Phi^{to} V^{-1} (Sec. 6.2).
+    """I_{P_from -> P_to} = Phi^{to} V^{-1} (Sec. 5.2).
 
     V is the Vandermonde of the source nodes (order P_from, modes 0..P_from);
     Phi^{to}_ij = psi_j(r^{to}_i) evaluates the same modes at the target nodes.

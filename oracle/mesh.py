@@ -20,7 +20,7 @@ Node numbering (global): 2D g = ix (Nz P + 1) + iz; 3D g = (ix (Ny P + 1) + iy)(
 vertical index fastest.  Elements: 2D e = ex Nz + ez, 3D e = (ex Ny + ey) Nz + ez.
 Element-local node (i[, m], j) with i along x, m along y, j along sigma; j fastest.
 Level meshes take h and eta sampled at the FINE level's horizontal GLL nodes and
-interpolate them element by element with the transfer matrix I_{Pp} of Sec. 6.2.
+interpolate them element by element with the transfer matrix I_{Pp} of Sec. 5.2.
 """
 import numpy as np
 

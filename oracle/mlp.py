@@ -4,18 +4,18 @@ The stage is not in the paper; it is defined by its formulas, written here plain
 (optionally emulating BF16 rounding of GEMM operands, RNE through float32):
 
 Element features (one element e, n = (P+1)^2 local nodes, local order i*(P+1)+j):
-    r_e = R_e r          (R_e: element restriction of an assembled vector, the R_i of Sec. 6.3)
+    r_e = R_e r          (R_e: element restriction of an assembled vector, the R_i of Sec. 5.3)
     s_e = ||r_e||_2
     X_e = [r_e / s_e, G_rr / g_e, G_rs / g_e, G_ss / g_e, m_e / mean(m_e)],
           g_e = mean over the element's nodes of (G_rr + G_ss)
 Network: 4n -> 128 -> 128 -> n with exact GELU(x) = x (1 + erf(x / sqrt 2)) / 2 on the two
 hidden layers.  Output scaling: c_e = (s_e / a_e) y_e, a_e = mean of diag(A_e) (element matrix).
-Assembly: c = W sum_e R_e^T c_e with W = (sum_e R_e R_e^T)^{-1} (the weight operator of Sec. 6.3:
+Assembly: c = W sum_e R_e^T c_e with W = (sum_e R_e R_e^T)^{-1} (the weight operator of Sec. 5.3:
 the average over the elements sharing a node); zero on Dirichlet nodes.
 Step: q = A c, alpha = (c.r)/(c.q), the energy-optimal step; accepted when alpha > 0 is finite
 (then x += alpha c and the A-norm of the error drops by (c.r)^2 / (c.q)), otherwise skipped.  Training target: the element-local error determined by
 the residual, t_e = (a_e / s_e) (R_e A R_e^T)^{-1} R_e r (the local solve of the Schwarz smoother,
-Sec. 6.3); the raw global error R_e e is also available (``targets``).
+Sec. 5.3); the raw global error R_e e is also available (``targets``).
 Loss: mean over samples and outputs of (y - t)^2.  Adam (beta1 .9, beta2 .999, eps 1e-8).
 """
 import math
@@ -156,7 +156,7 @@ def targets(mesh, e, s, scales=None):
 
 def local_targets(mesh, A, r, s, scales=None):
     """Targets from the element-block solves: t_e = (a_e / s_e) (R_e A R_e^T)^{-1} R_e r, the
-    local solve of the Schwarz smoother of Sec. 6.3 (A: the masked assembled matrix)."""
+    local solve of the Schwarz smoother of Sec. 5.3 (A: the masked assembled matrix)."""
     _, _, a = scales if scales is not None else element_scales(mesh)
     Ad = A.tocsr()
     r = np.asarray(r, dtype=np.float64)

@@ -1,14 +1,14 @@
 """Oracle: geometric p-multigrid V-cycle and outer iterations (test infrastructure only).
 
-Sec. 6 of the paper:
-* grid hierarchy by reducing the polynomial order with the mesh kept (Sec. 6.1).  Eq. gridcoars
+Sec. 5 of the paper:
+* grid hierarchy by reducing the polynomial order with the mesh kept (Sec. 5.1).  Eq. gridcoars
   as printed, P_{n-1} = ceil((P_n + 1)/2), stalls at 2 and never reaches the P = 1 coarsest
   grid the section names; it is read as P_{n-1} = ceil(P_n / 2) (8 -> 4 -> 2 -> 1);
 * prolongation from interpolation, I_{Pp} = Phi^p V^{-1}, applied per element and per
-  direction (tensor product), and restriction R = P^T (Sec. 6.2);
+  direction (tensor product), and restriction R = P^T (Sec. 5.2);
 * a fixed number of smoothing steps on every level before and after the coarse correction
-  (Sec. 6.3, V-cycle of Sec. 6); the smoothers here are damped Jacobi, Chebyshev acceleration
-  of Jacobi (polynomials in D^{-1} A) and the paper's additive Schwarz smoother (Sec. 6.3):
+  (Sec. 5.3, V-cycle of Sec. 5); the smoothers here are damped Jacobi, Chebyshev acceleration
+  of Jacobi (polynomials in D^{-1} A) and the paper's additive Schwarz smoother (Sec. 5.3):
   x <- x + S^{-1}(b - A x), S^{-1} = W sum_i R_i^T (R_i A R_i^T)^{-1} R_i,
   W = (sum_i R_i R_i^T)^{-1}.  Its subdomains are read as the element blocks (each element's
   (P+1)^d nodes; blocks of neighbouring elements share their face nodes, and no further overlap
@@ -21,9 +21,9 @@ Sec. 6 of the paper:
   has at most ``coarse_dense_max`` nodes, which is solved exactly.  (The paper is silent on the
   coarse solver; this reading is stated where it is used.)
 * coarse operators re-discretised with the same formula at the coarse order;
-* outer iterations: preconditioned defect correction x += B(b - A x) (Sec. 6.4), flexible
+* outer iterations: preconditioned defect correction x += B(b - A x) (Sec. 5.4), flexible
   conjugate gradients (one-term Polak-Ribiere beta) with B as preconditioner, and GMRES with B
-  as right preconditioner (Sec. 6.4 names GMRES, Saad and Schultz 1986): restarted every m
+  as right preconditioner (Sec. 5.4 names GMRES, Saad and Schultz 1986): restarted every m
   steps, the k-th iterate of a cycle minimises ||b - A x|| over x0 + span{B v_1 .. B v_k} with
   v_1 .. v_k the Arnoldi basis (the flexible form, Saad 1993, which equals right-preconditioned
   GMRES for the fixed linear B of a V-cycle).
@@ -209,7 +209,7 @@ class Hierarchy:
         return x
 
     def schwarz_sweeps(self, l, b, x, sweeps):
-        """Additive Schwarz smoothing (Sec. 6.3): x <- x - S^{-1}(A x - b), ``sweeps`` times."""
+        """Additive Schwarz smoothing (Sec. 5.3): x <- x - S^{-1}(A x - b), ``sweeps`` times."""
         L = self.levels[l]
         for _ in range(sweeps):
             x = x + L.schwarz(b - L.A @ x)
@@ -351,7 +351,7 @@ def fpcg(A, b, x0, prec, tol, maxit=500):
 
 
 def pdc(A, b, x0, prec, tol, maxit=500):
-    """Preconditioned defect correction x_{k+1} = x_k + B (b - A x_k) (Sec. 6.4)."""
+    """Preconditioned defect correction x_{k+1} = x_k + B (b - A x_k) (Sec. 5.4)."""
     x = x0.copy()
     nb = np.linalg.norm(b)
     r = b - A @ x

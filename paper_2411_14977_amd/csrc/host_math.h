@@ -9,7 +9,7 @@
 
 namespace semh {
 
-// ---- 1D spectral pieces (paper Sec. 5.3) -------------------------------------------------
+// ---- 1D spectral pieces (paper Sec. 4.3) -------------------------------------------------
 // GLL nodes (ascending) and weights of order P: end points plus the roots of P_P'.
 void gll_rule(int P, std::vector<double>& r, std::vector<double>& w);
 // Lagrange differentiation matrix at the GLL nodes, row-major D[i*(P+1)+k] = l_k'(r_i).

@@ -1,6 +1,6 @@
 // gfx950 kernels of the spectral-element pressure-Poisson solver.
 //
-// Operator (paper Sec. 5.2, element matrices summed into the global matrix, eq. globallocal;
+// Operator (paper Sec. 4.2, element matrices summed into the global matrix, eq. globallocal;
 // stiffness read as sum_ab D_a^T G_ab D_b with GLL collocation): applied matrix-free and
 // sum-factorised.  In 2D one workgroup owns one vertical column of Nz elements, so the faces
 // between vertically stacked elements are summed in LDS; the vertical node lines shared by
@@ -787,7 +787,7 @@ hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* 
 }
 
 // ------------------------------------------------------------------------------------------
-// additive Schwarz smoothing (Sec. 6.3), element blocks
+// additive Schwarz smoothing (Sec. 5.3), element blocks
 // ------------------------------------------------------------------------------------------
 // z_e = (R_e A R_e^T)^{-1} R_e r for every element: one thread per row of an element block,
 // 256 / (P+1)^2 elements per workgroup; the element's residual is staged in LDS and the
@@ -2060,7 +2060,7 @@ hipError_t fill(bool dbl, void* p, double v, size_t n, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------------------------------
-// p-transfers (paper Sec. 6.2): prolongation = coarse Lagrange basis at fine GLL nodes
+// p-transfers (paper Sec. 5.2): prolongation = coarse Lagrange basis at fine GLL nodes
 // (I_Pp = Phi V^{-1}) per direction; restriction = its transpose on assembled vectors.
 // Both in pull form: every output node sums its own inputs, each shared input counted once.
 // ------------------------------------------------------------------------------------------

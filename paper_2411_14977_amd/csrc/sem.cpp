@@ -1,10 +1,10 @@
 // C ABI, set-up and solver driver of the MI355X spectral-element pressure-Poisson solver.
 //
 // Set-up (host FP64, then upload): GLL rules and matrices per level, sigma-mapped geometric
-// factors (paper Sec. 2.2 eq. sigtrans / eq. 1_Scoef, Sec. 5.3), assembled inverse diagonals,
+// factors (paper Sec. 2.2 eq. sigtrans / eq. 1_Scoef, Sec. 4.3), assembled inverse diagonals,
 // lambda_hat of D^{-1}A by Lanczos on the device, and the exact block-cyclic-reduction factors of
-// the P = 1 coarse operator.  Solve (device): V-cycles of Sec. 6 inside FP64 flexible CG or
-// defect correction (Sec. 6.4); each outer iteration is one captured HIP graph.
+// the P = 1 coarse operator.  Solve (device): V-cycles of Sec. 5 inside FP64 flexible CG or
+// defect correction (Sec. 5.4); each outer iteration is one captured HIP graph.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -219,7 +219,7 @@ void parallel_ranges(size_t n, const std::function<void(size_t, size_t)>& f) {
 }
 
 // Inverses of the element blocks R_e A R_e^T of the masked assembled operator of a 2D level
-// (the local matrices of the Schwarz smoother, Sec. 6.3), from factors Gr in the level's
+// (the local matrices of the Schwarz smoother, Sec. 5.3), from factors Gr in the level's
 // storage precision: each block is the element's own matrix plus, on the nodes it shares with
 // its (up to eight) neighbours, their element matrices' entries between those nodes; rows and
 // columns of Dirichlet surface nodes are identity when masked.  Output [E][n][n], host FP64.

@@ -8,7 +8,7 @@ sem_learned_features.  Right-hand sides: seeded smooth Gaussian sources and whit
 addition raw random residuals go through the same feature map so the network sees every
 direction of the element residual space.  Targets (target="local", default): the element-local
 error the residual determines, (R_e A R_e^T)^{-1} R_e r_pre, the local solve of the Schwarz
-smoother (Sec. 6.3); target="error": the true error restricted to the element, whose smooth
+smoother (Sec. 5.3); target="error": the true error restricted to the element, whose smooth
 global part no element-local model can see.
 
 Geometries (layout="tank", default): windows of 64 x 16 elements of the 25.6 m wave tank at its

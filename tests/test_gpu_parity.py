@@ -342,7 +342,7 @@ def test_benchmark_hooks():
     t.close()
 
 
-# ---- additive Schwarz smoother (Sec. 6.3) -------------------------------------------------
+# ---- additive Schwarz smoother (Sec. 5.3) -------------------------------------------------
 @pytest.mark.parametrize("name", ["tank8", "ragged", "c2"])
 def test_vcycle_schwarz(name):
     wl = CASES[name]

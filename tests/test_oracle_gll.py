@@ -9,7 +9,7 @@ from oracle import gll
 
 
 def test_recurrence_start_and_p2():
-    # Sec. 5.3: P~0 = 1/sqrt(2), P~1 = sqrt(3/2) x; the recurrence then gives
+    # Sec. 4.3: P~0 = 1/sqrt(2), P~1 = sqrt(3/2) x; the recurrence then gives
     # P~2 = sqrt(5/2) (3x^2 - 1)/2 (orthonormal Legendre, textbook closed form).
     x = np.linspace(-1, 1, 7)
     p = gll.legendre_orthonormal(2, x)

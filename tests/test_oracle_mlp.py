@@ -1,5 +1,5 @@
 """Pins of the oracle's learned-stage pieces: GELU, BF16 rounding, gradients, Adam, features,
-the assembled correction (checked against the additive-Schwarz formula of Sec. 6.3) and the
+the assembled correction (checked against the additive-Schwarz formula of Sec. 5.3) and the
 energy behaviour of the accepted step."""
 import math
 
@@ -99,7 +99,7 @@ def test_zero_network_is_skipped():
 def test_exact_local_solves_reproduce_additive_schwarz():
     """With the network replaced by the exact element solve y_e = (a_e/s_e) (R_e A R_e^T)^{-1} r_e,
     the gather / scaling / weighted assembly plumbing gives W sum_e R_e^T (R_e A R_e^T)^{-1} R_e r,
-    the non-overlapping Schwarz preconditioner of Sec. 6.3, computed here independently."""
+    the non-overlapping Schwarz preconditioner of Sec. 5.3, computed here independently."""
     wl, m, A = _tank()
     Ad = A.toarray()
     r = W.random_vector(m.N, 6)

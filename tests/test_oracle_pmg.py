@@ -242,7 +242,7 @@ def test_h_levels_3d_vcycle_symmetric_and_solve_matches_direct():
     assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
 
 
-# ---- additive Schwarz smoother (Sec. 6.3) -----------------------------------------------
+# ---- additive Schwarz smoother (Sec. 5.3) -----------------------------------------------
 def test_schwarz_one_element_is_the_exact_solve():
     # a single element block holds every node and W = 1: one sweep solves A x = b exactly
     wl = W.tank(1, 1, 4, Lx=0.1)

@@ -6,7 +6,7 @@ eta(x), right-hand-side bumps f(x, z), manufactured solutions and their boundary
 mesh sizes of each workload, all evaluated at coordinates the caller supplies.  Each side (the
 CPU oracle and the HIP library) computes its own node coordinates.
 
-Workloads (wave-tank shaped, after the paper's submerged-bar test, Sec. 7.2: still-water depth
+Workloads (wave-tank shaped, after the paper's submerged-bar test, Sec. 6.2: still-water depth
 0.4 m over 0.1 m on the bar, incident wavelength 3.74 m so kh = 0.67 at h = 0.4):
   c1  manufactured sin(x) cosh(z+1) on [0, 2pi] x [-1, 0], 8 x 4 elements, P = 4, levels 4-2-1,
       Jacobi(2,2);
