@@ -113,6 +113,8 @@ typedef struct {
   float lr;                  /* peak learning rate, cosine decay to 0 (default 1e-3)       */
   float val_frac;            /* trailing fraction of the rows held out (default 0.1)      */
   unsigned long long seed;   /* SplitMix64 seed of the initial weights and shuffles       */
+  const void *init;          /* host network blob to start from (NULL: the seeded draw)   */
+  size_t init_nbytes;        /* its size in bytes                                         */
 } sem_train_cfg;
 
 /* Fill *d with defaults (2D, top Dirichlet, FP64, Chebyshev(3) on [0.1, 1.1] lambda_hat,
@@ -264,11 +266,34 @@ size_t sem_mlp_blob_size(int nin, int nout);
 sem_status sem_learned_features(sem_ctx *ctx, const double *r, const double *e, float *X,
                                 float *T);
 
-/* Train a network on device rows X [n x nin], T [n x nout] (FP32) with the library's BF16 MFMA
- * forward/backward kernels and Adam (FP32 master weights).  blob: host buffer of
- * sem_mlp_blob_size(nin, nout) bytes (output).  losses: host array of 2*epochs floats
- * (training loss of the last batch, validation loss) or NULL.  No context is needed; errors are
- * reported through sem_last_error(NULL). */
+/* Training pairs of the learned stage from this context's own p-multigrid (2D, fine order
+ * P <= 8, at most 4096 elements, FP64 context recommended).  For cycles >= 1: defect-correction
+ * cycles x <- x + B (b - A x) from x = 0 on the right-hand side b (device FP64, n_global, zero
+ * on the surface rows); at each cycle, at the point where the stage acts (the fine level after
+ * pre-smoothing of the cycle's residual r from zero: r_pre = r - A S(r)), rows of features
+ * X [rows x 5n] and element-block targets T [rows x n] (the features and targets of
+ * sem_learned_features with e = NULL) are written for `per` elements drawn without
+ * replacement by a SplitMix64-driven Fisher-Yates prefix (seed, draws counted through the call;
+ * per = 0: every element in order).  cycles = 0: one set of rows for b itself as the residual.
+ * The stage does not act in these cycles.  X, T: device FP32 with room for
+ * max(cycles, 1) * (per or E) rows; *rows receives the count written (may be NULL). */
+sem_status sem_learned_harvest(sem_ctx *ctx, const double *b, int cycles, int per,
+                               unsigned long long seed, float *X, float *T, size_t *rows);
+
+/* Train the learned stage's network for this context's fine level (nin = 5n, nout = n) on
+ * device rows X [n x nin], T [n x nout] (FP32; e.g. from sem_learned_harvest) with the
+ * library's BF16 MFMA forward/backward kernels (FP32 accumulation, FP32 master weights), Adam
+ * (beta 0.9 / 0.999, eps 1e-8) and a cosine learning rate from cfg->lr to 0 over all steps
+ * (cfg NULL: defaults).  blob: host buffer of *nbytes bytes (at least sem_mlp_blob_size(5n, n));
+ * *nbytes receives the blob's size.  The trained network is also loaded into the context, with
+ * the stage's placement as it was (off if no network was loaded before). */
+sem_status sem_learned_train(sem_ctx *ctx, const float *X, const float *T, int n,
+                             const sem_train_cfg *cfg, void *blob, size_t *nbytes);
+
+/* The same training without a context, for any nin, nout: device rows X [n x nin], T [n x nout]
+ * (FP32).  blob: host buffer of sem_mlp_blob_size(nin, nout) bytes (output).  losses: host
+ * array of 2*epochs floats (training loss of the last batch, validation loss) or NULL.  Errors
+ * are reported through sem_last_error(NULL). */
 sem_status sem_mlp_train(const float *X, const float *T, int n, int nin, int nout,
                          const sem_train_cfg *cfg, void *blob, size_t nbytes, float *losses);
 

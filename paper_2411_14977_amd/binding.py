@@ -41,7 +41,8 @@ class MeshDesc(ctypes.Structure):
 
 class TrainCfg(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
-                ("val_frac", ctypes.c_float), ("seed", ctypes.c_ulonglong)]
+                ("val_frac", ctypes.c_float), ("seed", ctypes.c_ulonglong),
+                ("init", ctypes.c_void_p), ("init_nbytes", ctypes.c_size_t)]
 
 
 class SolveInfo(ctypes.Structure):
@@ -102,6 +103,10 @@ def lib():
         "sem_mlp_train": (ctypes.c_int, [dp, dp, ip, ip, ip, ctypes.POINTER(TrainCfg), vp,
                                          ctypes.c_size_t, ctypes.POINTER(ctypes.c_float)]),
         "sem_mlp_forward": (ctypes.c_int, [vp, ctypes.c_size_t, dp, ip, dp]),
+        "sem_learned_harvest": (ctypes.c_int, [vp, dp, ip, ip, ctypes.c_ulonglong, dp, dp,
+                                               ctypes.POINTER(ctypes.c_size_t)]),
+        "sem_learned_train": (ctypes.c_int, [vp, dp, dp, ip, ctypes.POINTER(TrainCfg), vp,
+                                             ctypes.POINTER(ctypes.c_size_t)]),
         "sem_mlp_forward_noalloc": (ctypes.c_int, [vp, ctypes.c_size_t, dp, ip, dp]),
         "sem_mlp_gradients": (ctypes.c_int, [vp, ctypes.c_size_t, dp, dp, ip,
                                              ctypes.POINTER(ctypes.c_float),
@@ -270,10 +275,41 @@ def sem_learned_features(ctx, r, e, X, T):
     _check(ctx, lib().sem_learned_features(ctx, _ptr(r), _ptr(e), _ptr32(X), _ptr32(T)))
 
 
-def sem_mlp_train(X, T, nin, nout, epochs=30, batch=1024, lr=1e-3, val_frac=0.1, seed=1234):
+def _train_cfg(epochs, batch, lr, val_frac, seed, init):
+    cfg = TrainCfg(epochs, batch, lr, val_frac, seed, None, 0)
+    if init is not None:
+        buf = ctypes.create_string_buffer(bytes(init), len(init))
+        cfg.init = ctypes.cast(buf, ctypes.c_void_p)
+        cfg.init_nbytes = len(init)
+        cfg._keep = buf
+    return cfg
+
+
+def sem_learned_harvest(ctx, b, cycles, per, seed, X, T):
+    """Training rows of the context's own p-multigrid into device float32 X, T; returns the
+    number of rows written."""
+    rows = ctypes.c_size_t()
+    _check(ctx, lib().sem_learned_harvest(ctx, _ptr(b), int(cycles), int(per), int(seed),
+                                          _ptr32(X), _ptr32(T), ctypes.byref(rows)))
+    return rows.value
+
+
+def sem_learned_train(ctx, X, T, epochs=30, batch=1024, lr=1e-3, val_frac=0.1, seed=1234,
+                      init=None):
+    """Train the context's stage network on device float32 rows X, T; returns the blob."""
+    cfg = _train_cfg(epochs, batch, lr, val_frac, seed, init)
+    nb = ctypes.c_size_t(sem_mlp_blob_size(X.shape[1], T.shape[1]))
+    blob = ctypes.create_string_buffer(nb.value)
+    _check(ctx, lib().sem_learned_train(ctx, _ptr32(X), _ptr32(T), X.shape[0], ctypes.byref(cfg),
+                                        blob, ctypes.byref(nb)))
+    return bytes(blob.raw[:nb.value])
+
+
+def sem_mlp_train(X, T, nin, nout, epochs=30, batch=1024, lr=1e-3, val_frac=0.1, seed=1234,
+                  init=None):
     """Train on device float32 rows X [n x nin], T [n x nout]; returns (blob bytes, losses)."""
     n = X.shape[0]
-    cfg = TrainCfg(epochs, batch, lr, val_frac, seed)
+    cfg = _train_cfg(epochs, batch, lr, val_frac, seed, init)
     nb = sem_mlp_blob_size(nin, nout)
     blob = ctypes.create_string_buffer(nb)
     losses = (ctypes.c_float * (2 * epochs))()

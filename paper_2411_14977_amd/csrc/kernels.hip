@@ -9,6 +9,8 @@
 // of an element: the sigma-direction contractions stay in registers, the x-direction ones go
 // through LDS.  The work is HBM bound (about 1.5-2.2 flop/byte in FP64), so no MFMA is used.
 #include <hip/hip_runtime.h>
+
+#include <cstdlib>
 #include <stdint.h>
 
 #include <map>
@@ -584,10 +586,22 @@ __global__ __launch_bounds__(1024) void k_cheb2d_first(T* __restrict__ x, T* __r
 // the workgroup count is a multiple of 8 (XCD-aware order) and at least 256, else two (FP64 at
 // P = 8: 2 is faster than 4); odd counts (no XCD order) are the slowest.  One owned column (the
 // halo doubles the work) still beats operator + update.  0: the fused form does not fit.
+// SEM_CHEB_CPB=1, 2 or 4 forces that count where it fits (read once per process; tuning only)
+static int cpb_override() {
+  static const int v = [] {
+    const char* e = std::getenv("SEM_CHEB_CPB");
+    const int k = e ? std::atoi(e) : 0;
+    return (k == 1 || k == 2 || k == 4) ? k : 0;
+  }();
+  return v;
+}
+
 int cheb2d_cpb(int P, int Nx, int Nz, bool dbl) {
   const int nthr = (P + 1) * Nz;
   const size_t sm = apply2d_smem(P, Nz, dbl), lds = 160 * 1024;
   auto fits = [&](int c) { return (c + 1) * nthr <= 1024 && (c + 1) * sm <= lds; };
+  if (const int f = cpb_override())
+    if (fits(f)) return f;
   const int b4 = (Nx + 3) / 4;
   if (fits(4) && 2 * 5 * sm <= lds && b4 % 8 == 0 && b4 >= 256) return 4;
   if (fits(2)) return 2;

@@ -50,8 +50,10 @@ struct TrainCfg {
 
 // Train on device samples X [n x nin] and T [n x nout] (fp32, row-major).  On return net holds
 // the trained FP32 weights; losses (optional) gets 2 floats per epoch (train, validation).
+// init (optional): start from these weights instead of the seeded draw.
 bool train(const float* X, const float* T, int n, int nin, int nout, const TrainCfg& cfg, Net& net,
-           std::vector<float>* losses, hipStream_t st, std::string& err);
+           std::vector<float>* losses, hipStream_t st, std::string& err,
+           const Net* init = nullptr);
 
 // Batched forward with the training kernels (test hook): Y [n x nout] fp32.
 bool forward(const Net& net, const float* X, int n, float* Y, hipStream_t st, std::string& err);
@@ -105,9 +107,10 @@ hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* y
                         double sr, int store_d, hipStream_t st);
 // Training features of an assembled residual r on a 2D mesh: X [E x 5n] fp32; targets T [E x n]
 // fp32 from the error e ((a_e/s_e) R_e e) or, if e is null, from the element-block inverses
-// Ainv [E x n x n] ((a_e/s_e) Ainv_e R_e r).
+// Ainv [E x n x n] ((a_e/s_e) Ainv_e R_e r).  elist (device, nrows entries): write row k for
+// element elist[k] only; null: row e for every element e.
 hipError_t features(const double* r, const double* e, const double* Ainv, const float* geo,
                     const float* abar, float* X, float* T, size_t E, int P, int Nz, int nzn,
-                    hipStream_t st);
+                    hipStream_t st, const int* elist = nullptr, size_t nrows = 0);
 
 }  // namespace semm

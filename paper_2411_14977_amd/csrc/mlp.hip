@@ -525,16 +525,25 @@ double read_loss(Acts& a, hipStream_t st, std::string& err, bool& ok) {
 }  // namespace
 
 bool train(const float* X, const float* T, int n, int nin, int nout, const TrainCfg& cfg, Net& net,
-           std::vector<float>* losses, hipStream_t st, std::string& err) {
+           std::vector<float>* losses, hipStream_t st, std::string& err, const Net* init) {
   if (n < 32 || nin < 1 || nout < 1 || cfg.batch < 16 || cfg.epochs < 1) {
     err = "bad training arguments";
+    return false;
+  }
+  if (init && (init->nin != nin || init->nout != nout)) {
+    err = "bad initial network (size mismatch)";
     return false;
   }
   const int B = (cfg.batch + 15) / 16 * 16;
   int nval = (int)std::floor(cfg.val_frac * n);
   if (nval < 0) nval = 0;
   const int ntr = n - nval;
-  net_init(net, nin, nout, cfg.seed);
+  if (init) {
+    net = *init;
+    net.seed = cfg.seed;
+  } else {
+    net_init(net, nin, nout, cfg.seed);
+  }
   Dev d;
   Params p;
   Acts a;
@@ -1084,9 +1093,11 @@ __global__ __launch_bounds__(128) void k_features(const double* __restrict__ r,
                                                   const double* __restrict__ Ainv,
                                                   const float* __restrict__ geo,
                                                   const float* __restrict__ abar, float* __restrict__ X,
-                                                  float* __restrict__ Tt, int P, int Nz, int nzn) {
+                                                  float* __restrict__ Tt, int P, int Nz, int nzn,
+                                                  const int* __restrict__ elist) {
   __shared__ double sh[8];
-  const int el = blockIdx.x;
+  const int orow = blockIdx.x;                     // output row
+  const int el = elist ? elist[orow] : orow;       // element it describes
   const int NP = P + 1, n = NP * NP;
   const int ex = el / Nz, ez = el - ex * Nz;
   double s2 = 0.0;
@@ -1099,8 +1110,8 @@ __global__ __launch_bounds__(128) void k_features(const double* __restrict__ r,
   for (int l = threadIdx.x; l < n; l += blockDim.x) {
     const int i = l / NP, j = l - i * NP;
     const size_t g = (size_t)(ex * P + i) * nzn + ez * P + j;
-    X[(size_t)el * 5 * n + l] = s > 0 ? (float)(r[g] / s) : 0.f;
-    if (Tt && e) Tt[(size_t)el * n + l] = s > 0 ? (float)((double)abar[el] / s * e[g]) : 0.f;
+    X[(size_t)orow * 5 * n + l] = s > 0 ? (float)(r[g] / s) : 0.f;
+    if (Tt && e) Tt[(size_t)orow * n + l] = s > 0 ? (float)((double)abar[el] / s * e[g]) : 0.f;
     if (Tt && !e) {
       double t = 0.0;
       const double* row = Ainv + ((size_t)el * n + l) * n;
@@ -1108,18 +1119,20 @@ __global__ __launch_bounds__(128) void k_features(const double* __restrict__ r,
         const int qi = q / NP, qj = q - qi * NP;
         t += row[q] * r[(size_t)(ex * P + qi) * nzn + ez * P + qj];
       }
-      Tt[(size_t)el * n + l] = s > 0 ? (float)((double)abar[el] / s * t) : 0.f;
+      Tt[(size_t)orow * n + l] = s > 0 ? (float)((double)abar[el] / s * t) : 0.f;
     }
   }
   for (int l = threadIdx.x; l < 4 * n; l += blockDim.x)
-    X[(size_t)el * 5 * n + n + l] = geo[(size_t)el * 4 * n + l];
+    X[(size_t)orow * 5 * n + n + l] = geo[(size_t)el * 4 * n + l];
 }
 
 hipError_t features(const double* r, const double* e, const double* Ainv, const float* geo,
                     const float* abar, float* X, float* T, size_t E, int P, int Nz, int nzn,
-                    hipStream_t st) {
-  hipLaunchKernelGGL(k_features, dim3((unsigned)E), dim3(128), 0, st, r, e, Ainv, geo, abar, X, T,
-                     P, Nz, nzn);
+                    hipStream_t st, const int* elist, size_t nrows) {
+  const size_t rows = elist ? nrows : E;
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features, dim3((unsigned)rows), dim3(128), 0, st, r, e, Ainv, geo, abar, X,
+                     T, P, Nz, nzn, elist);
   return hipGetLastError();
 }
 

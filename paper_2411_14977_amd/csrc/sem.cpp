@@ -120,6 +120,7 @@ struct Ctx {
   std::vector<float> abar_h;   // [E] mean element-matrix diagonal (host)
   float* geo_d = nullptr;
   double* ainv_d = nullptr;    // [E x n x n] inverses of R_e A R_e^T (training targets)
+  int* harvest_idx = nullptr;  // [E] elements sampled by sem_learned_harvest
   // graphs
   // iteration graphs (each ends with the copy of its partial sums into host slot 0 or 1)
   hipGraphExec_t g_first = nullptr, g_iter[2] = {nullptr, nullptr}, g_pdc[2] = {nullptr, nullptr};
@@ -2420,6 +2421,139 @@ sem_status sem_learned_features(sem_ctx* ctx, const double* r, const double* e, 
   });
 }
 
+// the stage-point residual of the V-cycle for the FP64 residual in c->ro: pre-smoothing from
+// x = 0 on the fine level, then r_pre = r - A x_pre (FP64 outer operator) into c->qo
+static void stage_point_residual(Ctx* c) {
+  DLevel& L = c->lev[0];
+  HK(semk::cast_to(L.dbl, c->ro, L.b, L.N, c->st));
+  smooth(c, 0, true);
+  HK(semk::cast_from(L.dbl, L.x, c->zo, L.N, c->st));
+  apply_outer(c, c->zo, c->masked);
+  HK(semk::resid64(c->ro, c->yo, c->So, c->qo, pset(c, PS_RR), nullptr, L.N, L.nzn, L.P, c->st));
+}
+
+// training rows of one residual: features and element-block targets of `per` elements drawn
+// without replacement by a SplitMix64 Fisher-Yates prefix (all elements in order if per = 0)
+static size_t harvest_rows(Ctx* c, const double* r, int per, unsigned long long seed,
+                           unsigned long long* ctr, float* X, float* T) {
+  DLevel& L = c->lev[0];
+  const size_t E = L.geo.E, n = (size_t)L.NP * L.NP;
+  if (per <= 0 || (size_t)per >= E) {
+    HK(semm::features(r, nullptr, c->ainv_d, c->geo_d, c->stage.abar, X, T, E, L.P, L.Nz, L.nzn,
+                      c->st));
+    return E;
+  }
+  std::vector<int> idx(E);
+  for (size_t i = 0; i < E; ++i) idx[i] = (int)i;
+  for (int k = 0; k < per; ++k) {
+    const double u = 0.5 * (semh::splitmix64_uniform(seed, (*ctr)++) + 1.0);  // [0, 1)
+    size_t j = (size_t)k + (size_t)(u * (double)(E - k));
+    if (j >= E) j = E - 1;
+    std::swap(idx[k], idx[j]);
+  }
+  HK(hipMemcpyAsync(c->harvest_idx, idx.data(), per * sizeof(int), hipMemcpyHostToDevice, c->st));
+  HK(semm::features(r, nullptr, c->ainv_d, c->geo_d, c->stage.abar, X, T, E, L.P, L.Nz, L.nzn,
+                    c->st, c->harvest_idx, (size_t)per));
+  HK(hipStreamSynchronize(c->st));  // idx is a host vector
+  (void)n;
+  return (size_t)per;
+}
+
+sem_status sem_learned_harvest(sem_ctx* ctx, const double* b, int cycles, int per,
+                               unsigned long long seed, float* X, float* T, size_t* rows) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
+    if (!b || !X || !T) throw ArgFail{"null vector"};
+    if (cycles < 0 || cycles > 1000 || per < 0) throw ArgFail{"bad cycles / per"};
+    if (!c->masked) return SEM_ERR_STATE;
+    DLevel& L = c->lev[0];
+    if (L.NP * L.NP > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
+    if (c->lev.size() < 2) throw ArgFail{"harvesting needs at least two levels"};
+    if (L.geo.E > 4096) throw ArgFail{"element-block targets are for training meshes (<= 4096 elements)"};
+    HK(hipStreamSynchronize(c->st));
+    stage_buffers(c);
+    if (!c->geo_d) c->geo_d = upload(c, c->geo_h);
+    if (!c->ainv_d) c->ainv_d = upload(c, element_block_inverses(c));
+    if (!c->harvest_idx) c->harvest_idx = (int*)dalloc(c, L.geo.E * sizeof(int));
+    // the stage must not act inside the cycles that generate its own training data
+    struct Restore {
+      bool& flag;
+      bool was;
+      ~Restore() { flag = was; }
+    } restore{c->stage.enabled, c->stage.enabled};
+    c->stage.enabled = false;
+    enter(c);
+    const size_t N = L.N, n = (size_t)L.NP * L.NP;
+    unsigned long long ctr = 0;
+    size_t out = 0;
+    if (cycles == 0) {  // b itself is a residual of the correction problem
+      HK(hipMemcpyAsync(c->qo, b, N * 8, hipMemcpyDeviceToDevice, c->st));
+      out += harvest_rows(c, c->qo, per, seed, &ctr, X, T);
+    } else {
+      HK(semk::fill(true, c->xo, 0.0, N, c->st));
+      for (int k = 0; k < cycles; ++k) {
+        // r = b - A x; training rows at the stage point; x += B r
+        apply_outer(c, c->xo, c->masked);
+        HK(semk::resid64(b, c->yo, c->So, c->ro, pset(c, PS_RR), nullptr, L.N, L.nzn, L.P, c->st));
+        stage_point_residual(c);
+        out += harvest_rows(c, c->qo, per, seed, &ctr, X + out * 5 * n, T + out * n);
+        vcycle(c, c->ro);
+        HK(semk::cast_from(L.dbl, L.x, c->zo, L.N, c->st));
+        HK(semk::axpy64(c->xo, c->zo, 1.0, L.N, c->st));
+      }
+    }
+    leave(c);
+    HK(hipStreamSynchronize(c->st));
+    if (rows) *rows = out;
+    return SEM_OK;
+  });
+}
+
+sem_status sem_learned_train(sem_ctx* ctx, const float* X, const float* T, int n,
+                             const sem_train_cfg* cfg, void* blob, size_t* nbytes) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
+    if (!X || !T || !blob || !nbytes) throw ArgFail{"null argument"};
+    const DLevel& L = c->lev[0];
+    const int nout = L.NP * L.NP, nin = 5 * nout;
+    const size_t need = semm::blob_size(nin, nout);
+    if (*nbytes < need) throw ArgFail{"blob buffer too small (see sem_mlp_blob_size)"};
+    semm::TrainCfg tc;
+    semm::Net init;
+    bool have_init = false;
+    if (cfg) {
+      tc.epochs = cfg->epochs;
+      tc.batch = cfg->batch;
+      tc.lr = cfg->lr;
+      tc.val_frac = cfg->val_frac;
+      tc.seed = cfg->seed;
+      if (cfg->init) {
+        std::string e;
+        if (!semm::net_from_blob(cfg->init, cfg->init_nbytes, init, e))
+          throw ArgFail{"bad initial network: " + e};
+        have_init = true;
+      }
+    }
+    if (tc.epochs < 1 || tc.epochs > 100000 || tc.batch < 16 || tc.batch > 65536 ||
+        !(tc.lr > 0) || tc.val_frac < 0 || tc.val_frac >= 1)
+      throw ArgFail{"bad training configuration"};
+    HK(hipStreamSynchronize(c->st));
+    enter(c);
+    semm::Net net;
+    std::string e;
+    if (!semm::train(X, T, n, nin, nout, tc, net, nullptr, c->st, e, have_init ? &init : nullptr))
+      throw ArgFail{"training failed: " + e};
+    HK(hipStreamSynchronize(c->st));
+    semm::net_to_blob(net, blob);
+    *nbytes = need;
+    learned_load_impl(c, blob, need, c->stage.enabled ? c->stage_mode : 0);
+    leave(c);
+    return SEM_OK;
+  });
+}
+
 sem_status sem_learned_stage(sem_ctx* ctx, const double* b, double* x, int* accepted) {
   Ctx* c = C(ctx);
   return guarded(c, [&]() {
@@ -2619,13 +2753,19 @@ sem_status sem_mlp_train(const float* X, const float* T, int n, int nin, int nou
       tc.val_frac = cfg->val_frac;
       tc.seed = cfg->seed;
     }
+    semm::Net init;
+    const bool have_init = cfg && cfg->init;
+    if (have_init && !semm::net_from_blob(cfg->init, cfg->init_nbytes, init, e)) {
+      e = "bad initial network: " + e;
+      return false;
+    }
     if (tc.epochs < 1 || tc.epochs > 100000 || tc.batch < 16 || tc.batch > 65536 ||
         !(tc.lr > 0) || tc.val_frac < 0 || tc.val_frac >= 1) { e = "bad training configuration"; return false; }
     hipStream_t st = nullptr;
     if (hipStreamCreate(&st) != hipSuccess) { e = "stream creation failed"; return false; }
     semm::Net net;
     std::vector<float> ls;
-    const bool ok = semm::train(X, T, n, nin, nout, tc, net, &ls, st, e);
+    const bool ok = semm::train(X, T, n, nin, nout, tc, net, &ls, st, e, have_init ? &init : nullptr);
     (void)hipStreamSynchronize(st);
     (void)hipStreamDestroy(st);
     if (!ok) return false;

@@ -1,15 +1,14 @@
 """Training data and training of the learned smoothing stage, driven through the C ABI.
 
-Pairs come from the library's own plain p-multigrid (FP64, Chebyshev(3), levels 8-4-2-1).  For
-each seeded training geometry, defect-correction cycles x <- x + B(b - A x) are run; at each
-cycle, at the point where the stage acts (finest level, after pre-smoothing of the V-cycle's
-right-hand side r), the residual r_pre = r - A x_pre is turned into element features by
-sem_learned_features.  Right-hand sides: seeded smooth Gaussian sources and white noise; in
-addition raw random residuals go through the same feature map so the network sees every
-direction of the element residual space.  Targets (target="local", default): the element-local
-error the residual determines, (R_e A R_e^T)^{-1} R_e r_pre, the local solve of the Schwarz
-smoother (Sec. 5.3); target="error": the true error restricted to the element, whose smooth
-global part no element-local model can see.
+Pairs come from the library's own plain p-multigrid (FP64, Chebyshev(3), levels 8-4-2-1):
+sem_learned_harvest runs defect-correction cycles x <- x + B(b - A x) on a training geometry
+and, at each cycle, at the point where the stage acts (finest level, after pre-smoothing of the
+cycle's residual r), writes element features of r_pre = r - A x_pre and the element-local error
+that residual determines, (R_e A R_e^T)^{-1} R_e r_pre (the local solve of the Schwarz smoother,
+Sec. 5.3), for a seeded sample of elements.  Right-hand sides: seeded smooth Gaussian sources
+and white noise; in addition raw random residuals go through the same feature map so the network
+sees every direction of the element residual space.  This module only chooses the geometries
+and the seeded inputs; every arithmetic step runs in the library.
 
 Geometries (layout="tank", default): windows of 64 x 16 elements of the 25.6 m wave tank at its
 test element size (dx = 0.025 m) with seeded offsets and free surfaces whose seeds are disjoint
@@ -22,7 +21,8 @@ import numpy as np
 
 import workloads as W
 
-from .binding import Solver, fine_x_nodes, sem_learned_features, sem_mlp_train
+from .binding import (Solver, fine_x_nodes, sem_learned_harvest, sem_learned_train,
+                      sem_mlp_train)
 
 TANK_L = 25.6
 WINDOW = (64, 16)   # elements of one training window (x, z)
@@ -69,29 +69,18 @@ def _surface_rows(sv):
 
 
 def harvest(n_surfaces=40, n_bump=4, n_white=4, n_cycles=8, n_random=16, per=32, P=8,
-            smoother="chebyshev", layout="tank", target="local", max_pairs=None, log=None):
-    """Device tensors X [n x 5(P+1)^2], T [n x (P+1)^2] (float32).
+            smoother="chebyshev", layout="tank", max_pairs=None, log=None):
+    """Device tensors X [n x 5(P+1)^2], T [n x (P+1)^2] (float32) from sem_learned_harvest.
 
-    per: elements drawn (seeded) from each residual; 0 keeps all of them."""
+    per: elements drawn (seeded, inside the library) from each residual; 0 keeps all of them."""
     import torch
     n = (P + 1) ** 2
-    g = torch.Generator(device="cuda")
-    g.manual_seed(0)
-    Xs, Ts = [], []
+    E = (WINDOW[0] * WINDOW[1]) if layout == "tank" else 32
+    each = per if 0 < per < E else E
+    calls = n_surfaces * ((n_bump + n_white) * max(n_cycles, 1) + n_random)
+    X = torch.zeros(calls * each, 5 * n, dtype=torch.float32, device="cuda")
+    T = torch.zeros(calls * each, n, dtype=torch.float32, device="cuda")
     total = 0
-
-    def take(sv, rpre, err):
-        nonlocal total
-        E = sv.n_local // n
-        X = torch.zeros(E, 5 * n, dtype=torch.float32, device="cuda")
-        T = torch.zeros(E, n, dtype=torch.float32, device="cuda")
-        sem_learned_features(sv.ctx, rpre, err, X, T)
-        if per and per < E:
-            idx = torch.randperm(E, generator=g, device="cuda")[:per]
-            X, T = X[idx], T[idx]
-        Xs.append(X)
-        Ts.append(T)
-        total += X.shape[0]
 
     def dev(a):
         return torch.tensor(a, dtype=torch.float64, device="cuda")
@@ -107,36 +96,32 @@ def harvest(n_surfaces=40, n_bump=4, n_white=4, n_cycles=8, n_random=16, per=32,
                 bb = np.random.default_rng(8000 + 31 * s + j).standard_normal(sv.n_global)
                 bb[top] = 0.0
                 b = dev(bb)
-            x = torch.zeros_like(b)
-            for _ in range(n_cycles):
-                r = b - sv.apply(x)
-                xpre = sv.smooth(0, r, pre=True)
-                rpre = r - sv.apply(xpre)
-                err = None
-                if target == "error":
-                    xs, _, _ = sv.solve(r, tol=1e-13)
-                    err = xs - xpre
-                take(sv, rpre, err)
-                x = x + sv.vcycle(r)
-        if target == "local":
-            for j in range(n_random):
-                rr = np.random.default_rng(12000 + 53 * s + j).standard_normal(sv.n_global)
-                rr[top] = 0.0   # residuals of the correction problem vanish on the surface
-                take(sv, dev(rr), None)
+            total += sem_learned_harvest(sv.ctx, b, n_cycles, per, 7000 + 97 * s + j,
+                                         X[total:], T[total:])
+        for j in range(n_random):
+            rr = np.random.default_rng(12000 + 53 * s + j).standard_normal(sv.n_global)
+            rr[top] = 0.0   # residuals of the correction problem vanish on the surface
+            total += sem_learned_harvest(sv.ctx, dev(rr), 0, per, 11000 + 89 * s + j,
+                                         X[total:], T[total:])
         sv.close()
         if log:
             log(f"[harvest] geometry {s}: {total} pairs")
         if max_pairs and total >= max_pairs:
             break
-    X = torch.cat(Xs)
-    T = torch.cat(Ts)
-    if max_pairs:
-        X, T = X[:max_pairs], T[:max_pairs]
-    return X.contiguous(), T.contiguous()
+    torch.cuda.synchronize()
+    keep = min(total, max_pairs) if max_pairs else total
+    return X[:keep].contiguous(), T[:keep].contiguous()
 
 
 def train(X, T, epochs=600, batch=512, lr=2e-3, seed=1234, val_frac=0.1):
-    """Blob of the trained network and its per-epoch (train, validation) losses."""
+    """Blob of the trained network and its per-epoch (train, validation) losses (no context)."""
     nin, nout = X.shape[1], T.shape[1]
     return sem_mlp_train(X, T, nin, nout, epochs=epochs, batch=batch, lr=lr, val_frac=val_frac,
                          seed=seed)
+
+
+def train_into(ctx, X, T, epochs=600, batch=512, lr=2e-3, seed=1234, val_frac=0.1):
+    """Train the stage network of a solver context (sem_learned_train: the network is loaded
+    into it); returns the blob, whose header holds the final training and validation losses."""
+    return sem_learned_train(ctx, X, T, epochs=epochs, batch=batch, lr=lr, val_frac=val_frac,
+                             seed=seed)

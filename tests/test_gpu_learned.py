@@ -238,3 +238,101 @@ def test_learned_solve_meets_the_oracle_bar():
             assert info.rel_res <= 1e-10 and err <= 1e-8, (prec, use, err)
             s.close()
     print(f"[gpu] learned solve (iters, skips, err): {res}", flush=True)
+
+
+# ---- training pairs and training through the context (sem_learned_harvest, sem_learned_train) --
+def _harvest_case():
+    """The c1-layout training geometry at P = 8 (32 elements) with its oracle hierarchy."""
+    h_fn, eta_fn = W.training_geometry(0)
+    x = oc.fine_x_nodes(8, 8, 2 * np.pi)
+    args = dict(dim=2, Nx=8, Nz=4, Lx=2 * np.pi, h=h_fn(x), eta=eta_fn(x))
+    Hh = pmg.Hierarchy(args, [8, 4, 2, 1])
+    pmg.estimate_lambdas(Hh)
+    sv, source = learned.training_solver(0, layout="c1")
+    for l, L in enumerate(Hh.levels[:-1]):
+        sv.set_lambda(l, L.lam)
+    return Hh, sv
+
+
+def _oracle_harvest(Hh, b, cycles):
+    """Rows of every element at the stage point of each defect-correction cycle (oracle)."""
+    L0 = Hh.levels[0]
+    m = L0.mesh
+    sc = mlp.element_scales(m)
+    x = np.zeros(L0.N)
+    Xs, Ts = [], []
+    for _ in range(cycles):
+        r = b - L0.A @ x
+        xpre = Hh.smooth(0, r, np.zeros(L0.N), pre=True)
+        rpre = r - L0.A @ xpre
+        X, s = mlp.features(m, rpre, sc)
+        Xs.append(X)
+        Ts.append(mlp.local_targets(m, L0.A, rpre, s, sc))
+        x = x + Hh.vcycle(r)
+    return np.concatenate(Xs), np.concatenate(Ts)
+
+
+def test_harvest_matches_oracle():
+    Hh, sv = _harvest_case()
+    L0 = Hh.levels[0]
+    E, n = L0.mesh.E, 81
+    b = W.random_vector(L0.N, 77)
+    b[L0.dn] = 0.0
+    cycles = 3
+    X = torch.zeros(cycles * E, 5 * n, dtype=torch.float32, device="cuda")
+    Tt = torch.zeros(cycles * E, n, dtype=torch.float32, device="cuda")
+    rows = B.sem_learned_harvest(sv.ctx, T64(b), cycles, 0, 5, X, Tt)
+    assert rows == cycles * E
+    Xo, To = _oracle_harvest(Hh, b, cycles)
+    eX = np.abs(H(X) - Xo).max() / np.abs(Xo).max()
+    eT = np.abs(H(Tt) - To).max() / np.abs(To).max()
+    print(f"[gpu] harvest vs oracle: features {eX:.2e}, targets {eT:.2e}", flush=True)
+    assert eX <= 1e-6 and eT <= 1e-6
+    # sampled rows: each cycle's rows are distinct elements of that cycle's oracle rows
+    per = 7
+    Xs = torch.zeros(cycles * per, 5 * n, dtype=torch.float32, device="cuda")
+    Ts = torch.zeros(cycles * per, n, dtype=torch.float32, device="cuda")
+    assert B.sem_learned_harvest(sv.ctx, T64(b), cycles, per, 6, Xs, Ts) == cycles * per
+    Xs, Ts = H(Xs), H(Ts)
+    for k in range(cycles):
+        ref = Xo[k * E:(k + 1) * E]
+        hit = []
+        for row in Xs[k * per:(k + 1) * per]:
+            d = np.abs(ref - row).max(axis=1)
+            hit.append(int(np.argmin(d)))
+            assert d.min() <= 1e-6 * np.abs(ref).max()
+        assert len(set(hit)) == per
+    # cycles = 0: the rows of b itself
+    X0 = torch.zeros(E, 5 * n, dtype=torch.float32, device="cuda")
+    T0 = torch.zeros(E, n, dtype=torch.float32, device="cuda")
+    assert B.sem_learned_harvest(sv.ctx, T64(b), 0, 0, 1, X0, T0) == E
+    Xb, sb = mlp.features(L0.mesh, b)
+    assert np.abs(H(X0) - Xb).max() <= 1e-6 * np.abs(Xb).max()
+    assert np.abs(H(T0) - mlp.local_targets(L0.mesh, L0.A, b, sb)).max() <= 1e-6 * np.abs(H(T0)).max()
+    sv.close()
+
+
+def test_learned_train_adam_matches_oracle():
+    """Three full-batch Adam steps with the cosine schedule from given weights: the change of
+    every parameter tensor against the oracle's FP64 Adam on its BF16-emulated gradients."""
+    wl = W.tank(16, 4, 8, Lx=1.6, name="tank8")
+    s = cases.make_solver(wl, prec="f32")
+    p0 = params(41, scale=1.0, bias=0.1)
+    rng = np.random.default_rng(42)
+    nrow = 256
+    X = rng.standard_normal((nrow, N_IN)).astype(np.float32).astype(np.float64)
+    Tt = (0.5 * rng.standard_normal((nrow, N_OUT))).astype(np.float32).astype(np.float64)
+    steps, lr = 3, 1e-3
+    bl = B.sem_learned_train(s.ctx, T32(X), T32(Tt), epochs=steps, batch=nrow, lr=lr,
+                             val_frac=0.0, seed=9, init=blob(p0))
+    got = B.blob_unpack(bl)
+    ref, losses = mlp.train_full_batch(dict(p0), X, Tt, steps, lr, emulate=True)
+    worst = 0.0
+    for k in p0:
+        e = frob(got[k] - p0[k], ref[k] - p0[k])
+        worst = max(worst, e)
+        print(f"[gpu] Adam {k}: change {np.linalg.norm(ref[k] - p0[k]):.3e}, error {e:.2e}", flush=True)
+        assert e <= 2e-2, k
+    # the network is now loaded into the context (placement off until enabled)
+    B.sem_learned_enable(s.ctx, 3)
+    s.close()
