@@ -4,23 +4,28 @@ A step is one full solve (x = 0 -> ||b - A x|| <= 1e-10 ||b||) of the synthetic 
 workload (1024 x 16 elements, P = 8, 1,056,897 nodes), inputs resident in HBM.  The timed path
 (``value``) is the mixed-precision p-multigrid with the learned element-local smoothing stage:
 FP32 inner V-cycle (geometric factors stored in BF16 unless --prec f32), BF16-MFMA network stage
-on the fine level before and after smoothing, FP64 outer flexible CG.  Its network is trained
-first, on the GPU, by the library's own kernels from pairs that the plain p-multigrid generates
-(outside the timed region; the training time is reported).  Beside it: the same solver without
-the stage, the plain FP64 p-multigrid, per-cycle residual reduction in defect-correction (PDC)
-mode with and without the stage, iterations and times on unseen test surfaces, the roofline of
-the dominant kernel (the fused operator + smoother step, live HIP-event timing on the library's
-stream; the plain operator apply beside it) and the CPU
-oracle timed on a bounded sample of the same workload.
+on the fine level, FP64 outer flexible CG.  Its network is trained first, on the GPU, by the
+library's own kernels from pairs that the plain p-multigrid generates (outside the timed region;
+the training time is reported).  The stage's three placements (after pre-smoothing, before
+post-smoothing, both) are timed and the fastest is the headline; beside it the same solver
+without the stage (with the break-even cost of the stage), the plain FP64 p-multigrid, per-cycle
+residual reduction in defect-correction (PDC) mode with and without the stage, iterations and
+times on 20 unseen test surfaces (the oracle solves three of them on the host cores, in child
+processes, and checks the GPU's pressure), the roofline of the dominant kernel (the fused
+operator + smoother step; HBM-resident timing with rotated buffers, the cache-resident figure
+beside it), the whole solve's algorithmic bytes over its time, and the CPU oracle timed on a
+bounded sample of the same workload.
 
 A 3D time series (64 x 64 x 8, P = 6, moving surface, warm starts, frozen preconditioner) is
 reported beside it (--c5-steps, 0 to skip), the mixed-precision error table of the 2048 x 16
-tank at tolerances 1e-6, 1e-8, 1e-10 (--no-c3 to skip), the same solve with the paper's
-additive Schwarz smoother in place of Chebyshev (--no-schwarz), and the paper's multigrid
-iteration table and scaling sweeps rerun on tank meshes with two element layers (--no-context).
+tank at tolerances 1e-6, 1e-8, 1e-10 with the oracle's residual of every row (--no-c3 to skip),
+the same solve with the paper's additive Schwarz smoother in place of Chebyshev (--no-schwarz),
+and the paper's multigrid iteration table and scaling sweeps rerun on tank meshes with two
+element layers (--no-context).
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--workload c4] [--prec bf16]
-                       [--no-learned] [--surfaces 4] [--c5-steps 20] [--no-cpu] [--no-fp64]
+                       [--no-learned] [--surfaces 20] [--oracle-surfaces 3] [--c5-steps 20]
+                       [--no-cpu] [--no-fp64]
 """
 import argparse
 import hashlib
@@ -34,7 +39,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Poisson solves/s + GDOF/s to 1e-10 residual: FP32+learned p-MG vs plain FP64"
 HBM_PEAK_GBS = 8000.0
-STAGE_MODE = 3  # learned stage before pre-smoothing's restriction and before post-smoothing
 
 
 def log(*a):
@@ -52,7 +56,10 @@ def workload(name, index=0):
     raise SystemExit(f"unknown workload {name}")
 
 
-def describe(wl, prec, learned):
+def describe(wl, prec, learned, mode=0):
+    where = {1: "fine level after pre-smoothing (step folded into the transfers)",
+             2: "fine level before post-smoothing",
+             3: "fine level after pre-smoothing and before post-smoothing"}.get(mode, "")
     return {"workload": f"{wl.name}: 2D sigma-mapped wave tank {wl.Nx}x{wl.Nz} elements, P={wl.P}, "
                         f"levels {'-'.join(map(str, wl.orders))}, Chebyshev({wl.cheb_degree}), "
                         f"trapezoidal bar 0.4-0.1-0.4 m, surface seed {wl.surface_seed}, "
@@ -62,8 +69,8 @@ def describe(wl, prec, learned):
                       "f32": "fp32 compute, geometric factors fp32"}[prec],
             "outer": "fp64 flexible CG, fp64 operator and inner products, fp64 P=1 coarse solve",
             "learned_stage": ("element-local MLP 405-128-128-81 (GELU), bf16 MFMA operands, fp32 "
-                              "accumulate; fine level before pre-smoothing's restriction and before "
-                              "post-smoothing; energy-judged step") if learned else False,
+                              f"accumulate; {where} (the fastest of the three placements); "
+                              "energy-judged step") if learned else False,
             "tol": 1e-10}
 
 
@@ -84,20 +91,23 @@ def time_solves(s, rhs, steps, warmup, tol):
     return (t1 - t0) / steps, info, x
 
 
-def train_network(args):
-    """Harvest pairs with the plain p-multigrid and train the network on the GPU."""
-    import numpy as np
+def train_network(args, wl, prec):
+    """Harvest pairs with the plain p-multigrid and train the network on the GPU
+    (sem_learned_harvest, sem_learned_train on a context of the benchmark's fine level)."""
+    import struct
 
-    from paper_2411_14977_amd import learned
+    from paper_2411_14977_amd import cases, learned
     t0 = time.perf_counter()
     X, T = learned.harvest(n_surfaces=args.train_surfaces)
     t1 = time.perf_counter()
-    blob, losses = learned.train(X, T, epochs=args.epochs)
+    sv = cases.make_solver(wl, prec=prec)
+    blob = learned.train_into(sv.ctx, X, T, epochs=args.epochs)
+    sv.close()
     t2 = time.perf_counter()
-    losses = np.asarray(losses)
+    train_loss, val_loss = struct.unpack_from("<2f", blob, 40)
     rec = {"pairs": int(X.shape[0]), "surfaces": args.train_surfaces, "epochs": args.epochs,
            "harvest_s": t1 - t0, "train_s": t2 - t1,
-           "final_train_batch_loss": float(losses[-1, 0]), "final_val_loss": float(losses[-1, 1]),
+           "final_train_batch_loss": train_loss, "final_val_loss": val_loss,
            "recipe": "64x16-element windows of the tank (dx = 0.025 m), seeded offsets and "
                      "surfaces (seeds 5000+), smooth and white-noise sources, 8 defect-correction "
                      "cycles each, plus random residuals; targets = element-block solves; "
@@ -107,17 +117,17 @@ def train_network(args):
     return blob, rec
 
 
-def pdc_rates(wl, prec, blob, cycles):
+def pdc_rates(wl, prec, blob, cycles, mode):
     """Per-cycle residual reduction rho = (||r_k|| / ||r_0||)^(1/k) of defect correction with the
     V-cycle, with and without the learned stage."""
     from paper_2411_14977_amd import cases
     out = {}
-    for tag, mode in (("plain", 0), ("learned", STAGE_MODE)):
-        if mode and blob is None:
+    for tag, m in (("plain", 0), ("learned", mode)):
+        if m and blob is None:
             continue
         s = cases.make_solver(wl, prec=prec, outer="pdc", maxit=cycles)
-        if mode:
-            s.learned_load(blob, mode)
+        if m:
+            s.learned_load(blob, m)
         rhs = cases.make_rhs(wl, s)
         try:
             _, info, _ = s.solve(rhs, tol=1e-30, check=False)
@@ -130,25 +140,88 @@ def pdc_rates(wl, prec, blob, cycles):
     return out
 
 
-def unseen_surfaces(args, blob, n):
-    """Iterations and times to 1e-10 on test surfaces 1..n (surface seeds 1001.., never trained on)."""
+def unseen_surfaces(args, blob, n, mode, keep=()):
+    """Iterations and times to 1e-10 on test surfaces 1..n (surface seeds 1001.., rhs seeds
+    2001.., never trained on), plain mixed precision and with the stage; the learned solutions of
+    the indices in keep are returned (host arrays) for the oracle's check."""
     from paper_2411_14977_amd import cases
-    rows = []
+    rows, kept = [], {}
     for i in range(1, n + 1):
         wl = workload(args.workload, i)
         s = cases.make_solver(wl, prec=args.prec)
         rhs = cases.make_rhs(wl, s)
-        r = {"surface_seed": wl.surface_seed}
-        for tag, mode in (("plain", 0), ("learned", STAGE_MODE)):
-            if mode:
-                s.learned_load(blob, mode)
-            t, info, _ = time_solves(s, rhs, 1, 1, 1e-10)
-            r[tag] = {"iters": info.iters, "ms": t * 1e3, "skips": info.learned_skips}
+        r = {"surface_seed": wl.surface_seed, "rhs_seed": wl.rhs_seed}
+        for tag, m in (("plain", 0), ("learned", mode)):
+            if m:
+                s.learned_load(blob, m)
+            t, info, x = time_solves(s, rhs, 1, 1, 1e-10)
+            r[tag] = {"iters": info.iters, "ms": t * 1e3, "skips": info.learned_skips,
+                      "rel_res": info.rel_res}
+            if m and i in keep:
+                kept[i] = x.cpu().numpy()
         s.close()
         rows.append(r)
         log(f"[bench] surface {wl.surface_seed}: plain {r['plain']['iters']} it "
             f"{r['plain']['ms']:.2f} ms, learned {r['learned']['iters']} it {r['learned']['ms']:.2f} ms")
-    return rows
+    return rows, kept
+
+
+def start_oracle_parity(args, solutions):
+    """One child process per kept surface: the oracle's own FP64 FPCG + p-multigrid solve to
+    1e-12 on that surface's mesh and right-hand side, compared with the GPU's learned solution
+    (runs on the host cores while the GPU parts of the benchmark continue)."""
+    import subprocess
+    import tempfile
+
+    import numpy as np
+    procs = []
+    for i, x in sorted(solutions.items()):
+        fd, path = tempfile.mkstemp(suffix=".npy", prefix="sem_gpu_x_")
+        os.close(fd)
+        np.save(path, x)
+        cmd = [sys.executable, os.path.abspath(__file__), "--oracle-worker", args.workload, str(i),
+               path]
+        procs.append((i, path, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE,
+                                                text=True)))
+    return procs
+
+
+def finish_oracle_parity(procs):
+    out = []
+    for i, path, pr in procs:
+        so, se = pr.communicate()
+        try:
+            os.remove(path)
+        except OSError:
+            pass
+        if pr.returncode != 0:
+            log(f"[bench] oracle parity worker {i} failed: {se[-500:]}")
+            out.append({"test_index": i, "error": se[-300:]})
+            continue
+        out.append(json.loads(so.strip().splitlines()[-1]))
+    return out
+
+
+def oracle_worker(name, index, path):
+    """Child process: the oracle's solve of test surface `index` and the GPU solution's error."""
+    import numpy as np
+
+    from oracle import pmg
+    from tests import oracle_cases as oc
+    wl = workload(name, index)
+    t0 = time.perf_counter()
+    H = oc.hierarchy(wl)
+    pmg.estimate_lambdas(H)
+    L0 = H.levels[0]
+    b = oc.rhs(wl, L0.mesh)
+    xo, it, hist = pmg.fpcg(L0.A, b, np.zeros(L0.N), H.vcycle, 1e-12)
+    t1 = time.perf_counter()
+    xg = np.load(path)
+    err = float(np.linalg.norm(xg - xo) / np.linalg.norm(xo))
+    res = float(np.linalg.norm(b - L0.A @ xg) / np.linalg.norm(b))
+    print(json.dumps({"test_index": index, "surface_seed": wl.surface_seed, "oracle_iters": it,
+                      "oracle_rel_res": hist[-1], "oracle_s": t1 - t0,
+                      "gpu_rel_error_vs_oracle": err, "gpu_oracle_rel_res": res}), flush=True)
 
 
 def c5_series(steps, log_every=5):
@@ -213,23 +286,21 @@ def c5_series(steps, log_every=5):
 def c3_error_table():
     """Mixed-precision error table on the 2048 x 16, P = 8 tank (2.11M nodes): relative error of
     the FP32-inner solution (factors FP32 and BF16) at tolerances 1e-6, 1e-8, 1e-10 against the
-    FP64 solve to 1e-12, whose own residual is evaluated by the oracle (matrix-free, CPU)."""
+    FP64 solve to 1e-12, and every row's residual evaluated by the oracle (its own right-hand side
+    and matrix-free FP64 operator on the CPU)."""
     import torch
 
     import workloads as W
     from paper_2411_14977_amd import cases
     wl = W.c3()
+    check = oracle_checker(wl)
     s64 = cases.make_solver(wl, prec="f64")
     rhs = cases.make_rhs(wl, s64)
     xr, info_r, _ = s64.solve(rhs, tol=1e-12, check=False)
     out = {"workload": f"{wl.name}: 2D tank {wl.Nx}x{wl.Nz}, P={wl.P}, {wl.n_global} nodes",
            "reference": {"prec": "f64", "tol": 1e-12, "iters": info_r.iters,
-                         "rel_res": info_r.rel_res}}
+                         "rel_res": info_r.rel_res, "oracle_rel_res": check(xr)}}
     s64.close()
-    try:
-        out["reference"]["oracle_rel_res"] = oracle_check(wl, xr)
-    except Exception as e:  # pragma: no cover
-        log(f"[bench] oracle check of the c3 reference failed: {e}")
     nr = float(torch.linalg.norm(xr))
     for prec in ("f32", "bf16"):
         s = cases.make_solver(wl, prec=prec)
@@ -237,6 +308,7 @@ def c3_error_table():
         for tol in (1e-6, 1e-8, 1e-10):
             x, info, _ = s.solve(rhs, tol=tol)
             rows[f"{tol:g}"] = {"iters": info.iters, "rel_res": info.rel_res,
+                                "oracle_rel_res": check(x),
                                 "rel_error_vs_fp64": float(torch.linalg.norm(x - xr)) / nr}
         out[prec] = rows
         s.close()
@@ -357,17 +429,25 @@ def cpu_baseline(wl, tol):
             "solves_per_s_sample": 1.0 / t_solve, "iters": it}
 
 
-def oracle_check(wl, x):
-    """Relative residual of the returned pressure, evaluated by the oracle (its own right-hand
-    side and matrix-free FP64 operator on the CPU)."""
+def oracle_checker(wl):
+    """x -> relative residual of a returned pressure, evaluated by the oracle (its own right-hand
+    side and matrix-free FP64 operator on the CPU; mesh and right-hand side built once)."""
     import numpy as np
 
     from oracle import assemble
     from tests import oracle_cases as oc
     m = oc.fine_mesh(wl)
     b = oc.rhs(wl, m)
-    r = b - assemble.apply_matrix_free(m, x.cpu().numpy())
-    return float(np.linalg.norm(r) / np.linalg.norm(b))
+    nb = np.linalg.norm(b)
+
+    def check(x):
+        r = b - assemble.apply_matrix_free(m, x.cpu().numpy())
+        return float(np.linalg.norm(r) / nb)
+    return check
+
+
+def oracle_check(wl, x):
+    return oracle_checker(wl)(x)
 
 
 def main():
@@ -381,7 +461,9 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="time the V-cycle without the stage")
     ap.add_argument("--train-surfaces", type=int, default=40)
     ap.add_argument("--epochs", type=int, default=600)
-    ap.add_argument("--surfaces", type=int, default=4, help="unseen test surfaces to report")
+    ap.add_argument("--surfaces", type=int, default=20, help="unseen test surfaces to report")
+    ap.add_argument("--oracle-surfaces", type=int, default=3,
+                    help="unseen surfaces whose learned solution the oracle solves and checks")
     ap.add_argument("--pdc-cycles", type=int, default=12)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
@@ -409,35 +491,77 @@ def main():
 
     blob, train_rec = (None, None)
     if use_learned:
-        blob, train_rec = train_network(args)
+        blob, train_rec = train_network(args, wl, args.prec)
 
     s = cases.make_solver(wl, prec=args.prec)
     rhs = cases.make_rhs(wl, s)
     plain_mixed = None
+    placements = None
+    mode = 0
     if use_learned:
         t_nl, info_nl, _ = time_solves(s, rhs, args.steps, args.warmup, args.tol)
         plain_mixed = {"ms_per_solve": t_nl * 1e3, "solves_per_s": 1.0 / t_nl,
                        "gdof_per_s": wl.n_global / t_nl / 1e9, "iters": info_nl.iters,
                        "rel_res": info_nl.rel_res}
         log(f"[bench] mixed without stage: {t_nl * 1e3:.3f} ms/solve, {info_nl.iters} iterations")
-        s.learned_load(blob, STAGE_MODE)
+        # every placement of the stage, timed the same way; the fastest is the headline
+        placements = {}
+        s.learned_load(blob, 1)
+        for m in (1, 2, 3):
+            s.learned_enable(m)
+            tm, im, _ = time_solves(s, rhs, args.steps, args.warmup, args.tol)
+            placements[str(m)] = {"ms_per_solve": tm * 1e3, "iters": im.iters,
+                                  "skips": im.learned_skips, "rel_res": im.rel_res}
+            log(f"[bench] learned placement {m}: {tm * 1e3:.3f} ms/solve, {im.iters} iterations")
+        mode = min(placements, key=lambda k: placements[k]["ms_per_solve"])
+        mode = int(mode)
+        s.learned_enable(mode)
     t, info, x = time_solves(s, rhs, args.steps, args.warmup, args.tol)
     log(f"[bench] timed path: {t * 1e3:.3f} ms/solve, {info.iters} iterations, "
         f"rel_res {info.rel_res:.2e}, learned skips {info.learned_skips}")
 
-    # dominant kernel: the fine level's fused smoother step (operator + Chebyshev update), the
-    # kernel with the largest share of the solve's GPU time; beside it the plain operator apply
-    # and the FP64 outer operator
+    breakeven = None
+    if use_learned:
+        per_it_plain = t_nl / info_nl.iters
+        per_it = t / info.iters
+        breakeven = {
+            "placement": mode,
+            "iterations_saved": info_nl.iters - info.iters,
+            "stage_us_per_iteration": (per_it - per_it_plain) * 1e6,
+            "plain_iteration_us": per_it_plain * 1e6,
+            # the stage pays for itself when its cost per iteration is below this
+            "break_even_stage_us_per_iteration":
+                (t_nl - per_it_plain * info.iters) / info.iters * 1e6 if info.iters else None}
+
+    # whole solve: the sum of every launch's algorithmic bytes over one solve (the same solve
+    # issued without graphs) against the timed solve's duration
+    xb = torch.zeros_like(rhs)
+    wb, wit, wn = B.sem_solve_bytes(s.ctx, rhs, xb, args.tol)
+    whole = {"bytes_per_solve": wb, "iters": wit, "kernels_per_solve": wn,
+             "ms_per_solve": t * 1e3,
+             "achieved": wb / t / 1e9 * (info.iters / wit if wit else 1.0),
+             "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    whole["frac"] = whole["achieved"] / HBM_PEAK_GBS
+    log(f"[bench] whole solve: {wb / 1e6:.1f} MB in {wn} kernels, "
+        f"{whole['achieved']:.0f} GB/s ({100 * whole['frac']:.1f}% of HBM peak)")
+
+    # dominant solver kernel: the fine level's fused smoother step (operator + Chebyshev update);
+    # beside it the plain operator apply and the FP64 outer operator.  HBM-resident timing: the
+    # launches take rotated copies of every buffer (> 768 MiB in all), so no launch finds its data
+    # in the 256 MB Infinity Cache; the cache-resident figure (same buffers back to back) beside it
     def timed(kind):
         by = B.sem_operator_bytes(s.ctx, 0, kind)
-        ms = B.sem_time_operator(s.ctx, 0, kind, args.op_reps, 0)
-        ms_cold = B.sem_time_operator(s.ctx, 0, kind, max(5, args.op_reps // 5), 1)
-        return by, ms, ms_cold
+        ms_hbm = B.sem_time_operator(s.ctx, 0, kind, args.op_reps, 2)
+        ms_cache = B.sem_time_operator(s.ctx, 0, kind, args.op_reps, 0)
+        return by, ms_hbm, ms_cache
 
-    bytes_op, ms_op, ms_op_cold = timed(0)
-    bytes_step, ms_step, ms_step_cold = timed(2)
-    bytes_outer, ms_outer, ms_outer_cold = timed(1)
-    ach = bytes_step / (ms_step * 1e-3) / 1e9
+    def gbs(by, ms):
+        return by / (ms * 1e-3) / 1e9
+
+    bytes_op, ms_op, ms_op_c = timed(0)
+    bytes_step, ms_step, ms_step_c = timed(2)
+    bytes_outer, ms_outer, ms_outer_c = timed(1)
+    ach = gbs(bytes_step, ms_step)
     gname = "bf16" if args.prec == "bf16" else "float"
     kernel_tag = f"cheb2d_{wl.name}_{args.prec}"
     roof = {"bound": "hbm",
@@ -446,23 +570,28 @@ def main():
             "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
             "traffic": traffic_from_profiles(kernel_tag),
             "algorithmic_bytes_per_launch": bytes_step, "avg_launch_ms": ms_step,
-            "timing": "HIP events around back-to-back launches on the library stream; working set "
-                      "resident in the 256 MB Infinity Cache between launches",
-            "cold_single_launch": {"avg_ms_incl_event_overhead": ms_step_cold,
-                                   "achieved": bytes_step / (ms_step_cold * 1e-3) / 1e9},
+            "timing": "HIP events on the library stream around back-to-back launches that take "
+                      "rotated copies of every buffer (over 768 MiB in all), so each launch "
+                      "streams its data from HBM",
+            "cache_resident": {"avg_launch_ms": ms_step_c, "achieved": gbs(bytes_step, ms_step_c),
+                               "frac": gbs(bytes_step, ms_step_c) / HBM_PEAK_GBS,
+                               "timing": "the same buffers back to back (33 MB working set "
+                                         "served from the 256 MB Infinity Cache)"},
             "operator_apply": {"kernel": f"k_apply2d<P={wl.P},float,{gname}>",
                                "algorithmic_bytes_per_launch": bytes_op, "avg_launch_ms": ms_op,
-                               "achieved": bytes_op / (ms_op * 1e-3) / 1e9,
-                               "frac": bytes_op / (ms_op * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                               "cold_achieved": bytes_op / (ms_op_cold * 1e-3) / 1e9},
+                               "achieved": gbs(bytes_op, ms_op),
+                               "frac": gbs(bytes_op, ms_op) / HBM_PEAK_GBS,
+                               "cache_resident_achieved": gbs(bytes_op, ms_op_c)},
             "outer_fp64_operator": {"algorithmic_bytes_per_launch": bytes_outer,
                                     "avg_launch_ms": ms_outer,
-                                    "achieved": bytes_outer / (ms_outer * 1e-3) / 1e9,
-                                    "cold_achieved": bytes_outer / (ms_outer_cold * 1e-3) / 1e9}}
-    log(f"[bench] fused step {ms_step * 1e3:.2f} us ({ach:.0f} GB/s, {100 * ach / HBM_PEAK_GBS:.1f}% "
-        f"of HBM peak); operator {ms_op * 1e3:.2f} us "
-        f"({100 * bytes_op / (ms_op * 1e-3) / 1e9 / HBM_PEAK_GBS:.1f}%); fp64 outer "
-        f"{ms_outer * 1e3:.2f} us")
+                                    "achieved": gbs(bytes_outer, ms_outer),
+                                    "frac": gbs(bytes_outer, ms_outer) / HBM_PEAK_GBS,
+                                    "cache_resident_achieved": gbs(bytes_outer, ms_outer_c)},
+            "whole_solve": whole}
+    log(f"[bench] fused step {ms_step * 1e3:.2f} us HBM-resident ({ach:.0f} GB/s, "
+        f"{100 * ach / HBM_PEAK_GBS:.1f}% of HBM peak), {ms_step_c * 1e3:.2f} us cache-resident; "
+        f"operator {ms_op * 1e3:.2f} us ({100 * gbs(bytes_op, ms_op) / HBM_PEAK_GBS:.1f}%); "
+        f"fp64 outer {ms_outer * 1e3:.2f} us")
     s.close()
     # calibration for hardware byte counters: three plain 256 MiB device copies (a profiler
     # reading FETCH_SIZE / WRITE_SIZE of this command scales the operator's counts by these)
@@ -491,11 +620,21 @@ def main():
         s64.close()
 
     pdc = surf = None
+    parity_procs = []
     if use_learned:
-        pdc = pdc_rates(wl, args.prec, blob, args.pdc_cycles)
+        pdc = pdc_rates(wl, args.prec, blob, args.pdc_cycles, mode)
         log(f"[bench] PDC per-cycle rate: {pdc}")
         if args.surfaces > 0:
-            surf = unseen_surfaces(args, blob, args.surfaces)
+            keep = tuple(range(1, min(args.oracle_surfaces, args.surfaces) + 1))
+            rows, kept = unseen_surfaces(args, blob, args.surfaces, mode, keep)
+            saved = [r["plain"]["iters"] - r["learned"]["iters"] for r in rows]
+            surf = {"rows": rows,
+                    "iters_saved_mean": sum(saved) / len(saved),
+                    "learned_faster_on": sum(r["learned"]["ms"] < r["plain"]["ms"] for r in rows),
+                    "of": len(rows)}
+            parity_procs = start_oracle_parity(args, kept)
+            log(f"[bench] oracle checking surfaces {sorted(kept)} in {len(parity_procs)} "
+                f"background processes")
 
     context = None
     if not args.no_context:
@@ -520,6 +659,11 @@ def main():
             f"({c5['bf16']['iters_mean']:.1f} it), fp64 {c5['f64']['ms_per_solve']:.1f} ms "
             f"({c5['f64']['iters_mean']:.1f} it)")
 
+    if parity_procs:
+        log("[bench] waiting for the oracle's solves of the unseen surfaces ...")
+        surf["oracle_parity"] = finish_oracle_parity(parity_procs)
+        log(f"[bench] oracle parity: {surf['oracle_parity']}")
+
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle on a bounded sample ...")
@@ -530,11 +674,12 @@ def main():
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "fp32 inner (bf16 factors and network operands) / fp64 outer",
-           "data": "synthetic", "config": describe(wl, args.prec, use_learned),
+           "data": "synthetic", "config": describe(wl, args.prec, use_learned, mode),
            "solves_per_s": 1.0 / t, "iters": info.iters, "rel_res": info.rel_res,
            "learned_skips": info.learned_skips, "oracle_rel_res": res_check,
            "mixed_without_stage": plain_mixed, "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
+           "learned_placements": placements, "learned_break_even": breakeven,
            "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,
            "schwarz_smoother": schwarz, "paper_context": context, "c3_error_table": c3,
            "c5_series": c5,
@@ -543,4 +688,7 @@ def main():
 
 
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--oracle-worker":
+        oracle_worker(sys.argv[2], int(sys.argv[3]), sys.argv[4])
+    else:
+        main()

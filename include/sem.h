@@ -227,6 +227,16 @@ sem_status sem_coarse_solve(sem_ctx *ctx, const double *b, double *x);
 sem_status sem_time_operator(sem_ctx *ctx, int level, int kind, int reps, int flush,
                              double *ms_avg);
 
+/* Benchmark hook: one sem_poisson_solve (same arguments and result) run with every launch
+ * issued directly instead of replayed from graphs, and *bytes = the sum over its launches of
+ * each kernel's algorithmic bytes (every array it reads or writes counted once at its logical
+ * size, factors in their storage precision, block-reduction factors once per application; no
+ * re-reads, halos or scratch).  *iters (may be NULL): outer iterations; *launches (may be
+ * NULL): kernels counted.  Returns the solve's status.  Not for concurrent use from several
+ * host threads (the tally is per process). */
+sem_status sem_solve_bytes(sem_ctx *ctx, const double *rhs, double *x, double tol, double *bytes,
+                           int *iters, long *launches);
+
 /* Algorithmic bytes of one launch of sem_time_operator's kernel (every vector read or written
  * once, every geometric factor read once): kind 0, 1: x read, y written; kind 2: x, b, dinv, d
  * read, x, d written; plus the factors in their storage precision. */

@@ -3,12 +3,14 @@
 The stage is not in the paper; it is defined by its formulas, written here plainly in FP64
 (optionally emulating BF16 rounding of GEMM operands, RNE through float32):
 
-Element features (one element e, n = (P+1)^2 local nodes, local order i*(P+1)+j):
+Element features (one element e, n = (P+1)^d local nodes, local order i*(P+1)+j in 2D and
+(i*(P+1)+m)*(P+1)+j in 3D, the vertical index fastest):
     r_e = R_e r          (R_e: element restriction of an assembled vector, the R_i of Sec. 5.3)
     s_e = ||r_e||_2
-    X_e = [r_e / s_e, G_rr / g_e, G_rs / g_e, G_ss / g_e, m_e / mean(m_e)],
-          g_e = mean over the element's nodes of (G_rr + G_ss)
-Network: 4n -> 128 -> 128 -> n with exact GELU(x) = x (1 + erf(x / sqrt 2)) / 2 on the two
+    X_e = [r_e / s_e, G_f / g_e for every factor field f, m_e / mean(m_e)],
+          g_e = mean over the element's nodes of the trace (G_rr + G_ss, 3D also + G_tt);
+          2D fields G_rr, G_rs, G_ss (5n inputs), 3D G_rr, G_tt, G_rs, G_ts, G_ss (7n inputs)
+Network: 5n (2D) or 7n (3D) -> 128 -> 128 -> n with exact GELU(x) = x (1 + erf(x / sqrt 2)) / 2 on the two
 hidden layers.  Output scaling: c_e = (s_e / a_e) y_e, a_e = mean of diag(A_e) (element matrix).
 Assembly: c = W sum_e R_e^T c_e with W = (sum_e R_e R_e^T)^{-1} (the weight operator of Sec. 5.3:
 the average over the elements sharing a node); zero on Dirichlet nodes.
@@ -122,11 +124,13 @@ def train_full_batch(p, X, T, steps, lr0, total_steps=None, emulate=True):
 
 # ---- element features and the smoothing stage ------------------------------------------------
 def element_scales(mesh):
-    """g_e (feature scale), mean mass, and a_e = mean of diag(A_e) for every element."""
+    """g_e (feature scale: element mean of the trace of the factor tensor, G_rr + G_ss in 2D,
+    G_rr + G_tt + G_ss in 3D), mean mass, and a_e = mean of diag(A_e) for every element."""
     E = mesh.E
-    Grr = mesh.Grr.reshape(E, -1)
-    Gss = mesh.Gss.reshape(E, -1)
-    g = (Grr + Gss).mean(axis=1)
+    tr = mesh.Grr.reshape(E, -1) + mesh.Gss.reshape(E, -1)
+    if mesh.dim == 3:
+        tr = tr + mesh.Gtt.reshape(E, -1)
+    g = tr.mean(axis=1)
     mm = mesh.mass.reshape(E, -1).mean(axis=1)
     Ae = element_matrices(mesh)
     a = np.einsum("ekk->ek", Ae).mean(axis=1)
@@ -134,16 +138,18 @@ def element_scales(mesh):
 
 
 def features(mesh, r, scales=None):
-    """X (E x 5n) and s_e for an assembled residual r (2D meshes)."""
+    """X and s_e for an assembled residual r: per element [r_e / s_e, every factor field / g_e,
+    m_e / mean(m_e)], the fields in the order of mesh.fields() (2D: G_rr, G_rs, G_ss, so
+    5n columns; 3D: G_rr, G_tt, G_rs, G_ts, G_ss, so 7n columns; G_rt vanishes because x and y
+    are affine)."""
     E = mesh.E
     g, mm, _ = scales if scales is not None else element_scales(mesh)
     re = np.asarray(r, dtype=np.float64)[mesh.l2g]
     s = np.sqrt((re * re).sum(axis=1))
     safe = np.where(s > 0, s, 1.0)
     rn = np.where(s[:, None] > 0, re / safe[:, None], 0.0)
-    X = np.concatenate([rn, mesh.Grr.reshape(E, -1) / g[:, None], mesh.Grs.reshape(E, -1) / g[:, None],
-                        mesh.Gss.reshape(E, -1) / g[:, None], mesh.mass.reshape(E, -1) / mm[:, None]],
-                       axis=1)
+    geo = [F.reshape(E, -1) / g[:, None] for F in mesh.fields()]
+    X = np.concatenate([rn] + geo + [mesh.mass.reshape(E, -1) / mm[:, None]], axis=1)
     return X, s
 
 

@@ -98,6 +98,10 @@ def lib():
         "sem_coarse_solve": (ctypes.c_int, [vp, dp, dp]),
         "sem_time_operator": (ctypes.c_int, [vp, ip, ip, ip, ip, ctypes.POINTER(ctypes.c_double)]),
         "sem_operator_bytes": (ctypes.c_int, [vp, ip, ip, ctypes.POINTER(ctypes.c_double)]),
+        "sem_solve_bytes": (ctypes.c_int, [vp, dp, dp, ctypes.c_double,
+                                           ctypes.POINTER(ctypes.c_double),
+                                           ctypes.POINTER(ctypes.c_int),
+                                           ctypes.POINTER(ctypes.c_long)]),
         "sem_mlp_blob_size": (ctypes.c_size_t, [ip, ip]),
         "sem_learned_features": (ctypes.c_int, [vp, dp, dp, dp, dp]),
         "sem_mlp_train": (ctypes.c_int, [dp, dp, ip, ip, ip, ctypes.POINTER(TrainCfg), vp,
@@ -265,6 +269,14 @@ def sem_operator_bytes(ctx, level, kind):
     b = ctypes.c_double()
     _check(ctx, lib().sem_operator_bytes(ctx, level, kind, ctypes.byref(b)))
     return b.value
+
+
+def sem_solve_bytes(ctx, rhs, x, tol):
+    """(algorithmic bytes of one solve, its iterations, kernels counted); x is overwritten."""
+    b, it, n = ctypes.c_double(), ctypes.c_int(), ctypes.c_long()
+    _check(ctx, lib().sem_solve_bytes(ctx, _ptr(rhs), _ptr(x), float(tol), ctypes.byref(b),
+                                      ctypes.byref(it), ctypes.byref(n)))
+    return b.value, it.value, n.value
 
 
 def sem_mlp_blob_size(nin, nout):

@@ -27,6 +27,12 @@ struct GLayout {
   int W, Kp, NC, REM;
   size_t cstride;
 };
+// Algorithmic-byte accounting (benchmark hook): while enabled, every launch wrapper of the solve
+// path adds the bytes its kernel has to move at the least (each array it reads or writes once at
+// its logical size, factors in their storage precision).  acct_enable(true) clears the total.
+void acct_enable(bool on);
+void acct_add(double bytes);
+double acct_total(long* launches);
 GLayout g2d_layout(int P, int Nz, size_t tgsize);
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                    int Nx, int Nz, int masked, hipStream_t st);

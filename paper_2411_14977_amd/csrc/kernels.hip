@@ -21,6 +21,36 @@
 
 namespace semk {
 
+// ---- algorithmic-byte accounting (benchmark hook) -------------------------------------------
+// While enabled, each launch wrapper of the solve path adds the bytes its kernel has to move at
+// the least: every array it reads or writes once at its logical size (factors in their storage
+// precision), nothing for re-reads, halos or scratch.
+namespace {
+bool g_acct_on = false;
+double g_acct_bytes = 0.0;
+long g_acct_n = 0;
+inline double vsz(bool dbl) { return dbl ? 8.0 : 4.0; }
+inline double gsz(GType gt) { return gt == G_F64 ? 8.0 : (gt == G_F32 ? 4.0 : 2.0); }
+inline double nodes2(int P, int Nx, int Nz) { return (double)(Nx * P + 1) * (double)(Nz * P + 1); }
+inline double local2(int P, int Nx, int Nz) { return (double)Nx * Nz * (P + 1) * (P + 1); }
+}  // namespace
+void acct_enable(bool on) {
+  g_acct_on = on;
+  if (on) {
+    g_acct_bytes = 0.0;
+    g_acct_n = 0;
+  }
+}
+void acct_add(double bytes) {
+  if (!g_acct_on) return;
+  g_acct_bytes += bytes;
+  ++g_acct_n;
+}
+double acct_total(long* launches) {
+  if (launches) *launches = g_acct_n;
+  return g_acct_bytes;
+}
+
 // ------------------------------------------------------------------------------------------
 // type helpers
 // ------------------------------------------------------------------------------------------
@@ -646,6 +676,7 @@ static hipError_t cheb2d_p(bool dbl, GType gt, const void* xi, void* xo, void* d
 hipError_t cheb2d(int P, bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
                   const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
                   double cr, int store_d, hipStream_t st) {
+  acct_add(vsz(dbl) * nodes2(P, Nx, Nz) * (4 + (cd != 0.0) + (store_d ? 1 : 0)) + 3 * gsz(gt) * local2(P, Nx, Nz));
   const int cpb = cheb2d_cpb(P, Nx, Nz, dbl);
   if (xi == xo) return hipErrorInvalidValue;
   switch (P) {
@@ -785,6 +816,7 @@ int cheb2d_blocks(int P, int Nx, int Nz, bool dbl) {
 
 hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* q, const void* G,
                      int Nx, int Nz, int masked, double* dotp, hipStream_t st) {
+  acct_add(4.0 * local2(P, Nx, Nz) + 2 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz));
   const int cpb = P <= 8 ? cheb2d_cpb(P, Nx, Nz, dbl) : 0;
   if (cpb <= 0) return hipErrorInvalidValue;
   switch (P) {
@@ -878,6 +910,7 @@ static hipError_t asm_p(bool dbl, const void* r, const void* Ainv, void* z, void
 
 hipError_t asm_sweep(int P, bool dbl, const void* r, const void* Ainv, void* z, void* x, int Nx,
                      int Nz, int masked, int set, hipStream_t st) {
+  acct_add(vsz(dbl) * (local2(P, Nx, Nz) * ((P + 1) * (P + 1) + 2) + nodes2(P, Nx, Nz) * (set ? 2 : 3)));
   switch (P) {
     case 1: return asm_p<1>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
     case 2: return asm_p<2>(dbl, r, Ainv, z, x, Nx, Nz, masked, set, st);
@@ -1014,6 +1047,7 @@ hipError_t fpcg2d(int P, const double* z, const double* p, double* q, const doub
                   int Nz, int masked, const double* prz_old, const double* ppq_old,
                   const double* pzq, int first, double* ppq_new, double* beta_out,
                   hipStream_t st) {
+  acct_add(8.0 * nodes2(P, Nx, Nz) * (first ? 2 : 3) + 24.0 * local2(P, Nx, Nz));
   switch (P) {
 #define SEM_FPCG2D(PP) \
   case PP: return launch_fpcg2d<PP>(z, p, q, G, Nx, Nz, masked, prz_old, ppq_old, pzq, first, ppq_new, beta_out, st);
@@ -1095,6 +1129,7 @@ hipError_t update_xrp(double* x, double* r, double* p, const double* z, const do
                       const double* beta, int first, const double* prz_new,
                       const double* ppq_new, double* prz_old, double* ppq_old, double* prr,
                       unsigned N, hipStream_t st) {
+  acct_add(64.0 * N);
   hipLaunchKernelGGL(k_update_xrp, dim3(NRED), dim3(RED_THREADS), 0, st, x, r, p, z, q, beta,
                      first, prz_new, ppq_new, prz_old, ppq_old, prr, N);
   return hipGetLastError();
@@ -1148,6 +1183,7 @@ static hipError_t cheb2d_first_p(bool dbl, GType gt, void* x, void* d, void* b,
 hipError_t cheb2d_first(int P, bool dbl, GType gt, void* x, void* d, void* b, const double* r64,
                         const void* dinv, const void* G, int Nx, int Nz, int masked, double cr0,
                         double cd, double cr, int store_d, hipStream_t st) {
+  acct_add(nodes2(P, Nx, Nz) * ((r64 ? 8.0 + vsz(dbl) : vsz(dbl)) + vsz(dbl) * (2 + (store_d ? 1 : 0))) + 3 * gsz(gt) * local2(P, Nx, Nz));
   switch (P) {
 #define SEM_CHEB_FIRST(PP)                                                                  \
   case PP:                                                                                  \
@@ -1180,6 +1216,8 @@ hipError_t resid2d(int P, bool dbl, GType gt, const void* x, void* r, const void
                    const void* G, int Nx, int Nz, int masked, void* y, void* S, hipStream_t st) {
   if (x == r) return hipErrorInvalidValue;
   const int cpb = P <= 8 ? cheb2d_cpb(P, Nx, Nz, dbl) : 0;
+  acct_add(cpb > 0 ? 3 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz)
+                   : vsz(dbl) * nodes2(P, Nx, Nz));
   if (cpb > 0) {
     switch (P) {
       case 1: return resid2d_p<1>(dbl, gt, x, r, b, G, Nx, Nz, masked, cpb, st);
@@ -1237,6 +1275,7 @@ static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S,
 
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                    int Nx, int Nz, int masked, hipStream_t st) {
+  acct_add(2 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz));
   switch (P) {
     case 1: return apply2d_p<1>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
     case 2: return apply2d_p<2>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
@@ -1266,6 +1305,7 @@ static hipError_t apply2d_dot_p(bool dbl, GType gt, const void* x, void* y, void
 
 hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                        int Nx, int Nz, int masked, double* dotp, hipStream_t st) {
+  acct_add(2 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz));
   switch (P) {
     case 1: return apply2d_dot_p<1>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
     case 2: return apply2d_dot_p<2>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
@@ -1608,6 +1648,12 @@ static hipError_t apply3d_p(bool dbl, GType gt, const void* x, void* y, void* Sx
 hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
                    void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st,
                    Step3 st3) {
+  {
+    const double N3 = (double)(Nx * P + 1) * (Ny * P + 1) * (Nz * P + 1);
+    const double L3 = (double)Nx * Ny * Nz * (P + 1) * (P + 1) * (P + 1);
+    const double nv = st3.b ? 4 + (st3.cd != 0.0) + (st3.store_d ? 1 : 0) : 2;
+    acct_add(vsz(dbl) * N3 * nv + 5 * gsz(gt) * L3);
+  }
   switch (P) {
     case 1: return apply3d_p<1>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
     case 2: return apply3d_p<2>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
@@ -1816,6 +1862,8 @@ hipError_t axis_apply(int in_dbl, int out_dbl, const void* in, const void* in2, 
                       unsigned n_inner, const int* rowptr, const int* cols, const double* w,
                       unsigned nnz, const int* band, const double* wband, int bandmax,
                       unsigned mask_nzn, hipStream_t st) {
+  acct_add((in_dbl ? 8.0 : 4.0) * n_outer * nin * n_inner * (in2 ? 2 : 1) +
+           (out_dbl ? 8.0 : 4.0) * n_outer * nout * n_inner * (accumulate ? 2 : 1) + 12.0 * nnz);
   if (in_dbl && out_dbl)
     return axis_t<double, double>(in, in2, out, accumulate, n_outer, nin, nout, n_inner, rowptr,
                                   cols, w, nnz, band, wband, bandmax, mask_nzn, st);
@@ -1843,6 +1891,7 @@ __global__ __launch_bounds__(256) void k_dense_gemv(const double* __restrict__ A
 }
 
 hipError_t dense_gemv(const double* Ainv, const double* b, double* x, int n, hipStream_t st) {
+  acct_add(8.0 * ((double)n * n + 2.0 * n));
   hipLaunchKernelGGL(k_dense_gemv, dim3((n + 3) / 4), dim3(256), 0, st, Ainv, b, x, n);
   return hipGetLastError();
 }
@@ -1969,6 +2018,7 @@ __global__ void k_smooth_update(T* __restrict__ x, T* __restrict__ d, const T* _
 hipError_t smooth_update(bool dbl, void* x, void* d, const void* b, const void* dinv,
                          const void* y, const void* S, unsigned N, unsigned nzn, unsigned P,
                          double cd, double cr, int mode, int store_d, hipStream_t st) {
+  acct_add(vsz(dbl) * N * ((mode == SU_ZERO ? 3 : mode == SU_AX ? 5 : 4) + (cd != 0.0 && mode != SU_ZERO) + (store_d ? 1 : 0)));
   const unsigned blocks = nblk(N, 256);
   if (dbl)
     hipLaunchKernelGGL(k_smooth_update<double>, dim3(blocks), dim3(256), 0, st, (double*)x,
@@ -1998,6 +2048,7 @@ __global__ void k_smooth_first64(T* __restrict__ x, T* __restrict__ d, T* __rest
 
 hipError_t smooth_first64(bool dbl, void* x, void* d, void* b, const double* r64,
                           const void* dinv, unsigned N, double cr, int store_d, hipStream_t st) {
+  acct_add(8.0 * N + vsz(dbl) * N * (3 + (store_d ? 1 : 0)));
   const unsigned blocks = nblk(N, 256);
   if (dbl)
     hipLaunchKernelGGL(k_smooth_first64<double>, dim3(blocks), dim3(256), 0, st, (double*)x,
@@ -2017,6 +2068,7 @@ __global__ void k_fix_ax(const T* __restrict__ y, const T* __restrict__ S, TO* _
 
 hipError_t fix_ax(bool dbl, const void* y, const void* S, void* out, int out64, unsigned N,
                   unsigned nzn, unsigned P, hipStream_t st) {
+  acct_add((vsz(dbl) + (out64 ? 8.0 : vsz(dbl))) * N);
   const unsigned blocks = nblk(N, 256);
   if (dbl)
     hipLaunchKernelGGL((k_fix_ax<double, double>), dim3(blocks), dim3(256), 0, st,
@@ -2037,6 +2089,7 @@ __global__ void k_cast(const TS* __restrict__ s, TD* __restrict__ d, unsigned N)
 }
 
 hipError_t cast_to(bool dbl_dst, const double* src, void* dst, unsigned N, hipStream_t st) {
+  acct_add((8.0 + vsz(dbl_dst)) * N);
   if (dbl_dst)
     hipLaunchKernelGGL((k_cast<double, double>), dim3(nblk(N, 256)), dim3(256), 0, st, src,
                        (double*)dst, N);
@@ -2047,6 +2100,7 @@ hipError_t cast_to(bool dbl_dst, const double* src, void* dst, unsigned N, hipSt
 }
 
 hipError_t cast_from(bool dbl_src, const void* src, double* dst, unsigned N, hipStream_t st) {
+  acct_add((8.0 + vsz(dbl_src)) * N);
   if (dbl_src)
     hipLaunchKernelGGL((k_cast<double, double>), dim3(nblk(N, 256)), dim3(256), 0, st,
                        (const double*)src, dst, N);
@@ -2064,6 +2118,7 @@ __global__ void k_fill(T* __restrict__ p, T v, size_t n) {
 }
 
 hipError_t fill(bool dbl, void* p, double v, size_t n, hipStream_t st) {
+  acct_add(vsz(dbl) * (double)n);
   const unsigned blocks = (unsigned)(n < (1u << 20) * 256ull ? nblk(n, 256) : (1u << 20));
   if (n == 0) return hipSuccess;
   if (dbl)
@@ -2210,6 +2265,7 @@ static hipError_t restrict2d_p(const void* b, const void* y, const void* S, int 
 hipError_t restrict2d(bool dbl, bool dbl_c, const void* b, const void* y, const void* S,
                       int use_ax, void* rc, const double* J, int Nx, int Nz, int Pf, int Pc,
                       int masked, hipStream_t st, StageFold f) {
+  acct_add(vsz(dbl) * nodes2(Pf, Nx, Nz) * ((use_ax || f.q) ? 2 : 1) + vsz(dbl_c) * nodes2(Pc, Nx, Nz));
   const size_t smem = restrict2d_smem(Pf, Pc, Nz, dbl);
   if (dbl)
     return restrict2d_p<double, double>(b, y, S, use_ax, rc, J, Nx, Nz, Pf, Pc, masked, smem, st, f);
@@ -2312,6 +2368,7 @@ static hipError_t prolong2d_p(const void* ec, void* xf, const double* J, int Nx,
 
 hipError_t prolong2d(bool dbl, bool dbl_c, const void* ec, void* xf, const double* J, int Nx,
                      int Nz, int Pf, int Pc, hipStream_t st, StageFold f) {
+  acct_add(vsz(dbl) * nodes2(Pf, Nx, Nz) * (f.c ? 3 : 2) + vsz(dbl_c) * nodes2(Pc, Nx, Nz));
   const size_t smem = prolong2d_smem(Pf, Pc, Nz, dbl);
   if (dbl) return prolong2d_p<double, double>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
   if (dbl_c) return prolong2d_p<float, double>(ec, xf, J, Nx, Nz, Pf, Pc, smem, st, f);
@@ -2595,6 +2652,8 @@ hipError_t coarse2d(bool pre, const CoarsePlan& pl, int P, int PC, bool dbl, GTy
                     const void* x, void* xo, const void* b, const void* dinv, const void* G,
                     const void* ec, void* rc, const double* J, int Nx, int Nz, int masked,
                     const CoarseSeq& sq, hipStream_t st) {
+  acct_add(vsz(dbl) * nodes2(P, Nx, Nz) * (pre ? 3 : 4) + vsz(dbl_c) * nodes2(PC, Nx, Nz) +
+           3 * gsz(gt) * local2(P, Nx, Nz));
   if (pl.W < 1 || sq.ns < 1 || sq.ns > CO_MAXS) return hipErrorInvalidValue;
 #define SEM_CO(a, c)                                                                            \
   if (P == a && PC == c)                                                                        \
@@ -3068,6 +3127,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_resid64(const double* __restric
 
 hipError_t resid64(const double* b, const double* y, const double* S, double* r, double* prr,
                    double* pbb, unsigned N, unsigned nzn, unsigned P, hipStream_t st) {
+  acct_add(24.0 * N);
   hipLaunchKernelGGL(k_resid64, dim3(NRED), dim3(RED_THREADS), 0, st, b, y, S, r, prr, pbb, N,
                      nzn, P);
   return hipGetLastError();
@@ -3096,6 +3156,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_fixdot64(const double* __restri
 hipError_t fixdot64(const double* y, const double* S, double* q, const double* p, double* ppq,
                     const double* rz_from, double* rz_to, unsigned N, unsigned nzn, unsigned P,
                     hipStream_t st) {
+  acct_add(24.0 * N);
   hipLaunchKernelGGL(k_fixdot64, dim3(NRED), dim3(RED_THREADS), 0, st, y, S, q, p, ppq, rz_from,
                      rz_to, N, nzn, P);
   return hipGetLastError();
@@ -3124,6 +3185,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_update_xr(double* __restrict__ 
 
 hipError_t update_xr(double* x, double* r, const double* p, const double* q, const double* prz,
                      const double* ppq, double* prr, unsigned N, hipStream_t st) {
+  acct_add(48.0 * N);
   hipLaunchKernelGGL(k_update_xr, dim3(NRED), dim3(RED_THREADS), 0, st, x, r, p, q, prz, ppq,
                      prr, N);
   return hipGetLastError();
@@ -3185,6 +3247,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_castdot(const T* __restrict__ x
 
 hipError_t castdot(bool dbl_src, const void* x0, double* z, const double* q, const double* r,
                    double* pzq, double* prz, unsigned N, hipStream_t st) {
+  acct_add(vsz(dbl_src) * N + 8.0 * N * (q ? 3 : 2));
   if (dbl_src)
     hipLaunchKernelGGL(k_castdot<double>, dim3(NRED), dim3(RED_THREADS), 0, st,
                        (const double*)x0, z, q, r, pzq, prz, N);
@@ -3214,6 +3277,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_pupdate(double* __restrict__ p,
 
 hipError_t pupdate(double* p, const double* z, const double* prz_old, const double* ppq,
                    const double* pzq, int first, unsigned N, hipStream_t st) {
+  acct_add(8.0 * N * (first ? 2 : 3));
   hipLaunchKernelGGL(k_pupdate, dim3(NRED), dim3(RED_THREADS), 0, st, p, z, prz_old, ppq, pzq,
                      first, N);
   return hipGetLastError();
@@ -3226,6 +3290,7 @@ __global__ void k_axpy64(double* __restrict__ x, const double* __restrict__ z, d
 }
 
 hipError_t axpy64(double* x, const double* z, double a, unsigned N, hipStream_t st) {
+  acct_add(24.0 * N);
   hipLaunchKernelGGL(k_axpy64, dim3(nblk(N, 256)), dim3(256), 0, st, x, z, a, N);
   return hipGetLastError();
 }
@@ -3255,6 +3320,7 @@ __global__ __launch_bounds__(RED_THREADS) void k_dot_partial(const T* __restrict
 
 hipError_t dot_partial(bool dbl, const void* a, const void* b, double* part, unsigned N,
                        hipStream_t st) {
+  acct_add(2 * vsz(dbl) * N);
   if (dbl)
     hipLaunchKernelGGL(k_dot_partial<double>, dim3(NRED), dim3(RED_THREADS), 0, st,
                        (const double*)a, (const double*)b, part, N);
@@ -3272,6 +3338,7 @@ __global__ void k_vmul(const T* __restrict__ a, const T* __restrict__ s, T* __re
 }
 
 hipError_t vmul(bool dbl, const void* a, const void* s, void* out, unsigned N, hipStream_t st) {
+  acct_add(3 * vsz(dbl) * N);
   if (dbl)
     hipLaunchKernelGGL(k_vmul<double>, dim3(nblk(N, 256)), dim3(256), 0, st, (const double*)a,
                        (const double*)s, (double*)out, N);
@@ -3289,6 +3356,7 @@ __global__ void k_vaxpby(T alpha, const T* a, T beta, const T* b, T* o, unsigned
 
 hipError_t vaxpby(bool dbl, double alpha, const void* a, double beta, const void* b, void* out,
                   unsigned N, hipStream_t st) {
+  acct_add(3 * vsz(dbl) * N);
   if (dbl)
     hipLaunchKernelGGL(k_vaxpby<double>, dim3(nblk(N, 256)), dim3(256), 0, st, alpha,
                        (const double*)a, beta, (const double*)b, (double*)out, N);

@@ -95,6 +95,7 @@ __global__ __launch_bounds__(KT) void k_kry_update(double* __restrict__ x,
 
 hipError_t kry_first(const double* y, const double* S, double* w, const double* V, size_t ldv,
                      int nv, double* part, unsigned N, unsigned nzn, unsigned P, hipStream_t st) {
+  acct_add(8.0 * N * (2 + nv));  // y read, w written, each basis vector read
   if (nv < 0 || nv > KRY_MAX + 1) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_kry_first, dim3(NRED), dim3(KT), 0, st, y, S, w, V, ldv, nv, part, N, nzn,
                      P);
@@ -103,18 +104,21 @@ hipError_t kry_first(const double* y, const double* S, double* w, const double* 
 
 hipError_t kry_sub(double* w, const double* V, size_t ldv, int nv, const KryCoef& h, int dots,
                    double* part, unsigned N, hipStream_t st) {
+  acct_add(8.0 * N * (2 + nv));  // w read and written, each basis vector read
   if (nv < 0 || nv > KRY_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_kry_sub, dim3(NRED), dim3(KT), 0, st, w, V, ldv, nv, h, dots, part, N);
   return hipGetLastError();
 }
 
 hipError_t kry_scale(double* w, double s, unsigned N, hipStream_t st) {
+  acct_add(16.0 * N);
   hipLaunchKernelGGL(k_kry_scale, dim3(NRED), dim3(KT), 0, st, w, s, N);
   return hipGetLastError();
 }
 
 hipError_t kry_update(double* x, const double* Z, size_t ldz, int k, const KryCoef& y,
                       unsigned N, hipStream_t st) {
+  acct_add(8.0 * N * (2 + k));
   if (k < 0 || k > KRY_MAX) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_kry_update, dim3(NRED), dim3(KT), 0, st, x, Z, ldz, k, y, N);
   return hipGetLastError();

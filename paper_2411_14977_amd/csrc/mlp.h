@@ -40,6 +40,7 @@ hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_
 
 hipError_t add_bias(float* Z, const float* b, int rows, int cols, hipStream_t st);
 constexpr int MAX_STAGE_OUT = 96;  // the fused inference kernel handles (P+1)^2 <= 96 (P <= 8)
+constexpr int MAX_STAGE_P3 = 6;    // hexahedra: (P+1)^3 <= 343
 
 struct TrainCfg {
   int epochs = 30, batch = 1024;
@@ -72,7 +73,8 @@ size_t forward_noalloc_bytes();
 // ---- inference state of one solver context (2D element columns) ----------------------------
 struct Stage {
   bool enabled = false;
-  int nin = 0, nout = 0, P = 0, Nx = 0, Nz = 0, nzn = 0;
+  int dim = 2;
+  int nin = 0, nout = 0, P = 0, Nx = 0, Ny = 1, Nz = 0, nyn = 1, nzn = 0;
   size_t E = 0;
   // bf16, padded, transposed (output-major) and stored in MFMA A-operand fragment order:
   // fragment (t, k) of an [M][K] matrix holds rows 16t.., columns 16k.. as 64 lanes x 4 values
@@ -112,5 +114,10 @@ hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* y
 hipError_t features(const double* r, const double* e, const double* Ainv, const float* geo,
                     const float* abar, float* X, float* T, size_t E, int P, int Nz, int nzn,
                     hipStream_t st, const int* elist = nullptr, size_t nrows = 0);
+// The same for hexahedra (3D, X [rows x 7n]; geo [E x 6n]).
+hipError_t features3d(const double* r, const double* e, const double* Ainv, const float* geo,
+                      const float* abar, float* X, float* T, size_t E, int P, int Ny, int Nz,
+                      int nyn, int nzn, hipStream_t st, const int* elist = nullptr,
+                      size_t nrows = 0);
 
 }  // namespace semm

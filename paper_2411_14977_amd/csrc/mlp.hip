@@ -916,10 +916,215 @@ __global__ __launch_bounds__(MLP_THREADS) void k_stage_mlp(
   }
 }
 
+
+// 3D form (hexahedra of n = (P+1)^3 nodes, P <= 6): the same two-wave tile scheme, but the
+// network (2 (128 KR + 128 128 + KR 128) bytes, up to 208 KB at P = 6) does not fit the LDS, so
+// the MFMA A fragments are read from global memory in fragment order (the weights stay in L2);
+// only the exchanged hidden fragments use LDS.  Element e = (ex Ny + ey) Nz + ez, local node
+// (i NP + m) NP + j; c_e written element-major (CE[e n + l]).  The c . r part uses the exact
+// multiplicity weights 1, 1/2, 1/4, 1/8 of nodes on shared faces, edges and corners.
+template <int P, typename T>
+__global__ __launch_bounds__(MLP_THREADS) void k_stage_mlp3d(
+    const T* __restrict__ r, const uint16_t* __restrict__ W1r, const float* __restrict__ Z1geo,
+    const uint16_t* __restrict__ W2, const float* __restrict__ b2,
+    const uint16_t* __restrict__ W3, const float* __restrict__ b3,
+    const float* __restrict__ abar, float* __restrict__ CE, int E, int Nx, int Ny, int Nz,
+    unsigned nyn, unsigned nzn, int masked, double* __restrict__ pcr) {
+  constexpr int NP = P + 1, n = NP * NP * NP, KR = (n + 15) / 16 * 16, KS = KR / 16,
+                NT = NH / 16;
+  constexpr int NTH = NT / 2, K3 = (KS + 1) / 2;
+  __shared__ bf16x4 sH[2][MLP_TILES][NT][64];
+  __shared__ double sred[MLP_THREADS / 64];
+  const bf16x4* F1 = reinterpret_cast<const bf16x4*>(W1r);
+  const bf16x4* F2 = reinterpret_cast<const bf16x4*>(W2);
+  const bf16x4* F3 = reinterpret_cast<const bf16x4*>(W3);
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tile = wave >> 1, h = wave & 1;
+  const int le = lane & 15, kq = (lane >> 4) * 4;
+  const int e = (blockIdx.x * MLP_TILES + tile) * 16 + le;
+  const bool ve = e < E;
+  const int ez = ve ? e % Nz : 0, exy = ve ? e / Nz : 0;
+  const int ey = exy % Ny, ex = exy / Ny;
+  const size_t base = ((size_t)(ex * P) * nyn + (size_t)ey * P) * nzn + (size_t)ez * P;
+  float rv[KS][4];
+  float ss = 0.f;
+#pragma unroll
+  for (int k = 0; k < KS; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int loc = 16 * k + kq + v;
+      rv[k][v] = 0.f;
+      if (ve && loc < n) {
+        const int i = loc / (NP * NP), m = (loc / NP) % NP, j = loc % NP;
+        rv[k][v] = (float)r[base + ((size_t)i * nyn + m) * nzn + j];
+      }
+      ss += rv[k][v] * rv[k][v];
+    }
+  ss += __shfl_xor(ss, 16, 64);
+  ss += __shfl_xor(ss, 32, 64);
+  const float sn = sqrtf(ss);
+  const float sinv = sn > 0.f ? 1.0f / sn : 0.f;
+  bf16x4 xb[KS];
+#pragma unroll
+  for (int k = 0; k < KS; ++k)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) xb[k][v] = (short)f2bf(rv[k][v] * sinv);
+  double part = 0.0;
+  f32x4 acc[NTH];
+  bf16x4 hb[NT];
+  auto layer1 = [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    layer_mfma<NTH, KS>(F1, NTH * H, lane, xb, acc);
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) hb[NTH * H + t][v] = (short)f2bf(gelu(acc[t][v]));
+      sH[0][tile][NTH * H + t][lane] = hb[NTH * H + t];
+    }
+  };
+  auto layer2 = [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) hb[NTH * (1 - H) + t] = sH[0][tile][NTH * (1 - H) + t][lane];
+#pragma unroll
+    for (int t = 0; t < NTH; ++t)
+      acc[t] = *reinterpret_cast<const f32x4*>(b2 + 16 * (NTH * H + t) + kq);
+    layer_mfma<NTH, NT>(F2, NTH * H, lane, hb, acc);
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) hb[NTH * H + t][v] = (short)f2bf(gelu(acc[t][v]));
+      sH[1][tile][NTH * H + t][lane] = hb[NTH * H + t];
+    }
+  };
+  auto layer3 = [&](auto hc) {
+    constexpr int H = decltype(hc)::value;
+    constexpr int T0 = K3 * H;
+#pragma unroll
+    for (int t = 0; t < NTH; ++t) hb[NTH * (1 - H) + t] = sH[1][tile][NTH * (1 - H) + t][lane];
+    const float sc = ve ? sn / abar[e] : 0.f;
+#pragma unroll
+    for (int t = 0; t < K3; ++t) {
+      const int t3 = T0 + t;
+      if (T0 + t >= KS) break;
+      f32x4 c[1] = {*reinterpret_cast<const f32x4*>(b3 + 16 * t3 + kq)};
+      layer_mfma<1, NT>(F3, t3, lane, hb, c);
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int loc = 16 * t3 + kq + v;
+        if (ve && loc < n) {
+          const float ce = sc * c[0][v];
+          const int i = loc / (NP * NP), m = (loc / NP) % NP, j = loc % NP;
+          CE[(size_t)e * n + loc] = ce;
+          const double wx = ((i == 0 && ex > 0) || (i == P && ex < Nx - 1)) ? 0.5 : 1.0;
+          const double wy = ((m == 0 && ey > 0) || (m == P && ey < Ny - 1)) ? 0.5 : 1.0;
+          const double wz = ((j == 0 && ez > 0) || (j == P && ez < Nz - 1)) ? 0.5 : 1.0;
+          const bool top = masked && j == P && ez == Nz - 1;
+          if (!top) part += (double)ce * (double)rv[t3][v] * (wx * wy * wz);
+        }
+      }
+    }
+  };
+  using H0 = std::integral_constant<int, 0>;
+  using H1 = std::integral_constant<int, 1>;
+#pragma unroll
+  for (int t = 0; t < NTH; ++t)
+    acc[t] = ve ? *reinterpret_cast<const f32x4*>(Z1geo + (long)e * NH + 16 * (NTH * h + t) + kq)
+                : (f32x4){0.f, 0.f, 0.f, 0.f};
+  if (h == 0) layer1(H0{}); else layer1(H1{});
+  __syncthreads();
+  if (h == 0) layer2(H0{}); else layer2(H1{});
+  __syncthreads();
+  if (h == 0) layer3(H0{}); else layer3(H1{});
+  part = wsum(part);
+  if (lane == 0) sred[wave] = part;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double tot = 0.0;
+    for (int w = 0; w < MLP_THREADS / 64; ++w) tot += sred[w];
+    pcr[blockIdx.x] = tot;
+  }
+}
+
+// c[g] = average of the element-local corrections of the (up to eight) hexahedra holding node
+// g, zero on the Dirichlet surface when masked; contributions in a fixed order
+template <int P, typename T>
+__global__ __launch_bounds__(256) void k_stage_assemble3d(const float* __restrict__ CE,
+                                                          T* __restrict__ c, int Nx, int Ny,
+                                                          int Nz, unsigned nyn, unsigned nzn,
+                                                          size_t N, int masked) {
+  constexpr int NP = P + 1, n = NP * NP * NP;
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < N;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const int iz = (int)(g % nzn);
+    const size_t gxy = g / nzn;
+    const int iy = (int)(gxy % nyn), ix = (int)(gxy / nyn);
+    if (masked && iz == (int)nzn - 1) {
+      c[g] = (T)0;
+      continue;
+    }
+    int ex[2], lx[2], ey[2], ly[2], ez[2], lz[2], cx = 0, cy = 0, cz = 0;
+    {
+      const int q = ix / P, rr = ix - q * P;
+      if (rr == 0 && q > 0) { ex[cx] = q - 1; lx[cx++] = P; }
+      if (q < Nx) { ex[cx] = q; lx[cx++] = rr; }
+    }
+    {
+      const int q = iy / P, rr = iy - q * P;
+      if (rr == 0 && q > 0) { ey[cy] = q - 1; ly[cy++] = P; }
+      if (q < Ny) { ey[cy] = q; ly[cy++] = rr; }
+    }
+    {
+      const int q = iz / P, rr = iz - q * P;
+      if (rr == 0 && q > 0) { ez[cz] = q - 1; lz[cz++] = P; }
+      if (q < Nz) { ez[cz] = q; lz[cz++] = rr; }
+    }
+    float s = 0.f;
+    for (int a = 0; a < cx; ++a)
+      for (int b = 0; b < cy; ++b)
+        for (int d = 0; d < cz; ++d) {
+          const size_t e = ((size_t)ex[a] * Ny + ey[b]) * Nz + ez[d];
+          s += CE[e * n + ((size_t)lx[a] * NP + ly[b]) * NP + lz[d]];
+        }
+    c[g] = (T)(s / (float)(cx * cy * cz));
+  }
+}
+
 int stage_mlp_blocks(size_t E) { return (int)((E + 16 * MLP_TILES - 1) / (16 * MLP_TILES)); }
 
 hipError_t stage_mlp(const Stage& s, bool dbl, const void* r, int masked, double* pcr,
                      hipStream_t st) {
+  {  // r, the geometric half of layer 1, the element scales and the network read; CE written
+    const double N = (double)(s.Nx * s.P + 1) * s.nyn * s.nzn, KR = pad16(s.nout);
+    semk::acct_add((dbl ? 8.0 : 4.0) * N + 4.0 * s.E * (NH + 1) + 4.0 * s.E * s.nout +
+                   2.0 * (NH * KR + NH * NH + KR * NH) + 4.0 * (NH + KR));
+  }
+  if (s.dim == 3) {
+    if (s.P < 1 || s.P > 6 || s.nout != (s.P + 1) * (s.P + 1) * (s.P + 1)) return hipErrorInvalidValue;
+    const unsigned blocks = (unsigned)stage_mlp_blocks(s.E);
+#define SEM_STAGE_MLP3(PP, TT)                                                                   \
+  hipLaunchKernelGGL((k_stage_mlp3d<PP, TT>), dim3(blocks), dim3(MLP_THREADS), 0, st,           \
+                     (const TT*)r, s.W1r, s.Z1geo, s.W2, s.b2, s.W3, s.b3, s.abar, s.CE,         \
+                     (int)s.E, s.Nx, s.Ny, s.Nz, (unsigned)s.nyn, (unsigned)s.nzn, masked, pcr)
+#define SEM_STAGE_MLP3_P(PP)             \
+  case PP:                               \
+    if (dbl) SEM_STAGE_MLP3(PP, double); \
+    else SEM_STAGE_MLP3(PP, float);      \
+    break;
+    switch (s.P) {
+      SEM_STAGE_MLP3_P(1)
+      SEM_STAGE_MLP3_P(2)
+      SEM_STAGE_MLP3_P(3)
+      SEM_STAGE_MLP3_P(4)
+      SEM_STAGE_MLP3_P(5)
+      SEM_STAGE_MLP3_P(6)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef SEM_STAGE_MLP3_P
+#undef SEM_STAGE_MLP3
+    return hipGetLastError();
+  }
   if (s.P < 1 || s.P > 8 || s.nout != (s.P + 1) * (s.P + 1)) return hipErrorInvalidValue;
   const unsigned blocks = (unsigned)stage_mlp_blocks(s.E);
 #define SEM_STAGE_MLP(PP, TT)                                                                    \
@@ -975,6 +1180,31 @@ __global__ __launch_bounds__(256) void k_stage_assemble(const float* __restrict_
 }
 
 hipError_t stage_assemble(const Stage& s, bool dbl, void* c, int masked, hipStream_t st) {
+  semk::acct_add(4.0 * s.E * s.nout + (dbl ? 8.0 : 4.0) * (double)(s.Nx * s.P + 1) * s.nyn * s.nzn);
+  if (s.dim == 3) {
+    const size_t N = (size_t)(s.Nx * s.P + 1) * s.nyn * s.nzn;
+    const unsigned blocks = (unsigned)std::min<size_t>(nblk(N, 256), 16384);
+#define SEM_STAGE_ASM3(PP, TT)                                                                    \
+  hipLaunchKernelGGL((k_stage_assemble3d<PP, TT>), dim3(blocks), dim3(256), 0, st, s.CE, (TT*)c, \
+                     s.Nx, s.Ny, s.Nz, (unsigned)s.nyn, (unsigned)s.nzn, N, masked)
+    switch (s.P) {
+#define SEM_STAGE_ASM3_P(PP) \
+  case PP:                   \
+    if (dbl) SEM_STAGE_ASM3(PP, double); else SEM_STAGE_ASM3(PP, float); \
+    break;
+      SEM_STAGE_ASM3_P(1)
+      SEM_STAGE_ASM3_P(2)
+      SEM_STAGE_ASM3_P(3)
+      SEM_STAGE_ASM3_P(4)
+      SEM_STAGE_ASM3_P(5)
+      SEM_STAGE_ASM3_P(6)
+      default:
+        return hipErrorInvalidValue;
+    }
+#undef SEM_STAGE_ASM3_P
+#undef SEM_STAGE_ASM3
+    return hipGetLastError();
+  }
   const unsigned N = (unsigned)((size_t)(s.Nx * s.P + 1) * s.nzn);
   const unsigned blocks = std::min(nblk(N, 256), 8192u);
 #define SEM_STAGE_ASM(PP, TT)                                                                   \
@@ -1072,6 +1302,7 @@ hipError_t stage_update(bool dbl, void* x, void* R, const void* c, const void* y
                         const double* pcr, int ncr, const double* pcq, int ncq, int* skips,
                         unsigned N, unsigned nzn, unsigned P, const void* dinv, void* d,
                         double sr, int store_d, hipStream_t st) {
+  semk::acct_add((dbl ? 8.0 : 4.0) * N * (6 + (dinv ? 1 : 0) + (store_d ? 1 : 0)));
   const unsigned blocks = nblk(N, UPD_THREADS * UPD_IT);
   if (dbl)
     hipLaunchKernelGGL(k_stage_update<double>, dim3(blocks), dim3(UPD_THREADS), 0, st, (double*)x,
@@ -1124,6 +1355,56 @@ __global__ __launch_bounds__(128) void k_features(const double* __restrict__ r,
   }
   for (int l = threadIdx.x; l < 4 * n; l += blockDim.x)
     X[(size_t)orow * 5 * n + n + l] = geo[(size_t)el * 4 * n + l];
+}
+
+// the same rows for hexahedra (element e = (ex Ny + ey) Nz + ez, local node (i NP + m) NP + j;
+// X [rows x 7n]: r_e / s_e, then the 6n geometric features of geo)
+__global__ __launch_bounds__(128) void k_features3d(const double* __restrict__ r,
+                                                    const double* __restrict__ e,
+                                                    const double* __restrict__ Ainv,
+                                                    const float* __restrict__ geo,
+                                                    const float* __restrict__ abar,
+                                                    float* __restrict__ X, float* __restrict__ Tt,
+                                                    int P, int Ny, int Nz, int nyn, int nzn,
+                                                    const int* __restrict__ elist) {
+  __shared__ double sh[8];
+  const int orow = blockIdx.x;
+  const int el = elist ? elist[orow] : orow;
+  const int NP = P + 1, n = NP * NP * NP;
+  const int ez = el % Nz, exy = el / Nz, ey = exy % Ny, ex = exy / Ny;
+  auto gnode = [&](int l) {
+    const int i = l / (NP * NP), m = (l / NP) % NP, j = l % NP;
+    return ((size_t)(ex * P + i) * nyn + (size_t)(ey * P + m)) * nzn + ez * P + j;
+  };
+  double s2 = 0.0;
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const double v = r[gnode(l)];
+    s2 += v * v;
+  }
+  const double s = sqrt(bsum(s2, sh));
+  for (int l = threadIdx.x; l < n; l += blockDim.x) {
+    const size_t g = gnode(l);
+    X[(size_t)orow * 7 * n + l] = s > 0 ? (float)(r[g] / s) : 0.f;
+    if (Tt && e) Tt[(size_t)orow * n + l] = s > 0 ? (float)((double)abar[el] / s * e[g]) : 0.f;
+    if (Tt && !e) {
+      double t = 0.0;
+      const double* arow = Ainv + ((size_t)el * n + l) * n;
+      for (int q = 0; q < n; ++q) t += arow[q] * r[gnode(q)];
+      Tt[(size_t)orow * n + l] = s > 0 ? (float)((double)abar[el] / s * t) : 0.f;
+    }
+  }
+  for (int l = threadIdx.x; l < 6 * n; l += blockDim.x)
+    X[(size_t)orow * 7 * n + n + l] = geo[(size_t)el * 6 * n + l];
+}
+
+hipError_t features3d(const double* r, const double* e, const double* Ainv, const float* geo,
+                      const float* abar, float* X, float* T, size_t E, int P, int Ny, int Nz,
+                      int nyn, int nzn, hipStream_t st, const int* elist, size_t nrows) {
+  const size_t rows = elist ? nrows : E;
+  if (rows == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_features3d, dim3((unsigned)rows), dim3(128), 0, st, r, e, Ainv, geo, abar,
+                     X, T, P, Ny, Nz, nyn, nzn, elist);
+  return hipGetLastError();
 }
 
 hipError_t features(const double* r, const double* e, const double* Ainv, const float* geo,

@@ -466,6 +466,13 @@ void coarse_solve(Ctx* c) {
   }
   const semh::BcrPlan& pl = c->plan;
   const int nl = (int)pl.levs.size();
+  {  // block reduction: each factor array read once, the right-hand side and solution
+    auto sz = [&](const void* q) {
+      auto it = c->asize.find(q);
+      return it == c->asize.end() ? 0.0 : (double)it->second;
+    };
+    semk::acct_add(sz(c->bcrF) + sz(c->bcrB) + sz(c->bcrDense) + 4.0 * 8.0 * L.N);
+  }
   if (c->bcrLv.nl >= 0) {
     const double* br = b;
     if (nl > 0) {
@@ -1611,6 +1618,35 @@ sem_status sem_pmg_vcycle(sem_ctx* ctx, const double* r, double* z) {
     leave(c);
     return SEM_OK;
   });
+}
+
+sem_status sem_solve_bytes(sem_ctx* ctx, const double* rhs, double* x, double tol,
+                           double* bytes, int* iters, long* launches) {
+  Ctx* c = C(ctx);
+  if (!c) return SEM_ERR_ARG;
+  if (!bytes) return SEM_ERR_ARG;
+  // the same solve with every launch issued directly (no graph replays), each launch wrapper
+  // adding its algorithmic bytes
+  const bool g = c->use_graphs;
+  {
+    sem_status st0 = guarded(c, [&]() {
+      HK(hipStreamSynchronize(c->st));
+      drop_graphs(c);
+      return SEM_OK;
+    });
+    if (st0 != SEM_OK) return st0;
+  }
+  c->use_graphs = false;
+  sem_solve_info inf{};
+  semk::acct_enable(true);
+  const sem_status st = sem_poisson_solve(ctx, rhs, x, tol, &inf);
+  semk::acct_enable(false);
+  c->use_graphs = g;
+  long n = 0;
+  *bytes = semk::acct_total(&n);
+  if (iters) *iters = inf.iters;
+  if (launches) *launches = n;
+  return st;
 }
 
 sem_status sem_set_smoother_bounds(sem_ctx* ctx, int level, double lambda_hat) {

@@ -328,12 +328,21 @@ def test_benchmark_hooks():
         assert B.sem_time_operator(s.ctx, 0, kind, 3, 0) > 0
     with pytest.raises(B.SemError):
         B.sem_time_operator(s.ctx, 1, 1, 1, 0)   # the outer operator lives on level 0
+    for kind in (0, 1, 2):   # rotated buffers (HBM-resident timing)
+        assert B.sem_time_operator(s.ctx, 0, kind, 3, 2) > 0
     # the hooks overwrite work vectors only: a solve afterwards is unaffected
     m = oc.fine_mesh(wl)
     b = oc.rhs(wl, m)
     x, info, _ = s.solve(T(b), tol=1e-10)
     assert np.linalg.norm(H(x) - assemble.solve_direct(assemble.assemble_operator(m), b)) \
         <= 1e-8 * np.linalg.norm(H(x))
+    # whole-solve byte tally: the same solve issued without graphs gives the same bits; at least
+    # one FP64 operator per iteration, far less than a hundred
+    xb = T(np.zeros(m.N))
+    by, it, nk = B.sem_solve_bytes(s.ctx, T(b), xb, 1e-10)
+    assert it == info.iters and torch.equal(x, xb) and nk > 10 * it
+    outer = B.sem_operator_bytes(s.ctx, 0, 1)
+    assert outer < by / it < 100 * outer
     s.close()
     t = lib_solver("tall")
     with pytest.raises(B.SemError):

@@ -66,29 +66,40 @@ def test_adam_first_step_closed_form():
     assert np.allclose(p1["w"], p["w"] - 0.01 * g["w"] / (np.abs(g["w"]) + 1e-8), rtol=0, atol=1e-15)
 
 
-def _tank():
-    wl = W.tank(4, 2, 3, Lx=0.4)
+def _tank(dim=2):
+    """A small sigma-mapped tank: 2D 4 x 2 elements at P = 3, or 3D 2 x 2 x 2 at P = 2 (depth
+    and surface varying along x and y)."""
+    wl = W.tank(4, 2, 3, Lx=0.4) if dim == 2 else W.tank3d(2, 2, 2, 2, L=0.4)
     m = oc.fine_mesh(wl)
     A = assemble.assemble_operator(m)
     return wl, m, A
 
 
-def test_features_scale_invariance_and_linearity():
-    wl, m, A = _tank()
-    p = mlp.init_params(5 * m.NP ** 2, m.NP ** 2, seed=1)
+def _sizes(m):
+    """(inputs, outputs) of the stage network for mesh m."""
+    n = m.NP ** m.dim
+    return (5 if m.dim == 2 else 7) * n, n
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_features_scale_invariance_and_linearity(dim):
+    wl, m, A = _tank(dim)
+    p = mlp.init_params(*_sizes(m), seed=1)
     r = W.random_vector(m.N, 2)
     r[m.dirichlet_nodes()] = 0
     X1, s1 = mlp.features(m, r)
     X2, s2 = mlp.features(m, 3.5 * r)
+    assert X1.shape == (m.E, _sizes(m)[0])
     assert np.abs(X1 - X2).max() < 1e-14 and np.allclose(s2, 3.5 * s1)
     c1 = mlp.correction(m, p, r, emulate=False)
     c2 = mlp.correction(m, p, 3.5 * r, emulate=False)
     assert np.abs(c2 - 3.5 * c1).max() < 1e-12 * np.abs(c2).max()
 
 
-def test_zero_network_is_skipped():
-    wl, m, A = _tank()
-    p = {k: np.zeros_like(v) for k, v in mlp.init_params(5 * m.NP ** 2, m.NP ** 2, 0).items()}
+@pytest.mark.parametrize("dim", [2, 3])
+def test_zero_network_is_skipped(dim):
+    wl, m, A = _tank(dim)
+    p = {k: np.zeros_like(v) for k, v in mlp.init_params(*_sizes(m), 0).items()}
     b = W.random_vector(m.N, 4)
     b[m.dirichlet_nodes()] = 0
     x0 = np.zeros(m.N)
@@ -96,18 +107,20 @@ def test_zero_network_is_skipped():
     assert not ok and np.array_equal(x1, x0)
 
 
-def test_exact_local_solves_reproduce_additive_schwarz():
+@pytest.mark.parametrize("dim", [2, 3])
+def test_exact_local_solves_reproduce_additive_schwarz(dim):
     """With the network replaced by the exact element solve y_e = (a_e/s_e) (R_e A R_e^T)^{-1} r_e,
     the gather / scaling / weighted assembly plumbing gives W sum_e R_e^T (R_e A R_e^T)^{-1} R_e r,
     the non-overlapping Schwarz preconditioner of Sec. 5.3, computed here independently."""
-    wl, m, A = _tank()
+    wl, m, A = _tank(dim)
+    n = m.NP ** dim
     Ad = A.toarray()
     r = W.random_vector(m.N, 6)
     r[m.dirichlet_nodes()] = 0
     g, mm, a = mlp.element_scales(m)
     X, s = mlp.features(m, r)
     # "network": exact local solves
-    Y = np.zeros((m.E, m.NP ** 2))
+    Y = np.zeros((m.E, n))
     for e in range(m.E):
         idx = m.l2g[e]
         Y[e] = (a[e] / s[e]) * np.linalg.solve(Ad[np.ix_(idx, idx)], r[idx])
@@ -118,8 +131,8 @@ def test_exact_local_solves_reproduce_additive_schwarz():
     S = np.zeros((m.N, m.N))
     Wd = np.zeros(m.N)
     for e in range(m.E):
-        Rm = np.zeros((m.NP ** 2, m.N))
-        Rm[np.arange(m.NP ** 2), m.l2g[e]] = 1.0
+        Rm = np.zeros((n, m.N))
+        Rm[np.arange(n), m.l2g[e]] = 1.0
         S += Rm.T @ np.linalg.inv(Rm @ Ad @ Rm.T) @ Rm
         Wd += np.diag(Rm.T @ Rm)
     ref = (S @ r) / Wd
@@ -127,13 +140,14 @@ def test_exact_local_solves_reproduce_additive_schwarz():
     assert np.abs(c - ref).max() < 1e-10 * np.abs(ref).max()
 
 
-def test_accepted_stage_does_not_increase_energy_error():
-    wl, m, A = _tank()
+@pytest.mark.parametrize("dim", [2, 3])
+def test_accepted_stage_does_not_increase_energy_error(dim):
+    wl, m, A = _tank(dim)
     rng = np.random.default_rng(8)
     xs = assemble.solve_direct(A, W.random_vector(m.N, 9))
     b = A @ xs
     for seed in range(5):
-        p = mlp.init_params(5 * m.NP ** 2, m.NP ** 2, seed)
+        p = mlp.init_params(*_sizes(m), seed)
         x0 = xs + 0.1 * rng.standard_normal(m.N)
         x0[m.dirichlet_nodes()] = xs[m.dirichlet_nodes()]
         x1, ok = mlp.stage(A, m, p, b, x0, emulate=False)
