@@ -224,11 +224,35 @@ def oracle_worker(name, index, path):
                       "gpu_rel_error_vs_oracle": err, "gpu_oracle_rel_res": res}), flush=True)
 
 
-def c5_series(steps, log_every=5):
+def c5_learned_network(args):
+    """Network of the 3D stage: pairs from 4 x 4 x 8 windows of the 3D tank at its element size
+    (sem_learned_harvest on FP64 windows), trained on the GPU; returns (blob, record)."""
+    import struct
+
+    from paper_2411_14977_amd import learned
+    t0 = time.perf_counter()
+    X, T = learned.harvest3d(n_windows=args.c5_train_windows)
+    t1 = time.perf_counter()
+    blob, losses = learned.train(X, T, epochs=args.c5_epochs, batch=512, lr=2e-3)
+    t2 = time.perf_counter()
+    train_loss, val_loss = struct.unpack_from("<2f", blob, 40)
+    rec = {"pairs": int(X.shape[0]), "windows": args.c5_train_windows, "epochs": args.c5_epochs,
+           "inputs": int(X.shape[1]), "harvest_s": t1 - t0, "train_s": t2 - t1,
+           "final_val_loss": val_loss,
+           "recipe": "4x4x8-hexahedron windows of the 64x64x8 tank (0.1 m elements), seeded "
+                     "offsets and surfaces (seeds 5000+), smooth and white-noise sources, 6 "
+                     "defect-correction cycles each plus random residuals; element-block targets"}
+    log(f"[bench] 3D network: {rec['pairs']} pairs, harvest {t1 - t0:.1f} s, train {t2 - t1:.1f} s, "
+        f"val loss {val_loss:.4f}")
+    return blob, rec
+
+
+def c5_series(steps, log_every=5, blob3=None, mode3=1):
     """3D time series (64 x 64 x 8 hexahedra, P = 6, 7.26M nodes): each step moves the free
     surface (sem_mesh_update_surface, preconditioner frozen at t = 0), re-evaluates the drifting
     source at the moved nodes and solves to 1e-10 warm-started from the previous pressure.
-    Mixed precision (FP32 inner, BF16 factors) and plain FP64; solve time timed per step."""
+    Mixed precision (FP32 inner, BF16 factors), the same with the learned stage (when a network
+    is given) and plain FP64; solve time timed per step."""
     import numpy as np
     import torch
 
@@ -243,14 +267,21 @@ def c5_series(steps, log_every=5):
     out = {"workload": "c5: 3D sigma-mapped tank 64x64x8 hexahedra, P=6, levels 6-3-1 then "
                        "h-levels 32x32, 16x16, 8x8 at P=1 (dense exact), dt = 0.01 s",
            "n_global": wl.n_global, "steps": steps}
-    for prec in ("bf16", "f64"):
+    runs = [("bf16", "bf16", 0)]
+    if blob3 is not None:
+        runs.append(("bf16_learned", "bf16", mode3))
+    runs.append(("f64", "f64", 0))
+    for tag, prec, mode in runs:
         t0 = time.perf_counter()
         s = cases.make_solver(wl, prec=prec)
+        if mode:
+            s.learned_load(blob3, mode)
         t_setup = time.perf_counter() - t0
         ms_op = B.sem_time_operator(s.ctx, 0, 0, 20, 0)
         by_op = B.sem_operator_bytes(s.ctx, 0, 0)
+        ms_op_hbm = B.sem_time_operator(s.ctx, 0, 0, 20, 2)
         x = torch.zeros(s.n_global, dtype=torch.float64, device="cuda")
-        solve_ms, iters, upd_ms = [], [], []
+        solve_ms, iters, upd_ms, skips = [], [], [], 0
         for k in range(steps):
             t = 0.01 * k
             eta = W.surface_3d(X, Y, t, wl.Lx, wl.surface_seed)
@@ -268,18 +299,26 @@ def c5_series(steps, log_every=5):
             torch.cuda.synchronize()
             solve_ms.append((time.perf_counter() - a0) * 1e3)
             iters.append(info.iters)
+            skips += info.learned_skips
             if log_every and k % log_every == 0:
-                log(f"[bench] c5 {prec} step {k}: {info.iters} iterations, {solve_ms[-1]:.1f} ms")
+                log(f"[bench] c5 {tag} step {k}: {info.iters} iterations, {solve_ms[-1]:.1f} ms")
         s.close()
         ms = float(np.mean(solve_ms[1:] if steps > 1 else solve_ms))
-        out[prec] = {"setup_s": t_setup, "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
-                     "gdof_per_s": wl.n_global / (ms * 1e-3) / 1e9,
-                     "iters_mean": float(np.mean(iters)), "iters_first": iters[0],
-                     "surface_update_ms": float(np.mean(upd_ms)),
-                     "operator_us": ms_op * 1e3,
-                     "operator_gb_per_s": by_op / (ms_op * 1e-3) / 1e9}
+        out[tag] = {"setup_s": t_setup, "ms_per_solve": ms, "solves_per_s": 1e3 / ms,
+                    "gdof_per_s": wl.n_global / (ms * 1e-3) / 1e9,
+                    "iters_mean": float(np.mean(iters)), "iters_first": iters[0],
+                    "surface_update_ms": float(np.mean(upd_ms)),
+                    "operator_us": ms_op * 1e3,
+                    "operator_gb_per_s": by_op / (ms_op * 1e-3) / 1e9,
+                    "operator_us_hbm_resident": ms_op_hbm * 1e3,
+                    "operator_gb_per_s_hbm_resident": by_op / (ms_op_hbm * 1e-3) / 1e9}
+        if mode:
+            out[tag]["placement"] = mode
+            out[tag]["learned_skips"] = skips
     out["speedup_mixed_vs_fp64"] = out["f64"]["ms_per_solve"] / out["bf16"]["ms_per_solve"]
-    out["learned_stage"] = "not built for 3D (the stage is 2D; 343-node elements need a wider network)"
+    if blob3 is not None:
+        out["speedup_learned_vs_fp64"] = (out["f64"]["ms_per_solve"] /
+                                          out["bf16_learned"]["ms_per_solve"])
     return out
 
 
@@ -469,6 +508,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--op-reps", type=int, default=50)
     ap.add_argument("--c5-steps", type=int, default=20, help="3D time-series steps (0: skip)")
+    ap.add_argument("--c5-train-windows", type=int, default=16,
+                    help="3D training windows of the 3D learned stage (0: no 3D stage)")
+    ap.add_argument("--c5-epochs", type=int, default=200)
     ap.add_argument("--no-c3", action="store_true", help="skip the c3 mixed-precision error table")
     ap.add_argument("--no-schwarz", action="store_true", help="skip the Schwarz-smoother rows")
     ap.add_argument("--no-context", action="store_true",
@@ -654,10 +696,18 @@ def main():
 
     c5 = None
     if args.c5_steps > 0:
-        c5 = c5_series(args.c5_steps)
-        log(f"[bench] c5 series: mixed {c5['bf16']['ms_per_solve']:.1f} ms "
-            f"({c5['bf16']['iters_mean']:.1f} it), fp64 {c5['f64']['ms_per_solve']:.1f} ms "
-            f"({c5['f64']['iters_mean']:.1f} it)")
+        blob3, rec3 = (None, None)
+        if args.c5_train_windows > 0:
+            blob3, rec3 = c5_learned_network(args)
+        c5 = c5_series(args.c5_steps, blob3=blob3)
+        c5["training"] = rec3
+        msg = (f"[bench] c5 series: mixed {c5['bf16']['ms_per_solve']:.1f} ms "
+               f"({c5['bf16']['iters_mean']:.1f} it), fp64 {c5['f64']['ms_per_solve']:.1f} ms "
+               f"({c5['f64']['iters_mean']:.1f} it)")
+        if blob3 is not None:
+            msg += (f", mixed + learned {c5['bf16_learned']['ms_per_solve']:.1f} ms "
+                    f"({c5['bf16_learned']['iters_mean']:.1f} it)")
+        log(msg)
 
     if parity_procs:
         log("[bench] waiting for the oracle's solves of the unseen surfaces ...")

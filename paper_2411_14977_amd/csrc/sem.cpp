@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <exception>
 #include <functional>
 #include <thread>
@@ -545,6 +546,24 @@ void learned_stage(Ctx* c, bool post = false, semk::StageFold* f = nullptr) {
                         dinv, L.d, sr, store_d, c->st));
 }
 
+// learned stage on the fine level of a 3D mesh: r = b - A x, the network's element corrections,
+// their average c, q = A c, and the judged update x += alpha c (alpha = c.r / c.q)
+void learned_stage3d(Ctx* c) {
+  DLevel& L = c->lev[0];
+  semm::Stage& s = c->stage;
+  const int ncr = semm::stage_mlp_blocks(s.E);
+  double* pcr = c->stparts;
+  double* pcq = c->stparts + ncr;
+  apply_level(c, 0, L.x, c->masked);
+  HK(semk::vaxpby(L.dbl, 1.0, L.b, -1.0, L.y, c->Rbuf, L.N, c->st));
+  HK(semm::stage_mlp(s, L.dbl, c->Rbuf, c->masked, pcr, c->st));
+  HK(semm::stage_assemble(s, L.dbl, c->cbuf, c->masked, c->st));
+  apply_level(c, 0, c->cbuf, c->masked);
+  HK(semk::dot_partial(L.dbl, c->cbuf, L.y, pcq, L.N, c->st));
+  HK(semm::stage_update(L.dbl, L.x, c->Rbuf, c->cbuf, L.y, nullptr, pcr, ncr, pcq, semk::NRED,
+                        s.skips, L.N, L.nzn, L.P, nullptr, L.d, 0.0, 0, c->st));
+}
+
 // z = B r on level 0 buffers: input r (FP64, device), output lev[0].x
 // the step coefficients of level l's smoothing sequence (as smooth() takes them) and the number
 // of operator applies of its one-kernel form; false when that form does not apply
@@ -621,7 +640,8 @@ void vcycle(Ctx* c, const double* r) {
     if (l >= 1 && coarse_fused(c, l, true)) continue;
     smooth(c, l, true);
     if (l == 0) c->vin64 = nullptr;
-    if (l == 0 && c->stage.enabled && (c->stage_mode & 1)) {
+    if (l == 0 && c->dim == 3 && c->stage.enabled && (c->stage_mode & 1)) learned_stage3d(c);
+    if (l == 0 && c->dim == 2 && c->stage.enabled && (c->stage_mode & 1)) {
       learned_stage(c, false, &fold);  // the step goes into the transfers when fold.q is set
       DLevel& F = c->lev[0];
       DLevel& C1 = c->lev[1];
@@ -642,7 +662,8 @@ void vcycle(Ctx* c, const double* r) {
     } else {
       prolong_from(c, l);
     }
-    if (l == 0 && c->stage.enabled && (c->stage_mode & 2)) {
+    if (l == 0 && c->dim == 3 && c->stage.enabled && (c->stage_mode & 2)) learned_stage3d(c);
+    if (l == 0 && c->dim == 2 && c->stage.enabled && (c->stage_mode & 2)) {
       const bool fold = c->desc.smoother != SEM_SMOOTH_SCHWARZ;
       learned_stage(c, fold);  // with fold, also the first post-smoothing step from its residual
       smooth(c, l, false, c->Rbuf, fold);
@@ -841,7 +862,12 @@ void lanczos(Ctx* c, int l) {
 
 // learned-stage geometry of the fine level (2D): per-element features and mean element-matrix
 // diagonal, from the level's current geometry
+void learned_geometry3d(Ctx* c);
 void learned_geometry(Ctx* c) {
+  if (c->dim == 3) {
+    learned_geometry3d(c);
+    return;
+  }
   const semh::LevelGeom& G = c->lev[0].geo;
   const int NP = G.NP, n = NP * NP;
   const size_t E = G.E, NL = n;
@@ -871,6 +897,51 @@ void learned_geometry(Ctx* c) {
       out[n + l] = (float)(Grs[l] / g);
       out[2 * n + l] = (float)(Gss[l] / g);
       out[3 * n + l] = (float)(ms[l] / mm);
+    }
+    c->abar_h[e] = (float)(dsum / n);
+  }
+}
+
+// the same for hexahedra (P <= 6): [G_rr, G_tt, G_rs, G_ts, G_ss] / g_e with g_e the element mean
+// of G_rr + G_tt + G_ss, then m_e / mean(m_e) (6n values per element), and a_e the mean of
+// diag(A_e): sum_k D_ki^2 G_rr + D_km^2 G_tt + D_kj^2 G_ss along the three lines through the node,
+// plus 2 D_ii D_jj G_rs + 2 D_mm D_jj G_ts at the node itself
+void learned_geometry3d(Ctx* c) {
+  const semh::LevelGeom& G = c->lev[0].geo;
+  const int NP = G.NP, n = NP * NP * NP;
+  if (G.P > semm::MAX_STAGE_P3) {
+    c->geo_h.clear();
+    c->abar_h.clear();
+    return;
+  }
+  const size_t E = G.E, NL = n;
+  c->geo_h.assign(E * 6 * n, 0.f);
+  c->abar_h.assign(E, 0.f);
+  const double* Dm = G.D.data();
+  for (size_t e = 0; e < E; ++e) {
+    const double* F[5];
+    for (int f = 0; f < 5; ++f) F[f] = &G.G[(size_t)f * E * NL + e * NL];
+    const double* ms = &G.mass[e * NL];
+    double gsum = 0, msum = 0, dsum = 0;
+    for (int l = 0; l < n; ++l) {
+      gsum += F[0][l] + F[1][l] + F[4][l];
+      msum += ms[l];
+      const int i = l / (NP * NP), m = (l / NP) % NP, j = l % NP;
+      double dl = 0;
+      for (int k = 0; k < NP; ++k) {
+        dl += Dm[k * NP + i] * Dm[k * NP + i] * F[0][(k * NP + m) * NP + j];
+        dl += Dm[k * NP + m] * Dm[k * NP + m] * F[1][(i * NP + k) * NP + j];
+        dl += Dm[k * NP + j] * Dm[k * NP + j] * F[4][(i * NP + m) * NP + k];
+      }
+      dl += 2.0 * Dm[i * NP + i] * Dm[j * NP + j] * F[2][l];
+      dl += 2.0 * Dm[m * NP + m] * Dm[j * NP + j] * F[3][l];
+      dsum += dl;
+    }
+    const double g = gsum / n, mm = msum / n;
+    float* out = &c->geo_h[e * 6 * n];
+    for (int l = 0; l < n; ++l) {
+      for (int f = 0; f < 5; ++f) out[f * n + l] = (float)(F[f][l] / g);
+      out[5 * n + l] = (float)(ms[l] / mm);
     }
     c->abar_h[e] = (float)(dsum / n);
   }
@@ -1157,6 +1228,7 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
     c->nAinv = n;
     for (int l = 0; l + 1 < nl; ++l) lanczos(c, l);
   }
+  learned_geometry(c);
   HK(hipStreamSynchronize(c->st));
 }
 
@@ -2019,16 +2091,19 @@ size_t sem_mlp_blob_size(int nin, int nout) {
 static void stage_buffers(Ctx* c) {
   if (c->stage_alloc) return;
   DLevel& L = c->lev[0];
-  const int n = L.NP * L.NP;
+  const int n = c->dim == 3 ? L.NP * L.NP * L.NP : L.NP * L.NP;
   const size_t E = L.geo.E;
   semm::Stage& s = c->stage;
+  s.dim = c->dim;
   s.P = L.P;
   s.Nx = L.Nx;
+  s.Ny = c->dim == 3 ? L.Ny : 1;
   s.Nz = L.Nz;
+  s.nyn = c->dim == 3 ? L.nyn : 1;
   s.nzn = L.nzn;
   s.E = E;
   s.nout = n;
-  s.nin = 5 * n;
+  s.nin = (c->dim == 3 ? 7 : 5) * n;
   const int KR = semm::pad16(n), N3 = semm::pad16(n);
   s.W1r = (uint16_t*)dalloc(c, (size_t)KR * semm::NH * 2);
   s.W2 = (uint16_t*)dalloc(c, (size_t)semm::NH * semm::NH * 2);
@@ -2043,17 +2118,73 @@ static void stage_buffers(Ctx* c) {
   c->Rbuf = dalloc(c, L.N * eb);
   c->cbuf = dalloc(c, L.N * eb);
   c->yq = dalloc(c, L.N * eb);
-  c->Sq = dalloc(c, L.nS * eb);
-  c->stparts = (double*)dalloc(
-      c, ((size_t)semm::stage_mlp_blocks(E) +
-          std::max(semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl),
-                   semk::cheb2d_blocks(L.P, L.Nx, L.Nz, L.dbl))) *
-             8);
+  c->Sq = c->dim == 2 ? dalloc(c, L.nS * eb) : nullptr;
+  const size_t ncq = c->dim == 2 ? (size_t)std::max(semk::apply2d_blocks(L.P, L.Nx, L.Nz, L.dbl),
+                                                    semk::cheb2d_blocks(L.P, L.Nx, L.Nz, L.dbl))
+                                 : (size_t)semk::NRED;
+  c->stparts = (double*)dalloc(c, ((size_t)semm::stage_mlp_blocks(E) + ncq) * 8);
   c->stage_alloc = true;
 }
 
 // inverses of the element blocks R_e A R_e^T of the masked assembled fine operator (host FP64)
+// 3D: R_e A R_e^T from the element matrices of e and its (up to 26) neighbours, each entry the
+// sum over the hexahedra that hold both nodes; surface rows and columns masked; then inverted
+static std::vector<double> element_block_inverses3d(Ctx* c) {
+  const semh::LevelGeom& G = c->lev[0].geo;
+  const int NP = G.NP, P = G.P, n = NP * NP * NP;
+  const size_t E = G.E, nn = (size_t)n * n;
+  const int Nx = G.Nx, Ny = G.Ny, Nz = G.Nz;
+  std::vector<double> Ae(E * nn);
+  parallel_ranges(E, [&](size_t lo, size_t hi) {
+    for (size_t e = lo; e < hi; ++e) semh::element_matrix(G, G.G, e, &Ae[e * nn]);
+  });
+  std::vector<double> out(E * nn);
+  std::atomic<bool> singular{false};
+  parallel_ranges(E, [&](size_t lo, size_t hi) {
+    std::vector<double> Ab(nn), Ai(nn);
+    std::vector<int> map(n);
+    for (size_t e = lo; e < hi; ++e) {
+      const int ez = (int)(e % Nz), exy = (int)(e / Nz), ey = exy % Ny, ex = exy / Ny;
+      std::fill(Ab.begin(), Ab.end(), 0.0);
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            const int fx = ex + dx, fy = ey + dy, fz = ez + dz;
+            if (fx < 0 || fx >= Nx || fy < 0 || fy >= Ny || fz < 0 || fz >= Nz) continue;
+            const size_t f = ((size_t)fx * Ny + fy) * Nz + fz;
+            // local index in e of each node of f (-1: not in e)
+            for (int l = 0; l < n; ++l) {
+              const int i = l / (NP * NP) + dx * P, m = (l / NP) % NP + dy * P, j = l % NP + dz * P;
+              map[l] = (i >= 0 && i <= P && m >= 0 && m <= P && j >= 0 && j <= P)
+                           ? (i * NP + m) * NP + j
+                           : -1;
+            }
+            const double* A = &Ae[f * nn];
+            for (int a = 0; a < n; ++a) {
+              if (map[a] < 0) continue;
+              for (int b = 0; b < n; ++b)
+                if (map[b] >= 0) Ab[(size_t)map[a] * n + map[b]] += A[(size_t)a * n + b];
+            }
+          }
+      if (c->masked && ez == Nz - 1)
+        for (int a = 0; a < n; ++a)
+          if (a % NP == P)
+            for (int b = 0; b < n; ++b) {
+              Ab[(size_t)a * n + b] = Ab[(size_t)b * n + a] = 0.0;
+            }
+      if (c->masked && ez == Nz - 1)
+        for (int a = 0; a < n; ++a)
+          if (a % NP == P) Ab[(size_t)a * n + a] = 1.0;
+      if (!semh::dense_inverse_public(n, Ab.data(), Ai.data())) singular = true;
+      std::copy(Ai.begin(), Ai.end(), out.begin() + e * nn);
+    }
+  });
+  if (singular) throw ArgFail{"singular element block"};
+  return out;
+}
+
 static std::vector<double> element_block_inverses(Ctx* c) {
+  if (c->dim == 3) return element_block_inverses3d(c);
   const semh::LevelGeom& G = c->lev[0].geo;
   const int NP = G.NP, n = NP * NP;
   const size_t E = G.E;
@@ -2112,19 +2243,21 @@ static std::vector<uint16_t> bf16_vec(const float* p, size_t rows, size_t cols, 
 
 // internal: load a network into the stage (see sem_learned_load); keeps a copy of the blob
 static void learned_load_impl(Ctx* c, const void* blob, size_t nbytes, int enable) {
-  if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
   semm::Net net;
   std::string e;
   if (!semm::net_from_blob(blob, nbytes, net, e)) throw ArgFail{e};
   DLevel& L = c->lev[0];
-  const int n = L.NP * L.NP;
-  if (n > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
-  if (net.nin != 5 * n || net.nout != n) throw ArgFail{"network sizes do not match the mesh"};
+  const bool d3 = c->dim == 3;
+  const int n = d3 ? L.NP * L.NP * L.NP : L.NP * L.NP;
+  const int nfg = d3 ? 6 : 4;  // geometric feature blocks (factor fields and mass)
+  if (!d3 && n > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
+  if (d3 && L.P > semm::MAX_STAGE_P3) throw ArgFail{"learned stage on hexahedra needs fine order P <= 6"};
+  if (net.nin != (1 + nfg) * n || net.nout != n) throw ArgFail{"network sizes do not match the mesh"};
   if (c->lev.size() < 2) throw ArgFail{"learned stage needs at least two levels"};
   HK(hipStreamSynchronize(c->st));
   stage_buffers(c);
   semm::Stage& s = c->stage;
-  const int NH = semm::NH, KR = semm::pad16(n), N3 = semm::pad16(n), K4 = semm::pad16(4 * n);
+  const int NH = semm::NH, KR = semm::pad16(n), N3 = semm::pad16(n), K4 = semm::pad16(nfg * n);
   const size_t E = s.E, Mp = (E + 15) / 16 * 16;
   auto put16 = [&](uint16_t* dst, const std::vector<uint16_t>& h) {
     HK(hipMemcpy(dst, h.data(), h.size() * 2, hipMemcpyHostToDevice));
@@ -2157,8 +2290,8 @@ static void learned_load_impl(Ctx* c, const void* blob, size_t nbytes, int enabl
   std::copy(net.b3.begin(), net.b3.end(), b3.begin());
   HK(hipMemcpy(s.b3, b3.data(), N3 * 4, hipMemcpyHostToDevice));
   // Z1geo = Xg W1g + b1 (geometric part of layer 1), computed once per mesh on the GPU
-  std::vector<uint16_t> xg = bf16_vec(c->geo_h.data(), E, 4 * n, Mp, K4);
-  std::vector<uint16_t> w1g = bf16_vec(net.W1.data() + (size_t)n * NH, 4 * n, NH, K4, NH);
+  std::vector<uint16_t> xg = bf16_vec(c->geo_h.data(), E, nfg * n, Mp, K4);
+  std::vector<uint16_t> w1g = bf16_vec(net.W1.data() + (size_t)n * NH, nfg * n, NH, K4, NH);
   void *dx = nullptr, *dw = nullptr, *dz = nullptr, *db = nullptr;
   HK(hipMalloc(&dx, xg.size() * 2));
   HK(hipMalloc(&dw, w1g.size() * 2));
@@ -2355,7 +2488,7 @@ static void rebuild_levels(Ctx* c) {
     }
     for (int l = 0; l + 1 < nl; ++l) lanczos(c, l);
   }
-  if (c->dim == 2) {
+  {
     learned_geometry(c);
     c->geo_d = nullptr;   // re-uploaded (and element-block inverses recomputed) on next use
     c->ainv_d = nullptr;
@@ -2434,24 +2567,49 @@ sem_status sem_launch_shape(const sem_ctx* ctx, int level, int* cols_per_block, 
   return SEM_OK;
 }
 
+// training rows of the fine level (2D or 3D) for the elements in elist (null: all, in order)
+static void stage_features(Ctx* c, const double* r, const double* e, float* X, float* T,
+                           const int* elist, size_t nrows) {
+  DLevel& L = c->lev[0];
+  if (c->dim == 3)
+    HK(semm::features3d(r, e, c->ainv_d, c->geo_d, c->stage.abar, X, T, L.geo.E, L.P, L.Ny, L.Nz,
+                        L.nyn, L.nzn, c->st, elist, nrows));
+  else
+    HK(semm::features(r, e, c->ainv_d, c->geo_d, c->stage.abar, X, T, L.geo.E, L.P, L.Nz, L.nzn,
+                      c->st, elist, nrows));
+}
+
+// the fine level can carry the stage: 2D P <= 8, 3D P <= 6
+static void check_stage_mesh(Ctx* c) {
+  DLevel& L = c->lev[0];
+  if (c->dim == 2 && L.NP * L.NP > semm::MAX_STAGE_OUT)
+    throw ArgFail{"learned stage needs fine order P <= 8"};
+  if (c->dim == 3 && L.P > semm::MAX_STAGE_P3)
+    throw ArgFail{"learned stage on hexahedra needs fine order P <= 6"};
+}
+
+// element-block inverses of the fine level for the training targets (training meshes only)
+static void need_block_inverses(Ctx* c) {
+  if (c->ainv_d) return;
+  const size_t E = c->lev[0].geo.E;
+  if ((c->dim == 2 && E > 4096) || (c->dim == 3 && E > 1024))
+    throw ArgFail{"element-block targets are for training meshes (<= 4096 elements in 2D, "
+                  "<= 1024 in 3D)"};
+  c->ainv_d = upload(c, element_block_inverses(c));
+}
+
 sem_status sem_learned_features(sem_ctx* ctx, const double* r, const double* e, float* X,
                                 float* T) {
   Ctx* c = C(ctx);
   return guarded(c, [&]() {
-    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
     if (!r || !X) throw ArgFail{"null vector"};
-    DLevel& L = c->lev[0];
-    if (L.NP * L.NP > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
+    check_stage_mesh(c);
     HK(hipStreamSynchronize(c->st));
     stage_buffers(c);
     if (!c->geo_d) c->geo_d = upload(c, c->geo_h);
-    if (T && !e && !c->ainv_d) {
-      if (L.geo.E > 4096) throw ArgFail{"element-block targets are for training meshes (<= 4096 elements)"};
-      c->ainv_d = upload(c, element_block_inverses(c));
-    }
+    if (T && !e) need_block_inverses(c);
     enter(c);
-    HK(semm::features(r, e, c->ainv_d, c->geo_d, c->stage.abar, X, T, L.geo.E, L.P, L.Nz, L.nzn,
-                      c->st));
+    stage_features(c, r, e, X, T, nullptr, 0);
     leave(c);
     return SEM_OK;
   });
@@ -2473,10 +2631,9 @@ static void stage_point_residual(Ctx* c) {
 static size_t harvest_rows(Ctx* c, const double* r, int per, unsigned long long seed,
                            unsigned long long* ctr, float* X, float* T) {
   DLevel& L = c->lev[0];
-  const size_t E = L.geo.E, n = (size_t)L.NP * L.NP;
+  const size_t E = L.geo.E;
   if (per <= 0 || (size_t)per >= E) {
-    HK(semm::features(r, nullptr, c->ainv_d, c->geo_d, c->stage.abar, X, T, E, L.P, L.Nz, L.nzn,
-                      c->st));
+    stage_features(c, r, nullptr, X, T, nullptr, 0);
     return E;
   }
   std::vector<int> idx(E);
@@ -2488,10 +2645,8 @@ static size_t harvest_rows(Ctx* c, const double* r, int per, unsigned long long 
     std::swap(idx[k], idx[j]);
   }
   HK(hipMemcpyAsync(c->harvest_idx, idx.data(), per * sizeof(int), hipMemcpyHostToDevice, c->st));
-  HK(semm::features(r, nullptr, c->ainv_d, c->geo_d, c->stage.abar, X, T, E, L.P, L.Nz, L.nzn,
-                    c->st, c->harvest_idx, (size_t)per));
+  stage_features(c, r, nullptr, X, T, c->harvest_idx, (size_t)per);
   HK(hipStreamSynchronize(c->st));  // idx is a host vector
-  (void)n;
   return (size_t)per;
 }
 
@@ -2499,18 +2654,16 @@ sem_status sem_learned_harvest(sem_ctx* ctx, const double* b, int cycles, int pe
                                unsigned long long seed, float* X, float* T, size_t* rows) {
   Ctx* c = C(ctx);
   return guarded(c, [&]() {
-    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
     if (!b || !X || !T) throw ArgFail{"null vector"};
     if (cycles < 0 || cycles > 1000 || per < 0) throw ArgFail{"bad cycles / per"};
     if (!c->masked) return SEM_ERR_STATE;
     DLevel& L = c->lev[0];
-    if (L.NP * L.NP > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
+    check_stage_mesh(c);
     if (c->lev.size() < 2) throw ArgFail{"harvesting needs at least two levels"};
-    if (L.geo.E > 4096) throw ArgFail{"element-block targets are for training meshes (<= 4096 elements)"};
     HK(hipStreamSynchronize(c->st));
     stage_buffers(c);
     if (!c->geo_d) c->geo_d = upload(c, c->geo_h);
-    if (!c->ainv_d) c->ainv_d = upload(c, element_block_inverses(c));
+    need_block_inverses(c);
     if (!c->harvest_idx) c->harvest_idx = (int*)dalloc(c, L.geo.E * sizeof(int));
     // the stage must not act inside the cycles that generate its own training data
     struct Restore {
@@ -2520,7 +2673,8 @@ sem_status sem_learned_harvest(sem_ctx* ctx, const double* b, int cycles, int pe
     } restore{c->stage.enabled, c->stage.enabled};
     c->stage.enabled = false;
     enter(c);
-    const size_t N = L.N, n = (size_t)L.NP * L.NP;
+    const size_t N = L.N, n = c->dim == 3 ? (size_t)L.NP * L.NP * L.NP : (size_t)L.NP * L.NP;
+    const size_t nin = (c->dim == 3 ? 7 : 5) * n;
     unsigned long long ctr = 0;
     size_t out = 0;
     if (cycles == 0) {  // b itself is a residual of the correction problem
@@ -2533,7 +2687,7 @@ sem_status sem_learned_harvest(sem_ctx* ctx, const double* b, int cycles, int pe
         apply_outer(c, c->xo, c->masked);
         HK(semk::resid64(b, c->yo, c->So, c->ro, pset(c, PS_RR), nullptr, L.N, L.nzn, L.P, c->st));
         stage_point_residual(c);
-        out += harvest_rows(c, c->qo, per, seed, &ctr, X + out * 5 * n, T + out * n);
+        out += harvest_rows(c, c->qo, per, seed, &ctr, X + out * nin, T + out * n);
         vcycle(c, c->ro);
         HK(semk::cast_from(L.dbl, L.x, c->zo, L.N, c->st));
         HK(semk::axpy64(c->xo, c->zo, 1.0, L.N, c->st));
@@ -2550,10 +2704,11 @@ sem_status sem_learned_train(sem_ctx* ctx, const float* X, const float* T, int n
                              const sem_train_cfg* cfg, void* blob, size_t* nbytes) {
   Ctx* c = C(ctx);
   return guarded(c, [&]() {
-    if (c->dim != 2) throw ArgFail{"the learned stage is built for 2D meshes"};
     if (!X || !T || !blob || !nbytes) throw ArgFail{"null argument"};
+    check_stage_mesh(c);
     const DLevel& L = c->lev[0];
-    const int nout = L.NP * L.NP, nin = 5 * nout;
+    const int nout = c->dim == 3 ? L.NP * L.NP * L.NP : L.NP * L.NP;
+    const int nin = (c->dim == 3 ? 7 : 5) * nout;
     const size_t need = semm::blob_size(nin, nout);
     if (*nbytes < need) throw ArgFail{"blob buffer too small (see sem_mlp_blob_size)"};
     semm::TrainCfg tc;
@@ -2601,7 +2756,8 @@ sem_status sem_learned_stage(sem_ctx* ctx, const double* b, double* x, int* acce
     HK(hipMemcpyAsync(&before, c->stage.skips, 4, hipMemcpyDeviceToHost, c->st));
     HK(semk::cast_to(L.dbl, b, L.b, L.N, c->st));
     HK(semk::cast_to(L.dbl, x, L.x, L.N, c->st));
-    learned_stage(c);
+    if (c->dim == 3) learned_stage3d(c);
+    else learned_stage(c);
     HK(semk::cast_from(L.dbl, L.x, x, L.N, c->st));
     HK(hipMemcpyAsync(&after, c->stage.skips, 4, hipMemcpyDeviceToHost, c->st));
     HK(hipStreamSynchronize(c->st));

@@ -59,13 +59,92 @@ def training_solver(s, P=8, smoother="chebyshev", layout="tank"):
     return sv, lambda xg, zg, j: W.bumps(xg + x0, zg, TANK_L, 6000 + 7 * s + j, h_fn, eta_fn)
 
 
+TANK3_L = 6.4
+WINDOW3 = (4, 4, 8)   # hexahedra of one 3D training window (x, y, sigma)
+
+
+def training_solver3d(s, P=6, smoother="chebyshev"):
+    """FP64 solver of 3D training window s: 4 x 4 x 8 hexahedra of the 64 x 64 x 8 tank at its
+    element size (0.1 m), seeded offset, the tank's bathymetry and a seeded free surface (seeds
+    5000+, disjoint from the tank's); with its source term f(x, y, z, j)."""
+    Nx, Ny, Nz = WINDOW3
+    dx = TANK3_L / 64
+    rng = np.random.default_rng(9500 + s)
+    x0, y0 = rng.uniform(0.0, TANK3_L - Nx * dx, size=2)
+
+    def h_fn(a, b):
+        return W.bar_depth_3d(np.asarray(a) + x0, np.asarray(b) + y0, TANK3_L, 300)
+
+    def eta_fn(a, b):
+        return W.surface_3d(np.asarray(a) + x0, np.asarray(b) + y0, 0.0, TANK3_L, 5000 + s)
+
+    xs = fine_x_nodes(Nx, P, Nx * dx)
+    ys = fine_x_nodes(Ny, P, Ny * dx)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    lv = [6, 3, 1] if P == 6 else _orders(P)
+    sv = Solver(3, (Nx, Ny, Nz), P, (Nx * dx, Ny * dx), h_fn(X, Y), eta_fn(X, Y), levels=lv,
+                prec="f64", smoother=smoother)
+
+    def source(xg, yg, zg, j):
+        return W.bumps_3d(np.asarray(xg) + x0, np.asarray(yg) + y0, zg, 0.0, TANK3_L,
+                          6100 + 7 * s + j,
+                          lambda a, b: W.bar_depth_3d(a, b, TANK3_L, 300),
+                          lambda a, b: W.surface_3d(a, b, 0.0, TANK3_L, 5000 + s))
+    return sv, source
+
+
 def _surface_rows(sv):
-    """Boolean mask of the free-surface (Dirichlet) rows of a 2D solver's global vectors."""
-    xg, zg = sv.coords(0)
-    nzn = int(np.count_nonzero(xg == xg[0]))   # nodes of one vertical line
+    """Boolean mask of the free-surface (Dirichlet) rows of a solver's global vectors (the
+    vertical index is fastest, so the top node of every vertical line)."""
+    c = sv.coords(0)
+    xg = c[0]
+    same = xg == xg[0]
+    if sv.dim == 3:
+        same &= c[1] == c[1][0]
+    nzn = int(np.count_nonzero(same))   # nodes of one vertical line
     m = np.zeros(sv.n_global, dtype=bool)
     m[nzn - 1::nzn] = True
     return m
+
+
+def harvest3d(n_windows=16, n_bump=3, n_white=3, n_cycles=6, n_random=8, per=32, P=6, log=None):
+    """Device tensors X [n x 7(P+1)^3], T [n x (P+1)^3] (float32) from sem_learned_harvest on
+    3D training windows (see training_solver3d)."""
+    import torch
+    n = (P + 1) ** 3
+    E = WINDOW3[0] * WINDOW3[1] * WINDOW3[2]
+    each = per if 0 < per < E else E
+    calls = n_windows * ((n_bump + n_white) * max(n_cycles, 1) + n_random)
+    X = torch.zeros(calls * each, 7 * n, dtype=torch.float32, device="cuda")
+    T = torch.zeros(calls * each, n, dtype=torch.float32, device="cuda")
+    total = 0
+
+    def dev(a):
+        return torch.tensor(a, dtype=torch.float64, device="cuda")
+
+    for s in range(n_windows):
+        sv, source = training_solver3d(s, P)
+        top = _surface_rows(sv)
+        xg, yg, zg = sv.coords(0)
+        for j in range(n_bump + n_white):
+            if j < n_bump:
+                b = sv.assemble_rhs(f=dev(source(xg, yg, zg, j)))
+            else:
+                bb = np.random.default_rng(8500 + 31 * s + j).standard_normal(sv.n_global)
+                bb[top] = 0.0
+                b = dev(bb)
+            total += sem_learned_harvest(sv.ctx, b, n_cycles, per, 7500 + 97 * s + j,
+                                         X[total:], T[total:])
+        for j in range(n_random):
+            rr = np.random.default_rng(12500 + 53 * s + j).standard_normal(sv.n_global)
+            rr[top] = 0.0
+            total += sem_learned_harvest(sv.ctx, dev(rr), 0, per, 11500 + 89 * s + j,
+                                         X[total:], T[total:])
+        sv.close()
+        if log:
+            log(f"[harvest3d] window {s}: {total} pairs")
+    torch.cuda.synchronize()
+    return X[:total].contiguous(), T[:total].contiguous()
 
 
 def harvest(n_surfaces=40, n_bump=4, n_white=4, n_cycles=8, n_random=16, per=32, P=8,
