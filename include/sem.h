@@ -105,6 +105,9 @@ typedef struct {
   double ms;          /* wall time of the call                                             */
   int nhist;          /* entries of hist                                                   */
   double hist[512];   /* relative residual after each iteration (hist[0] = initial)         */
+  int stage_off_at;   /* learned stage switched off for the rest of the solve after this many
+                         iterations, because the judge rejected every application in the
+                         last three (0: never)                                              */
 } sem_solve_info;
 
 typedef struct {
@@ -260,7 +263,11 @@ sem_status sem_launch_shape(const sem_ctx *ctx, int level, int *cols_per_block, 
  * mean diagonal of the element matrix and W the averaging weight of Sec. 5.3, zero on the
  * surface.  In the V-cycle the stage runs on the finest level after pre-smoothing: q = A c,
  * alpha = c.r / c.q (energy-optimal), accepted if alpha > 0 and finite (x += alpha c: the A-norm
- * of the error never grows), otherwise skipped and counted in sem_solve_info.learned_skips.  Training pairs: target
+ * of the error never grows), otherwise skipped and counted in sem_solve_info.learned_skips; after
+ * three outer iterations in a row in which every application was rejected, sem_poisson_solve
+ * switches the stage off for the rest of that solve (sem_solve_info.stage_off_at).  3D meshes
+ * (hexahedra, P <= 6): the same stage with 7n inputs (the residual, the factor fields G_rr, G_tt,
+ * G_rs, G_ts, G_ss over g_e = mean(G_rr + G_tt + G_ss), the mass), n = (P+1)^3.  Training pairs: target
  * t_e = (a_e / s_e) R_e e for the error e; loss = mean squared error; Adam.
  * Network blob: 64-byte header ("SEMN", version 1, sizes, seed, losses) followed by FP32
  * W1 [nin x 128], b1, W2 [128 x 128], b2, W3 [128 x nout], b3, row-major. */
@@ -268,11 +275,12 @@ sem_status sem_launch_shape(const sem_ctx *ctx, int level, int *cols_per_block, 
 /* Bytes of a network blob with nin inputs and nout outputs. */
 size_t sem_mlp_blob_size(int nin, int nout);
 
-/* Training features of the fine level (2D, P <= 8): for an assembled residual r (device FP64,
- * n_global) write X [E x 5n] and, if T is given, targets T [E x n] (device FP32, row-major;
+/* Training features of the fine level (2D, P <= 8, X [E x 5n]; 3D, P <= 6, X [E x 7n]): for an
+ * assembled residual r (device FP64, n_global) write X and, if T is given, targets T [E x n]
+ * (device FP32, row-major;
  * E = elements): with an error e, t_e = (a_e / s_e) R_e e; with e = NULL, the element-block solve
  * t_e = (a_e / s_e) (R_e A R_e^T)^{-1} R_e r (the local solve of the Schwarz smoother, Sec. 5.3;
- * meshes up to 4096 elements). */
+ * meshes up to 4096 elements in 2D, 1024 in 3D). */
 sem_status sem_learned_features(sem_ctx *ctx, const double *r, const double *e, float *X,
                                 float *T);
 
@@ -324,7 +332,8 @@ sem_status sem_mlp_gradients(const void *blob, size_t nbytes, const float *X, co
 sem_status sem_mlp_forward_noalloc(const void *blob, size_t nbytes, const float *X, int n,
                                    float *Y);
 
-/* Load a network blob (host) into the context (nin = 5n, nout = n of the fine level, P <= 8) and
+/* Load a network blob (host) into the context (nin = 5n in 2D, 7n in 3D, nout = n, the nodes of
+ * a fine-level element; 2D P <= 8, 3D P <= 6) and
  * set where the stage acts: enable = 0 off, bit 0 (1) after the finest pre-smoothing, bit 1 (2)
  * before the finest post-smoothing (3 = both, keeping the V-cycle close to symmetric for the
  * flexible-CG outer loop); sem_learned_enable changes it for a loaded network. */

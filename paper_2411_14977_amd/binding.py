@@ -49,7 +49,7 @@ class SolveInfo(ctypes.Structure):
     _fields_ = [
         ("iters", ctypes.c_int), ("vcycles", ctypes.c_int), ("learned_skips", ctypes.c_int),
         ("rel_res", ctypes.c_double), ("ms", ctypes.c_double), ("nhist", ctypes.c_int),
-        ("hist", ctypes.c_double * 512),
+        ("hist", ctypes.c_double * 512), ("stage_off_at", ctypes.c_int),
     ]
 
     def history(self):

@@ -85,7 +85,7 @@ struct Ctx {
          *zo = nullptr, *yo = nullptr, *So = nullptr, *mass = nullptr;
   double* parts = nullptr;        // partial-sum sets
   double* scal = nullptr;         // device scalars
-  double* hscal = nullptr;        // pinned host scalars: two sets of 3 NRED partials
+  double* hscal = nullptr;        // pinned host scalars: three slots of 3 NRED partials + 1
   std::vector<long long*> face_idx;
   std::vector<double*> face_w;
   std::vector<size_t> face_n;
@@ -132,7 +132,9 @@ struct Ctx {
   std::unordered_map<const void*, size_t> asize;  // bytes of every allocation in allocs
 };
 
-enum { PS_RR = 0, PS_BB, PS_PQ, PS_RZA, PS_RZB, PS_ZQ, PS_TMP, PS_PQ2, PS_NSETS };
+// partial-sum sets; the first double of PS_SKIP holds the learned stage's rejection counter (an
+// int), so one copy of sets RR, BB, PQ and that double brings everything the host checks
+enum { PS_RR = 0, PS_BB, PS_PQ, PS_SKIP, PS_RZA, PS_RZB, PS_ZQ, PS_TMP, PS_PQ2, PS_NSETS };
 
 struct HipFail {
   hipError_t e;
@@ -198,9 +200,10 @@ std::vector<TG> permute_G2d(const semh::LevelGeom& L, const std::vector<double>&
 }
 
 // run f(lo, hi) over [0, n) on up to 16 host threads (set-up work only)
-void parallel_ranges(size_t n, const std::function<void(size_t, size_t)>& f) {
+// grain: fewest items per thread (heavy items: a small grain spreads them over more threads)
+void parallel_ranges(size_t n, const std::function<void(size_t, size_t)>& f, size_t grain = 64) {
   const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
-  const size_t T = std::min<size_t>(std::min(16u, hw), std::max<size_t>(1, n / 64));
+  const size_t T = std::min<size_t>(std::min(16u, hw), std::max<size_t>(1, n / std::max<size_t>(1, grain)));
   if (T <= 1) {
     f(0, n);
     return;
@@ -1187,7 +1190,7 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
   c->So = nullptr;
   c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
   c->scal = (double*)dalloc(c, 64 * 8);
-  HK(hipHostMalloc((void**)&c->hscal, 3 * 3 * semk::NRED * 8, hipHostMallocDefault));
+  HK(hipHostMalloc((void**)&c->hscal, 3 * (3 * semk::NRED + 8) * 8, hipHostMallocDefault));
   {  // lumped mass and Neumann faces of the fine level
     const semh::LevelGeom& G = L0.geo;
     const size_t NL3 = (size_t)G.NP * G.NP * G.NP;
@@ -1403,7 +1406,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   c->So = (double*)dalloc(c, L0.nS * 8);
   c->parts = (double*)dalloc(c, (size_t)PS_NSETS * semk::NRED * 8);
   c->scal = (double*)dalloc(c, 64 * 8);
-  HK(hipHostMalloc((void**)&c->hscal, 3 * 3 * semk::NRED * 8, hipHostMallocDefault));
+  HK(hipHostMalloc((void**)&c->hscal, 3 * (3 * semk::NRED + 8) * 8, hipHostMallocDefault));
   // lumped mass and Neumann faces of the fine level
   {
     std::vector<double> m(N, 0.0);
@@ -1855,7 +1858,7 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn, L0.P,
                      c->st));
     const bool fpcg = c->desc.outer == SEM_OUTER_FPCG;
-    const size_t nset = 3 * (size_t)semk::NRED;
+    const size_t nset = 3 * (size_t)semk::NRED + 1;  // sets RR, BB, PQ and the skip counter
     double sums[3];
     // the initial residual's partial sums go to the host behind an event, and the first two
     // iterations are enqueued before the host looks at them (no GPU idle time at the start);
@@ -1887,6 +1890,7 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
       }
       HK(hipEventRecord(c->ev_it[hs], c->st));
     };
+    int skips_seen = 0;  // rejection counter at the last collected iteration
     auto collect = [&](int k) {
       HK(hipEventSynchronize(c->ev_it[k & 1]));
       const double* h = c->hscal + (k & 1) * nset;
@@ -1895,7 +1899,15 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
         for (int j = 0; j < semk::NRED; ++j) v += h[s * semk::NRED + j];
         sums[s] = v;
       }
+      skips_seen = *reinterpret_cast<const int*>(h + 3 * semk::NRED);
     };
+    // the learned stage is switched off for the rest of the solve after this many iterations in
+    // a row in which the judge rejected every application (the plain V-cycle remains)
+    constexpr int kStageOffAfter = 3;
+    const bool stage_on = c->stage_alloc && c->stage.enabled;
+    const int per_it = stage_on ? ((c->stage_mode & 1) + ((c->stage_mode >> 1) & 1)) : 0;
+    int rejected_run = 0, skips_prev = 0;
+    bool stage_off = false;
     int it = 0, launched = 0;
     const bool gmres = c->desc.outer == SEM_OUTER_GMRES;
     const int spec = gmres ? 0 : std::min(2, std::max(0, c->desc.maxit));
@@ -2056,6 +2068,18 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
       rel_prev = rel;
       rel = std::sqrt(sums[PS_RR] / bb);
       push(rel);
+      if (stage_on && !stage_off && per_it > 0) {
+        rejected_run = (skips_seen - skips_prev >= per_it) ? rejected_run + 1 : 0;
+        skips_prev = skips_seen;
+        if (rejected_run >= kStageOffAfter && rel > tol) {
+          // iterations already enqueued keep the stage; later ones are captured without it
+          HK(hipStreamSynchronize(c->st));
+          drop_graphs(c);
+          c->stage.enabled = false;
+          stage_off = true;
+          inf->stage_off_at = it;
+        }
+      }
       if (!std::isfinite(rel) || (fpcg && !(sums[PS_PQ] > 0))) {
         st = SEM_ERR_BREAKDOWN;
         set_err(c, "breakdown in the outer iteration (non-finite residual or p.Ap <= 0)");
@@ -2071,7 +2095,11 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     HK(hipStreamSynchronize(c->st));
     inf->iters = it;
     inf->rel_res = rel;
-    if (c->stage_alloc && c->stage.enabled) {
+    if (stage_off) {  // the next solve starts with the stage again (graphs captured anew)
+      drop_graphs(c);
+      c->stage.enabled = true;
+    }
+    if (stage_on) {
       int sk = 0;
       HK(hipMemcpy(&sk, c->stage.skips, sizeof(int), hipMemcpyDeviceToHost));
       inf->learned_skips = sk;
@@ -2113,7 +2141,7 @@ static void stage_buffers(Ctx* c) {
   s.Z1geo = (float*)dalloc(c, E * semm::NH * 4);
   s.abar = upload(c, c->abar_h);
   s.CE = (float*)dalloc(c, E * n * 4);
-  s.skips = (int*)dalloc(c, 64);
+  s.skips = reinterpret_cast<int*>(c->parts + (size_t)PS_SKIP * semk::NRED);
   const size_t eb = esz(L.dbl);
   c->Rbuf = dalloc(c, L.N * eb);
   c->cbuf = dalloc(c, L.N * eb);
@@ -2137,7 +2165,7 @@ static std::vector<double> element_block_inverses3d(Ctx* c) {
   std::vector<double> Ae(E * nn);
   parallel_ranges(E, [&](size_t lo, size_t hi) {
     for (size_t e = lo; e < hi; ++e) semh::element_matrix(G, G.G, e, &Ae[e * nn]);
-  });
+  }, 2);
   std::vector<double> out(E * nn);
   std::atomic<bool> singular{false};
   parallel_ranges(E, [&](size_t lo, size_t hi) {
@@ -2178,7 +2206,7 @@ static std::vector<double> element_block_inverses3d(Ctx* c) {
       if (!semh::dense_inverse_public(n, Ab.data(), Ai.data())) singular = true;
       std::copy(Ai.begin(), Ai.end(), out.begin() + e * nn);
     }
-  });
+  }, 2);
   if (singular) throw ArgFail{"singular element block"};
   return out;
 }

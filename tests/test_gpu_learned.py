@@ -336,3 +336,27 @@ def test_learned_train_adam_matches_oracle():
     # the network is now loaded into the context (placement off until enabled)
     B.sem_learned_enable(s.ctx, 3)
     s.close()
+
+
+@pytest.mark.parametrize("mode", [1, 3])
+def test_stage_switched_off_after_three_rejected_iterations(mode):
+    """A network whose every correction is rejected: after three iterations in a row with every
+    application rejected the stage is off for the rest of the solve, which then equals the plain
+    solve bit for bit (a rejected stage leaves the cycle unchanged); the next solve starts with
+    the stage on again."""
+    wl = W.tank(16, 4, 8, Lx=1.6, name="tank8")
+    s = cases.make_solver(wl, prec="f32")
+    b = cases.make_rhs(wl, s)
+    x0, i0, _ = s.solve(b, tol=1e-10)
+    # the zero network: c = 0, so every judge sees 0/0 and rejects the application
+    p = {k: np.zeros_like(v) for k, v in params(1).items()}
+    s.learned_load(blob(p), enable=mode)
+    per = 2 if mode == 3 else 1
+    for _ in range(2):
+        x1, i1, _ = s.solve(b, tol=1e-10)
+        print(f"[gpu] rejected stage mode {mode}: off after {i1.stage_off_at}, skips "
+              f"{i1.learned_skips}, iterations {i1.iters} vs {i0.iters}", flush=True)
+        assert i1.stage_off_at == 3
+        assert i1.learned_skips >= 3 * per
+        assert i1.iters == i0.iters and torch.equal(x0, x1)
+    s.close()
