@@ -4,7 +4,8 @@ Global sparse matrices are the sum of the local dense element matrices (Sec. 4.2
 flocal / globallocal).  The element stiffness (the L^b matrices of eq. flocal2, read with the
 missing transpose as D^T M D and with GLL collocation for the quadrature) is, per element,
     A_e = sum_{a,b} D_a^T diag(G_ab) D_b,   a, b in {r, s} (2D) or {r, t, s} (3D),
-with D_r = D (x) I, D_s = I (x) D in the element-local ordering (i slow, j fast).
+with D_r = D (x) I, D_s = I (x) D in the element-local ordering (i slow, j fast); on 2D meshes
+with different orders along x and sigma, D_r = D_x (x) I and D_s = I (x) D_sigma.
 
 Boundary value problem (Sec. 3.2): p = g_D on the free surface (top, eq. bcpd), n . grad p =
 g_N on walls and bottom (eq. bcpdneu), -lap p = f inside.  The discrete system solved is
@@ -21,8 +22,8 @@ def _kron_ops(mesh):
     NP = mesh.NP
     I = np.eye(NP)
     D = mesh.D
-    if mesh.dim == 2:
-        return {"r": np.kron(D, I), "s": np.kron(I, D)}
+    if mesh.dim == 2:  # x rule of order P, sigma rule of order Pz
+        return {"r": np.kron(D, np.eye(mesh.NPz)), "s": np.kron(I, mesh.Dz)}
     return {"r": np.kron(np.kron(D, I), I), "t": np.kron(np.kron(I, D), I),
             "s": np.kron(np.kron(I, I), D)}
 
@@ -41,7 +42,7 @@ def _field_pairs(mesh):
 def element_matrices(mesh):
     """Dense element stiffness matrices, shape (E, NL, NL)."""
     ops = _kron_ops(mesh)
-    NL = mesh.NP ** mesh.dim
+    NL = mesh.NL
     A = np.zeros((mesh.E, NL, NL))
     for a, b, G in _field_pairs(mesh):
         Da, Db = ops[a], ops[b]
@@ -88,12 +89,13 @@ def apply_matrix_free(mesh, x, dirichlet=True):
         x[dn] = 0.0
     NP, E, D = mesh.NP, mesh.E, mesh.D
     if mesh.dim == 2:
-        u = x[mesh.l2g].reshape(E, NP, NP)
+        Dz = mesh.Dz
+        u = x[mesh.l2g].reshape(E, NP, mesh.NPz)
         ur = np.einsum("ik,ekj->eij", D, u)
-        us = np.einsum("jk,eik->eij", D, u)
+        us = np.einsum("jk,eik->eij", Dz, u)
         wr = mesh.Grr * ur + mesh.Grs * us
         ws = mesh.Grs * ur + mesh.Gss * us
-        v = np.einsum("ki,ekj->eij", D, wr) + np.einsum("kj,eik->eij", D, ws)
+        v = np.einsum("ki,ekj->eij", D, wr) + np.einsum("kj,eik->eij", Dz, ws)
     else:
         u = x[mesh.l2g].reshape(E, NP, NP, NP)
         ur = np.einsum("ia,eamj->eimj", D, u)

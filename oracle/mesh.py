@@ -21,6 +21,11 @@ vertical index fastest.  Elements: 2D e = ex Nz + ez, 3D e = (ex Ny + ey) Nz + e
 Element-local node (i[, m], j) with i along x, m along y, j along sigma; j fastest.
 Level meshes take h and eta sampled at the FINE level's horizontal GLL nodes and
 interpolate them element by element with the transfer matrix I_{Pp} of Sec. 5.2.
+
+2D meshes may carry different orders along x (P) and sigma (Pz), as the semi-coarsened levels of
+Sec. 5.1 do: the element is then the tensor product of the order-P GLL rule in x and the
+order-Pz rule in sigma (local node (i, j), i = 0..P, j = 0..Pz, j fastest), and every formula
+above takes its x factor from the first rule and its sigma factor from the second.
 """
 import numpy as np
 
@@ -30,14 +35,22 @@ from . import gll
 class Mesh2D:
     dim = 2
 
-    def __init__(self, Nx, Nz, P, Lx, h_fine, eta_fine, P_fine=None):
+    def __init__(self, Nx, Nz, P, Lx, h_fine, eta_fine, P_fine=None, Pz=None):
+        """P: order along x; Pz: order along sigma (default P); P_fine: horizontal order of
+        the grid h_fine and eta_fine are sampled on."""
         P_fine = P if P_fine is None else P_fine
-        self.Nx, self.Nz, self.P, self.Lx = int(Nx), int(Nz), int(P), float(Lx)
+        Pz = P if Pz is None else int(Pz)
+        self.Nx, self.Nz, self.P, self.Pz, self.Lx = int(Nx), int(Nz), int(P), Pz, float(Lx)
         self.NP = P + 1
+        self.NPz = Pz + 1
+        self.NL = self.NP * self.NPz
         self.E = self.Nx * self.Nz
         self.r = gll.gll_nodes(P)
         self.w = gll.gll_weights(P, self.r)
         self.D = gll.diff_matrix(P)
+        self.rz = gll.gll_nodes(Pz)
+        self.wz = gll.gll_weights(Pz, self.rz)
+        self.Dz = gll.diff_matrix(Pz)
         self.dx = self.Lx / self.Nx
         self.dsig = 1.0 / self.Nz
         h_fine = np.asarray(h_fine, dtype=np.float64)
@@ -52,31 +65,32 @@ class Mesh2D:
         self.d = self.h + self.eta
         self.hx = (2.0 / self.dx) * (self.h @ self.D.T)
         self.dxd = (2.0 / self.dx) * (self.d @ self.D.T)
-        # coordinates of element-local nodes, arrays (Nx, Nz, NP, NP)
+        # coordinates of element-local nodes, arrays (Nx, Nz, NP, NPz)
         ex = np.arange(self.Nx)[:, None, None, None]
         ez = np.arange(self.Nz)[None, :, None, None]
         ri = self.r[None, None, :, None]
-        sj = self.r[None, None, None, :]
-        full = np.zeros((self.Nx, self.Nz, self.NP, self.NP))
+        sj = self.rz[None, None, None, :]
+        full = np.zeros((self.Nx, self.Nz, self.NP, self.NPz))
         self.X = self.Lx * (ex + (ri + 1.0) / 2.0) / self.Nx + full
         self.SIG = (ez + (sj + 1.0) / 2.0) / self.Nz + full
         d4 = self.d[:, None, :, None]
         h4 = self.h[:, None, :, None]
         self.Z = -h4 + self.SIG * d4
         sigx = (self.hx[:, None, :, None] - self.SIG * self.dxd[:, None, :, None]) / d4
-        ww = (self.w[:, None] * self.w[None, :])[None, None] * np.ones((self.Nx, self.Nz, 1, 1))
-        self.Grr = (ww * d4 * self.dsig / self.dx).reshape(self.E, self.NP, self.NP)
-        self.Grs = (ww * d4 * sigx).reshape(self.E, self.NP, self.NP)
-        self.Gss = (ww * (self.dx / self.dsig) * d4 * (sigx * sigx + 1.0 / (d4 * d4))).reshape(
-            self.E, self.NP, self.NP)
-        self.mass = (ww * d4 * self.dx * self.dsig / 4.0).reshape(self.E, self.NP, self.NP)
-        self.sigx = sigx.reshape(self.E, self.NP, self.NP)
+        ww = (self.w[:, None] * self.wz[None, :])[None, None] * np.ones((self.Nx, self.Nz, 1, 1))
+        EL = (self.E, self.NP, self.NPz)
+        self.Grr = (ww * d4 * self.dsig / self.dx).reshape(EL)
+        self.Grs = (ww * d4 * sigx).reshape(EL)
+        self.Gss = (ww * (self.dx / self.dsig) * d4 * (sigx * sigx + 1.0 / (d4 * d4))).reshape(EL)
+        self.mass = (ww * d4 * self.dx * self.dsig / 4.0).reshape(EL)
+        self.sigx = sigx.reshape(EL)
         self.nx_nodes = self.Nx * P + 1
-        self.nz_nodes = self.Nz * P + 1
+        self.nz_nodes = self.Nz * Pz + 1
         self.N = self.nx_nodes * self.nz_nodes
         gi = (np.arange(self.Nx)[:, None, None, None] * P + np.arange(self.NP)[None, None, :, None])
-        gj = (np.arange(self.Nz)[None, :, None, None] * P + np.arange(self.NP)[None, None, None, :])
-        self.l2g = (gi * self.nz_nodes + gj).reshape(self.E, self.NP * self.NP)
+        gj = (np.arange(self.Nz)[None, :, None, None] * Pz
+              + np.arange(self.NPz)[None, None, None, :])
+        self.l2g = (gi * self.nz_nodes + gj).reshape(self.E, self.NL)
         self.Xe = self.X.reshape(self.E, -1)
         self.Ze = self.Z.reshape(self.E, -1)
 
@@ -101,16 +115,16 @@ class Mesh2D:
         Returns dict face -> (global node indices, weights), faces 'left' (x=0), 'right'
         (x=Lx) and 'bottom' (z=-h).  Walls: dGamma = d dsig/2; bottom: (dx/2) sqrt(1+h_x^2).
         """
-        P, NP = self.P, self.NP
+        P, NP, Pz = self.P, self.NP, self.Pz
         out = {}
         for name, ex, i in (("left", 0, 0), ("right", self.Nx - 1, P)):
             idx = np.zeros(self.nz_nodes, dtype=np.int64)
             wts = np.zeros(self.nz_nodes)
             for ez in range(self.Nz):
-                for j in range(NP):
-                    iz = ez * P + j
+                for j in range(self.NPz):
+                    iz = ez * Pz + j
                     idx[iz] = (ex * P + i) * self.nz_nodes + iz
-                    wts[iz] += self.w[j] * self.d[ex, i] * self.dsig / 2.0
+                    wts[iz] += self.wz[j] * self.d[ex, i] * self.dsig / 2.0
             out[name] = (idx, wts)
         idx = np.zeros(self.nx_nodes, dtype=np.int64)
         wts = np.zeros(self.nx_nodes)
@@ -131,6 +145,7 @@ class Mesh3D:
         self.Nx, self.Ny, self.Nz, self.P = int(Nx), int(Ny), int(Nz), int(P)
         self.Lx, self.Ly = float(Lx), float(Ly)
         self.NP = P + 1
+        self.NL = self.NP ** 3
         self.E = self.Nx * self.Ny * self.Nz
         self.r = gll.gll_nodes(P)
         self.w = gll.gll_weights(P, self.r)

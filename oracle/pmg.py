@@ -4,6 +4,12 @@ Sec. 5 of the paper:
 * grid hierarchy by reducing the polynomial order with the mesh kept (Sec. 5.1).  Eq. gridcoars
   as printed, P_{n-1} = ceil((P_n + 1)/2), stalls at 2 and never reaches the P = 1 coarsest
   grid the section names; it is read as P_{n-1} = ceil(P_n / 2) (8 -> 4 -> 2 -> 1);
+* semi-coarsening (Sec. 5.1) where the x and sigma orders differ: each coarser level lowers only
+  the larger of the two orders, by the same rule, but not below the smaller one, until they
+  match; from there both drop together (16x8 -> 8x8 -> 4x4 -> ..., 2x8 -> 2x4 -> 2x2 -> 1x1;
+  the clamp at the smaller order is this reading of "until both directions have matching
+  orders").  The prolongation is then the interpolation along the changed direction and the
+  identity along the other;
 * prolongation from interpolation, I_{Pp} = Phi^p V^{-1}, applied per element and per
   direction (tensor product), and restriction R = P^T (Sec. 5.2);
 * a fixed number of smoothing steps on every level before and after the coarse correction
@@ -52,6 +58,26 @@ def coarsen_orders(P):
     return out
 
 
+def coarsen_orders_2d(Px, Pz):
+    """Level orders (P_x, P_sigma) from (Px, Pz) down to (1, 1): while the orders differ the
+    larger drops to max(ceil(P/2), the smaller); equal orders drop together."""
+    out = [(int(Px), int(Pz))]
+    while out[-1] != (1, 1):
+        px, pz = out[-1]
+        if px == pz:
+            out.append(((px + 1) // 2, (pz + 1) // 2))
+        elif px > pz:
+            out.append((max((px + 1) // 2, pz), pz))
+        else:
+            out.append((px, max((pz + 1) // 2, px)))
+    return out
+
+
+def level_orders_2d(orders):
+    """Level orders as (P_x, P_sigma) pairs: an int P stands for (P, P)."""
+    return [(int(o), int(o)) if np.isscalar(o) else (int(o[0]), int(o[1])) for o in orders]
+
+
 def prolongation_1d_linear(Nc):
     """Linear interpolation from Nc to 2 Nc intervals: even fine nodes coincide with coarse
     nodes, odd ones take the mean of their two neighbours."""
@@ -72,6 +98,8 @@ def prolongation_1d(Ne, Pc, Pf):
     shared by two elements takes the row of the element on its left (both agree: the
     coarse Lagrange basis is continuous).
     """
+    if Pc == Pf:
+        return sp.identity(Ne * Pf + 1, format="csr")
     J = gll.transfer_matrix(Pc, Pf)
     nf, nc = Ne * Pf + 1, Ne * Pc + 1
     M = np.zeros((nf, nc))
@@ -122,19 +150,22 @@ class Hierarchy:
     def __init__(self, mesh_args, orders, smoother="chebyshev", nu_pre=2, nu_post=2,
                  cheb_degree=3, jacobi_omega=2.0 / 3.0, cheb_lo=0.1, cheb_hi=1.1,
                  coarse_dense_max=1200, gstore=None):
-        """gstore: storage precision of the geometric factors on every level above the
-        coarsest (None / "f64", "f32", "bf16"); the coarsest level is always exact."""
+        """orders: level orders, fine to coarse; in 2D an entry may be a pair (P_x, P_sigma)
+        (semi-coarsened levels), a plain P meaning (P, P).  gstore: storage precision of the
+        geometric factors on every level above the coarsest (None / "f64", "f32", "bf16"); the
+        coarsest level is always exact."""
         self.dim = mesh_args["dim"]
         self.orders = list(orders)
-        if self.orders[-1] != 1:
+        pairs = level_orders_2d(self.orders) if self.dim == 2 else None
+        if (pairs[-1] if pairs else self.orders[-1]) not in (1, (1, 1)):
             raise ValueError("coarsest order must be 1")
         self.levels = []
-        Pf = self.orders[0]
+        Pf = pairs[0][0] if pairs else self.orders[0]
         for li, p in enumerate(self.orders):
             gs = gstore if li + 1 < len(self.orders) else None
             if self.dim == 2:
-                m = Mesh2D(mesh_args["Nx"], mesh_args["Nz"], p, mesh_args["Lx"],
-                           mesh_args["h"], mesh_args["eta"], P_fine=Pf)
+                m = Mesh2D(mesh_args["Nx"], mesh_args["Nz"], pairs[li][0], mesh_args["Lx"],
+                           mesh_args["h"], mesh_args["eta"], P_fine=Pf, Pz=pairs[li][1])
             else:
                 m = Mesh3D(mesh_args["Nx"], mesh_args["Ny"], mesh_args["Nz"], p,
                            mesh_args["Lx"], mesh_args["Ly"], mesh_args["h"], mesh_args["eta"],
@@ -142,12 +173,14 @@ class Hierarchy:
             self.levels.append(Level(m, gs))
         self.P = []
         for l in range(len(self.orders) - 1):
-            pf, pc = self.orders[l], self.orders[l + 1]
-            Px = prolongation_1d(mesh_args["Nx"], pc, pf)
-            Pz = prolongation_1d(mesh_args["Nz"], pc, pf)
             if self.dim == 2:
-                Pm = sp.kron(Px, Pz)
+                (pfx, pfz), (pcx, pcz) = pairs[l], pairs[l + 1]
+                Pm = sp.kron(prolongation_1d(mesh_args["Nx"], pcx, pfx),
+                             prolongation_1d(mesh_args["Nz"], pcz, pfz))
             else:
+                pf, pc = self.orders[l], self.orders[l + 1]
+                Px = prolongation_1d(mesh_args["Nx"], pc, pf)
+                Pz = prolongation_1d(mesh_args["Nz"], pc, pf)
                 Py = prolongation_1d(mesh_args["Ny"], pc, pf)
                 Pm = sp.kron(sp.kron(Px, Py), Pz)
             self.P.append(Pm.tocsr())

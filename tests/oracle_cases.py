@@ -42,7 +42,8 @@ def fine_mesh(wl, P=None):
     a = mesh_args(wl)
     P = wl.P if P is None else P
     if wl.dim == 2:
-        return mesh.Mesh2D(a["Nx"], a["Nz"], P, a["Lx"], a["h"], a["eta"], P_fine=wl.P)
+        return mesh.Mesh2D(a["Nx"], a["Nz"], P, a["Lx"], a["h"], a["eta"], P_fine=wl.P,
+                           Pz=wl.Pz)
     return mesh.Mesh3D(a["Nx"], a["Ny"], a["Nz"], P, a["Lx"], a["Ly"], a["h"], a["eta"],
                        P_fine=wl.P)
 
@@ -51,7 +52,8 @@ def hierarchy(wl, **kw):
     opts = dict(smoother=wl.smoother, nu_pre=wl.nu_pre, nu_post=wl.nu_post,
                 cheb_degree=wl.cheb_degree)
     opts.update(kw)
-    return pmg.Hierarchy(mesh_args(wl), wl.orders, **opts)
+    orders = wl.orders if wl.orders else pmg.coarsen_orders_2d(wl.P, wl.pz)
+    return pmg.Hierarchy(mesh_args(wl), orders, **opts)
 
 
 def rhs(wl, m, A_full=None):
@@ -75,9 +77,9 @@ def rhs(wl, m, A_full=None):
     return assemble.assemble_rhs(m, f=f)
 
 
-def affine_mesh(Nx, Nz, P, Lx, depth):
+def affine_mesh(Nx, Nz, P, Lx, depth, Pz=None):
     x = fine_x_nodes(Nx, P, Lx)
-    return mesh.Mesh2D(Nx, Nz, P, Lx, np.full_like(x, depth), np.zeros_like(x))
+    return mesh.Mesh2D(Nx, Nz, P, Lx, np.full_like(x, depth), np.zeros_like(x), Pz=Pz)
 
 
 def c1_fine_x(P):

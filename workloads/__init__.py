@@ -46,11 +46,16 @@ class Workload:
     surface_seed: int = 7
     rhs_seed: int = 107
     tol: float = 1e-10
+    Pz: Optional[int] = None          # 2D: order along sigma when it differs from P (along x)
+
+    @property
+    def pz(self):
+        return self.P if self.Pz is None else self.Pz
 
     @property
     def n_global(self):
         if self.dim == 2:
-            return (self.Nx * self.P + 1) * (self.Nz * self.P + 1)
+            return (self.Nx * self.P + 1) * (self.Nz * self.pz + 1)
         return (self.Nx * self.P + 1) * (self.Ny * self.P + 1) * (self.Nz * self.P + 1)
 
     @property
@@ -85,6 +90,14 @@ def tank(Nx, Nz, P, Lx=25.6, orders=None, name="tank", surface_seed=7, rhs_seed=
          smoother="chebyshev"):
     return Workload(name, 2, Nx, Nz, P, Lx, orders=orders or _orders(P),
                     surface_seed=surface_seed, rhs_seed=rhs_seed, smoother=smoother)
+
+
+def tank_semi(Nx, Nz, Px, Pz, Lx=25.6, name="tank_semi", surface_seed=7, rhs_seed=107,
+              smoother="chebyshev"):
+    """2D tank with order Px along x and Pz along sigma; the level orders are left to the
+    solver (empty list: its own semi-coarsened hierarchy)."""
+    return Workload(name, 2, Nx, Nz, Px, Lx, orders=[], surface_seed=surface_seed,
+                    rhs_seed=rhs_seed, smoother=smoother, Pz=Pz)
 
 
 def tank3d(Nx, Ny, Nz, P, L=6.4, orders=None, name="tank3d", surface_seed=300, rhs_seed=301):
