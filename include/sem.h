@@ -66,7 +66,8 @@ typedef struct {
   int ne[3];                   /* elements along x, y, z(sigma); ne[1] ignored in 2D        */
   int order;                   /* fine GLL order P, 1..SEM_MAX_ORDER                        */
   int nlevels;                 /* 0: P, ceil(P/2), ..., 1; else level_order[0..nlevels-1]   */
-  int level_order[SEM_MAX_LEVELS]; /* strictly decreasing, first = order, last = 1          */
+  int level_order[SEM_MAX_LEVELS]; /* strictly decreasing, first = order, last = 1 (with
+                                  order_z > 0: the x orders, see level_order_z)               */
   double len[2];               /* horizontal extents L_x, L_y (origin 0)                    */
   const double *h;             /* host: still-water depth at the fine horizontal GLL nodes:
                                   2D (ne[0] P + 1); 3D (ne[0] P + 1) x (ne[1] P + 1), y fastest */
@@ -95,6 +96,21 @@ typedef struct {
                                   Gram-Schmidt applied twice; x += Z y at the end of a cycle;
                                   sem_solve_info.hist holds the Givens residual estimates of the
                                   steps and, at the end of each cycle, the true residual.      */
+  int order_z;                 /* 2D: GLL order along sigma, 1..SEM_MAX_ORDER, when it differs
+                                  from `order` (then the order along x); 0 = `order`.  3D: 0 or
+                                  equal to `order`.  With different orders the hierarchy is
+                                  semi-coarsened (Sec. 5.1): with nlevels = 0 each coarser level
+                                  lowers only the larger order, to max(ceil(P/2), the smaller
+                                  order), until the two match, then both drop by ceil(P/2)
+                                  together down to 1 x 1; a level whose orders differ has no
+                                  transfer that changes both directions.  Such levels need
+                                  ne[2] (P_x+1) (P_sigma+1) <= 1024, take the Jacobi or Chebyshev
+                                  smoother (not Schwarz) and no learned stage.                 */
+  int level_order_z[SEM_MAX_LEVELS]; /* with nlevels > 0 and order_z > 0: each level's sigma
+                                  order (level_order then holds the x orders); the first equals
+                                  order_z, the last 1; from one level to the next neither order
+                                  grows and one of them drops, or both drop where both levels
+                                  have equal orders.                                          */
 } sem_mesh_desc;
 
 typedef struct {
@@ -133,14 +149,19 @@ sem_status sem_mesh_setup(const sem_mesh_desc *desc, sem_ctx **out);
 void sem_destroy(sem_ctx *ctx);
 
 /* Sizes: assembled nodes n_global, free (non-Dirichlet) nodes n_free, element-local nodes
- * n_local = elements (P+1)^dim.  Any pointer may be NULL. */
+ * n_local = elements (P+1)^dim (2D: elements (P_x+1)(P_sigma+1)).  Any pointer may be NULL. */
 sem_status sem_get_sizes(const sem_ctx *ctx, size_t *n_global, size_t *n_free, size_t *n_local);
 
 /* Number of levels of the hierarchy (0 for a NULL context). */
 int sem_num_levels(const sem_ctx *ctx);
 
-/* For level l (0 = finest): its order, node count and current lambda_hat. */
+/* For level l (0 = finest): its order (along x), node count and current lambda_hat. */
 sem_status sem_get_level(const sem_ctx *ctx, int level, int *order, size_t *n, double *lambda_hat);
+
+/* For level l (0 = finest): its GLL orders along x and along sigma (they differ on the
+ * semi-coarsened levels of a mesh built with order_z != order; 3D: both the order).  Either
+ * pointer may be NULL.  SEM_ERR_ARG for a NULL context or a level out of range. */
+sem_status sem_get_level_orders(const sem_ctx *ctx, int level, int *order_x, int *order_z);
 
 /* GLL nodes and weights of order P computed by the library (host arrays of P+1). */
 sem_status sem_gll(int P, double *nodes, double *weights);

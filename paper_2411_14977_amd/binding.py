@@ -35,7 +35,8 @@ class MeshDesc(ctypes.Structure):
         ("cheb_hi", ctypes.c_double), ("outer", ctypes.c_int), ("maxit", ctypes.c_int),
         ("lanczos_steps", ctypes.c_int), ("lanczos_seed", ctypes.c_ulonglong),
         ("stream", ctypes.c_void_p), ("coarse_dense_max", ctypes.c_int),
-        ("gmres_restart", ctypes.c_int),
+        ("gmres_restart", ctypes.c_int), ("order_z", ctypes.c_int),
+        ("level_order_z", ctypes.c_int * SEM_MAX_LEVELS),
     ]
 
 
@@ -80,6 +81,8 @@ def lib():
         "sem_num_levels": (ctypes.c_int, [vp]),
         "sem_get_level": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_int), sz,
                                          ctypes.POINTER(ctypes.c_double)]),
+        "sem_get_level_orders": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_int),
+                                                ctypes.POINTER(ctypes.c_int)]),
         "sem_gll": (ctypes.c_int, [ip, ctypes.POINTER(ctypes.c_double),
                                    ctypes.POINTER(ctypes.c_double)]),
         "sem_node_coords": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_double),
@@ -192,6 +195,13 @@ def sem_get_level(ctx, level):
     o, n, lam = ctypes.c_int(), ctypes.c_size_t(), ctypes.c_double()
     _check(ctx, lib().sem_get_level(ctx, level, ctypes.byref(o), ctypes.byref(n), ctypes.byref(lam)))
     return o.value, n.value, lam.value
+
+
+def sem_get_level_orders(ctx, level):
+    """(order along x, order along sigma) of a level."""
+    ox, oz = ctypes.c_int(), ctypes.c_int()
+    _check(ctx, lib().sem_get_level_orders(ctx, level, ctypes.byref(ox), ctypes.byref(oz)))
+    return ox.value, oz.value
 
 
 def sem_gll(P):
@@ -422,17 +432,26 @@ class Solver:
                  smoother="chebyshev", nu_pre=2, nu_post=2, cheb_degree=3, jacobi_omega=2.0 / 3.0,
                  cheb_lo=0.1, cheb_hi=1.1, outer="fpcg", maxit=500, dirichlet=True,
                  lanczos_steps=20, lanczos_seed=12345, coarse_dense_max=1200, stream=None,
-                 gmres_restart=30):
+                 gmres_restart=30, order_z=None):
+        """order: GLL order (2D: along x); order_z: 2D order along sigma when it differs;
+        levels: level orders, each an int or (with order_z) an (x, sigma) pair; None or []:
+        the library's own hierarchy."""
         import torch
         d = sem_mesh_desc_default()
         d.dim = dim
         for k in range(3):
             d.ne[k] = int(ne[k])
         d.order = int(order)
+        if order_z is not None:
+            d.order_z = int(order_z)
         if levels:
             d.nlevels = len(levels)
             for k, p in enumerate(levels):
-                d.level_order[k] = int(p)
+                if np.isscalar(p):
+                    d.level_order[k] = int(p)
+                    d.level_order_z[k] = int(p)
+                else:
+                    d.level_order[k], d.level_order_z[k] = int(p[0]), int(p[1])
         d.len[0] = float(length[0])
         d.len[1] = float(length[1]) if len(length) > 1 else 1.0
         self._h = np.ascontiguousarray(np.asarray(h, dtype=np.float64).ravel())
@@ -473,6 +492,9 @@ class Solver:
 
     def level(self, l):
         return sem_get_level(self.ctx, l)
+
+    def level_orders(self, l):
+        return sem_get_level_orders(self.ctx, l)
 
     def coords(self, level=0):
         return sem_node_coords(self.ctx, level, self.dim)

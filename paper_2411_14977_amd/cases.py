@@ -23,8 +23,8 @@ def surface_samples(wl):
 
 def make_solver(wl, prec="f64", **kw):
     h, eta = surface_samples(wl)
-    opts = dict(levels=wl.orders, prec=prec, smoother=wl.smoother, nu_pre=wl.nu_pre,
-                nu_post=wl.nu_post, cheb_degree=wl.cheb_degree)
+    opts = dict(levels=wl.orders or None, prec=prec, smoother=wl.smoother, nu_pre=wl.nu_pre,
+                nu_post=wl.nu_post, cheb_degree=wl.cheb_degree, order_z=wl.Pz)
     opts.update(kw)
     ne = (wl.Nx, wl.Ny if wl.dim == 3 else 1, wl.Nz)
     length = (wl.Lx, wl.Ly if wl.dim == 3 else 1.0)
@@ -37,7 +37,7 @@ def make_rhs(wl, s):
     dev = "cuda"
     if wl.kind == "manufactured":
         x, z = s.coords(0)
-        nzn, nxn = wl.Nz * wl.P + 1, wl.Nx * wl.P + 1
+        nzn, nxn = wl.Nz * wl.pz + 1, wl.Nx * wl.P + 1
         zl = z[:nzn]
         zr = z[(nxn - 1) * nzn:]
         xb = x[::nzn]

@@ -123,10 +123,13 @@ double splitmix64_uniform(uint64_t seed, uint64_t i) {
 
 // --------------------------------------------------------------------------------------------
 void build_level(LevelGeom& L, int dim, int Nx, int Ny, int Nz, int P, int Pf, double Lx,
-                 double Ly, const double* hf, const double* ef) {
+                 double Ly, const double* hf, const double* ef, int Pz) {
+  if (Pz < 1 || dim == 3) Pz = P;
   L.dim = dim;
   L.P = P;
   L.NP = P + 1;
+  L.Pz = Pz;
+  L.NPz = Pz + 1;
   L.Nx = Nx;
   L.Ny = dim == 3 ? Ny : 1;
   L.Nz = Nz;
@@ -135,20 +138,31 @@ void build_level(LevelGeom& L, int dim, int Nx, int Ny, int Nz, int P, int Pf, d
   const int NP = P + 1;
   gll_rule(P, L.r, L.w);
   L.D = diff_matrix(P, L.r);
+  if (Pz == P) {
+    L.rz = L.r;
+    L.wz = L.w;
+    L.Dz = L.D;
+  } else {
+    gll_rule(Pz, L.rz, L.wz);
+    L.Dz = diff_matrix(Pz, L.rz);
+  }
   std::vector<double> rf, wf;
   gll_rule(Pf, rf, wf);
   std::vector<double> I = interp_matrix(rf, L.r);  // (NP) x (Pf+1)
   L.nxn = Nx * P + 1;
   L.nyn = dim == 3 ? Ny * P + 1 : 1;
-  L.nzn = Nz * P + 1;
+  L.nzn = Nz * Pz + 1;
   L.N = (size_t)L.nxn * L.nyn * L.nzn;
   const double dx = Lx / Nx, dsig = 1.0 / Nz;
   const std::vector<double>& D = L.D;
   const std::vector<double>& w = L.w;
   if (dim == 2) {
+    const int NPz = Pz + 1;
+    const std::vector<double>& rz = L.rz;
+    const std::vector<double>& wz = L.wz;
     L.E = (size_t)Nx * Nz;
     L.nfields = 3;
-    const size_t NL = NP * NP;
+    const size_t NL = (size_t)NP * NPz;
     L.G.assign(3 * L.E * NL, 0.0);
     L.mass.assign(L.E * NL, 0.0);
     L.X.assign(L.N, 0.0);
@@ -181,16 +195,16 @@ void build_level(LevelGeom& L, int dim, int Nx, int Ny, int Nz, int P, int Pf, d
       for (int ez = 0; ez < Nz; ++ez) {
         const size_t e = (size_t)ex * Nz + ez;
         for (int i = 0; i < NP; ++i)
-          for (int j = 0; j < NP; ++j) {
-            const double sig = (ez + (L.r[j] + 1.0) / 2.0) / Nz;
+          for (int j = 0; j < NPz; ++j) {
+            const double sig = (ez + (rz[j] + 1.0) / 2.0) / Nz;
             const double sx = (hx[i] - sig * dxd[i]) / d[i];
-            const double ww = w[i] * w[j];
-            const size_t l = e * NL + i * NP + j;
+            const double ww = w[i] * wz[j];
+            const size_t l = e * NL + i * NPz + j;
             L.G[0 * L.E * NL + l] = ww * d[i] * dsig / dx;
             L.G[1 * L.E * NL + l] = ww * d[i] * sx;
             L.G[2 * L.E * NL + l] = ww * (dx / dsig) * d[i] * (sx * sx + 1.0 / (d[i] * d[i]));
             L.mass[l] = ww * d[i] * dx * dsig / 4.0;
-            const size_t g = (size_t)(ex * P + i) * L.nzn + ez * P + j;
+            const size_t g = (size_t)(ex * P + i) * L.nzn + ez * Pz + j;
             L.X[g] = Lx * (ex + (L.r[i] + 1.0) / 2.0) / Nx;
             L.Z[g] = -h[i] + sig * d[i];
           }
@@ -205,10 +219,10 @@ void build_level(LevelGeom& L, int dim, int Nx, int Ny, int Nz, int P, int Pf, d
       L.face_idx[f].assign(L.nzn, 0);
       L.face_w[f].assign(L.nzn, 0.0);
       for (int ez = 0; ez < Nz; ++ez)
-        for (int j = 0; j < NP; ++j) {
-          const int iz = ez * P + j;
+        for (int j = 0; j < NPz; ++j) {
+          const int iz = ez * Pz + j;
           L.face_idx[f][iz] = (int64_t)(ex * P + i) * L.nzn + iz;
-          L.face_w[f][iz] += w[j] * dd * dsig / 2.0;
+          L.face_w[f][iz] += wz[j] * dd * dsig / 2.0;
         }
     }
     L.face_idx[2].assign(L.nxn, 0);
@@ -371,8 +385,8 @@ size_t local_to_global(const LevelGeom& L, size_t e, int l) {
   const int NP = L.NP, P = L.P;
   if (L.dim == 2) {
     const size_t ex = e / L.Nz, ez = e % L.Nz;
-    const int i = l / NP, j = l % NP;
-    return (ex * P + i) * (size_t)L.nzn + ez * P + j;
+    const int i = l / L.NPz, j = l % L.NPz;
+    return (ex * P + i) * (size_t)L.nzn + ez * L.Pz + j;
   }
   const size_t ez = e % L.Nz, ey = (e / L.Nz) % L.Ny, ex = e / ((size_t)L.Nz * L.Ny);
   const int j = l % NP, m = (l / NP) % NP, i = l / (NP * NP);
@@ -383,20 +397,21 @@ static inline bool is_top(const LevelGeom& L, size_t g) { return (g % L.nzn) == 
 
 std::vector<double> assembled_diag(const LevelGeom& L, const std::vector<double>& Gr, bool masked) {
   std::vector<double> diag(L.N, 0.0);
-  const int NP = L.NP;
-  const size_t NL = L.dim == 2 ? NP * NP : (size_t)NP * NP * NP;
+  const int NP = L.NP, NPz = L.NPz;
+  const size_t NL = L.dim == 2 ? (size_t)NP * NPz : (size_t)NP * NP * NP;
   const double* D = L.D.data();
+  const double* Dz = L.Dz.data();
   for (size_t e = 0; e < L.E; ++e) {
     for (size_t l = 0; l < NL; ++l) {
       double s = 0;
       if (L.dim == 2) {
-        const int i = l / NP, j = l % NP;
+        const int i = l / NPz, j = l % NPz;
         const double* Grr = &Gr[0 * L.E * NL + e * NL];
         const double* Grs = &Gr[1 * L.E * NL + e * NL];
         const double* Gss = &Gr[2 * L.E * NL + e * NL];
-        for (int k = 0; k < NP; ++k) s += D[k * NP + i] * D[k * NP + i] * Grr[k * NP + j];
-        s += 2.0 * D[i * NP + i] * D[j * NP + j] * Grs[i * NP + j];
-        for (int k = 0; k < NP; ++k) s += D[k * NP + j] * D[k * NP + j] * Gss[i * NP + k];
+        for (int k = 0; k < NP; ++k) s += D[k * NP + i] * D[k * NP + i] * Grr[k * NPz + j];
+        s += 2.0 * D[i * NP + i] * Dz[j * NPz + j] * Grs[i * NPz + j];
+        for (int k = 0; k < NPz; ++k) s += Dz[k * NPz + j] * Dz[k * NPz + j] * Gss[i * NPz + k];
       } else {
         const int j = l % NP, m = (l / NP) % NP, i = l / (NP * NP);
         auto G = [&](int f, int a, int b, int c) {
@@ -419,15 +434,17 @@ std::vector<double> assembled_diag(const LevelGeom& L, const std::vector<double>
 
 void element_matrix(const LevelGeom& L, const std::vector<double>& Gr, size_t e, double* Ae) {
   // A_e = sum_q sum_{a,b} G_ab(q) (D_a phi)(q) (D_b phi)(q), quadrature at the GLL nodes.
-  const int NP = L.NP;
+  const int NP = L.NP, NPz = L.NPz;
   const int dim = L.dim;
-  const size_t NL = dim == 2 ? NP * NP : (size_t)NP * NP * NP;
+  const size_t NL = dim == 2 ? (size_t)NP * NPz : (size_t)NP * NP * NP;
   const double* D = L.D.data();
+  const double* Ds = dim == 2 ? L.Dz.data() : D;  // sigma direction
+  const int NS = dim == 2 ? NPz : NP;
   std::fill(Ae, Ae + NL * NL, 0.0);
   std::vector<double> gr(NL * 3);
   for (size_t q = 0; q < NL; ++q) {
     int qi, qm, qj;
-    if (dim == 2) { qi = q / NP; qm = 0; qj = q % NP; }
+    if (dim == 2) { qi = q / NPz; qm = 0; qj = q % NPz; }
     else { qj = q % NP; qm = (q / NP) % NP; qi = q / (NP * NP); }
     double Gq[3][3] = {{0}};
     if (dim == 2) {
@@ -444,11 +461,11 @@ void element_matrix(const LevelGeom& L, const std::vector<double>& Gr, size_t e,
     // reference gradients of every basis function at q (axis 0 = r, 1 = t, 2 = s)
     for (size_t a = 0; a < NL; ++a) {
       int ai, am, aj;
-      if (dim == 2) { ai = a / NP; am = 0; aj = a % NP; }
+      if (dim == 2) { ai = a / NPz; am = 0; aj = a % NPz; }
       else { aj = a % NP; am = (a / NP) % NP; ai = a / (NP * NP); }
       gr[a * 3 + 0] = (am == qm && aj == qj) ? D[qi * NP + ai] : 0.0;
       gr[a * 3 + 1] = (dim == 3 && ai == qi && aj == qj) ? D[qm * NP + am] : 0.0;
-      gr[a * 3 + 2] = (ai == qi && am == qm) ? D[qj * NP + aj] : 0.0;
+      gr[a * 3 + 2] = (ai == qi && am == qm) ? Ds[qj * NS + aj] : 0.0;
     }
     for (size_t a = 0; a < NL; ++a) {
       const double* ga = &gr[a * 3];

@@ -21,12 +21,16 @@ std::vector<double> interp_matrix(const std::vector<double>& rs, const std::vect
 // ---- one level of the hierarchy ------------------------------------------------------------
 struct LevelGeom {
   int dim = 2, P = 1, NP = 2;
+  // 2D: order along sigma (differs from P, the order along x, on semi-coarsened levels); local
+  // node (i, j) is i*NPz + j.  3D: equal to P.
+  int Pz = 1, NPz = 2;
   int Nx = 1, Ny = 1, Nz = 1;
   double Lx = 1, Ly = 1;
   int nxn = 0, nyn = 1, nzn = 0;   // nodes per direction
   size_t N = 0;                    // assembled nodes
   size_t E = 0;                    // elements
-  std::vector<double> r, w, D;     // GLL nodes, weights, differentiation matrix
+  std::vector<double> r, w, D;     // GLL nodes, weights, differentiation matrix (x; 3D all)
+  std::vector<double> rz, wz, Dz;  // the same along sigma (order Pz)
   // geometric factors, natural layout [field][e][local node] with local node
   // 2D (i*NP + j), 3D ((i*NP + m)*NP + j); fields 2D: rr, rs, ss; 3D: rr, tt, rs, ts, ss
   int nfields = 3;
@@ -40,11 +44,12 @@ struct LevelGeom {
 };
 
 // Build level geometry of order P from h, eta sampled at the fine horizontal GLL nodes of
-// order Pf (2D: Nx*Pf+1 values; 3D: (Nx*Pf+1)*(Ny*Pf+1), y fastest).
+// order Pf (2D: Nx*Pf+1 values; 3D: (Nx*Pf+1)*(Ny*Pf+1), y fastest).  Pz (2D only): order
+// along sigma, default P.
 void build_level(LevelGeom& L, int dim, int Nx, int Ny, int Nz, int P, int Pf, double Lx,
-                 double Ly, const double* h_fine, const double* eta_fine);
+                 double Ly, const double* h_fine, const double* eta_fine, int Pz = -1);
 
-// Global node of local node l (2D i*NP + j; 3D (i*NP + m)*NP + j) of element e.
+// Global node of local node l (2D i*NPz + j; 3D (i*NP + m)*NP + j) of element e.
 size_t local_to_global(const LevelGeom& L, size_t e, int l);
 
 // Assembled diagonal of the masked operator from (possibly rounded) factors Gr (same layout

@@ -36,6 +36,15 @@ double acct_total(long* launches);
 GLayout g2d_layout(int P, int Nz, size_t tgsize);
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                    int Nx, int Nz, int masked, hipStream_t st);
+// 2D operator on elements of order PX along x and PZ along sigma (semi.hip): same output
+// format as apply2d with P = PX (lines 0..PX-1 to y, line PX to S of the right neighbour);
+// G in the layout [ex][field][ez][i][j] (j fastest, i < PX+1, j < PZ+1); Dx, Dz the row-major
+// FP64 differentiation matrices.  apply2r_fits: the column fits one workgroup
+// ((PX+1)(PZ+1) Nz <= 1024 threads, 64 KB of LDS).
+bool apply2r_fits(int PX, int PZ, int Nz, bool dbl);
+hipError_t apply2r(int PX, int PZ, bool dbl, GType gt, const void* x, void* y, void* S,
+                   const void* G, const double* Dx, const double* Dz, int Nx, int Nz, int masked,
+                   hipStream_t st);
 // the same, plus each workgroup's part of x . (A x) in dotp[0 .. apply2d_blocks) (P <= 8)
 hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                        int Nx, int Nz, int masked, double* dotp, hipStream_t st);

@@ -36,6 +36,14 @@ using semk::GType;
 
 struct DLevel {
   int P = 1, NP = 2, Nx = 1, Ny = 1, Nz = 1, nxn = 0, nyn = 1, nzn = 0;
+  // 2D: order along sigma (P is the order along x); rect: the two differ, and the level runs
+  // the operator for such elements (Dx, Dz: its FP64 differentiation matrices)
+  int Pz = 1;
+  bool rect = false;
+  double *Dx = nullptr, *Dz = nullptr;
+  // 2D transfers from the next coarser level that change one direction only (axis 0: x,
+  // 2: sigma; -1: both directions, by the equal-order transfer kernels)
+  int axis = -1;
   unsigned N = 0;
   bool dbl = true;            // vector/compute type of this level (coarsest is always FP64)
   GType gt = semk::G_F64;
@@ -199,6 +207,20 @@ std::vector<TG> permute_G2d(const semh::LevelGeom& L, const std::vector<double>&
   return out;
 }
 
+// device factors of a 2D level in its operator's layout: the chunked column layout of the
+// equal-order kernels, or [ex][field][ez][i][j] for elements with different orders
+template <typename TG, typename Conv>
+std::vector<TG> layout_G2(const semh::LevelGeom& L, const std::vector<double>& G, Conv conv) {
+  if (L.Pz == L.P) return permute_G2d<TG>(L, G, conv);
+  const size_t nthr = (size_t)L.NP * L.NPz * L.Nz, E = L.E, nloc = (size_t)L.NP * L.NPz;
+  std::vector<TG> out(3 * E * nloc);
+  for (int ex = 0; ex < L.Nx; ++ex)
+    for (int f = 0; f < 3; ++f)
+      for (size_t t = 0; t < nthr; ++t)
+        out[((size_t)ex * 3 + f) * nthr + t] = conv(G[f * E * nloc + (size_t)ex * nthr + t]);
+  return out;
+}
+
 // run f(lo, hi) over [0, n) on up to 16 host threads (set-up work only)
 // grain: fewest items per thread (heavy items: a small grain spreads them over more threads)
 void parallel_ranges(size_t n, const std::function<void(size_t, size_t)>& f, size_t grain = 64) {
@@ -281,6 +303,9 @@ void apply_level(Ctx* c, int l, const void* x, int masked) {
   if (c->dim == 3)
     HK(semk::apply3d(L.P, L.dbl, L.gt, x, L.y, L.Sx, L.Sy, L.Sxy, L.G, L.Nx, L.Ny, L.Nz, masked,
                      c->st));
+  else if (L.rect)
+    HK(semk::apply2r(L.P, L.Pz, L.dbl, L.gt, x, L.y, L.S, L.G, L.Dx, L.Dz, L.Nx, L.Nz, masked,
+                     c->st));
   else
     HK(semk::apply2d(L.P, L.dbl, L.gt, x, L.y, L.S, L.G, L.Nx, L.Nz, masked, c->st));
 }
@@ -289,6 +314,9 @@ void apply_outer(Ctx* c, const double* x, int masked) {
   DLevel& L = c->lev[0];
   if (c->dim == 3)
     HK(semk::apply3d(L.P, true, semk::G_F64, x, c->yo, c->Sxo, c->Syo, c->Sxyo, c->G64, L.Nx, L.Ny,
+                     L.Nz, masked, c->st));
+  else if (L.rect)
+    HK(semk::apply2r(L.P, L.Pz, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Dx, L.Dz, L.Nx,
                      L.Nz, masked, c->st));
   else
     HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Nx, L.Nz, masked, c->st));
@@ -437,6 +465,21 @@ void restrict_to(Ctx* c, int l, bool use_ax) {
                         c->masked ? nzc : 0, c->st));
     return;
   }
+  if (F.axis >= 0) {  // one direction changes: b_c = R (b - A x) along it, Dirichlet rows zeroed
+    const void* r2 = nullptr;
+    if (use_ax) {  // A x complete into d (dead between the smoothing sweeps)
+      HK(semk::fix_ax(F.dbl, F.y, F.S, F.d, 0, F.N, F.nzn, F.P, c->st));
+      r2 = F.d;
+    }
+    const DLevel::Op1& R = F.R1[F.axis];
+    if (F.axis == 0)
+      HK(semk::axis_apply(F.dbl, C.dbl, F.b, r2, C.b, 0, 1, F.nxn, C.nxn, F.nzn, R.rp, R.ci, R.w,
+                          R.nnz, R.band, R.wband, R.bandmax, c->masked ? C.nzn : 0, c->st));
+    else
+      HK(semk::axis_apply(F.dbl, C.dbl, F.b, r2, C.b, 0, F.nxn, F.nzn, C.nzn, 1, R.rp, R.ci, R.w,
+                          R.nnz, R.band, R.wband, R.bandmax, c->masked ? C.nzn : 0, c->st));
+    return;
+  }
   HK(semk::restrict2d(F.dbl, C.dbl, F.b, F.y, F.S, use_ax ? 1 : 0, C.b, F.J, F.Nx, F.Nz, F.P,
                       C.P, c->masked, c->st));
 }
@@ -455,6 +498,16 @@ void prolong_from(Ctx* c, int l) {
     HK(semk::axis_apply(1, F.dbl, c->tA, nullptr, F.x, 1, nxf * nyf, nzc, nzf, 1, F.P1[2].rp,
                         F.P1[2].ci, F.P1[2].w, F.P1[2].nnz, F.P1[2].band,
                         F.P1[2].wband, F.P1[2].bandmax, 0, c->st));
+    return;
+  }
+  if (F.axis >= 0) {  // x_f += P x_c along the one direction that changes
+    const DLevel::Op1& Pr = F.P1[F.axis];
+    if (F.axis == 0)
+      HK(semk::axis_apply(C.dbl, F.dbl, C.x, nullptr, F.x, 1, 1, C.nxn, F.nxn, F.nzn, Pr.rp,
+                          Pr.ci, Pr.w, Pr.nnz, Pr.band, Pr.wband, Pr.bandmax, 0, c->st));
+    else
+      HK(semk::axis_apply(C.dbl, F.dbl, C.x, nullptr, F.x, 1, F.nxn, C.nzn, F.nzn, 1, Pr.rp,
+                          Pr.ci, Pr.w, Pr.nnz, Pr.band, Pr.wband, Pr.bandmax, 0, c->st));
     return;
   }
   HK(semk::prolong2d(F.dbl, C.dbl, C.x, F.x, F.J, F.Nx, F.Nz, F.P, C.P, c->st));
@@ -686,7 +739,7 @@ void fpcg_iteration(Ctx* c, bool first) {
   vcycle(c, c->ro);
   HK(semk::castdot(L0.dbl, L0.x, c->zo, first ? nullptr : c->qo, c->ro, pset(c, PS_ZQ),
                    pset(c, PS_RZB), N, c->st));
-  if (c->dim == 2 && semk::fpcg2d_fits(L0.P, L0.Nx, L0.Nz)) {
+  if (c->dim == 2 && !L0.rect && semk::fpcg2d_fits(L0.P, L0.Nx, L0.Nz)) {
     // direction update fused with the FP64 operator, then the x / r update (beta in scal[8])
     double* beta = c->scal + 8;
     HK(semk::fpcg2d(L0.P, c->zo, c->po, c->qo, c->G64, L0.Nx, L0.Nz, c->masked, pset(c, PS_RZA),
@@ -872,6 +925,11 @@ void learned_geometry(Ctx* c) {
     return;
   }
   const semh::LevelGeom& G = c->lev[0].geo;
+  if (c->lev[0].rect || c->lev[0].axis >= 0) {  // no learned stage on such a fine level
+    c->geo_h.clear();
+    c->abar_h.clear();
+    return;
+  }
   const int NP = G.NP, n = NP * NP;
   const size_t E = G.E, NL = n;
   c->geo_h.assign(E * 4 * n, 0.f);
@@ -1256,6 +1314,9 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     throw ArgFail{"bad smoother"};
   if (d->smoother == SEM_SMOOTH_SCHWARZ && (d->dim != 2 || d->order > 8))
     throw ArgFail{"the Schwarz smoother is built for 2D meshes with order <= 8"};
+  if (d->order_z < 0 || d->order_z > SEM_MAX_ORDER) throw ArgFail{"order_z out of range"};
+  if (d->dim == 3 && d->order_z != 0 && d->order_z != d->order)
+    throw ArgFail{"3D meshes take one order (order_z 0 or equal to order)"};
   if (d->outer != SEM_OUTER_FPCG && d->outer != SEM_OUTER_PDC && d->outer != SEM_OUTER_GMRES)
     throw ArgFail{"bad outer"};
   if (d->outer == SEM_OUTER_GMRES && (d->gmres_restart < 1 || d->gmres_restart > semk::KRY_MAX))
@@ -1265,18 +1326,56 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     throw ArgFail{"bad Chebyshev parameters"};
   if (d->smoother != SEM_SMOOTH_CHEBYSHEV && (d->nu_pre < 0 || d->nu_post < 0))
     throw ArgFail{"bad sweep counts"};
-  std::vector<int> orders;
+  std::vector<int> orders;   // x orders of the levels
+  std::vector<int> orders_z; // sigma orders (2D)
+  const bool semi = d->dim == 2 && d->order_z > 0 && d->order_z != d->order;
   if (d->nlevels <= 0) {
-    orders.push_back(d->order);
-    while (orders.back() > 1) orders.push_back((orders.back() + 1) / 2);
+    if (semi) {  // semi-coarsening: the larger order drops until the two match, then both
+      int px = d->order, pz = d->order_z;
+      orders.push_back(px);
+      orders_z.push_back(pz);
+      while (px > 1 || pz > 1) {
+        if (px == pz) px = pz = (px + 1) / 2;
+        else if (px > pz) px = std::max((px + 1) / 2, pz);
+        else pz = std::max((pz + 1) / 2, px);
+        orders.push_back(px);
+        orders_z.push_back(pz);
+      }
+      if ((int)orders.size() > SEM_MAX_LEVELS) throw ArgFail{"too many levels"};
+    } else {
+      orders.push_back(d->order);
+      while (orders.back() > 1) orders.push_back((orders.back() + 1) / 2);
+    }
   } else {
     if (d->nlevels > SEM_MAX_LEVELS) throw ArgFail{"too many levels"};
     for (int k = 0; k < d->nlevels; ++k) orders.push_back(d->level_order[k]);
     if (orders[0] != d->order) throw ArgFail{"level_order[0] must equal order"};
-    if (orders.back() != 1) throw ArgFail{"last level order must be 1"};
-    for (size_t k = 1; k < orders.size(); ++k)
-      if (orders[k] >= orders[k - 1] || orders[k] < 1) throw ArgFail{"level orders must decrease"};
+    if (semi || (d->dim == 2 && d->order_z > 0)) {
+      for (int k = 0; k < d->nlevels; ++k) orders_z.push_back(d->level_order_z[k]);
+      if (orders_z[0] != d->order_z) throw ArgFail{"level_order_z[0] must equal order_z"};
+      if (orders.back() != 1 || orders_z.back() != 1) throw ArgFail{"last level orders must be 1"};
+      for (size_t k = 1; k < orders.size(); ++k) {
+        const int fx = orders[k - 1], fz = orders_z[k - 1], cx = orders[k], cz = orders_z[k];
+        if (cx < 1 || cz < 1 || cx > fx || cz > fz || (cx == fx && cz == fz))
+          throw ArgFail{"level orders must not grow and one of them must drop"};
+        if (cx < fx && cz < fz && !(fx == fz && cx == cz))
+          throw ArgFail{"both orders may drop together only between levels of equal orders"};
+      }
+    } else {
+      if (orders.back() != 1) throw ArgFail{"last level order must be 1"};
+      for (size_t k = 1; k < orders.size(); ++k)
+        if (orders[k] >= orders[k - 1] || orders[k] < 1)
+          throw ArgFail{"level orders must decrease"};
+    }
   }
+  for (size_t k = 0; k < orders.size(); ++k)
+    if (orders[k] > SEM_MAX_ORDER || (k < orders_z.size() && orders_z[k] > SEM_MAX_ORDER))
+      throw ArgFail{"level order out of range"};
+  if (orders_z.empty()) orders_z = orders;
+  bool any_rect = false;
+  for (size_t k = 0; k < orders.size(); ++k) any_rect |= orders[k] != orders_z[k];
+  if (any_rect && d->smoother == SEM_SMOOTH_SCHWARZ)
+    throw ArgFail{"the Schwarz smoother needs equal orders along x and sigma"};
   {
     const size_t nh = d->dim == 2 ? (size_t)d->ne[0] * orders[0] + 1
                                   : ((size_t)d->ne[0] * orders[0] + 1) * ((size_t)d->ne[1] * orders[0] + 1);
@@ -1297,9 +1396,16 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     setup3d_impl(c, d, orders);
     return;
   }
-  if ((orders[0] + 1) * c->Nz > 1024) throw ArgFail{"(P+1)*ne[2] must not exceed 1024"};
+  for (size_t k = 0; k < orders.size(); ++k) {
+    if (orders[k] == orders_z[k] && (orders[k] + 1) * c->Nz > 1024)
+      throw ArgFail{"(P+1)*ne[2] must not exceed 1024"};
+    if (orders[k] != orders_z[k] &&
+        !semk::apply2r_fits(orders[k], orders_z[k], c->Nz, true))
+      throw ArgFail{"(P_x+1)*(P_sigma+1)*ne[2] must not exceed 1024 on levels with different "
+                    "orders"};
+  }
   if (c->Nz > 256) throw ArgFail{"ne[2] too large for the coarse solve"};
-  const double N64 = (double)(c->Nx * orders[0] + 1) * (c->Nz * orders[0] + 1);
+  const double N64 = (double)(c->Nx * orders[0] + 1) * (c->Nz * orders_z[0] + 1);
   if (N64 > 2.0e9) throw ArgFail{"problem too large"};
 
   c->ust = (hipStream_t)d->stream;
@@ -1319,9 +1425,15 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   for (int l = 0; l < nl; ++l) {
     DLevel& L = c->lev[l];
     semh::build_level(L.geo, 2, c->Nx, 1, c->Nz, orders[l], orders[0], d->len[0], 1.0, d->h,
-                      d->eta);
+                      d->eta, orders_z[l]);
     L.P = orders[l];
     L.NP = L.P + 1;
+    L.Pz = orders_z[l];
+    L.rect = L.Pz != L.P;
+    if (L.rect) {
+      L.Dx = upload(c, L.geo.D);
+      L.Dz = upload(c, L.geo.Dz);
+    }
     L.Nx = c->Nx;
     L.Nz = c->Nz;
     L.nxn = L.geo.nxn;
@@ -1337,12 +1449,12 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     else if (L.gt == semk::G_BF16)
       for (auto& v : Gr) v = semh::bf16_round(v);
     if (L.gt == semk::G_F64) {
-      L.G = upload(c, permute_G2d<double>(L.geo, L.geo.G, [](double v) { return v; }));
+      L.G = upload(c, layout_G2<double>(L.geo, L.geo.G, [](double v) { return v; }));
     } else if (L.gt == semk::G_F32) {
-      L.G = upload(c, permute_G2d<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
+      L.G = upload(c, layout_G2<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
     } else {
-      L.G = upload(c, permute_G2d<uint16_t>(L.geo, L.geo.G,
-                                            [](double v) { return semh::bf16_bits((float)v); }));
+      L.G = upload(c, layout_G2<uint16_t>(L.geo, L.geo.G,
+                                          [](double v) { return semh::bf16_bits((float)v); }));
     }
     std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
     std::vector<double> dinv(diag.size());
@@ -1356,7 +1468,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     L.y = dalloc(c, L.N * eb);
     L.nS = (size_t)(c->Nx + 1) * L.nzn;
     L.S = dalloc(c, L.nS * eb);
-    if (!coarsest && L.P <= 8 && semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl) > 0 && !no_fused_step)
+    if (!coarsest && !L.rect && L.P <= 8 && semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl) > 0 &&
+        !no_fused_step)
       L.xalt = dalloc(c, L.N * eb);
     if (!coarsest && d->smoother == SEM_SMOOTH_SCHWARZ) {
       const size_t n = (size_t)L.NP * L.NP;
@@ -1369,10 +1482,22 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   for (int l = 0; l + 1 < nl; ++l) {
     DLevel& F = c->lev[l];
     DLevel& C = c->lev[l + 1];
-    F.J = upload(c, semh::interp_matrix(C.geo.r, F.geo.r));
-    if (semk::restrict2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024 ||
-        semk::prolong2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024)
-      throw ArgFail{"transfer kernels exceed LDS for this size"};
+    if (F.P != C.P && F.Pz != C.Pz) {  // both directions (equal orders on both levels)
+      F.J = upload(c, semh::interp_matrix(C.geo.r, F.geo.r));
+      if (semk::restrict2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024 ||
+          semk::prolong2d_smem(F.P, C.P, c->Nz, F.dbl) > 160 * 1024)
+        throw ArgFail{"transfer kernels exceed LDS for this size"};
+      continue;
+    }
+    // one direction: 1D interpolation along it, its transpose for the restriction
+    F.axis = F.P != C.P ? 0 : 2;
+    const bool ax = F.axis == 0;
+    const int Ne = ax ? c->Nx : c->Nz, pf = ax ? F.P : F.Pz, pc = ax ? C.P : C.Pz;
+    const std::vector<double> J =
+        semh::interp_matrix(ax ? C.geo.r : C.geo.rz, ax ? F.geo.r : F.geo.rz);
+    const Rows1 Pr = prol1d_p(Ne, pf, pc, J);
+    upload_op(c, Pr, F.P1[F.axis]);
+    upload_op(c, transpose1d(Pr, Ne * pc + 1), F.R1[F.axis]);
   }
   // coarse levels whose smoothing sequences run as one kernel each (SEM_NO_COARSE_FUSED=1: none)
   {
@@ -1381,7 +1506,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     for (int l = 1; !off && l + 1 < nl; ++l) {
       DLevel& L = c->lev[l];
       const DLevel& C = c->lev[l + 1];
-      if (!L.xalt || !semk::coarse2d_supported(L.P, C.P)) continue;
+      if (!L.xalt || L.axis >= 0 || C.rect || !semk::coarse2d_supported(L.P, C.P)) continue;
       semk::CoarseSeq sq;
       int apre = 0, apost = 0;
       if (!coarse_seq(c, l, true, &sq, &apre) || !coarse_seq(c, l, false, &sq, &apost)) continue;
@@ -1389,12 +1514,12 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       L.cpost = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, false, apost);
     }
   }
-  if (semk::apply2d_smem(orders[0], c->Nz, true) > 160 * 1024)
+  if (!c->lev[0].rect && semk::apply2d_smem(orders[0], c->Nz, true) > 160 * 1024)
     throw ArgFail{"operator kernel exceeds LDS for this size"};
   // outer FP64 operator
   DLevel& L0 = c->lev[0];
   if (L0.dbl) c->G64 = (double*)L0.G;
-  else c->G64 = upload(c, permute_G2d<double>(L0.geo, L0.geo.G, [](double v) { return v; }));
+  else c->G64 = upload(c, layout_G2<double>(L0.geo, L0.geo.G, [](double v) { return v; }));
   const size_t N = L0.N;
   c->xo = (double*)dalloc(c, N * 8);
   c->bo = (double*)dalloc(c, N * 8);
@@ -1411,13 +1536,10 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   {
     std::vector<double> m(N, 0.0);
     const semh::LevelGeom& G = L0.geo;
-    const int NP = G.NP;
-    for (size_t e = 0; e < G.E; ++e) {
-      const size_t ex = e / G.Nz, ez = e % G.Nz;
-      for (int i = 0; i < NP; ++i)
-        for (int j = 0; j < NP; ++j)
-          m[(ex * G.P + i) * G.nzn + ez * G.P + j] += G.mass[e * NP * NP + i * NP + j];
-    }
+    const size_t NL = (size_t)G.NP * G.NPz;
+    for (size_t e = 0; e < G.E; ++e)
+      for (size_t l = 0; l < NL; ++l)
+        m[semh::local_to_global(G, e, (int)l)] += G.mass[e * NL + l];
     c->mass = upload(c, m);
     for (size_t f = 0; f < G.face_idx.size(); ++f) {
       std::vector<long long> idx(G.face_idx[f].begin(), G.face_idx[f].end());
@@ -1602,7 +1724,8 @@ sem_status sem_get_sizes(const sem_ctx* ctx, size_t* n_global, size_t* n_free, s
   const DLevel& L = c->lev[0];
   if (n_global) *n_global = L.N;
   if (n_free) *n_free = L.N - (c->masked ? (size_t)L.nxn * L.nyn : 0);
-  if (n_local) *n_local = L.geo.E * (size_t)std::pow(L.NP, c->dim);
+  if (n_local)
+    *n_local = L.geo.E * (c->dim == 2 ? (size_t)L.geo.NP * L.geo.NPz : (size_t)std::pow(L.NP, 3));
   return SEM_OK;
 }
 
@@ -1614,6 +1737,16 @@ sem_status sem_get_level(const sem_ctx* ctx, int level, int* order, size_t* n, d
   if (order) *order = L.P;
   if (n) *n = L.N;
   if (lam) *lam = L.lam;
+  return SEM_OK;
+}
+
+sem_status sem_get_level_orders(const sem_ctx* ctx, int level, int* order_x, int* order_z) {
+  const Ctx* c = C(ctx);
+  if (!c) return SEM_ERR_ARG;
+  if (level < 0 || level >= (int)c->lev.size()) return SEM_ERR_ARG;
+  const DLevel& L = c->lev[level];
+  if (order_x) *order_x = L.P;
+  if (order_z) *order_z = c->dim == 2 ? L.Pz : L.P;
   return SEM_OK;
 }
 
@@ -1640,11 +1773,12 @@ sem_status sem_node_coords(const sem_ctx* ctx, int level, double* x, double* y, 
   if (y && !G.Y.empty()) std::memcpy(y, G.Y.data(), G.N * 8);
   if (z && level > 0) std::memcpy(z, G.Z.data(), G.N * 8);
   if (z && level == 0) {  // current surface: z = -h + sigma (h + eta) on each vertical line
-    const int P = G.P, nzn = G.nzn;
+    const int Ps = c->dim == 2 ? G.Pz : G.P, nzn = G.nzn;  // order along sigma
+    const std::vector<double>& rs = c->dim == 2 ? G.rz : G.r;
     std::vector<double> sig(nzn);
     for (int iz = 0; iz < nzn; ++iz) {
-      const int ez = iz == nzn - 1 ? G.Nz - 1 : iz / P, j = iz - ez * P;
-      sig[iz] = (ez + (G.r[j] + 1.0) / 2.0) / G.Nz;
+      const int ez = iz == nzn - 1 ? G.Nz - 1 : iz / Ps, j = iz - ez * Ps;
+      sig[iz] = (ez + (rs[j] + 1.0) / 2.0) / G.Nz;
     }
     for (size_t col = 0; col < c->hf_h.size(); ++col)
       for (int iz = 0; iz < nzn; ++iz)
@@ -2278,6 +2412,9 @@ static void learned_load_impl(Ctx* c, const void* blob, size_t nbytes, int enabl
   const bool d3 = c->dim == 3;
   const int n = d3 ? L.NP * L.NP * L.NP : L.NP * L.NP;
   const int nfg = d3 ? 6 : 4;  // geometric feature blocks (factor fields and mass)
+  if (!d3 && (L.rect || L.axis >= 0))
+    throw ArgFail{"learned stage needs equal orders along x and sigma on the fine level and the "
+                  "next"};
   if (!d3 && n > semm::MAX_STAGE_OUT) throw ArgFail{"learned stage needs fine order P <= 8"};
   if (d3 && L.P > semm::MAX_STAGE_P3) throw ArgFail{"learned stage on hexahedra needs fine order P <= 6"};
   if (net.nin != (1 + nfg) * n || net.nout != n) throw ArgFail{"network sizes do not match the mesh"};
@@ -2360,7 +2497,7 @@ static void level_geometry(Ctx* c, int l, semh::LevelGeom& geo) {
   DLevel& L = c->lev[l];
   if (c->dim == 2) {
     semh::build_level(geo, 2, c->Nx, 1, c->Nz, L.P, c->Pf, c->len0, 1.0, c->hf_h.data(),
-                      c->ef_h.data());
+                      c->ef_h.data(), L.Pz);
     return;
   }
   if (L.Nx == c->Nx) {
@@ -2390,8 +2527,10 @@ static void update_outer(Ctx* c) {
   DLevel& L0 = c->lev[0];
   const size_t N = L0.N;
   if ((void*)c->G64 == L0.G) {  // FP64 inner levels share the fine factors: split them
-    const size_t n = c->dim == 2 ? semk::g2d_layout(L0.P, c->Nz, 8).cstride * c->Nx
-                                 : semk::g3d_layout(L0.P, c->Nz, 8).cstride * (size_t)c->Nx * c->Ny;
+    const size_t n = c->dim == 2
+                         ? (L0.rect ? 3 * L0.geo.E * (size_t)L0.geo.NP * L0.geo.NPz
+                                    : semk::g2d_layout(L0.P, c->Nz, 8).cstride * c->Nx)
+                         : semk::g3d_layout(L0.P, c->Nz, 8).cstride * (size_t)c->Nx * c->Ny;
     c->G64 = (double*)dalloc(c, n * 8);
   }
   const std::vector<double>& w = L0.geo.w;
@@ -2400,9 +2539,9 @@ static void update_outer(Ctx* c) {
   if (c->dim == 2) {
     semh::LevelGeom geo;
     level_geometry(c, 0, geo);
-    copy_to(c, c->G64, permute_G2d<double>(geo, geo.G, [](double v) { return v; }));
+    copy_to(c, c->G64, layout_G2<double>(geo, geo.G, [](double v) { return v; }));
     std::vector<double> m(N, 0.0);
-    const size_t NL = (size_t)geo.NP * geo.NP;
+    const size_t NL = (size_t)geo.NP * geo.NPz;
     for (size_t e = 0; e < geo.E; ++e)
       for (size_t l = 0; l < NL; ++l) m[semh::local_to_global(geo, e, (int)l)] += geo.mass[e * NL + l];
     copy_to(c, c->mass, m);
@@ -2464,9 +2603,9 @@ static void rebuild_levels(Ctx* c) {
     else if (L.gt == semk::G_BF16)
       for (auto& v : Gr) v = semh::bf16_round(v);
     if (c->dim == 2) {
-      if (L.gt == semk::G_F64) copy_to(c, L.G, permute_G2d<double>(L.geo, L.geo.G, [](double v) { return v; }));
-      else if (L.gt == semk::G_F32) copy_to(c, L.G, permute_G2d<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
-      else copy_to(c, L.G, permute_G2d<uint16_t>(L.geo, L.geo.G, [](double v) { return semh::bf16_bits((float)v); }));
+      if (L.gt == semk::G_F64) copy_to(c, L.G, layout_G2<double>(L.geo, L.geo.G, [](double v) { return v; }));
+      else if (L.gt == semk::G_F32) copy_to(c, L.G, layout_G2<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
+      else copy_to(c, L.G, layout_G2<uint16_t>(L.geo, L.geo.G, [](double v) { return semh::bf16_bits((float)v); }));
     } else {
       if (L.gt == semk::G_F64) copy_to(c, L.G, permute_G3d<double>(L.geo, [](double v) { return v; }));
       else if (L.gt == semk::G_F32) copy_to(c, L.G, permute_G3d<float>(L.geo, [](double v) { return (float)v; }));
@@ -2610,6 +2749,9 @@ static void stage_features(Ctx* c, const double* r, const double* e, float* X, f
 // the fine level can carry the stage: 2D P <= 8, 3D P <= 6
 static void check_stage_mesh(Ctx* c) {
   DLevel& L = c->lev[0];
+  if (c->dim == 2 && (L.rect || L.axis >= 0))
+    throw ArgFail{"learned stage needs equal orders along x and sigma on the fine level and the "
+                  "next"};
   if (c->dim == 2 && L.NP * L.NP > semm::MAX_STAGE_OUT)
     throw ArgFail{"learned stage needs fine order P <= 8"};
   if (c->dim == 3 && L.P > semm::MAX_STAGE_P3)
@@ -2929,7 +3071,8 @@ sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int kind, double* b
   const semk::GType gt = kind == 1 ? semk::G_F64 : L.gt;
   const double sv = dbl ? 8.0 : 4.0;
   const double sg = gt == semk::G_F64 ? 8.0 : (gt == semk::G_F32 ? 4.0 : 2.0);
-  const double nloc = (double)L.geo.E * std::pow((double)L.NP, c->dim);
+  const double nloc = c->dim == 2 ? (double)L.geo.E * L.geo.NP * L.geo.NPz
+                                  : (double)L.geo.E * std::pow((double)L.NP, 3);
   const double nvec = kind == 2 ? 6.0 : 2.0;  // step: x, b, dinv, d read; x, d written
   *bytes = nvec * sv * L.N + L.geo.nfields * sg * nloc;
   return SEM_OK;

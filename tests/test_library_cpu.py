@@ -65,3 +65,46 @@ def test_library_gll_rule_matches_oracle(P):
     r, w = B.sem_gll(P)
     assert np.abs(r - gll.gll_nodes(P)).max() < 1e-15
     assert np.abs(w - gll.gll_weights(P)).max() < 1e-14
+
+
+def test_bad_semi_coarsened_descriptors_are_rejected_before_gpu_use():
+    """Orders along x and sigma that the hierarchy cannot take: out of range, 3D with two
+    orders, level lists where an order grows, nothing drops, both drop between levels of
+    different orders, a first or last level that does not match, the Schwarz smoother on
+    such levels, and columns too tall for one workgroup."""
+    from paper_2411_14977_amd import binding as B
+    h = np.ones(4096)
+    dp = ctypes.POINTER(ctypes.c_double)
+
+    def desc(order, order_z, levels=None, dim=2, ne=(4, 1, 2), smoother=None):
+        d = B.sem_mesh_desc_default()
+        d.dim, d.order, d.order_z = dim, order, order_z
+        for k in range(3):
+            d.ne[k] = ne[k]
+        d.h = h.ctypes.data_as(dp)
+        d.eta = h.ctypes.data_as(dp)
+        if smoother is not None:
+            d.smoother = smoother
+        if levels:
+            d.nlevels = len(levels)
+            for k, (px, pz) in enumerate(levels):
+                d.level_order[k], d.level_order_z[k] = px, pz
+        return d
+
+    bad = [
+        desc(4, 13),
+        desc(4, -1),
+        desc(4, 2, dim=3, ne=(2, 2, 2)),
+        desc(6, 3, [(6, 3), (6, 4), (3, 3), (1, 1)]),          # sigma order grows
+        desc(6, 3, [(6, 3), (6, 3), (1, 1)]),                  # nothing drops
+        desc(6, 3, [(6, 3), (3, 2), (1, 1)]),                  # both drop, orders differ
+        desc(6, 3, [(6, 2), (3, 2), (1, 1)]),                  # first level is not (6, 3)
+        desc(6, 3, [(6, 3), (3, 3), (2, 2)]),                  # last level is not (1, 1)
+        desc(6, 3, smoother=2),                                # Schwarz on unequal orders
+        desc(12, 8, ne=(4, 1, 20)),                            # 13 * 9 * 20 threads > 1024
+    ]
+    for d in bad:
+        with pytest.raises(B.SemError) as e:
+            B.sem_mesh_setup(d)
+        assert e.value.status == 1
+
