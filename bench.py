@@ -378,35 +378,45 @@ def paper_context(prec):
     and the scaling figure) rerun with this solver on the synthetic tank: N_z = 2, P = 8,
     N_x = 102 at tolerances 1e-4, 1e-6, 1e-8 (PDC, FPCG and GMRES, the paper's two outer
     methods and this solver's default), then at 1e-6 the iterations and time against N_x
-    (P = 8, element width fixed at 0.25 m) and against P (N_x = 200) for FPCG and GMRES.  Inner
-    precision as the timed path, Chebyshev(3) smoothing; context, not the headline."""
+    (P = 8, element width fixed at 0.25 m) and against the horizontal order P_x at N_x = 200
+    with the vertical order fixed at P_z = 8 (semi-coarsened hierarchy, Sec. 5.1), for FPCG and
+    GMRES; beside it the equal-order sweep P_x = P_z.  Inner precision as the timed path,
+    Chebyshev(3) smoothing; context, not the headline."""
     import torch
 
     import workloads as W
     from paper_2411_14977_amd import cases
 
-    def run(Nx, P, outer, tols):
-        wl = W.tank(Nx, 2, P, Lx=0.25 * Nx, name=f"ctx{Nx}p{P}")
+    def run(Nx, P, outer, tols, Pz=None):
+        if Pz is None:
+            wl = W.tank(Nx, 2, P, Lx=0.25 * Nx, name=f"ctx{Nx}p{P}")
+        else:
+            wl = W.tank_semi(Nx, 2, P, Pz, Lx=0.25 * Nx, name=f"ctx{Nx}p{P}z{Pz}")
         s = cases.make_solver(wl, prec=prec, outer=outer)
         rhs = cases.make_rhs(wl, s)
         rows = {}
         for tol in tols:
             t, info, _ = time_solves(s, rhs, 2, 1, tol)
             rows[f"{tol:g}"] = {"iters": info.iters, "ms": t * 1e3}
+        levels = [list(s.level_orders(l)) for l in range(s.nlevels)]
         s.close()
-        return wl.n_global, rows
+        return wl.n_global, rows, levels
 
-    out = {"table": {}, "scaling_nx": [], "scaling_p": []}
+    out = {"table": {}, "scaling_nx": [], "scaling_px_pz8": [], "scaling_p": []}
     for outer in ("pdc", "fpcg", "gmres"):
-        n, rows = run(102, 8, outer, (1e-4, 1e-6, 1e-8))
+        n, rows, _ = run(102, 8, outer, (1e-4, 1e-6, 1e-8))
         out["table"][outer] = {"n_global": n, **rows}
     for outer in ("fpcg", "gmres"):
         for Nx in (25, 50, 100, 200, 400, 800):
-            n, rows = run(Nx, 8, outer, (1e-6,))
+            n, rows, _ = run(Nx, 8, outer, (1e-6,))
             out["scaling_nx"].append({"outer": outer, "Nx": Nx, "P": 8, "n_global": n,
                                       **rows["1e-06"]})
+        for Px in (2, 3, 4, 5, 6, 7, 8, 10, 12):
+            n, rows, levels = run(200, Px, outer, (1e-6,), Pz=8)
+            out["scaling_px_pz8"].append({"outer": outer, "Nx": 200, "Px": Px, "Pz": 8,
+                                          "n_global": n, "levels": levels, **rows["1e-06"]})
         for P in (2, 3, 4, 5, 6, 7, 8):
-            n, rows = run(200, P, outer, (1e-6,))
+            n, rows, _ = run(200, P, outer, (1e-6,))
             out["scaling_p"].append({"outer": outer, "Nx": 200, "P": P, "n_global": n,
                                      **rows["1e-06"]})
     torch.cuda.synchronize()
@@ -682,6 +692,10 @@ def main():
     if not args.no_context:
         context = paper_context(args.prec)
         log(f"[bench] paper-shaped runs: {context['table']}")
+        for outer in ("fpcg", "gmres"):
+            sw = [r for r in context["scaling_px_pz8"] if r["outer"] == outer]
+            log(f"[bench] P_x sweep at P_z = 8, N_x = 200, tol 1e-6 ({outer}): " +
+                ", ".join(f"P_x={r['Px']}: {r['iters']} it {r['ms']:.2f} ms" for r in sw))
 
     schwarz = None
     if not args.no_schwarz:
