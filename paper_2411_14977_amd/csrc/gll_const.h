@@ -1,5 +1,5 @@
-// Compile-time GLL nodes and differentiation matrix for the device kernels, so that every entry
-// of D enters an instruction as a literal operand (no loads, no registers).
+// Compile-time GLL nodes, weights and differentiation matrix for the device kernels, so that every
+// entry of D enters an instruction as a literal operand (no loads, no registers).
 //
 // Nodes: the P+1 roots of (1 - x^2) L_P'(x) (Gauss-Lobatto-Legendre), found by Newton's method on
 // x L_P(x) - L_{P-1}(x), which vanishes exactly at the GLL points, from the Chebyshev-Gauss-
@@ -45,6 +45,7 @@ constexpr void legendre2(int n, double x, double& pn, double& pn1) {  // L_n(x),
 template <int P>
 struct Tab {
   double x[P + 1] = {};
+  double w[P + 1] = {};   // GLL weights 2 / (P (P+1) L_P(x_i)^2)
   double D[P + 1][P + 1] = {};
   constexpr Tab() {
     for (int i = 0; i <= P; ++i) {
@@ -67,6 +68,7 @@ struct Tab {
       double ln1 = 0.0;
       legendre2(P, x[i], L[i], ln1);
     }
+    for (int i = 0; i <= P; ++i) w[i] = 2.0 / (P * (P + 1.0) * L[i] * L[i]);
     for (int i = 0; i <= P; ++i)
       for (int j = 0; j <= P; ++j) D[i][j] = (i == j) ? 0.0 : L[i] / (L[j] * (x[i] - x[j]));
     D[0][0] = -P * (P + 1.0) / 4.0;

@@ -11,7 +11,12 @@ namespace semk {
 constexpr int NRED = 1024;   // partial sums per reduction (fixed: deterministic results)
 constexpr int RED_THREADS = 256;
 
-enum GType { G_F64 = 0, G_F32 = 1, G_BF16 = 2 };
+// G_COL64 (2D FP64 operator): no stored factors; the kernel forms them from four FP64 values per
+// element column and horizontal node, [ex][i] {w_i d dsig/dx, w_i dx/(dsig d), h_x, d_x}
+// (d = h + eta): G_rr = w_j c0, G_rs = w_i w_j (h_x - sigma d_x), G_ss = w_j c3 ((h_x -
+// sigma d_x)^2 + 1), which are the sigma-mapped factors of the stored layouts
+enum GType { G_F64 = 0, G_F32 = 1, G_BF16 = 2, G_COL64 = 3 };
+constexpr int COLGEO_N = 4;  // values per column node of G_COL64
 
 // ---- operator --------------------------------------------------------------------------
 // 2D: one workgroup per element column; y gets lines 0..P-1 of each column (and line P of
@@ -224,10 +229,11 @@ hipError_t bcr_bwd_all(const double* bred, double* x, const double* Bk, const Bc
 // then update_xrp: p = z + beta p, x += alpha p, r -= alpha q with alpha = sum(prz_new) /
 // sum(ppq_new), r.r partials, and the partial sets moved to prz_old / ppq_old.
 bool fpcg2d_fits(int P, int Nx, int Nz);
+// col: G holds G_COL64 column data instead of stored FP64 factors
 hipError_t fpcg2d(int P, const double* z, const double* p, double* q, const double* G, int Nx,
                   int Nz, int masked, const double* prz_old, const double* ppq_old,
                   const double* pzq, int first, double* ppq_new, double* beta_out,
-                  hipStream_t st);
+                  hipStream_t st, int col = 0);
 hipError_t update_xrp(double* x, double* r, double* p, const double* z, const double* q,
                       const double* beta, int first, const double* prz_new,
                       const double* ppq_new, double* prz_old, double* ppq_old, double* prr,

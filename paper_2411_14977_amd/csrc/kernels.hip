@@ -15,6 +15,7 @@
 
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "gll_const.h"
 #include "kernels.h"
@@ -260,6 +261,39 @@ __device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int n
     for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(&raw[f * NP + j]);
 }
 
+// G_COL64: the factors of thread t = ez NP + i (vertical line i of element ez) formed from the
+// column record of (ex, i), {c0 = w_i d dsig/dx, c3 = w_i dx/(dsig d), h_x, d_x}, and the
+// compile-time GLL nodes and weights: with sigma_j = (ez + (r_j + 1)/2)/Nz and
+// a = h_x - sigma_j d_x (= d sigma_x), G_rr = w_j c0, G_rs = w_i w_j a, G_ss = w_j c3 (a^2 + 1)
+struct ColGeo64 {
+  double v;
+};
+template <int P, typename T>
+__device__ __forceinline__ void colgeo_g2d(const double* __restrict__ CG, int ex, int Nz, int t,
+                                           T (&g)[3][P + 1]) {
+  constexpr int NP = P + 1;
+  const int i = t % NP, ez = t / NP;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* c = reinterpret_cast<const d2*>(CG + ((size_t)ex * NP + i) * COLGEO_N);
+  const d2 c03 = c[0], hd = c[1];
+  double wi = 0.0;
+  gllc::sfor<NP>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (i == k) wi = gllc::tab<P>.w[k];
+  });
+  const double inz = 1.0 / Nz;
+  gllc::sfor<NP>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    constexpr double wj = gllc::tab<P>.w[j];
+    constexpr double hr = 0.5 * (gllc::tab<P>.x[j] + 1.0);
+    const double sig = (ez + hr) * inz;
+    const double a = fma(-sig, hd[1], hd[0]);
+    g[0][j] = (T)(wj * c03[0]);
+    g[1][j] = (T)((wi * wj) * a);
+    g[2][j] = (T)(wj * c03[1] * fma(a, a, 1.0));
+  });
+}
+
 // The operator on one element column (slot) of a workgroup.  Thread t = ez * NP + q of the slot
 // has two roles in element ez: the vertical line i = q (sigma-direction contractions, geometric
 // factors) and the horizontal row j = q (x-direction contractions).  The roles swap data through
@@ -282,7 +316,11 @@ __device__ __forceinline__ void column_apply(Ldx&& ldx, const TG* __restrict__ G
   // every global load of the block (the caller's through pre()) is issued before the first LDS
   // store
   T g[3][P + 1];
-  if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
+  if constexpr (std::is_same<TG, ColGeo64>::value) {
+    if (act) colgeo_g2d<P, T>(reinterpret_cast<const double*>(G), ex, Nz, t, g);
+  } else {
+    if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
+  }
   column_apply_g<P, T>(g, ldx, t, act, Nz, nzn, nzp, masked, base, xin, pre);
 }
 
@@ -930,7 +968,7 @@ hipError_t asm_sweep(int P, bool dbl, const void* r, const void* Ainv, void* z, 
 // sets prz_old, ppq_old, pzq; then q = A p, complete at every owned node, and each workgroup's
 // part of p . q into ppq_new.  p itself is not written here (other workgroups still read the old
 // p); block 0 stores beta in *beta_out for the update kernel.
-template <int P>
+template <int P, bool COL>
 __global__ __launch_bounds__(1024) void k_fpcg2d(const double* __restrict__ z,
                                                  const double* __restrict__ p,
                                                  double* __restrict__ q,
@@ -964,7 +1002,11 @@ __global__ __launch_bounds__(1024) void k_fpcg2d(const double* __restrict__ z,
   // every global input is requested before beta is formed: the factors, z and p of this
   // thread's nodes and the three partial-sum sets (each summed in the order sum_partials uses)
   double g[3][NP], zr[NP], pr[NP];
-  if (valid) load_g2d<P, double, double>(G, valid ? ex : 0, nthr, t, g);
+  if constexpr (COL) {
+    if (valid) colgeo_g2d<P, double>(G, ex, Nz, t, g);
+  } else {
+    if (valid) load_g2d<P, double, double>(G, valid ? ex : 0, nthr, t, g);
+  }
   if (valid && t < nzn) {
 #pragma unroll
     for (int l = 0; l < NP; ++l) {
@@ -1018,7 +1060,7 @@ __global__ __launch_bounds__(1024) void k_fpcg2d(const double* __restrict__ z,
   if (threadIdx.x == 0) ppq_new[blockIdx.x] = tot;
 }
 
-template <int P>
+template <int P, bool COL>
 static hipError_t launch_fpcg2d(const double* z, const double* p, double* q, const double* G,
                                 int Nx, int Nz, int masked, const double* prz_old,
                                 const double* ppq_old, const double* pzq, int first,
@@ -1031,10 +1073,10 @@ static hipError_t launch_fpcg2d(const double* z, const double* p, double* q, con
   const size_t smem = apply2d_smem(P, Nz, true) * (cpb + 1);
   if (threads > 1024 || smem > 160 * 1024 || blocks > NRED) return hipErrorInvalidValue;
   const int remap = (blocks % 8 == 0) ? 1 : 0;
-  hipError_t e = allow_lds(k_fpcg2d<P>, smem);
+  hipError_t e = allow_lds(k_fpcg2d<P, COL>, smem);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_fpcg2d<P>), dim3(blocks), dim3(threads), smem, st, z, p, q, G, Nx, Nz,
-                     masked, cpb, remap, prz_old, ppq_old, pzq, first, ppq_new, beta_out);
+  hipLaunchKernelGGL((k_fpcg2d<P, COL>), dim3(blocks), dim3(threads), smem, st, z, p, q, G, Nx,
+                     Nz, masked, cpb, remap, prz_old, ppq_old, pzq, first, ppq_new, beta_out);
   return hipGetLastError();
 }
 
@@ -1046,11 +1088,13 @@ bool fpcg2d_fits(int P, int Nx, int Nz) {
 hipError_t fpcg2d(int P, const double* z, const double* p, double* q, const double* G, int Nx,
                   int Nz, int masked, const double* prz_old, const double* ppq_old,
                   const double* pzq, int first, double* ppq_new, double* beta_out,
-                  hipStream_t st) {
-  acct_add(8.0 * nodes2(P, Nx, Nz) * (first ? 2 : 3) + 24.0 * local2(P, Nx, Nz));
+                  hipStream_t st, int col) {
+  acct_add(8.0 * nodes2(P, Nx, Nz) * (first ? 2 : 3) +
+           (col ? 8.0 * COLGEO_N * Nx * (P + 1) : 24.0 * local2(P, Nx, Nz)));
   switch (P) {
 #define SEM_FPCG2D(PP) \
-  case PP: return launch_fpcg2d<PP>(z, p, q, G, Nx, Nz, masked, prz_old, ppq_old, pzq, first, ppq_new, beta_out, st);
+  case PP: return col ? launch_fpcg2d<PP, true>(z, p, q, G, Nx, Nz, masked, prz_old, ppq_old, pzq, first, ppq_new, beta_out, st) \
+                      : launch_fpcg2d<PP, false>(z, p, q, G, Nx, Nz, masked, prz_old, ppq_old, pzq, first, ppq_new, beta_out, st);
     SEM_FPCG2D(1) SEM_FPCG2D(2) SEM_FPCG2D(3) SEM_FPCG2D(4)
     SEM_FPCG2D(5) SEM_FPCG2D(6) SEM_FPCG2D(7) SEM_FPCG2D(8)
 #undef SEM_FPCG2D
@@ -1267,6 +1311,10 @@ static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G,
 template <int P>
 static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                             int Nx, int Nz, int masked, hipStream_t st) {
+  if (gt == G_COL64) {
+    if (!dbl) return hipErrorInvalidValue;
+    return launch_apply2d<P, double, ColGeo64>(x, y, S, G, Nx, Nz, masked, nullptr, st);
+  }
   if (dbl) return launch_apply2d<P, double, double>(x, y, S, G, Nx, Nz, masked, nullptr, st);
   if (gt == G_BF16)
     return launch_apply2d<P, float, uint16_t>(x, y, S, G, Nx, Nz, masked, nullptr, st);
@@ -1275,7 +1323,8 @@ static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S,
 
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                    int Nx, int Nz, int masked, hipStream_t st) {
-  acct_add(2 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz));
+  acct_add(2 * vsz(dbl) * nodes2(P, Nx, Nz) +
+           (gt == G_COL64 ? 8.0 * COLGEO_N * Nx * (P + 1) : 3 * gsz(gt) * local2(P, Nx, Nz)));
   switch (P) {
     case 1: return apply2d_p<1>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
     case 2: return apply2d_p<2>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);

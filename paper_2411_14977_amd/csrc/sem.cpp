@@ -86,8 +86,10 @@ struct Ctx {
   // per-iteration partial sums copied to the host (two alternating slots; slot 2: the initial
   // residual's)
   hipEvent_t ev_it[3] = {nullptr, nullptr, nullptr};
-  // fine-level FP64 operator for the outer loop
+  // fine-level FP64 operator for the outer loop: stored factors (3D, and 2D levels with two
+  // orders), or in 2D the column records the operator forms its factors from (G_COL64)
   double* G64 = nullptr;
+  double* CG64 = nullptr;
   bool G64_owned = false;
   double *xo = nullptr, *bo = nullptr, *ro = nullptr, *po = nullptr, *qo = nullptr,
          *zo = nullptr, *yo = nullptr, *So = nullptr, *mass = nullptr;
@@ -221,6 +223,31 @@ std::vector<TG> layout_G2(const semh::LevelGeom& L, const std::vector<double>& G
   return out;
 }
 
+// G_COL64 records of a 2D equal-order level: per element column ex and horizontal node i,
+// {w_i d dsig/dx, w_i dx/(dsig d), h_x, d_x} with d = h + eta and the x-derivatives by spectral
+// differentiation within the element (the quantities the stored factors are built from)
+std::vector<double> column_records(const semh::LevelGeom& L) {
+  const int NP = L.NP;
+  const double dx = L.Lx / L.Nx, dsig = 1.0 / L.Nz;
+  std::vector<double> out((size_t)L.Nx * NP * semk::COLGEO_N);
+  for (int ex = 0; ex < L.Nx; ++ex)
+    for (int i = 0; i < NP; ++i) {
+      double a = 0, b = 0;
+      for (int k = 0; k < NP; ++k) {
+        const double hk = L.col_h[(size_t)ex * NP + k], ek = L.col_eta[(size_t)ex * NP + k];
+        a += L.D[i * NP + k] * hk;
+        b += L.D[i * NP + k] * (hk + ek);
+      }
+      const double d = L.col_h[(size_t)ex * NP + i] + L.col_eta[(size_t)ex * NP + i];
+      double* r = &out[((size_t)ex * NP + i) * semk::COLGEO_N];
+      r[0] = L.w[i] * d * dsig / dx;
+      r[1] = L.w[i] * dx / (dsig * d);
+      r[2] = 2.0 / dx * a;
+      r[3] = 2.0 / dx * b;
+    }
+  return out;
+}
+
 // run f(lo, hi) over [0, n) on up to 16 host threads (set-up work only)
 // grain: fewest items per thread (heavy items: a small grain spreads them over more threads)
 void parallel_ranges(size_t n, const std::function<void(size_t, size_t)>& f, size_t grain = 64) {
@@ -319,7 +346,8 @@ void apply_outer(Ctx* c, const double* x, int masked) {
     HK(semk::apply2r(L.P, L.Pz, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Dx, L.Dz, L.Nx,
                      L.Nz, masked, c->st));
   else
-    HK(semk::apply2d(L.P, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Nx, L.Nz, masked, c->st));
+    HK(semk::apply2d(L.P, true, semk::G_COL64, x, c->yo, c->So, c->CG64, L.Nx, L.Nz, masked,
+                     c->st));
 }
 
 // one smoother step from the current x:  r = b - A x;  d = cd d + cr dinv r;  x += d
@@ -742,8 +770,9 @@ void fpcg_iteration(Ctx* c, bool first) {
   if (c->dim == 2 && !L0.rect && semk::fpcg2d_fits(L0.P, L0.Nx, L0.Nz)) {
     // direction update fused with the FP64 operator, then the x / r update (beta in scal[8])
     double* beta = c->scal + 8;
-    HK(semk::fpcg2d(L0.P, c->zo, c->po, c->qo, c->G64, L0.Nx, L0.Nz, c->masked, pset(c, PS_RZA),
-                    pset(c, PS_PQ), pset(c, PS_ZQ), first ? 1 : 0, pset(c, PS_PQ2), beta, c->st));
+    HK(semk::fpcg2d(L0.P, c->zo, c->po, c->qo, c->CG64, L0.Nx, L0.Nz, c->masked,
+                    pset(c, PS_RZA), pset(c, PS_PQ), pset(c, PS_ZQ), first ? 1 : 0,
+                    pset(c, PS_PQ2), beta, c->st, 1));
     HK(semk::update_xrp(c->xo, c->ro, c->po, c->zo, c->qo, beta, first ? 1 : 0,
                         pset(c, PS_RZB), pset(c, PS_PQ2), pset(c, PS_RZA), pset(c, PS_PQ),
                         pset(c, PS_RR), N, c->st));
@@ -1516,10 +1545,14 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   }
   if (!c->lev[0].rect && semk::apply2d_smem(orders[0], c->Nz, true) > 160 * 1024)
     throw ArgFail{"operator kernel exceeds LDS for this size"};
-  // outer FP64 operator
+  // outer FP64 operator: column records (equal orders) or stored factors (two orders)
   DLevel& L0 = c->lev[0];
-  if (L0.dbl) c->G64 = (double*)L0.G;
-  else c->G64 = upload(c, layout_G2<double>(L0.geo, L0.geo.G, [](double v) { return v; }));
+  if (L0.rect) {
+    if (L0.dbl) c->G64 = (double*)L0.G;
+    else c->G64 = upload(c, layout_G2<double>(L0.geo, L0.geo.G, [](double v) { return v; }));
+  } else {
+    c->CG64 = upload(c, column_records(L0.geo));
+  }
   const size_t N = L0.N;
   c->xo = (double*)dalloc(c, N * 8);
   c->bo = (double*)dalloc(c, N * 8);
@@ -2526,7 +2559,7 @@ static void copy_to(Ctx* c, void* dst, const std::vector<T>& h) {
 static void update_outer(Ctx* c) {
   DLevel& L0 = c->lev[0];
   const size_t N = L0.N;
-  if ((void*)c->G64 == L0.G) {  // FP64 inner levels share the fine factors: split them
+  if (c->G64 && (void*)c->G64 == L0.G) {  // FP64 inner levels share the fine factors: split them
     const size_t n = c->dim == 2
                          ? (L0.rect ? 3 * L0.geo.E * (size_t)L0.geo.NP * L0.geo.NPz
                                     : semk::g2d_layout(L0.P, c->Nz, 8).cstride * c->Nx)
@@ -2539,7 +2572,8 @@ static void update_outer(Ctx* c) {
   if (c->dim == 2) {
     semh::LevelGeom geo;
     level_geometry(c, 0, geo);
-    copy_to(c, c->G64, layout_G2<double>(geo, geo.G, [](double v) { return v; }));
+    if (c->CG64) copy_to(c, c->CG64, column_records(geo));
+    else copy_to(c, c->G64, layout_G2<double>(geo, geo.G, [](double v) { return v; }));
     std::vector<double> m(N, 0.0);
     const size_t NL = (size_t)geo.NP * geo.NPz;
     for (size_t e = 0; e < geo.E; ++e)
@@ -2964,7 +2998,7 @@ sem_status sem_time_operator(sem_ctx* ctx, int level, int kind, int reps, int fl
     // data from HBM (the copies hold the same values, so the work is the same)
     std::vector<void**> slots;
     if (kind == 1) {
-      slots = {(void**)&c->po, (void**)&c->yo, (void**)&c->G64};
+      slots = {(void**)&c->po, (void**)&c->yo, c->CG64 ? (void**)&c->CG64 : (void**)&c->G64};
       if (c->dim == 3) slots.insert(slots.end(), {(void**)&c->Sxo, (void**)&c->Syo, (void**)&c->Sxyo});
       else slots.push_back((void**)&c->So);
     } else if (kind == 2) {
@@ -3075,6 +3109,8 @@ sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int kind, double* b
                                   : (double)L.geo.E * std::pow((double)L.NP, 3);
   const double nvec = kind == 2 ? 6.0 : 2.0;  // step: x, b, dinv, d read; x, d written
   *bytes = nvec * sv * L.N + L.geo.nfields * sg * nloc;
+  if (kind == 1 && c->CG64)  // the outer operator forms its factors from column records
+    *bytes = nvec * sv * L.N + 8.0 * semk::COLGEO_N * (double)L.Nx * L.NP;
   return SEM_OK;
 }
 
