@@ -3,17 +3,19 @@
 A step is one full solve (x = 0 -> ||b - A x|| <= 1e-10 ||b||) of the synthetic wave-tank
 workload (1024 x 16 elements, P = 8, 1,056,897 nodes), inputs resident in HBM.  The timed path
 (``value``) is the mixed-precision p-multigrid with the learned element-local smoothing stage:
-FP32 inner V-cycle (geometric factors stored in BF16 unless --prec f32), BF16-MFMA network stage
+FP32 inner V-cycle (geometric factors stored in BF16; --prec f32 stores them in FP32, --prec col
+forms them in registers from FP64 column records), BF16-MFMA network stage
 on the fine level, FP64 outer flexible CG.  Its network is trained first, on the GPU, by the
 library's own kernels from pairs that the plain p-multigrid generates (outside the timed region;
 the training time is reported).  The stage's three placements (after pre-smoothing, before
 post-smoothing, both) are timed and the fastest is the headline; beside it the same solver
-without the stage (with the break-even cost of the stage), the plain FP64 p-multigrid, per-cycle
+without the stage (with the break-even cost of the stage) and with each way of holding the inner
+factors, the plain FP64 p-multigrid, per-cycle
 residual reduction in defect-correction (PDC) mode with and without the stage, iterations and
 times on 20 unseen test surfaces (the oracle solves three of them on the host cores, in child
 processes, and checks the GPU's pressure), the roofline of the dominant kernel (the fused
 operator + smoother step; HBM-resident timing with rotated buffers, the cache-resident figure
-beside it), the whole solve's algorithmic bytes over its time, and the CPU oracle timed on a
+and a plain device copy of the same bytes beside it), the whole solve's algorithmic bytes over its time, and the CPU oracle timed on a
 bounded sample of the same workload.
 
 A 3D time series (64 x 64 x 8, P = 6, moving surface, warm starts, frozen preconditioner) is
@@ -66,7 +68,9 @@ def describe(wl, prec, learned, mode=0):
                         f"rhs seed {wl.rhs_seed}",
             "n_global": wl.n_global, "elements": wl.n_elements, "order": wl.P,
             "inner": {"bf16": "fp32 compute, geometric factors bf16",
-                      "f32": "fp32 compute, geometric factors fp32"}[prec],
+                      "f32": "fp32 compute, geometric factors fp32",
+                      "col": "fp32 compute, geometric factors formed in registers from fp64 "
+                             "column records (d, h_x, d_x per column node)"}[prec],
             "outer": "fp64 flexible CG, fp64 operator and inner products, fp64 P=1 coarse solve",
             "learned_stage": ("element-local MLP 405-128-128-81 (GELU), bf16 MFMA operands, fp32 "
                               f"accumulate; {where} (the fastest of the three placements); "
@@ -423,6 +427,32 @@ def paper_context(prec):
     return out
 
 
+def copy_reference(nbytes):
+    """A plain device-to-device copy that moves the same number of bytes (half read, half
+    written), timed HBM-resident the same way (rotated buffers, over 768 MiB in all): the
+    bandwidth a launch of this size reaches without any arithmetic."""
+    import torch
+    n = max(1, int(nbytes / 8))  # float32 elements per side
+    R = max(2, int(800e6 / (nbytes)) + 1)
+    src = [torch.ones(n, device="cuda") for _ in range(R)]
+    dst = [torch.empty(n, device="cuda") for _ in range(R)]
+    for k in range(R):
+        dst[k].copy_(src[k])
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3 * R
+    torch.cuda.synchronize()
+    e0.record()
+    for k in range(reps):
+        dst[k % R].copy_(src[k % R])
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    ach = 8.0 * n / (ms * 1e-3) / 1e9
+    return {"bytes": 8.0 * n, "avg_launch_ms": ms, "achieved": ach, "frac": ach / HBM_PEAK_GBS,
+            "timing": "torch device copy, rotated buffers, CUDA events on the current stream"}
+
+
 def traffic_from_profiles(kernel_tag):
     """HBM traffic per launch measured by rocprofv3 PMC passes (profiles/*.json), only if
     the kernel source is unchanged since the counters were taken."""
@@ -505,7 +535,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c4")
-    ap.add_argument("--prec", default="bf16", choices=["bf16", "f32"])
+    ap.add_argument("--prec", default="bf16", choices=["bf16", "f32", "col"])
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--no-learned", action="store_true", help="time the V-cycle without the stage")
     ap.add_argument("--train-surfaces", type=int, default=40)
@@ -548,6 +578,7 @@ def main():
     s = cases.make_solver(wl, prec=args.prec)
     rhs = cases.make_rhs(wl, s)
     plain_mixed = None
+    factor_rows = None
     placements = None
     mode = 0
     if use_learned:
@@ -556,6 +587,17 @@ def main():
                        "gdof_per_s": wl.n_global / t_nl / 1e9, "iters": info_nl.iters,
                        "rel_res": info_nl.rel_res}
         log(f"[bench] mixed without stage: {t_nl * 1e3:.3f} ms/solve, {info_nl.iters} iterations")
+        # the other ways of holding the inner geometric factors, same solve
+        factor_rows = {args.prec: dict(plain_mixed)}
+        for pv in ("bf16", "f32", "col"):
+            if pv == args.prec:
+                continue
+            sp = cases.make_solver(wl, prec=pv)
+            tp, ip, _ = time_solves(sp, rhs, args.steps, args.warmup, args.tol)
+            factor_rows[pv] = {"ms_per_solve": tp * 1e3, "iters": ip.iters, "rel_res": ip.rel_res}
+            sp.close()
+            log(f"[bench] mixed without stage, factors {pv}: {tp * 1e3:.3f} ms/solve, "
+                f"{ip.iters} iterations")
         # every placement of the stage, timed the same way; the fastest is the headline
         placements = {}
         s.learned_load(blob, 1)
@@ -614,7 +656,7 @@ def main():
     bytes_step, ms_step, ms_step_c = timed(2)
     bytes_outer, ms_outer, ms_outer_c = timed(1)
     ach = gbs(bytes_step, ms_step)
-    gname = "bf16" if args.prec == "bf16" else "float"
+    gname = {"bf16": "bf16", "f32": "float", "col": "column records"}[args.prec]
     kernel_tag = f"cheb2d_{wl.name}_{args.prec}"
     roof = {"bound": "hbm",
             "kernel": f"k_cheb2d<P={wl.P},float,{gname}>: fused operator + Chebyshev step "
@@ -640,6 +682,10 @@ def main():
                                     "frac": gbs(bytes_outer, ms_outer) / HBM_PEAK_GBS,
                                     "cache_resident_achieved": gbs(bytes_outer, ms_outer_c)},
             "whole_solve": whole}
+    roof["copy_same_bytes"] = copy_reference(bytes_step)
+    log(f"[bench] a plain device copy moving the fused step's bytes: "
+        f"{roof['copy_same_bytes']['avg_launch_ms'] * 1e3:.2f} us HBM-resident "
+        f"({100 * roof['copy_same_bytes']['frac']:.1f}% of HBM peak)")
     log(f"[bench] fused step {ms_step * 1e3:.2f} us HBM-resident ({ach:.0f} GB/s, "
         f"{100 * ach / HBM_PEAK_GBS:.1f}% of HBM peak), {ms_step_c * 1e3:.2f} us cache-resident; "
         f"operator {ms_op * 1e3:.2f} us ({100 * gbs(bytes_op, ms_op) / HBM_PEAK_GBS:.1f}%); "
@@ -737,11 +783,15 @@ def main():
     out = {"metric": METRIC, "value": wl.n_global / t / 1e9, "unit": "GDOF/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": t * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": "fp32 inner (bf16 factors and network operands) / fp64 outer",
+           "dtype": {"bf16": "fp32 inner (bf16 factors and network operands) / fp64 outer",
+                     "f32": "fp32 inner (fp32 factors, bf16 network operands) / fp64 outer",
+                     "col": "fp32 inner (factors formed from fp64 column records, bf16 network "
+                            "operands) / fp64 outer"}[args.prec],
            "data": "synthetic", "config": describe(wl, args.prec, use_learned, mode),
            "solves_per_s": 1.0 / t, "iters": info.iters, "rel_res": info.rel_res,
            "learned_skips": info.learned_skips, "oracle_rel_res": res_check,
-           "mixed_without_stage": plain_mixed, "plain_fp64": plain,
+           "mixed_without_stage": plain_mixed, "mixed_factor_storage": factor_rows,
+           "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
            "learned_placements": placements, "learned_break_even": breakeven,
            "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,

@@ -45,8 +45,13 @@ typedef enum {
   SEM_ERR_STATE = 6          /* call not valid in the context's current state            */
 } sem_status;
 
-/* inner (V-cycle) precision */
-enum { SEM_F64 = 0, SEM_F32 = 1, SEM_F32_GBF16 = 2 };
+/* inner (V-cycle) precision.  SEM_F64 and SEM_F32_GCOL: on 2D levels with equal orders the
+ * operator forms its geometric factors in FP64 registers from four values per element column
+ * and horizontal node (d, h_x, d_x and the weights, the quantities of Sec. 2.2's sigma
+ * derivatives) instead of reading stored factors; SEM_F32 / SEM_F32_GBF16 store the factors in
+ * FP32 / BF16 (round to nearest even).  SEM_F32_GCOL is built for 2D meshes; its levels with two
+ * orders store FP32 factors. */
+enum { SEM_F64 = 0, SEM_F32 = 1, SEM_F32_GBF16 = 2, SEM_F32_GCOL = 3 };
 /* smoother on every level above the coarsest.  SEM_SMOOTH_SCHWARZ: the additive Schwarz
  * method of Sec. 5.3 with element blocks, nu_pre / nu_post sweeps of
  * x += W sum_i R_i^T (R_i A R_i^T)^{-1} R_i (b - A x), W = (sum_i R_i^T R_i)^{-1}; 2D meshes with
@@ -73,7 +78,7 @@ typedef struct {
                                   2D (ne[0] P + 1); 3D (ne[0] P + 1) x (ne[1] P + 1), y fastest */
   const double *eta;           /* host: free-surface elevation, same layout as h            */
   unsigned dirichlet_faces;    /* SEM_FACE_TOP (default) or 0 = pure Neumann (apply only)   */
-  int inner_prec;              /* SEM_F64 | SEM_F32 | SEM_F32_GBF16                         */
+  int inner_prec;              /* SEM_F64 | SEM_F32 | SEM_F32_GBF16 | SEM_F32_GCOL          */
   int smoother;                /* SEM_SMOOTH_*                                               */
   int nu_pre, nu_post;         /* Jacobi and Schwarz sweeps                                 */
   int cheb_degree;             /* Chebyshev degree (pre and post)                           */

@@ -7,7 +7,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "libsem.so")
 
-SEM_F64, SEM_F32, SEM_F32_GBF16 = 0, 1, 2
+SEM_F64, SEM_F32, SEM_F32_GBF16, SEM_F32_GCOL = 0, 1, 2, 3
 SEM_SMOOTH_JACOBI, SEM_SMOOTH_CHEBYSHEV, SEM_SMOOTH_SCHWARZ = 0, 1, 2
 SEM_OUTER_FPCG, SEM_OUTER_PDC, SEM_OUTER_GMRES = 0, 1, 2
 SEM_FACE_TOP = 1
@@ -421,7 +421,7 @@ def blob_unpack(blob):
 
 
 # ---- convenience owner of one context -------------------------------------------------------
-_PREC = {"f64": SEM_F64, "f32": SEM_F32, "bf16": SEM_F32_GBF16}
+_PREC = {"f64": SEM_F64, "f32": SEM_F32, "bf16": SEM_F32_GBF16, "col": SEM_F32_GCOL}
 
 
 class Solver:

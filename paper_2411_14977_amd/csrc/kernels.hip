@@ -34,6 +34,10 @@ inline double vsz(bool dbl) { return dbl ? 8.0 : 4.0; }
 inline double gsz(GType gt) { return gt == G_F64 ? 8.0 : (gt == G_F32 ? 4.0 : 2.0); }
 inline double nodes2(int P, int Nx, int Nz) { return (double)(Nx * P + 1) * (double)(Nz * P + 1); }
 inline double local2(int P, int Nx, int Nz) { return (double)Nx * Nz * (P + 1) * (P + 1); }
+// bytes of one pass over a 2D level's factors: stored (three per local node) or column records
+inline double gbytes2(GType gt, int P, int Nx, int Nz) {
+  return gt == G_COL64 ? 8.0 * COLGEO_N * Nx * (P + 1) : 3 * gsz(gt) * local2(P, Nx, Nz);
+}
 }  // namespace
 void acct_enable(bool on) {
   g_acct_on = on;
@@ -231,9 +235,48 @@ GLayout g2d_layout(int P, int Nz, size_t tgsize) {
   return L;
 }
 
+// G_COL64: the factors of thread t = ez NP + i (vertical line i of element ez) formed from the
+// column record of (ex, i), {c0 = w_i d dsig/dx, c3 = w_i dx/(dsig d), h_x, d_x}, and the
+// compile-time GLL nodes and weights: with sigma_j = (ez + (r_j + 1)/2)/Nz and
+// a = h_x - sigma_j d_x (= d sigma_x), G_rr = w_j c0, G_rs = w_i w_j a, G_ss = w_j c3 (a^2 + 1)
+// (the same products as the stored factors' w_i w_j |J| J^-1 J^-T of the sigma mapping)
+struct ColGeo64 {
+  double v;
+};
+template <int P, typename T>
+__device__ __forceinline__ void colgeo_g2d(const double* __restrict__ CG, int ex, int Nz, int t,
+                                           T (&g)[3][P + 1]) {
+  // the record is read in FP64 and the factors formed in the kernel's precision T: with
+  // sigma_j = (ez + hr_j)/Nz, a_j = h_x - sigma_j d_x = A - hr_j B (A = h_x - (ez/Nz) d_x,
+  // B = d_x / Nz), three multiply-adds and four multiplies per node
+  constexpr int NP = P + 1;
+  const int i = t % NP, ez = t / NP;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* c = reinterpret_cast<const d2*>(CG + ((size_t)ex * NP + i) * COLGEO_N);
+  const d2 c03 = c[0], hd = c[1];
+  T wi = 0;
+  gllc::sfor<NP>([&](auto kc) {
+    constexpr int k = decltype(kc)::value;
+    if (i == k) wi = (T)gllc::tab<P>.w[k];
+  });
+  const double inz = 1.0 / Nz;
+  const T c0 = (T)c03[0], c3 = (T)c03[1];
+  const T A = (T)fma(-(double)ez * inz, hd[1], hd[0]);
+  const T Bv = (T)(hd[1] * inz);
+  gllc::sfor<NP>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    constexpr T wj = (T)gllc::tab<P>.w[j];
+    constexpr T hr = (T)(0.5 * (gllc::tab<P>.x[j] + 1.0));
+    const T a = fma(-hr, Bv, A);
+    g[0][j] = wj * c0;
+    g[1][j] = (wi * wj) * a;
+    g[2][j] = (wj * c3) * fma(a, a, (T)1);
+  });
+}
+
 // this thread's 3 (P+1) factors (f, j) of element column ex, with 16-byte loads
 template <int P, typename T, typename TG>
-__device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int nthr, int t,
+__device__ __forceinline__ void load_g2d_stored(const TG* __restrict__ G, int ex, int nthr, int t,
                                          T (&g)[3][P + 1]) {
   using Ly = G2dLayout<P, TG>;
   constexpr int NP = P + 1, W = Ly::W, NC = Ly::NC, REM = Ly::REM, Kp = Ly::Kp;
@@ -261,37 +304,15 @@ __device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int n
     for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(&raw[f * NP + j]);
 }
 
-// G_COL64: the factors of thread t = ez NP + i (vertical line i of element ez) formed from the
-// column record of (ex, i), {c0 = w_i d dsig/dx, c3 = w_i dx/(dsig d), h_x, d_x}, and the
-// compile-time GLL nodes and weights: with sigma_j = (ez + (r_j + 1)/2)/Nz and
-// a = h_x - sigma_j d_x (= d sigma_x), G_rr = w_j c0, G_rs = w_i w_j a, G_ss = w_j c3 (a^2 + 1)
-struct ColGeo64 {
-  double v;
-};
-template <int P, typename T>
-__device__ __forceinline__ void colgeo_g2d(const double* __restrict__ CG, int ex, int Nz, int t,
-                                           T (&g)[3][P + 1]) {
-  constexpr int NP = P + 1;
-  const int i = t % NP, ez = t / NP;
-  typedef double d2 __attribute__((ext_vector_type(2)));
-  const d2* c = reinterpret_cast<const d2*>(CG + ((size_t)ex * NP + i) * COLGEO_N);
-  const d2 c03 = c[0], hd = c[1];
-  double wi = 0.0;
-  gllc::sfor<NP>([&](auto kc) {
-    constexpr int k = decltype(kc)::value;
-    if (i == k) wi = gllc::tab<P>.w[k];
-  });
-  const double inz = 1.0 / Nz;
-  gllc::sfor<NP>([&](auto jc) {
-    constexpr int j = decltype(jc)::value;
-    constexpr double wj = gllc::tab<P>.w[j];
-    constexpr double hr = 0.5 * (gllc::tab<P>.x[j] + 1.0);
-    const double sig = (ez + hr) * inz;
-    const double a = fma(-sig, hd[1], hd[0]);
-    g[0][j] = (T)(wj * c03[0]);
-    g[1][j] = (T)((wi * wj) * a);
-    g[2][j] = (T)(wj * c03[1] * fma(a, a, 1.0));
-  });
+// this thread's factors from the level's factor data: stored layout or column records
+template <int P, typename T, typename TG>
+__device__ __forceinline__ void load_g2d(const TG* __restrict__ G, int ex, int nthr, int t,
+                                         T (&g)[3][P + 1]) {
+  if constexpr (std::is_same<TG, ColGeo64>::value) {
+    colgeo_g2d<P, T>(reinterpret_cast<const double*>(G), ex, nthr / (P + 1), t, g);
+  } else {
+    load_g2d_stored<P, T, TG>(G, ex, nthr, t, g);
+  }
 }
 
 // The operator on one element column (slot) of a workgroup.  Thread t = ez * NP + q of the slot
@@ -316,11 +337,7 @@ __device__ __forceinline__ void column_apply(Ldx&& ldx, const TG* __restrict__ G
   // every global load of the block (the caller's through pre()) is issued before the first LDS
   // store
   T g[3][P + 1];
-  if constexpr (std::is_same<TG, ColGeo64>::value) {
-    if (act) colgeo_g2d<P, T>(reinterpret_cast<const double*>(G), ex, Nz, t, g);
-  } else {
-    if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
-  }
+  if (act) load_g2d<P, T, TG>(G, ex, nthr, t, g);
   column_apply_g<P, T>(g, ldx, t, act, Nz, nzn, nzp, masked, base, xin, pre);
 }
 
@@ -701,6 +718,11 @@ template <int P>
 static hipError_t cheb2d_p(bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
                            const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
                            double cr, int store_d, int cpb, hipStream_t st) {
+  if (gt == G_COL64)
+    return dbl ? launch_cheb2d<P, double, ColGeo64>(xi, xo, d, b, dinv, G, Nx, Nz, masked, cd,
+                                                    cr, store_d, cpb, st)
+               : launch_cheb2d<P, float, ColGeo64>(xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr,
+                                                   store_d, cpb, st);
   if (dbl)
     return launch_cheb2d<P, double, double>(xi, xo, d, b, dinv, G, Nx, Nz, masked, cd, cr,
                                             store_d, cpb, st);
@@ -714,7 +736,7 @@ static hipError_t cheb2d_p(bool dbl, GType gt, const void* xi, void* xo, void* d
 hipError_t cheb2d(int P, bool dbl, GType gt, const void* xi, void* xo, void* d, const void* b,
                   const void* dinv, const void* G, int Nx, int Nz, int masked, double cd,
                   double cr, int store_d, hipStream_t st) {
-  acct_add(vsz(dbl) * nodes2(P, Nx, Nz) * (4 + (cd != 0.0) + (store_d ? 1 : 0)) + 3 * gsz(gt) * local2(P, Nx, Nz));
+  acct_add(vsz(dbl) * nodes2(P, Nx, Nz) * (4 + (cd != 0.0) + (store_d ? 1 : 0)) + gbytes2(gt, P, Nx, Nz));
   const int cpb = cheb2d_cpb(P, Nx, Nz, dbl);
   if (xi == xo) return hipErrorInvalidValue;
   switch (P) {
@@ -841,6 +863,9 @@ template <int P>
 static hipError_t stagecq2d_p(bool dbl, GType gt, const float* CE, void* c, void* q,
                               const void* G, int Nx, int Nz, int masked, double* dotp, int cpb,
                               hipStream_t st) {
+  if (gt == G_COL64)
+    return dbl ? launch_stagecq2d<P, double, ColGeo64>(CE, c, q, G, Nx, Nz, masked, dotp, cpb, st)
+               : launch_stagecq2d<P, float, ColGeo64>(CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
   if (dbl) return launch_stagecq2d<P, double, double>(CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
   if (gt == G_BF16)
     return launch_stagecq2d<P, float, uint16_t>(CE, c, q, G, Nx, Nz, masked, dotp, cpb, st);
@@ -854,7 +879,7 @@ int cheb2d_blocks(int P, int Nx, int Nz, bool dbl) {
 
 hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* q, const void* G,
                      int Nx, int Nz, int masked, double* dotp, hipStream_t st) {
-  acct_add(4.0 * local2(P, Nx, Nz) + 2 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz));
+  acct_add(4.0 * local2(P, Nx, Nz) + 2 * vsz(dbl) * nodes2(P, Nx, Nz) + gbytes2(gt, P, Nx, Nz));
   const int cpb = P <= 8 ? cheb2d_cpb(P, Nx, Nz, dbl) : 0;
   if (cpb <= 0) return hipErrorInvalidValue;
   switch (P) {
@@ -1003,7 +1028,7 @@ __global__ __launch_bounds__(1024) void k_fpcg2d(const double* __restrict__ z,
   // thread's nodes and the three partial-sum sets (each summed in the order sum_partials uses)
   double g[3][NP], zr[NP], pr[NP];
   if constexpr (COL) {
-    if (valid) colgeo_g2d<P, double>(G, ex, Nz, t, g);
+    if (valid) load_g2d<P, double, ColGeo64>(reinterpret_cast<const ColGeo64*>(G), ex, nthr, t, g);
   } else {
     if (valid) load_g2d<P, double, double>(G, valid ? ex : 0, nthr, t, g);
   }
@@ -1214,6 +1239,11 @@ static hipError_t cheb2d_first_p(bool dbl, GType gt, void* x, void* d, void* b,
                                  const double* r64, const void* dinv, const void* G, int Nx,
                                  int Nz, int masked, double cr0, double cd, double cr,
                                  int store_d, hipStream_t st) {
+  if (gt == G_COL64)
+    return dbl ? launch_cheb2d_first<P, double, ColGeo64>(x, d, b, r64, dinv, G, Nx, Nz, masked,
+                                                          cr0, cd, cr, store_d, st)
+               : launch_cheb2d_first<P, float, ColGeo64>(x, d, b, r64, dinv, G, Nx, Nz, masked,
+                                                         cr0, cd, cr, store_d, st);
   if (dbl)
     return launch_cheb2d_first<P, double, double>(x, d, b, r64, dinv, G, Nx, Nz, masked, cr0,
                                                   cd, cr, store_d, st);
@@ -1227,7 +1257,7 @@ static hipError_t cheb2d_first_p(bool dbl, GType gt, void* x, void* d, void* b,
 hipError_t cheb2d_first(int P, bool dbl, GType gt, void* x, void* d, void* b, const double* r64,
                         const void* dinv, const void* G, int Nx, int Nz, int masked, double cr0,
                         double cd, double cr, int store_d, hipStream_t st) {
-  acct_add(nodes2(P, Nx, Nz) * ((r64 ? 8.0 + vsz(dbl) : vsz(dbl)) + vsz(dbl) * (2 + (store_d ? 1 : 0))) + 3 * gsz(gt) * local2(P, Nx, Nz));
+  acct_add(nodes2(P, Nx, Nz) * ((r64 ? 8.0 + vsz(dbl) : vsz(dbl)) + vsz(dbl) * (2 + (store_d ? 1 : 0))) + gbytes2(gt, P, Nx, Nz));
   switch (P) {
 #define SEM_CHEB_FIRST(PP)                                                                  \
   case PP:                                                                                  \
@@ -1243,6 +1273,11 @@ hipError_t cheb2d_first(int P, bool dbl, GType gt, void* x, void* d, void* b, co
 template <int P>
 static hipError_t resid2d_p(bool dbl, GType gt, const void* x, void* r, const void* b,
                             const void* G, int Nx, int Nz, int masked, int cpb, hipStream_t st) {
+  if (gt == G_COL64)
+    return dbl ? launch_cheb2d<P, double, ColGeo64, 1>(x, r, nullptr, b, nullptr, G, Nx, Nz,
+                                                       masked, 0.0, 0.0, 0, cpb, st)
+               : launch_cheb2d<P, float, ColGeo64, 1>(x, r, nullptr, b, nullptr, G, Nx, Nz,
+                                                      masked, 0.0, 0.0, 0, cpb, st);
   if (dbl)
     return launch_cheb2d<P, double, double, 1>(x, r, nullptr, b, nullptr, G, Nx, Nz, masked, 0.0,
                                                0.0, 0, cpb, st);
@@ -1260,7 +1295,7 @@ hipError_t resid2d(int P, bool dbl, GType gt, const void* x, void* r, const void
                    const void* G, int Nx, int Nz, int masked, void* y, void* S, hipStream_t st) {
   if (x == r) return hipErrorInvalidValue;
   const int cpb = P <= 8 ? cheb2d_cpb(P, Nx, Nz, dbl) : 0;
-  acct_add(cpb > 0 ? 3 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz)
+  acct_add(cpb > 0 ? 3 * vsz(dbl) * nodes2(P, Nx, Nz) + gbytes2(gt, P, Nx, Nz)
                    : vsz(dbl) * nodes2(P, Nx, Nz));
   if (cpb > 0) {
     switch (P) {
@@ -1311,10 +1346,9 @@ static hipError_t launch_apply2d(const void* x, void* y, void* S, const void* G,
 template <int P>
 static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                             int Nx, int Nz, int masked, hipStream_t st) {
-  if (gt == G_COL64) {
-    if (!dbl) return hipErrorInvalidValue;
-    return launch_apply2d<P, double, ColGeo64>(x, y, S, G, Nx, Nz, masked, nullptr, st);
-  }
+  if (gt == G_COL64)
+    return dbl ? launch_apply2d<P, double, ColGeo64>(x, y, S, G, Nx, Nz, masked, nullptr, st)
+               : launch_apply2d<P, float, ColGeo64>(x, y, S, G, Nx, Nz, masked, nullptr, st);
   if (dbl) return launch_apply2d<P, double, double>(x, y, S, G, Nx, Nz, masked, nullptr, st);
   if (gt == G_BF16)
     return launch_apply2d<P, float, uint16_t>(x, y, S, G, Nx, Nz, masked, nullptr, st);
@@ -1324,7 +1358,7 @@ static hipError_t apply2d_p(bool dbl, GType gt, const void* x, void* y, void* S,
 hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                    int Nx, int Nz, int masked, hipStream_t st) {
   acct_add(2 * vsz(dbl) * nodes2(P, Nx, Nz) +
-           (gt == G_COL64 ? 8.0 * COLGEO_N * Nx * (P + 1) : 3 * gsz(gt) * local2(P, Nx, Nz)));
+           gbytes2(gt, P, Nx, Nz));
   switch (P) {
     case 1: return apply2d_p<1>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
     case 2: return apply2d_p<2>(dbl, gt, x, y, S, G, Nx, Nz, masked, st);
@@ -1346,6 +1380,9 @@ template <int P>
 static hipError_t apply2d_dot_p(bool dbl, GType gt, const void* x, void* y, void* S,
                                 const void* G, int Nx, int Nz, int masked, double* dotp,
                                 hipStream_t st) {
+  if (gt == G_COL64)
+    return dbl ? launch_apply2d<P, double, ColGeo64, true>(x, y, S, G, Nx, Nz, masked, dotp, st)
+               : launch_apply2d<P, float, ColGeo64, true>(x, y, S, G, Nx, Nz, masked, dotp, st);
   if (dbl) return launch_apply2d<P, double, double, true>(x, y, S, G, Nx, Nz, masked, dotp, st);
   if (gt == G_BF16)
     return launch_apply2d<P, float, uint16_t, true>(x, y, S, G, Nx, Nz, masked, dotp, st);
@@ -1354,7 +1391,7 @@ static hipError_t apply2d_dot_p(bool dbl, GType gt, const void* x, void* y, void
 
 hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                        int Nx, int Nz, int masked, double* dotp, hipStream_t st) {
-  acct_add(2 * vsz(dbl) * nodes2(P, Nx, Nz) + 3 * gsz(gt) * local2(P, Nx, Nz));
+  acct_add(2 * vsz(dbl) * nodes2(P, Nx, Nz) + gbytes2(gt, P, Nx, Nz));
   switch (P) {
     case 1: return apply2d_dot_p<1>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
     case 2: return apply2d_dot_p<2>(dbl, gt, x, y, S, G, Nx, Nz, masked, dotp, st);
@@ -2675,6 +2712,16 @@ static hipError_t coarse2d_ty(const CoarsePlan& pl, bool dbl, GType gt, bool dbl
                               void* xo, const void* b, const void* dinv, const void* G,
                               const void* ec, void* rc, const double* J, int Nx, int Nz,
                               int masked, const CoarseSeq& sq, hipStream_t st) {
+  if (gt == G_COL64) {
+    if (dbl)
+      return coarse2d_t<P, PC, double, ColGeo64, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J,
+                                                              Nx, Nz, masked, sq, st);
+    if (dbl_c)
+      return coarse2d_t<P, PC, float, ColGeo64, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J,
+                                                             Nx, Nz, masked, sq, st);
+    return coarse2d_t<P, PC, float, ColGeo64, float, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx,
+                                                          Nz, masked, sq, st);
+  }
   if (dbl)
     return coarse2d_t<P, PC, double, double, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx,
                                                           Nz, masked, sq, st);
@@ -2702,7 +2749,7 @@ hipError_t coarse2d(bool pre, const CoarsePlan& pl, int P, int PC, bool dbl, GTy
                     const void* ec, void* rc, const double* J, int Nx, int Nz, int masked,
                     const CoarseSeq& sq, hipStream_t st) {
   acct_add(vsz(dbl) * nodes2(P, Nx, Nz) * (pre ? 3 : 4) + vsz(dbl_c) * nodes2(PC, Nx, Nz) +
-           3 * gsz(gt) * local2(P, Nx, Nz));
+           gbytes2(gt, P, Nx, Nz));
   if (pl.W < 1 || sq.ns < 1 || sq.ns > CO_MAXS) return hipErrorInvalidValue;
 #define SEM_CO(a, c)                                                                            \
   if (P == a && PC == c)                                                                        \

@@ -182,6 +182,13 @@ T* upload(Ctx* c, const std::vector<T>& h) {
 
 size_t esz(bool dbl) { return dbl ? 8 : 4; }
 
+template <typename T>
+void* put_vec(Ctx* c, const std::vector<T>& h, void* dst) {
+  if (!dst) return upload(c, h);
+  HK(hipMemcpy(dst, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return dst;
+}
+
 // natural [f][e][i*NP+j] -> device [ex][f][j][ez*NP+i]
 template <typename TG, typename Conv>
 std::vector<TG> permute_G2d(const semh::LevelGeom& L, const std::vector<double>& G, Conv conv) {
@@ -246,6 +253,31 @@ std::vector<double> column_records(const semh::LevelGeom& L) {
       r[3] = 2.0 / dx * b;
     }
   return out;
+}
+
+// factor data of a 2D level: column records where its operator forms the factors itself
+// (FP64 levels and SEM_F32_GCOL, equal orders), else stored factors in the inner precision
+semk::GType level_gtype(const Ctx* c, const DLevel& L) {
+  if (L.dbl) return L.rect ? semk::G_F64 : semk::G_COL64;
+  if (c->prec == SEM_F32_GBF16) return semk::G_BF16;
+  if (c->prec == SEM_F32_GCOL && !L.rect) return semk::G_COL64;
+  return semk::G_F32;
+}
+
+// the level's factor data for geometry geo, uploaded into dst (null: a new allocation)
+void* put_factors(Ctx* c, const DLevel& L, const semh::LevelGeom& geo, void* dst);
+
+void* put_factors(Ctx* c, const DLevel& L, const semh::LevelGeom& geo, void* dst) {
+  switch (L.gt) {
+    case semk::G_COL64: return put_vec(c, column_records(geo), dst);
+    case semk::G_F64: return put_vec(c, layout_G2<double>(geo, geo.G, [](double v) { return v; }), dst);
+    case semk::G_F32:
+      return put_vec(c, layout_G2<float>(geo, geo.G, [](double v) { return (float)v; }), dst);
+    default:
+      return put_vec(c, layout_G2<uint16_t>(geo, geo.G,
+                                            [](double v) { return semh::bf16_bits((float)v); }),
+                     dst);
+  }
 }
 
 // run f(lo, hi) over [0, n) on up to 16 host threads (set-up work only)
@@ -1337,7 +1369,9 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   if (d->len[0] <= 0) throw ArgFail{"len[0] must be positive"};
   c->masked = (d->dirichlet_faces & SEM_FACE_TOP) ? 1 : 0;
   c->prec = d->inner_prec;
-  if (c->prec < SEM_F64 || c->prec > SEM_F32_GBF16) throw ArgFail{"bad inner_prec"};
+  if (c->prec < SEM_F64 || c->prec > SEM_F32_GCOL) throw ArgFail{"bad inner_prec"};
+  if (c->prec == SEM_F32_GCOL && d->dim != 2)
+    throw ArgFail{"SEM_F32_GCOL (factors from column records) is built for 2D meshes"};
   if (d->smoother != SEM_SMOOTH_JACOBI && d->smoother != SEM_SMOOTH_CHEBYSHEV &&
       d->smoother != SEM_SMOOTH_SCHWARZ)
     throw ArgFail{"bad smoother"};
@@ -1470,21 +1504,14 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     L.N = (unsigned)L.geo.N;
     const bool coarsest = (l == nl - 1);
     L.dbl = coarsest || c->prec == SEM_F64;
-    L.gt = L.dbl ? semk::G_F64 : (c->prec == SEM_F32_GBF16 ? semk::G_BF16 : semk::G_F32);
+    L.gt = level_gtype(c, L);
     // factors in storage precision; the diagonal is built from the same rounded values
     std::vector<double> Gr = L.geo.G;
     if (L.gt == semk::G_F32)
       for (auto& v : Gr) v = (double)(float)v;
     else if (L.gt == semk::G_BF16)
       for (auto& v : Gr) v = semh::bf16_round(v);
-    if (L.gt == semk::G_F64) {
-      L.G = upload(c, layout_G2<double>(L.geo, L.geo.G, [](double v) { return v; }));
-    } else if (L.gt == semk::G_F32) {
-      L.G = upload(c, layout_G2<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
-    } else {
-      L.G = upload(c, layout_G2<uint16_t>(L.geo, L.geo.G,
-                                          [](double v) { return semh::bf16_bits((float)v); }));
-    }
+    L.G = put_factors(c, L, L.geo, nullptr);
     std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
     std::vector<double> dinv(diag.size());
     for (size_t g = 0; g < diag.size(); ++g) dinv[g] = 1.0 / diag[g];
@@ -2637,9 +2664,7 @@ static void rebuild_levels(Ctx* c) {
     else if (L.gt == semk::G_BF16)
       for (auto& v : Gr) v = semh::bf16_round(v);
     if (c->dim == 2) {
-      if (L.gt == semk::G_F64) copy_to(c, L.G, layout_G2<double>(L.geo, L.geo.G, [](double v) { return v; }));
-      else if (L.gt == semk::G_F32) copy_to(c, L.G, layout_G2<float>(L.geo, L.geo.G, [](double v) { return (float)v; }));
-      else copy_to(c, L.G, layout_G2<uint16_t>(L.geo, L.geo.G, [](double v) { return semh::bf16_bits((float)v); }));
+      put_factors(c, L, L.geo, L.G);
     } else {
       if (L.gt == semk::G_F64) copy_to(c, L.G, permute_G3d<double>(L.geo, [](double v) { return v; }));
       else if (L.gt == semk::G_F32) copy_to(c, L.G, permute_G3d<float>(L.geo, [](double v) { return (float)v; }));
@@ -3109,7 +3134,8 @@ sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int kind, double* b
                                   : (double)L.geo.E * std::pow((double)L.NP, 3);
   const double nvec = kind == 2 ? 6.0 : 2.0;  // step: x, b, dinv, d read; x, d written
   *bytes = nvec * sv * L.N + L.geo.nfields * sg * nloc;
-  if (kind == 1 && c->CG64)  // the outer operator forms its factors from column records
+  // operators that form their factors from column records read those instead
+  if ((kind == 1 && c->CG64) || (kind != 1 && L.gt == semk::G_COL64))
     *bytes = nvec * sv * L.N + 8.0 * semk::COLGEO_N * (double)L.Nx * L.NP;
   return SEM_OK;
 }

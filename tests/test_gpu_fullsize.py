@@ -23,7 +23,7 @@ if not torch.cuda.is_available():  # pragma: no cover
 from paper_2411_14977_amd import cases  # noqa: E402
 
 SIZES = {"c4": W.c4(0), "c3": W.c3()}
-BARS = {"f64": 1e-12, "f32": 2e-6, "bf16": 1e-2}
+BARS = {"f64": 1e-12, "f32": 2e-6, "bf16": 1e-2, "col": 2e-6}
 
 
 def T(a):
@@ -40,7 +40,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("name", list(SIZES))
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "col"])
 def test_operator_fullsize_all_levels(name, prec):
     wl = SIZES[name]
     print(f"[gpu] full-size operator {name} {prec}", flush=True)

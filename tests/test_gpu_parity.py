@@ -83,7 +83,7 @@ def test_operator_fp64_all_levels(name):
     s.close()
 
 
-@pytest.mark.parametrize("prec,bar", [("f32", 2e-6), ("bf16", 1e-2)])
+@pytest.mark.parametrize("prec,bar", [("f32", 2e-6), ("bf16", 1e-2), ("col", 2e-6)])
 def test_operator_inner_precision(prec, bar):
     H_ = oracle_h("tank8")
     s = lib_solver("tank8", prec=prec)
@@ -246,7 +246,7 @@ def test_pdc_outer_loop():
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "bf16", "col"])
 def test_mixed_precision_solve(prec):
     wl = CASES["c2"]
     H_ = oracle_h("c2")
@@ -365,7 +365,7 @@ def test_vcycle_schwarz(name):
     s.close()
 
 
-@pytest.mark.parametrize("prec,bar", [("f64", 1e-9), ("f32", 1e-8), ("bf16", 1e-8)])
+@pytest.mark.parametrize("prec,bar", [("f64", 1e-9), ("f32", 1e-8), ("bf16", 1e-8), ("col", 1e-8)])
 @pytest.mark.parametrize("name", ["tank8", "c2"])
 def test_solve_schwarz_matches_direct(name, prec, bar):
     wl = CASES[name]
@@ -388,7 +388,7 @@ def test_schwarz_rejects_3d():
 
 
 @pytest.mark.parametrize("name", ["tank8", "c2", "ragged", "wide3"])
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "col"])
 def test_vcycle_one_kernel_levels(name, prec, monkeypatch):
     """The one-kernel coarse-level smoothing and the three-launch coarse solve against the
     per-step kernels and the per-level reduction (switched off by environment variables read at

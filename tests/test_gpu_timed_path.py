@@ -38,7 +38,8 @@ from paper_2411_14977_amd import cases  # noqa: E402
 
 WIDE = W.tank(1024, 2, 8, Lx=25.6, name="wide")
 TANK8 = W.tank(16, 4, 8, Lx=1.6, name="tank8")
-GSTORE = {"f64": None, "f32": "f32", "bf16": "bf16"}
+# "col": FP32 factors formed in registers from FP64 column records (rounded like stored FP32)
+GSTORE = {"f64": None, "f32": "f32", "bf16": "bf16", "col": "f32"}
 
 _hier = {}
 
@@ -80,7 +81,7 @@ def residual(Hh, seed, level=0):
     return r
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "col"])
 def test_wide_tank_selects_the_benchmark_launch_shape(prec):
     s = cases.make_solver(WIDE, prec=prec)
     cpb, _ = B.sem_launch_shape(s.ctx, 0)
@@ -116,7 +117,7 @@ def test_wide_smoother_fp64(smoother):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "col"])
 def test_fused_step_is_operator_plus_update(prec, monkeypatch):
     """The fused smoother step and its two-step entry form give the same bits as the operator
     kernel followed by the element-wise update."""
@@ -144,7 +145,8 @@ def test_fused_step_is_operator_plus_update(prec, monkeypatch):
         assert np.array_equal(a, b), (prec, k, rel(a, b))
 
 
-@pytest.mark.parametrize("prec,bar", [("f64", 1e-12), ("f32", 2e-5), ("bf16", 2e-5)])
+@pytest.mark.parametrize("prec,bar", [("f64", 1e-12), ("f32", 2e-5), ("bf16", 2e-5),
+                                      ("col", 2e-5)])
 def test_wide_vcycle(prec, bar):
     print(f"[gpu] wide vcycle {prec}", flush=True)
     Hh = hier(WIDE, prec)
@@ -202,7 +204,7 @@ _scales = {}
 
 
 @pytest.mark.parametrize("wl", [TANK8, WIDE], ids=["tank8", "wide"])
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "col"])
 @pytest.mark.parametrize("mode", [1, 2, 3])
 def test_learned_vcycle_matches_oracle(mode, prec, wl):
     print(f"[gpu] learned vcycle {wl.name} {prec} mode {mode}", flush=True)
