@@ -255,8 +255,9 @@ def c5_series(steps, log_every=5, blob3=None, mode3=1):
     """3D time series (64 x 64 x 8 hexahedra, P = 6, 7.26M nodes): each step moves the free
     surface (sem_mesh_update_surface, preconditioner frozen at t = 0), re-evaluates the drifting
     source at the moved nodes and solves to 1e-10 warm-started from the previous pressure.
-    Mixed precision (FP32 inner, BF16 factors), the same with the learned stage (when a network
-    is given) and plain FP64; solve time timed per step."""
+    Mixed precision (FP32 inner, BF16 factors; FP32 inner with factors formed from column
+    records), the same with the learned stage (when a network is given) and plain FP64; solve
+    time timed per step."""
     import numpy as np
     import torch
 
@@ -271,7 +272,7 @@ def c5_series(steps, log_every=5, blob3=None, mode3=1):
     out = {"workload": "c5: 3D sigma-mapped tank 64x64x8 hexahedra, P=6, levels 6-3-1 then "
                        "h-levels 32x32, 16x16, 8x8 at P=1 (dense exact), dt = 0.01 s",
            "n_global": wl.n_global, "steps": steps}
-    runs = [("bf16", "bf16", 0)]
+    runs = [("bf16", "bf16", 0), ("col", "col", 0)]
     if blob3 is not None:
         runs.append(("bf16_learned", "bf16", mode3))
     runs.append(("f64", "f64", 0))
@@ -762,8 +763,9 @@ def main():
         c5 = c5_series(args.c5_steps, blob3=blob3)
         c5["training"] = rec3
         msg = (f"[bench] c5 series: mixed {c5['bf16']['ms_per_solve']:.1f} ms "
-               f"({c5['bf16']['iters_mean']:.1f} it), fp64 {c5['f64']['ms_per_solve']:.1f} ms "
-               f"({c5['f64']['iters_mean']:.1f} it)")
+               f"({c5['bf16']['iters_mean']:.1f} it), mixed with column-record factors "
+               f"{c5['col']['ms_per_solve']:.1f} ms ({c5['col']['iters_mean']:.1f} it), "
+               f"fp64 {c5['f64']['ms_per_solve']:.1f} ms ({c5['f64']['iters_mean']:.1f} it)")
         if blob3 is not None:
             msg += (f", mixed + learned {c5['bf16_learned']['ms_per_solve']:.1f} ms "
                     f"({c5['bf16_learned']['iters_mean']:.1f} it)")

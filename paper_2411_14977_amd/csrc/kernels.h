@@ -16,7 +16,11 @@ constexpr int RED_THREADS = 256;
 // (d = h + eta): G_rr = w_j c0, G_rs = w_i w_j (h_x - sigma d_x), G_ss = w_j c3 ((h_x -
 // sigma d_x)^2 + 1), which are the sigma-mapped factors of the stored layouts
 enum GType { G_F64 = 0, G_F32 = 1, G_BF16 = 2, G_COL64 = 3 };
-constexpr int COLGEO_N = 4;  // values per column node of G_COL64
+constexpr int COLGEO_N = 4;  // values per column node of G_COL64 (2D)
+// 3D G_COL64: per element column (ex, ey) and horizontal node (i, m), eight FP64 values
+// {W K d r_x^2, W K s_s^2 / d, h_x, d_x, h_y, d_y, W K r_x s_s, dx/dy} (W = w_i w_m,
+// K = dx dy dsig / 8, r_x = 2/dx, s_s = 2/dsig), [c][i][m] with c = ex Ny + ey
+constexpr int COLGEO3_N = 8;
 
 // ---- operator --------------------------------------------------------------------------
 // 2D: one workgroup per element column; y gets lines 0..P-1 of each column (and line P of
@@ -124,6 +128,9 @@ hipError_t dense_gemv(const double* Ainv, const double* b, double* x, int n, hip
 // column samples hf, ef ((Nx P + 1) x (Ny P + 1), y fastest); r, w: GLL nodes and weights
 hipError_t geom3d(int P, const double* hf, const double* ef, const double* r, const double* w,
                   double* G, int Nx, int Ny, int Nz, double dx, double dy, hipStream_t st);
+// the G_COL64 records of the 3D fine level from its column samples (layout above)
+hipError_t colrec3d(int P, const double* hf, const double* ef, double* CG, int Nx, int Ny, int Nz,
+                    double dx, double dy, hipStream_t st);
 hipError_t mass3d(const double* hf, const double* ef, const double* Wx, const double* Wy,
                   const double* Wz, double* mass, unsigned nyn, unsigned nzn, size_t N,
                   double scale, hipStream_t st);

@@ -1428,10 +1428,42 @@ static size_t apply3d_slot(int P, int Nz, bool dbl) {
 
 size_t apply3d_smem(int P, int Nz, bool dbl) { return apply3d_slot(P, Nz, dbl) * (dbl ? 8 : 4); }
 
+// G_COL64 in 3D: the factors of thread t = (ez NP + i) NP + m (vertical line (i, m) of element
+// ez) formed from the record of column c, node (i, m): {W K d r_x^2, W K s_s^2 / d, h_x, d_x,
+// h_y, d_y, W K r_x s_s, dx/dy} with W = w_i w_m, K = dx dy dsig / 8, r_x = 2/dx, s_s = 2/dsig.
+// With a_x = h_x - sigma_j d_x and a_y = h_y - sigma_j d_y (d sigma_x, d sigma_y):
+// G_rr = w_j c_rr, G_tt = w_j c_rr (dx/dy)^2, G_rs = w_j c_rs a_x, G_ts = w_j c_rs (dx/dy) a_y,
+// G_ss = w_j c_ss (a_x^2 + a_y^2 + 1): the products w_i w_m w_j |J| J^-1 J^-T of the mapping
+template <int P, typename T>
+__device__ __forceinline__ void colgeo_g3d(const double* __restrict__ CG, int c, int Nz, int t,
+                                           T (&g)[5][P + 1]) {
+  constexpr int NP = P + 1, NL = NP * NP;
+  const int ez = t / NL, ab = t - ez * NL;
+  typedef double d2 __attribute__((ext_vector_type(2)));
+  const d2* rc = reinterpret_cast<const d2*>(CG + ((size_t)c * NL + ab) * COLGEO3_N);
+  const d2 q0 = rc[0], q1 = rc[1], q2 = rc[2], q3 = rc[3];
+  const double inz = 1.0 / Nz, ezn = (double)ez * inz;
+  const T crr = (T)q0[0], css = (T)q0[1], crs = (T)q3[0], rat = (T)q3[1];
+  const T ctt = crr * rat * rat, cts = crs * rat;
+  const T Ax = (T)fma(-ezn, q1[1], q1[0]), Bx = (T)(q1[1] * inz);
+  const T Ay = (T)fma(-ezn, q2[1], q2[0]), By = (T)(q2[1] * inz);
+  gllc::sfor<NP>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    constexpr T wj = (T)gllc::tab<P>.w[j];
+    constexpr T hr = (T)(0.5 * (gllc::tab<P>.x[j] + 1.0));
+    const T ax = fma(-hr, Bx, Ax), ay = fma(-hr, By, Ay);
+    g[0][j] = wj * crr;
+    g[1][j] = wj * ctt;
+    g[2][j] = (wj * crs) * ax;
+    g[3][j] = (wj * cts) * ay;
+    g[4][j] = (wj * css) * fma(ax, ax, fma(ay, ay, (T)1));
+  });
+}
+
 // this thread's 5 (P+1) factors (f, j) of element column c (3D layout: GLayout with K = 5 (P+1))
 template <int P, typename T, typename TG>
-__device__ __forceinline__ void load_g3d(const TG* __restrict__ G, int c, int nthr, int t,
-                                         T (&g)[5][P + 1]) {
+__device__ __forceinline__ void load_g3d_stored(const TG* __restrict__ G, int c, int nthr, int t,
+                                                T (&g)[5][P + 1]) {
   constexpr int NP = P + 1, K = 5 * NP, W = 16 / (int)sizeof(TG), H = W / 2 > 0 ? W / 2 : 1;
   constexpr int Kp = (K + H - 1) / H * H, NC = Kp / W, REM = Kp - NC * W;
   typedef TG vW __attribute__((ext_vector_type(W)));
@@ -1456,6 +1488,17 @@ __device__ __forceinline__ void load_g3d(const TG* __restrict__ G, int c, int nt
   for (int f = 0; f < 5; ++f)
 #pragma unroll
     for (int j = 0; j < NP; ++j) g[f][j] = gload<T, TG>(&raw[f * NP + j]);
+}
+
+// this thread's factors from the level's factor data: stored layout or column records
+template <int P, typename T, typename TG>
+__device__ __forceinline__ void load_g3d(const TG* __restrict__ G, int c, int nthr, int t,
+                                         T (&g)[5][P + 1]) {
+  if constexpr (std::is_same<TG, ColGeo64>::value) {
+    colgeo_g3d<P, T>(reinterpret_cast<const double*>(G), c, nthr / ((P + 1) * (P + 1)), t, g);
+  } else {
+    load_g3d_stored<P, T, TG>(G, c, nthr, t, g);
+  }
 }
 
 GLayout g3d_layout(int P, int Nz, size_t tgsize) {
@@ -1724,6 +1767,11 @@ template <int P>
 static hipError_t apply3d_p(bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
                             void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked,
                             hipStream_t st, Step3 st3) {
+  if (gt == G_COL64)
+    return dbl ? launch_apply3d<P, double, ColGeo64>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st,
+                                                     st3)
+               : launch_apply3d<P, float, ColGeo64>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st,
+                                                    st3);
   if (dbl)
     return launch_apply3d<P, double, double>(x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
   if (gt == G_BF16)
@@ -1738,7 +1786,8 @@ hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, 
     const double N3 = (double)(Nx * P + 1) * (Ny * P + 1) * (Nz * P + 1);
     const double L3 = (double)Nx * Ny * Nz * (P + 1) * (P + 1) * (P + 1);
     const double nv = st3.b ? 4 + (st3.cd != 0.0) + (st3.store_d ? 1 : 0) : 2;
-    acct_add(vsz(dbl) * N3 * nv + 5 * gsz(gt) * L3);
+    acct_add(vsz(dbl) * N3 * nv +
+             (gt == G_COL64 ? 8.0 * COLGEO3_N * Nx * Ny * (P + 1) * (P + 1) : 5 * gsz(gt) * L3));
   }
   switch (P) {
     case 1: return apply3d_p<1>(dbl, gt, x, y, Sx, Sy, Sxy, G, Nx, Ny, Nz, masked, st, st3);
@@ -2055,6 +2104,65 @@ hipError_t geom3d(int P, const double* hf, const double* ef, const double* r, co
       return hipErrorInvalidValue;
   }
 #undef SEM_GEOM
+  return hipGetLastError();
+}
+
+// the G_COL64 records of the fine level (layout above) from the column samples, one thread per
+// column node (c, i, m); slopes by spectral differentiation within the element as in k_geom3d
+template <int P>
+__global__ void k_colrec3d(const double* __restrict__ hf, const double* __restrict__ ef,
+                           double* __restrict__ CG, int Nx, int Ny, int Nz, double dx, double dy) {
+  constexpr int NP = P + 1, NL = NP * NP;
+  const int nyf = Ny * P + 1;
+  const double dsig = 1.0 / Nz, rx = 2.0 / dx, ty = 2.0 / dy, ss = 2.0 / dsig;
+  const double K = dx * dy * dsig / 8.0;
+  const size_t total = (size_t)Nx * Ny * NL;
+  for (size_t k = blockIdx.x * (size_t)blockDim.x + threadIdx.x; k < total;
+       k += (size_t)gridDim.x * blockDim.x) {
+    const size_t col = k / NL;
+    const int ab = (int)(k - col * NL), i = ab / NP, m = ab - (ab / NP) * NP;
+    const int ex = (int)(col / Ny), ey = (int)(col - (size_t)ex * Ny);
+    auto H = [&](int a, int b) { return hf[(size_t)(ex * P + a) * nyf + ey * P + b]; };
+    auto Dd = [&](int a, int b) { return H(a, b) + ef[(size_t)(ex * P + a) * nyf + ey * P + b]; };
+    double hx = 0, dxd = 0, hy = 0, dyd = 0, wi = 0, wm = 0;
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const double Di = gllc::tab<P>.D[i][q], Dm = gllc::tab<P>.D[m][q];
+      hx += Di * H(q, m);
+      dxd += Di * Dd(q, m);
+      hy += Dm * H(i, q);
+      dyd += Dm * Dd(i, q);
+      if (q == i) wi = gllc::tab<P>.w[q];
+      if (q == m) wm = gllc::tab<P>.w[q];
+    }
+    const double d = Dd(i, m), W = wi * wm;
+    double* r = CG + k * COLGEO3_N;
+    r[0] = W * K * d * rx * rx;
+    r[1] = W * K * ss * ss / d;
+    r[2] = rx * hx;
+    r[3] = rx * dxd;
+    r[4] = ty * hy;
+    r[5] = ty * dyd;
+    r[6] = W * K * rx * ss;
+    r[7] = dx / dy;
+  }
+}
+
+hipError_t colrec3d(int P, const double* hf, const double* ef, double* CG, int Nx, int Ny, int Nz,
+                    double dx, double dy, hipStream_t st) {
+  const size_t total = (size_t)Nx * Ny * (P + 1) * (P + 1);
+  const unsigned blocks = (unsigned)std::min<size_t>((total + 255) / 256, 65535);
+#define SEM_COLREC(PP) \
+  case PP:             \
+    hipLaunchKernelGGL(k_colrec3d<PP>, dim3(blocks), dim3(256), 0, st, hf, ef, CG, Nx, Ny, Nz, dx, dy); \
+    break;
+  switch (P) {
+    SEM_COLREC(1) SEM_COLREC(2) SEM_COLREC(3) SEM_COLREC(4) SEM_COLREC(5) SEM_COLREC(6)
+    SEM_COLREC(7) SEM_COLREC(8)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SEM_COLREC
   return hipGetLastError();
 }
 

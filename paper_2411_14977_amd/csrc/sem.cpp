@@ -255,6 +255,42 @@ std::vector<double> column_records(const semh::LevelGeom& L) {
   return out;
 }
 
+// G_COL64 records of a 3D level: per element column (ex, ey) and horizontal node (i, m),
+// {W K d r_x^2, W K s_s^2 / d, h_x, d_x, h_y, d_y, W K r_x s_s, dx/dy} (W = w_i w_m,
+// K = dx dy dsig / 8, r_x = 2/dx, s_s = 2/dsig), slopes by spectral differentiation of the
+// element-local h, d (the quantities the stored factors are built from)
+std::vector<double> column_records3d(const semh::LevelGeom& L) {
+  const int NP = L.NP, NL = NP * NP;
+  const double dx = L.Lx / L.Nx, dy = L.Ly / L.Ny, dsig = 1.0 / L.Nz;
+  const double rx = 2.0 / dx, ty = 2.0 / dy, ss = 2.0 / dsig, K = dx * dy * dsig / 8.0;
+  std::vector<double> out((size_t)L.Nx * L.Ny * NL * semk::COLGEO3_N);
+  for (size_t col = 0; col < (size_t)L.Nx * L.Ny; ++col) {
+    const double* h = &L.col_h[col * NL];
+    const double* et = &L.col_eta[col * NL];
+    for (int i = 0; i < NP; ++i)
+      for (int m = 0; m < NP; ++m) {
+        double a = 0, b = 0, cc = 0, e2 = 0;
+        for (int k = 0; k < NP; ++k) {
+          a += L.D[i * NP + k] * h[k * NP + m];
+          b += L.D[i * NP + k] * (h[k * NP + m] + et[k * NP + m]);
+          cc += L.D[m * NP + k] * h[i * NP + k];
+          e2 += L.D[m * NP + k] * (h[i * NP + k] + et[i * NP + k]);
+        }
+        const double d = h[i * NP + m] + et[i * NP + m], W = L.w[i] * L.w[m];
+        double* r = &out[(col * NL + i * NP + m) * semk::COLGEO3_N];
+        r[0] = W * K * d * rx * rx;
+        r[1] = W * K * ss * ss / d;
+        r[2] = rx * a;
+        r[3] = rx * b;
+        r[4] = ty * cc;
+        r[5] = ty * e2;
+        r[6] = W * K * rx * ss;
+        r[7] = dx / dy;
+      }
+  }
+  return out;
+}
+
 // factor data of a 2D level: column records where its operator forms the factors itself
 // (FP64 levels and SEM_F32_GCOL, equal orders), else stored factors in the inner precision
 semk::GType level_gtype(const Ctx* c, const DLevel& L) {
@@ -276,6 +312,22 @@ void* put_factors(Ctx* c, const DLevel& L, const semh::LevelGeom& geo, void* dst
     default:
       return put_vec(c, layout_G2<uint16_t>(geo, geo.G,
                                             [](double v) { return semh::bf16_bits((float)v); }),
+                     dst);
+  }
+}
+
+template <typename TG, typename Conv>
+std::vector<TG> permute_G3d(const semh::LevelGeom& L, Conv conv);
+
+// the same for a 3D level
+void* put_factors3d(Ctx* c, const DLevel& L, const semh::LevelGeom& geo, void* dst) {
+  switch (L.gt) {
+    case semk::G_COL64: return put_vec(c, column_records3d(geo), dst);
+    case semk::G_F64: return put_vec(c, permute_G3d<double>(geo, [](double v) { return v; }), dst);
+    case semk::G_F32:
+      return put_vec(c, permute_G3d<float>(geo, [](double v) { return (float)v; }), dst);
+    default:
+      return put_vec(c, permute_G3d<uint16_t>(geo, [](double v) { return semh::bf16_bits((float)v); }),
                      dst);
   }
 }
@@ -372,7 +424,7 @@ void apply_level(Ctx* c, int l, const void* x, int masked) {
 void apply_outer(Ctx* c, const double* x, int masked) {
   DLevel& L = c->lev[0];
   if (c->dim == 3)
-    HK(semk::apply3d(L.P, true, semk::G_F64, x, c->yo, c->Sxo, c->Syo, c->Sxyo, c->G64, L.Nx, L.Ny,
+    HK(semk::apply3d(L.P, true, semk::G_COL64, x, c->yo, c->Sxo, c->Syo, c->Sxyo, c->CG64, L.Nx, L.Ny,
                      L.Nz, masked, c->st));
   else if (L.rect)
     HK(semk::apply2r(L.P, L.Pz, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Dx, L.Dz, L.Nx,
@@ -1236,18 +1288,13 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
     L.N = (unsigned)L.geo.N;
     const bool coarsest = (l == nl - 1);
     L.dbl = coarsest || c->prec == SEM_F64;
-    L.gt = L.dbl ? semk::G_F64 : (c->prec == SEM_F32_GBF16 ? semk::G_BF16 : semk::G_F32);
+    L.gt = level_gtype(c, L);
     std::vector<double> Gr = L.geo.G;
     if (L.gt == semk::G_F32)
       for (auto& v : Gr) v = (double)(float)v;
     else if (L.gt == semk::G_BF16)
       for (auto& v : Gr) v = semh::bf16_round(v);
-    if (L.gt == semk::G_F64)
-      L.G = upload(c, permute_G3d<double>(L.geo, [](double v) { return v; }));
-    else if (L.gt == semk::G_F32)
-      L.G = upload(c, permute_G3d<float>(L.geo, [](double v) { return (float)v; }));
-    else
-      L.G = upload(c, permute_G3d<uint16_t>(L.geo, [](double v) { return semh::bf16_bits((float)v); }));
+    L.G = put_factors3d(c, L, L.geo, nullptr);
     std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
     std::vector<double> dinv(diag.size());
     for (size_t g = 0; g < diag.size(); ++g) dinv[g] = 1.0 / diag[g];
@@ -1291,10 +1338,9 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
   }
   c->tA = (double*)dalloc(c, tmax * 8);
   c->tB = (double*)dalloc(c, tmax * 8);
-  // outer FP64 operator
+  // outer FP64 operator: column records
   DLevel& L0 = c->lev[0];
-  if (L0.dbl) c->G64 = (double*)L0.G;
-  else c->G64 = upload(c, permute_G3d<double>(L0.geo, [](double v) { return v; }));
+  c->CG64 = upload(c, column_records3d(L0.geo));
   const size_t N = L0.N;
   c->xo = (double*)dalloc(c, N * 8);
   c->bo = (double*)dalloc(c, N * 8);
@@ -1370,8 +1416,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   c->masked = (d->dirichlet_faces & SEM_FACE_TOP) ? 1 : 0;
   c->prec = d->inner_prec;
   if (c->prec < SEM_F64 || c->prec > SEM_F32_GCOL) throw ArgFail{"bad inner_prec"};
-  if (c->prec == SEM_F32_GCOL && d->dim != 2)
-    throw ArgFail{"SEM_F32_GCOL (factors from column records) is built for 2D meshes"};
+
   if (d->smoother != SEM_SMOOTH_JACOBI && d->smoother != SEM_SMOOTH_CHEBYSHEV &&
       d->smoother != SEM_SMOOTH_SCHWARZ)
     throw ArgFail{"bad smoother"};
@@ -2623,8 +2668,7 @@ static void update_outer(Ctx* c) {
   }
   copy_to(c, c->ef_d, c->ef_h);
   const double dx = c->len0 / c->Nx, dy = c->len1 / c->Ny;
-  HK(semk::geom3d(L0.P, c->hf_d, c->ef_d, c->r_d, c->w_d, c->G64, c->Nx, c->Ny, c->Nz, dx, dy,
-                  c->st));
+  HK(semk::colrec3d(L0.P, c->hf_d, c->ef_d, c->CG64, c->Nx, c->Ny, c->Nz, dx, dy, c->st));
   HK(semk::mass3d(c->hf_d, c->ef_d, c->Wx_d, c->Wy_d, c->Wz_d, c->mass, L0.nyn, L0.nzn, N,
                   dx * dy * dsig / 8.0, c->st));
   // wall faces (x = 0, x = Lx: [iy][iz]; y = 0, y = Ly: [ix][iz]); the bottom depends on h only
@@ -2666,9 +2710,7 @@ static void rebuild_levels(Ctx* c) {
     if (c->dim == 2) {
       put_factors(c, L, L.geo, L.G);
     } else {
-      if (L.gt == semk::G_F64) copy_to(c, L.G, permute_G3d<double>(L.geo, [](double v) { return v; }));
-      else if (L.gt == semk::G_F32) copy_to(c, L.G, permute_G3d<float>(L.geo, [](double v) { return (float)v; }));
-      else copy_to(c, L.G, permute_G3d<uint16_t>(L.geo, [](double v) { return semh::bf16_bits((float)v); }));
+      put_factors3d(c, L, L.geo, L.G);
     }
     std::vector<double> diag = semh::assembled_diag(L.geo, Gr, c->masked);
     std::vector<double> dinv(diag.size());
@@ -3136,7 +3178,9 @@ sem_status sem_operator_bytes(const sem_ctx* ctx, int level, int kind, double* b
   *bytes = nvec * sv * L.N + L.geo.nfields * sg * nloc;
   // operators that form their factors from column records read those instead
   if ((kind == 1 && c->CG64) || (kind != 1 && L.gt == semk::G_COL64))
-    *bytes = nvec * sv * L.N + 8.0 * semk::COLGEO_N * (double)L.Nx * L.NP;
+    *bytes = nvec * sv * L.N + (c->dim == 2 ? 8.0 * semk::COLGEO_N * (double)L.Nx * L.NP
+                                            : 8.0 * semk::COLGEO3_N * (double)L.Nx * L.Ny *
+                                                  L.NP * L.NP);
   return SEM_OK;
 }
 

@@ -88,7 +88,7 @@ def test_operator_3d_fp64_all_levels(name):
     s.close()
 
 
-@pytest.mark.parametrize("prec,bar", [("f32", 2e-6), ("bf16", 1e-2)])
+@pytest.mark.parametrize("prec,bar", [("f32", 2e-6), ("bf16", 1e-2), ("col", 2e-6)])
 def test_operator_3d_inner_precision(prec, bar):
     Ho = oracle_h("t3a")
     s = lib_solver("t3a", prec=prec)
@@ -177,7 +177,7 @@ def test_rhs_assembly_3d(name):
 
 
 @pytest.mark.parametrize("name", ["t3a", "t3h", "t3hh", "t3p6"])
-@pytest.mark.parametrize("prec,bar", [("f64", 1e-9), ("f32", 1e-8), ("bf16", 1e-8)])
+@pytest.mark.parametrize("prec,bar", [("f64", 1e-9), ("f32", 1e-8), ("bf16", 1e-8), ("col", 1e-8)])
 def test_solve_3d_matches_direct(name, prec, bar):
     wl, _ = CASES3[name]
     Ho = oracle_h(name)
@@ -192,7 +192,7 @@ def test_solve_3d_matches_direct(name, prec, bar):
     s.close()
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "col"])
 def test_operator_fullsize_c5(prec):
     wl = W.c5()
     print(f"[gpu] c5 operator {prec}", flush=True)
@@ -200,7 +200,7 @@ def test_operator_fullsize_c5(prec):
     m = oc.fine_mesh(wl)
     x = W.random_vector(m.N, 11)
     ref = assemble.apply_matrix_free(m, x)
-    bar = {"f64": 1e-12, "f32": 2e-6, "bf16": 1e-2}[prec]
+    bar = {"f64": 1e-12, "f32": 2e-6, "bf16": 1e-2, "col": 2e-6}[prec]
     assert rel(H(s.apply_level(0, T(x))), ref) <= bar
     assert rel(H(s.apply(T(x))), ref) <= 1e-12
     s.close()
