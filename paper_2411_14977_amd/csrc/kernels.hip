@@ -1552,25 +1552,40 @@ __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __
 
   T g[5][NP];
   if (act) load_g3d<P, T, TG>(G, col, nthr, t, g);
-  // the column: NP*NP lines of nzn values, one coalesced pass per (line group)
+  // the column: NP*NP lines of nzn values, one coalesced pass per (line group).  Node k = t + r B
+  // of the column is (line, iz) = divmod(k, nzn), stepped from one pass to the next by
+  // divmod(B, nzn) (one division per thread instead of one per pass); offsets are 32-bit from
+  // the column's first node
+  const size_t cbase = ((size_t)gx0 * nyn + gy0) * nzn;
+  const unsigned B = blockDim.x, qB = B / nzn, rB = B - qB * nzn;
+  const unsigned line0 = t / nzn, iz0 = t - line0 * nzn;
   {
-    const int total = NL * nzn;
+    const T* xc = x + cbase;
     T xin[NP + 1];
+    unsigned line = line0, iz = iz0;
 #pragma unroll
     for (int r = 0; r <= NP; ++r) {
-      const int k = t + r * blockDim.x;
-      if (k < total) {
-        const int line = k / nzn, iz = k - (k / nzn) * nzn;
-        const int i = line / NP, m = line - (line / NP) * NP;
-        xin[r] = x[((gx0 + i) * nyn + gy0 + m) * nzn + iz];
+      if (line < (unsigned)NL) {
+        const unsigned i = line / NP, m = line - i * NP;
+        xin[r] = xc[(i * nyn + m) * nzn + iz];
+      }
+      iz += rB;
+      line += qB;
+      if (iz >= (unsigned)nzn) {
+        iz -= nzn;
+        ++line;
       }
     }
+    line = line0;
+    iz = iz0;
 #pragma unroll
     for (int r = 0; r <= NP; ++r) {
-      const int k = t + r * blockDim.x;
-      if (k < total) {
-        const int line = k / nzn, iz = k - (k / nzn) * nzn;
-        su[line * nzp + iz] = xin[r];
+      if (line < (unsigned)NL) su[line * nzp + iz] = xin[r];
+      iz += rB;
+      line += qB;
+      if (iz >= (unsigned)nzn) {
+        iz -= nzn;
+        ++line;
       }
     }
   }
@@ -1654,11 +1669,11 @@ __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __
   }
   __syncthreads();
   {
-    const int total = NL * nzn;
-    for (int k = t; k < total; k += blockDim.x) {
-      const int line = k / nzn, iz = k - (k / nzn) * nzn;
-      const int i = line / NP, m = line - (line / NP) * NP;
-      const size_t gg = ((gx0 + i) * nyn + gy0 + m) * nzn + iz;
+    // outputs, node by node (line, iz) as in the load, offsets from the column's first node
+    unsigned line = line0, iz = iz0;
+    for (; line < (unsigned)NL;) {
+      const unsigned i = line / NP, m = line - i * NP;
+      const size_t gg = cbase + (size_t)((i * nyn + m) * nzn + iz);
       const bool dx = i == P && ex < Nx - 1, dy = m == P && ey < Ny - 1;
       T val = su[line * nzp + iz];
       if (!dx && !dy) {
@@ -1676,9 +1691,15 @@ __global__ __launch_bounds__(1024) void k_apply3d(const T* __restrict__ x, T* __
           y[gg] = val;
         }
       } else {
-        if (masked && iz == nzn - 1) val = (T)0;
+        if (masked && iz == (unsigned)(nzn - 1)) val = (T)0;
         T* dst = dx ? (dy ? Sxy : Sx) : Sy;
         dst[gg] = val;
+      }
+      iz += rB;
+      line += qB;
+      if (iz >= (unsigned)nzn) {
+        iz -= nzn;
+        ++line;
       }
     }
   }
