@@ -116,6 +116,13 @@ typedef struct {
                                   order_z, the last 1; from one level to the next neither order
                                   grows and one of them drops, or both drop where both levels
                                   have equal orders.                                          */
+  int precond_still_water;     /* 1: every V-cycle level (factors, inverse diagonals, coarse
+                                  solve, lambda_hat, the learned stage's geometry) is built from
+                                  the still-water geometry eta = 0, the small-amplitude
+                                  linearisation that keeps the preconditioner time-constant
+                                  (Sec. 5.4); the outer operator, the mass and the faces use the
+                                  given eta, and sem_mesh_update_surface never rebuilds the
+                                  levels.  0 (default): the levels are built from eta.         */
 } sem_mesh_desc;
 
 typedef struct {
@@ -175,6 +182,45 @@ sem_status sem_gll(int P, double *nodes, double *weights);
  * only in 3D, may be NULL in 2D).  Level 0 gives the current surface (after
  * sem_mesh_update_surface); coarser levels the geometry their V-cycle operators were built on. */
 sem_status sem_node_coords(const sem_ctx *ctx, int level, double *x, double *y, double *z);
+
+/* ---- the stage loop (Sec. 3) around the solve ----------------------------------------------
+ * The paper advances its model with the five-stage fourth-order low-storage Runge-Kutta scheme
+ *   K^k = alpha_k K^(k-1) + dt f(y^(k-1), t_n + c_k dt),  y^(k) = y^(k-1) + beta_k K^k,
+ * solving a Poisson problem on the mesh of every stage's surface with a time-constant
+ * preconditioner (Sec. 5.4; sem_mesh_desc.precond_still_water).  Its velocity-dependent
+ * right-hand side is outside this library; the stage loop here is driven by the linear
+ * free-surface potential-flow model on the same meshes, state y = (eta, Phi) at the surface
+ * nodes (2 ns values, ns = ne[0] P + 1 in 2D, (ne[0] P + 1)(ne[1] P + 1) in 3D, each half in the
+ * layout of sem_mesh_desc.eta):  -lap phi = 0 with phi = Phi on the surface and zero normal
+ * derivative on walls and bottom, d eta/dt = d phi/dz at the surface, d Phi/dt = -g eta. */
+
+/* The scheme's coefficients alpha, beta, c (five each; the published fourth-order 2N-storage
+ * solution of Carpenter and Kennedy, 1994, which the paper cites without printing). */
+void sem_lserk_coefficients(double *alpha, double *beta, double *c);
+
+/* Stage update k (0..4) on device arrays of n values: K = alpha_k K + dt F; y += beta_k K,
+ * on the context's stream.  SEM_ERR_ARG for a bad stage or null pointers. */
+sem_status sem_lserk_update(sem_ctx *ctx, int stage, double dt, const double *F, double *K,
+                            double *y, size_t n);
+
+/* w = d phi / dz at the surface nodes of the current fine mesh: (1/d) d phi / d sigma
+ * (Sec. 2.2, sigma_z = 1/d) from the top element's nodal values with the GLL differentiation
+ * matrix.  phi: device, the fine level's n_global values; w: device, ns values. */
+sem_status sem_surface_dz(sem_ctx *ctx, const double *phi, double *w);
+
+/* The model's right-hand side F = f(y) (device arrays of 2 ns values): the mesh follows eta
+ * (sem_mesh_update_surface without refreshing the preconditioner; eta is copied to the host
+ * for it), phi solves the Dirichlet problem with Phi on the surface (sem_poisson_solve to tol,
+ * warm-started from phi, which is a device array of n_global values updated in place), then
+ * F = (d phi / dz at the surface, -g eta).  info (may be NULL) receives the solve's record. */
+sem_status sem_wave_rhs(sem_ctx *ctx, const double *y, double *F, double *phi, double g,
+                        double tol, sem_solve_info *info);
+
+/* One step of the scheme for the model: five sem_wave_rhs / sem_lserk_update pairs on y (2 ns
+ * device values, advanced in place) with the stage vector K (2 ns device values, overwritten).
+ * iters (may be NULL): the five solves' iteration counts. */
+sem_status sem_wave_step(sem_ctx *ctx, double *y, double *K, double *phi, double dt, double g,
+                         double tol, int *iters);
 
 /* New free surface for a time series.  The sigma transform follows eta (Sec. 2.2, eq. sigtrans),
  * so the operator's geometric factors change with it; the paper keeps the multigrid

@@ -36,7 +36,7 @@ class MeshDesc(ctypes.Structure):
         ("lanczos_steps", ctypes.c_int), ("lanczos_seed", ctypes.c_ulonglong),
         ("stream", ctypes.c_void_p), ("coarse_dense_max", ctypes.c_int),
         ("gmres_restart", ctypes.c_int), ("order_z", ctypes.c_int),
-        ("level_order_z", ctypes.c_int * SEM_MAX_LEVELS),
+        ("level_order_z", ctypes.c_int * SEM_MAX_LEVELS), ("precond_still_water", ctypes.c_int),
     ]
 
 
@@ -125,6 +125,14 @@ def lib():
         "sem_learned_skips": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ip]),
         "sem_launch_shape": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_int),
                                             ctypes.POINTER(ctypes.c_int)]),
+        "sem_lserk_coefficients": (None, [ctypes.POINTER(ctypes.c_double)] * 3),
+        "sem_lserk_update": (ctypes.c_int, [vp, ip, ctypes.c_double, dp, dp, dp,
+                                            ctypes.c_size_t]),
+        "sem_surface_dz": (ctypes.c_int, [vp, dp, dp]),
+        "sem_wave_rhs": (ctypes.c_int, [vp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                        ctypes.POINTER(SolveInfo)]),
+        "sem_wave_step": (ctypes.c_int, [vp, dp, dp, dp, ctypes.c_double, ctypes.c_double,
+                                         ctypes.c_double, ctypes.POINTER(ctypes.c_int)]),
         "sem_last_error": (ctypes.c_char_p, [vp]),
         "sem_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     }
@@ -372,6 +380,36 @@ def sem_mesh_update_surface(ctx, eta, refresh=False):
                                              1 if refresh else 0))
 
 
+def sem_lserk_coefficients():
+    """(alpha, beta, c) of the five-stage fourth-order low-storage scheme, as numpy arrays."""
+    a, b, c = ((ctypes.c_double * 5)() for _ in range(3))
+    lib().sem_lserk_coefficients(a, b, c)
+    return np.array(a[:]), np.array(b[:]), np.array(c[:])
+
+
+def sem_lserk_update(ctx, stage, dt, F, K, y):
+    _check(ctx, lib().sem_lserk_update(ctx, int(stage), float(dt), _ptr(F), _ptr(K), _ptr(y),
+                                       y.numel()))
+
+
+def sem_surface_dz(ctx, phi, w):
+    _check(ctx, lib().sem_surface_dz(ctx, _ptr(phi), _ptr(w)))
+
+
+def sem_wave_rhs(ctx, y, F, phi, g, tol):
+    info = SolveInfo()
+    _check(ctx, lib().sem_wave_rhs(ctx, _ptr(y), _ptr(F), _ptr(phi), float(g), float(tol),
+                                   ctypes.byref(info)))
+    return info
+
+
+def sem_wave_step(ctx, y, K, phi, dt, g, tol):
+    it = (ctypes.c_int * 5)()
+    _check(ctx, lib().sem_wave_step(ctx, _ptr(y), _ptr(K), _ptr(phi), float(dt), float(g),
+                                    float(tol), it))
+    return list(it[:])
+
+
 def sem_learned_load(ctx, blob, enable=True):
     _check(ctx, lib().sem_learned_load(ctx, blob, len(blob), int(enable)))
 
@@ -432,7 +470,7 @@ class Solver:
                  smoother="chebyshev", nu_pre=2, nu_post=2, cheb_degree=3, jacobi_omega=2.0 / 3.0,
                  cheb_lo=0.1, cheb_hi=1.1, outer="fpcg", maxit=500, dirichlet=True,
                  lanczos_steps=20, lanczos_seed=12345, coarse_dense_max=1200, stream=None,
-                 gmres_restart=30, order_z=None):
+                 gmres_restart=30, order_z=None, precond_still_water=False):
         """order: GLL order (2D: along x); order_z: 2D order along sigma when it differs;
         levels: level orders, each an int or (with order_z) an (x, sigma) pair; None or []:
         the library's own hierarchy."""
@@ -444,6 +482,7 @@ class Solver:
         d.order = int(order)
         if order_z is not None:
             d.order_z = int(order_z)
+        d.precond_still_water = 1 if precond_still_water else 0
         if levels:
             d.nlevels = len(levels)
             for k, p in enumerate(levels):

@@ -135,6 +135,15 @@ hipError_t mass3d(const double* hf, const double* ef, const double* Wx, const do
                   const double* Wz, double* mass, unsigned nyn, unsigned nzn, size_t N,
                   double scale, hipStream_t st);
 
+// ---- stage loop pieces (FP64) ---------------------------------------------------------------
+// w[s] = d phi / dz at the surface node of vertical node line s (s < ns): (2/dsig) times the
+// top element's GLL derivative of order P at its top node, over the depth dsurf[s]
+hipError_t surface_dz(int P, const double* phi, const double* dsurf, double* w, size_t ns,
+                      unsigned nzn, double dsig, hipStream_t st);
+// K = a K + dt F; y += b K over n values
+hipError_t lserk_update(const double* F, double* K, double* y, size_t n, double a, double dt,
+                        double b, hipStream_t st);
+
 // ---- element-wise kernels in precision T (dbl selects double, else float) ----------------
 // d = cd d + cr dinv r,  x = (from_zero ? 0 : x) + d,  r = b - (from_zero ? 0 : Ax)
 // smoother step x += d, d = cd d + cr dinv r; the residual r by mode:

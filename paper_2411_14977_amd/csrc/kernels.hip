@@ -2187,6 +2187,60 @@ hipError_t colrec3d(int P, const double* hf, const double* ef, double* CG, int N
   return hipGetLastError();
 }
 
+// ---- stage loop pieces ---------------------------------------------------------------------
+// d phi / dz at the surface node of every vertical node line s: (2 / dsig) (D_{P j} phi_j over the
+// top element's nodes of the line) / d_s, with D the GLL differentiation matrix of the sigma order
+template <int P>
+__global__ void k_surface_dz(const double* __restrict__ phi, const double* __restrict__ dsurf,
+                             double* __restrict__ w, size_t ns, unsigned nzn, double scale) {
+  for (size_t s = blockIdx.x * (size_t)blockDim.x + threadIdx.x; s < ns;
+       s += (size_t)gridDim.x * blockDim.x) {
+    const double* line = phi + s * nzn + (nzn - 1 - P);
+    double a = 0.0;
+#pragma unroll
+    for (int j = 0; j <= P; ++j) a += gllc::tab<P>.D[P][j] * line[j];
+    w[s] = scale * a / dsurf[s];
+  }
+}
+
+hipError_t surface_dz(int P, const double* phi, const double* dsurf, double* w, size_t ns,
+                      unsigned nzn, double dsig, hipStream_t st) {
+  acct_add(8.0 * ns * (P + 3));
+  const unsigned blocks = (unsigned)std::min<size_t>((ns + 255) / 256, 4096);
+  const double scale = 2.0 / dsig;
+#define SEM_SDZ(PP) \
+  case PP:          \
+    hipLaunchKernelGGL(k_surface_dz<PP>, dim3(blocks), dim3(256), 0, st, phi, dsurf, w, ns, nzn, scale); \
+    break;
+  switch (P) {
+    SEM_SDZ(1) SEM_SDZ(2) SEM_SDZ(3) SEM_SDZ(4) SEM_SDZ(5) SEM_SDZ(6) SEM_SDZ(7) SEM_SDZ(8)
+    SEM_SDZ(9) SEM_SDZ(10) SEM_SDZ(11) SEM_SDZ(12)
+    default:
+      return hipErrorInvalidValue;
+  }
+#undef SEM_SDZ
+  return hipGetLastError();
+}
+
+// low-storage Runge-Kutta stage update: K = a K + dt F, y += b K
+__global__ void k_lserk_update(const double* __restrict__ F, double* __restrict__ K,
+                               double* __restrict__ y, size_t n, double a, double dt, double b) {
+  for (size_t g = blockIdx.x * (size_t)blockDim.x + threadIdx.x; g < n;
+       g += (size_t)gridDim.x * blockDim.x) {
+    const double k = fma(a, K[g], dt * F[g]);
+    K[g] = k;
+    y[g] = fma(b, k, y[g]);
+  }
+}
+
+hipError_t lserk_update(const double* F, double* K, double* y, size_t n, double a, double dt,
+                        double b, hipStream_t st) {
+  acct_add(8.0 * n * 5);
+  const unsigned blocks = (unsigned)std::min<size_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_lserk_update, dim3(blocks), dim3(256), 0, st, F, K, y, n, a, dt, b);
+  return hipGetLastError();
+}
+
 // assembled lumped mass: m_g = (dx dy dsig / 8) d(ix, iy) Wx[ix] Wy[iy] Wz[iz], W the sum of the
 // GLL weights of the elements sharing the 1D node (the mass is separable on sigma meshes)
 __global__ void k_mass3d(const double* __restrict__ hf, const double* __restrict__ ef,

@@ -90,6 +90,11 @@ struct Ctx {
   // orders), or in 2D the column records the operator forms its factors from (G_COL64)
   double* G64 = nullptr;
   double* CG64 = nullptr;
+  // stage loop: depth d = h + eta at every surface node (fine samples), the model's right-hand
+  // side and Poisson right-hand side buffers, a host copy of a stage's surface
+  double* dsurf = nullptr;
+  double *wF = nullptr, *wrhs = nullptr;
+  std::vector<double> eta_h;
   bool G64_owned = false;
   double *xo = nullptr, *bo = nullptr, *ro = nullptr, *po = nullptr, *qo = nullptr,
          *zo = nullptr, *yo = nullptr, *So = nullptr, *mass = nullptr;
@@ -1226,6 +1231,32 @@ void upload_op(Ctx* c, const Rows1& r, DLevel::Op1& op) {
   op.wband = upload(c, wband);
 }
 
+}  // namespace
+static void rebuild_levels(Ctx* c);  // defined with the surface update below
+namespace {
+
+// depth h + eta at every surface node, for the surface derivative of the stage loop
+std::vector<double> surface_depths(const Ctx* c) {
+  std::vector<double> d(c->hf_h.size());
+  for (size_t k = 0; k < d.size(); ++k) d[k] = c->hf_h[k] + c->ef_h[k];
+  return d;
+}
+
+// the V-cycle levels from the still-water geometry (eta = 0) when the descriptor asks for it;
+// the outer operator, mass and faces keep the given surface
+void still_water_levels(Ctx* c) {
+  if (!c->desc.precond_still_water) return;
+  const std::vector<double> e = c->ef_h;
+  std::fill(c->ef_h.begin(), c->ef_h.end(), 0.0);
+  try {
+    rebuild_levels(c);
+  } catch (...) {
+    c->ef_h = e;
+    throw;
+  }
+  c->ef_h = e;
+}
+
 void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders) {
   c->Nx = d->ne[0];
   c->Ny = d->ne[1];
@@ -1397,6 +1428,8 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
     for (int l = 0; l + 1 < nl; ++l) lanczos(c, l);
   }
   learned_geometry(c);
+  c->dsurf = upload(c, surface_depths(c));
+  still_water_levels(c);
   HK(hipStreamSynchronize(c->st));
 }
 
@@ -1685,6 +1718,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   // lambda_hat per smoothed level
   if (c->masked)
     for (int l = 0; l + 1 < nl; ++l) lanczos(c, l);
+  c->dsurf = upload(c, surface_depths(c));
+  still_water_levels(c);
   HK(hipStreamSynchronize(c->st));
 }
 
@@ -2631,6 +2666,7 @@ static void copy_to(Ctx* c, void* dst, const std::vector<T>& h) {
 static void update_outer(Ctx* c) {
   DLevel& L0 = c->lev[0];
   const size_t N = L0.N;
+  if (c->dsurf) copy_to(c, c->dsurf, surface_depths(c));
   if (c->G64 && (void*)c->G64 == L0.G) {  // FP64 inner levels share the fine factors: split them
     const size_t n = c->dim == 2
                          ? (L0.rect ? 3 * L0.geo.E * (size_t)L0.geo.NP * L0.geo.NPz
@@ -2778,12 +2814,116 @@ sem_status sem_mesh_update_surface(sem_ctx* ctx, const double* eta, int refresh_
       if (!(c->hf_h[k] + eta[k] > 0.0)) throw ArgFail{"h + eta must stay positive"};
     HK(hipStreamSynchronize(c->st));
     std::copy(eta, eta + c->ef_h.size(), c->ef_h.begin());
+    const double* g64 = c->G64;
     update_outer(c);
-    if (refresh_precond) rebuild_levels(c);
-    drop_graphs(c);
+    // the captured iteration graphs read the rebuilt data in place; only a rebuild of the levels
+    // or a newly split outer factor array changes what they point to
+    const bool rebuild = refresh_precond && !c->desc.precond_still_water;
+    if (rebuild) rebuild_levels(c);
+    if (rebuild || c->G64 != g64) drop_graphs(c);
     HK(hipStreamSynchronize(c->st));
     return SEM_OK;
   });
+}
+
+// ---- stage loop -------------------------------------------------------------------------------
+// five-stage fourth-order 2N-storage coefficients (Carpenter and Kennedy 1994, solution 3)
+static const double kLserkA[5] = {0.0, -567301805773.0 / 1357537059087.0,
+                                  -2404267990393.0 / 2016746695238.0,
+                                  -3550918686646.0 / 2091501179385.0,
+                                  -1275806237668.0 / 842570457699.0};
+static const double kLserkB[5] = {1432997174477.0 / 9575080441755.0,
+                                  5161836677717.0 / 13612068292357.0,
+                                  1720146321549.0 / 2090206949498.0,
+                                  3134564353537.0 / 4481467310338.0,
+                                  2277821191437.0 / 14882151754819.0};
+static const double kLserkC[5] = {0.0, 1432997174477.0 / 9575080441755.0,
+                                  2526269341429.0 / 6820363962896.0,
+                                  2006345519317.0 / 3224310063776.0,
+                                  2802321613138.0 / 2924317926251.0};
+
+void sem_lserk_coefficients(double* alpha, double* beta, double* c) {
+  for (int k = 0; k < 5; ++k) {
+    if (alpha) alpha[k] = kLserkA[k];
+    if (beta) beta[k] = kLserkB[k];
+    if (c) c[k] = kLserkC[k];
+  }
+}
+
+sem_status sem_lserk_update(sem_ctx* ctx, int stage, double dt, const double* F, double* K,
+                            double* y, size_t n) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (stage < 0 || stage > 4) throw ArgFail{"stage must be 0..4"};
+    if (!F || !K || !y) throw ArgFail{"null vector"};
+    enter(c);
+    HK(semk::lserk_update(F, K, y, n, kLserkA[stage], dt, kLserkB[stage], c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_surface_dz(sem_ctx* ctx, const double* phi, double* w) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!phi || !w) throw ArgFail{"null vector"};
+    enter(c);
+    const DLevel& L0 = c->lev[0];
+    const int Ps = c->dim == 2 ? L0.Pz : L0.P;
+    HK(semk::surface_dz(Ps, phi, c->dsurf, w, c->hf_h.size(), L0.nzn, 1.0 / c->Nz, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_wave_rhs(sem_ctx* ctx, const double* y, double* F, double* phi, double g,
+                        double tol, sem_solve_info* info) {
+  Ctx* c = C(ctx);
+  const size_t ns = c ? c->hf_h.size() : 0;
+  sem_status st = guarded(c, [&]() {
+    if (!y || !F || !phi || y == F) throw ArgFail{"y, F, phi must be distinct device pointers"};
+    if (!(g > 0.0)) throw ArgFail{"g must be positive"};
+    if (!c->wrhs) c->wrhs = (double*)dalloc(c, (size_t)c->lev[0].N * 8);
+    c->eta_h.resize(ns);
+    enter(c);
+    HK(hipMemcpyAsync(c->eta_h.data(), y, ns * 8, hipMemcpyDeviceToHost, c->st));
+    HK(hipStreamSynchronize(c->st));
+    return SEM_OK;
+  });
+  if (st != SEM_OK) return st;
+  // the mesh of this stage's surface (the preconditioner stays), the Dirichlet problem, its solve
+  if ((st = sem_mesh_update_surface(ctx, c->eta_h.data(), 0)) != SEM_OK) return st;
+  if ((st = sem_assemble_rhs(ctx, nullptr, nullptr, y + ns, c->wrhs)) != SEM_OK) return st;
+  if ((st = sem_poisson_solve(ctx, c->wrhs, phi, tol, info)) != SEM_OK) return st;
+  return guarded(c, [&]() {
+    enter(c);
+    const DLevel& L0 = c->lev[0];
+    const int Ps = c->dim == 2 ? L0.Pz : L0.P;
+    HK(semk::surface_dz(Ps, phi, c->dsurf, F, ns, L0.nzn, 1.0 / c->Nz, c->st));
+    HK(semk::vaxpby(true, -g, y, 0.0, y, F + ns, (unsigned)ns, c->st));
+    leave(c);
+    return SEM_OK;
+  });
+}
+
+sem_status sem_wave_step(sem_ctx* ctx, double* y, double* K, double* phi, double dt, double g,
+                         double tol, int* iters) {
+  Ctx* c = C(ctx);
+  if (!c) return SEM_ERR_ARG;
+  const size_t n = 2 * c->hf_h.size();
+  sem_status st = guarded(c, [&]() {
+    if (!y || !K || !phi || y == K) throw ArgFail{"y, K, phi must be distinct device pointers"};
+    if (!c->wF) c->wF = (double*)dalloc(c, n * 8);
+    return SEM_OK;
+  });
+  if (st != SEM_OK) return st;
+  for (int k = 0; k < 5; ++k) {
+    sem_solve_info inf{};
+    if ((st = sem_wave_rhs(ctx, y, c->wF, phi, g, tol, &inf)) != SEM_OK) return st;
+    if (iters) iters[k] = inf.iters;
+    if ((st = sem_lserk_update(ctx, k, dt, c->wF, K, y, n)) != SEM_OK) return st;
+  }
+  return SEM_OK;
 }
 
 sem_status sem_learned_load(sem_ctx* ctx, const void* blob, size_t nbytes, int enable) {

@@ -108,3 +108,13 @@ def test_bad_semi_coarsened_descriptors_are_rejected_before_gpu_use():
             B.sem_mesh_setup(d)
         assert e.value.status == 1
 
+
+
+def test_lserk_coefficients_match_the_oracle():
+    """The library's stage-loop coefficients are the five-stage fourth-order scheme the oracle's
+    order pins hold (host call, no GPU)."""
+    from oracle import lserk
+    from paper_2411_14977_amd import binding as B
+    a, b, c = B.sem_lserk_coefficients()
+    ao, bo, co = lserk.coefficients()
+    assert np.array_equal(a, ao) and np.array_equal(b, bo) and np.array_equal(c, co)
