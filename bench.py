@@ -19,7 +19,9 @@ and a plain device copy of the same bytes beside it), the whole solve's algorith
 bounded sample of the same workload.
 
 A 3D time series (64 x 64 x 8, P = 6, moving surface, warm starts, frozen preconditioner) is
-reported beside it (--c5-steps, 0 to skip), the mixed-precision error table of the 2048 x 16
+reported beside it (--c5-steps, 0 to skip), the stage loop around the solve on the same tank
+(five-stage low-storage Runge-Kutta steps of the linear free-surface model, preconditioner frozen
+or built from still water; --stage-steps), the mixed-precision error table of the 2048 x 16
 tank at tolerances 1e-6, 1e-8, 1e-10 with the oracle's residual of every row (--no-c3 to skip),
 the same solve with the paper's additive Schwarz smoother in place of Chebyshev (--no-schwarz),
 and the paper's multigrid iteration table and scaling sweeps rerun on tank meshes with two
@@ -327,6 +329,49 @@ def c5_series(steps, log_every=5, blob3=None, mode3=1):
     return out
 
 
+def stage_loop_c5(steps, prec="bf16"):
+    """The stage loop around the solve on the 3D tank (64 x 64 x 8 hexahedra, P = 6): the linear
+    free-surface model (eta_t = phi_z, Phi_t = -g eta) advanced with the five-stage fourth-order
+    low-storage scheme, dt = 0.01 s, from the tank's surface with Phi = 0; every stage moves the
+    mesh to its surface, solves the Dirichlet problem to 1e-10 warm-started, and takes the
+    surface derivative (sem_wave_step).  Preconditioner built from the initial surface and kept
+    (frozen), or built from still water (the time-constant linearised form of Sec. 5.4)."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2411_14977_amd import binding as B
+    from paper_2411_14977_amd import cases
+    wl = W.c5()
+    xs = B.fine_x_nodes(wl.Nx, wl.P, wl.Lx)
+    ys = B.fine_x_nodes(wl.Ny, wl.P, wl.Ly)
+    X, Y = np.meshgrid(xs, ys, indexing="ij")
+    eta0 = W.surface_3d(X, Y, 0.0, wl.Lx, wl.surface_seed).ravel()
+    out = {"workload": "c5 tank, linear free-surface model, 5 stages per step, dt = 0.01 s, "
+                       "tol 1e-10", "steps": steps, "prec": prec}
+    for tag, still in (("frozen_initial_surface", False), ("still_water", True)):
+        s = cases.make_solver(wl, prec=prec, precond_still_water=still)
+        ns = eta0.size
+        y = torch.tensor(np.concatenate([eta0, np.zeros(ns)]), dtype=torch.float64, device="cuda")
+        K = torch.zeros_like(y)
+        phi = torch.zeros(s.n_global, dtype=torch.float64, device="cuda")
+        its, ms = [], []
+        for k in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            it = B.sem_wave_step(s.ctx, y, K, phi, 0.01, 9.81, 1e-10)
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            its.append(it)
+        s.close()
+        out[tag] = {"ms_per_step": float(np.mean(ms[1:] if steps > 1 else ms)),
+                    "iters_per_stage": its,
+                    "mean_iters_per_stage": float(np.mean(its))}
+        log(f"[bench] stage loop c5 ({tag}): {out[tag]['ms_per_step']:.1f} ms per step of 5 "
+            f"stages, iterations per stage {its}")
+    return out
+
+
 def c3_error_table():
     """Mixed-precision error table on the 2048 x 16, P = 8 tank (2.11M nodes): relative error of
     the FP32-inner solution (factors FP32 and BF16) at tolerances 1e-6, 1e-8, 1e-10 against the
@@ -552,6 +597,8 @@ def main():
     ap.add_argument("--c5-train-windows", type=int, default=16,
                     help="3D training windows of the 3D learned stage (0: no 3D stage)")
     ap.add_argument("--c5-epochs", type=int, default=200)
+    ap.add_argument("--stage-steps", type=int, default=3,
+                    help="steps of the 3D stage loop around the solve (0: skip)")
     ap.add_argument("--no-c3", action="store_true", help="skip the c3 mixed-precision error table")
     ap.add_argument("--no-schwarz", action="store_true", help="skip the Schwarz-smoother rows")
     ap.add_argument("--no-context", action="store_true",
@@ -771,6 +818,10 @@ def main():
                     f"({c5['bf16_learned']['iters_mean']:.1f} it)")
         log(msg)
 
+    stage_loop = None
+    if args.stage_steps > 0:
+        stage_loop = stage_loop_c5(args.stage_steps, args.prec)
+
     if parity_procs:
         log("[bench] waiting for the oracle's solves of the unseen surfaces ...")
         surf["oracle_parity"] = finish_oracle_parity(parity_procs)
@@ -798,7 +849,7 @@ def main():
            "learned_placements": placements, "learned_break_even": breakeven,
            "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,
            "schwarz_smoother": schwarz, "paper_context": context, "c3_error_table": c3,
-           "c5_series": c5,
+           "c5_series": c5, "stage_loop": stage_loop,
            "roofline": roof, "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
