@@ -183,6 +183,19 @@ sem_status sem_gll(int P, double *nodes, double *weights);
  * sem_mesh_update_surface); coarser levels the geometry their V-cycle operators were built on. */
 sem_status sem_node_coords(const sem_ctx *ctx, int level, double *x, double *y, double *z);
 
+/* Mixed-stage operator (2D).  Inside a Runge-Kutta stage the pressure operator is the
+ * divergence at stage k of the gradient taken with stage k-1's sigma transform (Sec. 3.1, eq.
+ * poissonp; weak form eq. weak4), read as the bilinear form
+ *   a(v, p) = int_{Omega^k} nabla^(k) v . nabla^(k-1) p dOmega^k,
+ * nabla^(m) p = (p_x + sigma_x^(m) p_sigma, sigma_z^(m) p_sigma): not symmetric once the two
+ * surfaces differ.  eta_prev: host array of stage k-1's surface in the layout of
+ * sem_mesh_desc.eta (the current surface is stage k).  The FP64 outer operator
+ * (sem_apply_laplacian, sem_assemble_rhs's lifting, the outer iteration) becomes this form until
+ * the next sem_mesh_update_surface or a call with eta_prev = NULL; the V-cycle stays the
+ * (time-constant) preconditioner.  sem_poisson_solve then needs SEM_OUTER_GMRES or
+ * SEM_OUTER_PDC (SEM_ERR_STATE with FPCG).  SEM_ERR_ARG in 3D or if h + eta_prev <= 0. */
+sem_status sem_mesh_mixed_stage(sem_ctx *ctx, const double *eta_prev);
+
 /* ---- the stage loop (Sec. 3) around the solve ----------------------------------------------
  * The paper advances its model with the five-stage fourth-order low-storage Runge-Kutta scheme
  *   K^k = alpha_k K^(k-1) + dt f(y^(k-1), t_n + c_k dt),  y^(k) = y^(k-1) + beta_k K^k,

@@ -125,6 +125,7 @@ def lib():
         "sem_learned_skips": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ip]),
         "sem_launch_shape": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_int),
                                             ctypes.POINTER(ctypes.c_int)]),
+        "sem_mesh_mixed_stage": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
         "sem_lserk_coefficients": (None, [ctypes.POINTER(ctypes.c_double)] * 3),
         "sem_lserk_update": (ctypes.c_int, [vp, ip, ctypes.c_double, dp, dp, dp,
                                             ctypes.c_size_t]),
@@ -380,6 +381,16 @@ def sem_mesh_update_surface(ctx, eta, refresh=False):
                                              1 if refresh else 0))
 
 
+def sem_mesh_mixed_stage(ctx, eta_prev):
+    """Mixed-stage outer operator with stage k-1's surface eta_prev (host array; None: back to
+    the same-stage operator)."""
+    if eta_prev is None:
+        _check(ctx, lib().sem_mesh_mixed_stage(ctx, None))
+        return
+    e = np.ascontiguousarray(np.asarray(eta_prev, dtype=np.float64).ravel())
+    _check(ctx, lib().sem_mesh_mixed_stage(ctx, e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+
 def sem_lserk_coefficients():
     """(alpha, beta, c) of the five-stage fourth-order low-storage scheme, as numpy arrays."""
     a, b, c = ((ctypes.c_double * 5)() for _ in range(3))
@@ -572,6 +583,9 @@ class Solver:
 
     def update_surface(self, eta, refresh=False):
         sem_mesh_update_surface(self.ctx, eta, refresh)
+
+    def mixed_stage(self, eta_prev):
+        sem_mesh_mixed_stage(self.ctx, eta_prev)
 
     def learned_load(self, blob, enable=True):
         sem_learned_load(self.ctx, blob, enable)

@@ -51,9 +51,11 @@ hipError_t apply2d(int P, bool dbl, GType gt, const void* x, void* y, void* S, c
 // FP64 differentiation matrices.  apply2r_fits: the column fits one workgroup
 // ((PX+1)(PZ+1) Nz <= 1024 threads, 64 KB of LDS).
 bool apply2r_fits(int PX, int PZ, int Nz, bool dbl);
+// nf = 4: a fourth field G_sr (layout [ex][field][ez][i][j] with four fields) for operators that
+// are not symmetric (the mixed-stage form of two stage geometries); nf = 3: G_sr = G_rs
 hipError_t apply2r(int PX, int PZ, bool dbl, GType gt, const void* x, void* y, void* S,
                    const void* G, const double* Dx, const double* Dz, int Nx, int Nz, int masked,
-                   hipStream_t st);
+                   hipStream_t st, int nf = 3);
 // the same, plus each workgroup's part of x . (A x) in dotp[0 .. apply2d_blocks) (P <= 8)
 hipError_t apply2d_dot(int P, bool dbl, GType gt, const void* x, void* y, void* S, const void* G,
                        int Nx, int Nz, int masked, double* dotp, hipStream_t st);

@@ -95,6 +95,10 @@ struct Ctx {
   double* dsurf = nullptr;
   double *wF = nullptr, *wrhs = nullptr;
   std::vector<double> eta_h;
+  // mixed-stage outer operator (2D): four FP64 factor fields of two stage geometries in the
+  // layout of the two-order operator kernel, and its differentiation matrices
+  bool mixed = false;
+  double *Gmix = nullptr, *Dmx = nullptr, *Dmz = nullptr;
   bool G64_owned = false;
   double *xo = nullptr, *bo = nullptr, *ro = nullptr, *po = nullptr, *qo = nullptr,
          *zo = nullptr, *yo = nullptr, *So = nullptr, *mass = nullptr;
@@ -431,6 +435,9 @@ void apply_outer(Ctx* c, const double* x, int masked) {
   if (c->dim == 3)
     HK(semk::apply3d(L.P, true, semk::G_COL64, x, c->yo, c->Sxo, c->Syo, c->Sxyo, c->CG64, L.Nx, L.Ny,
                      L.Nz, masked, c->st));
+  else if (c->mixed)
+    HK(semk::apply2r(L.P, L.Pz, true, semk::G_F64, x, c->yo, c->So, c->Gmix, c->Dmx, c->Dmz,
+                     L.Nx, L.Nz, masked, c->st, 4));
   else if (L.rect)
     HK(semk::apply2r(L.P, L.Pz, true, semk::G_F64, x, c->yo, c->So, c->G64, L.Dx, L.Dz, L.Nx,
                      L.Nz, masked, c->st));
@@ -2118,6 +2125,10 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
     if (!c->masked) return SEM_ERR_STATE;
     if (!rhs || !x || rhs == x) throw ArgFail{"rhs and x must be distinct device pointers"};
     if (!(tol >= 0)) throw ArgFail{"bad tol"};
+    if (c->mixed && c->desc.outer == SEM_OUTER_FPCG) {
+      set_err(c, "the mixed-stage operator is not symmetric: use GMRES or PDC");
+      return SEM_ERR_STATE;
+    }
     sem_solve_info loc{};
     sem_solve_info* inf = info ? info : &loc;
     std::memset(inf, 0, sizeof(*inf));
@@ -2820,7 +2831,81 @@ sem_status sem_mesh_update_surface(sem_ctx* ctx, const double* eta, int refresh_
     // or a newly split outer factor array changes what they point to
     const bool rebuild = refresh_precond && !c->desc.precond_still_water;
     if (rebuild) rebuild_levels(c);
-    if (rebuild || c->G64 != g64) drop_graphs(c);
+    const bool was_mixed = c->mixed;
+    c->mixed = false;  // a new surface ends the mixed-stage form (same-stage operator again)
+    if (rebuild || c->G64 != g64 || was_mixed) drop_graphs(c);
+    HK(hipStreamSynchronize(c->st));
+    return SEM_OK;
+  });
+}
+
+sem_status sem_mesh_mixed_stage(sem_ctx* ctx, const double* eta_prev) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (c->dim != 2) throw ArgFail{"the mixed-stage operator is built for 2D meshes"};
+    HK(hipStreamSynchronize(c->st));
+    if (!eta_prev) {
+      if (c->mixed) drop_graphs(c);
+      c->mixed = false;
+      return SEM_OK;
+    }
+    for (size_t k = 0; k < c->ef_h.size(); ++k)
+      if (!(c->hf_h[k] + eta_prev[k] > 0.0)) throw ArgFail{"h + eta_prev must stay positive"};
+    const DLevel& L0 = c->lev[0];
+    semh::LevelGeom gk, gp;  // stage k (current surface) and stage k-1
+    semh::build_level(gk, 2, c->Nx, 1, c->Nz, L0.P, c->Pf, c->len0, 1.0, c->hf_h.data(),
+                      c->ef_h.data(), L0.Pz);
+    semh::build_level(gp, 2, c->Nx, 1, c->Nz, L0.P, c->Pf, c->len0, 1.0, c->hf_h.data(),
+                      eta_prev, L0.Pz);
+    // G_rr = w d_k dsig/dx, G_rs = w d_k sx_(k-1), G_ss = w (dx/dsig) d_k (sx_k sx_(k-1) +
+    // 1/(d_k d_(k-1))), G_sr = w d_k sx_k, per node (e, i, j); sx = (h_x - sigma d_x)/d
+    const int NP = gk.NP, NPz = gk.NPz, Nz = c->Nz;
+    const size_t nloc = (size_t)NP * NPz, nthr = nloc * Nz;
+    const double dx = c->len0 / c->Nx, dsig = 1.0 / Nz;
+    std::vector<double> G(4 * nthr * c->Nx);
+    for (int ex = 0; ex < c->Nx; ++ex) {
+      std::vector<double> dk(NP), dp(NP), hx(NP), dxk(NP), dxp(NP);
+      for (int i = 0; i < NP; ++i) {
+        const size_t q = (size_t)ex * NP + i;
+        dk[i] = gk.col_h[q] + gk.col_eta[q];
+        dp[i] = gp.col_h[q] + gp.col_eta[q];
+      }
+      for (int i = 0; i < NP; ++i) {
+        double a = 0, b = 0, e2 = 0;
+        for (int k = 0; k < NP; ++k) {
+          a += gk.D[i * NP + k] * gk.col_h[(size_t)ex * NP + k];
+          b += gk.D[i * NP + k] * dk[k];
+          e2 += gk.D[i * NP + k] * dp[k];
+        }
+        hx[i] = 2.0 / dx * a;
+        dxk[i] = 2.0 / dx * b;
+        dxp[i] = 2.0 / dx * e2;
+      }
+      for (int ez = 0; ez < Nz; ++ez)
+        for (int i = 0; i < NP; ++i)
+          for (int j = 0; j < NPz; ++j) {
+            const double sig = (ez + (gk.rz[j] + 1.0) / 2.0) / Nz;
+            const double sk = (hx[i] - sig * dxk[i]) / dk[i];
+            const double sp = (hx[i] - sig * dxp[i]) / dp[i];
+            const double w = gk.w[i] * gk.wz[j];
+            const size_t t = (size_t)ez * nloc + (size_t)i * NPz + j;
+            double* gc = &G[(size_t)ex * 4 * nthr];
+            gc[0 * nthr + t] = w * dk[i] * dsig / dx;
+            gc[1 * nthr + t] = w * dk[i] * sp;
+            gc[2 * nthr + t] = w * (dx / dsig) * dk[i] * (sk * sp + 1.0 / (dk[i] * dp[i]));
+            gc[3 * nthr + t] = w * dk[i] * sk;
+          }
+    }
+    if (!semk::apply2r_fits(L0.P, L0.Pz, Nz, true))
+      throw ArgFail{"the mixed-stage operator needs (P_x+1)(P_z+1) ne[2] <= 1024"};
+    if (!c->Gmix) {
+      c->Gmix = (double*)dalloc(c, G.size() * 8);
+      c->Dmx = upload(c, gk.D);
+      c->Dmz = upload(c, gk.Dz);
+    }
+    copy_to(c, c->Gmix, G);
+    c->mixed = true;
+    drop_graphs(c);
     HK(hipStreamSynchronize(c->st));
     return SEM_OK;
   });

@@ -39,12 +39,15 @@ inline size_t rect_lds_elems(int PX, int PZ, int Nz) {
   return NPX * NPX + NPZ * NPZ + NPX * nzn + 2 * nthr + (size_t)Nz * NPX;
 }
 
+// nf = 3: fields G_rr, G_rs, G_ss (symmetric); nf = 4: G_rr, G_rs, G_ss, G_sr with G_rs pairing
+// the test function's r-derivative with the trial function's s-derivative and G_sr the reverse
+// (the mixed-stage operator of two stage geometries)
 template <typename T, typename TG>
 __global__ __launch_bounds__(1024) void k_apply2r(const T* __restrict__ x, T* __restrict__ y,
                                                   T* __restrict__ S, const TG* __restrict__ G,
                                                   const double* __restrict__ Dx,
                                                   const double* __restrict__ Dz, int Nx, int Nz,
-                                                  int PX, int PZ, int masked) {
+                                                  int PX, int PZ, int masked, int nf) {
   const int NPX = PX + 1, NPZ = PZ + 1, nloc = NPX * NPZ, nthr = nloc * Nz;
   const int nzn = Nz * PZ + 1;
   const int ex = blockIdx.x;
@@ -72,10 +75,11 @@ __global__ __launch_bounds__(1024) void k_apply2r(const T* __restrict__ x, T* __
     T ur = 0, us = 0;
     for (int k = 0; k < NPX; ++k) ur += Dxs[i * NPX + k] * xs[k * nzn + iz0 + j];
     for (int k = 0; k < NPZ; ++k) us += Dzs[j * NPZ + k] * xs[i * nzn + iz0 + k];
-    const TG* Gc = G + (size_t)ex * 3 * nthr + t;
+    const TG* Gc = G + (size_t)ex * nf * nthr + t;
     const T g0 = gval<T, TG>(Gc), g1 = gval<T, TG>(Gc + nthr), g2 = gval<T, TG>(Gc + 2 * nthr);
+    const T g3 = nf == 4 ? gval<T, TG>(Gc + 3 * nthr) : g1;
     wr[t] = g0 * ur + g1 * us;
-    ws[t] = g1 * ur + g2 * us;
+    ws[t] = g3 * ur + g2 * us;
   }
   __syncthreads();
   T v = 0;
@@ -100,13 +104,14 @@ __global__ __launch_bounds__(1024) void k_apply2r(const T* __restrict__ x, T* __
 
 template <typename T, typename TG>
 hipError_t launch(const void* x, void* y, void* S, const void* G, const double* Dx,
-                  const double* Dz, int Nx, int Nz, int PX, int PZ, int masked, hipStream_t st) {
+                  const double* Dz, int Nx, int Nz, int PX, int PZ, int masked, int nf,
+                  hipStream_t st) {
   const int nthr = (PX + 1) * (PZ + 1) * Nz;
   const int block = (nthr + 63) / 64 * 64;
   const size_t smem = rect_lds_elems(PX, PZ, Nz) * sizeof(T);
   if (block > 1024 || smem > 65536) return hipErrorInvalidConfiguration;
   hipLaunchKernelGGL((k_apply2r<T, TG>), dim3(Nx), dim3(block), smem, st, (const T*)x, (T*)y,
-                     (T*)S, (const TG*)G, Dx, Dz, Nx, Nz, PX, PZ, masked);
+                     (T*)S, (const TG*)G, Dx, Dz, Nx, Nz, PX, PZ, masked, nf);
   return hipGetLastError();
 }
 
@@ -119,18 +124,21 @@ bool apply2r_fits(int PX, int PZ, int Nz, bool dbl) {
 
 hipError_t apply2r(int PX, int PZ, bool dbl, GType gt, const void* x, void* y, void* S,
                    const void* G, const double* Dx, const double* Dz, int Nx, int Nz, int masked,
-                   hipStream_t st) {
+                   hipStream_t st, int nf) {
+  if (nf != 3 && nf != 4) return hipErrorInvalidValue;
   const double vs = dbl ? 8.0 : 4.0, gs = gt == G_F64 ? 8.0 : (gt == G_F32 ? 4.0 : 2.0);
   const double nodes = (double)(Nx * PX + 1) * (Nz * PZ + 1);
   // x read, y written (the shared lines once more into S), factors read once
   acct_add(vs * nodes * 2.0 + vs * (double)(Nx - 1) * (Nz * PZ + 1) +
-           gs * 3.0 * Nx * Nz * (PX + 1) * (PZ + 1));
+           gs * nf * Nx * Nz * (PX + 1) * (PZ + 1));
   if (dbl) {
     if (gt != G_F64) return hipErrorInvalidValue;
-    return launch<double, double>(x, y, S, G, Dx, Dz, Nx, Nz, PX, PZ, masked, st);
+    return launch<double, double>(x, y, S, G, Dx, Dz, Nx, Nz, PX, PZ, masked, nf, st);
   }
-  if (gt == G_F32) return launch<float, float>(x, y, S, G, Dx, Dz, Nx, Nz, PX, PZ, masked, st);
-  if (gt == G_BF16) return launch<float, uint16_t>(x, y, S, G, Dx, Dz, Nx, Nz, PX, PZ, masked, st);
+  if (gt == G_F32)
+    return launch<float, float>(x, y, S, G, Dx, Dz, Nx, Nz, PX, PZ, masked, nf, st);
+  if (gt == G_BF16)
+    return launch<float, uint16_t>(x, y, S, G, Dx, Dz, Nx, Nz, PX, PZ, masked, nf, st);
   return hipErrorInvalidValue;
 }
 
