@@ -427,7 +427,8 @@ def paper_context(prec):
     """The paper's multigrid-efficiency experiments (Sec. 6, table of iterations per tolerance
     and the scaling figure) rerun with this solver on the synthetic tank: N_z = 2, P = 8,
     N_x = 102 at tolerances 1e-4, 1e-6, 1e-8 (PDC, FPCG and GMRES, the paper's two outer
-    methods and this solver's default), then at 1e-6 the iterations and time against N_x
+    methods and this solver's default; PDC and GMRES also on the mixed-stage operator of two
+    stage surfaces, the paper's operator within a stage, with the same-stage V-cycle), then at 1e-6 the iterations and time against N_x
     (P = 8, element width fixed at 0.25 m) and against the horizontal order P_x at N_x = 200
     with the vertical order fixed at P_z = 8 (semi-coarsened hierarchy, Sec. 5.1), for FPCG and
     GMRES; beside it the equal-order sweep P_x = P_z.  Inner precision as the timed path,
@@ -452,10 +453,31 @@ def paper_context(prec):
         s.close()
         return wl.n_global, rows, levels
 
-    out = {"table": {}, "scaling_nx": [], "scaling_px_pz8": [], "scaling_p": []}
+    def run_mixed(Nx, P, outer, tols):
+        # the mixed-stage operator: stage k's surface is stage k-1's moved 5 cm along the tank
+        # (the distance a 1.2 m/s crest travels in a 0.04 s stage)
+        from paper_2411_14977_amd import binding as Bm
+        wl = W.tank(Nx, 2, P, Lx=0.25 * Nx, name=f"ctx{Nx}p{P}")
+        x = Bm.fine_x_nodes(wl.Nx, wl.P, wl.Lx)
+        s = cases.make_solver(wl, prec=prec, outer=outer)
+        s.update_surface(W.surface(x - 0.05, wl.Lx, wl.surface_seed))
+        s.mixed_stage(W.surface(x, wl.Lx, wl.surface_seed))
+        rhs = cases.make_rhs(wl, s)
+        rows = {}
+        for tol in tols:
+            t, info, _ = time_solves(s, rhs, 2, 1, tol)
+            rows[f"{tol:g}"] = {"iters": info.iters, "ms": t * 1e3}
+        s.close()
+        return wl.n_global, rows
+
+    out = {"table": {}, "mixed_stage_table": {}, "scaling_nx": [], "scaling_px_pz8": [],
+           "scaling_p": []}
     for outer in ("pdc", "fpcg", "gmres"):
         n, rows, _ = run(102, 8, outer, (1e-4, 1e-6, 1e-8))
         out["table"][outer] = {"n_global": n, **rows}
+    for outer in ("pdc", "gmres"):
+        n, rows = run_mixed(102, 8, outer, (1e-4, 1e-6, 1e-8))
+        out["mixed_stage_table"][outer] = {"n_global": n, **rows}
     for outer in ("fpcg", "gmres"):
         for Nx in (25, 50, 100, 200, 400, 800):
             n, rows, _ = run(Nx, 8, outer, (1e-6,))
@@ -786,6 +808,7 @@ def main():
     if not args.no_context:
         context = paper_context(args.prec)
         log(f"[bench] paper-shaped runs: {context['table']}")
+        log(f"[bench] mixed-stage operator: {context['mixed_stage_table']}")
         for outer in ("fpcg", "gmres"):
             sw = [r for r in context["scaling_px_pz8"] if r["outer"] == outer]
             log(f"[bench] P_x sweep at P_z = 8, N_x = 200, tol 1e-6 ({outer}): " +
