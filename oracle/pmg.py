@@ -17,9 +17,9 @@ Sec. 5 of the paper:
   of Jacobi (polynomials in D^{-1} A) and the paper's additive Schwarz smoother (Sec. 5.3):
   x <- x + S^{-1}(b - A x), S^{-1} = W sum_i R_i^T (R_i A R_i^T)^{-1} R_i,
   W = (sum_i R_i R_i^T)^{-1}.  Its subdomains are read as the element blocks (each element's
-  (P+1)^d nodes; blocks of neighbouring elements share their face nodes, and no further overlap
-  nodes are added); 2D only (3D blocks of 343 nodes would need 31 GB of local inverses at the
-  64x64x8 benchmark size);
+  (P+1)^d nodes; blocks of neighbouring elements share their face nodes), widened by a chosen
+  number of overlap node layers across every face (the paper leaves the overlap to the user);
+  2D and 3D;
 * the coarsest (P = 1) problem solved exactly (sparse direct).  In 3D the paper's P = 1 grid is
   too large for an exact solve at the benchmark size; the hierarchy is continued below it by
   coarsening the mesh by 2 in x and y (P = 1, linear interpolation in x and y, identity in
@@ -125,21 +125,47 @@ class Level:
         self.lu = None
         self._blocks = None
 
-    def schwarz_blocks(self):
-        """Inverses of the element blocks R_i A R_i^T (A the masked assembled matrix) and the
+    def block_nodes(self, overlap=0):
+        """Global nodes of every subdomain: element e's nodes, widened by `overlap` node layers
+        across each of its faces into the neighbouring elements (clipped at the domain)."""
+        m = self.mesh
+        out = []
+        if m.dim == 2:
+            Px, Pz = m.P, m.Pz
+            for e in range(m.E):
+                ex, ez = divmod(e, m.Nz)
+                ix = np.arange(max(0, ex * Px - overlap), min(m.nx_nodes, ex * Px + Px + overlap + 1))
+                iz = np.arange(max(0, ez * Pz - overlap), min(m.nz_nodes, ez * Pz + Pz + overlap + 1))
+                out.append((ix[:, None] * m.nz_nodes + iz[None, :]).ravel())
+            return out
+        P = m.P
+        for e in range(m.E):
+            ez = e % m.Nz
+            ey = (e // m.Nz) % m.Ny
+            ex = e // (m.Nz * m.Ny)
+            ix = np.arange(max(0, ex * P - overlap), min(m.nx_nodes, ex * P + P + overlap + 1))
+            iy = np.arange(max(0, ey * P - overlap), min(m.ny_nodes, ey * P + P + overlap + 1))
+            iz = np.arange(max(0, ez * P - overlap), min(m.nz_nodes, ez * P + P + overlap + 1))
+            g = (ix[:, None, None] * m.ny_nodes + iy[None, :, None]) * m.nz_nodes + iz[None, None, :]
+            out.append(g.ravel())
+        return out
+
+    def schwarz_blocks(self, overlap=0):
+        """Inverses of the subdomain blocks R_i A R_i^T (A the masked assembled matrix) and the
         weights W = (sum_i R_i R_i^T)^{-1} (one over the number of blocks holding a node)."""
-        if self._blocks is None:
+        if self._blocks is None or self._blocks[2] != overlap:
             A = self.A.tocsr()
-            inv = [np.linalg.inv(A[idx][:, idx].toarray()) for idx in self.mesh.l2g]
-            w = 1.0 / np.bincount(self.mesh.l2g.ravel(), minlength=self.N)
-            self._blocks = (inv, w)
+            nodes = self.block_nodes(overlap)
+            inv = [np.linalg.inv(A[idx][:, idx].toarray()) for idx in nodes]
+            w = 1.0 / np.bincount(np.concatenate(nodes), minlength=self.N)
+            self._blocks = (inv, w, overlap, nodes)
         return self._blocks
 
-    def schwarz(self, r, weighted=True):
+    def schwarz(self, r, weighted=True, overlap=0):
         """S^{-1} r = W sum_i R_i^T (R_i A R_i^T)^{-1} R_i r (weighted=False: without W)."""
-        inv, w = self.schwarz_blocks()
+        inv, w, _, nodes = self.schwarz_blocks(overlap)
         z = np.zeros(self.N)
-        for Ai, idx in zip(inv, self.mesh.l2g):
+        for Ai, idx in zip(inv, nodes):
             np.add.at(z, idx, Ai @ r[idx])
         return w * z if weighted else z
 
@@ -149,7 +175,7 @@ class Hierarchy:
 
     def __init__(self, mesh_args, orders, smoother="chebyshev", nu_pre=2, nu_post=2,
                  cheb_degree=3, jacobi_omega=2.0 / 3.0, cheb_lo=0.1, cheb_hi=1.1,
-                 coarse_dense_max=1200, gstore=None):
+                 coarse_dense_max=1200, gstore=None, schwarz_overlap=0):
         """orders: level orders, fine to coarse; in 2D an entry may be a pair (P_x, P_sigma)
         (semi-coarsened levels), a plain P meaning (P, P).  gstore: storage precision of the
         geometric factors on every level above the coarsest (None / "f64", "f32", "bf16"); the
@@ -207,6 +233,7 @@ class Hierarchy:
         last = self.levels[-1]
         last.lu = spla.splu(sp.csc_matrix(last.A))
         self.smoother = smoother
+        self.schwarz_overlap = int(schwarz_overlap)
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.cheb_degree = cheb_degree
         self.omega = jacobi_omega
@@ -245,7 +272,7 @@ class Hierarchy:
         """Additive Schwarz smoothing (Sec. 5.3): x <- x - S^{-1}(A x - b), ``sweeps`` times."""
         L = self.levels[l]
         for _ in range(sweeps):
-            x = x + L.schwarz(b - L.A @ x)
+            x = x + L.schwarz(b - L.A @ x, overlap=self.schwarz_overlap)
         return x
 
     def smooth(self, l, b, x, pre):

@@ -265,7 +265,7 @@ def test_schwarz_unweighted_sum_is_symmetric_and_weights_partition_unity():
         e[k] = 1.0
         S0[:, k] = L.schwarz(e, weighted=False)
     assert np.abs(S0 - S0.T).max() < 1e-11 * np.abs(S0).max()
-    inv, w = L.schwarz_blocks()
+    inv, w = L.schwarz_blocks()[:2]
     counts = np.zeros(n)
     for idx in L.mesh.l2g:
         counts[idx] += 1.0
