@@ -53,10 +53,15 @@ typedef enum {
  * orders store FP32 factors. */
 enum { SEM_F64 = 0, SEM_F32 = 1, SEM_F32_GBF16 = 2, SEM_F32_GCOL = 3 };
 /* smoother on every level above the coarsest.  SEM_SMOOTH_SCHWARZ: the additive Schwarz
- * method of Sec. 5.3 with element blocks, nu_pre / nu_post sweeps of
- * x += W sum_i R_i^T (R_i A R_i^T)^{-1} R_i (b - A x), W = (sum_i R_i^T R_i)^{-1}; 2D meshes with
- * fine order P <= 8 only; the inverses of the element blocks are built at set-up (host FP64)
- * and stored per level in the inner precision (E (P_l+1)^4 values). */
+ * method of Sec. 5.3, nu_pre / nu_post sweeps of
+ * x += W sum_i R_i^T (R_i A R_i^T)^{-1} R_i (b - A x), W = (sum_i R_i^T R_i)^{-1}, over one
+ * subdomain per element: the element's nodes widened by sem_mesh_desc.schwarz_overlap node
+ * layers across every face (clipped at the domain); 2D and 3D, fine order P <= 8, equal orders
+ * along x and sigma.  The inverses of the subdomain blocks are built at set-up (host FP64),
+ * rebuilt when the surface moves, and stored per level in the inner precision: E (P_l+1)^4
+ * values in 2D without overlap, else E n_max^2 with n_max = prod over the axes of
+ * min(nodes along the axis, P_l + 1 + 2 overlap), at most 4096 nodes and 4 GiB of FP64
+ * inverses per level (SEM_ERR_ARG beyond). */
 enum { SEM_SMOOTH_JACOBI = 0, SEM_SMOOTH_CHEBYSHEV = 1, SEM_SMOOTH_SCHWARZ = 2 };
 /* outer iteration */
 enum { SEM_OUTER_FPCG = 0, SEM_OUTER_PDC = 1, SEM_OUTER_GMRES = 2 };
@@ -123,6 +128,9 @@ typedef struct {
                                   (Sec. 5.4); the outer operator, the mass and the faces use the
                                   given eta, and sem_mesh_update_surface never rebuilds the
                                   levels.  0 (default): the levels are built from eta.         */
+  int schwarz_overlap;         /* SEM_SMOOTH_SCHWARZ: node layers added to each element's
+                                  subdomain across every face, 0..8 (default 0: the element
+                                  blocks, neighbouring blocks sharing only face nodes).       */
 } sem_mesh_desc;
 
 typedef struct {

@@ -37,6 +37,7 @@ class MeshDesc(ctypes.Structure):
         ("stream", ctypes.c_void_p), ("coarse_dense_max", ctypes.c_int),
         ("gmres_restart", ctypes.c_int), ("order_z", ctypes.c_int),
         ("level_order_z", ctypes.c_int * SEM_MAX_LEVELS), ("precond_still_water", ctypes.c_int),
+        ("schwarz_overlap", ctypes.c_int),
     ]
 
 
@@ -481,7 +482,7 @@ class Solver:
                  smoother="chebyshev", nu_pre=2, nu_post=2, cheb_degree=3, jacobi_omega=2.0 / 3.0,
                  cheb_lo=0.1, cheb_hi=1.1, outer="fpcg", maxit=500, dirichlet=True,
                  lanczos_steps=20, lanczos_seed=12345, coarse_dense_max=1200, stream=None,
-                 gmres_restart=30, order_z=None, precond_still_water=False):
+                 gmres_restart=30, order_z=None, precond_still_water=False, schwarz_overlap=0):
         """order: GLL order (2D: along x); order_z: 2D order along sigma when it differs;
         levels: level orders, each an int or (with order_z) an (x, sigma) pair; None or []:
         the library's own hierarchy."""
@@ -494,6 +495,7 @@ class Solver:
         if order_z is not None:
             d.order_z = int(order_z)
         d.precond_still_water = 1 if precond_still_water else 0
+        d.schwarz_overlap = int(schwarz_overlap)
         if levels:
             d.nlevels = len(levels)
             for k, p in enumerate(levels):

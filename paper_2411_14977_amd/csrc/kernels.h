@@ -92,6 +92,20 @@ hipError_t stagecq2d(int P, bool dbl, GType gt, const float* CE, void* c, void* 
 // Dirichlet surface is left alone (set: zeroed) when masked
 hipError_t asm_sweep(int P, bool dbl, const void* r, const void* Ainv, void* z, void* x, int Nx,
                      int Nz, int masked, int set, hipStream_t st);
+// additive Schwarz sweep tail over box subdomains (2D with overlap, 3D): the subdomain of
+// element e = (ex Ny + ey) Nz + ez (2D: Ny = 1, nyn = 1) is its node index box widened by ov
+// layers per side, clipped to the grid.  z_e = Ainv_e R_e (r - y) (y optional: A x, complete),
+// then x = (set ? 0 : x) + W sum_e R_e^T z_e; the Dirichlet surface is left alone (set: zeroed)
+// when masked.  Ainv: [E][nmax * nmax], subdomain e's symmetric n_e x n_e inverse at its start;
+// z: [E][nmax].  ainv_vals = sum_e n_e^2 and z_vals = sum_e n_e count the traffic only.
+constexpr int ASM_BOX_NMAX = 4096;
+struct AsmBox {
+  int Nx = 1, Ny = 1, Nz = 1, P = 1, ov = 0, nmax = 0;
+  unsigned nxn = 1, nyn = 1, nzn = 1;
+  double ainv_vals = 0.0, z_vals = 0.0;
+};
+hipError_t asm_box_sweep(const AsmBox& bx, bool dbl, const void* r, const void* y,
+                         const void* Ainv, void* z, void* x, int masked, int set, hipStream_t st);
 // residual r = b - A x, complete at every node (2D); fused with the operator where cheb2d_cpb
 // allows, else apply2d into the scratch y, S and an element-wise pass.  r must differ from x.
 hipError_t resid2d(int P, bool dbl, GType gt, const void* x, void* r, const void* b,

@@ -11,6 +11,7 @@
 #include <atomic>
 #include <exception>
 #include <functional>
+#include <mutex>
 #include <thread>
 #include <chrono>
 #include <climits>
@@ -57,8 +58,11 @@ struct DLevel {
   void* xalt = nullptr;
   // 2D coarse levels: the pre- and post-smoothing sequences as one kernel each (W = 0: no)
   semk::CoarsePlan cpre, cpost;
-  // Schwarz smoother: inverses of the element blocks [E][n][n] and the element results [E][n]
+  // Schwarz smoother: inverses of the element blocks [E][n][n] and the element results [E][n];
+  // with asm_box, of the box subdomains (overlap or 3D) [E][nmax^2] and [E][nmax]
   void *Ainv_s = nullptr, *Zs = nullptr;
+  bool asm_box = false;
+  semk::AsmBox abox;
   size_t nS = 0;
   double lam = 0.0;
   // 3D: side buffers of the operator (completed into y by the face fix-up; S stays null) and
@@ -413,6 +417,142 @@ std::vector<double> schwarz_inverses(const semh::LevelGeom& G, const std::vector
   return out;
 }
 
+// node range of element k's Schwarz box along one axis (order p, ov overlap layers, nn nodes)
+struct Span1 {
+  int lo, len;
+};
+inline Span1 box_span(int k, int p, int ov, int nn) {
+  const int lo = std::max(0, k * p - ov), hi = std::min(nn - 1, k * p + p + ov);
+  return {lo, hi - lo + 1};
+}
+
+// The box subdomains of the Schwarz smoother (Sec. 5.3) on a level with equal orders: element
+// e's node box widened by ov layers per side and clipped; bx gets the sizes the kernels need.
+// Returns the inverses of R_e A R_e^T of the masked assembled operator (factors Gr in the
+// level's storage precision), subdomain e's n_e x n_e inverse at e nmax^2 (host FP64); rows and
+// columns of Dirichlet surface nodes are identity when masked.
+std::vector<double> schwarz_box_inverses(const semh::LevelGeom& G, const std::vector<double>& Gr,
+                                         bool masked, int ov, semk::AsmBox* bx) {
+  const bool d3 = G.dim == 3;
+  const int P = G.P, NP = G.NP;
+  const int Nx = G.Nx, Ny = d3 ? G.Ny : 1, Nz = G.Nz;
+  const int nxn = (int)G.nxn, nyn = d3 ? (int)G.nyn : 1, nzn = (int)G.nzn;
+  const size_t NL = d3 ? (size_t)NP * NP * NP : (size_t)NP * NP;
+  const size_t E = G.E;
+  auto cap = [&](int nn) { return std::min(nn, P + 1 + 2 * ov); };
+  const size_t nmax = (size_t)cap(nxn) * cap(nyn) * cap(nzn);
+  if (nmax > (size_t)semk::ASM_BOX_NMAX)
+    throw ArgFail{"Schwarz subdomains too large (at most 4096 nodes; lower schwarz_overlap)"};
+  if ((double)E * nmax * nmax * 8.0 > 4.0 * (1ull << 30))
+    throw ArgFail{"Schwarz subdomain inverses exceed 4 GiB on a level (lower schwarz_overlap or "
+                  "the mesh size)"};
+  bx->Nx = Nx;
+  bx->Ny = Ny;
+  bx->Nz = Nz;
+  bx->P = P;
+  bx->ov = ov;
+  bx->nmax = (int)nmax;
+  bx->nxn = nxn;
+  bx->nyn = nyn;
+  bx->nzn = nzn;
+  std::vector<double> Aall(E * NL * NL);
+  parallel_ranges(E, [&](size_t lo, size_t hi) {
+    for (size_t e = lo; e < hi; ++e) semh::element_matrix(G, Gr, e, &Aall[e * NL * NL]);
+  }, 4);
+  auto elem = [&](size_t e, int* ex, int* ey, int* ez) {
+    *ez = (int)(e % Nz);
+    const size_t exy = e / Nz;
+    *ey = (int)(exy % Ny);
+    *ex = (int)(exy / Ny);
+  };
+  std::vector<double> out(E * nmax * nmax, 0.0);
+  double vals = 0.0, zv = 0.0;
+  std::mutex mu;
+  parallel_ranges(E, [&](size_t lo, size_t hi) {
+    std::vector<double> B, Bi;
+    std::vector<std::pair<int, int>> in;  // (element-local node, box-local node)
+    double v2 = 0.0, v1 = 0.0;
+    for (size_t e = lo; e < hi; ++e) {
+      int ex, ey, ez;
+      elem(e, &ex, &ey, &ez);
+      const Span1 sx = box_span(ex, P, ov, nxn), sy = box_span(ey, P, ov, nyn),
+                  sz = box_span(ez, P, ov, nzn);
+      const int n = sx.len * sy.len * sz.len;
+      B.assign((size_t)n * n, 0.0);
+      Bi.assign((size_t)n * n, 0.0);
+      // elements whose nodes meet the box along every axis
+      auto range = [&](const Span1& sp, int Ne, int* f0, int* f1) {
+        const int hi = sp.lo + sp.len - 1;
+        *f0 = sp.lo > P ? (sp.lo - 1) / P : 0;
+        *f1 = std::min(Ne - 1, hi / P);
+      };
+      int fx0, fx1, fy0, fy1, fz0, fz1;
+      range(sx, Nx, &fx0, &fx1);
+      range(sy, Ny, &fy0, &fy1);
+      range(sz, Nz, &fz0, &fz1);
+      if (!d3) fy0 = fy1 = 0;
+      for (int fx = fx0; fx <= fx1; ++fx)
+        for (int fy = fy0; fy <= fy1; ++fy)
+          for (int fz = fz0; fz <= fz1; ++fz) {
+            const size_t f = ((size_t)fx * Ny + fy) * Nz + fz;
+            in.clear();
+            for (size_t a = 0; a < NL; ++a) {
+              int ai, am, aj;
+              if (d3) { aj = (int)(a % NP); am = (int)((a / NP) % NP); ai = (int)(a / (NP * NP)); }
+              else { ai = (int)(a / NP); am = 0; aj = (int)(a % NP); }
+              const int gx = fx * P + ai - sx.lo, gy = (d3 ? fy * P + am : 0) - sy.lo,
+                        gz = fz * P + aj - sz.lo;
+              if (gx < 0 || gx >= sx.len || gy < 0 || gy >= sy.len || gz < 0 || gz >= sz.len)
+                continue;
+              in.push_back({(int)a, (gx * sy.len + gy) * sz.len + gz});
+            }
+            const double* Af = &Aall[f * NL * NL];
+            for (const auto& a : in)
+              for (const auto& b : in)
+                B[(size_t)a.second * n + b.second] += Af[(size_t)a.first * NL + b.first];
+          }
+      if (masked && sz.lo + sz.len == nzn)  // box-local nodes on the surface: identity rows
+        for (int q = sz.len - 1; q < n; q += sz.len) {
+          for (int k = 0; k < n; ++k) B[(size_t)q * n + k] = B[(size_t)k * n + q] = 0.0;
+          B[(size_t)q * n + q] = 1.0;
+        }
+      if (!semh::dense_inverse_public(n, B.data(), Bi.data()))
+        throw ArgFail{"singular subdomain block in the Schwarz smoother"};
+      std::copy(Bi.begin(), Bi.end(), out.begin() + e * nmax * nmax);
+      v2 += (double)n * n;
+      v1 += n;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    vals += v2;
+    zv += v1;
+  }, 1);
+  bx->ainv_vals = vals;
+  bx->z_vals = zv;
+  return out;
+}
+
+// Schwarz smoother data of a level above the coarsest: element blocks (2D without overlap) or
+// box subdomains, inverses in the level's precision; refresh: recompute the inverses of a new
+// geometry into the existing buffers
+void schwarz_setup(Ctx* c, DLevel& L, const std::vector<double>& Gr, bool refresh = false) {
+  const int ov = c->desc.schwarz_overlap;
+  const size_t eb = esz(L.dbl);
+  std::vector<double> inv;
+  size_t zn;
+  if (c->dim == 2 && ov == 0) {
+    inv = schwarz_inverses(L.geo, Gr, c->masked != 0);
+    zn = (size_t)L.NP * L.NP;
+  } else {
+    inv = schwarz_box_inverses(L.geo, Gr, c->masked != 0, ov, &L.abox);
+    L.asm_box = true;
+    zn = (size_t)L.abox.nmax;
+  }
+  void* dst = refresh ? L.Ainv_s : nullptr;
+  if (L.dbl) L.Ainv_s = put_vec(c, inv, dst);
+  else L.Ainv_s = put_vec(c, std::vector<float>(inv.begin(), inv.end()), dst);
+  if (!refresh) L.Zs = dalloc(c, L.geo.E * zn * eb);
+}
+
 void set_err(Ctx* c, const std::string& s) { c->err = s; }
 
 // ------------------------------------------------------------------------------------------
@@ -497,18 +637,27 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr, bool first_don
     for (int s = 0; s < nu; ++s) {
       const bool fz = pre && s == 0;  // x = 0 on entry: r = b
       const void* r = nullptr;
+      const void* ax = nullptr;       // with r = b: A x, complete (3D), subtracted in the gather
       if (fz) {
         if (l == 0 && c->vin64) HK(semk::cast_to(L.dbl, c->vin64, L.b, L.N, c->st));
         r = L.b;
       } else if (!pre && s == 0 && resid) {
         r = resid;
+      } else if (c->dim == 3) {
+        apply_level(c, l, L.x, c->masked);
+        r = L.b;
+        ax = L.y;
       } else {  // residual of the current x into the level's d vector (unused by this smoother)
         HK(semk::resid2d(L.P, L.dbl, L.gt, L.x, L.d, L.b, L.G, L.Nx, L.Nz, c->masked, L.y, L.S,
                          c->st));
         r = L.d;
       }
-      HK(semk::asm_sweep(L.P, L.dbl, r, L.Ainv_s, L.Zs, L.x, L.Nx, L.Nz, c->masked, fz ? 1 : 0,
-                         c->st));
+      if (L.asm_box)
+        HK(semk::asm_box_sweep(L.abox, L.dbl, r, ax, L.Ainv_s, L.Zs, L.x, c->masked, fz ? 1 : 0,
+                               c->st));
+      else
+        HK(semk::asm_sweep(L.P, L.dbl, r, L.Ainv_s, L.Zs, L.x, L.Nx, L.Nz, c->masked,
+                           fz ? 1 : 0, c->st));
     }
     return;
   }
@@ -1348,6 +1497,7 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
     L.Sxy = dalloc(c, L.N * eb);
     L.S = nullptr;
     L.nS = 0;
+    if (!coarsest && d->smoother == SEM_SMOOTH_SCHWARZ) schwarz_setup(c, L, Gr);
   }
   // transfers and their temporaries
   size_t tmax = 1;
@@ -1460,8 +1610,10 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   if (d->smoother != SEM_SMOOTH_JACOBI && d->smoother != SEM_SMOOTH_CHEBYSHEV &&
       d->smoother != SEM_SMOOTH_SCHWARZ)
     throw ArgFail{"bad smoother"};
-  if (d->smoother == SEM_SMOOTH_SCHWARZ && (d->dim != 2 || d->order > 8))
-    throw ArgFail{"the Schwarz smoother is built for 2D meshes with order <= 8"};
+  if (d->smoother == SEM_SMOOTH_SCHWARZ && d->order > 8)
+    throw ArgFail{"the Schwarz smoother is built for orders <= 8"};
+  if (d->schwarz_overlap < 0 || d->schwarz_overlap > 8)
+    throw ArgFail{"schwarz_overlap out of range (0..8)"};
   if (d->order_z < 0 || d->order_z > SEM_MAX_ORDER) throw ArgFail{"order_z out of range"};
   if (d->dim == 3 && d->order_z != 0 && d->order_z != d->order)
     throw ArgFail{"3D meshes take one order (order_z 0 or equal to order)"};
@@ -1612,13 +1764,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
     if (!coarsest && !L.rect && L.P <= 8 && semk::cheb2d_cpb(L.P, L.Nx, L.Nz, L.dbl) > 0 &&
         !no_fused_step)
       L.xalt = dalloc(c, L.N * eb);
-    if (!coarsest && d->smoother == SEM_SMOOTH_SCHWARZ) {
-      const size_t n = (size_t)L.NP * L.NP;
-      std::vector<double> inv = schwarz_inverses(L.geo, Gr, c->masked != 0);
-      if (L.dbl) L.Ainv_s = upload(c, inv);
-      else L.Ainv_s = upload(c, std::vector<float>(inv.begin(), inv.end()));
-      L.Zs = dalloc(c, L.geo.E * n * eb);
-    }
+    if (!coarsest && d->smoother == SEM_SMOOTH_SCHWARZ) schwarz_setup(c, L, Gr);
   }
   for (int l = 0; l + 1 < nl; ++l) {
     DLevel& F = c->lev[l];
@@ -2764,6 +2910,7 @@ static void rebuild_levels(Ctx* c) {
     for (size_t g = 0; g < diag.size(); ++g) dinv[g] = 1.0 / diag[g];
     if (L.dbl) copy_to(c, L.dinv, dinv);
     else copy_to(c, L.dinv, std::vector<float>(dinv.begin(), dinv.end()));
+    if (L.Ainv_s) schwarz_setup(c, L, Gr, true);
   }
   if (c->masked) {
     DLevel& LC = c->lev.back();

@@ -381,12 +381,6 @@ def test_solve_schwarz_matches_direct(name, prec, bar):
     s.close()
 
 
-def test_schwarz_rejects_3d():
-    wl = W.tank3d(2, 2, 2, 2, L=0.4, name="t3s")
-    with pytest.raises(B.SemError):
-        cases.make_solver(wl, smoother="asm")
-
-
 @pytest.mark.parametrize("name", ["tank8", "c2", "ragged", "wide3"])
 @pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "col"])
 def test_vcycle_one_kernel_levels(name, prec, monkeypatch):

@@ -46,7 +46,9 @@ def test_bad_descriptors_are_rejected_before_gpu_use():
     cases.append(d)
     h = np.ones(9)
     for mutate in (lambda d: setattr(d, "inner_prec", 7), lambda d: setattr(d, "outer", 3),
-                   lambda d: setattr(d, "smoother", 9), lambda d: setattr(d, "cheb_lo", -1.0)):
+                   lambda d: setattr(d, "smoother", 9), lambda d: setattr(d, "cheb_lo", -1.0),
+                   lambda d: setattr(d, "schwarz_overlap", 9),
+                   lambda d: setattr(d, "schwarz_overlap", -1)):
         d = B.sem_mesh_desc_default()
         d.order, d.ne[0], d.ne[2] = 4, 2, 2
         d.h = h.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
