@@ -72,6 +72,10 @@ def lib():
         return _lib
     if not os.path.exists(_LIB_PATH):
         raise RuntimeError(f"{_LIB_PATH} is not built; run python -m paper_2411_14977_amd.build")
+    # torch first: its HIP runtime is then the one the library binds to, the runtime that owns
+    # the device pointers and streams passed in (loaded alone, the library would bind the
+    # system runtime, a second one in the process)
+    import torch  # noqa: F401
     L = ctypes.CDLL(_LIB_PATH)
     vp, dp, ip, sz = ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)
     sig = {
