@@ -65,7 +65,8 @@ def describe(wl, prec, learned, mode=0):
              2: "fine level before post-smoothing",
              3: "fine level after pre-smoothing and before post-smoothing"}.get(mode, "")
     return {"workload": f"{wl.name}: 2D sigma-mapped wave tank {wl.Nx}x{wl.Nz} elements, P={wl.P}, "
-                        f"levels {'-'.join(map(str, wl.orders))}, Chebyshev({wl.cheb_degree}), "
+                        f"levels {'-'.join(map(str, wl.orders))}, Chebyshev({wl.cheb_degree}) on "
+                        f"[{wl.cheb_lo}, {wl.cheb_hi}] x lambda_hat, "
                         f"trapezoidal bar 0.4-0.1-0.4 m, surface seed {wl.surface_seed}, "
                         f"rhs seed {wl.rhs_seed}",
             "n_global": wl.n_global, "elements": wl.n_elements, "order": wl.P,
@@ -574,7 +575,8 @@ def cpu_baseline(wl, tol):
     xs = oc.fine_x_nodes(ncols, wl.P, Ls)
     args = dict(dim=2, Nx=ncols, Nz=wl.Nz, Lx=Ls, h=full_h(xs + x0), eta=full_eta(xs + x0))
     t0 = time.perf_counter()
-    H = pmg.Hierarchy(args, wl.orders, smoother="chebyshev", cheb_degree=wl.cheb_degree)
+    H = pmg.Hierarchy(args, wl.orders, smoother="chebyshev", cheb_degree=wl.cheb_degree,
+                      cheb_lo=wl.cheb_lo, cheb_hi=wl.cheb_hi)
     pmg.estimate_lambdas(H)
     t_setup = time.perf_counter() - t0
     L0 = H.levels[0]

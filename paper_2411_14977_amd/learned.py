@@ -36,7 +36,9 @@ def _orders(P):
 
 
 def training_solver(s, P=8, smoother="chebyshev", layout="tank"):
-    """FP64 solver of training geometry s, with the source term it takes: (solver, f(x, z, j))."""
+    """FP64 solver of training geometry s, with the source term it takes: (solver, f(x, z, j)).
+    Tank windows smooth as the large tanks do (their Chebyshev degree and interval), so the
+    stage-point residuals are drawn from the cycle the stage runs in."""
     if layout == "c1":
         h_fn, eta_fn = W.training_geometry(s)
         x = fine_x_nodes(8, P, 2 * math.pi)
@@ -54,8 +56,9 @@ def training_solver(s, P=8, smoother="chebyshev", layout="tank"):
         return W.surface(np.asarray(a), TANK_L, 5000 + s)
 
     x = fine_x_nodes(Nx, P, Nx * dx)
+    cheb = W.TANK_CHEB if smoother == "chebyshev" else {}
     sv = Solver(2, (Nx, 1, Nz), P, (Nx * dx,), h_fn(x + x0), eta_fn(x + x0), levels=_orders(P),
-                prec="f64", smoother=smoother)
+                prec="f64", smoother=smoother, **cheb)
     return sv, lambda xg, zg, j: W.bumps(xg + x0, zg, TANK_L, 6000 + 7 * s + j, h_fn, eta_fn)
 
 
@@ -82,8 +85,9 @@ def training_solver3d(s, P=6, smoother="chebyshev"):
     ys = fine_x_nodes(Ny, P, Ny * dx)
     X, Y = np.meshgrid(xs, ys, indexing="ij")
     lv = [6, 3, 1] if P == 6 else _orders(P)
+    cheb = W.TANK_CHEB if smoother == "chebyshev" else {}
     sv = Solver(3, (Nx, Ny, Nz), P, (Nx * dx, Ny * dx), h_fn(X, Y), eta_fn(X, Y), levels=lv,
-                prec="f64", smoother=smoother)
+                prec="f64", smoother=smoother, **cheb)
 
     def source(xg, yg, zg, j):
         return W.bumps_3d(np.asarray(xg) + x0, np.asarray(yg) + y0, zg, 0.0, TANK3_L,

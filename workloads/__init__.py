@@ -42,6 +42,8 @@ class Workload:
     nu_pre: int = 2
     nu_post: int = 2
     cheb_degree: int = 3
+    cheb_lo: float = 0.1              # Chebyshev interval [cheb_lo, cheb_hi] x lambda_hat
+    cheb_hi: float = 1.1
     kind: str = "tank"                # "manufactured" | "tank" | "tank3d"
     surface_seed: int = 7
     rhs_seed: int = 107
@@ -63,6 +65,12 @@ class Workload:
         return self.Nx * self.Nz * (self.Ny if self.dim == 3 else 1)
 
 
+# Chebyshev smoothing of the large tanks (1024 and 2048 x 16, P = 8; 64 x 64 x 8, P = 6) and of
+# the windows the learned stage is trained on: degree 6 on [0.02, 1.1] x lambda_hat (the c2 tank
+# keeps Chebyshev(3) on [0.1, 1.1])
+TANK_CHEB = dict(cheb_degree=6, cheb_lo=0.02, cheb_hi=1.1)
+
+
 def c1(P=4):
     return Workload("c1", 2, 8, 4, P, 2.0 * math.pi, orders=_orders(P), smoother="jacobi",
                     nu_pre=2, nu_post=2, kind="manufactured", tol=1e-12)
@@ -73,17 +81,17 @@ def c2():
 
 
 def c3():
-    return Workload("c3", 2, 2048, 16, 8, 25.6, orders=[8, 4, 2, 1])
+    return Workload("c3", 2, 2048, 16, 8, 25.6, orders=[8, 4, 2, 1], **TANK_CHEB)
 
 
 def c4(test_index=0):
     return Workload("c4", 2, 1024, 16, 8, 25.6, orders=[8, 4, 2, 1],
-                    surface_seed=1000 + test_index, rhs_seed=2000 + test_index)
+                    surface_seed=1000 + test_index, rhs_seed=2000 + test_index, **TANK_CHEB)
 
 
 def c5():
     return Workload("c5", 3, 64, 8, 6, 6.4, Ny=64, Ly=6.4, orders=[6, 3, 1], kind="tank3d",
-                    surface_seed=300, rhs_seed=301)
+                    surface_seed=300, rhs_seed=301, **TANK_CHEB)
 
 
 def tank(Nx, Nz, P, Lx=25.6, orders=None, name="tank", surface_seed=7, rhs_seed=107,
