@@ -576,7 +576,8 @@ def cpu_baseline(wl, tol):
     args = dict(dim=2, Nx=ncols, Nz=wl.Nz, Lx=Ls, h=full_h(xs + x0), eta=full_eta(xs + x0))
     t0 = time.perf_counter()
     H = pmg.Hierarchy(args, wl.orders, smoother="chebyshev", cheb_degree=wl.cheb_degree,
-                      cheb_lo=wl.cheb_lo, cheb_hi=wl.cheb_hi)
+                      cheb_lo=wl.cheb_lo, cheb_hi=wl.cheb_hi,
+                      cheb_degree_coarse=wl.cheb_degree_coarse or None)
     pmg.estimate_lambdas(H)
     t_setup = time.perf_counter() - t0
     L0 = H.levels[0]

@@ -86,7 +86,8 @@ typedef struct {
   int inner_prec;              /* SEM_F64 | SEM_F32 | SEM_F32_GBF16 | SEM_F32_GCOL          */
   int smoother;                /* SEM_SMOOTH_*                                               */
   int nu_pre, nu_post;         /* Jacobi and Schwarz sweeps                                 */
-  int cheb_degree;             /* Chebyshev degree (pre and post)                           */
+  int cheb_degree;             /* Chebyshev degree (pre and post) on the finest level, and on
+                                  the coarser levels unless cheb_degree_coarse is set          */
   double jacobi_omega;         /* damping, default 2/3                                      */
   double cheb_lo, cheb_hi;     /* Chebyshev interval as fractions of lambda_hat (0.1, 1.1)  */
   int outer;                   /* SEM_OUTER_FPCG | SEM_OUTER_PDC | SEM_OUTER_GMRES          */
@@ -131,6 +132,11 @@ typedef struct {
   int schwarz_overlap;         /* SEM_SMOOTH_SCHWARZ: node layers added to each element's
                                   subdomain across every face, 0..8 (default 0: the element
                                   blocks, neighbouring blocks sharing only face nodes).       */
+  int cheb_degree_coarse;      /* Chebyshev degree on every level between the finest and the
+                                  coarsest (0, default: cheb_degree).  The one-kernel smoothing
+                                  of a 2D coarse level holds its columns plus a halo of one
+                                  column per step in a workgroup, so a low degree there keeps
+                                  that form when the finest level takes a high one.           */
 } sem_mesh_desc;
 
 typedef struct {

@@ -175,7 +175,8 @@ class Hierarchy:
 
     def __init__(self, mesh_args, orders, smoother="chebyshev", nu_pre=2, nu_post=2,
                  cheb_degree=3, jacobi_omega=2.0 / 3.0, cheb_lo=0.1, cheb_hi=1.1,
-                 coarse_dense_max=1200, gstore=None, schwarz_overlap=0):
+                 coarse_dense_max=1200, gstore=None, schwarz_overlap=0,
+                 cheb_degree_coarse=None):
         """orders: level orders, fine to coarse; in 2D an entry may be a pair (P_x, P_sigma)
         (semi-coarsened levels), a plain P meaning (P, P).  gstore: storage precision of the
         geometric factors on every level above the coarsest (None / "f64", "f32", "bf16"); the
@@ -236,6 +237,7 @@ class Hierarchy:
         self.schwarz_overlap = int(schwarz_overlap)
         self.nu_pre, self.nu_post = nu_pre, nu_post
         self.cheb_degree = cheb_degree
+        self.cheb_degree_coarse = cheb_degree_coarse or cheb_degree   # levels 1 .. L-2
         self.omega = jacobi_omega
         self.cheb_lo, self.cheb_hi = cheb_lo, cheb_hi
 
@@ -280,7 +282,7 @@ class Hierarchy:
             return self.jacobi(l, b, x, self.nu_pre if pre else self.nu_post)
         if self.smoother == "asm":
             return self.schwarz_sweeps(l, b, x, self.nu_pre if pre else self.nu_post)
-        return self.chebyshev(l, b, x, self.cheb_degree)
+        return self.chebyshev(l, b, x, self.cheb_degree if l == 0 else self.cheb_degree_coarse)
 
     # ---- V-cycle -----------------------------------------------------------------------
     def restrict(self, l, r_fine):

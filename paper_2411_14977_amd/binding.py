@@ -37,7 +37,7 @@ class MeshDesc(ctypes.Structure):
         ("stream", ctypes.c_void_p), ("coarse_dense_max", ctypes.c_int),
         ("gmres_restart", ctypes.c_int), ("order_z", ctypes.c_int),
         ("level_order_z", ctypes.c_int * SEM_MAX_LEVELS), ("precond_still_water", ctypes.c_int),
-        ("schwarz_overlap", ctypes.c_int),
+        ("schwarz_overlap", ctypes.c_int), ("cheb_degree_coarse", ctypes.c_int),
     ]
 
 
@@ -486,7 +486,8 @@ class Solver:
                  smoother="chebyshev", nu_pre=2, nu_post=2, cheb_degree=3, jacobi_omega=2.0 / 3.0,
                  cheb_lo=0.1, cheb_hi=1.1, outer="fpcg", maxit=500, dirichlet=True,
                  lanczos_steps=20, lanczos_seed=12345, coarse_dense_max=1200, stream=None,
-                 gmres_restart=30, order_z=None, precond_still_water=False, schwarz_overlap=0):
+                 gmres_restart=30, order_z=None, precond_still_water=False, schwarz_overlap=0,
+                 cheb_degree_coarse=0):
         """order: GLL order (2D: along x); order_z: 2D order along sigma when it differs;
         levels: level orders, each an int or (with order_z) an (x, sigma) pair; None or []:
         the library's own hierarchy."""
@@ -500,6 +501,7 @@ class Solver:
             d.order_z = int(order_z)
         d.precond_still_water = 1 if precond_still_water else 0
         d.schwarz_overlap = int(schwarz_overlap)
+        d.cheb_degree_coarse = int(cheb_degree_coarse)
         if levels:
             d.nlevels = len(levels)
             for k, p in enumerate(levels):

@@ -24,7 +24,8 @@ def surface_samples(wl):
 def make_solver(wl, prec="f64", **kw):
     h, eta = surface_samples(wl)
     opts = dict(levels=wl.orders or None, prec=prec, smoother=wl.smoother, nu_pre=wl.nu_pre,
-                nu_post=wl.nu_post, cheb_degree=wl.cheb_degree, cheb_lo=wl.cheb_lo,
+                nu_post=wl.nu_post, cheb_degree=wl.cheb_degree,
+                cheb_degree_coarse=wl.cheb_degree_coarse, cheb_lo=wl.cheb_lo,
                 cheb_hi=wl.cheb_hi, order_z=wl.Pz)
     opts.update(kw)
     ne = (wl.Nx, wl.Ny if wl.dim == 3 else 1, wl.Nz)

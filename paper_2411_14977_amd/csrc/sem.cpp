@@ -612,6 +612,12 @@ void smooth_step(Ctx* c, int l, double cd, double cr, int store_d) {
                          semk::SU_AX, store_d, c->st));
 }
 
+// Chebyshev degree on level l (the finest, or every coarser level above the coarsest)
+int cheb_k(const Ctx* c, int l) {
+  const sem_mesh_desc& d = c->desc;
+  return (l > 0 && d.cheb_degree_coarse > 0) ? d.cheb_degree_coarse : d.cheb_degree;
+}
+
 // coefficient and d-store flag of the first post-smoothing step taken from a known residual
 // (x += cr dinv r, d = that step when more steps follow)
 void first_post_step(const Ctx* c, int l, double* cr, int* store_d) {
@@ -623,7 +629,7 @@ void first_post_step(const Ctx* c, int l, double* cr, int* store_d) {
   }
   const double lam = c->lev[l].lam;
   *cr = 1.0 / (0.5 * (d.cheb_hi * lam + d.cheb_lo * lam));
-  *store_d = d.cheb_degree > 1 ? 1 : 0;
+  *store_d = cheb_k(c, l) > 1 ? 1 : 0;
 }
 
 // pre- or post-smoothing on level l; resid (post-smoothing only): the residual of the current x,
@@ -693,7 +699,7 @@ void smooth(Ctx* c, int l, bool pre, const void* resid = nullptr, bool first_don
   const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
   const double sigma1 = theta / delta;
   double rho = 1.0 / sigma1;
-  const int k = d.cheb_degree;
+  const int k = cheb_k(c, l);
   const bool given = !pre && resid;
   int j0 = 1;
   if (!pre && !given) {
@@ -900,7 +906,7 @@ bool coarse_seq(const Ctx* c, int l, bool pre, semk::CoarseSeq* sq, int* applies
   const sem_mesh_desc& d = c->desc;
   const DLevel& L = c->lev[l];
   if (d.smoother == SEM_SMOOTH_CHEBYSHEV) {
-    const int k = d.cheb_degree;
+    const int k = cheb_k(c, l);
     if (k < 1 || k > semk::CO_MAXS) return false;
     const double a = d.cheb_lo * L.lam, b = d.cheb_hi * L.lam;
     const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
@@ -1622,7 +1628,8 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
   if (d->outer == SEM_OUTER_GMRES && (d->gmres_restart < 1 || d->gmres_restart > semk::KRY_MAX))
     throw ArgFail{"GMRES restart must be 1..64"};
   if (d->smoother == SEM_SMOOTH_CHEBYSHEV &&
-      (d->cheb_degree < 1 || !(d->cheb_hi > d->cheb_lo) || d->cheb_lo <= 0))
+      (d->cheb_degree < 1 || d->cheb_degree_coarse < 0 || !(d->cheb_hi > d->cheb_lo) ||
+       d->cheb_lo <= 0))
     throw ArgFail{"bad Chebyshev parameters"};
   if (d->smoother != SEM_SMOOTH_CHEBYSHEV && (d->nu_pre < 0 || d->nu_post < 0))
     throw ArgFail{"bad sweep counts"};

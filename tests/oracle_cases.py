@@ -50,7 +50,8 @@ def fine_mesh(wl, P=None):
 
 def hierarchy(wl, **kw):
     opts = dict(smoother=wl.smoother, nu_pre=wl.nu_pre, nu_post=wl.nu_post,
-                cheb_degree=wl.cheb_degree, cheb_lo=wl.cheb_lo, cheb_hi=wl.cheb_hi)
+                cheb_degree=wl.cheb_degree, cheb_lo=wl.cheb_lo, cheb_hi=wl.cheb_hi,
+                cheb_degree_coarse=wl.cheb_degree_coarse or None)
     opts.update(kw)
     orders = wl.orders if wl.orders else pmg.coarsen_orders_2d(wl.P, wl.pz)
     return pmg.Hierarchy(mesh_args(wl), orders, **opts)

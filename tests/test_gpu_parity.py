@@ -189,6 +189,24 @@ def test_vcycle(name):
     s.close()
 
 
+@pytest.mark.parametrize("name", ["tank8", "c2", "wide3"])
+@pytest.mark.parametrize("deg,deg_c", [(6, 3), (5, 2), (2, 6)])
+def test_vcycle_level_degrees(name, deg, deg_c):
+    """Chebyshev degree of the finest level and of the levels below it set apart
+    (cheb_degree_coarse): the V-cycle against the oracle's with the same degrees."""
+    wl = CASES[name]
+    H_ = oc.hierarchy(wl, cheb_degree=deg, cheb_degree_coarse=deg_c)
+    pmg.estimate_lambdas(H_)
+    s = lib_solver(name, cheb_degree=deg, cheb_degree_coarse=deg_c)
+    for l, L in enumerate(H_.levels[:-1]):
+        s.set_lambda(l, L.lam)
+    L0 = H_.levels[0]
+    r = W.random_vector(L0.N, 904)
+    r[L0.dn] = 0.0
+    assert rel(H(s.vcycle(T(r))), H_.vcycle(r)) < 1e-12
+    s.close()
+
+
 @pytest.mark.parametrize("name", ["c1", "ragged", "tank8", "c2"])
 def test_rhs_assembly(name):
     wl = CASES[name]

@@ -53,7 +53,8 @@ def args_with(wl, eta):
 
 def hierarchy_with(wl, eta, **kw):
     opts = dict(smoother=wl.smoother, nu_pre=wl.nu_pre, nu_post=wl.nu_post,
-                cheb_degree=wl.cheb_degree, cheb_lo=wl.cheb_lo, cheb_hi=wl.cheb_hi)
+                cheb_degree=wl.cheb_degree, cheb_lo=wl.cheb_lo, cheb_hi=wl.cheb_hi,
+                cheb_degree_coarse=wl.cheb_degree_coarse or None)
     opts.update(kw)
     return pmg.Hierarchy(args_with(wl, eta), wl.orders, **opts)
 

@@ -78,9 +78,9 @@ def test_vcycle_symmetric(smoother):
     np.linalg.cholesky(0.5 * (B + B.T)[np.ix_(free, free)])
 
 
-def _smoother_matrix(H, fn):
+def _smoother_matrix(H, fn, level=0):
     """Error propagation of a smoother: x_out = E x_in for b = 0."""
-    n = H.levels[0].N
+    n = H.levels[level].N
     E = np.zeros((n, n))
     for k in range(n):
         e = np.zeros(n)
@@ -107,6 +107,25 @@ def test_chebyshev_is_the_scaled_chebyshev_polynomial():
     for j in range(lam.size):
         expect = Tk((theta - lam[j]) / delta) / Tk(theta / delta)
         assert np.abs(E @ V[:, j] - expect * V[:, j]).max() < 1e-9
+
+
+def test_level_degrees_in_the_smoother():
+    """With a coarse degree set, the smoother of every level between the finest and the
+    coarsest is that degree's scaled Chebyshev polynomial on each eigenvector (the finest keeps
+    its own degree)."""
+    wl, H = _tank(Nx=4, Nz=2, P=4, cheb_degree=5, cheb_degree_coarse=2)
+    for l, k in ((0, 5), (1, 2)):
+        L = H.levels[l]
+        L.lam = 2.1
+        E = _smoother_matrix(H, lambda b, x: H.smooth(l, b, x, pre=True), level=l)
+        lam, V = np.linalg.eig(np.diag(L.dinv) @ L.A.toarray())
+        lam, V = lam.real, V.real
+        a, b = H.cheb_lo * L.lam, H.cheb_hi * L.lam
+        theta, delta = (a + b) / 2, (b - a) / 2
+        Tk = npcheb.Chebyshev.basis(k)
+        for j in range(lam.size):
+            expect = Tk((theta - lam[j]) / delta) / Tk(theta / delta)
+            assert np.abs(E @ V[:, j] - expect * V[:, j]).max() < 1e-9, (l, j)
 
 
 def test_jacobi_error_propagation():

@@ -42,6 +42,7 @@ class Workload:
     nu_pre: int = 2
     nu_post: int = 2
     cheb_degree: int = 3
+    cheb_degree_coarse: int = 0       # Chebyshev degree below the finest level (0: cheb_degree)
     cheb_lo: float = 0.1              # Chebyshev interval [cheb_lo, cheb_hi] x lambda_hat
     cheb_hi: float = 1.1
     kind: str = "tank"                # "manufactured" | "tank" | "tank3d"
