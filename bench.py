@@ -11,7 +11,8 @@ the training time is reported).  The stage's three placements (after pre-smoothi
 post-smoothing, both) are timed and the fastest is the headline; beside it the same solver
 without the stage (with the break-even cost of the stage) and with each way of holding the inner
 factors, the plain FP64 p-multigrid, per-cycle
-residual reduction in defect-correction (PDC) mode with and without the stage, iterations and
+residual reduction in defect-correction (PDC) mode with and without the stage, the plain
+smoother's verdict on the stage (residual reduction per cycle and per unit of time), iterations and
 times on 20 unseen test surfaces (the oracle solves three of them on the host cores, in child
 processes, and checks the GPU's pressure), the roofline of the dominant kernel (the fused
 operator + smoother step; HBM-resident timing with rotated buffers, the cache-resident figure
@@ -718,6 +719,19 @@ def main():
             "break_even_stage_us_per_iteration":
                 (t_nl - per_it_plain * info.iters) / info.iters * 1e6 if info.iters else None}
 
+    # the plain smoother as the judge of the stage: residual reduction per cycle and per unit of
+    # time with the stage off and on (sem_learned_judge); where it switches the stage off, the
+    # solve with its verdict is timed beside the headline (which keeps the stage on)
+    judge = None
+    if use_learned:
+        judge = s.learned_judge(rhs, cycles=6)
+        log(f"[bench] judge: {judge}")
+        if not judge["enabled"]:
+            tj, ij, _ = time_solves(s, rhs, args.steps, args.warmup, args.tol)
+            judge["solve_with_verdict"] = {"stage": "off", "ms_per_solve": tj * 1e3,
+                                           "iters": ij.iters, "rel_res": ij.rel_res}
+        s.learned_enable(mode)
+
     # whole solve: the sum of every launch's algorithmic bytes over one solve (the same solve
     # issued without graphs) against the timed solve's duration
     xb = torch.zeros_like(rhs)
@@ -891,6 +905,7 @@ def main():
            "plain_fp64": plain,
            "speedup_vs_fp64": (plain["ms_per_solve"] / (t * 1e3)) if plain else None,
            "learned_placements": placements, "learned_break_even": breakeven,
+           "learned_judge": judge,
            "training": train_rec, "pdc_rate": pdc, "unseen_surfaces": surf,
            "schwarz_smoother": schwarz, "paper_context": context, "c3_error_table": c3,
            "c5_series": c5, "stage_loop": stage_loop,

@@ -448,6 +448,24 @@ sem_status sem_learned_stage(sem_ctx *ctx, const double *b, double *x, int *acce
  * reading.  SEM_ERR_STATE if no network was ever loaded. */
 sem_status sem_learned_skips(sem_ctx *ctx, int *skips, int reset);
 
+/* The plain smoother as the judge of the learned stage, by residual reduction per cycle and
+ * per unit of time: for A x = rhs (rhs: device FP64, n_global, as for sem_poisson_solve) the
+ * call runs defect-correction cycles x += B(rhs - A x) from x = 0, with the stage off and then
+ * on (its placement from sem_learned_load / sem_learned_enable, after pre-smoothing if it is
+ * off), one cycle untimed and `cycles` timed (1..100) each, every cycle one captured HIP graph
+ * timed with HIP events on the library stream.  rho = (||r_end|| / ||r_start||)^(1/cycles)
+ * over the timed cycles, ms the time per cycle.  The stage is left enabled iff it reduces the
+ * residual faster per unit of time (rho_learned < 1 and ln(rho_learned) / ms_learned <
+ * ln(rho_plain) / ms_plain), else disabled (as sem_learned_enable(ctx, 0)); the rejection
+ * counter is reset.  out (may be NULL) receives both measurements and the decision.
+ * SEM_ERR_STATE without a loaded network. */
+typedef struct {
+  double rho_plain, rho_learned;   /* residual reduction per cycle, stage off / on       */
+  double ms_plain, ms_learned;     /* milliseconds per cycle, stage off / on             */
+  int enabled;                     /* 1: the stage stays on                              */
+} sem_judge_result;
+sem_status sem_learned_judge(sem_ctx *ctx, const double *rhs, int cycles, sem_judge_result *out);
+
 /* Text of the last error on this context ("" if none).  Valid until the next call. */
 const char *sem_last_error(const sem_ctx *ctx);
 

@@ -41,6 +41,12 @@ class MeshDesc(ctypes.Structure):
     ]
 
 
+class JudgeResult(ctypes.Structure):
+    _fields_ = [("rho_plain", ctypes.c_double), ("rho_learned", ctypes.c_double),
+                ("ms_plain", ctypes.c_double), ("ms_learned", ctypes.c_double),
+                ("enabled", ctypes.c_int)]
+
+
 class TrainCfg(ctypes.Structure):
     _fields_ = [("epochs", ctypes.c_int), ("batch", ctypes.c_int), ("lr", ctypes.c_float),
                 ("val_frac", ctypes.c_float), ("seed", ctypes.c_ulonglong),
@@ -128,6 +134,7 @@ def lib():
         "sem_learned_enable": (ctypes.c_int, [vp, ip]),
         "sem_learned_stage": (ctypes.c_int, [vp, dp, dp, ctypes.POINTER(ctypes.c_int)]),
         "sem_learned_skips": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_int), ip]),
+        "sem_learned_judge": (ctypes.c_int, [vp, dp, ip, ctypes.POINTER(JudgeResult)]),
         "sem_launch_shape": (ctypes.c_int, [vp, ip, ctypes.POINTER(ctypes.c_int),
                                             ctypes.POINTER(ctypes.c_int)]),
         "sem_mesh_mixed_stage": (ctypes.c_int, [vp, ctypes.POINTER(ctypes.c_double)]),
@@ -440,6 +447,15 @@ def sem_learned_stage(ctx, b, x):
     return bool(acc.value)
 
 
+def sem_learned_judge(ctx, rhs, cycles=6):
+    """The plain smoother's verdict on the learned stage (see sem.h): a dict of the per-cycle
+    residual reductions and times with the stage off and on, and whether it stays on."""
+    r = JudgeResult()
+    _check(ctx, lib().sem_learned_judge(ctx, _ptr(rhs), int(cycles), ctypes.byref(r)))
+    return {"rho_plain": r.rho_plain, "rho_learned": r.rho_learned, "ms_plain": r.ms_plain,
+            "ms_learned": r.ms_learned, "enabled": bool(r.enabled)}
+
+
 def sem_learned_skips(ctx, reset=False):
     k = ctypes.c_int()
     _check(ctx, lib().sem_learned_skips(ctx, ctypes.byref(k), 1 if reset else 0))
@@ -600,6 +616,9 @@ class Solver:
 
     def learned_enable(self, enable):
         sem_learned_enable(self.ctx, enable)
+
+    def learned_judge(self, rhs, cycles=6):
+        return sem_learned_judge(self.ctx, rhs, cycles)
 
     def smooth(self, level, b, x=None, pre=True):
         x = self._new(self.level(level)[1]) if x is None else x

@@ -3185,6 +3185,75 @@ sem_status sem_learned_enable(sem_ctx* ctx, int enable) {
   });
 }
 
+sem_status sem_learned_judge(sem_ctx* ctx, const double* rhs, int cycles, sem_judge_result* out) {
+  Ctx* c = C(ctx);
+  return guarded(c, [&]() {
+    if (!c->stage_alloc || c->stage_blob.empty()) return SEM_ERR_STATE;
+    if (!rhs) throw ArgFail{"null right-hand side"};
+    if (cycles < 1 || cycles > 100) throw ArgFail{"cycles must be 1..100"};
+    enter(c);
+    DLevel& L0 = c->lev[0];
+    const unsigned N = L0.N;
+    const int mode = c->stage.enabled ? c->stage_mode : 1;
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    HK(hipEventCreate(&t0));
+    HK(hipEventCreate(&t1));
+    double rho[2] = {1.0, 1.0}, ms[2] = {0.0, 0.0};
+    hipGraphExec_t g = nullptr;
+    try {
+      for (int on = 0; on < 2; ++on) {
+        c->stage.enabled = on != 0;
+        if (on) c->stage_mode = mode;
+        drop_graphs(c);
+        HK(hipMemcpyAsync(c->bo, rhs, (size_t)N * 8, hipMemcpyDeviceToDevice, c->st));
+        HK(hipMemsetAsync(c->xo, 0, (size_t)N * 8, c->st));
+        HK(semk::copy_top(c->xo, c->bo, L0.nxn * L0.nyn, L0.nzn, c->st));
+        apply_outer(c, c->xo, c->masked);
+        HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn,
+                         L0.P, c->st));
+        g = capture(c, [&]() { pdc_iteration(c); });
+        HK(hipGraphLaunch(g, c->st));  // the untimed cycle
+        double s0[3], s1[3];
+        read_sums(c, s0);
+        HK(hipEventRecord(t0, c->st));
+        for (int k = 0; k < cycles; ++k) HK(hipGraphLaunch(g, c->st));
+        HK(hipEventRecord(t1, c->st));
+        read_sums(c, s1);
+        float el = 0.f;
+        HK(hipEventElapsedTime(&el, t0, t1));
+        HK(hipGraphExecDestroy(g));
+        g = nullptr;
+        ms[on] = (double)el / cycles;
+        rho[on] = (s0[0] > 0.0 && std::isfinite(s1[0]))
+                      ? std::pow(std::sqrt(s1[0] / s0[0]), 1.0 / cycles) : 1.0;
+      }
+    } catch (...) {
+      if (g) (void)hipGraphExecDestroy(g);
+      (void)hipEventDestroy(t0);
+      (void)hipEventDestroy(t1);
+      throw;
+    }
+    HK(hipEventDestroy(t0));
+    HK(hipEventDestroy(t1));
+    const bool keep = rho[1] < 1.0 && rho[0] > 0.0 && ms[0] > 0.0 && ms[1] > 0.0 &&
+                      (rho[0] >= 1.0 || std::log(rho[1]) / ms[1] < std::log(rho[0]) / ms[0]);
+    c->stage.enabled = keep;
+    c->stage_mode = mode;
+    drop_graphs(c);
+    HK(hipMemsetAsync(c->stage.skips, 0, sizeof(int), c->st));
+    leave(c);
+    HK(hipStreamSynchronize(c->st));
+    if (out) {
+      out->rho_plain = rho[0];
+      out->rho_learned = rho[1];
+      out->ms_plain = ms[0];
+      out->ms_learned = ms[1];
+      out->enabled = keep ? 1 : 0;
+    }
+    return SEM_OK;
+  });
+}
+
 sem_status sem_learned_skips(sem_ctx* ctx, int* skips, int reset) {
   Ctx* c = C(ctx);
   return guarded(c, [&]() {

@@ -360,3 +360,74 @@ def test_stage_switched_off_after_three_rejected_iterations(mode):
         assert i1.learned_skips >= 3 * per
         assert i1.iters == i0.iters and torch.equal(x0, x1)
     s.close()
+
+
+# ---- the plain smoother as the judge of the stage (sem_learned_judge) -------------------------
+def _judge_case(prec):
+    wl = W.tank(16, 4, 8, Lx=1.6, name="tank8")
+    Ho = oc.hierarchy(wl)
+    pmg.estimate_lambdas(Ho)
+    s = cases.make_solver(wl, prec=prec)
+    for l, L in enumerate(Ho.levels[:-1]):
+        s.set_lambda(l, L.lam)
+    m = Ho.levels[0].mesh
+    return wl, Ho, s, oc.rhs(wl, m)
+
+
+def test_judge_rates_match_the_oracle_defect_correction():
+    """rho of the plain cycles equals the oracle's defect-correction rate over the same cycles
+    (one untimed, then `cycles` timed) in FP64; a network every judge rejects (zero output)
+    leaves the rate unchanged, costs time, and is switched off."""
+    wl, Ho, s, b = _judge_case("f64")
+    L0 = Ho.levels[0]
+    x = np.zeros(L0.N)
+    x[L0.dn] = b[L0.dn]
+    norms = []
+    for _ in range(5):
+        r = b - L0.A @ x
+        norms.append(np.linalg.norm(r))
+        x = x + Ho.vcycle(r)
+    norms.append(np.linalg.norm(b - L0.A @ x))
+    rho_ref = (norms[5] / norms[1]) ** (1.0 / 4)
+    p = {k: np.zeros_like(v) for k, v in params(1).items()}
+    s.learned_load(blob(p), enable=1)
+    res = s.learned_judge(T64(b), cycles=4)
+    print(f"[gpu] judge (zero network): {res}, oracle rho {rho_ref:.6f}", flush=True)
+    assert abs(res["rho_plain"] - rho_ref) <= 1e-9 * rho_ref
+    assert abs(res["rho_learned"] - res["rho_plain"]) <= 1e-12 * rho_ref
+    assert res["ms_plain"] > 0 and res["ms_learned"] > 0
+    assert res["enabled"] is False
+    # the stage stays off: a solve rejects nothing
+    s.solve(T64(b), tol=1e-10)
+    assert B.sem_learned_skips(s.ctx) == 0
+    s.close()
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_judge_decision_follows_its_measurements(prec):
+    """With a network that passes the scaled residual through (a Jacobi-like element step) the
+    decision is the rule applied to the returned numbers, and the stage state follows it."""
+    wl, Ho, s, b = _judge_case(prec)
+    n = (wl.P + 1) ** 2
+    pz = params_p(wl.P, 5, scale=0.0, bias=0.0)
+    # GELU(u) - GELU(-u) = u: hidden pair (+u, -u) and output difference, per node
+    W1 = np.zeros((5 * n, 128)); W2 = np.zeros((128, 128)); W3 = np.zeros((128, n))
+    for j in range(min(n, 64)):
+        W1[j, 2 * j], W1[j, 2 * j + 1] = 1.0, -1.0
+        W2[2 * j, 2 * j], W2[2 * j + 1, 2 * j + 1] = 1.0, 1.0
+        W3[2 * j, j], W3[2 * j + 1, j] = 1.0, -1.0
+    pz.update(W1=W1, W2=W2, W3=W3)
+    s.learned_load(B.blob_pack(5 * n, n, pz["W1"], pz["b1"], pz["W2"], pz["b2"], pz["W3"],
+                               pz["b3"]), enable=1)
+    res = s.learned_judge(T64(b), cycles=5)
+    print(f"[gpu] judge ({prec}): {res}", flush=True)
+    import math
+    rule = (res["rho_learned"] < 1.0 and math.log(res["rho_learned"]) / res["ms_learned"]
+            < math.log(res["rho_plain"]) / res["ms_plain"])
+    assert res["enabled"] == rule
+    assert 0.0 < res["rho_plain"] < 1.0 and 0.0 < res["rho_learned"] < 1.0
+    # the decision holds for the next solve: skips are counted only with the stage on
+    B.sem_learned_skips(s.ctx, reset=True)
+    x, info, _ = s.solve(T64(b), tol=1e-10)
+    assert info.rel_res <= 1e-10
+    s.close()
