@@ -222,12 +222,25 @@ struct CoarsePlan {
   int W = 0, HL = 0, nslot = 0;
   size_t smem = 0;
 };
-CoarsePlan coarse2d_plan(int P, int PC, int Nz, bool dbl, bool pre, int applies);
+// What a coarse-level launch does besides its smoothing steps: CO_FROM_X (pre family) start
+// from x instead of x = 0; CO_RESTRICT (pre family) end with the residual and its restriction
+// into rc; CO_PROLONG (post family) start by adding the prolongation of ec to x.  din (optional)
+// holds the Chebyshev direction d at the start (a sequence continued from an earlier launch);
+// dout (optional) receives d of the owned columns at the end.  A sequence too long for one
+// window runs as two launches: the first writes x and d, the second continues from them.
+constexpr int CO_FROM_X = 1, CO_RESTRICT = 2, CO_PROLONG = 4;
+struct CoarseIO {
+  const void* din = nullptr;
+  void* dout = nullptr;
+  int flags = 0;
+};
+// window of a launch with `applies` operator applies and the given CO_RESTRICT / CO_PROLONG
+CoarsePlan coarse2d_plan(int P, int PC, int Nz, bool dbl, int flags, int applies);
 bool coarse2d_supported(int P, int PC);
 hipError_t coarse2d(bool pre, const CoarsePlan& pl, int P, int PC, bool dbl, GType gt, bool dbl_c,
                     const void* x, void* xo, const void* b, const void* dinv, const void* G,
                     const void* ec, void* rc, const double* J, int Nx, int Nz, int masked,
-                    const CoarseSeq& sq, hipStream_t st);
+                    const CoarseSeq& sq, hipStream_t st, CoarseIO io);
 
 // ---- exact coarse solve (block cyclic reduction, FP64, in place on b, result in x) ---------
 // unknown r of block blk sits at blk * bstride + r + r / nzf (nzf = free nodes per line)

@@ -2666,7 +2666,7 @@ __global__ __launch_bounds__(1024) void k_coarse2d(const T* __restrict__ x, T* _
                                                    const TC* __restrict__ ec, TC* __restrict__ rc,
                                                    const double* __restrict__ Jg, int Nx, int Nz,
                                                    int masked, int W, int HL, int nslot,
-                                                   CoarseSeq sq) {
+                                                   CoarseSeq sq, CoarseIO io) {
   constexpr int NP = P + 1, NPC = PC + 1;
   constexpr int V = lds_vec<T>();
   constexpr int JP = (NP * NPC + V - 1) / V * V;
@@ -2688,8 +2688,13 @@ __global__ __launch_bounds__(1024) void k_coarse2d(const T* __restrict__ x, T* _
   T* slots = WX + (size_t)(nslot * P + 1) * nzp;
   T* base = slots + (size_t)(valid ? cs : 0) * slot;   // this column's apply space
   const size_t g0 = (size_t)(valid ? ex : 0) * P * nzn + t;
+  const bool from_x = !PRE || (io.flags & CO_FROM_X);
+  const bool do_restrict = PRE && (io.flags & CO_RESTRICT);
+  const bool do_prolong = !PRE && (io.flags & CO_PROLONG);
+  const T* din = static_cast<const T*>(io.din);
+  T* dout = static_cast<T*>(io.dout);
 
-  // every global load first: factors, b, dinv (and x, the coarse correction for POST)
+  // every global load first: factors, b, dinv (and x, d, the coarse correction when used)
   T g[3][NP], xr[NP], dr[NP], br[NP], di[NP];
   if (valid) load_g2d<P, T, TG>(G, ex, nthr, t, g);
 #pragma unroll
@@ -2701,21 +2706,22 @@ __global__ __launch_bounds__(1024) void k_coarse2d(const T* __restrict__ x, T* _
     if (nodes && l < nl) {
       br[l] = b[g0 + (size_t)l * nzn];
       di[l] = dinv[g0 + (size_t)l * nzn];
-      if constexpr (!PRE) xr[l] = x[g0 + (size_t)l * nzn];
+      if (from_x) xr[l] = x[g0 + (size_t)l * nzn];
+      if (din) dr[l] = din[g0 + (size_t)l * nzn];
     }
   }
   for (int k = threadIdx.x; k < NP * NPC; k += blockDim.x) sJ[k] = (T)Jg[k];
   for (int k = threadIdx.x; k < (nslot * P + 1) * nzp; k += blockDim.x) WX[k] = (T)0;
   T* sce = base;                 // POST: coarse lines of the column [NPC][nzc]
   T* stv = base + NPC * nzc;     // POST: interpolated along z [NPC][nzn]
-  if constexpr (!PRE) {
+  if (do_prolong) {
     if (valid) {
       const size_t cb = (size_t)ex * PC * nzc;
       for (int k = t; k < NPC * nzc; k += nthr) sce[k] = (T)ec[cb + k];
     }
   }
   __syncthreads();
-  if constexpr (!PRE) {  // x += P ec on the window: along z, then along x
+  if (do_prolong) {  // x += P ec on the window: along z, then along x (uniform branch)
     if (valid) {
       for (int k = t; k < NPC * nzn; k += nthr) {
         const int kc = k / nzn, izf = k - kc * nzn;
@@ -2782,7 +2788,7 @@ __global__ __launch_bounds__(1024) void k_coarse2d(const T* __restrict__ x, T* _
     T ax[NP];
 #pragma unroll
     for (int l = 0; l < NP; ++l) ax[l] = 0;
-    if (!(PRE && st == 0)) apply(ax);  // PRE starts from x = 0: A x = 0
+    if (!(st == 0 && !from_x)) apply(ax);  // from x = 0: A x = 0
     if (nodes) {
 #pragma unroll
       for (int l = 0; l < NP; ++l) {
@@ -2796,7 +2802,7 @@ __global__ __launch_bounds__(1024) void k_coarse2d(const T* __restrict__ x, T* _
     }
   }
 
-  if constexpr (PRE) {
+  if (do_restrict) {
     // residual of the smoothed x, into WX (lines of each column), then its restriction onto
     // the owned coarse lines: along x first, then along z
     T ax[NP];
@@ -2833,34 +2839,34 @@ __global__ __launch_bounds__(1024) void k_coarse2d(const T* __restrict__ x, T* _
         rc[(size_t)(ex * PC + kc) * nzc + izc] = (TC)s;
       }
     }
-    if (owned && t < nzn) {
+  }
+  if (owned && t < nzn) {
 #pragma unroll
-      for (int l = 0; l < NP; ++l)
-        if (l < nl) xo[g0 + (size_t)l * nzn] = xr[l];
-    }
-  } else {
-    if (owned && t < nzn) {
-#pragma unroll
-      for (int l = 0; l < NP; ++l)
-        if (l < nl) xo[g0 + (size_t)l * nzn] = xr[l];
+    for (int l = 0; l < NP; ++l) {
+      if (l < nl) {
+        xo[g0 + (size_t)l * nzn] = xr[l];
+        if (dout) dout[g0 + (size_t)l * nzn] = dr[l];
+      }
     }
   }
 }
 
 // window shape of a coarse-level kernel: columns per workgroup and margins, 0 when it does not
 // fit one workgroup (1024 threads) or its LDS
-CoarsePlan coarse2d_plan(int P, int PC, int Nz, bool dbl, bool pre, int applies) {
+CoarsePlan coarse2d_plan(int P, int PC, int Nz, bool dbl, int flags, int applies) {
   CoarsePlan pl;
   const int nthr = (P + 1) * Nz;
   const int V = dbl ? 2 : 4;
   const int nzn = Nz * P + 1, nzc = Nz * PC + 1;
   const int nzp = (nzn + V - 1) / V * V;
-  const int HL = applies + (pre ? 1 : 0), HR = applies;
+  const bool rs = (flags & CO_RESTRICT) != 0, pr = (flags & CO_PROLONG) != 0;
+  const int HL = applies + (rs ? 1 : 0), HR = applies;
   const int maxs = 1024 / nthr;
   const int W = maxs - HL - HR;
   if (W < 1) return pl;
   const size_t slot = slot2d_elems<size_t>(P + 1, Nz, nzp, V);
-  const size_t scratch = pre ? (size_t)(PC + 1) * nzn : (size_t)(PC + 1) * (nzc + nzn);
+  const size_t scratch = std::max(rs ? (size_t)(PC + 1) * nzn : 0,
+                                  pr ? (size_t)(PC + 1) * (nzc + nzn) : 0);
   if (scratch > slot) return pl;
   const int nslot = W + HL + HR;
   const size_t JP = ((size_t)(P + 1) * (PC + 1) + V - 1) / V * V;
@@ -2878,7 +2884,7 @@ template <int P, int PC, typename T, typename TG, typename TC, bool PRE>
 static hipError_t coarse2d_t(const CoarsePlan& pl, const void* x, void* xo, const void* b,
                              const void* dinv, const void* G, const void* ec, void* rc,
                              const double* J, int Nx, int Nz, int masked, const CoarseSeq& sq,
-                             hipStream_t st) {
+                             hipStream_t st, CoarseIO io) {
   const hipError_t e = allow_lds(k_coarse2d<P, PC, T, TG, TC, PRE>, pl.smem);
   if (e != hipSuccess) return e;
   const unsigned blocks = (unsigned)((Nx + pl.W - 1) / pl.W);
@@ -2886,7 +2892,7 @@ static hipError_t coarse2d_t(const CoarsePlan& pl, const void* x, void* xo, cons
   hipLaunchKernelGGL((k_coarse2d<P, PC, T, TG, TC, PRE>), dim3(blocks), dim3(pl.nslot * nthr),
                      pl.smem, st, (const T*)x, (T*)xo, (const T*)b, (const T*)dinv,
                      (const TG*)G, (const TC*)ec, (TC*)rc, J, Nx, Nz, masked, pl.W, pl.HL,
-                     pl.nslot, sq);
+                     pl.nslot, sq, io);
   return hipGetLastError();
 }
 
@@ -2894,32 +2900,32 @@ template <int P, int PC, bool PRE>
 static hipError_t coarse2d_ty(const CoarsePlan& pl, bool dbl, GType gt, bool dbl_c, const void* x,
                               void* xo, const void* b, const void* dinv, const void* G,
                               const void* ec, void* rc, const double* J, int Nx, int Nz,
-                              int masked, const CoarseSeq& sq, hipStream_t st) {
+                              int masked, const CoarseSeq& sq, hipStream_t st, CoarseIO io) {
   if (gt == G_COL64) {
     if (dbl)
       return coarse2d_t<P, PC, double, ColGeo64, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J,
-                                                              Nx, Nz, masked, sq, st);
+                                                              Nx, Nz, masked, sq, st, io);
     if (dbl_c)
       return coarse2d_t<P, PC, float, ColGeo64, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J,
-                                                             Nx, Nz, masked, sq, st);
+                                                             Nx, Nz, masked, sq, st, io);
     return coarse2d_t<P, PC, float, ColGeo64, float, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx,
-                                                          Nz, masked, sq, st);
+                                                          Nz, masked, sq, st, io);
   }
   if (dbl)
     return coarse2d_t<P, PC, double, double, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx,
-                                                          Nz, masked, sq, st);
+                                                          Nz, masked, sq, st, io);
   if (gt == G_BF16) {
     if (dbl_c)
       return coarse2d_t<P, PC, float, uint16_t, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J,
-                                                             Nx, Nz, masked, sq, st);
+                                                             Nx, Nz, masked, sq, st, io);
     return coarse2d_t<P, PC, float, uint16_t, float, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx,
-                                                          Nz, masked, sq, st);
+                                                          Nz, masked, sq, st, io);
   }
   if (dbl_c)
     return coarse2d_t<P, PC, float, float, double, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx, Nz,
-                                                        masked, sq, st);
+                                                        masked, sq, st, io);
   return coarse2d_t<P, PC, float, float, float, PRE>(pl, x, xo, b, dinv, G, ec, rc, J, Nx, Nz,
-                                                     masked, sq, st);
+                                                     masked, sq, st, io);
 }
 
 bool coarse2d_supported(int P, int PC) {
@@ -2930,16 +2936,21 @@ bool coarse2d_supported(int P, int PC) {
 hipError_t coarse2d(bool pre, const CoarsePlan& pl, int P, int PC, bool dbl, GType gt, bool dbl_c,
                     const void* x, void* xo, const void* b, const void* dinv, const void* G,
                     const void* ec, void* rc, const double* J, int Nx, int Nz, int masked,
-                    const CoarseSeq& sq, hipStream_t st) {
-  acct_add(vsz(dbl) * nodes2(P, Nx, Nz) * (pre ? 3 : 4) + vsz(dbl_c) * nodes2(PC, Nx, Nz) +
-           gbytes2(gt, P, Nx, Nz));
+                    const CoarseSeq& sq, hipStream_t st, CoarseIO io) {
+  {
+    const bool from_x = !pre || (io.flags & CO_FROM_X);
+    const bool coarse = pre ? (io.flags & CO_RESTRICT) : (io.flags & CO_PROLONG);
+    const double nv = 3 + (from_x ? 1 : 0) + (io.din ? 1 : 0) + (io.dout ? 1 : 0);
+    acct_add(vsz(dbl) * nodes2(P, Nx, Nz) * nv + (coarse ? vsz(dbl_c) * nodes2(PC, Nx, Nz) : 0) +
+             gbytes2(gt, P, Nx, Nz));
+  }
   if (pl.W < 1 || sq.ns < 1 || sq.ns > CO_MAXS) return hipErrorInvalidValue;
 #define SEM_CO(a, c)                                                                            \
   if (P == a && PC == c)                                                                        \
     return pre ? coarse2d_ty<a, c, true>(pl, dbl, gt, dbl_c, x, xo, b, dinv, G, ec, rc, J, Nx,  \
-                                         Nz, masked, sq, st)                                    \
+                                         Nz, masked, sq, st, io)                                \
                : coarse2d_ty<a, c, false>(pl, dbl, gt, dbl_c, x, xo, b, dinv, G, ec, rc, J, Nx, \
-                                          Nz, masked, sq, st);
+                                          Nz, masked, sq, st, io);
   SEM_CO(4, 2) SEM_CO(4, 1) SEM_CO(3, 2) SEM_CO(3, 1) SEM_CO(2, 1)
 #undef SEM_CO
   return hipErrorInvalidValue;

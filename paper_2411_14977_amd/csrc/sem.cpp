@@ -58,6 +58,10 @@ struct DLevel {
   void* xalt = nullptr;
   // 2D coarse levels: the pre- and post-smoothing sequences as one kernel each (W = 0: no)
   semk::CoarsePlan cpre, cpost;
+  // sequences too long for one window: the second launch's window and the steps in the first
+  // (0: one launch)
+  semk::CoarsePlan cpre2, cpost2;
+  int cpre_k1 = 0, cpost_k1 = 0;
   // Schwarz smoother: inverses of the element blocks [E][n][n] and the element results [E][n];
   // with asm_box, of the box subdomains (overlap or 3D) [E][nmax^2] and [E][nmax]
   void *Ainv_s = nullptr, *Zs = nullptr;
@@ -948,12 +952,48 @@ bool coarse_fused(Ctx* c, int l, bool pre) {
   int applies = 0;
   if (!coarse_seq(c, l, pre, &sq, &applies)) return false;
   DLevel& C = c->lev[l + 1];
+  const int k1 = pre ? L.cpre_k1 : L.cpost_k1;
+  if (k1 == 0) {
+    semk::CoarseIO io;
+    io.flags = pre ? semk::CO_RESTRICT : semk::CO_PROLONG;
+    if (pre) {
+      HK(semk::coarse2d(true, pl, L.P, C.P, L.dbl, L.gt, C.dbl, nullptr, L.x, L.b, L.dinv, L.G,
+                        nullptr, C.b, L.J, L.Nx, L.Nz, c->masked, sq, c->st, io));
+    } else {
+      HK(semk::coarse2d(false, pl, L.P, C.P, L.dbl, L.gt, C.dbl, L.x, L.xalt, L.b, L.dinv, L.G,
+                        C.x, nullptr, L.J, L.Nx, L.Nz, c->masked, sq, c->st, io));
+      std::swap(L.x, L.xalt);
+    }
+    return true;
+  }
+  // two launches: steps 0 .. k1-1 (x and d written), then k1 .. ns-1 continuing from them
+  semk::CoarseSeq s1, s2;
+  s1.ns = k1;
+  s2.ns = sq.ns - k1;
+  for (int j = 0; j < sq.ns; ++j) {
+    semk::CoarseSeq& t = j < k1 ? s1 : s2;
+    const int i = j < k1 ? j : j - k1;
+    t.cd[i] = sq.cd[j];
+    t.cr[i] = sq.cr[j];
+  }
+  const semk::CoarsePlan& pl2 = pre ? L.cpre2 : L.cpost2;
+  semk::CoarseIO first, second;
+  first.dout = L.d;
+  second.din = L.d;
   if (pre) {
+    second.flags = semk::CO_FROM_X | semk::CO_RESTRICT;
     HK(semk::coarse2d(true, pl, L.P, C.P, L.dbl, L.gt, C.dbl, nullptr, L.x, L.b, L.dinv, L.G,
-                      nullptr, C.b, L.J, L.Nx, L.Nz, c->masked, sq, c->st));
+                      nullptr, nullptr, L.J, L.Nx, L.Nz, c->masked, s1, c->st, first));
+    HK(semk::coarse2d(true, pl2, L.P, C.P, L.dbl, L.gt, C.dbl, L.x, L.xalt, L.b, L.dinv, L.G,
+                      nullptr, C.b, L.J, L.Nx, L.Nz, c->masked, s2, c->st, second));
+    std::swap(L.x, L.xalt);
   } else {
+    first.flags = semk::CO_PROLONG;
     HK(semk::coarse2d(false, pl, L.P, C.P, L.dbl, L.gt, C.dbl, L.x, L.xalt, L.b, L.dinv, L.G,
-                      C.x, nullptr, L.J, L.Nx, L.Nz, c->masked, sq, c->st));
+                      C.x, nullptr, L.J, L.Nx, L.Nz, c->masked, s1, c->st, first));
+    std::swap(L.x, L.xalt);
+    HK(semk::coarse2d(false, pl2, L.P, C.P, L.dbl, L.gt, C.dbl, L.x, L.xalt, L.b, L.dinv, L.G,
+                      nullptr, nullptr, L.J, L.Nx, L.Nz, c->masked, s2, c->st, second));
     std::swap(L.x, L.xalt);
   }
   return true;
@@ -1803,9 +1843,51 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
       if (!L.xalt || L.axis >= 0 || C.rect || !semk::coarse2d_supported(L.P, C.P)) continue;
       semk::CoarseSeq sq;
       int apre = 0, apost = 0;
-      if (!coarse_seq(c, l, true, &sq, &apre) || !coarse_seq(c, l, false, &sq, &apost)) continue;
-      L.cpre = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, true, apre);
-      L.cpost = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, false, apost);
+      if (!coarse_seq(c, l, true, &sq, &apre)) continue;
+      const int npre = sq.ns;
+      if (!coarse_seq(c, l, false, &sq, &apost)) continue;
+      const int npost = sq.ns;
+      // one launch per sequence where the window fits, else two (the first writes x and d)
+      auto plans = [&](bool pre, int ns, int applies, semk::CoarsePlan* p1, semk::CoarsePlan* p2,
+                       int* k1) {
+        const int fl = pre ? semk::CO_RESTRICT : semk::CO_PROLONG;
+        *p1 = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, fl, applies);
+        *p2 = semk::CoarsePlan();
+        *k1 = 0;
+        if (p1->W >= 1 || ns < 2) return;
+        // split after step a: pre, steps 0 .. a-1 from x = 0 (a - 1 applies), then the rest and
+        // the residual; post, the prolongation and steps 0 .. a-1, then the rest.  The split
+        // taken is the one with the least recomputed work: applies times window slots per
+        // owned column, summed over the two launches
+        double best = 1e300;
+        for (int a = 1; a < ns; ++a) {
+          semk::CoarsePlan q1, q2;
+          int n1, n2;
+          if (pre) {
+            n1 = a - 1;
+            n2 = ns - a + 1;
+            q1 = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, 0, n1);
+            q2 = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, semk::CO_RESTRICT, n2);
+          } else {
+            n1 = a;
+            n2 = ns - a;
+            q1 = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, semk::CO_PROLONG, n1);
+            q2 = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, 0, n2);
+          }
+          if (q1.W < 1 || q2.W < 1) continue;
+          const double cost = std::max(n1, 1) * (double)q1.nslot / q1.W +
+                              std::max(n2, 1) * (double)q2.nslot / q2.W;
+          if (cost < best) {
+            best = cost;
+            *p1 = q1;
+            *p2 = q2;
+            *k1 = a;
+          }
+        }
+        if (*k1 == 0) *p1 = semk::CoarsePlan();
+      };
+      plans(true, npre, apre, &L.cpre, &L.cpre2, &L.cpre_k1);
+      plans(false, npost, apost, &L.cpost, &L.cpost2, &L.cpost_k1);
     }
   }
   if (!c->lev[0].rect && semk::apply2d_smem(orders[0], c->Nz, true) > 160 * 1024)

@@ -207,6 +207,43 @@ def test_vcycle_level_degrees(name, deg, deg_c):
     s.close()
 
 
+TALL16 = W.tank(8, 16, 8, Lx=0.8, name="tall16")   # its P = 4 level: columns of 80 threads
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16"])
+@pytest.mark.parametrize("deg", [6, 8])
+def test_two_launch_coarse_sequences(prec, deg, monkeypatch):
+    """A Chebyshev sequence longer than one window of the coarse-level kernel (the P = 4 level of
+    16-element columns at degree 6 and 8) runs as two launches, the second continuing from the
+    first's x and d: the V-cycle against the oracle's (FP64, 1e-12) and against the per-step
+    kernels (every precision, to its rounding)."""
+    print(f"[gpu] two-launch coarse sequences degree {deg} {prec}", flush=True)
+    H_ = oc.hierarchy(TALL16, cheb_degree=deg)
+    pmg.estimate_lambdas(H_)
+    L0 = H_.levels[0]
+    r = W.random_vector(L0.N, 905)
+    r[L0.dn] = 0.0
+
+    def run():
+        s = cases.make_solver(TALL16, prec=prec, cheb_degree=deg)
+        for l, L in enumerate(H_.levels[:-1]):
+            s.set_lambda(l, L.lam)
+        shape = B.sem_launch_shape(s.ctx, 1)
+        z = H(s.vcycle(T(r)))
+        s.close()
+        return z, shape
+
+    fused, shape = run()
+    assert shape[1] >= 1, shape          # the level runs its sequences in the coarse kernel
+    if prec == "f64":
+        assert rel(fused, H_.vcycle(r)) < 1e-12
+    monkeypatch.setenv("SEM_NO_COARSE_FUSED", "1")
+    plain, shape0 = run()
+    assert shape0[1] == 0
+    tol = 1e-12 if prec == "f64" else 2e-5
+    assert rel(fused, plain) < tol, (prec, deg, rel(fused, plain))
+
+
 @pytest.mark.parametrize("name", ["c1", "ragged", "tank8", "c2"])
 def test_rhs_assembly(name):
     wl = CASES[name]
