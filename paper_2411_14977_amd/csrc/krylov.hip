@@ -51,14 +51,20 @@ __global__ __launch_bounds__(KT) void k_kry_first(const double* __restrict__ y,
 
 __global__ __launch_bounds__(KT) void k_kry_sub(double* __restrict__ w,
                                                 const double* __restrict__ V, size_t ldv, int nv,
-                                                KryCoef h, int dots, double* __restrict__ part,
+                                                KryCoef h, const double* __restrict__ hd,
+                                                int dots, double* __restrict__ part,
                                                 unsigned N) {
   __shared__ double sh[KT / 64];
+  __shared__ double hs[KRY_MAX];
+  if (hd) {  // coefficients from device memory
+    for (int i = threadIdx.x; i < nv; i += blockDim.x) hs[i] = hd[i];
+    __syncthreads();
+  }
   const unsigned stride = gridDim.x * blockDim.x;
   double ww = 0.0;
   for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += stride) {
     double s = w[g];
-    for (int i = 0; i < nv; ++i) s -= h.h[i] * V[(size_t)i * ldv + g];
+    for (int i = 0; i < nv; ++i) s -= (hd ? hs[i] : h.h[i]) * V[(size_t)i * ldv + g];
     w[g] = s;
     ww += s * s;
   }
@@ -74,6 +80,34 @@ __global__ __launch_bounds__(KT) void k_kry_sub(double* __restrict__ w,
   }
   ww = kry_block_sum(ww, sh);
   if (threadIdx.x == 0) part[(size_t)nv * NRED + blockIdx.x] = ww;
+}
+
+// one workgroup per set: the NRED partials summed in a fixed order (each thread a strided
+// run, then the block tree)
+__global__ __launch_bounds__(KT) void k_kry_sums(const double* __restrict__ part,
+                                                 double* __restrict__ out) {
+  __shared__ double sh[KT / 64];
+  const double* p = part + (size_t)blockIdx.x * NRED;
+  double a = 0.0;
+  for (int q = threadIdx.x; q < NRED; q += KT) a += p[q];
+  a = kry_block_sum(a, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = a;
+}
+
+__global__ __launch_bounds__(KT) void k_kry_finish(double* __restrict__ w,
+                                                   const double* __restrict__ ww,
+                                                   const double* __restrict__ h1,
+                                                   const double* __restrict__ h2, int j,
+                                                   double* __restrict__ col, unsigned N) {
+  const double hn = sqrt(*ww);
+  if (blockIdx.x == 0) {
+    for (int i = threadIdx.x; i <= j; i += blockDim.x) col[i] = h1[i] + h2[i];
+    if (threadIdx.x == 0) col[j + 1] = hn;
+  }
+  if (!(hn > 0.0)) return;
+  const double s = 1.0 / hn;
+  for (unsigned g = blockIdx.x * blockDim.x + threadIdx.x; g < N; g += gridDim.x * blockDim.x)
+    w[g] *= s;
 }
 
 __global__ __launch_bounds__(KT) void k_kry_scale(double* __restrict__ w, double s, unsigned N) {
@@ -106,7 +140,32 @@ hipError_t kry_sub(double* w, const double* V, size_t ldv, int nv, const KryCoef
                    double* part, unsigned N, hipStream_t st) {
   acct_add(8.0 * N * (2 + nv));  // w read and written, each basis vector read
   if (nv < 0 || nv > KRY_MAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_kry_sub, dim3(NRED), dim3(KT), 0, st, w, V, ldv, nv, h, dots, part, N);
+  hipLaunchKernelGGL(k_kry_sub, dim3(NRED), dim3(KT), 0, st, w, V, ldv, nv, h,
+                     (const double*)nullptr, dots, part, N);
+  return hipGetLastError();
+}
+
+hipError_t kry_sub_dev(double* w, const double* V, size_t ldv, int nv, const double* hd, int dots,
+                       double* part, unsigned N, hipStream_t st) {
+  acct_add(8.0 * N * (2 + nv));
+  if (nv < 0 || nv > KRY_MAX || !hd) return hipErrorInvalidValue;
+  KryCoef none{};
+  hipLaunchKernelGGL(k_kry_sub, dim3(NRED), dim3(KT), 0, st, w, V, ldv, nv, none, hd, dots, part,
+                     N);
+  return hipGetLastError();
+}
+
+hipError_t kry_sums(const double* part, int nsets, double* out, hipStream_t st) {
+  if (nsets < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_kry_sums, dim3(nsets), dim3(KT), 0, st, part, out);
+  return hipGetLastError();
+}
+
+hipError_t kry_finish(double* w, const double* ww, const double* h1, const double* h2, int j,
+                      double* col, unsigned N, hipStream_t st) {
+  acct_add(16.0 * N);
+  if (j < 0 || j >= KRY_MAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_kry_finish, dim3(NRED), dim3(KT), 0, st, w, ww, h1, h2, j, col, N);
   return hipGetLastError();
 }
 

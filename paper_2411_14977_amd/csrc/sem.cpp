@@ -134,6 +134,7 @@ struct Ctx {
   double* bcrRed = nullptr;  // reduced right-hand side of the one-launch reduction
   // GMRES: Arnoldi basis V (m + 1 vectors), preconditioned basis Z (m), reduction partials
   double *kV = nullptr, *kZ = nullptr, *kpart = nullptr, *hkpart = nullptr;
+  double* kcoef = nullptr;  // GMRES on the device: h1, h2 [KRY_MAX + 1], ||w||^2, the step's column
   semk::BcrLevels bcrLv;     // its level table (nl = -1: per-level kernels)
   int* rowmap = nullptr;
   // FP64 right-hand side of the next V-cycle, read by the first smoothing step of level 0
@@ -2475,19 +2476,13 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
         c->kV = (double*)dalloc(c, (size_t)(m + 1) * Nn * 8);
         c->kZ = (double*)dalloc(c, (size_t)m * Nn * 8);
         c->kpart = (double*)dalloc(c, (size_t)(m + 2) * NR * 8);
+        c->kcoef = (double*)dalloc(c, (size_t)(3 * (semk::KRY_MAX + 2)) * 8);
         HK(hipHostMalloc((void**)&c->hkpart, (size_t)(m + 2) * NR * 8, hipHostMallocDefault));
       }
-      // sums of the partial sets s0 .. s0 + n - 1 (each NR partials, fixed order)
-      auto read_parts = [&](int s0, int n, double* out) {
-        HK(hipMemcpyAsync(c->hkpart, c->kpart + (size_t)s0 * NR, (size_t)n * NR * 8,
-                          hipMemcpyDeviceToHost, c->st));
-        HK(hipStreamSynchronize(c->st));
-        for (int i = 0; i < n; ++i) {
-          double v = 0.0;
-          for (int q = 0; q < NR; ++q) v += c->hkpart[(size_t)i * NR + q];
-          out[i] = v;
-        }
-      };
+      double* kh1 = c->kcoef;                            // [KRY_MAX + 2]
+      double* kh2 = c->kcoef + (semk::KRY_MAX + 2);      // [KRY_MAX + 2]
+      double* kcol = c->kcoef + 2 * (semk::KRY_MAX + 2); // [KRY_MAX + 2]: ||w||^2, then the column
+      double* kww = kh2 + semk::KRY_MAX + 1;
       const double nb = std::sqrt(bb);
       double beta = rel * nb;
       std::vector<double> Hm((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1);
@@ -2508,24 +2503,26 @@ sem_status sem_poisson_solve(sem_ctx* ctx, const double* rhs, double* x, double 
           apply_outer(c, zj, c->masked);
           HK(semk::kry_first(c->yo, c->So, w, c->kV, Nn, j + 1, c->kpart, N, L0.nzn, L0.P,
                              c->st));
-          double h1[semk::KRY_MAX + 1], h2[semk::KRY_MAX + 1], ww = 0.0;
-          read_parts(0, j + 1, h1);
-          semk::KryCoef co;
-          for (int i = 0; i <= j; ++i) co.h[i] = h1[i];
-          HK(semk::kry_sub(w, c->kV, Nn, j + 1, co, 1, c->kpart, N, c->st));
-          read_parts(0, j + 1, h2);
-          for (int i = 0; i <= j; ++i) co.h[i] = h2[i];
-          HK(semk::kry_sub(w, c->kV, Nn, j + 1, co, 0, c->kpart, N, c->st));
-          read_parts(j + 1, 1, &ww);
-          const double hn = std::sqrt(ww);
-          for (int i = 0; i <= j; ++i) H(i, j) = h1[i] + h2[i];
+          // classical Gram-Schmidt twice with the coefficients kept on the device; the host
+          // reads the finished column once per step (enqueuing the next step before that wait
+          // was measured slower: the step run past the end of each cycle costs more than the
+          // wait it hides at these sizes)
+          HK(semk::kry_sums(c->kpart, j + 1, kh1, c->st));
+          HK(semk::kry_sub_dev(w, c->kV, Nn, j + 1, kh1, 1, c->kpart, N, c->st));
+          HK(semk::kry_sums(c->kpart, j + 1, kh2, c->st));
+          HK(semk::kry_sub_dev(w, c->kV, Nn, j + 1, kh2, 0, c->kpart, N, c->st));
+          HK(semk::kry_sums(c->kpart + (size_t)(j + 1) * NR, 1, kww, c->st));
+          HK(semk::kry_finish(w, kww, kh1, kh2, j, kcol, N, c->st));
+          HK(hipMemcpyAsync(c->hkpart, kcol, (size_t)(j + 2) * 8, hipMemcpyDeviceToHost, c->st));
+          HK(hipStreamSynchronize(c->st));
+          const double hn = c->hkpart[j + 1];
+          for (int i = 0; i <= j; ++i) H(i, j) = c->hkpart[i];
           H(j + 1, j) = hn;
           if (!std::isfinite(hn)) {
             st = SEM_ERR_BREAKDOWN;
             set_err(c, "breakdown in GMRES (non-finite Arnoldi vector)");
             return;
           }
-          if (hn > 0.0) HK(semk::kry_scale(w, 1.0 / hn, N, c->st));
           for (int i = 0; i < j; ++i) {  // earlier rotations on the new column
             const double t = cs[i] * H(i, j) + sn[i] * H(i + 1, j);
             H(i + 1, j) = -sn[i] * H(i, j) + cs[i] * H(i + 1, j);
