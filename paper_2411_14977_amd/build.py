@@ -14,7 +14,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsem.so")
 ARCH = os.environ.get("SEM_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["kernels.hip", "semi.hip", "schwarz.hip", "mlp.hip", "krylov.hip", "host_math.cpp", "sem.cpp"]
+SOURCES = ["kernels.hip", "semi.hip", "schwarz.hip", "p1.hip", "mlp.hip", "krylov.hip", "host_math.cpp", "sem.cpp"]
 # no packed-FP32 instructions: some of their forms have given silent wrong results on this
 # hardware pool; the host pass warns that it does not know the feature (harmless)
 HIPFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

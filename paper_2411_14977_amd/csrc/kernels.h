@@ -128,6 +128,13 @@ struct Step3 {
 hipError_t apply3d(int P, bool dbl, GType gt, const void* x, void* y, void* Sx, void* Sy,
                    void* Sxy, const void* G, int Nx, int Ny, int Nz, int masked, hipStream_t st,
                    Step3 st3 = Step3());
+// 3D levels of order 1 (p1.hip): y = A x with the assembled 27-point stencil coef [27][N]
+// (offset k = (dx+1) 9 + (dy+1) 3 + (dz+1), zero outside the grid and towards masked nodes,
+// identity rows on them), complete at every node; with st3.b the smoother step of apply3d,
+// written out of place into xo (xo != x)
+hipError_t stencil3d(bool dbl, const void* x, void* y, const void* coef, unsigned nxn,
+                     unsigned nyn, unsigned nzn, hipStream_t st, Step3 st3 = Step3(),
+                     void* xo = nullptr);
 // one 1D operator (CSR rows over the output index) along the middle axis of [outer][n][inner]
 // arrays; in2 (optional) is subtracted from in; mask_nzn > 0 zeroes every mask_nzn-th output
 // (the Dirichlet surface rows when inner is the vertical axis)

@@ -67,6 +67,9 @@ struct DLevel {
   void *Ainv_s = nullptr, *Zs = nullptr;
   bool asm_box = false;
   semk::AsmBox abox;
+  // 3D levels of order 1 above the coarsest: the assembled 27-point stencil [27][N] in the
+  // level's precision and the second solution vector of its out-of-place smoother step
+  void *st27 = nullptr, *x3alt = nullptr;
   size_t nS = 0;
   double lam = 0.0;
   // 3D: side buffers of the operator (completed into y by the face fix-up; S stays null) and
@@ -536,6 +539,53 @@ std::vector<double> schwarz_box_inverses(const semh::LevelGeom& G, const std::ve
   return out;
 }
 
+// The assembled operator of a 3D level of order 1 as a 27-point stencil, offset-major [27][N]
+// (offset k = (dx+1) 9 + (dy+1) 3 + (dz+1)), from the element matrices of factors Gr; masked:
+// identity rows on the Dirichlet surface and no coupling towards it (the masked matrix).
+std::vector<double> stencil27(const semh::LevelGeom& G, const std::vector<double>& Gr,
+                              bool masked) {
+  const size_t N = G.N, nyn = G.nyn, nzn = G.nzn;
+  std::vector<double> co(27 * N, 0.0), Ae(64);
+  auto coords = [&](size_t g, long* ix, long* iy, long* iz) {
+    *iz = (long)(g % nzn);
+    const size_t q = g / nzn;
+    *iy = (long)(q % nyn);
+    *ix = (long)(q / nyn);
+  };
+  for (size_t e = 0; e < G.E; ++e) {
+    semh::element_matrix(G, Gr, e, Ae.data());
+    for (int a = 0; a < 8; ++a) {
+      const size_t ga = semh::local_to_global(G, e, a);
+      long ax, ay, az;
+      coords(ga, &ax, &ay, &az);
+      for (int b = 0; b < 8; ++b) {
+        long bx, by, bz;
+        coords(semh::local_to_global(G, e, b), &bx, &by, &bz);
+        const long k = (bx - ax + 1) * 9 + (by - ay + 1) * 3 + (bz - az + 1);
+        co[(size_t)k * N + ga] += Ae[(size_t)a * 8 + b];
+      }
+    }
+  }
+  if (masked)
+    for (size_t g = 0; g < N; ++g) {
+      const bool top = g % nzn == nzn - 1;
+      for (int k = 0; k < 27; ++k) {
+        const int dz = k % 3 - 1;
+        if (top) co[(size_t)k * N + g] = (k == 13) ? 1.0 : 0.0;
+        else if ((long)(g % nzn) + dz == (long)nzn - 1) co[(size_t)k * N + g] = 0.0;
+      }
+    }
+  return co;
+}
+
+// stencil of a 3D level of order 1 (set-up, or refresh into the existing buffer)
+void stencil_setup(Ctx* c, DLevel& L, const std::vector<double>& Gr) {
+  const std::vector<double> co = stencil27(L.geo, Gr, c->masked != 0);
+  if (L.dbl) L.st27 = put_vec(c, co, L.st27);
+  else L.st27 = put_vec(c, std::vector<float>(co.begin(), co.end()), L.st27);
+  if (!L.x3alt) L.x3alt = dalloc(c, L.N * esz(L.dbl));
+}
+
 // Schwarz smoother data of a level above the coarsest: element blocks (2D without overlap) or
 // box subdomains, inverses in the level's precision; refresh: recompute the inverses of a new
 // geometry into the existing buffers
@@ -565,7 +615,9 @@ void set_err(Ctx* c, const std::string& s) { c->err = s; }
 // ------------------------------------------------------------------------------------------
 void apply_level(Ctx* c, int l, const void* x, int masked) {
   DLevel& L = c->lev[l];
-  if (c->dim == 3)
+  if (c->dim == 3 && L.st27 && masked == c->masked)
+    HK(semk::stencil3d(L.dbl, x, L.y, L.st27, L.nxn, L.nyn, L.nzn, c->st));
+  else if (c->dim == 3)
     HK(semk::apply3d(L.P, L.dbl, L.gt, x, L.y, L.Sx, L.Sy, L.Sxy, L.G, L.Nx, L.Ny, L.Nz, masked,
                      c->st));
   else if (L.rect)
@@ -602,6 +654,11 @@ void smooth_step(Ctx* c, int l, double cd, double cr, int store_d) {
     s3.cd = cd;
     s3.cr = cr;
     s3.store_d = store_d;
+    if (L.st27) {  // out of place into the second vector, then the two swap
+      HK(semk::stencil3d(L.dbl, L.x, L.y, L.st27, L.nxn, L.nyn, L.nzn, c->st, s3, L.x3alt));
+      std::swap(L.x, L.x3alt);
+      return;
+    }
     HK(semk::apply3d(L.P, L.dbl, L.gt, L.x, L.y, L.Sx, L.Sy, L.Sxy, L.G, L.Nx, L.Ny, L.Nz,
                      c->masked, c->st, s3));
     return;
@@ -1545,6 +1602,10 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
     L.S = nullptr;
     L.nS = 0;
     if (!coarsest && d->smoother == SEM_SMOOTH_SCHWARZ) schwarz_setup(c, L, Gr);
+    // order-1 levels above the coarsest: the assembled stencil (SEM_NO_STENCIL=1: the
+    // matrix-free operator with its face fix-up)
+    const char* ns = std::getenv("SEM_NO_STENCIL");
+    if (!coarsest && L.P == 1 && c->masked && !(ns && ns[0] == '1')) stencil_setup(c, L, Gr);
   }
   // transfers and their temporaries
   size_t tmax = 1;
@@ -2997,6 +3058,7 @@ static void rebuild_levels(Ctx* c) {
     if (L.dbl) copy_to(c, L.dinv, dinv);
     else copy_to(c, L.dinv, std::vector<float>(dinv.begin(), dinv.end()));
     if (L.Ainv_s) schwarz_setup(c, L, Gr, true);
+    if (L.st27) stencil_setup(c, L, Gr);
   }
   if (c->masked) {
     DLevel& LC = c->lev.back();
