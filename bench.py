@@ -291,6 +291,7 @@ def c5_series(steps, log_every=5, blob3=None, mode3=1):
         ms_op_hbm = B.sem_time_operator(s.ctx, 0, 0, 20, 2)
         x = torch.zeros(s.n_global, dtype=torch.float64, device="cuda")
         solve_ms, iters, upd_ms, skips = [], [], [], 0
+        verdict = None
         for k in range(steps):
             t = 0.01 * k
             eta = W.surface_3d(X, Y, t, wl.Lx, wl.surface_seed)
@@ -302,6 +303,9 @@ def c5_series(steps, log_every=5, blob3=None, mode3=1):
             f = W.bumps_3d(xg, yg, zg, t, wl.Lx, wl.rhs_seed, hfn,
                            lambda a, b: W.surface_3d(a, b, t, wl.Lx, wl.surface_seed))
             b = s.assemble_rhs(f=torch.tensor(f, dtype=torch.float64, device="cuda"))
+            if mode and k == 0:  # the plain smoother's verdict on the stage; the series keeps it on
+                verdict = s.learned_judge(b, cycles=6)
+                s.learned_enable(mode)
             torch.cuda.synchronize()
             a0 = time.perf_counter()
             _, info, _ = s.solve(b, x=x, tol=1e-10)
@@ -324,6 +328,7 @@ def c5_series(steps, log_every=5, blob3=None, mode3=1):
         if mode:
             out[tag]["placement"] = mode
             out[tag]["learned_skips"] = skips
+            out[tag]["judge"] = verdict
     out["speedup_mixed_vs_fp64"] = out["f64"]["ms_per_solve"] / out["bf16"]["ms_per_solve"]
     if blob3 is not None:
         out["speedup_learned_vs_fp64"] = (out["f64"]["ms_per_solve"] /
