@@ -28,16 +28,20 @@ __global__ __launch_bounds__(64) void k_stencil3d(const T* __restrict__ x, T* __
     const int xs[3] = {ix > 0 ? -(int)(nyn * nzn) : 0, 0, ix + 1 < nxn ? (int)(nyn * nzn) : 0};
     const int ys[3] = {iy > 0 ? -(int)nzn : 0, 0, iy + 1 < nyn ? (int)nzn : 0};
     const int zs[3] = {iz > 0 ? -1 : 0, 0, iz + 1 < nzn ? 1 : 0};
-    T acc = 0;
+    // every load first (54 independent requests in flight), then the sum in offset order
+    T cv[27], xv[27];
+#pragma unroll
+    for (int k = 0; k < 27; ++k) cv[k] = coef[(size_t)k * N + g];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b)
 #pragma unroll
-        for (int q = 0; q < 3; ++q) {
-          const int k = a * 9 + b * 3 + q;
-          acc += coef[(size_t)k * N + g] * x[(size_t)((int)g + xs[a] + ys[b] + zs[q])];
-        }
+        for (int q = 0; q < 3; ++q)
+          xv[a * 9 + b * 3 + q] = x[(size_t)((int)g + xs[a] + ys[b] + zs[q])];
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < 27; ++k) acc += cv[k] * xv[k];
     if (!st3.b) {
       y[g] = acc;
       continue;
