@@ -1605,7 +1605,9 @@ void setup3d_impl(Ctx* c, const sem_mesh_desc* d, const std::vector<int>& orders
     // order-1 levels above the coarsest: the assembled stencil (SEM_NO_STENCIL=1: the
     // matrix-free operator with its face fix-up)
     const char* ns = std::getenv("SEM_NO_STENCIL");
-    if (!coarsest && L.P == 1 && c->masked && !(ns && ns[0] == '1')) stencil_setup(c, L, Gr);
+    if (!coarsest && L.P == 1 && c->masked && !(ns && ns[0] == '1') &&
+        27.0 * L.N * 8.0 <= 2.0 * (1ull << 30))  // host assembly within 2 GiB
+      stencil_setup(c, L, Gr);
   }
   // transfers and their temporaries
   size_t tmax = 1;
