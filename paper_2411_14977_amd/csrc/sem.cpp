@@ -1918,12 +1918,14 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
         *p1 = semk::coarse2d_plan(L.P, C.P, c->Nz, L.dbl, fl, applies);
         *p2 = semk::CoarsePlan();
         *k1 = 0;
-        if (p1->W >= 1 || ns < 2) return;
-        // split after step a: pre, steps 0 .. a-1 from x = 0 (a - 1 applies), then the rest and
-        // the residual; post, the prolongation and steps 0 .. a-1, then the rest.  The split
-        // taken is the one with the least recomputed work: applies times window slots per
-        // owned column, summed over the two launches
-        double best = 1e300;
+        // one launch wherever its window owns two columns or more (a second launch costs more
+        // than the recomputation it saves there, measured at degrees 3 and 6); else the sequence
+        // splits after step a: pre, steps 0 .. a-1 from x = 0 (a - 1 applies), then the rest and
+        // the residual; post, the prolongation and steps 0 .. a-1, then the rest, at the split
+        // with the least recomputed work (applies times window slots per owned column, summed
+        // over the two launches; one owned column among twelve slots recomputes far more)
+        if (p1->W >= 2 || ns < 2) return;
+        double best = p1->W >= 1 ? std::max(applies, 1) * (double)p1->nslot / p1->W : 1e300;
         for (int a = 1; a < ns; ++a) {
           semk::CoarsePlan q1, q2;
           int n1, n2;
@@ -1948,7 +1950,7 @@ void setup_impl(Ctx* c, const sem_mesh_desc* d) {
             *k1 = a;
           }
         }
-        if (*k1 == 0) *p1 = semk::CoarsePlan();
+        if (*k1 == 0 && best >= 1e300) *p1 = semk::CoarsePlan();
       };
       plans(true, npre, apre, &L.cpre, &L.cpre2, &L.cpre_k1);
       plans(false, npost, apost, &L.cpost, &L.cpost2, &L.cpost_k1);
