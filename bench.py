@@ -849,6 +849,7 @@ def main():
 
     pdc = surf = None
     parity_procs = []
+    parity_kept = None   # surfaces whose GPU pressure the oracle checks, once the GPU timing is done
     if use_learned:
         pdc = pdc_rates(wl, args.prec, blob, args.pdc_cycles, mode)
         log(f"[bench] PDC per-cycle rate: {pdc}")
@@ -860,9 +861,7 @@ def main():
                     "iters_saved_mean": sum(saved) / len(saved),
                     "learned_faster_on": sum(r["learned"]["ms"] < r["plain"]["ms"] for r in rows),
                     "of": len(rows)}
-            parity_procs = start_oracle_parity(args, kept)
-            log(f"[bench] oracle checking surfaces {sorted(kept)} in {len(parity_procs)} "
-                f"background processes")
+            parity_kept = kept
 
     context = None
     if not args.no_context:
@@ -905,6 +904,12 @@ def main():
     if args.stage_steps > 0:
         stage_loop = stage_loop_c5(args.stage_steps, args.prec)
 
+    # the oracle's checks run on the host cores after every GPU timing, so that they do not
+    # compete with the host side of the timed solves
+    if parity_kept:
+        parity_procs = start_oracle_parity(args, parity_kept)
+        log(f"[bench] oracle checking surfaces {sorted(parity_kept)} in {len(parity_procs)} "
+            f"background processes")
     if parity_procs:
         log("[bench] waiting for the oracle's solves of the unseen surfaces ...")
         surf["oracle_parity"] = finish_oracle_parity(parity_procs)
