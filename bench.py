@@ -674,7 +674,7 @@ def main():
                     help="skip the paper-shaped iteration table and scaling sweeps")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU only (the solver has no multi-GPU path); "
+        print("bench.py: the solver runs on one GPU (it has no multi-GPU path); "
               "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
