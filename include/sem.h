@@ -453,7 +453,8 @@ sem_status sem_learned_skips(sem_ctx *ctx, int *skips, int reset);
  * call runs defect-correction cycles x += B(rhs - A x) from x = 0, with the stage off and then
  * on (its placement from sem_learned_load / sem_learned_enable, after pre-smoothing if it is
  * off), one cycle untimed and `cycles` timed (1..100) each, every cycle one captured HIP graph
- * timed with HIP events on the library stream.  rho = (||r_end|| / ||r_start||)^(1/cycles)
+ * (launched directly under SEM_NO_GRAPH=1, as the solves are), timed with HIP events on the
+ * library stream.  rho = (||r_end|| / ||r_start||)^(1/cycles)
  * over the timed cycles, ms the time per cycle.  The stage is left enabled iff it reduces the
  * residual faster per unit of time (rho_learned < 1 and ln(rho_learned) / ms_learned <
  * ln(rho_plain) / ms_plain), else disabled (as sem_learned_enable(ctx, 0)); the rejection

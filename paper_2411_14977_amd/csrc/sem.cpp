@@ -3356,17 +3356,22 @@ sem_status sem_learned_judge(sem_ctx* ctx, const double* rhs, int cycles, sem_ju
         apply_outer(c, c->xo, c->masked);
         HK(semk::resid64(c->bo, c->yo, c->So, c->ro, pset(c, PS_RR), pset(c, PS_BB), N, L0.nzn,
                          L0.P, c->st));
-        g = capture(c, [&]() { pdc_iteration(c); });
-        HK(hipGraphLaunch(g, c->st));  // the untimed cycle
+        // one cycle as a graph, as the solves run it (SEM_NO_GRAPH=1: launched directly)
+        if (c->use_graphs) g = capture(c, [&]() { pdc_iteration(c); });
+        auto cycle = [&]() {
+          if (g) HK(hipGraphLaunch(g, c->st));
+          else pdc_iteration(c);
+        };
+        cycle();  // the untimed cycle
         double s0[3], s1[3];
         read_sums(c, s0);
         HK(hipEventRecord(t0, c->st));
-        for (int k = 0; k < cycles; ++k) HK(hipGraphLaunch(g, c->st));
+        for (int k = 0; k < cycles; ++k) cycle();
         HK(hipEventRecord(t1, c->st));
         read_sums(c, s1);
         float el = 0.f;
         HK(hipEventElapsedTime(&el, t0, t1));
-        HK(hipGraphExecDestroy(g));
+        if (g) HK(hipGraphExecDestroy(g));
         g = nullptr;
         ms[on] = (double)el / cycles;
         rho[on] = (s0[0] > 0.0 && std::isfinite(s1[0]))
