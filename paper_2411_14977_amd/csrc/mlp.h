@@ -36,7 +36,8 @@ void net_init(Net& net, int nin, int nout, uint64_t seed);   // U(+-1/sqrt(fan_i
 hipError_t gemm_bf16(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
                      float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st);
 hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_t* dst, int ldd,
-                          int dcols, const int* rowidx, hipStream_t st);
+                          int dcols, const int* rowidx, hipStream_t st, uint16_t* dstT = nullptr,
+                          int ldT = 0);
 
 hipError_t add_bias(float* Z, const float* b, int rows, int cols, hipStream_t st);
 constexpr int MAX_STAGE_OUT = 96;  // the fused inference kernel handles (P+1)^2 <= 96 (P <= 8)

@@ -50,97 +50,150 @@ __device__ __forceinline__ f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c) {
 // for v = 0..3, and the result D[4(l/16)+v][l%16].
 
 // ------------------------------------------------------------------------------------------
-// generic GEMM (training and set-up): one wave computes a 16 x 64 block
+// generic GEMM (training and set-up): C = A B (+ C).  One workgroup owns a 16 x 64 block of C
+// and its GEMM_W waves split the K range (wave w takes the 16-wide k-steps w, w + GEMM_W,
+// ...).  A wave issues the loads of up to GEMM_CH k-steps before its first product, so one
+// memory latency covers a whole chunk; the partial blocks are summed through LDS in wave order
+// (the result does not depend on timing).  Operands whose k direction is contiguous (A and B
+// with unit k stride) load a lane's four k values as one 8-byte word.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_gemm_bf16(const uint16_t* __restrict__ A, long sam,
-                                                   long sak, const uint16_t* __restrict__ B,
-                                                   long sbk, long sbn, float* __restrict__ C,
-                                                   int ldc, int M, int N, int K, int accumulate) {
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int m0 = blockIdx.y * 64 + wave * 16;
-  const int n0 = blockIdx.x * 64;
-  if (m0 >= M) return;  // no block-level synchronisation in this kernel
-  const int li = lane & 15, kq = (lane >> 4) * 4;
-  f32x4 acc[4];
-  for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += 16) {
-    bf16x4 a;
-    const uint16_t* ap = A + (long)(m0 + li) * sam + (long)(k0 + kq) * sak;
-    for (int v = 0; v < 4; ++v) a[v] = (short)ap[v * sak];
+constexpr int GEMM_CH = 8, GEMM_W = 8;
+
+template <bool VEC>
+__device__ __forceinline__ bf16x4 frag_load(const uint16_t* p, long sk) {
+  if constexpr (VEC) {
+    return __builtin_bit_cast(bf16x4, *reinterpret_cast<const uint2*>(p));
+  } else {
+    bf16x4 r;
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-      const int n = n0 + 16 * t;
-      if (n < N) {
-        bf16x4 b;
-        const uint16_t* bp = B + (long)(k0 + kq) * sbk + (long)(n + li) * sbn;
-        for (int v = 0; v < 4; ++v) b[v] = (short)bp[v * sbk];
-        acc[t] = mfma16(a, b, acc[t]);
+    for (int v = 0; v < 4; ++v) r[v] = (short)p[v * sk];
+    return r;
+  }
+}
+
+template <bool AV, bool BV>
+__global__ __launch_bounds__(64 * GEMM_W) void k_gemm_bf16(const uint16_t* __restrict__ A,
+                                                          long sam, long sak,
+                                                          const uint16_t* __restrict__ B, long sbk,
+                                                          long sbn, float* __restrict__ C, int ldc,
+                                                          int M, int N, int K, int accumulate) {
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 64;
+  const int nt = min(4, (N - n0) >> 4);  // 16-column tiles of this block (uniform)
+  const int li = lane & 15, kq = (lane >> 4) * 4;
+  const int ks = K >> 4;
+  const uint16_t* ap = A + (long)(m0 + li) * sam + (long)kq * sak;
+  const uint16_t* bp = B + (long)kq * sbk + (long)(n0 + li) * sbn;
+  f32x4 acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int s0 = wave; s0 < ks; s0 += GEMM_W * GEMM_CH) {
+    bf16x4 a[GEMM_CH], b[GEMM_CH][4];
+#pragma unroll
+    for (int c = 0; c < GEMM_CH; ++c) {
+      const int s = s0 + GEMM_W * c;
+      if (s < ks) {
+        a[c] = frag_load<AV>(ap + (long)s * 16 * sak, sak);
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < nt) b[c][t] = frag_load<BV>(bp + (long)s * 16 * sbk + (long)t * 16 * sbn, sbk);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < GEMM_CH; ++c) {
+      if (s0 + GEMM_W * c < ks) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+          if (t < nt) acc[t] = mfma16(a[c], b[c][t], acc[t]);
       }
     }
   }
+  __shared__ f32x4 part[GEMM_W][4][64];  // [wave][tile][lane]
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int n = n0 + 16 * t;
-    if (n >= N) continue;
-    for (int v = 0; v < 4; ++v) {
-      float* cp = C + (long)(m0 + kq + v) * ldc + n + li;
-      *cp = accumulate ? *cp + acc[t][v] : acc[t][v];
-    }
+  for (int t = 0; t < 4; ++t) part[wave][t][lane] = acc[t];
+  __syncthreads();
+  const int t = wave;  // wave w < 4 sums and stores tile w
+  if (t >= nt) return;
+  f32x4 s = part[0][t][lane];
+#pragma unroll
+  for (int w = 1; w < GEMM_W; ++w) s += part[w][t][lane];
+  const int n = n0 + 16 * t + li;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    float* cp = C + (long)(m0 + kq + v) * ldc + n;
+    *cp = accumulate ? *cp + s[v] : s[v];
   }
 }
 
 hipError_t gemm_bf16(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
                      float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st) {
-  if (M % 16 || N % 16 || K % 16) return hipErrorInvalidValue;
-  dim3 grid(nblk(N, 64), nblk(M, 64));
-  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, st, A, sam, sak, B, sbk, sbn, C, ldc, M, N,
-                     K, accumulate);
+  if (M % 16 || N % 16 || K % 16 || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
+  // 8-byte fragment loads need a unit k stride, a row stride that keeps every row's start on
+  // 8 bytes, and an 8-byte aligned base
+  const bool av = sak == 1 && sam % 4 == 0 && ((uintptr_t)A & 7) == 0;
+  const bool bv = sbk == 1 && sbn % 4 == 0 && ((uintptr_t)B & 7) == 0;
+  const dim3 grid(M / 16, nblk(N, 64));
+  if (av && bv)
+    hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(64 * GEMM_W), 0, st, A, sam, sak, B,
+                       sbk, sbn, C, ldc, M, N, K, accumulate);
+  else if (av)
+    hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(64 * GEMM_W), 0, st, A, sam, sak, B,
+                       sbk, sbn, C, ldc, M, N, K, accumulate);
+  else  // (a k-contiguous B alone takes the element loads too: no such product in this library)
+    hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, dim3(64 * GEMM_W), 0, st, A, sam, sak, B,
+                       sbk, sbn, C, ldc, M, N, K, accumulate);
   return hipGetLastError();
 }
 
 __global__ void k_to_bf16_padded(const float* __restrict__ src, int rows, int cols, int lds,
                                  uint16_t* __restrict__ dst, int ldd, int dcols,
-                                 const int* __restrict__ rowidx) {
+                                 const int* __restrict__ rowidx, uint16_t* __restrict__ dstT,
+                                 int ldT) {
   const long total = (long)rows * dcols;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int r = (int)(t / dcols), c = (int)(t - (long)r * dcols);
     const int sr = rowidx ? rowidx[r] : r;
     const float v = (sr >= 0 && c < cols) ? src[(long)sr * lds + c] : 0.0f;
     dst[(long)r * ldd + c] = f2bf(v);
+    if (dstT) dstT[(long)c * ldT + r] = f2bf(v);
   }
 }
 
 hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_t* dst, int ldd,
-                          int dcols, const int* rowidx, hipStream_t st) {
+                          int dcols, const int* rowidx, hipStream_t st, uint16_t* dstT, int ldT) {
   const long total = (long)rows * dcols;
   hipLaunchKernelGGL(k_to_bf16_padded, dim3(std::min<long>(nblk(total, 256), 65535)), dim3(256), 0,
-                     st, src, rows, cols, lds, dst, ldd, dcols, rowidx);
+                     st, src, rows, cols, lds, dst, ldd, dcols, rowidx, dstT, ldT);
   return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------
 // training element-wise kernels
 // ------------------------------------------------------------------------------------------
-// Z (M x ld) += bias; H = bf16(GELU(Z))
+// Z (M x ld) += bias; H = bf16(GELU(Z)), and its transpose HT [N x ldT] when given
 __global__ void k_bias_gelu(float* __restrict__ Z, const float* __restrict__ bias,
-                            uint16_t* __restrict__ H, int M, int N, int ld) {
+                            uint16_t* __restrict__ H, int M, int N, int ld,
+                            uint16_t* __restrict__ HT, int ldT) {
   const long total = (long)M * N;
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
     const int r = (int)(t / N), c = (int)(t - (long)r * N);
     const float z = Z[(long)r * ld + c] + bias[c];
     Z[(long)r * ld + c] = z;
-    H[(long)r * ld + c] = f2bf(gelu(z));
+    const uint16_t h = f2bf(gelu(z));
+    H[(long)r * ld + c] = h;
+    if (HT) HT[(long)c * ldT + r] = h;
   }
 }
 
 // y = Y + b3 on the first nout columns; d = y - t on valid rows (< nvalid); dY = 2 d / (nvalid
-// nout) (fp32 and bf16, padded columns and rows zero); Y is overwritten with y; per-block partial
-// sums of d^2 into part[blockIdx.x]
+// nout) (fp32 and bf16, padded columns and rows zero; the bf16 also transposed into dYbT
+// [ldy x ldT]); Y is overwritten with y; per-block partial sums of d^2 into part[blockIdx.x]
 __global__ __launch_bounds__(256) void k_loss_grad(float* __restrict__ Y, const float* __restrict__ b3,
                                                    const float* __restrict__ T, int ldt,
                                                    float* __restrict__ dYf,
                                                    uint16_t* __restrict__ dYb, int M, int ldy,
-                                                   int nout, int nvalid, double* part) {
+                                                   int nout, int nvalid, double* part,
+                                                   uint16_t* __restrict__ dYbT, int ldT) {
   __shared__ double sh[8];
   double acc = 0.0;
   const float scale = 2.0f / ((float)nvalid * (float)nout);
@@ -159,6 +212,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(float* __restrict__ Y, const 
     }
     dYf[t] = g;
     dYb[t] = f2bf(g);
+    dYbT[(long)c * ldT + r] = f2bf(g);
   }
   for (int o = 32; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
@@ -170,13 +224,16 @@ __global__ __launch_bounds__(256) void k_loss_grad(float* __restrict__ Y, const 
   }
 }
 
-// dZ = dH * GELU'(Z) (fp32 and bf16)
+// dZ = dH * GELU'(Z) (fp32 and bf16, rows of NH; the bf16 also transposed into dZbT [NH x ldT])
 __global__ void k_gelu_back(const float* __restrict__ dH, const float* __restrict__ Z,
-                            float* __restrict__ dZf, uint16_t* __restrict__ dZb, long n) {
+                            float* __restrict__ dZf, uint16_t* __restrict__ dZb, long n,
+                            uint16_t* __restrict__ dZbT, int ldT) {
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
     const float g = dH[t] * gelu_grad(Z[t]);
+    const long r = t / NH, c = t - r * NH;
     dZf[t] = g;
     dZb[t] = f2bf(g);
+    dZbT[c * ldT + r] = f2bf(g);
   }
 }
 
@@ -188,8 +245,18 @@ __global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ D, in
   const int cl = threadIdx.x & 63, rg = threadIdx.x >> 6;
   const int c = blockIdx.x * 64 + cl;
   float s = 0.0f;
-  if (c < N)
-    for (int r = rg; r < M; r += 16) s += D[(long)r * ld + c];
+  if (c < N) {
+    // eight rows' loads issued before their sum (one memory latency per eight rows)
+    int r = rg;
+    for (; r + 7 * 16 < M; r += 8 * 16) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = D[(long)(r + 16 * u) * ld + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; r < M; r += 16) s += D[(long)r * ld + c];
+  }
   part[rg][cl] = s;
   __syncthreads();
   if (rg == 0 && c < N) {
@@ -203,19 +270,39 @@ static void colsum(const float* D, int M, int N, int ld, float* out, hipStream_t
   hipLaunchKernelGGL(k_colsum, dim3(nblk(N, 64)), dim3(1024), 0, st, D, M, N, ld, out);
 }
 
-// Adam on FP32 master weights; wb = bf16 copy (may be null)
-__global__ void k_adam(float* __restrict__ w, const float* __restrict__ g, float* __restrict__ m,
-                       float* __restrict__ v, long n, float lr_t, float b1, float b2, float eps,
-                       float c1, float c2, uint16_t* __restrict__ wb) {
+// Adam on FP32 master weights of all six parameter tensors in one launch; g, m, v hold the
+// tensors back to back (tensor i from off[i]), the weights sit in their own buffers, wb[i] is
+// the bf16 copy and wbt[i] the transposed bf16 copy of a [rows x cols] tensor (either may be
+// null)
+struct AdamSlots {
+  float* w[6];
+  uint16_t* wb[6];
+  uint16_t* wbt[6];
+  int cols[6];
+  long off[7];
+};
+
+__global__ void k_adam(AdamSlots sl, const float* __restrict__ g, float* __restrict__ m,
+                       float* __restrict__ v, float lr_t, float b1, float b2, float eps, float c1,
+                       float c2) {
+  const long n = sl.off[6];
   for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
+    int i = 0;
+    while (t >= sl.off[i + 1]) ++i;
+    const long j = t - sl.off[i];
     const float gi = g[t];
     const float mi = b1 * m[t] + (1.0f - b1) * gi;
     const float vi = b2 * v[t] + (1.0f - b2) * gi * gi;
     m[t] = mi;
     v[t] = vi;
-    const float wi = w[t] - lr_t * (mi / c1) / (sqrtf(vi / c2) + eps);
-    w[t] = wi;
-    if (wb) wb[t] = f2bf(wi);
+    const float wi = sl.w[i][j] - lr_t * (mi / c1) / (sqrtf(vi / c2) + eps);
+    sl.w[i][j] = wi;
+    const uint16_t h = f2bf(wi);
+    if (sl.wb[i]) sl.wb[i][j] = h;
+    if (sl.wbt[i]) {
+      const long r = j / sl.cols[i], c = j - r * sl.cols[i];
+      sl.wbt[i][c * ((sl.off[i + 1] - sl.off[i]) / sl.cols[i]) + r] = h;
+    }
   }
 }
 
@@ -366,6 +453,9 @@ struct Params {
   int nin, nout, K1, N3;
   float *W1, *b1, *W2, *b2, *W3, *b3;      // padded: W1 [K1 x NH], W3 [NH x N3], b3 [N3]
   uint16_t *W1b, *W2b, *W3b;
+  // transposed bf16 copies (W1bT [NH x K1], W2bT [NH x NH], W3bT [N3 x NH]), so that the forward
+  // products read k-contiguous fragments; null where only the row-major copies are kept
+  uint16_t *W1bT = nullptr, *W2bT = nullptr, *W3bT = nullptr;
   size_t n1() const { return (size_t)K1 * NH; }
   size_t n2() const { return (size_t)NH * NH; }
   size_t n3() const { return (size_t)NH * N3; }
@@ -385,6 +475,9 @@ bool alloc_params(Dev& d, Params& p, int nin, int nout) {
   p.W1b = d.alloc<uint16_t>(p.n1());
   p.W2b = d.alloc<uint16_t>(p.n2());
   p.W3b = d.alloc<uint16_t>(p.n3());
+  p.W1bT = d.alloc<uint16_t>(p.n1());
+  p.W2bT = d.alloc<uint16_t>(p.n2());
+  p.W3bT = d.alloc<uint16_t>(p.n3());
   return d.e == hipSuccess;
 }
 
@@ -401,9 +494,9 @@ bool upload_params(const Net& net, Params& p, hipStream_t st, std::string& err) 
   CK(hipMemcpyAsync(p.b1, net.b1.data(), NH * 4, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(p.b2, net.b2.data(), NH * 4, hipMemcpyHostToDevice, st));
   CK(hipMemcpyAsync(p.b3, b3.data(), p.N3 * 4, hipMemcpyHostToDevice, st));
-  CK(to_bf16_padded(p.W1, p.K1, NH, NH, p.W1b, NH, NH, nullptr, st));
-  CK(to_bf16_padded(p.W2, NH, NH, NH, p.W2b, NH, NH, nullptr, st));
-  CK(to_bf16_padded(p.W3, NH, p.N3, p.N3, p.W3b, p.N3, p.N3, nullptr, st));
+  CK(to_bf16_padded(p.W1, p.K1, NH, NH, p.W1b, NH, NH, nullptr, st, p.W1bT, p.K1));
+  CK(to_bf16_padded(p.W2, NH, NH, NH, p.W2b, NH, NH, nullptr, st, p.W2bT, NH));
+  CK(to_bf16_padded(p.W3, NH, p.N3, p.N3, p.W3b, p.N3, p.N3, nullptr, st, p.W3bT, NH));
   CK(hipStreamSynchronize(st));
   return true;
 }
@@ -435,6 +528,10 @@ bool download_params(const Params& p, Net& net, hipStream_t st, std::string& err
 struct Acts {
   int Bmax, K1, N3;
   uint16_t *Xb, *H1b, *H2b, *dYb, *dZ2b, *dZ1b;
+  // batch-major (transposed) bf16 copies [cols x Bmax] for the weight-gradient products, whose
+  // k index is the batch row; null in the forward-only set
+  uint16_t *XbT = nullptr, *H1bT = nullptr, *H2bT = nullptr, *dYbT = nullptr, *dZ2bT = nullptr,
+           *dZ1bT = nullptr;
   float *Z1, *Z2, *Y, *T, *dYf, *dH2, *dZ2f, *dH1, *dZ1f;
   int* idx;
   double* part;
@@ -451,6 +548,12 @@ bool alloc_acts(Dev& d, Acts& a, int Bmax, int K1, int N3) {
   a.dYb = d.alloc<uint16_t>(B * N3);
   a.dZ2b = d.alloc<uint16_t>(B * NH);
   a.dZ1b = d.alloc<uint16_t>(B * NH);
+  a.XbT = d.alloc<uint16_t>(B * K1);
+  a.H1bT = d.alloc<uint16_t>(B * NH);
+  a.H2bT = d.alloc<uint16_t>(B * NH);
+  a.dYbT = d.alloc<uint16_t>(B * N3);
+  a.dZ2bT = d.alloc<uint16_t>(B * NH);
+  a.dZ1bT = d.alloc<uint16_t>(B * NH);
   a.Z1 = d.alloc<float>(B * NH);
   a.Z2 = d.alloc<float>(B * NH);
   a.Y = d.alloc<float>(B * N3);
@@ -469,44 +572,55 @@ constexpr int LOSS_BLOCKS = 64;
 
 // forward of rows idx[0..M) (M multiple of 16; idx < 0 = zero row); Y holds y on return
 bool fwd(const Params& p, Acts& a, const float* X, int M, hipStream_t st, std::string& err) {
-  CK(to_bf16_padded(X, M, p.nin, p.nin, a.Xb, p.K1, p.K1, a.idx, st));
-  CK(gemm_bf16(a.Xb, p.K1, 1, p.W1b, NH, 1, a.Z1, NH, M, NH, p.K1, 0, st));
+  const int lt = a.Bmax;
+  CK(to_bf16_padded(X, M, p.nin, p.nin, a.Xb, p.K1, p.K1, a.idx, st, a.XbT, lt));
+  // B = W (K x N): the transposed copy gives unit k stride
+  const bool wt = p.W1bT != nullptr;
+  CK(gemm_bf16(a.Xb, p.K1, 1, wt ? p.W1bT : p.W1b, wt ? 1 : NH, wt ? p.K1 : 1, a.Z1, NH, M, NH,
+               p.K1, 0, st));
   hipLaunchKernelGGL(k_bias_gelu, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.Z1, p.b1,
-                     a.H1b, M, NH, NH);
+                     a.H1b, M, NH, NH, a.H1bT, lt);
   CK(hipGetLastError());
-  CK(gemm_bf16(a.H1b, NH, 1, p.W2b, NH, 1, a.Z2, NH, M, NH, NH, 0, st));
+  CK(gemm_bf16(a.H1b, NH, 1, wt ? p.W2bT : p.W2b, wt ? 1 : NH, wt ? NH : 1, a.Z2, NH, M, NH, NH, 0,
+               st));
   hipLaunchKernelGGL(k_bias_gelu, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.Z2, p.b2,
-                     a.H2b, M, NH, NH);
+                     a.H2b, M, NH, NH, a.H2bT, lt);
   CK(hipGetLastError());
-  CK(gemm_bf16(a.H2b, NH, 1, p.W3b, p.N3, 1, a.Y, p.N3, M, p.N3, NH, 0, st));
+  CK(gemm_bf16(a.H2b, NH, 1, wt ? p.W3bT : p.W3b, wt ? 1 : p.N3, wt ? NH : 1, a.Y, p.N3, M, p.N3,
+               NH, 0, st));
   return true;
 }
 
 // loss (sum of squares over valid rows) + gradients into padded g buffers
 bool bwd(const Params& p, Acts& a, const float* Tsrc, int M, int nvalid, float* gW1, float* gb1,
          float* gW2, float* gb2, float* gW3, float* gb3, hipStream_t st, std::string& err) {
+  if (!a.H1bT || !a.H2bT || !a.dYbT || !a.dZ2bT || !a.dZ1bT || !a.XbT) {
+    err = "gradient pass without the batch-major activation copies";
+    return false;
+  }
+  const int lt = a.Bmax;
   hipLaunchKernelGGL(k_gather_f32, dim3(nblk((size_t)M * p.nout, 256)), dim3(256), 0, st, Tsrc,
                      p.nout, a.idx, M, a.T);
   CK(hipGetLastError());
   hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, st, a.Y, p.b3, a.T, p.nout,
-                     a.dYf, a.dYb, M, p.N3, p.nout, nvalid, a.part);
+                     a.dYf, a.dYb, M, p.N3, p.nout, nvalid, a.part, a.dYbT, lt);
   CK(hipGetLastError());
   // dW3 = H2^T dY, db3 = colsum dY
-  CK(gemm_bf16(a.H2b, 1, NH, a.dYb, p.N3, 1, gW3, p.N3, NH, p.N3, M, 0, st));
+  CK(gemm_bf16(a.H2bT, lt, 1, a.dYbT, 1, lt, gW3, p.N3, NH, p.N3, M, 0, st));
   colsum(a.dYf, M, p.N3, p.N3, gb3, st);
   // dH2 = dY W3^T; dZ2 = dH2 * gelu'(Z2)
   CK(gemm_bf16(a.dYb, p.N3, 1, p.W3b, 1, p.N3, a.dH2, NH, M, NH, p.N3, 0, st));
   hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH2, a.Z2,
-                     a.dZ2f, a.dZ2b, (long)M * NH);
+                     a.dZ2f, a.dZ2b, (long)M * NH, a.dZ2bT, lt);
   // dW2 = H1^T dZ2, db2
-  CK(gemm_bf16(a.H1b, 1, NH, a.dZ2b, NH, 1, gW2, NH, NH, NH, M, 0, st));
+  CK(gemm_bf16(a.H1bT, lt, 1, a.dZ2bT, 1, lt, gW2, NH, NH, NH, M, 0, st));
   colsum(a.dZ2f, M, NH, NH, gb2, st);
   // dH1 = dZ2 W2^T; dZ1
   CK(gemm_bf16(a.dZ2b, NH, 1, p.W2b, 1, NH, a.dH1, NH, M, NH, NH, 0, st));
   hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH1, a.Z1,
-                     a.dZ1f, a.dZ1b, (long)M * NH);
+                     a.dZ1f, a.dZ1b, (long)M * NH, a.dZ1bT, lt);
   // dW1 = X^T dZ1, db1
-  CK(gemm_bf16(a.Xb, 1, p.K1, a.dZ1b, NH, 1, gW1, NH, p.K1, NH, M, 0, st));
+  CK(gemm_bf16(a.XbT, lt, 1, a.dZ1bT, 1, lt, gW1, NH, p.K1, NH, M, 0, st));
   colsum(a.dZ1f, M, NH, NH, gb1, st);
   CK(hipGetLastError());
   return true;
@@ -565,17 +679,36 @@ bool train(const float* X, const float* T, int n, int nin, int nout, const Train
   float* gb2 = gW2 + p.n2();
   float* gW3 = gb2 + NH;
   float* gb3 = gW3 + p.n3();
-  struct Slot { float* w; float* g; size_t n; size_t off; uint16_t* wb; };
-  const Slot slots[6] = {{p.W1, gW1, p.n1(), 0, p.W1b},
-                         {p.b1, gb1, NH, p.n1(), nullptr},
-                         {p.W2, gW2, p.n2(), p.n1() + NH, p.W2b},
-                         {p.b2, gb2, NH, p.n1() + NH + p.n2(), nullptr},
-                         {p.W3, gW3, p.n3(), p.n1() + 2 * NH + p.n2(), p.W3b},
-                         {p.b3, gb3, (size_t)p.N3, p.n1() + 2 * NH + p.n2() + p.n3(), nullptr}};
+  AdamSlots slots;
+  {
+    float* const w[6] = {p.W1, p.b1, p.W2, p.b2, p.W3, p.b3};
+    uint16_t* const wb[6] = {p.W1b, nullptr, p.W2b, nullptr, p.W3b, nullptr};
+    uint16_t* const wbt[6] = {p.W1bT, nullptr, p.W2bT, nullptr, p.W3bT, nullptr};
+    const size_t sz[6] = {p.n1(), NH, p.n2(), NH, p.n3(), (size_t)p.N3};
+    const int cols[6] = {NH, NH, NH, NH, p.N3, p.N3};
+    slots.off[0] = 0;
+    for (int i = 0; i < 6; ++i) {
+      slots.w[i] = w[i];
+      slots.wb[i] = wb[i];
+      slots.wbt[i] = wbt[i];
+      slots.cols[i] = cols[i];
+      slots.off[i + 1] = slots.off[i] + (long)sz[i];
+    }
+  }
   const int steps_per_epoch = (ntr + B - 1) / B;
   const long total_steps = (long)steps_per_epoch * cfg.epochs;
-  std::vector<int> perm(ntr), idx(B);
+  // the row indices of a whole epoch (batch k at k B, -1 pads a short batch to a multiple of 16)
+  // go to the device in one copy, and the validation rows' once
+  const int vsteps = (nval + B - 1) / B;
+  int* eidx = d.alloc<int>((size_t)steps_per_epoch * B);
+  int* vidx = vsteps ? d.alloc<int>((size_t)vsteps * B) : nullptr;
+  if (d.e != hipSuccess) { err = "device allocation failed"; return false; }
+  std::vector<int> perm(ntr), idx((size_t)std::max(steps_per_epoch, vsteps) * B, -1);
   for (int i = 0; i < ntr; ++i) perm[i] = i;
+  if (vsteps) {
+    for (int r = 0; r < vsteps * B; ++r) idx[r] = r < nval ? ntr + r : -1;
+    CK(hipMemcpyAsync(vidx, idx.data(), (size_t)vsteps * B * sizeof(int), hipMemcpyHostToDevice, st));
+  }
   uint64_t ctr = 0;
   long step = 0;
   for (int ep = 0; ep < cfg.epochs; ++ep) {
@@ -586,13 +719,15 @@ bool train(const float* X, const float* T, int n, int nin, int nout, const Train
       if (j > i) j = i;
       std::swap(perm[i], perm[j]);
     }
+    for (int r = 0; r < steps_per_epoch * B; ++r) idx[r] = r < ntr ? perm[r] : -1;
+    CK(hipMemcpyAsync(eidx, idx.data(), (size_t)steps_per_epoch * B * sizeof(int),
+                      hipMemcpyHostToDevice, st));
     double ep_loss = 0.0;
     long ep_count = 0;
     for (int s0 = 0; s0 < ntr; s0 += B) {
       const int nv = std::min(B, ntr - s0);
       const int M = (nv + 15) / 16 * 16;
-      for (int r = 0; r < M; ++r) idx[r] = r < nv ? perm[s0 + r] : -1;
-      CK(hipMemcpyAsync(a.idx, idx.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+      a.idx = eidx + s0;
       if (!fwd(p, a, X, M, st, err)) return false;
       if (!bwd(p, a, T, M, nv, gW1, gb1, gW2, gb2, gW3, gb3, st, err)) return false;
       ++step;
@@ -600,10 +735,8 @@ bool train(const float* X, const float* T, int n, int nin, int nout, const Train
       const float lr_t = (float)(cfg.lr * 0.5 * (1.0 + std::cos(M_PI * (double)(step - 1) / total_steps)));
       const float c1 = (float)(1.0 - std::pow(b1, (double)step));
       const float c2 = (float)(1.0 - std::pow(b2, (double)step));
-      for (const Slot& sl : slots)
-        hipLaunchKernelGGL(k_adam, dim3(nblk(sl.n, 256)), dim3(256), 0, st, sl.w, sl.g,
-                           m + sl.off, v + sl.off, (long)sl.n, lr_t, (float)b1, (float)b2, 1e-8f,
-                           c1, c2, sl.wb);
+      hipLaunchKernelGGL(k_adam, dim3(nblk(np, 256)), dim3(256), 0, st, slots, g, m, v, lr_t,
+                         (float)b1, (float)b2, 1e-8f, c1, c2);
       CK(hipGetLastError());
       bool ok = true;
       if (s0 + B >= ntr) {  // epoch loss from the last batch only (cheap); full loss below
@@ -618,8 +751,7 @@ bool train(const float* X, const float* T, int n, int nin, int nout, const Train
     for (int s0 = 0; s0 < nval; s0 += B) {
       const int nv = std::min(B, nval - s0);
       const int M = (nv + 15) / 16 * 16;
-      for (int r = 0; r < M; ++r) idx[r] = r < nv ? ntr + s0 + r : -1;
-      CK(hipMemcpyAsync(a.idx, idx.data(), M * sizeof(int), hipMemcpyHostToDevice, st));
+      a.idx = vidx + s0;
       if (!fwd(p, a, X, M, st, err)) return false;
       if (!bwd(p, a, T, M, nv, gW1, gb1, gW2, gb2, gW3, gb3, st, err)) return false;  // loss
       bool ok = true;
