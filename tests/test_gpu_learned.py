@@ -98,6 +98,34 @@ def test_mlp_gradients_match_oracle():
         assert e <= 1e-3, k
 
 
+@pytest.mark.parametrize("n,nin,nout", [(1100, 1200, 50), (70, 30, 40)])
+def test_mlp_gradients_other_shapes(n, nin, nout):
+    """Loss and gradients at shapes the stage's own network does not have: more than 64 16-wide
+    k-steps in the products (input width 1200 padded to 1216; 1100 rows padded to 1104), and
+    output widths that leave a partial 64-column block (40 -> 48 padded)."""
+    rng = np.random.default_rng(17)
+    p = mlp.init_params(nin, nout, 23)
+    for k in ("b1", "b2", "b3"):
+        p[k] = rng.standard_normal(p[k].shape) * 0.1
+    p = {k: v.astype(np.float32).astype(np.float64) for k, v in p.items()}
+    bl = B.blob_pack(nin, nout, p["W1"], p["b1"], p["W2"], p["b2"], p["W3"], p["b3"])
+    X = rng.standard_normal((n, nin)).astype(np.float32).astype(np.float64)
+    Tt = rng.standard_normal((n, nout)).astype(np.float32).astype(np.float64)
+    npar = sum(v.size for v in p.values())
+    g, loss = B.sem_mlp_gradients(bl, T32(X), T32(Tt), npar)
+    Y, cache = mlp.forward(p, X, emulate=True)
+    lref, dY = mlp.mse(Y, Tt)
+    gref = mlp.backward(p, cache, dY, emulate=True)
+    assert abs(loss - lref) <= 1e-5 * lref
+    off = 0
+    for k in ("W1", "b1", "W2", "b2", "W3", "b3"):
+        gk = g[off:off + p[k].size].reshape(p[k].shape).astype(np.float64)
+        off += p[k].size
+        e = frob(gk, gref[k])
+        print(f"[gpu] grad {k} ({n} x {nin} -> {nout}): {e:.2e}", flush=True)
+        assert e <= 1e-3, k
+
+
 def _train_mesh_case():
     h_fn, eta_fn = W.training_geometry(0)
     x = oc.fine_x_nodes(8, 8, 2 * np.pi)
