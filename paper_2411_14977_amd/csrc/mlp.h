@@ -33,8 +33,21 @@ void net_init(Net& net, int nin, int nout, uint64_t seed);   // U(+-1/sqrt(fan_i
 
 // ---- generic BF16 GEMM: C[m][n] (+)= sum_k A(m,k) B(k,n), A(m,k) = A[m*sam + k*sak],
 // B(k,n) = B[k*sbk + n*sbn] (bf16 bits), C fp32 row-major with ldc.  M, N, K multiples of 16.
+// Optional epilogue of a product with ldc columns of hidden units (row r, column n, sum s):
+//   BIAS_GELU:  z = s + bias[n];        C = z, Hb = bf16(GELU(z))
+//   GELU_BACK:  g = s GELU'(Zin[r][n]);  C = g, Hb = bf16(g)
+// each also writing the bf16 value batch-major into HT[n * ldT + r] when HT is given.
+struct GemmEpi {
+  enum Kind { BIAS_GELU = 1, GELU_BACK = 2 } kind;
+  const float* bias;
+  const float* Zin;
+  uint16_t* Hb;
+  uint16_t* HT;
+  int ldT;
+};
 hipError_t gemm_bf16(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
-                     float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st);
+                     float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st,
+                     const GemmEpi* epi = nullptr);
 hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_t* dst, int ldd,
                           int dcols, const int* rowidx, hipStream_t st, uint16_t* dstT = nullptr,
                           int ldT = 0);

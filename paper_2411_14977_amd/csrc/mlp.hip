@@ -71,12 +71,13 @@ __device__ __forceinline__ bf16x4 frag_load(const uint16_t* p, long sk) {
   }
 }
 
-template <bool AV, bool BV>
+template <bool AV, bool BV, int EPI>
 __global__ __launch_bounds__(64 * GEMM_W) void k_gemm_bf16(const uint16_t* __restrict__ A,
                                                           long sam, long sak,
                                                           const uint16_t* __restrict__ B, long sbk,
                                                           long sbn, float* __restrict__ C, int ldc,
-                                                          int M, int N, int K, int accumulate) {
+                                                          int M, int N, int K, int accumulate,
+                                                          GemmEpi ep) {
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int m0 = blockIdx.x * 16, n0 = blockIdx.y * 64;
   const int nt = min(4, (N - n0) >> 4);  // 16-column tiles of this block (uniform)
@@ -120,28 +121,62 @@ __global__ __launch_bounds__(64 * GEMM_W) void k_gemm_bf16(const uint16_t* __res
   const int n = n0 + 16 * t + li;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
-    float* cp = C + (long)(m0 + kq + v) * ldc + n;
-    *cp = accumulate ? *cp + s[v] : s[v];
+    const long r = m0 + kq + v;
+    float* cp = C + r * ldc + n;
+    if constexpr (EPI == 0) {
+      *cp = accumulate ? *cp + s[v] : s[v];
+    } else {
+      float o;
+      uint16_t h;
+      if constexpr (EPI == GemmEpi::BIAS_GELU) {
+        o = s[v] + ep.bias[n];
+        h = f2bf(gelu(o));
+      } else {
+        o = s[v] * gelu_grad(ep.Zin[r * ldc + n]);
+        h = f2bf(o);
+      }
+      *cp = o;
+      ep.Hb[r * ldc + n] = h;
+      if (ep.HT) ep.HT[(long)n * ep.ldT + r] = h;
+    }
   }
 }
 
+template <int EPI>
+void launch_gemm(bool av, bool bv, dim3 grid, const uint16_t* A, long sam, long sak,
+                 const uint16_t* B, long sbk, long sbn, float* C, int ldc, int M, int N, int K,
+                 int accumulate, const GemmEpi& ep, hipStream_t st) {
+  if (av && bv)
+    hipLaunchKernelGGL((k_gemm_bf16<true, true, EPI>), grid, dim3(64 * GEMM_W), 0, st, A, sam,
+                       sak, B, sbk, sbn, C, ldc, M, N, K, accumulate, ep);
+  else if (av)
+    hipLaunchKernelGGL((k_gemm_bf16<true, false, EPI>), grid, dim3(64 * GEMM_W), 0, st, A, sam,
+                       sak, B, sbk, sbn, C, ldc, M, N, K, accumulate, ep);
+  else  // (a k-contiguous B alone takes the element loads too: no such product in this library)
+    hipLaunchKernelGGL((k_gemm_bf16<false, false, EPI>), grid, dim3(64 * GEMM_W), 0, st, A, sam,
+                       sak, B, sbk, sbn, C, ldc, M, N, K, accumulate, ep);
+}
+
 hipError_t gemm_bf16(const uint16_t* A, long sam, long sak, const uint16_t* B, long sbk, long sbn,
-                     float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st) {
+                     float* C, int ldc, int M, int N, int K, int accumulate, hipStream_t st,
+                     const GemmEpi* epi) {
   if (M % 16 || N % 16 || K % 16 || M <= 0 || N <= 0 || K <= 0) return hipErrorInvalidValue;
+  if (epi && (accumulate || !epi->Hb || (epi->kind == GemmEpi::BIAS_GELU ? !epi->bias : !epi->Zin)))
+    return hipErrorInvalidValue;
   // 8-byte fragment loads need a unit k stride, a row stride that keeps every row's start on
   // 8 bytes, and an 8-byte aligned base
   const bool av = sak == 1 && sam % 4 == 0 && ((uintptr_t)A & 7) == 0;
   const bool bv = sbk == 1 && sbn % 4 == 0 && ((uintptr_t)B & 7) == 0;
   const dim3 grid(M / 16, nblk(N, 64));
-  if (av && bv)
-    hipLaunchKernelGGL((k_gemm_bf16<true, true>), grid, dim3(64 * GEMM_W), 0, st, A, sam, sak, B,
-                       sbk, sbn, C, ldc, M, N, K, accumulate);
-  else if (av)
-    hipLaunchKernelGGL((k_gemm_bf16<true, false>), grid, dim3(64 * GEMM_W), 0, st, A, sam, sak, B,
-                       sbk, sbn, C, ldc, M, N, K, accumulate);
-  else  // (a k-contiguous B alone takes the element loads too: no such product in this library)
-    hipLaunchKernelGGL((k_gemm_bf16<false, false>), grid, dim3(64 * GEMM_W), 0, st, A, sam, sak, B,
-                       sbk, sbn, C, ldc, M, N, K, accumulate);
+  const GemmEpi none{GemmEpi::BIAS_GELU, nullptr, nullptr, nullptr, nullptr, 0};
+  if (!epi)
+    launch_gemm<0>(av, bv, grid, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, accumulate, none, st);
+  else if (epi->kind == GemmEpi::BIAS_GELU)
+    launch_gemm<GemmEpi::BIAS_GELU>(av, bv, grid, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, 0,
+                                    *epi, st);
+  else
+    launch_gemm<GemmEpi::GELU_BACK>(av, bv, grid, A, sam, sak, B, sbk, sbn, C, ldc, M, N, K, 0,
+                                    *epi, st);
   return hipGetLastError();
 }
 
@@ -170,21 +205,6 @@ hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_
 // ------------------------------------------------------------------------------------------
 // training element-wise kernels
 // ------------------------------------------------------------------------------------------
-// Z (M x ld) += bias; H = bf16(GELU(Z)), and its transpose HT [N x ldT] when given
-__global__ void k_bias_gelu(float* __restrict__ Z, const float* __restrict__ bias,
-                            uint16_t* __restrict__ H, int M, int N, int ld,
-                            uint16_t* __restrict__ HT, int ldT) {
-  const long total = (long)M * N;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int r = (int)(t / N), c = (int)(t - (long)r * N);
-    const float z = Z[(long)r * ld + c] + bias[c];
-    Z[(long)r * ld + c] = z;
-    const uint16_t h = f2bf(gelu(z));
-    H[(long)r * ld + c] = h;
-    if (HT) HT[(long)c * ldT + r] = h;
-  }
-}
-
 // y = Y + b3 on the first nout columns; d = y - t on valid rows (< nvalid); dY = 2 d / (nvalid
 // nout) (fp32 and bf16, padded columns and rows zero; the bf16 also transposed into dYbT
 // [ldy x ldT]); Y is overwritten with y; per-block partial sums of d^2 into part[blockIdx.x]
@@ -221,19 +241,6 @@ __global__ __launch_bounds__(256) void k_loss_grad(float* __restrict__ Y, const 
     double s = 0.0;
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) s += sh[w];
     part[blockIdx.x] = s;
-  }
-}
-
-// dZ = dH * GELU'(Z) (fp32 and bf16, rows of NH; the bf16 also transposed into dZbT [NH x ldT])
-__global__ void k_gelu_back(const float* __restrict__ dH, const float* __restrict__ Z,
-                            float* __restrict__ dZf, uint16_t* __restrict__ dZb, long n,
-                            uint16_t* __restrict__ dZbT, int ldT) {
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < n; t += (long)gridDim.x * blockDim.x) {
-    const float g = dH[t] * gelu_grad(Z[t]);
-    const long r = t / NH, c = t - r * NH;
-    dZf[t] = g;
-    dZb[t] = f2bf(g);
-    dZbT[c * ldT + r] = f2bf(g);
   }
 }
 
@@ -532,7 +539,7 @@ struct Acts {
   // k index is the batch row; null in the forward-only set
   uint16_t *XbT = nullptr, *H1bT = nullptr, *H2bT = nullptr, *dYbT = nullptr, *dZ2bT = nullptr,
            *dZ1bT = nullptr;
-  float *Z1, *Z2, *Y, *T, *dYf, *dH2, *dZ2f, *dH1, *dZ1f;
+  float *Z1, *Z2, *Y, *T, *dYf, *dZ2f, *dZ1f;
   int* idx;
   double* part;
 };
@@ -559,9 +566,7 @@ bool alloc_acts(Dev& d, Acts& a, int Bmax, int K1, int N3) {
   a.Y = d.alloc<float>(B * N3);
   a.T = d.alloc<float>(B * N3);
   a.dYf = d.alloc<float>(B * N3);
-  a.dH2 = d.alloc<float>(B * NH);
   a.dZ2f = d.alloc<float>(B * NH);
-  a.dH1 = d.alloc<float>(B * NH);
   a.dZ1f = d.alloc<float>(B * NH);
   a.idx = d.alloc<int>(B);
   a.part = d.alloc<double>(256);
@@ -576,16 +581,13 @@ bool fwd(const Params& p, Acts& a, const float* X, int M, hipStream_t st, std::s
   CK(to_bf16_padded(X, M, p.nin, p.nin, a.Xb, p.K1, p.K1, a.idx, st, a.XbT, lt));
   // B = W (K x N): the transposed copy gives unit k stride
   const bool wt = p.W1bT != nullptr;
+  // hidden layers: Z = X W + b and H = bf16(GELU(Z)) (and its batch-major copy) in the epilogue
+  const GemmEpi e1{GemmEpi::BIAS_GELU, p.b1, nullptr, a.H1b, a.H1bT, lt};
   CK(gemm_bf16(a.Xb, p.K1, 1, wt ? p.W1bT : p.W1b, wt ? 1 : NH, wt ? p.K1 : 1, a.Z1, NH, M, NH,
-               p.K1, 0, st));
-  hipLaunchKernelGGL(k_bias_gelu, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.Z1, p.b1,
-                     a.H1b, M, NH, NH, a.H1bT, lt);
-  CK(hipGetLastError());
+               p.K1, 0, st, &e1));
+  const GemmEpi e2{GemmEpi::BIAS_GELU, p.b2, nullptr, a.H2b, a.H2bT, lt};
   CK(gemm_bf16(a.H1b, NH, 1, wt ? p.W2bT : p.W2b, wt ? 1 : NH, wt ? NH : 1, a.Z2, NH, M, NH, NH, 0,
-               st));
-  hipLaunchKernelGGL(k_bias_gelu, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.Z2, p.b2,
-                     a.H2b, M, NH, NH, a.H2bT, lt);
-  CK(hipGetLastError());
+               st, &e2));
   CK(gemm_bf16(a.H2b, NH, 1, wt ? p.W3bT : p.W3b, wt ? 1 : p.N3, wt ? NH : 1, a.Y, p.N3, M, p.N3,
                NH, 0, st));
   return true;
@@ -608,17 +610,15 @@ bool bwd(const Params& p, Acts& a, const float* Tsrc, int M, int nvalid, float* 
   // dW3 = H2^T dY, db3 = colsum dY
   CK(gemm_bf16(a.H2bT, lt, 1, a.dYbT, 1, lt, gW3, p.N3, NH, p.N3, M, 0, st));
   colsum(a.dYf, M, p.N3, p.N3, gb3, st);
-  // dH2 = dY W3^T; dZ2 = dH2 * gelu'(Z2)
-  CK(gemm_bf16(a.dYb, p.N3, 1, p.W3b, 1, p.N3, a.dH2, NH, M, NH, p.N3, 0, st));
-  hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH2, a.Z2,
-                     a.dZ2f, a.dZ2b, (long)M * NH, a.dZ2bT, lt);
+  // dZ2 = (dY W3^T) * gelu'(Z2), the factor applied in the product's epilogue
+  const GemmEpi g2{GemmEpi::GELU_BACK, nullptr, a.Z2, a.dZ2b, a.dZ2bT, lt};
+  CK(gemm_bf16(a.dYb, p.N3, 1, p.W3b, 1, p.N3, a.dZ2f, NH, M, NH, p.N3, 0, st, &g2));
   // dW2 = H1^T dZ2, db2
   CK(gemm_bf16(a.H1bT, lt, 1, a.dZ2bT, 1, lt, gW2, NH, NH, NH, M, 0, st));
   colsum(a.dZ2f, M, NH, NH, gb2, st);
-  // dH1 = dZ2 W2^T; dZ1
-  CK(gemm_bf16(a.dZ2b, NH, 1, p.W2b, 1, NH, a.dH1, NH, M, NH, NH, 0, st));
-  hipLaunchKernelGGL(k_gelu_back, dim3(nblk((size_t)M * NH, 256)), dim3(256), 0, st, a.dH1, a.Z1,
-                     a.dZ1f, a.dZ1b, (long)M * NH, a.dZ1bT, lt);
+  // dZ1 = (dZ2 W2^T) * gelu'(Z1)
+  const GemmEpi g1{GemmEpi::GELU_BACK, nullptr, a.Z1, a.dZ1b, a.dZ1bT, lt};
+  CK(gemm_bf16(a.dZ2b, NH, 1, p.W2b, 1, NH, a.dZ1f, NH, M, NH, NH, 0, st, &g1));
   // dW1 = X^T dZ1, db1
   CK(gemm_bf16(a.XbT, lt, 1, a.dZ1bT, 1, lt, gW1, NH, p.K1, NH, M, 0, st));
   colsum(a.dZ1f, M, NH, NH, gb1, st);
