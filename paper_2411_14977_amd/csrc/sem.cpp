@@ -2904,7 +2904,9 @@ static void learned_load_impl(Ctx* c, const void* blob, size_t nbytes, int enabl
   HK(hipMemcpy(s.b3, b3.data(), N3 * 4, hipMemcpyHostToDevice));
   // Z1geo = Xg W1g + b1 (geometric part of layer 1), computed once per mesh on the GPU
   std::vector<uint16_t> xg = bf16_vec(c->geo_h.data(), E, nfg * n, Mp, K4);
-  std::vector<uint16_t> w1g = bf16_vec(net.W1.data() + (size_t)n * NH, nfg * n, NH, K4, NH);
+  // W1g output-major [NH x K4], so that the product reads k-contiguous fragments of both operands
+  std::vector<uint16_t> w1g =
+      bf16_vec(transpose(net.W1.data() + (size_t)n * NH, nfg * n, NH).data(), NH, nfg * n, NH, K4);
   void *dx = nullptr, *dw = nullptr, *dz = nullptr, *db = nullptr;
   HK(hipMalloc(&dx, xg.size() * 2));
   HK(hipMalloc(&dw, w1g.size() * 2));
@@ -2913,7 +2915,7 @@ static void learned_load_impl(Ctx* c, const void* blob, size_t nbytes, int enabl
   HK(hipMemcpy(dx, xg.data(), xg.size() * 2, hipMemcpyHostToDevice));
   HK(hipMemcpy(dw, w1g.data(), w1g.size() * 2, hipMemcpyHostToDevice));
   HK(hipMemcpy(db, net.b1.data(), NH * 4, hipMemcpyHostToDevice));
-  HK(semm::gemm_bf16((const uint16_t*)dx, K4, 1, (const uint16_t*)dw, NH, 1, (float*)dz, NH,
+  HK(semm::gemm_bf16((const uint16_t*)dx, K4, 1, (const uint16_t*)dw, 1, K4, (float*)dz, NH,
                      (int)Mp, NH, K4, 0, c->st));
   HK(semm::add_bias((float*)dz, (const float*)db, (int)Mp, NH, c->st));
   HK(hipMemcpyAsync(s.Z1geo, dz, E * NH * 4, hipMemcpyDeviceToDevice, c->st));
