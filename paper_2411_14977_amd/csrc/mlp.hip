@@ -205,15 +205,17 @@ hipError_t to_bf16_padded(const float* src, int rows, int cols, int lds, uint16_
 // ------------------------------------------------------------------------------------------
 // training element-wise kernels
 // ------------------------------------------------------------------------------------------
-// y = Y + b3 on the first nout columns; d = y - t on valid rows (< nvalid); dY = 2 d / (nvalid
-// nout) (fp32 and bf16, padded columns and rows zero; the bf16 also transposed into dYbT
-// [ldy x ldT]); Y is overwritten with y; per-block partial sums of d^2 into part[blockIdx.x]
+// y = Y + b3 on the first nout columns; d = y - t on valid rows (< nvalid; t = row idx[r] of T,
+// read in place); dY = 2 d / (nvalid nout) (fp32 and bf16, padded columns and rows zero; the
+// bf16 also transposed into dYbT [ldy x ldT]); Y is overwritten with y; per-block partial sums
+// of d^2 into part[blockIdx.x]
 __global__ __launch_bounds__(256) void k_loss_grad(float* __restrict__ Y, const float* __restrict__ b3,
                                                    const float* __restrict__ T, int ldt,
                                                    float* __restrict__ dYf,
                                                    uint16_t* __restrict__ dYb, int M, int ldy,
                                                    int nout, int nvalid, double* part,
-                                                   uint16_t* __restrict__ dYbT, int ldT) {
+                                                   uint16_t* __restrict__ dYbT, int ldT,
+                                                   const int* __restrict__ idx) {
   __shared__ double sh[8];
   double acc = 0.0;
   const float scale = 2.0f / ((float)nvalid * (float)nout);
@@ -225,7 +227,7 @@ __global__ __launch_bounds__(256) void k_loss_grad(float* __restrict__ Y, const 
       const float y = Y[t] + b3[c];
       Y[t] = y;
       if (r < nvalid) {
-        const float d = y - T[(long)r * ldt + c];
+        const float d = y - T[(long)idx[r] * ldt + c];
         acc += (double)d * (double)d;
         g = scale * d;
       }
@@ -333,16 +335,6 @@ hipError_t add_bias(float* Z, const float* b, int rows, int cols, hipStream_t st
   hipLaunchKernelGGL(k_add_bias, dim3(nblk((size_t)rows * cols, 256)), dim3(256), 0, st, Z, b,
                      rows, cols);
   return hipGetLastError();
-}
-
-__global__ void k_gather_f32(const float* __restrict__ src, int cols, const int* __restrict__ idx,
-                             int rows, float* __restrict__ dst) {
-  const long total = (long)rows * cols;
-  for (long t = blockIdx.x * (long)blockDim.x + threadIdx.x; t < total; t += (long)gridDim.x * blockDim.x) {
-    const int r = (int)(t / cols), c = (int)(t - (long)r * cols);
-    const int sr = idx[r];
-    dst[t] = sr >= 0 ? src[(long)sr * cols + c] : 0.0f;
-  }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -539,7 +531,7 @@ struct Acts {
   // k index is the batch row; null in the forward-only set
   uint16_t *XbT = nullptr, *H1bT = nullptr, *H2bT = nullptr, *dYbT = nullptr, *dZ2bT = nullptr,
            *dZ1bT = nullptr;
-  float *Z1, *Z2, *Y, *T, *dYf, *dZ2f, *dZ1f;
+  float *Z1, *Z2, *Y, *dYf, *dZ2f, *dZ1f;
   int* idx;
   double* part;
 };
@@ -564,7 +556,6 @@ bool alloc_acts(Dev& d, Acts& a, int Bmax, int K1, int N3) {
   a.Z1 = d.alloc<float>(B * NH);
   a.Z2 = d.alloc<float>(B * NH);
   a.Y = d.alloc<float>(B * N3);
-  a.T = d.alloc<float>(B * N3);
   a.dYf = d.alloc<float>(B * N3);
   a.dZ2f = d.alloc<float>(B * NH);
   a.dZ1f = d.alloc<float>(B * NH);
@@ -601,11 +592,8 @@ bool bwd(const Params& p, Acts& a, const float* Tsrc, int M, int nvalid, float* 
     return false;
   }
   const int lt = a.Bmax;
-  hipLaunchKernelGGL(k_gather_f32, dim3(nblk((size_t)M * p.nout, 256)), dim3(256), 0, st, Tsrc,
-                     p.nout, a.idx, M, a.T);
-  CK(hipGetLastError());
-  hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, st, a.Y, p.b3, a.T, p.nout,
-                     a.dYf, a.dYb, M, p.N3, p.nout, nvalid, a.part, a.dYbT, lt);
+  hipLaunchKernelGGL(k_loss_grad, dim3(LOSS_BLOCKS), dim3(256), 0, st, a.Y, p.b3, Tsrc, p.nout,
+                     a.dYf, a.dYb, M, p.N3, p.nout, nvalid, a.part, a.dYbT, lt, a.idx);
   CK(hipGetLastError());
   // dW3 = H2^T dY, db3 = colsum dY
   CK(gemm_bf16(a.H2bT, lt, 1, a.dYbT, 1, lt, gW3, p.N3, NH, p.N3, M, 0, st));
